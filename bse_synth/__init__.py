@@ -1,0 +1,338 @@
+"""Seeded synthetic inputs for the Tamm-Dancoff BSE Hamiltonian build.
+
+This module is shared by the CPU oracle tests, the GPU tests and the benchmark.
+It produces only *inputs*: periodic parts u_nk(r) of Bloch functions on a real
+space grid, band energies, the plane-wave basis (G-spheres) of every momentum
+transfer q, the bare Coulomb kernel on the q=0 sphere, and a screened
+interaction W_GG'(q).  It contains none of the Hamiltonian arithmetic (no pair
+densities, no exchange or direct terms, no k-pair folding).
+
+Everything upstream of the Hamiltonian in the paper (ground-state DFT, the RPA
+response and the inversion of the dielectric matrix) is replaced by seeded
+random draws that have the structure the paper's quantities have:
+
+* u_nk: complex Gaussian per grid point, orthonormalised per k (QR), so that
+  sum_r |u|^2 = 1 and the bands at one k are orthogonal.
+* eps: valence energies uniform in [-3, 0] eV, conduction in [1, 4] eV.
+* W_GG'(q) = v^1/2(q+G) [eps^-1]_GG' v^1/2(q+G') with eps^-1 = (I + A A^H/N_G)^-1
+  for a complex Gaussian A (Hermitian, positive definite), following the form
+  of the statically screened interaction in Sec. III.A (4 pi inside v).
+* The q = 0 head is fixed to 4 pi * 0.1 / Omega_cell and the wings are zero
+  (the paper integrates the divergence out analytically, Sec. II.C; the
+  synthetic value stands in for that result).
+* W obeys the time-reversal relation of Sec. III.A with T = identity:
+  W_{G,G'}(q) = conj(W_{-G-G0,-G'-G0}(qbar)) where -q = qbar + G0 folds back
+  into the mesh.  Without it the Hamiltonian is not Hermitian.
+
+Random numbers come from numpy PCG64 streams spawned from SeedSequence(seed):
+[wave functions (one child per k), energies, W (one child per q), system draws].
+"""
+from __future__ import annotations
+
+import dataclasses
+import hashlib
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HARTREE_EV = 27.211386245988  # CODATA 2018
+
+
+@dataclasses.dataclass
+class System:
+    name: str
+    cell: np.ndarray          # (3,3) rows a1, a2, a3 in bohr
+    grid: tuple               # (N1, N2, N3); N3 fastest in u
+    kmesh: tuple              # (n1, n2, n3); k index (i1*n2 + i2)*n3 + i3
+    nv: int
+    nc: int
+    ecut: float               # Hartree, sphere 1/2 |q+G|^2 <= ecut
+    coulomb: str              # "bulk" or "slab"
+    slab_L: float             # truncation length (slab only)
+    head: float               # W_00(q=0), bohr units as stored
+    ng: np.ndarray            # int32 [Nk]            sphere size per q index
+    gvec: np.ndarray          # int32 [Nk][ng_max][3] Miller indices, padded with 0
+    vx: np.ndarray            # float64 [ng_max]      v(G) on the q=0 sphere, entry 0 = 0
+    u: np.ndarray             # complex128 [Nk][nb][Nr]
+    eps: np.ndarray           # float64 [Nk][nb] eV, bands 0..nv-1 valence
+    W: np.ndarray             # complex128 [Nk][ng_max][ng_max], padding zero
+    seed: int
+
+    @property
+    def nk(self) -> int:
+        return int(np.prod(self.kmesh))
+
+    @property
+    def nb(self) -> int:
+        return self.nv + self.nc
+
+    @property
+    def nr(self) -> int:
+        return int(np.prod(self.grid))
+
+    @property
+    def ns(self) -> int:
+        return self.nk * self.nv * self.nc
+
+    @property
+    def ng_max(self) -> int:
+        return int(self.gvec.shape[1])
+
+    @property
+    def omega_cell(self) -> float:
+        return abs(float(np.linalg.det(self.cell)))
+
+    def digest(self) -> str:
+        h = hashlib.sha256()
+        for a in (self.cell, self.ng, self.gvec, self.vx, self.u, self.eps, self.W):
+            h.update(np.ascontiguousarray(a).tobytes())
+        return h.hexdigest()[:16]
+
+
+# ----------------------------------------------------------------------------
+# lattices
+
+def cell_sc(a: float) -> np.ndarray:
+    return a * np.eye(3)
+
+
+def cell_fcc(a: float) -> np.ndarray:
+    return 0.5 * a * np.array([[0.0, 1.0, 1.0], [1.0, 0.0, 1.0], [1.0, 1.0, 0.0]])
+
+
+def cell_hex(a: float, c: float) -> np.ndarray:
+    return np.array([[a, 0.0, 0.0], [-0.5 * a, 0.5 * math.sqrt(3.0) * a, 0.0], [0.0, 0.0, c]])
+
+
+def reciprocal(cell: np.ndarray) -> np.ndarray:
+    """Rows b_d with a_i . b_j = 2 pi delta_ij."""
+    return 2.0 * math.pi * np.linalg.inv(cell).T
+
+
+def q_vector(cell: np.ndarray, kmesh: Sequence[int], iq: int) -> np.ndarray:
+    n1, n2, n3 = kmesh
+    i3 = iq % n3
+    i2 = (iq // n3) % n2
+    i1 = iq // (n2 * n3)
+    frac = np.array([i1 / n1, i2 / n2, i3 / n3])
+    return frac @ reciprocal(cell)
+
+
+def gsphere(cell: np.ndarray, qv: np.ndarray, ecut: float) -> np.ndarray:
+    """Miller indices m with 1/2 |q + sum_d m_d b_d|^2 <= ecut.
+
+    Ordered by (|q+G|^2 rounded to 1e-12, m1, m2, m3), so that at q = 0 the
+    first entry is G = 0.
+    """
+    b = reciprocal(cell)
+    gmax = math.sqrt(2.0 * ecut)
+    lens = np.linalg.norm(cell, axis=1)
+    frac = np.linalg.solve(b.T, qv)  # q in units of b
+    rng = [np.arange(int(math.floor(-frac[d] - gmax * lens[d] / (2 * math.pi))) - 1,
+                     int(math.ceil(-frac[d] + gmax * lens[d] / (2 * math.pi))) + 2) for d in range(3)]
+    m = np.stack(np.meshgrid(*rng, indexing="ij"), axis=-1).reshape(-1, 3)
+    p = qv[None, :] + m @ b
+    g2 = np.einsum("ij,ij->i", p, p)
+    keep = 0.5 * g2 <= ecut * (1.0 + 1e-13)
+    m = m[keep]
+    g2 = np.round(g2[keep], 12)
+    order = np.lexsort((m[:, 2], m[:, 1], m[:, 0], g2))
+    return m[order].astype(np.int32)
+
+
+def coulomb(p: np.ndarray, kind: str, slab_L: float) -> np.ndarray:
+    """Bare Coulomb kernel 4 pi/|p|^2 (bulk) or its 2-D truncated form (slab,
+    cell axis 3 along z).  Entries with p = 0 return 0; callers treat them."""
+    p2 = np.einsum("ij,ij->i", p, p)
+    out = np.zeros(len(p))
+    nz = p2 > 1e-20
+    out[nz] = 4.0 * math.pi / p2[nz]
+    if kind == "slab":
+        ppar = np.sqrt(p[:, 0] ** 2 + p[:, 1] ** 2)
+        out[nz] *= 1.0 - np.exp(-ppar[nz] * slab_L / 2.0) * np.cos(p[nz, 2] * slab_L / 2.0)
+    elif kind != "bulk":
+        raise ValueError(kind)
+    return out
+
+
+def kindex(kmesh, i):
+    n1, n2, n3 = kmesh
+    return (i[0] * n2 + i[1]) * n3 + i[2]
+
+
+def ktriplet(kmesh, k):
+    n1, n2, n3 = kmesh
+    return np.array([k // (n2 * n3), (k // n3) % n2, k % n3])
+
+
+# ----------------------------------------------------------------------------
+# generator
+
+def make_system(cell, grid, kmesh, nv, nc, ecut, *, coulomb_kind="bulk", slab_L=0.0,
+                head_factor=0.1, seed=1206, name="custom", wf="gaussian", wf_ecut=None,
+                ss: Optional[np.random.SeedSequence] = None) -> System:
+    cell = np.asarray(cell, dtype=np.float64)
+    grid = tuple(int(x) for x in grid)
+    kmesh = tuple(int(x) for x in kmesh)
+    nk = int(np.prod(kmesh))
+    nb = nv + nc
+    nr = int(np.prod(grid))
+    omega = abs(float(np.linalg.det(cell)))
+    head = 4.0 * math.pi * head_factor / omega
+    b = reciprocal(cell)
+
+    if ss is None:
+        ss = np.random.SeedSequence(seed)
+    ss_wf, ss_eps, ss_w, _ = ss.spawn(4)
+
+    # plane-wave basis per q
+    spheres = [gsphere(cell, q_vector(cell, kmesh, iq), ecut) for iq in range(nk)]
+    ng = np.array([len(s) for s in spheres], dtype=np.int32)
+    ng_max = int(ng.max())
+    gvec = np.zeros((nk, ng_max, 3), dtype=np.int32)
+    for iq, s in enumerate(spheres):
+        gvec[iq, : len(s)] = s
+    assert np.all(gvec[0, 0] == 0), "G=0 must lead the q=0 sphere"
+    # every shifted sphere must fit the grid without aliasing
+    allm = np.concatenate(spheres)
+    for d in range(3):
+        span = int(allm[:, d].max() - allm[:, d].min()) + 1 + (1 if kmesh[d] > 1 else 0)
+        if span > grid[d]:
+            raise ValueError(f"G-sphere spans {span} > grid {grid[d]} along axis {d}")
+
+    vx = np.zeros(ng_max)
+    vx[: ng[0]] = coulomb(spheres[0] @ b, coulomb_kind, slab_L)
+    vx[0] = 0.0
+
+    # wave functions
+    u = np.empty((nk, nb, nr), dtype=np.complex128)
+    kids = ss_wf.spawn(nk)
+    for k in range(nk):
+        rng = np.random.Generator(np.random.PCG64(kids[k]))
+        if wf == "gaussian":
+            z = rng.standard_normal((nr, nb)) + 1j * rng.standard_normal((nr, nb))
+        elif wf == "bandlimited":
+            # random coefficients on a small sphere of plane waves, then inverse DFT
+            msph = gsphere(cell, np.zeros(3), wf_ecut)
+            c = rng.standard_normal((len(msph), nb)) + 1j * rng.standard_normal((len(msph), nb))
+            spec = np.zeros(grid + (nb,), dtype=np.complex128)
+            spec[msph[:, 0] % grid[0], msph[:, 1] % grid[1], msph[:, 2] % grid[2]] = c
+            z = np.fft.ifftn(spec, axes=(0, 1, 2)).reshape(nr, nb)
+        else:
+            raise ValueError(wf)
+        q, _ = np.linalg.qr(z)
+        u[k] = q.T
+
+    # energies
+    rng = np.random.Generator(np.random.PCG64(ss_eps))
+    eps = np.empty((nk, nb))
+    eps[:, :nv] = rng.uniform(-3.0, 0.0, size=(nk, nv))
+    eps[:, nv:] = rng.uniform(1.0, 4.0, size=(nk, nc))
+
+    # screened interaction, one representative per time-reversal orbit
+    W = np.zeros((nk, ng_max, ng_max), dtype=np.complex128)
+    done = np.zeros(nk, dtype=bool)
+    wkids = ss_w.spawn(nk)
+    n = np.array(kmesh)
+    for iq in range(nk):
+        if done[iq]:
+            continue
+        rng = np.random.Generator(np.random.PCG64(wkids[iq]))
+        s = spheres[iq]
+        g = len(s)
+        qv = q_vector(cell, kmesh, iq)
+        A = rng.standard_normal((g, g)) + 1j * rng.standard_normal((g, g))
+        M = np.eye(g) + (A @ A.conj().T) / g
+        Lc = np.linalg.cholesky(M)
+        Li = np.linalg.solve(Lc, np.eye(g))
+        einv = Li.conj().T @ Li
+        v = coulomb(qv[None, :] + s @ b, coulomb_kind, slab_L)
+        sv = np.sqrt(v)
+        Wq = sv[:, None] * einv * sv[None, :]
+        if iq == 0:
+            Wq[0, :] = 0.0
+            Wq[:, 0] = 0.0
+            Wq[0, 0] = head
+        Wq = 0.5 * (Wq + Wq.conj().T)
+        # time-reversal partner: -iq = qbar + n t
+        iv = ktriplet(kmesh, iq)
+        qb = (-iv) % n
+        t = (-iv - qb) // n
+        iqb = kindex(kmesh, qb)
+        sb = spheres[iqb]
+        lut = {tuple(m): i for i, m in enumerate(sb)}
+        perm = np.array([lut[tuple(t - m)] for m in s])
+        if iqb == iq:
+            Wq = 0.5 * (Wq + np.conj(Wq[np.ix_(perm, perm)]))
+            W[iq, :g, :g] = Wq
+        else:
+            W[iq, :g, :g] = Wq
+            Wb = np.zeros((g, g), dtype=np.complex128)
+            Wb[np.ix_(perm, perm)] = np.conj(Wq)
+            W[iqb, :g, :g] = Wb
+            done[iqb] = True
+        done[iq] = True
+
+    return System(name=name, cell=cell, grid=grid, kmesh=kmesh, nv=nv, nc=nc, ecut=ecut,
+                  coulomb=coulomb_kind, slab_L=slab_L, head=head, ng=ng, gvec=gvec, vx=vx,
+                  u=u, eps=eps, W=W, seed=seed)
+
+
+# ----------------------------------------------------------------------------
+# the named workloads
+
+CONFIG_NAMES = {
+    0: "tiny-sc16-k2-b2x2",
+    1: "si-fcc24-k4-b3x3",
+    2: "si-fcc32-k8-b4x4",
+    3: "hbn-hex24x24x96-ragged16-b4x4",
+    4: "si-fcc32-k8-b4x4-backward",
+}
+
+A_SI = 10.26        # bohr (5.431 angstrom)
+A_HBN = 4.74        # bohr
+C_HBN = 30.0        # bohr: 15 bohr of vacuum on each side of the sheet
+HBN_MESHES = (6, 8, 9, 12)
+
+
+def make_config(i: int, seed: Optional[int] = None, **over):
+    """Workload i (0..4).  Config 3 returns a list of 16 systems."""
+    if seed is None:
+        seed = 1206 + i
+    if i == 0:
+        kw = dict(cell=cell_sc(10.0), grid=(16, 16, 16), kmesh=(2, 2, 2), nv=2, nc=2, ecut=3.0)
+    elif i == 1:
+        kw = dict(cell=cell_fcc(A_SI), grid=(24, 24, 24), kmesh=(4, 4, 4), nv=3, nc=3, ecut=6.0)
+    elif i in (2, 4):
+        kw = dict(cell=cell_fcc(A_SI), grid=(32, 32, 32), kmesh=(8, 8, 8), nv=4, nc=4, ecut=8.0)
+    elif i == 3:
+        nsys = over.pop("nsys", 16)
+        return make_hbn_batch(seed, nsys=nsys, **over)
+    else:
+        raise ValueError(i)
+    kw.update(over)
+    return make_system(seed=seed, name=CONFIG_NAMES[i], **kw)
+
+
+def hbn_draws(seed: int, nsys: int = 16) -> List[int]:
+    ss = np.random.SeedSequence(seed)
+    _, _, _, ss_sys = ss.spawn(4)
+    rng = np.random.Generator(np.random.PCG64(ss_sys))
+    return [int(x) for x in rng.choice(HBN_MESHES, size=nsys)]
+
+
+def make_hbn_batch(seed: int, nsys: int = 16, grid=(24, 24, 96), ecut=9.0, nv=4, nc=4,
+                   meshes: Optional[Sequence[int]] = None) -> List[System]:
+    ss = np.random.SeedSequence(seed)
+    _, _, _, ss_sys = ss.spawn(4)
+    kids = ss_sys.spawn(nsys)
+    if meshes is None:
+        meshes = hbn_draws(seed, nsys)
+    out = []
+    for s in range(nsys):
+        n = int(meshes[s])
+        out.append(make_system(cell_hex(A_HBN, C_HBN), grid, (n, n, 1), nv, nc, ecut,
+                               coulomb_kind="slab", slab_L=C_HBN, seed=seed,
+                               name=f"hbn{s}-k{n}", ss=kids[s]))
+    return out
