@@ -1,0 +1,158 @@
+/*
+ * bse.h -- C ABI of the MI355X (gfx950) Tamm-Dancoff Bethe-Salpeter
+ * Hamiltonian builder.
+ *
+ * Paper: J. Yan, K. W. Jacobsen, K. S. Thygesen, "Optical properties of bulk
+ * semiconductors and graphene/boron-nitride: the Bethe-Salpeter equation with
+ * derivative discontinuity-corrected DFT energies", PRB 86, 045208 (2012).
+ *
+ * What is computed (Sec. II.C, with the Tamm-Dancoff approximation of Sec. IV.C
+ * and the appendix):
+ *
+ *   H_SS' = (e_ck - e_vk) delta_SS' + c * (2 Vbar_SS' - D_SS'),
+ *   c     = E_h / (Nk * Omega_cell)             (E_h = 27.211386245988 eV),
+ *   S = (k, v, c) with row index (k*nv + v)*nc + c,
+ *   Vbar_SS' = sum_{G != 0} conj(n_{vk,ck}(G)) v(G) n_{v'k',c'k'}(G)    (e-h exchange, G = 0 left out)
+ *   D_SS'    = sum_{G,G'} conj(n_{vk,v'k'}(G)) W_GG'(k'-k) n_{ck,c'k'}(G')  (screened direct term)
+ *   n_{ak,bk'}(G) = sum_r conj(u_ak(r)) u_bk'(r) exp(-2 pi i (m - m0).j / N)  (pair density, Sec. II.B)
+ *
+ * where k' - k = q + G0 is folded onto the k-shaped q mesh (Sec. III.A),
+ * m are the Miller indices of the plane-wave sphere of q and m0 those of G0.
+ *
+ * Conventions shared by every entry point:
+ *   - Complex numbers are interleaved (re, im) doubles.
+ *   - Arrays marked DEVICE live in GPU memory of the current HIP device;
+ *     arrays marked HOST live in host memory and are read during the call.
+ *   - The caller owns every buffer, including the workspace.  The library
+ *     allocates no device memory.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
+ *     on it and the call returns; the caller synchronises.  Host-side plan
+ *     tables are uploaded with a copy that blocks the calling thread until
+ *     the stream has consumed them.
+ *   - A non-zero return means nothing was enqueued (argument errors) or that
+ *     a HIP call failed; bse_last_error() gives text for the calling thread.
+ *   - Calls on one device that share a workspace must not overlap.
+ */
+#ifndef BSE_H
+#define BSE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum bse_status {
+    BSE_OK = 0,
+    BSE_ERR_INVALID_ARG = -1,  /* null pointer, bad size or unsupported value  */
+    BSE_ERR_SHAPE = -2,        /* grid / sphere / band counts not supported      */
+    BSE_ERR_WORKSPACE = -3,    /* ws_bytes below bse_workspace_size()            */
+    BSE_ERR_HIP = -4,          /* a HIP runtime call failed                      */
+    BSE_ERR_NOT_HERMITIAN = -5,/* BSE_VALIDATE: W(q) violates Hermiticity / TR   */
+    BSE_ERR_NONFINITE = -6,    /* BSE_VALIDATE: NaN or Inf in an input           */
+    BSE_ERR_UNSUPPORTED = -7   /* mode not implemented                           */
+};
+
+/* Arithmetic of the two dense contractions (exchange and direct term).
+ * Pair densities, the transition-energy diagonal and the q = 0 head of W
+ * are always FP64. */
+enum bse_precision {
+    BSE_FP64 = 0,       /* FP64 MFMA                                           */
+    BSE_SPLIT_FP32 = 1, /* operands split into FP32 hi + lo, 3 products, FP32 acc */
+    BSE_BF16X3 = 2      /* operands split into BF16 hi + lo, 3 products, FP32 acc */
+};
+
+enum bse_flags {
+    BSE_VALIDATE = 1,   /* scan inputs (synchronously) before enqueueing       */
+    BSE_PERSISTENT = 2  /* build a batch of systems with one persistent launch */
+};
+
+enum bse_pd_kind {
+    BSE_PD_EXCH = 0,   /* n_{vk,ck}(G) on S(0):   out [Nk][nv][nc][ng_max]             */
+    BSE_PD_VV = 1,     /* n_{vk,v'k'}(G) on S(q): out [npairs][nv][nv][ng_max]          */
+    BSE_PD_CC = 2,     /* n_{ck,c'k'}(G) on S(q): out [npairs][nc][nc][ng_max]          */
+    BSE_PD_DIPOLE = 3  /* <u_vk| grad |u_ck>:     out [Nk][nv][nc][3]                   */
+};
+
+/*
+ * One crystal.  Shapes: Nk = n1*n2*n3, nb = nv + nc, Nr = N1*N2*N3,
+ * NS = Nk*nv*nc.  Supported grids: N2, N3 in {8, 12, 16, 24, 32, 48, 64, 96},
+ * any N1 >= 1.
+ */
+typedef struct bse_system {
+    int grid[3];          /* N1, N2, N3; real-space index (j1*N2 + j2)*N3 + j3            */
+    int kmesh[3];         /* n1, n2, n3; k index (i1*n2 + i2)*n3 + i3                       */
+    int nv, nc;           /* valence and conduction bands in H (bands 0..nv-1 are valence)  */
+    double omega_cell;    /* unit-cell volume in bohr^3                                     */
+    int ng_max;           /* row stride of gvec, W and every pair-density row               */
+    const int *ng;        /* HOST  [Nk]               sphere size N_G(q), q indexed like k     */
+    const int *gvec;      /* HOST  [Nk][ng_max][3]    Miller indices; gvec[0][0] = (0,0,0)     */
+    const double *vx;     /* DEVICE [ng_max]          Coulomb v(G) on S(0) (4 pi inside), Ha*bohr^3
+                                                      units of W; entry 0 is not read            */
+    const double *u;      /* DEVICE [Nk][nb][Nr] complex  periodic parts, sum_r |u|^2 = 1      */
+    const double *eps;    /* DEVICE [Nk][nb]           band energies in eV                       */
+    const double *W;      /* DEVICE [Nk][ng_max][ng_max] complex, W[q][G][G'] (4 pi inside);
+                                                      Hermitian and obeying time reversal;
+                                                      entries past ng(q) are not read           */
+    double *H;            /* DEVICE [NS][NS] complex, out, eV; every element is written        */
+} bse_system;
+
+/* Bytes of device workspace that bse_build_H / bse_pair_density /
+ * bse_build_H_backward need for these systems, precision and flags. */
+size_t bse_workspace_size(const bse_system *sys, int nsys, int precision, int flags);
+
+/*
+ * Pair densities n_{ak,bk'}(G) (Sec. II.B, eq. for the charge density matrix)
+ * for the ordered k pairs `kpairs` (HOST [npairs][2] = (k, k')), or for every
+ * k (BSE_PD_EXCH, BSE_PD_DIPOLE; kpairs ignored).  Entries g >= ng(q) of each
+ * row are written as zero.  BSE_PD_EXCH rows are NOT scaled by v(G).
+ * BSE_PD_DIPOLE gives the k.p matrix element <u_vk|grad|u_ck> of Sec. II.B
+ * (Cartesian, bohr^-1) from the spectral derivative of u with the Nyquist
+ * planes removed; it needs sys->H = NULL allowed and uses the cell given in
+ * `cell` (HOST [9], rows a1 a2 a3 in bohr; ignored for other kinds).
+ * `out` is DEVICE complex.
+ */
+int bse_pair_density(const bse_system *sys, int kind, const int *kpairs, int npairs,
+                     const double *cell, double *out, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Builds H for `nsys` independent systems (each writes its own sys[i].H).
+ * precision: enum bse_precision.  flags: enum bse_flags.
+ */
+int bse_build_H(const bse_system *sys, int nsys, int precision, int flags,
+                void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Adjoint of bse_build_H for one system: given dL/dH (DEVICE [NS][NS] complex,
+ * the PyTorch convention dL/dRe + i dL/dIm), returns
+ *   dW   DEVICE [Nk][ng_max][ng_max] complex (nullable)  dL/dW_GG'(q)
+ *   deps DEVICE [Nk][nb]             (nullable)          dL/de (eV/eV)
+ * Pair densities are recomputed, not read from a previous build.
+ * dW is the plain partial derivative of the assembled upper-triangle + mirror
+ * map; the Python layer projects it onto Hermitian/time-reversal symmetric W.
+ */
+int bse_build_H_backward(const bse_system *sys, const double *dH, double *dW, double *deps,
+                         int precision, int flags, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Absorption spectrum from the spectral representation of the irreducible
+ * response (Sec. II.C, macroscopic dielectric function with Vbar; Tamm-Dancoff
+ * so the overlap matrix is the identity):
+ *   t_l     = sum_S A[S][l] d[S]
+ *   eps2(w) = pref * sum_l |t_l|^2 * eta / ((w - E_l)^2 + eta^2)
+ * E (DEVICE [nlam], eV), A (DEVICE [ns][nlam] complex, eigenvectors as
+ * columns), d (DEVICE [ns] complex), eps2 (DEVICE [nw]) on w_i = w0 + i*(w1-w0)/(nw-1).
+ * Energies and eta are in eV and converted to Hartree inside; pref carries
+ * 8 pi / (Nk Omega_cell) and the units of d.
+ */
+int bse_spectrum(int ns, int nlam, const double *E, const double *A, const double *d, double pref,
+                 int nw, double w0_eV, double w1_eV, double eta_eV, double *eps2, void *stream);
+
+/* Text describing the last non-zero status returned on this thread. */
+const char *bse_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSE_H */

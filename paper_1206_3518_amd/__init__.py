@@ -1,0 +1,194 @@
+"""Python binding of libbse.so, the MI355X Tamm-Dancoff BSE Hamiltonian builder.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in include/bse.h.  PyTorch provides device
+memory and the current HIP stream.  The library must be built
+(``python -m paper_1206_3518_amd.build`` or ``__graft_entry__.build()``); there
+is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbse.so")
+_LIB = None
+
+BSE_OK = 0
+BSE_FP64, BSE_SPLIT_FP32, BSE_BF16X3 = 0, 1, 2
+BSE_VALIDATE, BSE_PERSISTENT = 1, 2
+BSE_PD_EXCH, BSE_PD_VV, BSE_PD_CC, BSE_PD_DIPOLE = 0, 1, 2, 3
+PRECISIONS = {"fp64": BSE_FP64, "split_fp32": BSE_SPLIT_FP32, "bf16x3": BSE_BF16X3}
+HARTREE_EV = 27.211386245988
+
+
+class BseError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"bse status {code}: {msg}")
+        self.code = code
+
+
+class bse_system(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_int * 3), ("kmesh", ctypes.c_int * 3), ("nv", ctypes.c_int),
+                ("nc", ctypes.c_int), ("omega_cell", ctypes.c_double), ("ng_max", ctypes.c_int),
+                ("ng", ctypes.c_void_p), ("gvec", ctypes.c_void_p), ("vx", ctypes.c_void_p),
+                ("u", ctypes.c_void_p), ("eps", ctypes.c_void_p), ("W", ctypes.c_void_p),
+                ("H", ctypes.c_void_p)]
+
+
+SYMBOLS = ["bse_workspace_size", "bse_pair_density", "bse_build_H", "bse_build_H_backward",
+           "bse_spectrum", "bse_last_error"]
+
+
+def lib():
+    """Loads libbse.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, D, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+        L.bse_workspace_size.argtypes = [P, I, I, I]
+        L.bse_workspace_size.restype = S
+        L.bse_pair_density.argtypes = [P, I, P, I, P, P, P, S, P]
+        L.bse_pair_density.restype = I
+        L.bse_build_H.argtypes = [P, I, I, I, P, S, P]
+        L.bse_build_H.restype = I
+        L.bse_build_H_backward.argtypes = [P, P, P, P, I, I, P, S, P]
+        L.bse_build_H_backward.restype = I
+        L.bse_spectrum.argtypes = [I, I, P, P, P, D, I, D, D, D, P, P]
+        L.bse_spectrum.restype = I
+        L.bse_last_error.argtypes = []
+        L.bse_last_error.restype = ctypes.c_char_p
+        _LIB = L
+    return _LIB
+
+
+def bse_last_error() -> str:
+    return lib().bse_last_error().decode()
+
+
+def _check(rc):
+    if rc != BSE_OK:
+        raise BseError(rc, bse_last_error())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class DeviceSystem:
+    """Device-resident inputs of one crystal (and its output H)."""
+
+    def __init__(self, sys, device="cuda", H=None):
+        import torch
+        self.src = sys
+        self.device = torch.device(device)
+        self.grid = tuple(sys.grid)
+        self.kmesh = tuple(sys.kmesh)
+        self.nv, self.nc = int(sys.nv), int(sys.nc)
+        self.omega_cell = float(sys.omega_cell)
+        self.ng_max = int(sys.ng_max)
+        self.ng = np.ascontiguousarray(sys.ng, dtype=np.int32)
+        self.gvec = np.ascontiguousarray(sys.gvec, dtype=np.int32)
+        self.u = torch.from_numpy(np.ascontiguousarray(sys.u)).to(self.device)
+        self.eps = torch.from_numpy(np.ascontiguousarray(sys.eps, dtype=np.float64)).to(self.device)
+        self.W = torch.from_numpy(np.ascontiguousarray(sys.W)).to(self.device)
+        self.vx = torch.from_numpy(np.ascontiguousarray(sys.vx, dtype=np.float64)).to(self.device)
+        self.nk = int(np.prod(self.kmesh))
+        self.ns = self.nk * self.nv * self.nc
+        self.H = H if H is not None else torch.empty((self.ns, self.ns), dtype=torch.complex128, device=self.device)
+
+    def struct(self) -> bse_system:
+        s = bse_system()
+        s.grid[:] = self.grid
+        s.kmesh[:] = self.kmesh
+        s.nv, s.nc = self.nv, self.nc
+        s.omega_cell = self.omega_cell
+        s.ng_max = self.ng_max
+        s.ng = self.ng.ctypes.data
+        s.gvec = self.gvec.ctypes.data
+        s.vx = self.vx.data_ptr()
+        s.u = self.u.data_ptr()
+        s.eps = self.eps.data_ptr()
+        s.W = self.W.data_ptr()
+        s.H = self.H.data_ptr() if self.H is not None else None
+        return s
+
+
+def _structs(systems: Sequence[DeviceSystem]):
+    arr = (bse_system * len(systems))()
+    for i, s in enumerate(systems):
+        arr[i] = s.struct()
+    return arr
+
+
+def bse_workspace_size(systems, precision=BSE_FP64, flags=0) -> int:
+    systems = systems if isinstance(systems, (list, tuple)) else [systems]
+    arr = _structs(systems)
+    n = lib().bse_workspace_size(arr, len(systems), int(precision), int(flags))
+    if n == 0:
+        raise BseError(-1, bse_last_error())
+    return int(n)
+
+
+def workspace(nbytes, device="cuda"):
+    import torch
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def bse_build_H(systems, precision=BSE_FP64, flags=0, ws=None, stream=None):
+    """Enqueues the build of H for each system into its .H tensor."""
+    systems = systems if isinstance(systems, (list, tuple)) else [systems]
+    arr = _structs(systems)
+    if ws is None:
+        ws = workspace(bse_workspace_size(systems, precision, flags), systems[0].device)
+    _check(lib().bse_build_H(arr, len(systems), int(precision), int(flags), _ptr(ws), ws.numel(), _stream(stream)))
+    return [s.H for s in systems]
+
+
+def bse_pair_density(system: DeviceSystem, kind, kpairs=None, ws=None, stream=None, cell=None):
+    """Pair densities of one kind (see include/bse.h) as a complex128 tensor."""
+    import torch
+    nv, nc, nk, ngm = system.nv, system.nc, system.nk, system.ng_max
+    kp = None
+    if kind == BSE_PD_EXCH:
+        shape = (nk, nv, nc, ngm)
+    elif kind in (BSE_PD_VV, BSE_PD_CC):
+        kp = np.ascontiguousarray(np.asarray(kpairs, dtype=np.int32).reshape(-1, 2))
+        nb = nv if kind == BSE_PD_VV else nc
+        shape = (len(kp), nb, nb, ngm)
+    elif kind == BSE_PD_DIPOLE:
+        shape = (nk, nv, nc, 3)
+    else:
+        raise ValueError(kind)
+    out = torch.empty(shape, dtype=torch.complex128, device=system.device)
+    if ws is None:
+        ws = workspace(bse_workspace_size([system]), system.device)
+    cell_arr = None
+    if cell is not None:
+        cell_arr = np.ascontiguousarray(cell, dtype=np.float64)
+    st = system.struct()
+    _check(lib().bse_pair_density(ctypes.byref(st), int(kind), kp.ctypes.data if kp is not None else None,
+                                  0 if kp is None else len(kp),
+                                  cell_arr.ctypes.data if cell_arr is not None else None, _ptr(out),
+                                  _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def build_H(sys_or_dev, precision="fp64", flags=0, ws=None):
+    """Convenience: H (complex128, on the GPU) of one system."""
+    d = sys_or_dev if isinstance(sys_or_dev, DeviceSystem) else DeviceSystem(sys_or_dev)
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    bse_build_H([d], p, flags, ws)
+    return d.H

@@ -1,0 +1,392 @@
+// C ABI of the BSE Hamiltonian builder: argument checks, the host planner
+// (k-pair folding, G-sphere tables, FFT windows, GEMM tile lists), workspace
+// layout and the kernel sequence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bse.h"
+#include "bse_internal.h"
+#include "kernels.h"
+
+using namespace bse;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(BSE_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// k' - k = q + G0: q on the k-shaped mesh (componentwise in [0, n)), G0 = m0 . b
+// with m0 in {-1, 0} (Sec. III.A: the q mesh has the form of the k mesh).
+void fold(const int* n, int ka, int kb, int& iq, int m0[3]) {
+  int ta[3] = {ka / (n[1] * n[2]), (ka / n[2]) % n[1], ka % n[2]};
+  int tb[3] = {kb / (n[1] * n[2]), (kb / n[2]) % n[1], kb % n[2]};
+  int r[3];
+  for (int d = 0; d < 3; ++d) {
+    const int dd = tb[d] - ta[d];
+    r[d] = imod(dd, n[d]);
+    m0[d] = (dd - r[d]) / n[d];
+  }
+  iq = (r[0] * n[1] + r[1]) * n[2] + r[2];
+}
+
+struct Plan {
+  int N1 = 0, N2 = 0, N3 = 0, nk = 0, nv = 0, nc = 0, nb = 0, ng_max = 0, ns = 0, nt = 0;
+  int lo[3] = {0, 0, 0}, F[3] = {0, 0, 0};
+  std::vector<int> gpack, ng;
+  std::vector<int4> pairs;  // (ka, kb, iq, m0p), k <= k', sorted by q
+  std::vector<int> qstart;  // [nk + 1]
+  std::vector<PdJob> jx, jv, jc;
+  std::vector<S1Tile> s1;
+  std::vector<int2> xt;
+  // byte offsets inside the workspace
+  size_t o_gpack = 0, o_ng = 0, o_pairs = 0, o_qstart = 0, o_jx = 0, o_jv = 0, o_jc = 0, o_s1 = 0, o_xt = 0;
+  size_t tables = 0, o_vs = 0, o_X = 0, o_RV = 0, o_RC = 0, o_Z = 0, total = 0;
+};
+
+int check_system(const bse_system* s) {
+  if (!s) return fail(BSE_ERR_INVALID_ARG, "system pointer is NULL");
+  for (int d = 0; d < 3; ++d) {
+    if (s->grid[d] < 1 || s->grid[d] > 4096) return fail(BSE_ERR_SHAPE, "grid[%d] = %d out of range", d, s->grid[d]);
+    if (s->kmesh[d] < 1 || s->kmesh[d] > 1024) return fail(BSE_ERR_SHAPE, "kmesh[%d] = %d out of range", d, s->kmesh[d]);
+  }
+  if (!pd_grid_supported(s->grid[1], s->grid[2]))
+    return fail(BSE_ERR_SHAPE, "grid (N2, N3) = (%d, %d) has no FFT kernel", s->grid[1], s->grid[2]);
+  if (s->nv < 1 || s->nc < 1 || s->nv > 255 || s->nc > 255) return fail(BSE_ERR_SHAPE, "nv/nc out of range");
+  if (s->ng_max < 1 || s->ng_max > 1024) return fail(BSE_ERR_SHAPE, "ng_max = %d out of range (1..1024)", s->ng_max);
+  if (!(s->omega_cell > 0.0)) return fail(BSE_ERR_INVALID_ARG, "omega_cell must be positive");
+  if (!s->ng || !s->gvec) return fail(BSE_ERR_INVALID_ARG, "ng / gvec host tables are NULL");
+  if (!s->u || !s->eps || !s->W || !s->vx) return fail(BSE_ERR_INVALID_ARG, "a device input pointer is NULL");
+  return BSE_OK;
+}
+
+int make_plan(const bse_system* s, Plan& P) {
+  int rc = check_system(s);
+  if (rc) return rc;
+  P.N1 = s->grid[0];
+  P.N2 = s->grid[1];
+  P.N3 = s->grid[2];
+  P.nk = s->kmesh[0] * s->kmesh[1] * s->kmesh[2];
+  P.nv = s->nv;
+  P.nc = s->nc;
+  P.nb = s->nv + s->nc;
+  P.ng_max = s->ng_max;
+  P.nt = s->nv * s->nc;
+  const long long ns = (long long)P.nk * P.nt;
+  if (ns > (1LL << 20)) return fail(BSE_ERR_SHAPE, "NS = %lld too large", ns);
+  P.ns = (int)ns;
+  P.ng.assign(s->ng, s->ng + P.nk);
+  P.gpack.assign((size_t)P.nk * P.ng_max, pack_m(0, 0, 0));
+  int mlo[3] = {1 << 20, 1 << 20, 1 << 20}, mhi[3] = {-(1 << 20), -(1 << 20), -(1 << 20)};
+  for (int q = 0; q < P.nk; ++q) {
+    if (P.ng[q] < 1 || P.ng[q] > P.ng_max) return fail(BSE_ERR_SHAPE, "ng[%d] = %d not in 1..ng_max", q, P.ng[q]);
+    for (int g = 0; g < P.ng[q]; ++g) {
+      const int* m = s->gvec + ((size_t)q * P.ng_max + g) * 3;
+      for (int d = 0; d < 3; ++d) {
+        if (m[d] < -500 || m[d] > 500) return fail(BSE_ERR_SHAPE, "Miller index out of range");
+        mlo[d] = std::min(mlo[d], m[d]);
+        mhi[d] = std::max(mhi[d], m[d]);
+      }
+      P.gpack[(size_t)q * P.ng_max + g] = pack_m(m[0], m[1], m[2]);
+    }
+  }
+  if (s->gvec[0] != 0 || s->gvec[1] != 0 || s->gvec[2] != 0)
+    return fail(BSE_ERR_SHAPE, "gvec[0][0] must be G = 0");
+  // kept frequencies f = m - m0 with m0 in {-1, 0} along axes with more than one k
+  const int N[3] = {P.N1, P.N2, P.N3};
+  for (int d = 0; d < 3; ++d) {
+    P.lo[d] = mlo[d];
+    const int hi = mhi[d] + (s->kmesh[d] > 1 ? 1 : 0);
+    P.F[d] = hi - P.lo[d] + 1;
+    if (P.F[d] > N[d])
+      return fail(BSE_ERR_SHAPE, "G-sphere window %d exceeds grid %d along axis %d", P.F[d], N[d], d);
+  }
+
+  // k pairs k <= k' grouped by q
+  std::vector<std::vector<int4>> byq(P.nk);
+  for (int ka = 0; ka < P.nk; ++ka)
+    for (int kb = ka; kb < P.nk; ++kb) {
+      int iq, m0[3];
+      fold(s->kmesh, ka, kb, iq, m0);
+      byq[iq].push_back(make_int4(ka, kb, iq, pack_m(m0[0], m0[1], m0[2])));
+    }
+  P.qstart.assign(P.nk + 1, 0);
+  P.pairs.clear();
+  for (int q = 0; q < P.nk; ++q) {
+    P.qstart[q] = (int)P.pairs.size();
+    P.pairs.insert(P.pairs.end(), byq[q].begin(), byq[q].end());
+  }
+  P.qstart[P.nk] = (int)P.pairs.size();
+  const int np = (int)P.pairs.size();
+
+  P.jx.resize(P.nk);
+  for (int k = 0; k < P.nk; ++k)
+    P.jx[k] = PdJob{k, k, pack_m(0, 0, 0), 0, 0, P.nv, P.nv | (P.nc << 8), k * P.nt};
+  P.jv.resize(np);
+  P.jc.resize(np);
+  for (int p = 0; p < np; ++p) {
+    const int4 pr = P.pairs[p];
+    P.jv[p] = PdJob{pr.x, pr.y, pr.w, pr.z, 0, 0, P.nv | (P.nv << 8), p * P.nv * P.nv};
+    P.jc[p] = PdJob{pr.x, pr.y, pr.w, pr.z, P.nv, P.nv, P.nc | (P.nc << 8), p * P.nc * P.nc};
+  }
+  // stage-1 tiles: per q, rows = pairs(q) * nv^2, cols = ng(q)
+  P.s1.clear();
+  for (int q = 0; q < P.nk; ++q) {
+    const int rows = (P.qstart[q + 1] - P.qstart[q]) * P.nv * P.nv;
+    const int mt = (rows + 63) / 64, nt = (P.ng[q] + 63) / 64;
+    for (int i = 0; i < mt; ++i)
+      for (int j = 0; j < nt; ++j) P.s1.push_back(S1Tile{q, i, j, 0});
+  }
+  // exchange tiles: upper tile triangle plus the first sub-diagonal (k blocks
+  // of nv*nc rows may straddle a 64-row tile boundary)
+  P.xt.clear();
+  const int T = (P.ns + 63) / 64;
+  for (int i = 0; i < T; ++i)
+    for (int j = std::max(0, i - 1); j < T; ++j) P.xt.push_back(make_int2(i, j));
+
+  // workspace layout
+  size_t o = 0;
+  auto put = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  P.o_gpack = put(P.gpack.size() * sizeof(int));
+  P.o_ng = put(P.ng.size() * sizeof(int));
+  P.o_pairs = put(P.pairs.size() * sizeof(int4));
+  P.o_qstart = put(P.qstart.size() * sizeof(int));
+  P.o_jx = put(P.jx.size() * sizeof(PdJob));
+  P.o_jv = put(P.jv.size() * sizeof(PdJob));
+  P.o_jc = put(P.jc.size() * sizeof(PdJob));
+  P.o_s1 = put(P.s1.size() * sizeof(S1Tile));
+  P.o_xt = put(P.xt.size() * sizeof(int2));
+  P.tables = o;
+  P.o_vs = put((size_t)P.ng_max * sizeof(double));
+  P.o_X = put((size_t)P.ns * P.ng_max * sizeof(double2));
+  P.o_RV = put((size_t)np * P.nv * P.nv * P.ng_max * sizeof(double2));
+  P.o_RC = put((size_t)np * P.nc * P.nc * P.ng_max * sizeof(double2));
+  P.o_Z = put((size_t)np * P.nv * P.nv * P.ng_max * sizeof(double2));
+  P.total = o;
+  return BSE_OK;
+}
+
+int upload_tables(const Plan& P, char* ws, hipStream_t st) {
+  std::vector<char> buf(P.tables, 0);
+  auto cp = [&](size_t off, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(buf.data() + off, src, bytes);
+  };
+  cp(P.o_gpack, P.gpack.data(), P.gpack.size() * sizeof(int));
+  cp(P.o_ng, P.ng.data(), P.ng.size() * sizeof(int));
+  cp(P.o_pairs, P.pairs.data(), P.pairs.size() * sizeof(int4));
+  cp(P.o_qstart, P.qstart.data(), P.qstart.size() * sizeof(int));
+  cp(P.o_jx, P.jx.data(), P.jx.size() * sizeof(PdJob));
+  cp(P.o_jv, P.jv.data(), P.jv.size() * sizeof(PdJob));
+  cp(P.o_jc, P.jc.data(), P.jc.size() * sizeof(PdJob));
+  cp(P.o_s1, P.s1.data(), P.s1.size() * sizeof(S1Tile));
+  cp(P.o_xt, P.xt.data(), P.xt.size() * sizeof(int2));
+  HIP_TRY(hipMemcpyWithStream(ws, buf.data(), P.tables, hipMemcpyHostToDevice, st));
+  return BSE_OK;
+}
+
+PdArgs pd_args(const Plan& P, const bse_system* s, char* ws) {
+  PdArgs a{};
+  a.u = reinterpret_cast<const double2*>(s->u);
+  a.nb = P.nb;
+  a.N1 = P.N1;
+  a.gpack = reinterpret_cast<const int*>(ws + P.o_gpack);
+  a.ng = reinterpret_cast<const int*>(ws + P.o_ng);
+  a.ng_max = P.ng_max;
+  a.lo2 = P.lo[1];
+  a.lo3 = P.lo[2];
+  a.F2 = P.F[1];
+  a.F3 = P.F[2];
+  a.vscale = nullptr;
+  return a;
+}
+
+int check_lds(const Plan& P) {
+  if (pd_lds_bytes(P.N1, P.N2, P.N3, P.F[1], P.F[2], P.ng_max) > 160 * 1024)
+    return fail(BSE_ERR_SHAPE, "FFT window needs more than 160 KiB of LDS");
+  return BSE_OK;
+}
+
+int build_one(const bse_system* s, int precision, int flags, char* ws, size_t ws_bytes, hipStream_t st) {
+  Plan P;
+  int rc = make_plan(s, P);
+  if (rc) return rc;
+  if ((rc = check_lds(P))) return rc;
+  if (!s->H) return fail(BSE_ERR_INVALID_ARG, "H is NULL");
+  if (ws_bytes < P.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, P.total);
+  if (precision != BSE_FP64) return fail(BSE_ERR_UNSUPPORTED, "precision %d not available", precision);
+  (void)flags;
+  if ((rc = upload_tables(P, ws, st))) return rc;
+
+  double* vs = reinterpret_cast<double*>(ws + P.o_vs);
+  HIP_TRY(launch_vscale(s->vx, P.ng[0], P.ng_max, vs, st));
+
+  PdArgs a = pd_args(P, s, ws);
+  // exchange pair densities, scaled by sqrt v(G)
+  a.jobs = reinterpret_cast<const PdJob*>(ws + P.o_jx);
+  a.out = reinterpret_cast<double2*>(ws + P.o_X);
+  a.vscale = vs;
+  HIP_TRY(launch_pair_density(a, P.N2, P.N3, (int)P.jx.size(), st));
+  a.vscale = nullptr;
+  a.jobs = reinterpret_cast<const PdJob*>(ws + P.o_jv);
+  a.out = reinterpret_cast<double2*>(ws + P.o_RV);
+  HIP_TRY(launch_pair_density(a, P.N2, P.N3, (int)P.jv.size(), st));
+  a.jobs = reinterpret_cast<const PdJob*>(ws + P.o_jc);
+  a.out = reinterpret_cast<double2*>(ws + P.o_RC);
+  HIP_TRY(launch_pair_density(a, P.N2, P.N3, (int)P.jc.size(), st));
+
+  GemmArgs g{};
+  g.X = reinterpret_cast<const double2*>(ws + P.o_X);
+  g.ns = P.ns;
+  g.ng_max = P.ng_max;
+  g.ngx = P.ng[0];
+  g.H = reinterpret_cast<double2*>(s->H);
+  g.cpref = 27.211386245988 / ((double)P.nk * s->omega_cell);
+  g.RV = reinterpret_cast<const double2*>(ws + P.o_RV);
+  g.RC = reinterpret_cast<const double2*>(ws + P.o_RC);
+  g.Z = reinterpret_cast<double2*>(ws + P.o_Z);
+  g.W = reinterpret_cast<const double2*>(s->W);
+  g.ng = reinterpret_cast<const int*>(ws + P.o_ng);
+  g.qstart = reinterpret_cast<const int*>(ws + P.o_qstart);
+  g.pairs = reinterpret_cast<const int4*>(ws + P.o_pairs);
+  g.s1tiles = reinterpret_cast<const S1Tile*>(ws + P.o_s1);
+  g.eps = s->eps;
+  g.nv = P.nv;
+  g.nc = P.nc;
+  g.nb = P.nb;
+  g.npairs = (int)P.pairs.size();
+  g.precision = precision;
+  HIP_TRY(launch_exchange(g, reinterpret_cast<const int2*>(ws + P.o_xt), (int)P.xt.size(), st));
+  HIP_TRY(launch_direct_s1(g, (int)P.s1.size(), st));
+  HIP_TRY(launch_direct_s2(g, 0, st));
+  HIP_TRY(launch_mirror(g.H, P.ns, P.nt, st));
+  return BSE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t bse_workspace_size(const bse_system* sys, int nsys, int precision, int flags) {
+  (void)precision;
+  (void)flags;
+  if (!sys || nsys < 1) return 0;
+  size_t mx = 0;
+  for (int i = 0; i < nsys; ++i) {
+    Plan P;
+    if (make_plan(&sys[i], P)) return 0;
+    mx = std::max(mx, P.total);
+  }
+  return mx;
+}
+
+int bse_pair_density(const bse_system* sys, int kind, const int* kpairs, int npairs, const double* cell,
+                     double* out, void* ws, size_t ws_bytes, void* stream) {
+  (void)cell;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  Plan P;
+  int rc = make_plan(sys, P);
+  if (rc) return rc;
+  if ((rc = check_lds(P))) return rc;
+  if (!out || !ws) return fail(BSE_ERR_INVALID_ARG, "out / ws is NULL");
+  std::vector<PdJob> jobs;
+  if (kind == BSE_PD_EXCH) {
+    jobs = P.jx;
+  } else if (kind == BSE_PD_VV || kind == BSE_PD_CC) {
+    if (!kpairs || npairs < 0) return fail(BSE_ERR_INVALID_ARG, "kpairs is NULL");
+    const int nA = kind == BSE_PD_VV ? P.nv : P.nc, b0 = kind == BSE_PD_VV ? 0 : P.nv;
+    for (int i = 0; i < npairs; ++i) {
+      const int ka = kpairs[2 * i], kb = kpairs[2 * i + 1];
+      if (ka < 0 || kb < 0 || ka >= P.nk || kb >= P.nk) return fail(BSE_ERR_INVALID_ARG, "k pair %d out of range", i);
+      int iq, m0[3];
+      fold(sys->kmesh, ka, kb, iq, m0);
+      jobs.push_back(PdJob{ka, kb, pack_m(m0[0], m0[1], m0[2]), iq, b0, b0, nA | (nA << 8), i * nA * nA});
+    }
+  } else if (kind == BSE_PD_DIPOLE) {
+    return fail(BSE_ERR_UNSUPPORTED, "dipole kind not available");
+  } else {
+    return fail(BSE_ERR_INVALID_ARG, "unknown kind %d", kind);
+  }
+  // tables: gpack, ng, jobs
+  const size_t o_g = 0, o_n = align256(P.gpack.size() * sizeof(int));
+  const size_t o_j = align256(o_n + P.ng.size() * sizeof(int));
+  const size_t need = align256(o_j + jobs.size() * sizeof(PdJob));
+  if (ws_bytes < need) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+  std::vector<char> buf(need, 0);
+  std::memcpy(buf.data() + o_g, P.gpack.data(), P.gpack.size() * sizeof(int));
+  std::memcpy(buf.data() + o_n, P.ng.data(), P.ng.size() * sizeof(int));
+  if (!jobs.empty()) std::memcpy(buf.data() + o_j, jobs.data(), jobs.size() * sizeof(PdJob));
+  char* w = static_cast<char*>(ws);
+  HIP_TRY(hipMemcpyWithStream(w, buf.data(), need, hipMemcpyHostToDevice, st));
+  PdArgs a{};
+  a.u = reinterpret_cast<const double2*>(sys->u);
+  a.nb = P.nb;
+  a.N1 = P.N1;
+  a.gpack = reinterpret_cast<const int*>(w + o_g);
+  a.ng = reinterpret_cast<const int*>(w + o_n);
+  a.ng_max = P.ng_max;
+  a.lo2 = P.lo[1];
+  a.lo3 = P.lo[2];
+  a.F2 = P.F[1];
+  a.F3 = P.F[2];
+  a.vscale = nullptr;
+  a.jobs = reinterpret_cast<const PdJob*>(w + o_j);
+  a.out = reinterpret_cast<double2*>(out);
+  HIP_TRY(launch_pair_density(a, P.N2, P.N3, (int)jobs.size(), st));
+  return BSE_OK;
+}
+
+int bse_build_H(const bse_system* sys, int nsys, int precision, int flags, void* ws, size_t ws_bytes, void* stream) {
+  if (!sys || nsys < 1) return fail(BSE_ERR_INVALID_ARG, "no systems");
+  if (!ws) return fail(BSE_ERR_INVALID_ARG, "workspace is NULL");
+  if (precision < BSE_FP64 || precision > BSE_BF16X3) return fail(BSE_ERR_INVALID_ARG, "bad precision %d", precision);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  for (int i = 0; i < nsys; ++i) {
+    int rc = build_one(&sys[i], precision, flags, static_cast<char*>(ws), ws_bytes, st);
+    if (rc) return rc;
+  }
+  return BSE_OK;
+}
+
+int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, double* deps, int precision, int flags,
+                         void* ws, size_t ws_bytes, void* stream) {
+  (void)sys; (void)dH; (void)dW; (void)deps; (void)precision; (void)flags; (void)ws; (void)ws_bytes; (void)stream;
+  return fail(BSE_ERR_UNSUPPORTED, "backward not available");
+}
+
+int bse_spectrum(int ns, int nlam, const double* E, const double* A, const double* d, double pref, int nw,
+                 double w0_eV, double w1_eV, double eta_eV, double* eps2, void* stream) {
+  (void)ns; (void)nlam; (void)E; (void)A; (void)d; (void)pref; (void)nw; (void)w0_eV; (void)w1_eV; (void)eta_eV;
+  (void)eps2; (void)stream;
+  return fail(BSE_ERR_UNSUPPORTED, "spectrum not available");
+}
+
+const char* bse_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

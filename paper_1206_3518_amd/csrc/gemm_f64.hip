@@ -1,0 +1,252 @@
+// FP64 MFMA contractions of the Hamiltonian (Sec. II.C of the paper):
+//   exchange  H[S][S'] = 2c sum_g conj(X[S][g]) X[S'][g]     (X scaled by sqrt v(G), G = 0 left out)
+//   direct 1  Z[r][n]  = sum_g conj(RV[r][g]) W_q[g][n]       (rows r: band pairs vv' of the k pairs of q)
+//   direct 2  H[(k v c),(k' v' c')] -= c sum_g Z[(kk' vv')][g] RC[(kk' cc')][g], plus e_ck - e_vk on the diagonal
+//   mirror    lower k blocks = conjugate transpose of the upper ones
+// Complex products run as four real v_mfma_f64_16x16x4 products per step.
+#include "bse_internal.h"
+#include "kernels.h"
+
+namespace bse {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int TM = 64, TN = 64, KC = 16;
+
+// 64x64 complex tile of C = op(A) * B with op(A) = conj(A) if CONJ_A.
+// A: rows a_row0.. of a row-major complex matrix, ld = lda, valid rows < a_rows.
+// B: if B_T, B[k][n] = Bt[b_row0 + n][k] (rows of a row-major matrix, ld = ldb,
+//    valid n < b_cols); else B[k][n] = Bm[k][b_col0 + n] (row-major, ld = ldb).
+// K: valid k < K.  The result lands in cre/cim (f64 MFMA accumulator layout).
+template <bool CONJ_A, bool B_T>
+__device__ __forceinline__ void tile_gemm(const double2* __restrict__ A, int lda, int a_row0, int a_rows,
+                                          const double2* __restrict__ B, int ldb, int b_off, int b_cols, int K,
+                                          d4 (&cre)[2][2], d4 (&cim)[2][2]) {
+  __shared__ double As_re[TM][KC + 1], As_im[TM][KC + 1];
+  __shared__ double Bs_re[KC][TN + 1], Bs_im[KC][TN + 1];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cre[i][j] = d4{0, 0, 0, 0};
+      cim[i][j] = d4{0, 0, 0, 0};
+    }
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    {  // A chunk: row t>>2, 4 consecutive k
+      const int r = t >> 2, c0 = (t & 3) * 4;
+      const int gr = a_row0 + r;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = k0 + c0 + i;
+        double2 v = (gr < a_rows && k < K) ? A[(size_t)gr * lda + k] : make_double2(0.0, 0.0);
+        As_re[r][c0 + i] = v.x;
+        As_im[r][c0 + i] = CONJ_A ? -v.y : v.y;
+      }
+    }
+    if (B_T) {
+      const int n = t >> 2, c0 = (t & 3) * 4;
+      const int gn = b_off + n;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = k0 + c0 + i;
+        double2 v = (n < b_cols && k < K) ? B[(size_t)gn * ldb + k] : make_double2(0.0, 0.0);
+        Bs_re[c0 + i][n] = v.x;
+        Bs_im[c0 + i][n] = v.y;
+      }
+    } else {
+      const int kr = t >> 4, c0 = (t & 15) * 4;
+      const int k = k0 + kr;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int n = c0 + i;
+        double2 v = (k < K && n < b_cols) ? B[(size_t)k * ldb + b_off + n] : make_double2(0.0, 0.0);
+        Bs_re[kr][n] = v.x;
+        Bs_im[kr][n] = v.y;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      double are[2], aim[2], bre[2], bim[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        are[i] = As_re[wr * 32 + i * 16 + (lane & 15)][kk + (lane >> 4)];
+        aim[i] = As_im[wr * 32 + i * 16 + (lane & 15)][kk + (lane >> 4)];
+        bre[i] = Bs_re[kk + (lane >> 4)][wc * 32 + i * 16 + (lane & 15)];
+        bim[i] = Bs_im[kk + (lane >> 4)][wc * 32 + i * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          cre[i][j] = mfma64(are[i], bre[j], cre[i][j]);
+          cre[i][j] = mfma64(-aim[i], bim[j], cre[i][j]);
+          cim[i][j] = mfma64(are[i], bim[j], cim[i][j]);
+          cim[i][j] = mfma64(aim[i], bre[j], cim[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ exchange
+
+__global__ __launch_bounds__(256) void k_exchange(GemmArgs g, const int2* __restrict__ tiles) {
+  const int2 tl = tiles[blockIdx.x];
+  const int r0 = tl.x * TM, c0 = tl.y * TN;
+  d4 cre[2][2], cim[2][2];
+  tile_gemm<true, true>(g.X, g.ng_max, r0, g.ns, g.X, g.ng_max, c0, g.ns - c0, g.ngx, cre, cim);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+  const double s = 2.0 * g.cpref;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + wr * 32 + i * 16 + 4 * r + (lane >> 4);
+        const int col = c0 + wc * 32 + j * 16 + (lane & 15);
+        if (row < g.ns && col < g.ns) g.H[(size_t)row * g.ns + col] = make_double2(s * cre[i][j][r], s * cim[i][j][r]);
+      }
+}
+
+hipError_t launch_exchange(const GemmArgs& g, const int2* tiles, int ntiles, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_exchange, dim3(ntiles), dim3(256), 0, st, g, tiles);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ direct, stage 1
+
+__global__ __launch_bounds__(256) void k_direct_s1(GemmArgs g) {
+  const S1Tile tl = g.s1tiles[blockIdx.x];
+  const int nv2 = g.nv * g.nv;
+  const int row_base = g.qstart[tl.iq] * nv2;
+  const int rows = (g.qstart[tl.iq + 1] - g.qstart[tl.iq]) * nv2;
+  const int K = g.ng[tl.iq];
+  const double2* A = g.RV + (size_t)row_base * g.ng_max;
+  const double2* Wq = g.W + (size_t)tl.iq * g.ng_max * g.ng_max;
+  d4 cre[2][2], cim[2][2];
+  const int r0 = tl.mt * TM, c0 = tl.nt * TN;
+  tile_gemm<true, false>(A, g.ng_max, r0, rows, Wq, g.ng_max, c0, K - c0, K, cre, cim);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+  double2* Z = g.Z + (size_t)row_base * g.ng_max;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + wr * 32 + i * 16 + 4 * r + (lane >> 4);
+        const int col = c0 + wc * 32 + j * 16 + (lane & 15);
+        if (row < rows && col < K) Z[(size_t)row * g.ng_max + col] = make_double2(cre[i][j][r], cim[i][j][r]);
+      }
+}
+
+hipError_t launch_direct_s1(const GemmArgs& g, int ntiles, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_direct_s1, dim3(ntiles), dim3(256), 0, st, g);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ direct, stage 2 + assembly
+
+__global__ __launch_bounds__(256) void k_direct_s2(GemmArgs g, int tiles_i, int tiles_j, int nitems) {
+  const int lane = threadIdx.x & 63;
+  const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= nitems) return;
+  const int per = tiles_i * tiles_j;
+  const int p = item / per, ti = (item % per) / tiles_j, tj = item % tiles_j;
+  const int4 pr = g.pairs[p];
+  const int ka = pr.x, kb = pr.y;
+  const int K = g.ng[pr.z];
+  const int nv2 = g.nv * g.nv, nc2 = g.nc * g.nc;
+  const int ia = ti * 16 + (lane & 15), jb = tj * 16 + (lane & 15);
+  const double2* zr = g.Z + ((size_t)p * nv2 + (ia < nv2 ? ia : 0)) * g.ng_max;
+  const double2* cr = g.RC + ((size_t)p * nc2 + (jb < nc2 ? jb : 0)) * g.ng_max;
+  d4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const int k = k0 + (lane >> 4);
+    const double2 a = (ia < nv2 && k < K) ? zr[k] : make_double2(0.0, 0.0);
+    const double2 b = (jb < nc2 && k < K) ? cr[k] : make_double2(0.0, 0.0);
+    cre = mfma64(a.x, b.x, cre);
+    cre = mfma64(-a.y, b.y, cre);
+    cim = mfma64(a.x, b.y, cim);
+    cim = mfma64(a.y, b.x, cim);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = ti * 16 + 4 * r + (lane >> 4);
+    const int j = tj * 16 + (lane & 15);
+    if (i < nv2 && j < nc2) {
+      const int v = i / g.nv, v2 = i % g.nv, c = j / g.nc, c2 = j % g.nc;
+      const size_t S = ((size_t)ka * g.nv + v) * g.nc + c;
+      const size_t S2 = ((size_t)kb * g.nv + v2) * g.nc + c2;
+      double2 h = g.H[S * g.ns + S2];
+      h.x -= g.cpref * cre[r];
+      h.y -= g.cpref * cim[r];
+      if (S == S2) h.x += g.eps[(size_t)ka * g.nb + g.nv + c] - g.eps[(size_t)ka * g.nb + v];
+      g.H[S * g.ns + S2] = h;
+    }
+  }
+}
+
+hipError_t launch_direct_s2(const GemmArgs& g, int dtiles, hipStream_t st) {
+  const int ti = (g.nv * g.nv + 15) / 16, tj = (g.nc * g.nc + 15) / 16;
+  const int nitems = g.npairs * ti * tj;
+  if (nitems <= 0) return hipSuccess;
+  (void)dtiles;
+  hipLaunchKernelGGL(k_direct_s2, dim3((nitems + 3) / 4), dim3(256), 0, st, g, ti, tj, nitems);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ mirror
+
+__global__ __launch_bounds__(256) void k_mirror(double2* __restrict__ H, int ns, int nt) {
+  __shared__ double2 tile[32][33];
+  const int bi = blockIdx.y, bj = blockIdx.x;  // destination tile rows bi, cols bj
+  if (bi < bj) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  // source: rows of tile bj, cols of tile bi
+#pragma unroll
+  for (int r = ty; r < 32; r += 8) {
+    const int sr = bj * 32 + r, sc = bi * 32 + tx;
+    tile[r][tx] = (sr < ns && sc < ns) ? H[(size_t)sr * ns + sc] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = ty; r < 32; r += 8) {
+    const int dr = bi * 32 + r, dc = bj * 32 + tx;
+    if (dr < ns && dc < ns && dr / nt > dc / nt) {
+      const double2 v = tile[tx][r];
+      H[(size_t)dr * ns + dc] = make_double2(v.x, -v.y);
+    }
+  }
+}
+
+hipError_t launch_mirror(double2* H, int ns, int nt, hipStream_t st) {
+  const int T = (ns + 31) / 32;
+  if (T <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mirror, dim3(T, T), dim3(256), 0, st, H, ns, nt);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ sqrt v(G)
+
+__global__ void k_vscale(const double* __restrict__ vx, int ngx, int ng_max, double* __restrict__ out) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < ng_max) out[g] = (g == 0 || g >= ngx) ? 0.0 : sqrt(vx[g]);
+}
+
+hipError_t launch_vscale(const double* vx, int ngx, int ng_max, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_vscale, dim3((ng_max + 255) / 256), dim3(256), 0, st, vx, ngx, ng_max, out);
+  return hipGetLastError();
+}
+
+}  // namespace bse

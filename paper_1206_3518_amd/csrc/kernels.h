@@ -1,0 +1,69 @@
+// Launch interfaces of the HIP kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+
+namespace bse {
+
+// One pair-density job: band block [a0, a0+nA) at k = ka (conjugated operand)
+// times [b0, b0+nB) at k' = kb, shift m0 (packed), sphere iq.  Output row of
+// band pair (ia, ib) is row0 + ia*nB + ib.
+struct PdJob {
+  int ka, kb, m0p, iq, a0, b0, nab, row0;
+};
+
+struct PdArgs {
+  const double2* u;
+  int nb;
+  int N1;
+  const int* gpack;     // [Nk][ng_max] packed Miller indices
+  const int* ng;        // [Nk]
+  int ng_max;
+  int lo2, lo3;         // lowest kept frequency (m - m0) along axes 2, 3
+  int F2, F3;           // kept window widths
+  const double* vscale; // [ng_max] output scale (sqrt v) or null
+  const PdJob* jobs;
+  double2* out;         // rows of ng_max
+};
+
+bool pd_grid_supported(int N2, int N3);
+size_t pd_lds_bytes(int N1, int N2, int N3, int F2, int F3, int ng_max);
+hipError_t launch_pair_density(const PdArgs& a, int N2, int N3, int njobs, hipStream_t st);
+
+// A GEMM tile of the direct term's first stage: q group iq, tile (mt, nt).
+struct S1Tile {
+  int iq, mt, nt, pad;
+};
+
+struct GemmArgs {
+  // exchange:   H[S][S'] = cpref2 * sum_g conj(X[S][g]) X[S'][g], upper tiles
+  // stage 1:    Z[r][n]  = sum_g conj(RV[r][g]) W[q][g][n], rows r of q group
+  // stage 2:    D[vv'][cc'] = sum_g Z[p][vv'][g] RC[p][cc'][g];  H block -= c * D (+ diag)
+  const double2* X;
+  int ns;
+  int ng_max;
+  int ngx;              // K of the exchange (= ng(q=0))
+  double2* H;
+  double cpref;         // E_h / (Nk Omega_cell)
+  const double2* RV;
+  const double2* RC;
+  double2* Z;
+  const double2* W;
+  const int* ng;
+  const int* qstart;    // [Nk+1] first pair of each q group (pairs sorted by q)
+  const int4* pairs;    // (ka, kb, iq, m0p)
+  const S1Tile* s1tiles;
+  const double* eps;
+  int nv, nc, nb, npairs;
+  int precision;
+  int w_head_fp64;      // mixed precision: q=0 head added separately in FP64
+};
+
+hipError_t launch_vscale(const double* vx, int ngx, int ng_max, double* out, hipStream_t st);
+hipError_t launch_exchange(const GemmArgs& g, const int2* tiles, int ntiles, hipStream_t st);
+hipError_t launch_direct_s1(const GemmArgs& g, int ntiles, hipStream_t st);
+hipError_t launch_direct_s2(const GemmArgs& g, int dtiles, hipStream_t st);
+hipError_t launch_mirror(double2* H, int ns, int nt, hipStream_t st);
+
+}  // namespace bse

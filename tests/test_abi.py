@@ -1,0 +1,87 @@
+"""The C-ABI library loads, exports every declared entry point and rejects bad
+arguments on the host side (no device work is enqueued).  CPU only."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import bse_synth as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    import paper_1206_3518_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return P, P.lib()
+
+
+def test_exports_every_declared_symbol():
+    P, L = _lib()
+    hdr = open(os.path.join(ROOT, "include", "bse.h")).read()
+    declared = set(re.findall(r"^(?:size_t|int|const char \*)\s*(bse_\w+)\s*\(", hdr, re.M))
+    assert declared == set(P.SYMBOLS)
+    for name in declared:
+        assert hasattr(L, name)
+
+
+def _fake_struct(P, s):
+    st = P.bse_system()
+    st.grid[:] = s.grid
+    st.kmesh[:] = s.kmesh
+    st.nv, st.nc = s.nv, s.nc
+    st.omega_cell = s.omega_cell
+    st.ng_max = s.ng_max
+    ng = np.ascontiguousarray(s.ng, dtype=np.int32)
+    gv = np.ascontiguousarray(s.gvec, dtype=np.int32)
+    st.ng = ng.ctypes.data
+    st.gvec = gv.ctypes.data
+    # device pointers are never dereferenced on these paths
+    for f in ("vx", "u", "eps", "W", "H"):
+        setattr(st, f, 0x1000)
+    return st, (ng, gv)
+
+
+def test_workspace_size_and_host_errors():
+    P, L = _lib()
+    s = B.make_config(0)
+    st, keep = _fake_struct(P, s)
+    n = L.bse_workspace_size(ctypes.byref(st), 1, 0, 0)
+    nt = s.nv * s.nc
+    npairs = s.nk * (s.nk + 1) // 2
+    # X + RV + RC + Z rows of ng_max complex
+    assert n >= 16 * s.ng_max * (s.ns + 3 * npairs * nt)
+    # workspace too small: refused before any enqueue
+    rc = L.bse_build_H(ctypes.byref(st), 1, 0, 0, ctypes.c_void_p(0x1000), n - 1, None)
+    assert rc == -3 and "workspace" in P.bse_last_error()
+    # null workspace
+    rc = L.bse_build_H(ctypes.byref(st), 1, 0, 0, None, n, None)
+    assert rc == -1
+    # bad precision
+    rc = L.bse_build_H(ctypes.byref(st), 1, 7, 0, ctypes.c_void_p(0x1000), n, None)
+    assert rc == -1
+    # unsupported grid
+    st2, keep2 = _fake_struct(P, s)
+    st2.grid[2] = 20
+    assert L.bse_build_H(ctypes.byref(st2), 1, 0, 0, ctypes.c_void_p(0x1000), n, None) == -2
+    # null input pointer
+    st3, keep3 = _fake_struct(P, s)
+    st3.u = None
+    assert L.bse_build_H(ctypes.byref(st3), 1, 0, 0, ctypes.c_void_p(0x1000), n, None) == -1
+    # sphere exceeding the grid window
+    st4, keep4 = _fake_struct(P, s)
+    gv = keep4[1].copy()
+    gv[1, 1] = (15, 0, 0)
+    keep4 = (keep4[0], gv)
+    st4.gvec = gv.ctypes.data
+    assert L.bse_build_H(ctypes.byref(st4), 1, 0, 0, ctypes.c_void_p(0x1000), n, None) == -2
+    # pair densities: bad kind and out-of-range k pair
+    out = ctypes.c_void_p(0x1000)
+    assert L.bse_pair_density(ctypes.byref(st), 9, None, 0, None, out, ctypes.c_void_p(0x1000), n, None) == -1
+    kp = np.array([[0, s.nk]], dtype=np.int32)
+    assert L.bse_pair_density(ctypes.byref(st), 1, kp.ctypes.data, 1, None, out, ctypes.c_void_p(0x1000), n,
+                              None) == -1

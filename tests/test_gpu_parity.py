@@ -1,0 +1,129 @@
+"""HIP path vs the CPU oracle on identical seeded inputs (FP64 mode)."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import bse_synth as B
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(s):
+    import paper_1206_3518_amd as P
+    return P.DeviceSystem(s)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _upper_pairs(nk):
+    return [(a, b) for a in range(nk) for b in range(a, nk)]
+
+
+def _pd_case(s, rng, npairs=24):
+    import paper_1206_3518_amd as P
+    import torch
+    d = _dev(s)
+    nk, nv, nc = s.nk, s.nv, s.nc
+    # exchange set: n_{vk,ck} for every k
+    got = P.bse_pair_density(d, P.BSE_PD_EXCH).cpu().numpy()
+    items = [(k, v, k, nv + c) for k in range(nk) for v in range(nv) for c in range(nc)]
+    ref = O.pair_density_items(s, items).reshape(nk, nv, nc, s.ng_max)
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() <= 1e-12 * scale
+    # direct sets on random ordered pairs (both k <= k' and k > k')
+    kp = rng.integers(0, nk, size=(npairs, 2)).astype(np.int32)
+    kp[0] = (0, 0)
+    kp[1] = (nk - 1, 0)
+    for kind, nbnd, off in ((P.BSE_PD_VV, nv, 0), (P.BSE_PD_CC, nc, nv)):
+        got = P.bse_pair_density(d, kind, kp).cpu().numpy()
+        items = [(int(a), off + i, int(b), off + j) for a, b in kp for i in range(nbnd) for j in range(nbnd)]
+        ref = O.pair_density_items(s, items).reshape(len(kp), nbnd, nbnd, s.ng_max)
+        scale = np.abs(ref).max()
+        assert np.abs(got - ref).max() <= 1e-12 * scale, kind
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("case", ["cfg0", "cfg1", "ragged"])
+def test_pair_densities_match_oracle(case):
+    rng = np.random.default_rng(1)
+    if case == "cfg0":
+        s = B.make_config(0)
+    elif case == "cfg1":
+        s = B.make_config(1)
+    else:  # non-cubic grid, odd mesh, nv != nc
+        s = B.make_system(B.cell_fcc(7.5), (10, 12, 16), (3, 1, 2), 3, 2, 3.0, seed=21)
+    _say(f"pair densities {case}: grid {s.grid} kmesh {s.kmesh} ng_max {s.ng_max}")
+    _pd_case(s, rng)
+
+
+def _check_H(s, H, Href, tag):
+    K = Href - np.diag(np.diag(Href))
+    err = np.abs(H - Href).max()
+    _say(f"{tag}: max|dH| = {err:.3e} eV, max|K| = {np.abs(K).max():.3e} eV")
+    assert err <= 1e-12 * max(np.abs(Href).max(), 1.0)
+    assert np.abs(H - H.conj().T).max() <= 1e-12 * np.abs(K).max() + 1e-15
+    e = np.linalg.eigvalsh(H)[:10]
+    er = np.linalg.eigvalsh(Href)[:10]
+    assert np.all(np.abs(e - er) <= 1e-6 * np.abs(er))
+
+
+@pytest.mark.parametrize("case", ["cfg0", "cfg1", "ragged", "one_k", "one_band"])
+def test_build_H_fp64_matches_oracle(case):
+    import paper_1206_3518_amd as P
+    import torch
+    if case == "cfg0":
+        s = B.make_config(0)
+    elif case == "cfg1":
+        s = B.make_config(1)
+    elif case == "ragged":  # nv*nc = 6 does not divide the 64-row tiles; m0 = -1 on two axes
+        s = B.make_system(B.cell_fcc(7.5), (10, 12, 16), (3, 1, 2), 3, 2, 3.0, seed=21)
+    elif case == "one_k":
+        s = B.make_system(B.cell_sc(8.0), (8, 8, 8), (1, 1, 1), 2, 3, 2.0, seed=22)
+    else:
+        s = B.make_system(B.cell_sc(8.0), (16, 16, 16), (2, 1, 2), 1, 1, 2.5, seed=23)
+    _say(f"build_H {case}: grid {s.grid} kmesh {s.kmesh} nv {s.nv} nc {s.nc}")
+    H = P.build_H(s, "fp64")
+    torch.cuda.synchronize()
+    Href = O.build_H(s)
+    _check_H(s, H.cpu().numpy(), Href, case)
+
+
+def test_build_H_is_deterministic():
+    import paper_1206_3518_amd as P
+    import torch
+    s = B.make_config(0)
+    d = _dev(s)
+    a = P.build_H(d).clone()
+    b = P.build_H(d).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_full_size_si_blocks_match_oracle():
+    """32^3 grid, 8^3 k mesh, 4+4 bands (H dimension 8192) in the launch
+    configuration the benchmark times; oracle blocks on a sample of k pairs."""
+    import paper_1206_3518_amd as P
+    import torch
+    s = B.make_config(2)
+    _say(f"full size: NS = {s.ns}, ng_max = {s.ng_max}")
+    H = P.build_H(s, "fp64")
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    nk, nt = s.nk, s.nv * s.nc
+    blocks = [(0, 0), (nk - 1, nk - 1), (0, nk - 1), (nk - 1, 0), (7, 300)]
+    blocks += [tuple(int(x) for x in rng.integers(0, nk, 2)) for _ in range(7)]
+    ref = O.build_blocks(s, blocks)
+    for (ka, kb), r in zip(blocks, ref):
+        g = H[ka * nt:(ka + 1) * nt, kb * nt:(kb + 1) * nt].cpu().numpy()
+        assert np.abs(g - r).max() <= 1e-12 * max(np.abs(r).max(), 1.0), (ka, kb)
+    Hc = H.cpu().numpy() if False else None
+    # Hermiticity on a sampled strip
+    strip = H[:512].cpu().numpy()
+    col = H[:, :512].cpu().numpy()
+    assert np.abs(strip[:, :512] - col[:512].conj().T).max() < 1e-15
