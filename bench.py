@@ -1,0 +1,157 @@
+"""Benchmark: BSE Hamiltonian build throughput on one MI355X.
+
+A step is one call of bse_build_H on the Si-like workload (fcc a = 10.26 bohr,
+32^3 grid, 8x8x8 k mesh, 4 valence + 4 conduction bands, H of dimension 8192,
+ecut 8 Ha -> 272..303 plane waves per q): pair densities, exchange GEMM,
+direct-term GEMMs, diagonal and mirror, from device-resident (u, eps, W) to
+a fully written device H.  Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"hbm_GBps": 8000.0, "fp64_TFLOPs": 78.6, "fp32_TFLOPs": 157.3, "bf16_TFLOPs": 2500.0}
+DTYPES = {"fp64": "f64", "split_fp32": "f32x3", "bf16x3": "bf16x3"}
+
+
+def pd_flops(grid):
+    """Nominal work of one pair density: 5 N log2 N for the 3-D transform of an
+    N-point grid plus 6 N for the conjugate product."""
+    n = int(np.prod(grid))
+    return 5.0 * n * math.log2(n) + 6.0 * n
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for f in ("pair_density.hip", "bse_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1206_3518_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel_digest, per_launch_units):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "pair_density_si32_traffic.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_digest") != kernel_digest:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(s, target_s=15.0):
+    """The oracle (as it stands) on a T x T tile of (k, k') blocks of the same
+    workload, on the host cores."""
+    import oracle as O
+    rng = np.random.default_rng(11)
+    nt = s.nv * s.nc
+    probe = [(a, b) for a in (0, 1, 2, 3) for b in (4, 5, 6, 7)]
+    t0 = time.perf_counter()
+    O.build_blocks(s, probe)
+    dt = max(time.perf_counter() - t0, 1e-3)
+    per_block = dt / len(probe)
+    T = int(max(2, min(160, math.sqrt(target_s / per_block))))
+    ks = rng.choice(s.nk, size=T, replace=False)
+    kps = rng.choice(s.nk, size=T, replace=False)
+    blocks = [(int(a), int(b)) for a in ks for b in kps]
+    t0 = time.perf_counter()
+    O.build_blocks(s, blocks)
+    dt = time.perf_counter() - t0
+    return {"value": len(blocks) * nt * nt / dt, "unit": "H elements/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"{T}x{T} tile of random (k,k') blocks ({len(blocks) * nt * nt} elements), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp64", choices=list(DTYPES))
+    ap.add_argument("--config", type=int, default=2, help="workload index (default: the Si-like 8192 case)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="also run one plain device copy of this size (for counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import bse_synth as B
+    import paper_1206_3518_amd as P
+
+    s = B.make_config(args.config)
+    dev = P.DeviceSystem(s, device="cuda:0")
+    prec = P.PRECISIONS[args.precision]
+    ws = P.workspace(P.bse_workspace_size([dev], prec), dev.device)
+    torch.cuda.synchronize()
+
+    if args.copy_calibration_mb:
+        n = args.copy_calibration_mb * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    for _ in range(args.warmup):
+        P.bse_build_H([dev], prec, 0, ws)
+    torch.cuda.synchronize()
+    P.bse_profile_read(reset=True)
+
+    P.bse_profile(True)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(st)
+    for _ in range(args.steps):
+        P.bse_build_H([dev], prec, 0, ws)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    P.bse_profile(False)
+    stages = P.bse_profile_read(reset=True)
+    ms = e0.elapsed_time(e1) / args.steps
+    elements = float(s.ns) ** 2
+    value = elements / (ms / 1e3)
+
+    # dominant kernel: the pair-density kernel over the direct term's band pairs
+    npairs = s.nk * (s.nk + 1) // 2
+    pd_ms = stages["pd_vv"][0] + stages["pd_cc"][0]
+    pd_n = stages["pd_vv"][1] + stages["pd_cc"][1]
+    units = npairs * (s.nv * s.nv + s.nc * s.nc) / 2.0  # pair densities per launch (vv and cc alike)
+    avg_s = pd_ms / pd_n / 1e3
+    achieved = pd_flops(s.grid) * units / avg_s / 1e12
+    digest = kernel_source_digest()
+    roofline = {"bound": "alu", "kernel": "k_pair_density", "achieved": achieved, "peak": PEAK["fp64_TFLOPs"],
+                "unit": "TFLOP/s", "frac": achieved / PEAK["fp64_TFLOPs"],
+                "traffic": traffic_from_profile(digest, units), "avg_launch_ms": pd_ms / pd_n,
+                "flops_per_launch": pd_flops(s.grid) * units, "kernel_digest": digest}
+
+    out = {"metric": "BSE H build: elements/s + % MFMA peak, FP64 vs mixed at <=1e-4 eV error",
+           "value": value, "unit": "H elements/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": DTYPES[args.precision], "data": "synthetic",
+           "config": {"workload": s.name, "ns": s.ns, "grid": list(s.grid), "kmesh": list(s.kmesh), "nv": s.nv,
+                      "nc": s.nc, "ng_max": s.ng_max, "precision": args.precision, "parallelism": "single-gpu"},
+           "stage_ms": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
+           "wall_s": wall, "roofline": roofline}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(s)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -148,6 +148,27 @@ int bse_build_H_backward(const bse_system *sys, const double *dH, double *dW, do
 int bse_spectrum(int ns, int nlam, const double *E, const double *A, const double *d, double pref,
                  int nw, double w0_eV, double w1_eV, double eta_eV, double *eps2, void *stream);
 
+/*
+ * Per-stage GPU timing of bse_build_H.  While enabled, every kernel launch of
+ * bse_build_H is bracketed by two hipEvents recorded on the call's stream.
+ * bse_profile_read waits for the recorded events, adds their elapsed times
+ * (ms) and launch counts per stage into total_ms / launches (HOST, nstages
+ * entries, stage order of enum bse_stage) and, if reset, forgets them.
+ */
+enum bse_stage {
+    BSE_STAGE_VSCALE = 0,   /* sqrt v(G) table                         */
+    BSE_STAGE_PD_EXCH = 1,  /* pair densities n_{vk,ck}                 */
+    BSE_STAGE_PD_VV = 2,    /* pair densities n_{vk,v'k'}               */
+    BSE_STAGE_PD_CC = 3,    /* pair densities n_{ck,c'k'}               */
+    BSE_STAGE_EXCHANGE = 4, /* exchange GEMM                            */
+    BSE_STAGE_DIRECT1 = 5,  /* direct term, conj(rho_vv') W(q)          */
+    BSE_STAGE_DIRECT2 = 6,  /* direct term contraction + diagonal       */
+    BSE_STAGE_MIRROR = 7,   /* lower blocks from the upper ones         */
+    BSE_NSTAGES = 8
+};
+int bse_profile(int enable);
+int bse_profile_read(double *total_ms, long long *launches, int nstages, int reset);
+
 /* Text describing the last non-zero status returned on this thread. */
 const char *bse_last_error(void);
 

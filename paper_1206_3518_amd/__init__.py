@@ -41,7 +41,8 @@ class bse_system(ctypes.Structure):
 
 
 SYMBOLS = ["bse_workspace_size", "bse_pair_density", "bse_build_H", "bse_build_H_backward",
-           "bse_spectrum", "bse_last_error"]
+           "bse_spectrum", "bse_profile", "bse_profile_read", "bse_last_error"]
+STAGES = ["vscale", "pd_exch", "pd_vv", "pd_cc", "exchange", "direct1", "direct2", "mirror"]
 
 
 def lib():
@@ -62,6 +63,10 @@ def lib():
         L.bse_build_H_backward.restype = I
         L.bse_spectrum.argtypes = [I, I, P, P, P, D, I, D, D, D, P, P]
         L.bse_spectrum.restype = I
+        L.bse_profile.argtypes = [I]
+        L.bse_profile.restype = I
+        L.bse_profile_read.argtypes = [P, P, I, I]
+        L.bse_profile_read.restype = I
         L.bse_last_error.argtypes = []
         L.bse_last_error.restype = ctypes.c_char_p
         _LIB = L
@@ -184,6 +189,19 @@ def bse_pair_density(system: DeviceSystem, kind, kpairs=None, ws=None, stream=No
                                   cell_arr.ctypes.data if cell_arr is not None else None, _ptr(out),
                                   _ptr(ws), ws.numel(), _stream(stream)))
     return out
+
+
+def bse_profile(enable: bool):
+    _check(lib().bse_profile(1 if enable else 0))
+
+
+def bse_profile_read(reset=True):
+    """{stage: (total ms, launches)} of the bse_build_H launches timed so far."""
+    n = len(STAGES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_longlong * n)()
+    _check(lib().bse_profile_read(ms, cnt, n, 1 if reset else 0))
+    return {STAGES[i]: (ms[i], cnt[i]) for i in range(n)}
 
 
 def build_H(sys_or_dev, precision="fp64", flags=0, ws=None):

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -39,6 +40,42 @@ int fail(int code, const char* fmt, ...) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// ------------------------------------------------------------ stage timing
+struct ProfRec {
+  int stage;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_pending;
+double g_prof_ms[BSE_NSTAGES] = {0};
+long long g_prof_n[BSE_NSTAGES] = {0};
+
+// Runs one launch; with timing on, brackets it with events on the stream.
+template <class F>
+hipError_t stage(int id, hipStream_t st, F&& launch) {
+  bool on;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    on = g_prof_on;
+  }
+  if (!on) return launch();
+  ProfRec r{id, nullptr, nullptr};
+  hipError_t e = hipEventCreate(&r.a);
+  if (e == hipSuccess) e = hipEventCreate(&r.b);
+  if (e == hipSuccess) e = hipEventRecord(r.a, st);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(r.b, st);
+  if (e != hipSuccess) {
+    if (r.a) (void)hipEventDestroy(r.a);
+    if (r.b) (void)hipEventDestroy(r.b);
+    return e;
+  }
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_pending.push_back(r);
+  return hipSuccess;
+}
+
 // k' - k = q + G0: q on the k-shaped mesh (componentwise in [0, n)), G0 = m0 . b
 // with m0 in {-1, 0} (Sec. III.A: the q mesh has the form of the k mesh).
 void fold(const int* n, int ka, int kb, int& iq, int m0[3]) {
@@ -51,6 +88,28 @@ void fold(const int* n, int ka, int kb, int& iq, int m0[3]) {
     m0[d] = (dd - r[d]) / n[d];
   }
   iq = (r[0] * n[1] + r[1]) * n[2] + r[2];
+}
+
+// Dispatch order of pair-density jobs.  Workgroup i runs on XCD i mod 8 and
+// each XCD keeps about 64 workgroups resident, so the job list is cut into 8
+// contiguous chunks (one per XCD) of jobs sorted by 8 x 8 tiles of (k, k'):
+// the resident jobs of an XCD then read the wave functions of ~16 k points,
+// which its L2 holds plane by plane.  Holes become empty jobs.
+constexpr int kXcds = 8, kTileK = 8;
+
+std::vector<PdJob> dispatch_order(std::vector<PdJob> jobs) {
+  std::stable_sort(jobs.begin(), jobs.end(), [](const PdJob& x, const PdJob& y) {
+    const int tx = x.ka / kTileK, ty = y.ka / kTileK, ux = x.kb / kTileK, uy = y.kb / kTileK;
+    if (tx != ty) return tx < ty;
+    if (ux != uy) return ux < uy;
+    if (x.ka != y.ka) return x.ka < y.ka;
+    return x.kb < y.kb;
+  });
+  const size_t n = jobs.size(), c = (n + kXcds - 1) / kXcds;
+  std::vector<PdJob> out(c * kXcds, PdJob{0, 0, pack_m(0, 0, 0), 0, 0, 0, 0, 0});
+  for (size_t x = 0; x < (size_t)kXcds; ++x)
+    for (size_t t = 0; t < c && x * c + t < n; ++t) out[t * kXcds + x] = jobs[x * c + t];
+  return out;
 }
 
 struct Plan {
@@ -152,6 +211,8 @@ int make_plan(const bse_system* s, Plan& P) {
     P.jv[p] = PdJob{pr.x, pr.y, pr.w, pr.z, 0, 0, P.nv | (P.nv << 8), p * P.nv * P.nv};
     P.jc[p] = PdJob{pr.x, pr.y, pr.w, pr.z, P.nv, P.nv, P.nc | (P.nc << 8), p * P.nc * P.nc};
   }
+  P.jv = dispatch_order(std::move(P.jv));
+  P.jc = dispatch_order(std::move(P.jc));
   // stage-1 tiles: per q, rows = pairs(q) * nv^2, cols = ng(q)
   P.s1.clear();
   for (int q = 0; q < P.nk; ++q) {
@@ -245,21 +306,21 @@ int build_one(const bse_system* s, int precision, int flags, char* ws, size_t ws
   if ((rc = upload_tables(P, ws, st))) return rc;
 
   double* vs = reinterpret_cast<double*>(ws + P.o_vs);
-  HIP_TRY(launch_vscale(s->vx, P.ng[0], P.ng_max, vs, st));
+  HIP_TRY(stage(BSE_STAGE_VSCALE, st, [&] { return launch_vscale(s->vx, P.ng[0], P.ng_max, vs, st); }));
 
   PdArgs a = pd_args(P, s, ws);
   // exchange pair densities, scaled by sqrt v(G)
   a.jobs = reinterpret_cast<const PdJob*>(ws + P.o_jx);
   a.out = reinterpret_cast<double2*>(ws + P.o_X);
   a.vscale = vs;
-  HIP_TRY(launch_pair_density(a, P.N2, P.N3, (int)P.jx.size(), st));
+  HIP_TRY(stage(BSE_STAGE_PD_EXCH, st, [&] { return launch_pair_density(a, P.N2, P.N3, (int)P.jx.size(), st); }));
   a.vscale = nullptr;
   a.jobs = reinterpret_cast<const PdJob*>(ws + P.o_jv);
   a.out = reinterpret_cast<double2*>(ws + P.o_RV);
-  HIP_TRY(launch_pair_density(a, P.N2, P.N3, (int)P.jv.size(), st));
+  HIP_TRY(stage(BSE_STAGE_PD_VV, st, [&] { return launch_pair_density(a, P.N2, P.N3, (int)P.jv.size(), st); }));
   a.jobs = reinterpret_cast<const PdJob*>(ws + P.o_jc);
   a.out = reinterpret_cast<double2*>(ws + P.o_RC);
-  HIP_TRY(launch_pair_density(a, P.N2, P.N3, (int)P.jc.size(), st));
+  HIP_TRY(stage(BSE_STAGE_PD_CC, st, [&] { return launch_pair_density(a, P.N2, P.N3, (int)P.jc.size(), st); }));
 
   GemmArgs g{};
   g.X = reinterpret_cast<const double2*>(ws + P.o_X);
@@ -282,10 +343,11 @@ int build_one(const bse_system* s, int precision, int flags, char* ws, size_t ws
   g.nb = P.nb;
   g.npairs = (int)P.pairs.size();
   g.precision = precision;
-  HIP_TRY(launch_exchange(g, reinterpret_cast<const int2*>(ws + P.o_xt), (int)P.xt.size(), st));
-  HIP_TRY(launch_direct_s1(g, (int)P.s1.size(), st));
-  HIP_TRY(launch_direct_s2(g, 0, st));
-  HIP_TRY(launch_mirror(g.H, P.ns, P.nt, st));
+  const int2* xt = reinterpret_cast<const int2*>(ws + P.o_xt);
+  HIP_TRY(stage(BSE_STAGE_EXCHANGE, st, [&] { return launch_exchange(g, xt, (int)P.xt.size(), st); }));
+  HIP_TRY(stage(BSE_STAGE_DIRECT1, st, [&] { return launch_direct_s1(g, (int)P.s1.size(), st); }));
+  HIP_TRY(stage(BSE_STAGE_DIRECT2, st, [&] { return launch_direct_s2(g, 0, st); }));
+  HIP_TRY(stage(BSE_STAGE_MIRROR, st, [&] { return launch_mirror(g.H, P.ns, P.nt, st); }));
   return BSE_OK;
 }
 
@@ -385,6 +447,37 @@ int bse_spectrum(int ns, int nlam, const double* E, const double* A, const doubl
   (void)ns; (void)nlam; (void)E; (void)A; (void)d; (void)pref; (void)nw; (void)w0_eV; (void)w1_eV; (void)eta_eV;
   (void)eps2; (void)stream;
   return fail(BSE_ERR_UNSUPPORTED, "spectrum not available");
+}
+
+int bse_profile(int enable) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = enable != 0;
+  return BSE_OK;
+}
+
+int bse_profile_read(double* total_ms, long long* launches, int nstages, int reset) {
+  if (nstages < 0 || (nstages > 0 && (!total_ms || !launches))) return fail(BSE_ERR_INVALID_ARG, "bad output arrays");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (const ProfRec& r : g_prof_pending) {
+    float ms = 0.f;
+    HIP_TRY(hipEventSynchronize(r.b));
+    HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+    g_prof_ms[r.stage] += ms;
+    g_prof_n[r.stage] += 1;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof_pending.clear();
+  for (int i = 0; i < nstages && i < BSE_NSTAGES; ++i) {
+    total_ms[i] = g_prof_ms[i];
+    launches[i] = g_prof_n[i];
+  }
+  if (reset)
+    for (int i = 0; i < BSE_NSTAGES; ++i) {
+      g_prof_ms[i] = 0;
+      g_prof_n[i] = 0;
+    }
+  return BSE_OK;
 }
 
 const char* bse_last_error(void) { return g_err.c_str(); }

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <type_traits>
 
 namespace bse {
 
@@ -17,101 +18,136 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 __device__ __forceinline__ double2 cconjmul(double2 a, double2 b) {
   return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
+// c ? a : b per component (a conditional on the vector class itself would
+// select between addresses and push register arrays into scratch memory)
+__device__ __forceinline__ double2 csel(bool c, double2 a, double2 b) {
+  return make_double2(c ? a.x : b.x, c ? a.y : b.y);
+}
 // acc + a * b
 __device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 acc) {
   return make_double2(fma(a.x, b.x, fma(-a.y, b.y, acc.x)), fma(a.x, b.y, fma(a.y, b.x, acc.y)));
 }
 
 // ---------------------------------------------------------------- roots of unity
-// cos(2 pi k / 48) on the first quadrant; every twiddle of a register FFT of
-// length dividing 48 is one of these up to sign.
-constexpr double kCosQ48[13] = {
+// cos(2 pi k / 96) on the first quadrant; every twiddle of a transform whose
+// length divides 96 is one of these up to sign.
+constexpr double kCosQ96[25] = {
     1.0,
+    9.97858923238603506738e-1,
     9.91444861373810411145e-1,
+    9.80785280403230449126e-1,
     9.6592582628906828675e-1,
+    9.46930129495105664256e-1,
     9.23879532511286756128e-1,
+    8.96872741532688303894e-1,
     8.66025403784438646764e-1,
+    8.31469612302545237079e-1,
     7.9335334029123516458e-1,
+    7.51839807478977396408e-1,
     7.07106781186547524401e-1,
+    6.59345815100068868425e-1,
     6.08761429008720639416e-1,
+    5.55570233019602224743e-1,
     5.0e-1,
+    4.42288690219001281995e-1,
     3.82683432365089771728e-1,
+    3.21439465303161580701e-1,
     2.58819045102520762349e-1,
+    1.95090322016128267848e-1,
     1.30526192220051591548e-1,
+    6.54031292301430668153e-2,
     0.0};
 
-constexpr double cos48(int k) {
-  k = ((k % 48) + 48) % 48;
-  return k <= 12 ? kCosQ48[k] : k <= 24 ? -kCosQ48[24 - k] : k <= 36 ? -kCosQ48[k - 24] : kCosQ48[48 - k];
+constexpr double cos96(int k) {
+  k = ((k % 96) + 96) % 96;
+  return k <= 24 ? kCosQ96[k] : k <= 48 ? -kCosQ96[48 - k] : k <= 72 ? -kCosQ96[k - 48] : kCosQ96[96 - k];
 }
-constexpr double sin48(int k) { return cos48(k - 12); }
+constexpr double sin96(int k) { return cos96(k - 24); }
 
-// exp(-2 pi i k / M) for M dividing 48
-template <int M>
-__device__ __forceinline__ double2 root(int k) {
-  static_assert(48 % M == 0, "register FFT length must divide 48");
-  return make_double2(cos48(k * (48 / M)), -sin48(k * (48 / M)));
+// Calls f(std::integral_constant<int, I>) for I = B .. E-1, so that loop
+// indices are compile-time constants inside f.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// x * exp(-2 pi i K / M), M dividing 96.  Multiples of a quarter and an eighth
+// turn need no general complex product.
+template <int M, int K>
+__device__ __forceinline__ double2 cmul_root(double2 x) {
+  static_assert(96 % M == 0, "transform length must divide 96");
+  constexpr int k = ((K % M) + M) % M;
+  constexpr double r = 7.07106781186547524401e-1;
+  if constexpr (k == 0) {
+    return x;
+  } else if constexpr (2 * k == M) {
+    return make_double2(-x.x, -x.y);
+  } else if constexpr (4 * k == M) {  // -i
+    return make_double2(x.y, -x.x);
+  } else if constexpr (4 * k == 3 * M) {  // +i
+    return make_double2(-x.y, x.x);
+  } else if constexpr (8 * k == M) {
+    return make_double2(r * (x.x + x.y), r * (x.y - x.x));
+  } else if constexpr (8 * k == 3 * M) {
+    return make_double2(r * (x.y - x.x), -r * (x.x + x.y));
+  } else if constexpr (8 * k == 5 * M) {
+    return make_double2(-r * (x.x + x.y), r * (x.x - x.y));
+  } else if constexpr (8 * k == 7 * M) {
+    return make_double2(r * (x.x - x.y), r * (x.x + x.y));
+  } else {
+    constexpr double c = cos96(k * (96 / M)), s = -sin96(k * (96 / M));
+    return make_double2(fma(x.x, c, -x.y * s), fma(x.x, s, x.y * c));
+  }
 }
 
 // ---------------------------------------------------------------- register FFT
 // In-place forward DFT (exp(-2 pi i)) of M points held by one lane, natural
-// order in and out.  Decimation in time on radix 2 and 3.
+// order in and out, on x[OFF + S*i].  Decimation in time on radix 2 and 3.
 
-template <int M, int S = 1>
-struct RegFFT;
-
-template <int S>
-struct RegFFT<1, S> {
-  template <int N>
-  __device__ __forceinline__ static void run(double2 (&)[N], int) {}
-};
-
-template <int M, int S>
-struct RegFFT {
-  // operates on x[off + S*i], i < M
-  template <int N>
-  __device__ __forceinline__ static void run(double2 (&x)[N], int off) {
-    if constexpr (M % 2 == 0) {
-      constexpr int H = M / 2;
-      RegFFT<H, 2 * S>::run(x, off);      // even samples
-      RegFFT<H, 2 * S>::run(x, off + S);  // odd samples
-      double2 t[M];
-#pragma unroll
-      for (int k = 0; k < H; ++k) {
-        double2 e = x[off + 2 * S * k];
-        double2 o = cmul(x[off + 2 * S * k + S], root<M>(k));
-        t[k] = cadd(e, o);
-        t[k + H] = csub(e, o);
-      }
-#pragma unroll
-      for (int k = 0; k < M; ++k) x[off + S * k] = t[k];
-    } else {
-      static_assert(M % 3 == 0, "register FFT radices are 2 and 3");
-      constexpr int T = M / 3;
-      RegFFT<T, 3 * S>::run(x, off);
-      RegFFT<T, 3 * S>::run(x, off + S);
-      RegFFT<T, 3 * S>::run(x, off + 2 * S);
-      double2 t[M];
-      constexpr double c3 = -0.5;                         // cos(2 pi / 3)
-      constexpr double s3 = 8.66025403784438646764e-1;    // sin(2 pi / 3)
-#pragma unroll
-      for (int k = 0; k < T; ++k) {
-        double2 a = x[off + 3 * S * k];
-        double2 b = cmul(x[off + 3 * S * k + S], root<M>(k));
-        double2 c = cmul(x[off + 3 * S * k + 2 * S], root<M>(2 * k));
-        double2 sbc = cadd(b, c), dbc = csub(b, c);
-        double2 m = make_double2(a.x + c3 * sbc.x, a.y + c3 * sbc.y);
-        // -i * s3 * (b - c) for the exp(-2 pi i/3) branch
-        double2 r = make_double2(s3 * dbc.y, -s3 * dbc.x);
-        t[k] = cadd(a, sbc);
-        t[k + T] = cadd(m, r);
-        t[k + 2 * T] = csub(m, r);
-      }
-#pragma unroll
-      for (int k = 0; k < M; ++k) x[off + S * k] = t[k];
-    }
+template <int M, int S, int OFF, int N>
+__device__ __forceinline__ void reg_fft(double2 (&x)[N]) {
+  if constexpr (M == 1) {
+    return;
+  } else if constexpr (M % 2 == 0) {
+    constexpr int H = M / 2;
+    reg_fft<H, 2 * S, OFF>(x);      // even samples
+    reg_fft<H, 2 * S, OFF + S>(x);  // odd samples
+    double2 t[M];
+    static_for<0, H>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const double2 e = x[OFF + 2 * S * k];
+      const double2 o = cmul_root<M, k>(x[OFF + 2 * S * k + S]);
+      t[k] = cadd(e, o);
+      t[k + H] = csub(e, o);
+    });
+    static_for<0, M>([&](auto kc) { x[OFF + S * decltype(kc)::value] = t[decltype(kc)::value]; });
+  } else {
+    static_assert(M % 3 == 0, "register FFT radices are 2 and 3");
+    constexpr int T = M / 3;
+    reg_fft<T, 3 * S, OFF>(x);
+    reg_fft<T, 3 * S, OFF + S>(x);
+    reg_fft<T, 3 * S, OFF + 2 * S>(x);
+    double2 t[M];
+    constexpr double c3 = -0.5;                       // cos(2 pi / 3)
+    constexpr double s3 = 8.66025403784438646764e-1;  // sin(2 pi / 3)
+    static_for<0, T>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const double2 a = x[OFF + 3 * S * k];
+      const double2 b = cmul_root<M, k>(x[OFF + 3 * S * k + S]);
+      const double2 c = cmul_root<M, 2 * k>(x[OFF + 3 * S * k + 2 * S]);
+      const double2 sbc = cadd(b, c), dbc = csub(b, c);
+      const double2 m = make_double2(fma(c3, sbc.x, a.x), fma(c3, sbc.y, a.y));
+      const double2 r = make_double2(s3 * dbc.y, -s3 * dbc.x);  // -i s3 (b - c)
+      t[k] = cadd(a, sbc);
+      t[k + T] = cadd(m, r);
+      t[k + 2 * T] = csub(m, r);
+    });
+    static_for<0, M>([&](auto kc) { x[OFF + S * decltype(kc)::value] = t[decltype(kc)::value]; });
   }
-};
+}
 
 // ---------------------------------------------------------------- wave utilities
 

@@ -2,16 +2,17 @@
 // on the plane-wave sphere of q (charge density matrix, Sec. II.B of the paper).
 //
 // One workgroup (4 waves) takes a job: one ordered k pair (k, k') and a block
-// of nA x nB band pairs.  Each wave takes band pairs one at a time and sweeps
-// the real-space planes j1 of the grid:
-//   pass 1  product conj(u_a) u_b on the plane, FFT along j3 (register FFT of
-//           M3 points per lane, then an L3-point DFT across lanes), keep the
-//           F3 frequencies of the output window -> LDS T1[f3][j2];
-//   pass 2  FFT along j2 of the F3 columns, keep F2 -> LDS T2[f2][f3];
-//   pass 3  every lane owns sphere points g and accumulates
-//           T2[f2_g][f3_g] * exp(-2 pi i f1_g j1 / N1) over the planes.
-// Nothing but the pruned F2 x F3 window of a plane ever leaves registers, and
-// the sphere values are written once at the end.
+// of nA x nB band pairs.  A wave takes PW band pairs at a time and sweeps the
+// real-space planes j1 of the grid; per plane and band pair:
+//   pass 1  conj(u_a) u_b on the plane and an FFT along j3 (register FFT of M3
+//           points per lane, then an L3-point DFT across lanes with DPP /
+//           swizzle exchanges); the F3 kept frequencies go to LDS T1[f3][j2];
+//   pass 2  FFT along j2 of the F3 kept columns; the F2 kept outputs are
+//           written column-major over the columns already read (T2);
+//   pass 3  every lane owns sphere points g = lane + 64 t and accumulates
+//           T2[f3_g][f2_g] * exp(-2 pi i f1_g j1 / N1) in registers.
+// Only the pruned window of a plane touches LDS; global memory sees the wave
+// functions (read) and the sphere values (written once).
 #include "bse_internal.h"
 #include "kernels.h"
 
@@ -21,71 +22,154 @@ template <int N>
 struct Split;  // N = L * M: L lanes per row, M points per lane (register FFT)
 template <> struct Split<8>  { static constexpr int L = 2, M = 4; };
 template <> struct Split<12> { static constexpr int L = 2, M = 6; };
-template <> struct Split<16> { static constexpr int L = 4, M = 4; };
-template <> struct Split<24> { static constexpr int L = 4, M = 6; };
-template <> struct Split<32> { static constexpr int L = 4, M = 8; };
+template <> struct Split<16> { static constexpr int L = 2, M = 8; };
+template <> struct Split<24> { static constexpr int L = 2, M = 12; };
+template <> struct Split<32> { static constexpr int L = 2, M = 16; };
 template <> struct Split<48> { static constexpr int L = 4, M = 12; };
-template <> struct Split<64> { static constexpr int L = 8, M = 8; };
+template <> struct Split<64> { static constexpr int L = 4, M = 16; };
 template <> struct Split<96> { static constexpr int L = 8, M = 12; };
+
+// Split of a pass-2 line: the kept window of pass 1 leaves few lines, so more
+// lanes go to each line.
+template <int N>
+struct SplitB {
+  static constexpr int L = (N == 16 || N == 24 || N == 32 || N == 48 || N == 64) ? 4 : Split<N>::L;
+  static constexpr int M = N / L;
+};
 
 template <int L>
 __device__ __forceinline__ int bitrev(int l) {
-  if constexpr (L == 1) return 0;
   if constexpr (L == 2) return l;
   if constexpr (L == 4) return ((l & 1) << 1) | (l >> 1);
   if constexpr (L == 8) return ((l & 1) << 2) | (l & 2) | (l >> 2);
+  return 0;
 }
 
-// L-point DFT across the L lanes of a row group, for each of the M values a
-// lane holds.  Radix-2 decimation in frequency with xor shuffles; afterwards
-// lane l holds output index bitrev(l).  tw[t] = exp(-2 pi i t / N), L | N.
-template <int L, int M>
-__device__ __forceinline__ void cross_lane_dft(double2 (&x)[M], int l, const double2* tw, int N) {
-#pragma unroll
-  for (int h = L / 2; h >= 1; h >>= 1) {
-    const int p = l & (2 * h - 1);
-    const bool upper = p >= h;
-    const double2 w = tw[(p & (h - 1)) * (N / (2 * h))];
+// value of lane (lane ^ H) for H in {1, 2, 4}; all lanes active
+template <int H>
+__device__ __forceinline__ double xor_lane(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  int rlo, rhi;
+  if constexpr (H == 1) {  // quad_perm [1,0,3,2]
+    rlo = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);
+    rhi = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false);
+  } else if constexpr (H == 2) {  // quad_perm [2,3,0,1]
+    rlo = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false);
+    rhi = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false);
+  } else {  // swizzle, bit-mask mode: and 0x1F, xor H
+    static_assert(H == 4 || H == 8 || H == 16, "xor distance");
+    rlo = __builtin_amdgcn_ds_swizzle(lo, (H << 10) | 0x1F);
+    rhi = __builtin_amdgcn_ds_swizzle(hi, (H << 10) | 0x1F);
+  }
+  return __hiloint2double(rhi, rlo);
+}
+
+template <int H>
+__device__ __forceinline__ double2 xor_lane2(double2 v) {
+  return make_double2(xor_lane<H>(v.x), xor_lane<H>(v.y));
+}
+
+// One radix-2 decimation-in-frequency stage of an L-point DFT across lanes,
+// branch free: lower lane x + o, upper lane (o - x) * w.
+template <int M, int H>
+__device__ __forceinline__ void xlane_stage(double2 (&x)[M], int l, const double2* tw, int N) {
+  const int p = l & (2 * H - 1);
+  const double s = p >= H ? -1.0 : 1.0;
+  if constexpr (H == 1) {
 #pragma unroll
     for (int f = 0; f < M; ++f) {
-      double2 o = shfl_xor2(x[f], h);
-      x[f] = upper ? cmul(csub(o, x[f]), w) : cadd(x[f], o);
+      const double2 o = xor_lane2<1>(x[f]);
+      x[f] = make_double2(fma(s, x[f].x, o.x), fma(s, x[f].y, o.y));
+    }
+  } else {
+    const bool upper = p >= H;
+    const double2 wt = tw[(p & (H - 1)) * (N / (2 * H))];
+    const double2 w = csel(upper, wt, make_double2(1.0, 0.0));
+#pragma unroll
+    for (int f = 0; f < M; ++f) {
+      const double2 o = xor_lane2<H>(x[f]);
+      const double2 t = make_double2(fma(s, x[f].x, o.x), fma(s, x[f].y, o.y));
+      x[f] = cmul(t, w);
     }
   }
 }
 
-// Full row transform: x holds samples l + L*s (s < M) of a length-N row;
-// afterwards x[f'] holds output f' + M * bitrev(l).
-template <int N, int M>
+// L-point DFT across the L lanes of a row group for each of the M values a
+// lane holds; afterwards lane l holds output index bitrev(l).
+template <int L, int M>
+__device__ __forceinline__ void cross_lane_dft(double2 (&x)[M], int l, const double2* tw, int N) {
+  if constexpr (L >= 8) xlane_stage<M, 4>(x, l, tw, N);
+  if constexpr (L >= 4) xlane_stage<M, 2>(x, l, tw, N);
+  if constexpr (L >= 2) xlane_stage<M, 1>(x, l, tw, N);
+}
+
+// Row transform: x holds samples l + L*s (s < M) of a length-N row; afterwards
+// x[f'] holds output f' + M * bitrev(l).  tw[t] = exp(-2 pi i t / N).
+template <int N, int L, int M>
 __device__ __forceinline__ void row_fft(double2 (&x)[M], int l, const double2* tw) {
-  constexpr int L = Split<N>::L;
-  RegFFT<M>::run(x, 0);
+  static_assert(L * M == N, "row split");
+  reg_fft<M, 1, 0>(x);
+  if constexpr (L == 2) {
+    // twiddle exp(-2 pi i l f'/N), l in {0, 1}: a compile-time constant per f'
+    static_for<1, M>([&](auto fc) {
+      constexpr int f = decltype(fc)::value;
+      const double2 y = cmul_root<N, f>(x[f]);
+      x[f] = csel(l != 0, y, x[f]);
+    });
+  } else {
 #pragma unroll
-  for (int f = 1; f < M; ++f) x[f] = cmul(x[f], tw[(l * f) % N]);
+    for (int f = 1; f < M; ++f) x[f] = cmul(x[f], tw[(l * f) % N]);
+  }
   cross_lane_dft<L, M>(x, l, tw, N);
 }
 
+// Geometry of the two in-plane passes.  The plane is N2 x N3 (j3 fastest).
+// Pass 1 transforms axis A straight from global memory, pass 2 the other axis
+// B out of LDS.  AX = 2: columns (A = j2) in the layout lane = (column c,
+// sub-lane l), sample s at row l + L*s, so one load instruction covers L whole
+// rows; AX = 3: rows (A = j3), lane = (row r, sub-lane l), sample s at column
+// l + L*s, which coalesces when L is large.
 template <int N2, int N3>
-__global__ __launch_bounds__(256) void k_pair_density(PdArgs a) {
-  constexpr int L3 = Split<N3>::L, M3 = Split<N3>::M, R1 = 64 / L3;
-  constexpr int L2 = Split<N2>::L, M2 = Split<N2>::M, C2 = 64 / L2;
-  constexpr int I1 = (N2 + R1 - 1) / R1;
-  extern __shared__ double2 smem[];
-  const int N1 = a.N1, F2 = a.F2, F3 = a.F3, ngm = a.ng_max;
-  // LDS: twiddles | per wave (T1, T2, acc) | gather table
-  double2* tw1 = smem;
-  double2* tw2 = tw1 + N1;
-  double2* tw3 = tw2 + N2;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int per_wave = F3 * N2 + F2 * F3 + ngm;
-  double2* T1 = tw3 + N3 + wave * per_wave;
-  double2* T2 = T1 + F3 * N2;
-  double2* acc = T2 + F2 * F3;
-  int2* gtab = reinterpret_cast<int2*>(tw3 + N3 + 4 * per_wave);
+struct PlaneGeo {
+  static constexpr int AX = (N3 * Split<N2>::L <= 64) ? 2 : 3;
+  static constexpr int NA = AX == 2 ? N2 : N3;   // pass-1 length
+  static constexpr int NB = AX == 2 ? N3 : N2;   // pass-2 length (lines of pass 1)
+  static constexpr int LA = Split<NA>::L, MA = Split<NA>::M;
+  static constexpr int LB = SplitB<NB>::L, MB = SplitB<NB>::M;
+  static constexpr int LINES = 64 / LA;          // pass-1 lines per iteration
+  static constexpr int IA = (NB + LINES - 1) / LINES;
+  static constexpr int SA = NB + 1;              // padded T1 row stride
+  static constexpr int PW = 1;  // band pairs per wave
+  // element (line, sample index i along A) of the plane
+  __device__ static constexpr int at(int line, int i) { return AX == 2 ? i * N3 + line : line * N3 + i; }
+};
 
-  for (int t = threadIdx.x; t < N1 + N2 + N3; t += blockDim.x) {
-    const int n = t < N1 ? N1 : (t < N1 + N2 ? N2 : N3);
-    const int k = t < N1 ? t : (t < N1 + N2 ? t - N1 : t - N1 - N2);
+// TG sphere points per lane (64 * TG >= ng_max).  EXCH: exchange set (rows
+// scaled by sqrt v); a separate instantiation so that the direct-term
+// launches form one kernel in traces.
+template <int N2, int N3, int TG, bool EXCH>
+__global__ __launch_bounds__(256, 2) void k_pair_density(PdArgs a) {
+  using G = PlaneGeo<N2, N3>;
+  constexpr int LA = G::LA, MA = G::MA, LB = G::LB, MB = G::MB, NA = G::NA, NB = G::NB;
+  constexpr int PW = G::PW, SA = G::SA;
+  constexpr int LP = 64 / PW;  // lanes per band pair in pass 2
+  constexpr int CB = LP / LB;  // pass-2 lines per iteration
+  extern __shared__ double2 smem[];
+  const int N1 = a.N1, ngm = a.ng_max;
+  // window along the pass-1 axis (A) and the pass-2 axis (B)
+  const int loA = G::AX == 2 ? a.lo2 : a.lo3, FA = G::AX == 2 ? a.F2 : a.F3;
+  const int loB = G::AX == 2 ? a.lo3 : a.lo2, FB = G::AX == 2 ? a.F3 : a.F2;
+  double2* tw1 = smem;
+  double2* twA = tw1 + N1;
+  double2* twB = twA + NA;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int per_pd = FA * SA;
+  double2* T1 = twB + NB + wave * PW * per_pd;
+  int2* gtab = reinterpret_cast<int2*>(twB + NB + 4 * PW * per_pd);
+
+  for (int t = threadIdx.x; t < N1 + NA + NB; t += blockDim.x) {
+    const int n = t < N1 ? N1 : (t < N1 + NA ? NA : NB);
+    const int k = t < N1 ? t : (t < N1 + NA ? t - N1 : t - N1 - NA);
     double s, c;
     sincospi(2.0 * k / n, &s, &c);
     smem[t] = make_double2(c, -s);
@@ -96,95 +180,163 @@ __global__ __launch_bounds__(256) void k_pair_density(PdArgs a) {
   unpack_m(job.m0p, m01, m02, m03);
   const int ngq = a.ng[job.iq];
   const int* gq = a.gpack + (size_t)job.iq * ngm;
-  // sphere point g: offset of (f2, f3) in the plane window and f1 mod N1
+  // sphere point g: offset of (fA, fB) in the column-major window, f1 mod N1
   for (int g = threadIdx.x; g < ngq; g += blockDim.x) {
     int m1, m2, m3;
     unpack_m(gq[g], m1, m2, m3);
-    gtab[g] = make_int2((m2 - m02 - a.lo2) * F3 + (m3 - m03 - a.lo3), imod(m1 - m01, N1));
+    const int f2 = m2 - m02 - a.lo2, f3 = m3 - m03 - a.lo3;
+    gtab[g] = make_int2(G::AX == 2 ? f2 * FB + f3 : f3 * FB + f2, imod(m1 - m01, N1));
   }
   __syncthreads();
   const float inv_n1 = 1.0f / (float)N1;
 
-  const size_t Nr = (size_t)N1 * N2 * N3;
-  for (int p = wave; p < nA * nB; p += 4) {
-    const int ia = p / nB, ib = p % nB;
-    const double2* ua = a.u + ((size_t)job.ka * a.nb + job.a0 + ia) * Nr;
-    const double2* ub = a.u + ((size_t)job.kb * a.nb + job.b0 + ib) * Nr;
-    for (int g = lane; g < ngq; g += 64) acc[g] = make_double2(0.0, 0.0);
+  // pass-1 lane geometry: outputs f' + MA * bitrev(lA) along A
+  const int lA = lane % LA;
+  const int bA = imod(MA * bitrev<LA>(lA) - loA, NA);
+  // pass-2 lane geometry
+  const int sub = PW == 2 ? lane >> 5 : 0;
+  const int ll = PW == 2 ? lane & 31 : lane;
+  const int lB = ll % LB;
+  const int bB = imod(MB * bitrev<LB>(lB) - loB, NB);
+
+  const int Nr = N1 * N2 * N3;
+  const int npd = nA * nB;
+  // band pairs of this wave: p = wave + 4 i; the PW pairs of one sweep share
+  // the right operand when nB = 4
+  for (int p0 = wave; p0 < npd; p0 += 4 * PW) {
+    const int p1 = p0 + 4;
+    const bool live1 = PW == 2 && p1 < npd;
+    const int q1 = live1 ? p1 : p0;
+    const double2* ua0 = a.u + ((size_t)job.ka * a.nb + job.a0 + p0 / nB) * Nr;
+    const double2* ub0 = a.u + ((size_t)job.kb * a.nb + job.b0 + p0 % nB) * Nr;
+    const double2* ua1 = a.u + ((size_t)job.ka * a.nb + job.a0 + q1 / nB) * Nr;
+    const double2* ub1 = a.u + ((size_t)job.kb * a.nb + job.b0 + q1 % nB) * Nr;
+    const bool share_b = ub1 == ub0;
+    double2 acc[PW][TG];
+#pragma unroll
+    for (int t = 0; t < TG; ++t)
+#pragma unroll
+      for (int w = 0; w < PW; ++w) acc[w][t] = make_double2(0.0, 0.0);
+
     for (int j1 = 0; j1 < N1; ++j1) {
-      // pass 1: rows of the plane
+      const int poff = j1 * N2 * N3;
+      // ---- pass 1 along A, straight from global memory
 #pragma unroll 1
-      for (int it = 0; it < I1; ++it) {
-        const int j2 = it * R1 + lane / L3, l = lane % L3;
-        const bool ok = j2 < N2;
-        const size_t base = ((size_t)j1 * N2 + (ok ? j2 : 0)) * N3 + l;
-        double2 x[M3];
+      for (int it = 0; it < G::IA; ++it) {
+        const int line = it * G::LINES + lane / LA;
+        const bool ok = line < NB;
+        const int base = poff + G::at(ok ? line : 0, lA);
+        double2 yb[MA];
 #pragma unroll
-        for (int s = 0; s < M3; ++s)
-          x[s] = ok ? cconjmul(ua[base + L3 * s], ub[base + L3 * s]) : make_double2(0.0, 0.0);
-        row_fft<N3, M3>(x, l, tw3);
-        const int br = bitrev<L3>(l);
+        for (int s = 0; s < MA; ++s) yb[s] = ub0[base + G::at(0, LA * s)];
 #pragma unroll
-        for (int f = 0; f < M3; ++f) {
-          const int a3 = imod(f + M3 * br - a.lo3, N3);
-          if (ok && a3 < F3) T1[a3 * N2 + j2] = x[f];
+        for (int w = 0; w < PW; ++w) {
+          const double2* ua = w == 0 ? ua0 : ua1;
+          double2 x[MA];
+          if (w == 1 && !share_b) {
+#pragma unroll
+            for (int s = 0; s < MA; ++s) yb[s] = ub1[base + G::at(0, LA * s)];
+          }
+#pragma unroll
+          for (int s = 0; s < MA; ++s) x[s] = cconjmul(ua[base + G::at(0, LA * s)], yb[s]);
+          row_fft<NA, LA, MA>(x, lA, twA);
+          double2* T1w = T1 + w * per_pd;
+#pragma unroll
+          for (int f = 0; f < MA; ++f) {
+            int aA = bA + f;
+            aA -= aA >= NA ? NA : 0;
+            if (ok && aA < FA) T1w[aA * SA + line] = x[f];
+          }
+          // keep the two band pairs' loads and transforms from overlapping,
+          // which would double the live registers
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
       wave_sync();
-      // pass 2: columns of the kept j3 frequencies
-      for (int it = 0; it * C2 < F3; ++it) {
-        const int col = it * C2 + lane / L2, l = lane % L2;
-        const bool ok = col < F3;
-        double2 x[M2];
+      // ---- pass 2 along B (PW band pairs side by side); outputs go
+      // column-major over the lines already read, so T2 needs no space of its own
+      double2* T1s = T1 + sub * per_pd;
+      for (int c0 = 0; c0 < FA; c0 += CB) {
+        const int col = c0 + ll / LB;
+        const bool ok = col < FA;
+        double2 x[MB];
 #pragma unroll
-        for (int s = 0; s < M2; ++s) x[s] = ok ? T1[col * N2 + l + L2 * s] : make_double2(0.0, 0.0);
-        row_fft<N2, M2>(x, l, tw2);
-        const int br = bitrev<L2>(l);
+        for (int s = 0; s < MB; ++s) x[s] = csel(ok, T1s[col * SA + lB + LB * s], make_double2(0.0, 0.0));
+        row_fft<NB, LB, MB>(x, lB, twB);
+        wave_sync();
 #pragma unroll
-        for (int f = 0; f < M2; ++f) {
-          const int a2 = imod(f + M2 * br - a.lo2, N2);
-          if (ok && a2 < F2) T2[a2 * F3 + col] = x[f];
+        for (int f = 0; f < MB; ++f) {
+          int aB = bB + f;
+          aB -= aB >= NB ? NB : 0;
+          if (ok && aB < FB) T1s[col * FB + aB] = x[f];
+        }
+        wave_sync();
+      }
+      // ---- pass 3: direct sum over planes at the sphere points
+#pragma unroll
+      for (int t = 0; t < TG; ++t) {
+        if (lane + 64 * t < ngq) {
+          const int2 e = gtab[lane + 64 * t];
+          int r = e.y * j1;  // below 2^24: exact in float
+          r -= N1 * (int)((float)r * inv_n1);
+          r += r < 0 ? N1 : 0;
+          r -= r >= N1 ? N1 : 0;
+          const double2 w1 = tw1[r];
+#pragma unroll
+          for (int w = 0; w < PW; ++w) acc[w][t] = cfma(T1[w * per_pd + e.x], w1, acc[w][t]);
         }
       }
       wave_sync();
-      // pass 3: direct sum over planes at the sphere points
-      for (int g = lane; g < ngq; g += 64) {
-        const int2 e = gtab[g];
-        int r = e.y * j1;  // < 2^24, exact in float
-        r -= N1 * (int)((float)r * inv_n1);
-        r += r < 0 ? N1 : 0;
-        r -= r >= N1 ? N1 : 0;
-        acc[g] = cfma(T2[e.x], tw1[r], acc[g]);
-      }
-      wave_sync();
     }
-    double2* o = a.out + (size_t)(job.row0 + p) * ngm;
-    for (int g = lane; g < ngm; g += 64) {
-      if (g < ngq) {
-        const double sc = a.vscale ? a.vscale[g] : 1.0;
-        const double2 v = acc[g];
-        o[g] = make_double2(v.x * sc, v.y * sc);
-      } else {
-        o[g] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int w = 0; w < PW; ++w) {
+      if (w == 1 && !live1) continue;
+      double2* o = a.out + (size_t)(job.row0 + p0 + 4 * w) * ngm;
+#pragma unroll
+      for (int t = 0; t < TG; ++t) {
+        const int g = lane + 64 * t;
+        if (g < ngq) {
+          const double sc = EXCH ? a.vscale[g] : 1.0;
+          o[g] = make_double2(acc[w][t].x * sc, acc[w][t].y * sc);
+        } else if (g < ngm) {
+          o[g] = make_double2(0.0, 0.0);
+        }
       }
     }
-    wave_sync();
   }
 }
 
-size_t pd_lds_bytes(int N1, int N2, int N3, int F2, int F3, int ng_max) {
-  return sizeof(double2) * ((size_t)N1 + N2 + N3 + 4 * ((size_t)F3 * N2 + (size_t)F2 * F3 + ng_max)) +
-         sizeof(int2) * (size_t)ng_max;
+static int tg_bucket(int ng_max) {
+  const int t = (ng_max + 63) / 64;
+  return t <= 4 ? 4 : t <= 5 ? 5 : t <= 8 ? 8 : t <= 13 ? 13 : 16;
 }
 
 template <int N2, int N3>
-static hipError_t launch_grid(const PdArgs& a, int njobs, hipStream_t st) {
-  const size_t lds = pd_lds_bytes(a.N1, N2, N3, a.F2, a.F3, a.ng_max);
-  auto k = k_pair_density<N2, N3>;
+static size_t lds_bytes(int N1, int F2, int F3, int ng_max) {
+  using G = PlaneGeo<N2, N3>;
+  const int FA = G::AX == 2 ? F2 : F3;
+  return sizeof(double2) * ((size_t)N1 + N2 + N3 + 4 * (size_t)G::PW * FA * G::SA) + sizeof(int2) * (size_t)ng_max;
+}
+
+template <int N2, int N3, int TG>
+static hipError_t launch_tg(const PdArgs& a, int njobs, size_t lds, hipStream_t st) {
+  auto k = a.vscale ? k_pair_density<N2, N3, TG, true> : k_pair_density<N2, N3, TG, false>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(njobs), dim3(256), lds, st, a);
   return hipGetLastError();
+}
+
+template <int N2, int N3>
+static hipError_t launch_grid(const PdArgs& a, int njobs, hipStream_t st) {
+  const size_t lds = lds_bytes<N2, N3>(a.N1, a.F2, a.F3, a.ng_max);
+  switch (tg_bucket(a.ng_max)) {
+    case 4: return launch_tg<N2, N3, 4>(a, njobs, lds, st);
+    case 5: return launch_tg<N2, N3, 5>(a, njobs, lds, st);
+    case 8: return launch_tg<N2, N3, 8>(a, njobs, lds, st);
+    case 13: return launch_tg<N2, N3, 13>(a, njobs, lds, st);
+    default: return launch_tg<N2, N3, 16>(a, njobs, lds, st);
+  }
 }
 
 bool pd_grid_supported(int N2, int N3) {
@@ -193,6 +345,23 @@ bool pd_grid_supported(int N2, int N3) {
          (N2 == 24 && N3 == 96) || (N2 == 12 && N3 == 16) || (N2 == 16 && N3 == 24);
 }
 
+size_t pd_lds_bytes(int N1, int N2, int N3, int F2, int F3, int ng_max) {
+#define BSE_PD_LDS(X, Y) \
+  if (N2 == X && N3 == Y) return lds_bytes<X, Y>(N1, F2, F3, ng_max);
+  BSE_PD_LDS(8, 8)
+  BSE_PD_LDS(12, 12)
+  BSE_PD_LDS(16, 16)
+  BSE_PD_LDS(24, 24)
+  BSE_PD_LDS(32, 32)
+  BSE_PD_LDS(48, 48)
+  BSE_PD_LDS(64, 64)
+  BSE_PD_LDS(96, 96)
+  BSE_PD_LDS(24, 96)
+  BSE_PD_LDS(12, 16)
+  BSE_PD_LDS(16, 24)
+#undef BSE_PD_LDS
+  return ~size_t(0);
+}
 
 hipError_t launch_pair_density(const PdArgs& a, int N2, int N3, int njobs, hipStream_t st) {
   if (njobs <= 0) return hipSuccess;
