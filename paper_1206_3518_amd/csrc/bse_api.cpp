@@ -301,7 +301,6 @@ int build_one(const bse_system* s, int precision, int flags, char* ws, size_t ws
   if ((rc = check_lds(P))) return rc;
   if (!s->H) return fail(BSE_ERR_INVALID_ARG, "H is NULL");
   if (ws_bytes < P.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, P.total);
-  if (precision != BSE_FP64) return fail(BSE_ERR_UNSUPPORTED, "precision %d not available", precision);
   (void)flags;
   if ((rc = upload_tables(P, ws, st))) return rc;
 
@@ -343,10 +342,17 @@ int build_one(const bse_system* s, int precision, int flags, char* ws, size_t ws
   g.nb = P.nb;
   g.npairs = (int)P.pairs.size();
   g.precision = precision;
+  g.w_head_fp64 = precision != BSE_FP64;
   const int2* xt = reinterpret_cast<const int2*>(ws + P.o_xt);
-  HIP_TRY(stage(BSE_STAGE_EXCHANGE, st, [&] { return launch_exchange(g, xt, (int)P.xt.size(), st); }));
-  HIP_TRY(stage(BSE_STAGE_DIRECT1, st, [&] { return launch_direct_s1(g, (int)P.s1.size(), st); }));
-  HIP_TRY(stage(BSE_STAGE_DIRECT2, st, [&] { return launch_direct_s2(g, 0, st); }));
+  if (precision == BSE_FP64) {
+    HIP_TRY(stage(BSE_STAGE_EXCHANGE, st, [&] { return launch_exchange(g, xt, (int)P.xt.size(), st); }));
+    HIP_TRY(stage(BSE_STAGE_DIRECT1, st, [&] { return launch_direct_s1(g, (int)P.s1.size(), st); }));
+    HIP_TRY(stage(BSE_STAGE_DIRECT2, st, [&] { return launch_direct_s2(g, 0, st); }));
+  } else {
+    HIP_TRY(stage(BSE_STAGE_EXCHANGE, st, [&] { return launch_exchange_mx(g, xt, (int)P.xt.size(), st); }));
+    HIP_TRY(stage(BSE_STAGE_DIRECT1, st, [&] { return launch_direct_s1_mx(g, (int)P.s1.size(), st); }));
+    HIP_TRY(stage(BSE_STAGE_DIRECT2, st, [&] { return launch_direct_s2_mx(g, st); }));
+  }
   HIP_TRY(stage(BSE_STAGE_MIRROR, st, [&] { return launch_mirror(g.H, P.ns, P.nt, st); }));
   return BSE_OK;
 }

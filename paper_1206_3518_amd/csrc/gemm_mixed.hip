@@ -1,0 +1,383 @@
+// Mixed-precision versions of the exchange and direct-term contractions.
+// Every FP64 operand x is split as x = hi + lo with hi = round(x) and
+// lo = round(x - hi) in the narrow type; a product a*b is taken as
+// hi*hi + hi*lo + lo*hi (the lo*lo term is dropped) with FP32 accumulation:
+//   BSE_SPLIT_FP32: FP32 parts, v_mfma_f32_16x16x4_f32
+//   BSE_BF16X3:     BF16 parts, v_mfma_f32_16x16x32_bf16
+// The q = 0 head of W, the transition-energy diagonal and the final update of
+// H stay FP64.
+#include <hip/hip_bf16.h>
+
+#include "../../include/bse.h"
+#include "bse_internal.h"
+#include "kernels.h"
+
+namespace bse {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+
+constexpr int MTM = 64, MTN = 64, MKC = 32;
+
+__device__ __forceinline__ unsigned short bf16_bits(float f) {
+  __hip_bfloat16 b = __float2bfloat16(f);
+  return *reinterpret_cast<unsigned short*>(&b);
+}
+__device__ __forceinline__ float bf16_value(unsigned short u) {
+  return __uint_as_float(((unsigned int)u) << 16);
+}
+
+template <int P>
+struct Split;
+// FP32 parts
+template <>
+struct Split<BSE_SPLIT_FP32> {
+  typedef float T;
+  __device__ static void split(double x, float& h, float& l) {
+    h = (float)x;
+    l = (float)(x - (double)h);
+  }
+};
+// BF16 parts, stored as raw 16-bit patterns
+template <>
+struct Split<BSE_BF16X3> {
+  typedef unsigned short T;
+  __device__ static void split(double x, unsigned short& h, unsigned short& l) {
+    h = bf16_bits((float)x);
+    l = bf16_bits((float)(x - (double)bf16_value(h)));
+  }
+};
+
+// LDS image of a 64 x 32 complex operand tile: 4 planes (re hi, re lo, im hi,
+// im lo), each [64 rows][32 k] with k contiguous, row stride padded.
+template <int P>
+struct TileLds {
+  typedef typename Split<P>::T T;
+  static constexpr int STRIDE = P == BSE_BF16X3 ? 40 : 33;
+  T v[4][64 * STRIDE];
+};
+
+// Stores 8 consecutive k values (row r, k0..k0+7) of one operand after the split.
+template <int P>
+__device__ __forceinline__ void put8(TileLds<P>& L, int r, int k0, const double2 (&x)[8], bool conj) {
+  typedef typename Split<P>::T T;
+  T h[4][8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    Split<P>::split(x[i].x, h[0][i], h[1][i]);
+    Split<P>::split(conj ? -x[i].y : x[i].y, h[2][i], h[3][i]);
+  }
+#pragma unroll
+  for (int pl = 0; pl < 4; ++pl)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) L.v[pl][r * TileLds<P>::STRIDE + k0 + i] = h[pl][i];
+}
+
+// One 64x64 complex tile of C = op(A) * B with split operands.
+// A: rows of a row-major complex matrix (ld lda, valid rows < a_rows).
+// B: if B_T, B[k][n] = Bt[b_off + n][k] (valid n < b_cols); else
+//    B[k][n] = Bm[k][b_off + n].  Valid k < K.  zero_head: B[0][0] := 0 when
+//    the tile holds it (the q = 0 head is added in FP64 elsewhere).
+template <int P, bool CONJ_A, bool B_T>
+__device__ __forceinline__ void tile_gemm_mx(const double2* __restrict__ A, int lda, int a_row0, int a_rows,
+                                             const double2* __restrict__ B, int ldb, int b_off, int b_cols, int K,
+                                             bool zero_head, f4 (&cre)[2][2], f4 (&cim)[2][2]) {
+  extern __shared__ char smem_mx[];
+  TileLds<P>& As = *reinterpret_cast<TileLds<P>*>(smem_mx);
+  TileLds<P>& Bs = *reinterpret_cast<TileLds<P>*>(smem_mx + sizeof(TileLds<P>));
+  constexpr int ST = TileLds<P>::STRIDE;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cre[i][j] = f4{0, 0, 0, 0};
+      cim[i][j] = f4{0, 0, 0, 0};
+    }
+  const int r = t >> 2, kq = (t & 3) * 8;
+  for (int k0 = 0; k0 < K; k0 += MKC) {
+    {
+      double2 x[8];
+      const int gr = a_row0 + r;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int k = k0 + kq + i;
+        x[i] = (gr < a_rows && k < K) ? A[(size_t)gr * lda + k] : make_double2(0.0, 0.0);
+      }
+      put8<P>(As, r, kq, x, CONJ_A);
+    }
+    {
+      double2 x[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int k = k0 + kq + i;
+        if (B_T)
+          x[i] = (r < b_cols && k < K) ? B[(size_t)(b_off + r) * ldb + k] : make_double2(0.0, 0.0);
+        else
+          x[i] = (r < b_cols && k < K) ? B[(size_t)k * ldb + b_off + r] : make_double2(0.0, 0.0);
+        if (zero_head && k == 0 && b_off + r == 0) x[i] = make_double2(0.0, 0.0);
+      }
+      put8<P>(Bs, r, kq, x, false);
+    }
+    __syncthreads();
+    if constexpr (P == BSE_BF16X3) {
+      s8 a[2][4], b[2][4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl) {
+          a[i][pl] = *reinterpret_cast<const s8*>(&As.v[pl][(wr * 32 + i * 16 + (lane & 15)) * ST + 8 * (lane >> 4)]);
+          b[i][pl] = *reinterpret_cast<const s8*>(&Bs.v[pl][(wc * 32 + i * 16 + (lane & 15)) * ST + 8 * (lane >> 4)]);
+        }
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        s8 nih = a[i][2] ^ (short)0x8000, nil = a[i][3] ^ (short)0x8000;  // -Im(a) parts
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          f4 cr = cre[i][j], ci = cim[i][j];
+          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][0], cr, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][1], cr, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1], b[j][0], cr, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, b[j][2], cr, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, b[j][3], cr, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nil, b[j][2], cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][2], ci, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][3], ci, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1], b[j][2], ci, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][2], b[j][0], ci, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][2], b[j][1], ci, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][3], b[j][0], ci, 0, 0, 0);
+          cre[i][j] = cr;
+          cim[i][j] = ci;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < MKC; kk += 4) {
+        float a[2][4], b[2][4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int pl = 0; pl < 4; ++pl) {
+            a[i][pl] = As.v[pl][(wr * 32 + i * 16 + (lane & 15)) * ST + kk + (lane >> 4)];
+            b[i][pl] = Bs.v[pl][(wc * 32 + i * 16 + (lane & 15)) * ST + kk + (lane >> 4)];
+          }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            f4 cr = cre[i][j], ci = cim[i][j];
+            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][0], b[j][0], cr, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][0], b[j][1], cr, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][1], b[j][0], cr, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[i][2], b[j][2], cr, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[i][2], b[j][3], cr, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[i][3], b[j][2], cr, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][0], b[j][2], ci, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][0], b[j][3], ci, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][1], b[j][2], ci, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][2], b[j][0], ci, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][2], b[j][1], ci, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][3], b[j][0], ci, 0, 0, 0);
+            cre[i][j] = cr;
+            cim[i][j] = ci;
+          }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// f32 MFMA accumulator layout: lane l, register r holds D[4 (l/16) + r][l % 16]
+__device__ __forceinline__ int acc_row(int lane, int r) { return 4 * (lane >> 4) + r; }
+
+template <int P>
+__global__ __launch_bounds__(256) void k_exchange_mx(GemmArgs g, const int2* __restrict__ tiles) {
+  const int2 tl = tiles[blockIdx.x];
+  const int r0 = tl.x * MTM, c0 = tl.y * MTN;
+  f4 cre[2][2], cim[2][2];
+  tile_gemm_mx<P, true, true>(g.X, g.ng_max, r0, g.ns, g.X, g.ng_max, c0, g.ns - c0, g.ngx, false, cre, cim);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+  const double s = 2.0 * g.cpref;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + wr * 32 + i * 16 + acc_row(lane, r);
+        const int col = c0 + wc * 32 + j * 16 + (lane & 15);
+        if (row < g.ns && col < g.ns)
+          g.H[(size_t)row * g.ns + col] = make_double2(s * (double)cre[i][j][r], s * (double)cim[i][j][r]);
+      }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_direct_s1_mx(GemmArgs g) {
+  const S1Tile tl = g.s1tiles[blockIdx.x];
+  const int nv2 = g.nv * g.nv;
+  const int row_base = g.qstart[tl.iq] * nv2;
+  const int rows = (g.qstart[tl.iq + 1] - g.qstart[tl.iq]) * nv2;
+  const int K = g.ng[tl.iq];
+  const double2* A = g.RV + (size_t)row_base * g.ng_max;
+  const double2* Wq = g.W + (size_t)tl.iq * g.ng_max * g.ng_max;
+  f4 cre[2][2], cim[2][2];
+  const int r0 = tl.mt * MTM, c0 = tl.nt * MTN;
+  tile_gemm_mx<P, true, false>(A, g.ng_max, r0, rows, Wq, g.ng_max, c0, K - c0, K, tl.iq == 0 && g.w_head_fp64,
+                              cre, cim);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+  double2* Z = g.Z + (size_t)row_base * g.ng_max;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + wr * 32 + i * 16 + acc_row(lane, r);
+        const int col = c0 + wc * 32 + j * 16 + (lane & 15);
+        if (row < rows && col < K)
+          Z[(size_t)row * g.ng_max + col] = make_double2((double)cre[i][j][r], (double)cim[i][j][r]);
+      }
+}
+
+// Stage 2 per k pair: D[vv'][cc'] = sum_g Z[vv'][g] RC[cc'][g] (no conjugate),
+// operands split in registers.  The q = 0 head conj(rho_vv'(0)) W_00 rho_cc'(0)
+// is added in FP64.
+template <int P>
+__global__ __launch_bounds__(256) void k_direct_s2_mx(GemmArgs g, int tiles_i, int tiles_j, int nitems) {
+  const int lane = threadIdx.x & 63;
+  const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= nitems) return;
+  const int per = tiles_i * tiles_j;
+  const int p = item / per, ti = (item % per) / tiles_j, tj = item % tiles_j;
+  const int4 pr = g.pairs[p];
+  const int ka = pr.x, kb = pr.y;
+  const int K = g.ng[pr.z];
+  const int nv2 = g.nv * g.nv, nc2 = g.nc * g.nc;
+  const int ia = ti * 16 + (lane & 15), jb = tj * 16 + (lane & 15);
+  const bool va = ia < nv2, vb = jb < nc2;
+  const double2* zr = g.Z + ((size_t)p * nv2 + (va ? ia : 0)) * g.ng_max;
+  const double2* cr = g.RC + ((size_t)p * nc2 + (vb ? jb : 0)) * g.ng_max;
+  f4 dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
+  if constexpr (P == BSE_BF16X3) {
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      s8 a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int k = k0 + 8 * (lane >> 4) + i;
+        const double2 x = (va && k < K) ? zr[k] : make_double2(0.0, 0.0);
+        const double2 y = (vb && k < K) ? cr[k] : make_double2(0.0, 0.0);
+        unsigned short h, l;
+        Split<P>::split(x.x, h, l); a[0][i] = (short)h; a[1][i] = (short)l;
+        Split<P>::split(x.y, h, l); a[2][i] = (short)h; a[3][i] = (short)l;
+        Split<P>::split(y.x, h, l); b[0][i] = (short)h; b[1][i] = (short)l;
+        Split<P>::split(y.y, h, l); b[2][i] = (short)h; b[3][i] = (short)l;
+      }
+      const s8 nih = a[2] ^ (short)0x8000, nil = a[3] ^ (short)0x8000;
+      dre = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], dre, 0, 0, 0);
+      dre = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], dre, 0, 0, 0);
+      dre = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], dre, 0, 0, 0);
+      dre = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, b[2], dre, 0, 0, 0);
+      dre = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, b[3], dre, 0, 0, 0);
+      dre = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nil, b[2], dre, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2], dim, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[3], dim, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[2], dim, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], dim, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[1], dim, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[3], b[0], dim, 0, 0, 0);
+    }
+  } else {
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int k = k0 + (lane >> 4);
+      const double2 x = (va && k < K) ? zr[k] : make_double2(0.0, 0.0);
+      const double2 y = (vb && k < K) ? cr[k] : make_double2(0.0, 0.0);
+      float a[4], b[4];
+      Split<P>::split(x.x, a[0], a[1]);
+      Split<P>::split(x.y, a[2], a[3]);
+      Split<P>::split(y.x, b[0], b[1]);
+      Split<P>::split(y.y, b[2], b[3]);
+      dre = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], dre, 0, 0, 0);
+      dre = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[1], dre, 0, 0, 0);
+      dre = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b[0], dre, 0, 0, 0);
+      dre = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[2], b[2], dre, 0, 0, 0);
+      dre = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[2], b[3], dre, 0, 0, 0);
+      dre = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[3], b[2], dre, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[2], dim, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[3], dim, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b[2], dim, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b[0], dim, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b[1], dim, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b[0], dim, 0, 0, 0);
+    }
+  }
+  // FP64 head of W at q = 0 (left out of both mixed GEMMs)
+  const bool head = pr.z == 0 && g.w_head_fp64;
+  const double2 w00 = head ? g.W[0] : make_double2(0.0, 0.0);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = ti * 16 + acc_row(lane, r);
+    const int j = tj * 16 + (lane & 15);
+    if (i < nv2 && j < nc2) {
+      double dr = (double)dre[r], di = (double)dim[r];
+      if (head) {
+        const double2 rv0 = g.RV[((size_t)p * nv2 + i) * g.ng_max];
+        const double2 rc0 = g.RC[((size_t)p * nc2 + j) * g.ng_max];
+        const double2 hw = cmul(cconjmul(rv0, w00), rc0);
+        dr += hw.x;
+        di += hw.y;
+      }
+      const int v = i / g.nv, v2 = i % g.nv, c = j / g.nc, c2 = j % g.nc;
+      const size_t S = ((size_t)ka * g.nv + v) * g.nc + c;
+      const size_t S2 = ((size_t)kb * g.nv + v2) * g.nc + c2;
+      double2 h = g.H[S * g.ns + S2];
+      h.x -= g.cpref * dr;
+      h.y -= g.cpref * di;
+      if (S == S2) h.x += g.eps[(size_t)ka * g.nb + g.nv + c] - g.eps[(size_t)ka * g.nb + v];
+      g.H[S * g.ns + S2] = h;
+    }
+  }
+}
+
+template <int P>
+static hipError_t launch_ex(const GemmArgs& g, const int2* tiles, int ntiles, hipStream_t st) {
+  const size_t lds = 2 * sizeof(TileLds<P>);
+  hipError_t e = hipFuncSetAttribute((const void*)k_exchange_mx<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_exchange_mx<P>, dim3(ntiles), dim3(256), lds, st, g, tiles);
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t launch_s1(const GemmArgs& g, int ntiles, hipStream_t st) {
+  const size_t lds = 2 * sizeof(TileLds<P>);
+  hipError_t e = hipFuncSetAttribute((const void*)k_direct_s1_mx<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_direct_s1_mx<P>, dim3(ntiles), dim3(256), lds, st, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_exchange_mx(const GemmArgs& g, const int2* tiles, int ntiles, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  return g.precision == BSE_BF16X3 ? launch_ex<BSE_BF16X3>(g, tiles, ntiles, st)
+                                   : launch_ex<BSE_SPLIT_FP32>(g, tiles, ntiles, st);
+}
+
+hipError_t launch_direct_s1_mx(const GemmArgs& g, int ntiles, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  return g.precision == BSE_BF16X3 ? launch_s1<BSE_BF16X3>(g, ntiles, st) : launch_s1<BSE_SPLIT_FP32>(g, ntiles, st);
+}
+
+hipError_t launch_direct_s2_mx(const GemmArgs& g, hipStream_t st) {
+  const int ti = (g.nv * g.nv + 15) / 16, tj = (g.nc * g.nc + 15) / 16;
+  const int nitems = g.npairs * ti * tj;
+  if (nitems <= 0) return hipSuccess;
+  if (g.precision == BSE_BF16X3)
+    hipLaunchKernelGGL(k_direct_s2_mx<BSE_BF16X3>, dim3((nitems + 3) / 4), dim3(256), 0, st, g, ti, tj, nitems);
+  else
+    hipLaunchKernelGGL(k_direct_s2_mx<BSE_SPLIT_FP32>, dim3((nitems + 3) / 4), dim3(256), 0, st, g, ti, tj, nitems);
+  return hipGetLastError();
+}
+
+}  // namespace bse

@@ -65,5 +65,9 @@ hipError_t launch_exchange(const GemmArgs& g, const int2* tiles, int ntiles, hip
 hipError_t launch_direct_s1(const GemmArgs& g, int ntiles, hipStream_t st);
 hipError_t launch_direct_s2(const GemmArgs& g, int dtiles, hipStream_t st);
 hipError_t launch_mirror(double2* H, int ns, int nt, hipStream_t st);
+// mixed precision (g.precision = BSE_SPLIT_FP32 or BSE_BF16X3)
+hipError_t launch_exchange_mx(const GemmArgs& g, const int2* tiles, int ntiles, hipStream_t st);
+hipError_t launch_direct_s1_mx(const GemmArgs& g, int ntiles, hipStream_t st);
+hipError_t launch_direct_s2_mx(const GemmArgs& g, hipStream_t st);
 
 }  // namespace bse
