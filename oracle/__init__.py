@@ -117,3 +117,67 @@ def build_H(sys, separable=True):
 def exciton_energies(H, n=10):
     """Lowest n eigenvalues of the Hermitian H (LAPACK zheevd through numpy)."""
     return np.linalg.eigvalsh(H)[:n]
+
+
+def adjoint(sys, Gbar, qs=None, separable=True):
+    """Adjoint of the block-by-block map (W, eps) -> H of ``build_H``.
+
+    Gbar = dL/dRe H + i dL/dIm H (the PyTorch convention for a real L of a
+    complex H).  With dL = Re sum conj(Gbar) dH:
+      dL/dW_{GG'}(q) = -c sum_{(k,k') folding to q} sum_{vv'cc'} Gbar_SS' n_{vk,v'k'}(G) conj(n_{ck,c'k'}(G'))
+      dL/de_ck = sum_v Re Gbar_SS,   dL/de_vk = -sum_c Re Gbar_SS
+    (direct term and transition energies of Sec. II.C).  ``qs`` restricts dW
+    to those q.  Returns (dW [Nk][ng_max][ng_max], deps [Nk][nb]).
+    """
+    nk, nv, nc, nb = sys.nk, sys.nv, sys.nc, sys.nb
+    nt = nv * nc
+    c = HARTREE_EV / (nk * sys.omega_cell)
+    dW = np.zeros((nk, sys.ng_max, sys.ng_max), dtype=np.complex128)
+    pairs = []
+    for ka in range(nk):
+        for kb in range(nk):
+            iq, _ = fold(sys.kmesh, ka, kb)
+            if qs is None or iq in qs:
+                pairs.append((ka, kb, iq))
+    items = []
+    for ka, kb, _ in pairs:
+        items += [(ka, v, kb, v2) for v in range(nv) for v2 in range(nv)]
+        items += [(ka, nv + c1, kb, nv + c2) for c1 in range(nc) for c2 in range(nc)]
+    rho = pair_density_items(sys, items, separable) if items else None
+    per = nv * nv + nc * nc
+    for i, (ka, kb, iq) in enumerate(pairs):
+        ng = sys.ng[iq]
+        blk = rho[i * per:(i + 1) * per, :ng]
+        rv = blk[: nv * nv].reshape(nv, nv, ng)
+        rc = blk[nv * nv:].reshape(nc, nc, ng)
+        gb = Gbar[ka * nt:(ka + 1) * nt, kb * nt:(kb + 1) * nt].reshape(nv, nc, nv, nc)
+        dW[iq, :ng, :ng] += -c * np.einsum("acbd,abg,cdh->gh", gb, rv, np.conj(rc))
+    deps = np.zeros((nk, nb))
+    dg = np.real(np.diag(Gbar)).reshape(nk, nv, nc)
+    deps[:, nv:] = dg.sum(axis=1)
+    deps[:, :nv] = -dg.sum(axis=2)
+    return dW, deps
+
+
+def tr_orbit(sys, iq, g, gp):
+    """The entries of W tied to W_{g g'}(q) by Hermiticity and time reversal
+    (Sec. III.A with T = 1), as (q, g, g', conjugated) tuples."""
+    n = np.array(sys.kmesh)
+    n1, n2, n3 = sys.kmesh
+    iv = np.array([iq // (n2 * n3), (iq // n3) % n2, iq % n3])
+    qb = (-iv) % n
+    t = (-iv - qb) // n
+    iqb = int((qb[0] * n2 + qb[1]) * n3 + qb[2])
+    lut = {tuple(m): i for i, m in enumerate(sys.gvec[iqb, : sys.ng[iqb]])}
+    m, mp = sys.gvec[iq, g], sys.gvec[iq, gp]
+    gb, gpb = lut[tuple(t - m)], lut[tuple(t - mp)]
+    return {(iq, g, gp, False), (iq, gp, g, True), (iqb, gb, gpb, True), (iqb, gpb, gb, False)}
+
+
+def orbit_direction(sys, iq, g, gp, h):
+    """A perturbation of W that keeps it Hermitian and time-reversal
+    symmetric: h at (q, g, g') and the tied entries accordingly."""
+    D = np.zeros_like(sys.W)
+    for q, a, b, cj in tr_orbit(sys, iq, g, gp):
+        D[q, a, b] += np.conj(h) if cj else h
+    return D
