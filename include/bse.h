@@ -63,8 +63,10 @@ enum bse_precision {
 };
 
 enum bse_flags {
-    BSE_VALIDATE = 1,   /* scan inputs (synchronously) before enqueueing       */
-    BSE_PERSISTENT = 2  /* build a batch of systems with one persistent launch */
+    BSE_VALIDATE = 1,    /* scan inputs (synchronously) before enqueueing         */
+    BSE_PERSISTENT = 2,  /* build a batch of systems with one persistent launch   */
+    BSE_PROJECT_DW = 4   /* backward: project dW onto Hermitian, time-reversal
+                            symmetric W (group average of Sec. III.A, T = 1)     */
 };
 
 enum bse_pd_kind {
@@ -124,12 +126,16 @@ int bse_build_H(const bse_system *sys, int nsys, int precision, int flags,
 
 /*
  * Adjoint of bse_build_H for one system: given dL/dH (DEVICE [NS][NS] complex,
- * the PyTorch convention dL/dRe + i dL/dIm), returns
- *   dW   DEVICE [Nk][ng_max][ng_max] complex (nullable)  dL/dW_GG'(q)
+ * the PyTorch convention dL/dRe H + i dL/dIm H), returns
+ *   dW   DEVICE [Nk][ng_max][ng_max] complex (nullable)  dL/dW_GG'(q), zero past ng(q)
  *   deps DEVICE [Nk][nb]             (nullable)          dL/de (eV/eV)
- * Pair densities are recomputed, not read from a previous build.
- * dW is the plain partial derivative of the assembled upper-triangle + mirror
- * map; the Python layer projects it onto Hermitian/time-reversal symmetric W.
+ * Only W and eps are differentiated (u, v and the cell are constants).
+ * Pair densities are recomputed, not read from a previous build.  Without
+ * BSE_PROJECT_DW, dW is the partial derivative of the map the build computes
+ * (upper k blocks, lower ones mirrored); with it, dW is projected onto the
+ * Hermitian, time-reversal symmetric W on which that map and the all-blocks
+ * definition agree.  precision selects the arithmetic of the dW contraction
+ * (its q = 0 head entry is FP64 in every mode); sys->H is not read.
  */
 int bse_build_H_backward(const bse_system *sys, const double *dH, double *dW, double *deps,
                          int precision, int flags, void *ws, size_t ws_bytes, void *stream);

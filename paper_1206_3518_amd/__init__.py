@@ -210,3 +210,62 @@ def build_H(sys_or_dev, precision="fp64", flags=0, ws=None):
     p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     bse_build_H([d], p, flags, ws)
     return d.H
+
+
+def bse_build_H_backward(system: DeviceSystem, dH, want_dW=True, want_deps=True, precision=BSE_FP64, flags=0,
+                         ws=None, stream=None):
+    """(dL/dW, dL/deps) for dL/dH = dH (complex128 [NS][NS], PyTorch convention)."""
+    import torch
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    dH = dH.contiguous()
+    dW = torch.empty_like(system.W) if want_dW else None
+    deps = torch.empty_like(system.eps) if want_deps else None
+    if ws is None:
+        ws = workspace(bse_workspace_size([system], p, flags), system.device)
+    st = system.struct()
+    _check(lib().bse_build_H_backward(ctypes.byref(st), _ptr(dH), _ptr(dW), _ptr(deps), p, int(flags), _ptr(ws),
+                                      ws.numel(), _stream(stream)))
+    return dW, deps
+
+
+def _autograd():
+    import torch
+
+    class BuildH(torch.autograd.Function):
+        """H(W, eps) with the adjoint kernel as its backward.  u, v and the
+        cell are constants; dW is projected onto Hermitian, time-reversal
+        symmetric W when ``project``."""
+
+        @staticmethod
+        def forward(ctx, W, eps, system, precision, project):
+            d = DeviceSystem.__new__(DeviceSystem)
+            d.__dict__.update(system.__dict__)
+            d.W = W.detach().contiguous()
+            d.eps = eps.detach().contiguous()
+            d.H = torch.empty((d.ns, d.ns), dtype=torch.complex128, device=d.device)
+            bse_build_H([d], PRECISIONS.get(precision, precision))
+            ctx.system = d
+            ctx.precision = precision
+            ctx.project = project
+            return d.H
+
+        @staticmethod
+        def backward(ctx, dH):
+            flags = BSE_PROJECT_DW if ctx.project else 0
+            dW, deps = bse_build_H_backward(ctx.system, dH, ctx.needs_input_grad[0], ctx.needs_input_grad[1],
+                                            ctx.precision, flags)
+            return dW, deps, None, None, None
+
+    return BuildH
+
+
+BSE_PROJECT_DW = 4
+_BUILDH = None
+
+
+def build_H_autograd(system: DeviceSystem, W, eps, precision="fp64", project=True):
+    """Differentiable H(W, eps) for one system (see BuildH)."""
+    global _BUILDH
+    if _BUILDH is None:
+        _BUILDH = _autograd()
+    return _BUILDH.apply(W, eps, system, precision, project)

@@ -1,0 +1,221 @@
+// Adjoint of the Hamiltonian build (the map (W, eps) -> H of Sec. II.C with
+// the upper k blocks computed and the lower ones mirrored).
+//
+// With Gbar = dL/dRe H + i dL/dIm H and dL = Re sum conj(Gbar) dH, an upper
+// block (k <= k') enters through Gbar_eff = Gbar + Gbar^H (k < k': the mirrored
+// lower block adds its conjugate transpose) or Gbar (k = k'), and
+//   T[(kk' vv')][g']   = sum_{cc'} Gbar_eff[(k v c),(k' v' c')] conj(rho_cc'(g'))   (k_adj_T)
+//   dL/dW_q[g][g']     = -c sum_{pairs of q, vv'} rho_vv'(g) T[(kk' vv')][g']       (k_adj_dW, MFMA)
+//   dL/de_ck = sum_v Re Gbar_SS,  dL/de_vk = -sum_c Re Gbar_SS                       (k_adj_deps)
+// Optionally dW is projected onto Hermitian, time-reversal symmetric W by the
+// group average over (g g') -> conj(g' g) and (q g g') -> conj(qbar, t-g, t-g')
+// (Sec. III.A with T = 1).
+#include "bse_internal.h"
+#include "gemm_tiles.h"
+#include "kernels.h"
+
+namespace bse {
+
+// T for one k pair and one 16-row block of vv', all g'.  f64 MFMA: A = Gbar_eff
+// block (16 x 16 over vv' x cc'), B[cc'][g'] = conj(rho_cc'(g')).
+__global__ __launch_bounds__(256) void k_adj_T(AdjArgs a, int tiles_i, int nitems) {
+  const int lane = threadIdx.x & 63;
+  const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= nitems) return;
+  const int p = item / tiles_i, ti = item % tiles_i;
+  const int4 pr = a.pairs[p];
+  const int ka = pr.x, kb = pr.y;
+  const int K = a.ng[pr.z];
+  const int nv = a.nv, nc = a.nc, nv2 = nv * nv, nc2 = nc * nc, ns = a.ns;
+  const int i = ti * 16 + (lane & 15);  // vv' row of the A operand
+  double2* T = a.T + (size_t)p * nv2 * a.ng_max;
+  for (int n0 = 0; n0 < a.ng_max; n0 += 16) {
+    d4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+    for (int kc = 0; kc < nc2; kc += 4) {
+      const int j = kc + (lane >> 4);  // cc'
+      double2 g = make_double2(0.0, 0.0);
+      if (i < nv2 && j < nc2) {
+        const int v = i / nv, v2 = i % nv, c = j / nc, c2 = j % nc;
+        const size_t S = ((size_t)ka * nv + v) * nc + c;
+        const size_t S2 = ((size_t)kb * nv + v2) * nc + c2;
+        g = a.dH[S * ns + S2];
+        if (ka != kb) {
+          const double2 h = a.dH[S2 * ns + S];
+          g.x += h.x;
+          g.y -= h.y;
+        }
+      }
+      const int n = n0 + (lane & 15);
+      double2 b = make_double2(0.0, 0.0);
+      if (j < nc2 && n < K) {
+        const double2 r = a.RC[((size_t)p * nc2 + j) * a.ng_max + n];
+        b = make_double2(r.x, -r.y);
+      }
+      // B operand of lane l: B[k = l/16][n = l%16]; A operand: A[i = l%16][k = l/16]
+      cre = mfma64(g.x, b.x, cre);
+      cre = mfma64(-g.y, b.y, cre);
+      cim = mfma64(g.x, b.y, cim);
+      cim = mfma64(g.y, b.x, cim);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = ti * 16 + 4 * r + (lane >> 4);
+      const int col = n0 + (lane & 15);
+      if (row < nv2 && col < a.ng_max)
+        T[(size_t)row * a.ng_max + col] = col < K ? make_double2(cre[r], cim[r]) : make_double2(0.0, 0.0);
+    }
+  }
+}
+
+// dW_q tile = -c RV_q^T T_q (A transposed: A[g][r] = RV[r][g]).
+template <int P>
+__global__ __launch_bounds__(256) void k_adj_dW(AdjArgs a) {
+  const int4 tl = a.dwtiles[blockIdx.x];
+  const int q = tl.x;
+  const int nv2 = a.nv * a.nv;
+  const int row_base = a.qstart[q] * nv2;
+  const int K = (a.qstart[q + 1] - a.qstart[q]) * nv2;
+  const int ngq = a.ng[q];
+  const double2* A = a.RV + (size_t)row_base * a.ng_max;
+  const double2* Bm = a.T + (size_t)row_base * a.ng_max;
+  const int r0 = tl.y * 64, c0 = tl.z * 64;
+  double2* out = a.dWout + (size_t)q * a.ng_max * a.ng_max;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+  if constexpr (P == BSE_FP64) {
+    d4 cre[2][2], cim[2][2];
+    tile_gemm<false, false, true>(A, a.ng_max, r0, ngq, Bm, a.ng_max, c0, ngq, K, cre, cim);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + wr * 32 + i * 16 + 4 * r + (lane >> 4);
+          const int col = c0 + wc * 32 + j * 16 + (lane & 15);
+          if (row < a.ng_max && col < a.ng_max)
+            out[(size_t)row * a.ng_max + col] = make_double2(-a.cpref * cre[i][j][r], -a.cpref * cim[i][j][r]);
+        }
+  } else {
+    f4 cre[2][2], cim[2][2];
+    tile_gemm_mx<P, false, false, true>(A, a.ng_max, r0, ngq, Bm, a.ng_max, c0, ngq, K, false, cre, cim);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + wr * 32 + i * 16 + acc_row(lane, r);
+          const int col = c0 + wc * 32 + j * 16 + (lane & 15);
+          if (row < a.ng_max && col < a.ng_max)
+            out[(size_t)row * a.ng_max + col] =
+                make_double2(-a.cpref * (double)cre[i][j][r], -a.cpref * (double)cim[i][j][r]);
+        }
+  }
+}
+
+// FP64 head entry dW_0[0][0] (mixed precision): one workgroup reduction.
+__global__ __launch_bounds__(256) void k_adj_head(AdjArgs a) {
+  __shared__ double sre[256], sim[256];
+  const int nv2 = a.nv * a.nv;
+  const int rows = (a.qstart[1] - a.qstart[0]) * nv2;
+  const double2* A = a.RV + (size_t)a.qstart[0] * nv2 * a.ng_max;
+  const double2* Bm = a.T + (size_t)a.qstart[0] * nv2 * a.ng_max;
+  double re = 0.0, im = 0.0;
+  for (int r = threadIdx.x; r < rows; r += 256) {
+    const double2 x = A[(size_t)r * a.ng_max], y = Bm[(size_t)r * a.ng_max];
+    re += x.x * y.x - x.y * y.y;
+    im += x.x * y.y + x.y * y.x;
+  }
+  sre[threadIdx.x] = re;
+  sim[threadIdx.x] = im;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sre[threadIdx.x] += sre[threadIdx.x + s];
+      sim[threadIdx.x] += sim[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.dWout[0] = make_double2(-a.cpref * sre[0], -a.cpref * sim[0]);
+}
+
+__global__ void k_adj_deps(AdjArgs a) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nb = a.nv + a.nc;
+  if (id >= a.nk * nb) return;
+  const int k = id / nb, b = id % nb;
+  double s = 0.0;
+  if (b >= a.nv) {
+    const int c = b - a.nv;
+    for (int v = 0; v < a.nv; ++v) {
+      const size_t S = ((size_t)k * a.nv + v) * a.nc + c;
+      s += a.dH[S * a.ns + S].x;
+    }
+  } else {
+    for (int c = 0; c < a.nc; ++c) {
+      const size_t S = ((size_t)k * a.nv + b) * a.nc + c;
+      s -= a.dH[S * a.ns + S].x;
+    }
+  }
+  a.deps[id] = s;
+}
+
+// Orthogonal projection onto Hermitian, time-reversal symmetric W.
+__global__ void k_adj_project(AdjArgs a, const double2* __restrict__ raw, double2* __restrict__ out) {
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t per = (size_t)a.ng_max * a.ng_max;
+  if (id >= per * a.nk) return;
+  const int q = (int)(id / per);
+  const int g = (int)((id % per) / a.ng_max), h = (int)(id % a.ng_max);
+  const int n = a.ng[q];
+  if (g >= n || h >= n) {
+    out[id] = make_double2(0.0, 0.0);
+    return;
+  }
+  const int qb = a.qbar[q];
+  const int gb = a.trmap[(size_t)q * a.ng_max + g], hb = a.trmap[(size_t)q * a.ng_max + h];
+  const double2 x0 = raw[id];
+  const double2 x1 = raw[(size_t)q * per + (size_t)h * a.ng_max + g];
+  const double2 x2 = raw[(size_t)qb * per + (size_t)gb * a.ng_max + hb];
+  const double2 x3 = raw[(size_t)qb * per + (size_t)hb * a.ng_max + gb];
+  out[id] = make_double2(0.25 * (x0.x + x1.x + x2.x + x3.x), 0.25 * (x0.y - x1.y - x2.y + x3.y));
+}
+
+hipError_t launch_adjoint(const AdjArgs& a, int precision, int ndw_tiles, bool project, hipStream_t st) {
+  const int ti = (a.nv * a.nv + 15) / 16;
+  const int nitems = a.npairs * ti;
+  if (nitems > 0) {
+    hipLaunchKernelGGL(k_adj_T, dim3((nitems + 3) / 4), dim3(256), 0, st, a, ti, nitems);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (a.dWout && ndw_tiles > 0) {
+    if (precision == BSE_FP64) {
+      hipLaunchKernelGGL(k_adj_dW<BSE_FP64>, dim3(ndw_tiles), dim3(256), 0, st, a);
+    } else {
+      const size_t lds = precision == BSE_BF16X3 ? 2 * sizeof(TileLds<BSE_BF16X3>) : 2 * sizeof(TileLds<BSE_SPLIT_FP32>);
+      auto k = precision == BSE_BF16X3 ? k_adj_dW<BSE_BF16X3> : k_adj_dW<BSE_SPLIT_FP32>;
+      hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k, dim3(ndw_tiles), dim3(256), lds, st, a);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_adj_head, dim3(1), dim3(256), 0, st, a);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (project) {
+      const size_t n = (size_t)a.nk * a.ng_max * a.ng_max;
+      hipLaunchKernelGGL(k_adj_project, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, a.dWout, a.dWfinal);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  }
+  if (a.deps) {
+    const int n = a.nk * (a.nv + a.nc);
+    hipLaunchKernelGGL(k_adj_deps, dim3((n + 255) / 256), dim3(256), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace bse

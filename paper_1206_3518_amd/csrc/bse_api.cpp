@@ -121,9 +121,13 @@ struct Plan {
   std::vector<PdJob> jx, jv, jc;
   std::vector<S1Tile> s1;
   std::vector<int2> xt;
+  std::vector<int4> dwt;   // adjoint dW tiles (q, mt, nt, -)
+  std::vector<int> qbar, trmap;
+  bool tr_closed = true;
   // byte offsets inside the workspace
   size_t o_gpack = 0, o_ng = 0, o_pairs = 0, o_qstart = 0, o_jx = 0, o_jv = 0, o_jc = 0, o_s1 = 0, o_xt = 0;
-  size_t tables = 0, o_vs = 0, o_X = 0, o_RV = 0, o_RC = 0, o_Z = 0, total = 0;
+  size_t o_dwt = 0, o_qbar = 0, o_trmap = 0;
+  size_t tables = 0, o_vs = 0, o_X = 0, o_RV = 0, o_RC = 0, o_Z = 0, o_dWraw = 0, total = 0;
 };
 
 int check_system(const bse_system* s) {
@@ -228,6 +232,43 @@ int make_plan(const bse_system* s, Plan& P) {
   for (int i = 0; i < T; ++i)
     for (int j = std::max(0, i - 1); j < T; ++j) P.xt.push_back(make_int2(i, j));
 
+  // adjoint: dW tiles over ng_max x ng_max per q; time-reversal partners
+  P.dwt.clear();
+  {
+    const int T2 = (P.ng_max + 63) / 64;
+    for (int q = 0; q < P.nk; ++q)
+      for (int i = 0; i < T2; ++i)
+        for (int j = 0; j < T2; ++j) P.dwt.push_back(make_int4(q, i, j, 0));
+  }
+  P.qbar.assign(P.nk, 0);
+  P.trmap.assign((size_t)P.nk * P.ng_max, 0);
+  {
+    const int* n = s->kmesh;
+    for (int q = 0; q < P.nk; ++q) {
+      const int iv[3] = {q / (n[1] * n[2]), (q / n[2]) % n[1], q % n[2]};
+      int qb[3], tt[3];
+      for (int d = 0; d < 3; ++d) {
+        qb[d] = imod(-iv[d], n[d]);
+        tt[d] = (-iv[d] - qb[d]) / n[d];
+      }
+      const int iqb = (qb[0] * n[1] + qb[1]) * n[2] + qb[2];
+      P.qbar[q] = iqb;
+      for (int g = 0; g < P.ng[q]; ++g) {
+        int m1, m2, m3;
+        unpack_m(P.gpack[(size_t)q * P.ng_max + g], m1, m2, m3);
+        const int want = pack_m(tt[0] - m1, tt[1] - m2, tt[2] - m3);
+        int found = -1;
+        for (int h = 0; h < P.ng[iqb]; ++h)
+          if (P.gpack[(size_t)iqb * P.ng_max + h] == want) {
+            found = h;
+            break;
+          }
+        if (found < 0) P.tr_closed = false;
+        P.trmap[(size_t)q * P.ng_max + g] = found < 0 ? 0 : found;
+      }
+    }
+  }
+
   // workspace layout
   size_t o = 0;
   auto put = [&](size_t bytes) {
@@ -244,12 +285,16 @@ int make_plan(const bse_system* s, Plan& P) {
   P.o_jc = put(P.jc.size() * sizeof(PdJob));
   P.o_s1 = put(P.s1.size() * sizeof(S1Tile));
   P.o_xt = put(P.xt.size() * sizeof(int2));
+  P.o_dwt = put(P.dwt.size() * sizeof(int4));
+  P.o_qbar = put(P.qbar.size() * sizeof(int));
+  P.o_trmap = put(P.trmap.size() * sizeof(int));
   P.tables = o;
   P.o_vs = put((size_t)P.ng_max * sizeof(double));
   P.o_X = put((size_t)P.ns * P.ng_max * sizeof(double2));
   P.o_RV = put((size_t)np * P.nv * P.nv * P.ng_max * sizeof(double2));
   P.o_RC = put((size_t)np * P.nc * P.nc * P.ng_max * sizeof(double2));
   P.o_Z = put((size_t)np * P.nv * P.nv * P.ng_max * sizeof(double2));
+  P.o_dWraw = put((size_t)P.nk * P.ng_max * P.ng_max * sizeof(double2));
   P.total = o;
   return BSE_OK;
 }
@@ -268,6 +313,9 @@ int upload_tables(const Plan& P, char* ws, hipStream_t st) {
   cp(P.o_jc, P.jc.data(), P.jc.size() * sizeof(PdJob));
   cp(P.o_s1, P.s1.data(), P.s1.size() * sizeof(S1Tile));
   cp(P.o_xt, P.xt.data(), P.xt.size() * sizeof(int2));
+  cp(P.o_dwt, P.dwt.data(), P.dwt.size() * sizeof(int4));
+  cp(P.o_qbar, P.qbar.data(), P.qbar.size() * sizeof(int));
+  cp(P.o_trmap, P.trmap.data(), P.trmap.size() * sizeof(int));
   HIP_TRY(hipMemcpyWithStream(ws, buf.data(), P.tables, hipMemcpyHostToDevice, st));
   return BSE_OK;
 }
@@ -444,8 +492,50 @@ int bse_build_H(const bse_system* sys, int nsys, int precision, int flags, void*
 
 int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, double* deps, int precision, int flags,
                          void* ws, size_t ws_bytes, void* stream) {
-  (void)sys; (void)dH; (void)dW; (void)deps; (void)precision; (void)flags; (void)ws; (void)ws_bytes; (void)stream;
-  return fail(BSE_ERR_UNSUPPORTED, "backward not available");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  Plan P;
+  int rc = make_plan(sys, P);
+  if (rc) return rc;
+  if ((rc = check_lds(P))) return rc;
+  if (!dH || !ws) return fail(BSE_ERR_INVALID_ARG, "dH / ws is NULL");
+  if (precision < BSE_FP64 || precision > BSE_BF16X3) return fail(BSE_ERR_INVALID_ARG, "bad precision %d", precision);
+  if (ws_bytes < P.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, P.total);
+  const bool project = (flags & BSE_PROJECT_DW) != 0;
+  if (project && !P.tr_closed)
+    return fail(BSE_ERR_NOT_HERMITIAN, "G spheres are not closed under time reversal; cannot project dW");
+  char* w = static_cast<char*>(ws);
+  if ((rc = upload_tables(P, w, st))) return rc;
+  // recompute the pair densities of the direct term
+  PdArgs a = pd_args(P, sys, w);
+  a.jobs = reinterpret_cast<const PdJob*>(w + P.o_jv);
+  a.out = reinterpret_cast<double2*>(w + P.o_RV);
+  HIP_TRY(launch_pair_density(a, P.N2, P.N3, (int)P.jv.size(), st));
+  a.jobs = reinterpret_cast<const PdJob*>(w + P.o_jc);
+  a.out = reinterpret_cast<double2*>(w + P.o_RC);
+  HIP_TRY(launch_pair_density(a, P.N2, P.N3, (int)P.jc.size(), st));
+  AdjArgs g{};
+  g.dH = reinterpret_cast<const double2*>(dH);
+  g.RV = reinterpret_cast<const double2*>(w + P.o_RV);
+  g.RC = reinterpret_cast<const double2*>(w + P.o_RC);
+  g.T = reinterpret_cast<double2*>(w + P.o_Z);
+  g.dWfinal = reinterpret_cast<double2*>(dW);
+  g.dWout = dW ? (project ? reinterpret_cast<double2*>(w + P.o_dWraw) : reinterpret_cast<double2*>(dW)) : nullptr;
+  g.deps = deps;
+  g.pairs = reinterpret_cast<const int4*>(w + P.o_pairs);
+  g.ng = reinterpret_cast<const int*>(w + P.o_ng);
+  g.qstart = reinterpret_cast<const int*>(w + P.o_qstart);
+  g.dwtiles = reinterpret_cast<const int4*>(w + P.o_dwt);
+  g.qbar = reinterpret_cast<const int*>(w + P.o_qbar);
+  g.trmap = reinterpret_cast<const int*>(w + P.o_trmap);
+  g.nk = P.nk;
+  g.nv = P.nv;
+  g.nc = P.nc;
+  g.ns = P.ns;
+  g.ng_max = P.ng_max;
+  g.npairs = (int)P.pairs.size();
+  g.cpref = 27.211386245988 / ((double)P.nk * sys->omega_cell);
+  HIP_TRY(launch_adjoint(g, precision, (int)P.dwt.size(), project, st));
+  return BSE_OK;
 }
 
 int bse_spectrum(int ns, int nlam, const double* E, const double* A, const double* d, double pref, int nw,

@@ -5,95 +5,10 @@
 //   mirror    lower k blocks = conjugate transpose of the upper ones
 // Complex products run as four real v_mfma_f64_16x16x4 products per step.
 #include "bse_internal.h"
+#include "gemm_tiles.h"
 #include "kernels.h"
 
 namespace bse {
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-constexpr int TM = 64, TN = 64, KC = 16;
-
-// 64x64 complex tile of C = op(A) * B with op(A) = conj(A) if CONJ_A.
-// A: rows a_row0.. of a row-major complex matrix, ld = lda, valid rows < a_rows.
-// B: if B_T, B[k][n] = Bt[b_row0 + n][k] (rows of a row-major matrix, ld = ldb,
-//    valid n < b_cols); else B[k][n] = Bm[k][b_col0 + n] (row-major, ld = ldb).
-// K: valid k < K.  The result lands in cre/cim (f64 MFMA accumulator layout).
-template <bool CONJ_A, bool B_T>
-__device__ __forceinline__ void tile_gemm(const double2* __restrict__ A, int lda, int a_row0, int a_rows,
-                                          const double2* __restrict__ B, int ldb, int b_off, int b_cols, int K,
-                                          d4 (&cre)[2][2], d4 (&cim)[2][2]) {
-  __shared__ double As_re[TM][KC + 1], As_im[TM][KC + 1];
-  __shared__ double Bs_re[KC][TN + 1], Bs_im[KC][TN + 1];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wr = w >> 1, wc = w & 1;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      cre[i][j] = d4{0, 0, 0, 0};
-      cim[i][j] = d4{0, 0, 0, 0};
-    }
-  for (int k0 = 0; k0 < K; k0 += KC) {
-    {  // A chunk: row t>>2, 4 consecutive k
-      const int r = t >> 2, c0 = (t & 3) * 4;
-      const int gr = a_row0 + r;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int k = k0 + c0 + i;
-        double2 v = (gr < a_rows && k < K) ? A[(size_t)gr * lda + k] : make_double2(0.0, 0.0);
-        As_re[r][c0 + i] = v.x;
-        As_im[r][c0 + i] = CONJ_A ? -v.y : v.y;
-      }
-    }
-    if (B_T) {
-      const int n = t >> 2, c0 = (t & 3) * 4;
-      const int gn = b_off + n;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int k = k0 + c0 + i;
-        double2 v = (n < b_cols && k < K) ? B[(size_t)gn * ldb + k] : make_double2(0.0, 0.0);
-        Bs_re[c0 + i][n] = v.x;
-        Bs_im[c0 + i][n] = v.y;
-      }
-    } else {
-      const int kr = t >> 4, c0 = (t & 15) * 4;
-      const int k = k0 + kr;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int n = c0 + i;
-        double2 v = (k < K && n < b_cols) ? B[(size_t)k * ldb + b_off + n] : make_double2(0.0, 0.0);
-        Bs_re[kr][n] = v.x;
-        Bs_im[kr][n] = v.y;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < KC; kk += 4) {
-      double are[2], aim[2], bre[2], bim[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        are[i] = As_re[wr * 32 + i * 16 + (lane & 15)][kk + (lane >> 4)];
-        aim[i] = As_im[wr * 32 + i * 16 + (lane & 15)][kk + (lane >> 4)];
-        bre[i] = Bs_re[kk + (lane >> 4)][wc * 32 + i * 16 + (lane & 15)];
-        bim[i] = Bs_im[kk + (lane >> 4)][wc * 32 + i * 16 + (lane & 15)];
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          cre[i][j] = mfma64(are[i], bre[j], cre[i][j]);
-          cre[i][j] = mfma64(-aim[i], bim[j], cre[i][j]);
-          cim[i][j] = mfma64(are[i], bim[j], cim[i][j]);
-          cim[i][j] = mfma64(aim[i], bre[j], cim[i][j]);
-        }
-    }
-    __syncthreads();
-  }
-}
 
 // ------------------------------------------------------------------ exchange
 
@@ -101,7 +16,7 @@ __global__ __launch_bounds__(256) void k_exchange(GemmArgs g, const int2* __rest
   const int2 tl = tiles[blockIdx.x];
   const int r0 = tl.x * TM, c0 = tl.y * TN;
   d4 cre[2][2], cim[2][2];
-  tile_gemm<true, true>(g.X, g.ng_max, r0, g.ns, g.X, g.ng_max, c0, g.ns - c0, g.ngx, cre, cim);
+  tile_gemm<true, true>(g.X, g.ng_max, r0, g.ns, g.X, g.ng_max, c0, g.ns, g.ngx, cre, cim);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
   const double s = 2.0 * g.cpref;
 #pragma unroll
@@ -134,7 +49,7 @@ __global__ __launch_bounds__(256) void k_direct_s1(GemmArgs g) {
   const double2* Wq = g.W + (size_t)tl.iq * g.ng_max * g.ng_max;
   d4 cre[2][2], cim[2][2];
   const int r0 = tl.mt * TM, c0 = tl.nt * TN;
-  tile_gemm<true, false>(A, g.ng_max, r0, rows, Wq, g.ng_max, c0, K - c0, K, cre, cim);
+  tile_gemm<true, false>(A, g.ng_max, r0, rows, Wq, g.ng_max, c0, K, K, cre, cim);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
   double2* Z = g.Z + (size_t)row_base * g.ng_max;
 #pragma unroll

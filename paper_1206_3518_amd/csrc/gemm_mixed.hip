@@ -6,198 +6,19 @@
 //   BSE_BF16X3:     BF16 parts, v_mfma_f32_16x16x32_bf16
 // The q = 0 head of W, the transition-energy diagonal and the final update of
 // H stay FP64.
-#include <hip/hip_bf16.h>
-
 #include "../../include/bse.h"
 #include "bse_internal.h"
+#include "gemm_tiles.h"
 #include "kernels.h"
 
 namespace bse {
-
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef short s8 __attribute__((ext_vector_type(8)));
-
-constexpr int MTM = 64, MTN = 64, MKC = 32;
-
-__device__ __forceinline__ unsigned short bf16_bits(float f) {
-  __hip_bfloat16 b = __float2bfloat16(f);
-  return *reinterpret_cast<unsigned short*>(&b);
-}
-__device__ __forceinline__ float bf16_value(unsigned short u) {
-  return __uint_as_float(((unsigned int)u) << 16);
-}
-
-template <int P>
-struct Split;
-// FP32 parts
-template <>
-struct Split<BSE_SPLIT_FP32> {
-  typedef float T;
-  __device__ static void split(double x, float& h, float& l) {
-    h = (float)x;
-    l = (float)(x - (double)h);
-  }
-};
-// BF16 parts, stored as raw 16-bit patterns
-template <>
-struct Split<BSE_BF16X3> {
-  typedef unsigned short T;
-  __device__ static void split(double x, unsigned short& h, unsigned short& l) {
-    h = bf16_bits((float)x);
-    l = bf16_bits((float)(x - (double)bf16_value(h)));
-  }
-};
-
-// LDS image of a 64 x 32 complex operand tile: 4 planes (re hi, re lo, im hi,
-// im lo), each [64 rows][32 k] with k contiguous, row stride padded.
-template <int P>
-struct TileLds {
-  typedef typename Split<P>::T T;
-  static constexpr int STRIDE = P == BSE_BF16X3 ? 40 : 33;
-  T v[4][64 * STRIDE];
-};
-
-// Stores 8 consecutive k values (row r, k0..k0+7) of one operand after the split.
-template <int P>
-__device__ __forceinline__ void put8(TileLds<P>& L, int r, int k0, const double2 (&x)[8], bool conj) {
-  typedef typename Split<P>::T T;
-  T h[4][8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    Split<P>::split(x[i].x, h[0][i], h[1][i]);
-    Split<P>::split(conj ? -x[i].y : x[i].y, h[2][i], h[3][i]);
-  }
-#pragma unroll
-  for (int pl = 0; pl < 4; ++pl)
-#pragma unroll
-    for (int i = 0; i < 8; ++i) L.v[pl][r * TileLds<P>::STRIDE + k0 + i] = h[pl][i];
-}
-
-// One 64x64 complex tile of C = op(A) * B with split operands.
-// A: rows of a row-major complex matrix (ld lda, valid rows < a_rows).
-// B: if B_T, B[k][n] = Bt[b_off + n][k] (valid n < b_cols); else
-//    B[k][n] = Bm[k][b_off + n].  Valid k < K.  zero_head: B[0][0] := 0 when
-//    the tile holds it (the q = 0 head is added in FP64 elsewhere).
-template <int P, bool CONJ_A, bool B_T>
-__device__ __forceinline__ void tile_gemm_mx(const double2* __restrict__ A, int lda, int a_row0, int a_rows,
-                                             const double2* __restrict__ B, int ldb, int b_off, int b_cols, int K,
-                                             bool zero_head, f4 (&cre)[2][2], f4 (&cim)[2][2]) {
-  extern __shared__ char smem_mx[];
-  TileLds<P>& As = *reinterpret_cast<TileLds<P>*>(smem_mx);
-  TileLds<P>& Bs = *reinterpret_cast<TileLds<P>*>(smem_mx + sizeof(TileLds<P>));
-  constexpr int ST = TileLds<P>::STRIDE;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wr = w >> 1, wc = w & 1;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      cre[i][j] = f4{0, 0, 0, 0};
-      cim[i][j] = f4{0, 0, 0, 0};
-    }
-  const int r = t >> 2, kq = (t & 3) * 8;
-  for (int k0 = 0; k0 < K; k0 += MKC) {
-    {
-      double2 x[8];
-      const int gr = a_row0 + r;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int k = k0 + kq + i;
-        x[i] = (gr < a_rows && k < K) ? A[(size_t)gr * lda + k] : make_double2(0.0, 0.0);
-      }
-      put8<P>(As, r, kq, x, CONJ_A);
-    }
-    {
-      double2 x[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int k = k0 + kq + i;
-        if (B_T)
-          x[i] = (r < b_cols && k < K) ? B[(size_t)(b_off + r) * ldb + k] : make_double2(0.0, 0.0);
-        else
-          x[i] = (r < b_cols && k < K) ? B[(size_t)k * ldb + b_off + r] : make_double2(0.0, 0.0);
-        if (zero_head && k == 0 && b_off + r == 0) x[i] = make_double2(0.0, 0.0);
-      }
-      put8<P>(Bs, r, kq, x, false);
-    }
-    __syncthreads();
-    if constexpr (P == BSE_BF16X3) {
-      s8 a[2][4], b[2][4];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int pl = 0; pl < 4; ++pl) {
-          a[i][pl] = *reinterpret_cast<const s8*>(&As.v[pl][(wr * 32 + i * 16 + (lane & 15)) * ST + 8 * (lane >> 4)]);
-          b[i][pl] = *reinterpret_cast<const s8*>(&Bs.v[pl][(wc * 32 + i * 16 + (lane & 15)) * ST + 8 * (lane >> 4)]);
-        }
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        s8 nih = a[i][2] ^ (short)0x8000, nil = a[i][3] ^ (short)0x8000;  // -Im(a) parts
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          f4 cr = cre[i][j], ci = cim[i][j];
-          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][0], cr, 0, 0, 0);
-          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][1], cr, 0, 0, 0);
-          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1], b[j][0], cr, 0, 0, 0);
-          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, b[j][2], cr, 0, 0, 0);
-          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, b[j][3], cr, 0, 0, 0);
-          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nil, b[j][2], cr, 0, 0, 0);
-          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][2], ci, 0, 0, 0);
-          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][3], ci, 0, 0, 0);
-          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1], b[j][2], ci, 0, 0, 0);
-          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][2], b[j][0], ci, 0, 0, 0);
-          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][2], b[j][1], ci, 0, 0, 0);
-          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][3], b[j][0], ci, 0, 0, 0);
-          cre[i][j] = cr;
-          cim[i][j] = ci;
-        }
-      }
-    } else {
-#pragma unroll
-      for (int kk = 0; kk < MKC; kk += 4) {
-        float a[2][4], b[2][4];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int pl = 0; pl < 4; ++pl) {
-            a[i][pl] = As.v[pl][(wr * 32 + i * 16 + (lane & 15)) * ST + kk + (lane >> 4)];
-            b[i][pl] = Bs.v[pl][(wc * 32 + i * 16 + (lane & 15)) * ST + kk + (lane >> 4)];
-          }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            f4 cr = cre[i][j], ci = cim[i][j];
-            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][0], b[j][0], cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][0], b[j][1], cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][1], b[j][0], cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[i][2], b[j][2], cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[i][2], b[j][3], cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[i][3], b[j][2], cr, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][0], b[j][2], ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][0], b[j][3], ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][1], b[j][2], ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][2], b[j][0], ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][2], b[j][1], ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][3], b[j][0], ci, 0, 0, 0);
-            cre[i][j] = cr;
-            cim[i][j] = ci;
-          }
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// f32 MFMA accumulator layout: lane l, register r holds D[4 (l/16) + r][l % 16]
-__device__ __forceinline__ int acc_row(int lane, int r) { return 4 * (lane >> 4) + r; }
 
 template <int P>
 __global__ __launch_bounds__(256) void k_exchange_mx(GemmArgs g, const int2* __restrict__ tiles) {
   const int2 tl = tiles[blockIdx.x];
   const int r0 = tl.x * MTM, c0 = tl.y * MTN;
   f4 cre[2][2], cim[2][2];
-  tile_gemm_mx<P, true, true>(g.X, g.ng_max, r0, g.ns, g.X, g.ng_max, c0, g.ns - c0, g.ngx, false, cre, cim);
+  tile_gemm_mx<P, true, true>(g.X, g.ng_max, r0, g.ns, g.X, g.ng_max, c0, g.ns, g.ngx, false, cre, cim);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
   const double s = 2.0 * g.cpref;
 #pragma unroll
@@ -224,7 +45,7 @@ __global__ __launch_bounds__(256) void k_direct_s1_mx(GemmArgs g) {
   const double2* Wq = g.W + (size_t)tl.iq * g.ng_max * g.ng_max;
   f4 cre[2][2], cim[2][2];
   const int r0 = tl.mt * MTM, c0 = tl.nt * MTN;
-  tile_gemm_mx<P, true, false>(A, g.ng_max, r0, rows, Wq, g.ng_max, c0, K - c0, K, tl.iq == 0 && g.w_head_fp64,
+  tile_gemm_mx<P, true, false>(A, g.ng_max, r0, rows, Wq, g.ng_max, c0, K, K, tl.iq == 0 && g.w_head_fp64,
                               cre, cim);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
   double2* Z = g.Z + (size_t)row_base * g.ng_max;

@@ -1,0 +1,291 @@
+// Tile engines of the MFMA contractions: a 64 x 64 complex output tile per
+// 256-thread workgroup (4 waves, 32 x 32 each), operands staged through LDS.
+//   tile_gemm     FP64: four real v_mfma_f64_16x16x4 products per step
+//   tile_gemm_mx  split operands (FP32 or BF16 hi + lo), FP32 accumulation
+#pragma once
+#include <hip/hip_bf16.h>
+
+#include "../../include/bse.h"
+#include "bse_internal.h"
+
+namespace bse {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int TM = 64, TN = 64, KC = 16;
+
+// 64x64 complex tile of C = op(A) * B with op(A) = conj(A) if CONJ_A.
+// A[m][k] = Am[(a_off + m) * lda + k]   (A_T: Am[k * lda + a_off + m]), valid a_off + m < a_lim;
+// B[k][n] = Bm[k * ldb + b_off + n]     (B_T: Bm[(b_off + n) * ldb + k]), valid b_off + n < b_lim;
+// valid k < K.  The result lands in cre/cim (f64 MFMA accumulator layout).
+template <bool CONJ_A, bool B_T, bool A_T = false>
+__device__ __forceinline__ void tile_gemm(const double2* __restrict__ A, int lda, int a_off, int a_lim,
+                                          const double2* __restrict__ B, int ldb, int b_off, int b_lim, int K,
+                                          d4 (&cre)[2][2], d4 (&cim)[2][2]) {
+  __shared__ double As_re[TM][KC + 1], As_im[TM][KC + 1];
+  __shared__ double Bs_re[KC][TN + 1], Bs_im[KC][TN + 1];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cre[i][j] = d4{0, 0, 0, 0};
+      cim[i][j] = d4{0, 0, 0, 0};
+    }
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    if (!A_T) {  // A chunk: row t>>2, 4 consecutive k
+      const int r = t >> 2, c0 = (t & 3) * 4;
+      const int gr = a_off + r;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = k0 + c0 + i;
+        double2 v = (gr < a_lim && k < K) ? A[(size_t)gr * lda + k] : make_double2(0.0, 0.0);
+        As_re[r][c0 + i] = v.x;
+        As_im[r][c0 + i] = CONJ_A ? -v.y : v.y;
+      }
+    } else {  // k row t>>4, 4 consecutive m
+      const int kr = t >> 4, m0 = (t & 15) * 4;
+      const int k = k0 + kr;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = a_off + m0 + i;
+        double2 v = (m < a_lim && k < K) ? A[(size_t)k * lda + m] : make_double2(0.0, 0.0);
+        As_re[m0 + i][kr] = v.x;
+        As_im[m0 + i][kr] = CONJ_A ? -v.y : v.y;
+      }
+    }
+    if (B_T) {
+      const int n = t >> 2, c0 = (t & 3) * 4;
+      const int gn = b_off + n;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = k0 + c0 + i;
+        double2 v = (gn < b_lim && k < K) ? B[(size_t)gn * ldb + k] : make_double2(0.0, 0.0);
+        Bs_re[c0 + i][n] = v.x;
+        Bs_im[c0 + i][n] = v.y;
+      }
+    } else {
+      const int kr = t >> 4, c0 = (t & 15) * 4;
+      const int k = k0 + kr;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int n = c0 + i;
+        double2 v = (k < K && b_off + n < b_lim) ? B[(size_t)k * ldb + b_off + n] : make_double2(0.0, 0.0);
+        Bs_re[kr][n] = v.x;
+        Bs_im[kr][n] = v.y;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      double are[2], aim[2], bre[2], bim[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        are[i] = As_re[wr * 32 + i * 16 + (lane & 15)][kk + (lane >> 4)];
+        aim[i] = As_im[wr * 32 + i * 16 + (lane & 15)][kk + (lane >> 4)];
+        bre[i] = Bs_re[kk + (lane >> 4)][wc * 32 + i * 16 + (lane & 15)];
+        bim[i] = Bs_im[kk + (lane >> 4)][wc * 32 + i * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          cre[i][j] = mfma64(are[i], bre[j], cre[i][j]);
+          cre[i][j] = mfma64(-aim[i], bim[j], cre[i][j]);
+          cim[i][j] = mfma64(are[i], bim[j], cim[i][j]);
+          cim[i][j] = mfma64(aim[i], bre[j], cim[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+}
+
+
+// ------------------------------------------------------------------ split operands
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+
+constexpr int MTM = 64, MTN = 64, MKC = 32;
+
+__device__ __forceinline__ unsigned short bf16_bits(float f) {
+  __hip_bfloat16 b = __float2bfloat16(f);
+  return *reinterpret_cast<unsigned short*>(&b);
+}
+__device__ __forceinline__ float bf16_value(unsigned short u) {
+  return __uint_as_float(((unsigned int)u) << 16);
+}
+
+template <int P>
+struct Split;
+// FP32 parts
+template <>
+struct Split<BSE_SPLIT_FP32> {
+  typedef float T;
+  __device__ static void split(double x, float& h, float& l) {
+    h = (float)x;
+    l = (float)(x - (double)h);
+  }
+};
+// BF16 parts, stored as raw 16-bit patterns
+template <>
+struct Split<BSE_BF16X3> {
+  typedef unsigned short T;
+  __device__ static void split(double x, unsigned short& h, unsigned short& l) {
+    h = bf16_bits((float)x);
+    l = bf16_bits((float)(x - (double)bf16_value(h)));
+  }
+};
+
+// LDS image of a 64 x 32 complex operand tile: 4 planes (re hi, re lo, im hi,
+// im lo), each [64 rows][32 k] with k contiguous, row stride padded.
+template <int P>
+struct TileLds {
+  typedef typename Split<P>::T T;
+  static constexpr int STRIDE = P == BSE_BF16X3 ? 40 : 33;
+  T v[4][64 * STRIDE];
+};
+
+// Stores 8 consecutive k values (row r, k0..k0+7) of one operand after the split.
+template <int P>
+__device__ __forceinline__ void put8(TileLds<P>& L, int r, int k0, const double2 (&x)[8], bool conj) {
+  typedef typename Split<P>::T T;
+  T h[4][8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    Split<P>::split(x[i].x, h[0][i], h[1][i]);
+    Split<P>::split(conj ? -x[i].y : x[i].y, h[2][i], h[3][i]);
+  }
+#pragma unroll
+  for (int pl = 0; pl < 4; ++pl)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) L.v[pl][r * TileLds<P>::STRIDE + k0 + i] = h[pl][i];
+}
+
+// One 64x64 complex tile of C = op(A) * B with split operands; operand
+// addressing as in tile_gemm.  zero_head: B[0][0] := 0 when the tile holds it
+// (the q = 0 head is added in FP64 elsewhere).
+template <int P, bool CONJ_A, bool B_T, bool A_T = false>
+__device__ __forceinline__ void tile_gemm_mx(const double2* __restrict__ A, int lda, int a_off, int a_lim,
+                                             const double2* __restrict__ B, int ldb, int b_off, int b_lim, int K,
+                                             bool zero_head, f4 (&cre)[2][2], f4 (&cim)[2][2]) {
+  extern __shared__ char smem_mx[];
+  TileLds<P>& As = *reinterpret_cast<TileLds<P>*>(smem_mx);
+  TileLds<P>& Bs = *reinterpret_cast<TileLds<P>*>(smem_mx + sizeof(TileLds<P>));
+  constexpr int ST = TileLds<P>::STRIDE;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cre[i][j] = f4{0, 0, 0, 0};
+      cim[i][j] = f4{0, 0, 0, 0};
+    }
+  const int r = t >> 2, kq = (t & 3) * 8;
+  for (int k0 = 0; k0 < K; k0 += MKC) {
+    {
+      double2 x[8];
+      const int gr = a_off + r;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int k = k0 + kq + i;
+        if (A_T)
+          x[i] = (gr < a_lim && k < K) ? A[(size_t)k * lda + gr] : make_double2(0.0, 0.0);
+        else
+          x[i] = (gr < a_lim && k < K) ? A[(size_t)gr * lda + k] : make_double2(0.0, 0.0);
+      }
+      put8<P>(As, r, kq, x, CONJ_A);
+    }
+    {
+      double2 x[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int k = k0 + kq + i;
+        if (B_T)
+          x[i] = (b_off + r < b_lim && k < K) ? B[(size_t)(b_off + r) * ldb + k] : make_double2(0.0, 0.0);
+        else
+          x[i] = (b_off + r < b_lim && k < K) ? B[(size_t)k * ldb + b_off + r] : make_double2(0.0, 0.0);
+        if (zero_head && k == 0 && b_off + r == 0) x[i] = make_double2(0.0, 0.0);
+      }
+      put8<P>(Bs, r, kq, x, false);
+    }
+    __syncthreads();
+    if constexpr (P == BSE_BF16X3) {
+      s8 a[2][4], b[2][4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl) {
+          a[i][pl] = *reinterpret_cast<const s8*>(&As.v[pl][(wr * 32 + i * 16 + (lane & 15)) * ST + 8 * (lane >> 4)]);
+          b[i][pl] = *reinterpret_cast<const s8*>(&Bs.v[pl][(wc * 32 + i * 16 + (lane & 15)) * ST + 8 * (lane >> 4)]);
+        }
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        s8 nih = a[i][2] ^ (short)0x8000, nil = a[i][3] ^ (short)0x8000;  // -Im(a) parts
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          f4 cr = cre[i][j], ci = cim[i][j];
+          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][0], cr, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][1], cr, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1], b[j][0], cr, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, b[j][2], cr, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, b[j][3], cr, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nil, b[j][2], cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][2], ci, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][3], ci, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1], b[j][2], ci, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][2], b[j][0], ci, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][2], b[j][1], ci, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][3], b[j][0], ci, 0, 0, 0);
+          cre[i][j] = cr;
+          cim[i][j] = ci;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < MKC; kk += 4) {
+        float a[2][4], b[2][4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int pl = 0; pl < 4; ++pl) {
+            a[i][pl] = As.v[pl][(wr * 32 + i * 16 + (lane & 15)) * ST + kk + (lane >> 4)];
+            b[i][pl] = Bs.v[pl][(wc * 32 + i * 16 + (lane & 15)) * ST + kk + (lane >> 4)];
+          }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            f4 cr = cre[i][j], ci = cim[i][j];
+            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][0], b[j][0], cr, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][0], b[j][1], cr, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][1], b[j][0], cr, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[i][2], b[j][2], cr, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[i][2], b[j][3], cr, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[i][3], b[j][2], cr, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][0], b[j][2], ci, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][0], b[j][3], ci, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][1], b[j][2], ci, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][2], b[j][0], ci, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][2], b[j][1], ci, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][3], b[j][0], ci, 0, 0, 0);
+            cre[i][j] = cr;
+            cim[i][j] = ci;
+          }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// f32 MFMA accumulator layout: lane l, register r holds D[4 (l/16) + r][l % 16]
+__device__ __forceinline__ int acc_row(int lane, int r) { return 4 * (lane >> 4) + r; }
+
+
+}  // namespace bse

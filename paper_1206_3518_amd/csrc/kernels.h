@@ -70,4 +70,24 @@ hipError_t launch_exchange_mx(const GemmArgs& g, const int2* tiles, int ntiles, 
 hipError_t launch_direct_s1_mx(const GemmArgs& g, int ntiles, hipStream_t st);
 hipError_t launch_direct_s2_mx(const GemmArgs& g, hipStream_t st);
 
+// Adjoint of the build.
+struct AdjArgs {
+  const double2* dH;   // [NS][NS] dL/dH
+  const double2* RV;   // recomputed pair densities (layout of the forward build)
+  const double2* RC;
+  double2* T;          // [npairs][nv^2][ng_max] scratch
+  double2* dWout;      // dW GEMM output (dW itself, or the raw gradient before projection)
+  double2* dWfinal;    // projected dW
+  double* deps;        // [Nk][nb]
+  const int4* pairs;
+  const int* ng;
+  const int* qstart;
+  const int4* dwtiles; // (q, row tile, column tile, -)
+  const int* qbar;     // [Nk] time-reversal partner of q
+  const int* trmap;    // [Nk][ng_max] index of t - m_g in the sphere of qbar
+  int nk, nv, nc, ns, ng_max, npairs;
+  double cpref;
+};
+hipError_t launch_adjoint(const AdjArgs& a, int precision, int ndw_tiles, bool project, hipStream_t st);
+
 }  // namespace bse
