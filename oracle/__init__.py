@@ -181,3 +181,52 @@ def orbit_direction(sys, iq, g, gp, h):
     for q, a, b, cj in tr_orbit(sys, iq, g, gp):
         D[q, a, b] += np.conj(h) if cj else h
     return D
+
+
+def signed_freq(N):
+    """Signed DFT frequencies of an N-point axis with the Nyquist term set to 0."""
+    f = np.fft.fftfreq(N, 1.0 / N)
+    if N % 2 == 0:
+        f[N // 2] = 0.0
+    return f
+
+
+def grad_matrix(sys):
+    """<u_vk| grad |u_ck> (Cartesian, bohr^-1) for every k, v, c: the k.p
+    matrix element of Sec. II.B with the derivative taken spectrally,
+      <u|grad|u'> = (i / N_r) sum_m G_m conj(U(m)) U'(m),  U = unnormalised DFT of u,
+    G_m = sum_d m_d b_d with signed frequencies and the Nyquist planes removed.
+    Returns [Nk][nv][nc][3] complex."""
+    N1, N2, N3 = sys.grid
+    b = 2.0 * math.pi * np.linalg.inv(sys.cell).T
+    f = [signed_freq(N) for N in (N1, N2, N3)]
+    out = np.zeros((sys.nk, sys.nv, sys.nc, 3), dtype=np.complex128)
+    for k in range(sys.nk):
+        U = np.fft.fftn(sys.u[k].reshape(sys.nb, N1, N2, N3), axes=(1, 2, 3))
+        for d in range(3):
+            sh = [1, 1, 1]
+            sh[d] = -1
+            w = f[d].reshape(sh)
+            # S_d[v][c] = sum_m m_d conj(U_v) U_c
+            Sd = np.einsum("vxyz,cxyz->vc", np.conj(U[: sys.nv]), U[sys.nv:] * w)
+            out[k, :, :, :] += (1j / sys.nr) * Sd[:, :, None] * b[d][None, None, :]
+    return out
+
+
+def transition_dipoles(sys, qhat):
+    """d_S = qhat . <u_vk|grad|u_ck> / (e_ck - e_vk) in Hartree atomic units
+    (the q -> 0 limit of the pair density, Sec. II.B, up to the phase -i)."""
+    D = grad_matrix(sys) @ np.asarray(qhat, dtype=np.float64)
+    de = (sys.eps[:, None, sys.nv:] - sys.eps[:, : sys.nv, None]) / HARTREE_EV
+    return (D / de).reshape(-1)
+
+
+def spectrum(E, A, d, pref, w):
+    """eps2(w) = pref sum_l |t_l|^2 eta / ((w - E_l)^2 + eta^2) with t_l = sum_S A[S][l] d_S:
+    the imaginary part of the macroscopic dielectric function from the spectral
+    representation of Sec. II.C with the Tamm-Dancoff overlap matrix = identity.
+    E, w in Hartree; w = (grid, eta)."""
+    grid, eta = w
+    t = A.T @ d
+    wt = np.abs(t) ** 2
+    return pref * np.sum(wt[None, :] * eta / ((grid[:, None] - E[None, :]) ** 2 + eta ** 2), axis=1)
