@@ -110,9 +110,10 @@ size_t bse_workspace_size(const bse_system *sys, int nsys, int precision, int fl
  * row are written as zero.  BSE_PD_EXCH rows are NOT scaled by v(G).
  * BSE_PD_DIPOLE gives the k.p matrix element <u_vk|grad|u_ck> of Sec. II.B
  * (Cartesian, bohr^-1) from the spectral derivative of u with the Nyquist
- * planes removed; it needs sys->H = NULL allowed and uses the cell given in
- * `cell` (HOST [9], rows a1 a2 a3 in bohr; ignored for other kinds).
- * `out` is DEVICE complex.
+ * planes removed, using the cell given in `cell` (HOST [9], rows a1 a2 a3 in
+ * bohr; ignored for other kinds); it needs every grid length in the supported
+ * set (N1 included), nc <= 8 and a workspace of Nk*nb*Nr complex.
+ * `out` is DEVICE complex; sys->H is not read.
  */
 int bse_pair_density(const bse_system *sys, int kind, const int *kpairs, int npairs,
                      const double *cell, double *out, void *ws, size_t ws_bytes, void *stream);
@@ -147,12 +148,14 @@ int bse_build_H_backward(const bse_system *sys, const double *dH, double *dW, do
  *   t_l     = sum_S A[S][l] d[S]
  *   eps2(w) = pref * sum_l |t_l|^2 * eta / ((w - E_l)^2 + eta^2)
  * E (DEVICE [nlam], eV), A (DEVICE [ns][nlam] complex, eigenvectors as
- * columns), d (DEVICE [ns] complex), eps2 (DEVICE [nw]) on w_i = w0 + i*(w1-w0)/(nw-1).
- * Energies and eta are in eV and converted to Hartree inside; pref carries
- * 8 pi / (Nk Omega_cell) and the units of d.
+ * columns), d (DEVICE [ns] complex, Hartree atomic units), eps2 (DEVICE [nw])
+ * on w_i = w0 + i*(w1-w0)/(nw-1).  Energies and eta are in eV and converted
+ * to Hartree inside; pref carries 8 pi / (Nk Omega_cell) (spin 2).  ws
+ * (DEVICE) needs nlam doubles.
  */
 int bse_spectrum(int ns, int nlam, const double *E, const double *A, const double *d, double pref,
-                 int nw, double w0_eV, double w1_eV, double eta_eV, double *eps2, void *stream);
+                 int nw, double w0_eV, double w1_eV, double eta_eV, double *eps2, void *ws, size_t ws_bytes,
+                 void *stream);
 
 /*
  * Per-stage GPU timing of bse_build_H.  While enabled, every kernel launch of

@@ -61,7 +61,7 @@ def lib():
         L.bse_build_H.restype = I
         L.bse_build_H_backward.argtypes = [P, P, P, P, I, I, P, S, P]
         L.bse_build_H_backward.restype = I
-        L.bse_spectrum.argtypes = [I, I, P, P, P, D, I, D, D, D, P, P]
+        L.bse_spectrum.argtypes = [I, I, P, P, P, D, I, D, D, D, P, P, S, P]
         L.bse_spectrum.restype = I
         L.bse_profile.argtypes = [I]
         L.bse_profile.restype = I
@@ -179,8 +179,13 @@ def bse_pair_density(system: DeviceSystem, kind, kpairs=None, ws=None, stream=No
         raise ValueError(kind)
     out = torch.empty(shape, dtype=torch.complex128, device=system.device)
     if ws is None:
-        ws = workspace(bse_workspace_size([system]), system.device)
+        n = bse_workspace_size([system])
+        if kind == BSE_PD_DIPOLE:
+            n = max(n, system.u.numel() * 16)
+        ws = workspace(n, system.device)
     cell_arr = None
+    if cell is None and kind == BSE_PD_DIPOLE:
+        cell = system.src.cell
     if cell is not None:
         cell_arr = np.ascontiguousarray(cell, dtype=np.float64)
     st = system.struct()
@@ -269,3 +274,38 @@ def build_H_autograd(system: DeviceSystem, W, eps, precision="fp64", project=Tru
     if _BUILDH is None:
         _BUILDH = _autograd()
     return _BUILDH.apply(W, eps, system, precision, project)
+
+
+def bse_spectrum(E, A, d, pref, nw, w0_eV, w1_eV, eta_eV, ws=None, stream=None):
+    """eps2 on nw points of [w0, w1] (eV) from exciton energies E (eV, [nlam]),
+    eigenvectors A ([ns][nlam] complex) and transition dipoles d ([ns])."""
+    import torch
+    E = E.contiguous()
+    A = A.contiguous()
+    d = d.contiguous()
+    ns, nlam = A.shape
+    eps2 = torch.empty(nw, dtype=torch.float64, device=A.device)
+    if ws is None:
+        ws = workspace(8 * nlam, A.device)
+    _check(lib().bse_spectrum(ns, nlam, _ptr(E), _ptr(A), _ptr(d), float(pref), int(nw), float(w0_eV), float(w1_eV),
+                              float(eta_eV), _ptr(eps2), _ptr(ws), ws.numel(), _stream(stream)))
+    return eps2
+
+
+def absorption(system: DeviceSystem, H, qhats=((1, 0, 0), (0, 1, 0), (0, 0, 1)), nw=1001, w0=0.0, w1=10.0, eta=0.1):
+    """eps2(w) averaged over the polarisations qhats: FP64 host eigensolve of H,
+    dipoles and spectrum on the GPU."""
+    import torch
+    Hn = H.cpu().numpy()
+    E, A = np.linalg.eigh(Hn)
+    Ed = torch.from_numpy(E).to(system.device)
+    Ad = torch.from_numpy(np.ascontiguousarray(A)).to(system.device)
+    D = bse_pair_density(system, BSE_PD_DIPOLE)                         # [Nk][nv][nc][3], bohr^-1
+    de = (system.eps[:, None, system.nv:] - system.eps[:, :system.nv, None]) / HARTREE_EV
+    pref = 8.0 * np.pi / (system.nk * system.omega_cell)
+    out = torch.zeros(nw, dtype=torch.float64, device=system.device)
+    for q in qhats:
+        qv = torch.tensor(q, dtype=torch.complex128, device=system.device)
+        d = ((D @ qv) / de).reshape(-1).contiguous()
+        out += bse_spectrum(Ed, Ad, d, pref, nw, w0, w1, eta)
+    return out / len(qhats)

@@ -445,7 +445,32 @@ int bse_pair_density(const bse_system* sys, int kind, const int* kpairs, int npa
       jobs.push_back(PdJob{ka, kb, pack_m(m0[0], m0[1], m0[2]), iq, b0, b0, nA | (nA << 8), i * nA * nA});
     }
   } else if (kind == BSE_PD_DIPOLE) {
-    return fail(BSE_ERR_UNSUPPORTED, "dipole kind not available");
+    if (!cell) return fail(BSE_ERR_INVALID_ARG, "cell is NULL (needed for the dipole kind)");
+    if (!fft_len_supported(P.N1) || !fft_len_supported(P.N2) || !fft_len_supported(P.N3))
+      return fail(BSE_ERR_SHAPE, "grid (%d, %d, %d) has no full-grid FFT", P.N1, P.N2, P.N3);
+    if (P.nc > 8) return fail(BSE_ERR_SHAPE, "dipoles support at most 8 conduction bands");
+    const size_t need = (size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * sizeof(double2);
+    if (ws_bytes < need) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    // reciprocal vectors b = 2 pi A^-T (rows)
+    const double* A = cell;
+    const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                       A[2] * (A[3] * A[7] - A[4] * A[6]);
+    if (!(std::fabs(det) > 0.0)) return fail(BSE_ERR_INVALID_ARG, "singular cell");
+    GradCell bc;
+    const double tp = 6.283185307179586476925286766559 / det;
+    // rows of 2 pi (A^-1)^T = 2 pi / det * cofactor rows
+    bc.b[0][0] = tp * (A[4] * A[8] - A[5] * A[7]);
+    bc.b[0][1] = tp * (A[5] * A[6] - A[3] * A[8]);
+    bc.b[0][2] = tp * (A[3] * A[7] - A[4] * A[6]);
+    bc.b[1][0] = tp * (A[2] * A[7] - A[1] * A[8]);
+    bc.b[1][1] = tp * (A[0] * A[8] - A[2] * A[6]);
+    bc.b[1][2] = tp * (A[1] * A[6] - A[0] * A[7]);
+    bc.b[2][0] = tp * (A[1] * A[5] - A[2] * A[4]);
+    bc.b[2][1] = tp * (A[2] * A[3] - A[0] * A[5]);
+    bc.b[2][2] = tp * (A[0] * A[4] - A[1] * A[3]);
+    HIP_TRY(launch_grad(reinterpret_cast<const double2*>(sys->u), static_cast<double2*>(ws), P.nk, P.nb, P.nv, P.nc,
+                        P.N1, P.N2, P.N3, bc, reinterpret_cast<double2*>(out), st));
+    return BSE_OK;
   } else {
     return fail(BSE_ERR_INVALID_ARG, "unknown kind %d", kind);
   }
@@ -539,10 +564,15 @@ int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, do
 }
 
 int bse_spectrum(int ns, int nlam, const double* E, const double* A, const double* d, double pref, int nw,
-                 double w0_eV, double w1_eV, double eta_eV, double* eps2, void* stream) {
-  (void)ns; (void)nlam; (void)E; (void)A; (void)d; (void)pref; (void)nw; (void)w0_eV; (void)w1_eV; (void)eta_eV;
-  (void)eps2; (void)stream;
-  return fail(BSE_ERR_UNSUPPORTED, "spectrum not available");
+                 double w0_eV, double w1_eV, double eta_eV, double* eps2, void* ws, size_t ws_bytes, void* stream) {
+  if (ns < 1 || nlam < 1 || nlam > ns || nw < 1) return fail(BSE_ERR_INVALID_ARG, "bad sizes");
+  if (!E || !A || !d || !eps2 || !ws) return fail(BSE_ERR_INVALID_ARG, "NULL pointer");
+  if (!(eta_eV > 0.0)) return fail(BSE_ERR_INVALID_ARG, "eta must be positive");
+  if (ws_bytes < (size_t)nlam * sizeof(double)) return fail(BSE_ERR_WORKSPACE, "workspace below nlam doubles");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  HIP_TRY(launch_spectrum(ns, nlam, E, reinterpret_cast<const double2*>(A), reinterpret_cast<const double2*>(d), pref,
+                          nw, w0_eV, w1_eV, eta_eV, static_cast<double*>(ws), eps2, st));
+  return BSE_OK;
 }
 
 int bse_profile(int enable) {

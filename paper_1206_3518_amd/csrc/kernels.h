@@ -88,6 +88,16 @@ struct AdjArgs {
   int nk, nv, nc, ns, ng_max, npairs;
   double cpref;
 };
+// Reciprocal vectors (rows b_d, bohr^-1) for the gradient matrix elements.
+struct GradCell {
+  double b[3][3];
+};
+bool fft_len_supported(int N);
+hipError_t launch_grad(const double2* u, double2* scratch, int nk, int nb, int nv, int nc, int N1, int N2, int N3,
+                       const GradCell& bc, double2* out, hipStream_t st);
+hipError_t launch_spectrum(int ns, int nlam, const double* E, const double2* A, const double2* d, double pref,
+                           int nw, double w0, double w1, double eta, double* t2, double* eps2, hipStream_t st);
+
 hipError_t launch_adjoint(const AdjArgs& a, int precision, int ndw_tiles, bool project, hipStream_t st);
 
 }  // namespace bse
