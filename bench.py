@@ -30,6 +30,23 @@ def pd_flops(grid):
     return 5.0 * n * math.log2(n) + 6.0 * n
 
 
+def gemm_flops(s):
+    """Useful flops (8 per complex multiply-add) of the direct term's first
+    contraction conj(rho_vv')^T W(q) over the k <= k' pairs, and of the
+    exchange over the upper half of H."""
+    n = np.array(s.kmesh)
+    idx = np.arange(s.nk)
+    trip = np.stack([idx // (n[1] * n[2]), (idx // n[2]) % n[1], idx % n[2]], axis=1)
+    ka, kb = np.triu_indices(s.nk)
+    r = (trip[kb] - trip[ka]) % n
+    iq = (r[:, 0] * n[1] + r[:, 1]) * n[2] + r[:, 2]
+    counts = np.bincount(iq, minlength=s.nk)
+    ng = s.ng.astype(np.float64)
+    direct1 = float(np.sum(8.0 * counts * s.nv * s.nv * ng * ng))
+    exchange = 8.0 * s.ns * (s.ns + 1) / 2.0 * (s.ng[0] - 1)
+    return direct1, exchange
+
+
 def kernel_source_digest():
     h = hashlib.sha256()
     for f in ("pair_density.hip", "bse_internal.h"):
@@ -72,6 +89,28 @@ def cpu_baseline(s, target_s=15.0):
             "sample": f"{T}x{T} tile of random (k,k') blocks ({len(blocks) * nt * nt} elements), {dt:.1f} s"}
 
 
+def run_steps(P, dev, prec, ws, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        P.bse_build_H([dev], prec, 0, ws)
+    torch.cuda.synchronize()
+    P.bse_profile_read(reset=True)
+    P.bse_profile(True)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(st)
+    for _ in range(steps):
+        P.bse_build_H([dev], prec, 0, ws)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    P.bse_profile(False)
+    stages = P.bse_profile_read(reset=True)
+    return e0.elapsed_time(e1) / steps, wall, stages
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +119,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=list(DTYPES))
     ap.add_argument("--config", type=int, default=2, help="workload index (default: the Si-like 8192 case)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the split-FP32 / BF16x3 comparison runs")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run one plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -105,27 +145,20 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    for _ in range(args.warmup):
-        P.bse_build_H([dev], prec, 0, ws)
-    torch.cuda.synchronize()
-    P.bse_profile_read(reset=True)
-
-    P.bse_profile(True)
-    st = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(st)
-    for _ in range(args.steps):
-        P.bse_build_H([dev], prec, 0, ws)
-    e1.record(st)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    P.bse_profile(False)
-    stages = P.bse_profile_read(reset=True)
-    ms = e0.elapsed_time(e1) / args.steps
+    ms, wall, stages = run_steps(P, dev, prec, ws, args.steps, args.warmup)
     elements = float(s.ns) ** 2
     value = elements / (ms / 1e3)
+    d1_flops, ex_flops = gemm_flops(s)
+    hw = {"fp64": (1.0, PEAK["fp64_TFLOPs"]), "split_fp32": (3.0, PEAK["fp32_TFLOPs"]),
+          "bf16x3": (3.0, PEAK["bf16_TFLOPs"])}
+
+    def gemm_report(stg, precision):
+        mult, peak = hw[precision]
+        d1 = stg["direct1"][0] / max(stg["direct1"][1], 1) / 1e3
+        ex = stg["exchange"][0] / max(stg["exchange"][1], 1) / 1e3
+        return {"direct1_useful_TFLOPs": d1_flops / d1 / 1e12, "direct1_hw_TFLOPs": mult * d1_flops / d1 / 1e12,
+                "direct1_frac_of_peak": mult * d1_flops / d1 / 1e12 / peak, "peak_TFLOPs": peak,
+                "exchange_useful_TFLOPs": ex_flops / ex / 1e12}
 
     # dominant kernel: the pair-density kernel over the direct term's band pairs
     npairs = s.nk * (s.nk + 1) // 2
@@ -147,7 +180,23 @@ def main():
            "config": {"workload": s.name, "ns": s.ns, "grid": list(s.grid), "kmesh": list(s.kmesh), "nv": s.nv,
                       "nc": s.nc, "ng_max": s.ng_max, "precision": args.precision, "parallelism": "single-gpu"},
            "stage_ms": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
+           "gemm": gemm_report(stages, args.precision),
            "wall_s": wall, "roofline": roofline}
+    if not args.no_mixed and args.precision == "fp64":
+        import torch
+        H64 = dev.H.clone()
+        kscale = (H64 - torch.diag(torch.diag(H64))).abs().max().item()
+        mixed = {}
+        for name in ("split_fp32", "bf16x3"):
+            pm = P.PRECISIONS[name]
+            msm, _, stm = run_steps(P, dev, pm, ws, max(2, args.steps // 2), 1)
+            dH = (dev.H - H64).abs().max().item()
+            mixed[name] = {"value": elements / (msm / 1e3), "ms_per_step": msm, "speedup_vs_fp64": ms / msm,
+                           "max_abs_dH_eV": dH, "max_abs_dH_over_kernel": dH / kscale,
+                           "stage_ms": {k: v[0] / max(v[1], 1) for k, v in stm.items()},
+                           "gemm": gemm_report(stm, name)}
+        out["mixed"] = mixed
+        del H64
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s)
     print(json.dumps(out))
