@@ -104,8 +104,22 @@ __device__ __forceinline__ double2 cmul_root(double2 x) {
 }
 
 // ---------------------------------------------------------------- register FFT
-// In-place forward DFT (exp(-2 pi i)) of M points held by one lane, natural
-// order in and out, on x[OFF + S*i].  Decimation in time on radix 2 and 3.
+// In-place forward DFT (exp(-2 pi i)) of M points held by one lane, on
+// x[OFF + S*i] for i < M (natural order in).  Decimation in time on radix 2
+// and 3 with every butterfly writing back into its own input slots, so no
+// temporaries are live; output f ends in slot OFF + S * fft_pos<M>(f).
+
+template <int M>
+__host__ __device__ constexpr int fft_pos(int f) {
+  if constexpr (M == 1) {
+    return 0;
+  } else if constexpr (M % 2 == 0) {
+    return f < M / 2 ? 2 * fft_pos<M / 2>(f) : 2 * fft_pos<M / 2>(f - M / 2) + 1;
+  } else {
+    static_assert(M % 3 == 0, "register FFT radices are 2 and 3");
+    return 3 * fft_pos<M / 3>(f % (M / 3)) + f / (M / 3);
+  }
+}
 
 template <int M, int S, int OFF, int N>
 __device__ __forceinline__ void reg_fft(double2 (&x)[N]) {
@@ -115,37 +129,35 @@ __device__ __forceinline__ void reg_fft(double2 (&x)[N]) {
     constexpr int H = M / 2;
     reg_fft<H, 2 * S, OFF>(x);      // even samples
     reg_fft<H, 2 * S, OFF + S>(x);  // odd samples
-    double2 t[M];
     static_for<0, H>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
-      const double2 e = x[OFF + 2 * S * k];
-      const double2 o = cmul_root<M, k>(x[OFF + 2 * S * k + S]);
-      t[k] = cadd(e, o);
-      t[k + H] = csub(e, o);
+      constexpr int pe = OFF + 2 * S * fft_pos<H>(k);  // E_k; O_k sits S further
+      const double2 e = x[pe];
+      const double2 o = cmul_root<M, k>(x[pe + S]);
+      x[pe] = cadd(e, o);      // output k
+      x[pe + S] = csub(e, o);  // output k + H
     });
-    static_for<0, M>([&](auto kc) { x[OFF + S * decltype(kc)::value] = t[decltype(kc)::value]; });
   } else {
     static_assert(M % 3 == 0, "register FFT radices are 2 and 3");
     constexpr int T = M / 3;
     reg_fft<T, 3 * S, OFF>(x);
     reg_fft<T, 3 * S, OFF + S>(x);
     reg_fft<T, 3 * S, OFF + 2 * S>(x);
-    double2 t[M];
     constexpr double c3 = -0.5;                       // cos(2 pi / 3)
     constexpr double s3 = 8.66025403784438646764e-1;  // sin(2 pi / 3)
     static_for<0, T>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
-      const double2 a = x[OFF + 3 * S * k];
-      const double2 b = cmul_root<M, k>(x[OFF + 3 * S * k + S]);
-      const double2 c = cmul_root<M, 2 * k>(x[OFF + 3 * S * k + 2 * S]);
+      constexpr int pa = OFF + 3 * S * fft_pos<T>(k);
+      const double2 a = x[pa];
+      const double2 b = cmul_root<M, k>(x[pa + S]);
+      const double2 c = cmul_root<M, 2 * k>(x[pa + 2 * S]);
       const double2 sbc = cadd(b, c), dbc = csub(b, c);
       const double2 m = make_double2(fma(c3, sbc.x, a.x), fma(c3, sbc.y, a.y));
       const double2 r = make_double2(s3 * dbc.y, -s3 * dbc.x);  // -i s3 (b - c)
-      t[k] = cadd(a, sbc);
-      t[k + T] = cadd(m, r);
-      t[k + 2 * T] = csub(m, r);
+      x[pa] = cadd(a, sbc);         // output k
+      x[pa + S] = cadd(m, r);       // output k + T
+      x[pa + 2 * S] = csub(m, r);   // output k + 2T
     });
-    static_for<0, M>([&](auto kc) { x[OFF + S * decltype(kc)::value] = t[decltype(kc)::value]; });
   }
 }
 

@@ -93,7 +93,7 @@ __device__ __forceinline__ void cross_lane_dft(double2 (&x)[M], int l, const dou
 }
 
 // Row transform: x holds samples l + L*s (s < M) of a length-N row; afterwards
-// x[f'] holds output f' + M * bitrev(l).  tw[t] = exp(-2 pi i t / N).
+// slot fft_pos<M>(f') holds output f' + M * bitrev(l).  tw[t] = exp(-2 pi i t / N).
 template <int N, int L, int M>
 __device__ __forceinline__ void row_fft(double2 (&x)[M], int l, const double2* tw) {
   static_assert(L * M == N, "row split");
@@ -101,13 +101,15 @@ __device__ __forceinline__ void row_fft(double2 (&x)[M], int l, const double2* t
   if constexpr (L == 2) {
     // twiddle exp(-2 pi i l f'/N), l in {0, 1}: a compile-time constant per f'
     static_for<1, M>([&](auto fc) {
-      constexpr int f = decltype(fc)::value;
-      const double2 y = cmul_root<N, f>(x[f]);
-      x[f] = csel(l != 0, y, x[f]);
+      constexpr int f = decltype(fc)::value, p = fft_pos<M>(f);
+      const double2 y = cmul_root<N, f>(x[p]);
+      x[p] = csel(l != 0, y, x[p]);
     });
-  } else {
-#pragma unroll
-    for (int f = 1; f < M; ++f) x[f] = cmul(x[f], tw[(l * f) % N]);
+  } else if constexpr (L > 2) {
+    static_for<1, M>([&](auto fc) {
+      constexpr int f = decltype(fc)::value, p = fft_pos<M>(f);
+      x[p] = cmul(x[p], tw[(l * f) % N]);
+    });
   }
   cross_lane_dft<L, M>(x, l, tw, N);
 }

@@ -137,12 +137,12 @@ __global__ __launch_bounds__(256, 2) void k_pair_density(PdArgs a) {
           for (int s = 0; s < MA; ++s) x[s] = cconjmul(ua[base + G::at(0, LA * s)], yb[s]);
           row_fft<NA, LA, MA>(x, lA, twA);
           double2* T1w = T1 + w * per_pd;
-#pragma unroll
-          for (int f = 0; f < MA; ++f) {
+          static_for<0, MA>([&](auto fc) {
+            constexpr int f = decltype(fc)::value;
             int aA = bA + f;
             aA -= aA >= NA ? NA : 0;
-            if (ok && aA < FA) T1w[aA * SA + line] = x[f];
-          }
+            if (ok && aA < FA) T1w[aA * SA + line] = x[fft_pos<MA>(f)];
+          });
           // keep the two band pairs' loads and transforms from overlapping,
           // which would double the live registers
           __builtin_amdgcn_sched_barrier(0);
@@ -160,12 +160,12 @@ __global__ __launch_bounds__(256, 2) void k_pair_density(PdArgs a) {
         for (int s = 0; s < MB; ++s) x[s] = csel(ok, T1s[col * SA + lB + LB * s], make_double2(0.0, 0.0));
         row_fft<NB, LB, MB>(x, lB, twB);
         wave_sync();
-#pragma unroll
-        for (int f = 0; f < MB; ++f) {
+        static_for<0, MB>([&](auto fc) {
+          constexpr int f = decltype(fc)::value;
           int aB = bB + f;
           aB -= aB >= NB ? NB : 0;
-          if (ok && aB < FB) T1s[col * FB + aB] = x[f];
-        }
+          if (ok && aB < FB) T1s[col * FB + aB] = x[fft_pos<MB>(f)];
+        });
         wave_sync();
       }
       // ---- pass 3: direct sum over planes at the sphere points
@@ -216,7 +216,7 @@ static size_t lds_bytes(int N1, int F2, int F3, int ng_max) {
 
 template <int N2, int N3, int TG>
 static hipError_t launch_tg(const PdArgs& a, int njobs, size_t lds, hipStream_t st) {
-  auto k = a.vscale ? k_pair_density<N2, N3, TG, true> : k_pair_density<N2, N3, TG, false>;
+  void (*k)(PdArgs) = a.vscale ? k_pair_density<N2, N3, TG, true> : k_pair_density<N2, N3, TG, false>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(njobs), dim3(256), lds, st, a);

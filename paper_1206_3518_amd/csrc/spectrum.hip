@@ -53,8 +53,10 @@ __global__ __launch_bounds__(256) void k_fft_axis(double2* __restrict__ data, in
   row_fft<N, L, M>(x, l, tw);
   const int br = bitrev<L>(l);
   if (ok) {
-#pragma unroll
-    for (int f = 0; f < M; ++f) data[base + (size_t)(f + M * br) * stride] = x[f];
+    static_for<0, M>([&](auto fc) {
+      constexpr int f = decltype(fc)::value;
+      data[base + (size_t)(f + M * br) * stride] = x[fft_pos<M>(f)];
+    });
   }
 }
 
