@@ -49,7 +49,7 @@ def gemm_flops(s):
 
 def kernel_source_digest():
     h = hashlib.sha256()
-    for f in ("pair_density.hip", "bse_internal.h"):
+    for f in ("pair_density.hip", "bse_internal.h", "fft_row.h"):
         h.update(open(os.path.join(ROOT, "paper_1206_3518_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -168,7 +168,8 @@ def main():
     avg_s = pd_ms / pd_n / 1e3
     achieved = pd_flops(s.grid) * units / avg_s / 1e12
     digest = kernel_source_digest()
-    roofline = {"bound": "alu", "kernel": "k_pair_density", "achieved": achieved, "peak": PEAK["fp64_TFLOPs"],
+    line = s.grid[1] <= 32 and s.grid[2] <= 32 and s.grid[1] % 2 == 0 and s.grid[2] % 2 == 0
+    roofline = {"bound": "alu", "kernel": "k_pair_density_line" if line else "k_pair_density", "achieved": achieved, "peak": PEAK["fp64_TFLOPs"],
                 "unit": "TFLOP/s", "frac": achieved / PEAK["fp64_TFLOPs"],
                 "traffic": traffic_from_profile(digest, units), "avg_launch_ms": pd_ms / pd_n,
                 "flops_per_launch": pd_flops(s.grid) * units, "kernel_digest": digest}
@@ -186,13 +187,18 @@ def main():
         import torch
         H64 = dev.H.clone()
         kscale = (H64 - torch.diag(torch.diag(H64))).abs().max().item()
+        # lowest exciton energies, FP64 eigensolve of each H (outside the timed region)
+        E64 = torch.linalg.eigvalsh(H64)[:10].cpu().numpy()
+        out["lowest_exciton_eV"] = E64.tolist()
         mixed = {}
         for name in ("split_fp32", "bf16x3"):
             pm = P.PRECISIONS[name]
             msm, _, stm = run_steps(P, dev, pm, ws, max(2, args.steps // 2), 1)
             dH = (dev.H - H64).abs().max().item()
+            Em = torch.linalg.eigvalsh(dev.H)[:10].cpu().numpy()
             mixed[name] = {"value": elements / (msm / 1e3), "ms_per_step": msm, "speedup_vs_fp64": ms / msm,
                            "max_abs_dH_eV": dH, "max_abs_dH_over_kernel": dH / kscale,
+                           "max_abs_dE_lowest10_eV": float(np.abs(Em - E64).max()),
                            "stage_ms": {k: v[0] / max(v[1], 1) for k, v in stm.items()},
                            "gemm": gemm_report(stm, name)}
         out["mixed"] = mixed

@@ -202,6 +202,198 @@ __global__ __launch_bounds__(256, 2) void k_pair_density(PdArgs a) {
   }
 }
 
+// Planes of at most 32 x 32 points: one lane owns a whole line, so both
+// in-plane transforms are register FFTs with compile-time twiddles and no
+// exchange between lanes, and each is pruned to the kept window by
+// wave-uniform branches.  A wave takes one band pair and two planes at a time
+// (lanes 0-31 plane j1, lanes 32-63 plane j1 + 1):
+//   pass 1  lane (h, j3): column j3 of plane j1 + h, product and FFT along j2
+//           as two half-length FFTs of the even and odd rows, combined only at
+//           the kept f2 -> T1_h[f2][j3];
+//   pass 2  lane (h, f2): row f2, the same split along j3 -> T2_h[f2][f3],
+//           written over the rows already read;
+//   pass 3  sphere point g = lane + 64 t accumulates both planes.
+// Element i of a wave-uniform array, addressed by a 32-bit byte offset so that
+// the load takes the scalar-base + 32-bit vector-offset form.
+__device__ __forceinline__ double2 ldg(const double2* base, unsigned i) {
+  return *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(base) + (size_t)(i * 16u));
+}
+
+// Materialise every value of x here: stops the optimiser from sinking the
+// last butterflies into the branches that pick the kept window, which would
+// keep their inputs live across all of them.
+template <int M>
+__device__ __forceinline__ void pin(double2 (&x)[M]) {
+#pragma unroll
+  for (int i = 0; i < M; ++i) asm volatile("" : "+v"(x[i].x), "+v"(x[i].y));
+}
+
+template <int N2, int N3, int TG, bool EXCH>
+__global__ __launch_bounds__(256, 2) void k_pair_density_line(PdArgs a) {
+  static_assert(N2 <= 32 && N3 <= 32 && N2 % 2 == 0 && N3 % 2 == 0, "lines must fit a half wave");
+  constexpr int H2 = N2 / 2, H3 = N3 / 2;
+  constexpr int S1 = 33;  // T1 row stride: columns N3..31 of idle lanes land in the padding
+  extern __shared__ double2 smem[];
+  const int N1 = a.N1, ngm = a.ng_max;
+  const int F2 = a.F2, F3 = a.F3;
+  double2* tw1 = smem;
+  // wave index made uniform so that band pointers live in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int h = lane >> 5, c = lane & 31;
+  const int per_pl = F2 * S1;
+  double2* T1 = tw1 + N1 + wave * 2 * per_pl;
+  int2* gtab = reinterpret_cast<int2*>(tw1 + N1 + 8 * per_pl);
+
+  for (int t = threadIdx.x; t < N1; t += blockDim.x) {
+    double s, cs;
+    sincospi(2.0 * t / N1, &s, &cs);
+    tw1[t] = make_double2(cs, -s);
+  }
+  const PdJob job = a.jobs[blockIdx.x];
+  const int nA = job.nab & 255, nB = job.nab >> 8;
+  int m01, m02, m03;
+  unpack_m(job.m0p, m01, m02, m03);
+  const int ngq = a.ng[job.iq];
+  const int* gq = a.gpack + (size_t)job.iq * ngm;
+  // sphere point g: offset of (f2, f3) in the window, f1 mod N1
+  for (int g = threadIdx.x; g < ngq; g += blockDim.x) {
+    int m1, m2, m3;
+    unpack_m(gq[g], m1, m2, m3);
+    gtab[g] = make_int2((m2 - m02 - a.lo2) * F3 + (m3 - m03 - a.lo3), imod(m1 - m01, N1));
+  }
+  // kept frequencies as bit masks: f is kept when (f - lo) mod N < F
+  unsigned keep2 = 0, keep3 = 0;
+  for (int f = 0; f < N2; ++f) keep2 |= (unsigned)(imod(f - a.lo2, N2) < F2) << f;
+  for (int f = 0; f < N3; ++f) keep3 |= (unsigned)(imod(f - a.lo3, N3) < F3) << f;
+  __syncthreads();
+  const float inv_n1 = 1.0f / (float)N1;
+
+  const int Nr = N1 * N2 * N3;
+  const int npd = nA * nB;
+  double2* T1h = T1 + h * per_pl;
+  for (int p = wave; p < npd; p += 4) {
+    const double2* ua = a.u + ((size_t)job.ka * a.nb + job.a0 + p / nB) * Nr;
+    const double2* ub = a.u + ((size_t)job.kb * a.nb + job.b0 + p % nB) * Nr;
+    double2 acc[TG];
+#pragma unroll
+    for (int t = 0; t < TG; ++t) acc[t] = make_double2(0.0, 0.0);
+
+    for (int j1 = 0; j1 < N1; j1 += 2) {
+      const bool two = j1 + 1 < N1;  // the second plane exists
+      // window masks and origins re-read per plane: kept loop-invariant they
+      // would pin one scalar condition per frequency across the loop
+      unsigned k2 = keep2, k3 = keep3;
+      int lo2 = a.lo2, lo3 = a.lo3;
+      asm volatile("" : "+s"(k2), "+s"(k3), "+s"(lo2), "+s"(lo3));
+      // ---- pass 1 (idle lanes load a valid column and write padding or a
+      // plane that pass 3 skips)
+      {
+        const unsigned off = (unsigned)((c < N3 ? c : 0) + (two ? j1 + h : j1) * (N2 * N3));
+        // even rows: load, multiply
+        double2 E[H2], O[H2];
+#pragma unroll
+        for (int s = 0; s < H2; ++s) E[s] = cconjmul(ldg(ua, off + 2 * s * N3), ldg(ub, off + 2 * s * N3));
+        __builtin_amdgcn_sched_barrier(0);
+        // first half of the odd rows in flight during the even-row FFT; the
+        // second half after it, so that at most half the odd rows sit in raw
+        // registers next to the even-row transform
+        constexpr int HO = H2 / 2;
+        double2 ra[HO], rb[HO];
+#pragma unroll
+        for (int s = 0; s < HO; ++s) {
+          ra[s] = ldg(ua, off + (2 * s + 1) * N3);
+          rb[s] = ldg(ub, off + (2 * s + 1) * N3);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        reg_fft<H2, 1, 0>(E);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s = 0; s < HO; ++s) O[s] = cconjmul(ra[s], rb[s]);
+#pragma unroll
+        for (int s = HO; s < H2; ++s) O[s] = cconjmul(ldg(ua, off + (2 * s + 1) * N3), ldg(ub, off + (2 * s + 1) * N3));
+        __builtin_amdgcn_sched_barrier(0);
+        reg_fft<H2, 1, 0>(O);
+        pin(E);
+        pin(O);
+        static_for<0, N2>([&](auto fc) {
+          constexpr int f = decltype(fc)::value;
+          if (k2 & (1u << f)) {  // wave-uniform
+            int r = f - lo2;
+            r += r < 0 ? N2 : 0;
+            r -= r >= N2 ? N2 : 0;
+            constexpr int q = fft_pos<H2>(f % H2);
+            T1h[r * S1 + c] = cadd(E[q], cmul_root<N2, f>(O[q]));
+          }
+        });
+      }
+      wave_sync();
+      // ---- pass 2
+      {
+        const bool ok = c < F2;
+        const int row = (ok ? c : 0) * S1;
+        double2 E[H3], O[H3];
+#pragma unroll
+        for (int s = 0; s < H3; ++s) {
+          E[s] = T1h[row + 2 * s];
+          O[s] = T1h[row + 2 * s + 1];
+        }
+        reg_fft<H3, 1, 0>(E);
+        reg_fft<H3, 1, 0>(O);
+        pin(E);
+        pin(O);
+        wave_sync();
+        static_for<0, N3>([&](auto fc) {
+          constexpr int f = decltype(fc)::value;
+          if (k3 & (1u << f)) {  // wave-uniform
+            int r = f - lo3;
+            r += r < 0 ? N3 : 0;
+            r -= r >= N3 ? N3 : 0;
+            constexpr int q = fft_pos<H3>(f % H3);
+            const double2 v = cadd(E[q], cmul_root<N3, f>(O[q]));
+            if (ok) T1h[c * F3 + r] = v;
+          }
+        });
+      }
+      wave_sync();
+      // ---- pass 3
+#pragma unroll
+      for (int t = 0; t < TG; ++t) {
+        if (lane + 64 * t < ngq) {
+          const int2 e = gtab[lane + 64 * t];
+          int r = e.y * j1;  // below 2^24: exact in float
+          r -= N1 * (int)((float)r * inv_n1);
+          r += r < 0 ? N1 : 0;
+          r -= r >= N1 ? N1 : 0;
+          acc[t] = cfma(T1[e.x], tw1[r], acc[t]);
+          if (two) {
+            r += e.y;
+            r -= r >= N1 ? N1 : 0;
+            acc[t] = cfma(T1[per_pl + e.x], tw1[r], acc[t]);
+          }
+        }
+      }
+      wave_sync();
+    }
+    double2* o = a.out + (size_t)(job.row0 + p) * ngm;
+#pragma unroll
+    for (int t = 0; t < TG; ++t) {
+      const int g = lane + 64 * t;
+      if (g < ngq) {
+        const double sc = EXCH ? a.vscale[g] : 1.0;
+        o[g] = make_double2(acc[t].x * sc, acc[t].y * sc);
+      } else if (g < ngm) {
+        o[g] = make_double2(0.0, 0.0);
+      }
+    }
+  }
+}
+
+template <int N2, int N3>
+constexpr bool use_line() {
+  return N2 <= 32 && N3 <= 32 && N2 % 2 == 0 && N3 % 2 == 0;
+}
+
 static int tg_bucket(int ng_max) {
   const int t = (ng_max + 63) / 64;
   return t <= 4 ? 4 : t <= 5 ? 5 : t <= 8 ? 8 : t <= 13 ? 13 : 16;
@@ -209,6 +401,8 @@ static int tg_bucket(int ng_max) {
 
 template <int N2, int N3>
 static size_t lds_bytes(int N1, int F2, int F3, int ng_max) {
+  if constexpr (use_line<N2, N3>())
+    return sizeof(double2) * ((size_t)N1 + 8 * (size_t)F2 * 33) + sizeof(int2) * (size_t)ng_max;
   using G = PlaneGeo<N2, N3>;
   const int FA = G::AX == 2 ? F2 : F3;
   return sizeof(double2) * ((size_t)N1 + N2 + N3 + 4 * (size_t)G::PW * FA * G::SA) + sizeof(int2) * (size_t)ng_max;
@@ -216,7 +410,11 @@ static size_t lds_bytes(int N1, int F2, int F3, int ng_max) {
 
 template <int N2, int N3, int TG>
 static hipError_t launch_tg(const PdArgs& a, int njobs, size_t lds, hipStream_t st) {
-  void (*k)(PdArgs) = a.vscale ? k_pair_density<N2, N3, TG, true> : k_pair_density<N2, N3, TG, false>;
+  void (*k)(PdArgs);
+  if constexpr (use_line<N2, N3>())
+    k = a.vscale ? k_pair_density_line<N2, N3, TG, true> : k_pair_density_line<N2, N3, TG, false>;
+  else
+    k = a.vscale ? k_pair_density<N2, N3, TG, true> : k_pair_density<N2, N3, TG, false>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(njobs), dim3(256), lds, st, a);
