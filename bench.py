@@ -66,7 +66,7 @@ def traffic_from_profile(kernel_digest, per_launch_units):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(s, target_s=15.0):
+def cpu_baseline(s, target_s=35.0):
     """The oracle (as it stands) on a T x T tile of (k, k') blocks of the same
     workload, on the host cores."""
     import oracle as O

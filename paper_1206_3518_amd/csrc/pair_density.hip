@@ -272,9 +272,18 @@ __global__ __launch_bounds__(256, 2) void k_pair_density_line(PdArgs a) {
   const int Nr = N1 * N2 * N3;
   const int npd = nA * nB;
   double2* T1h = T1 + h * per_pl;
+  // with an even number of bands on both sides the four waves of a step take
+  // a 2 x 2 block of band pairs (four distinct grids per step instead of five)
+  const bool blk = nA % 2 == 0 && nB % 2 == 0;
   for (int p = wave; p < npd; p += 4) {
-    const double2* ua = a.u + ((size_t)job.ka * a.nb + job.a0 + p / nB) * Nr;
-    const double2* ub = a.u + ((size_t)job.kb * a.nb + job.b0 + p % nB) * Nr;
+    int ia = p / nB, ib = p % nB;
+    if (blk) {
+      const int i = p >> 2, nb2 = nB >> 1;
+      ia = 2 * (i / nb2) + (wave >> 1);
+      ib = 2 * (i % nb2) + (wave & 1);
+    }
+    const double2* ua = a.u + ((size_t)job.ka * a.nb + job.a0 + ia) * Nr;
+    const double2* ub = a.u + ((size_t)job.kb * a.nb + job.b0 + ib) * Nr;
     double2 acc[TG];
 #pragma unroll
     for (int t = 0; t < TG; ++t) acc[t] = make_double2(0.0, 0.0);
@@ -375,7 +384,7 @@ __global__ __launch_bounds__(256, 2) void k_pair_density_line(PdArgs a) {
       }
       wave_sync();
     }
-    double2* o = a.out + (size_t)(job.row0 + p) * ngm;
+    double2* o = a.out + (size_t)(job.row0 + ia * nB + ib) * ngm;
 #pragma unroll
     for (int t = 0; t < TG; ++t) {
       const int g = lane + 64 * t;
