@@ -89,10 +89,10 @@ def cpu_baseline(s, target_s=35.0):
             "sample": f"{T}x{T} tile of random (k,k') blocks ({len(blocks) * nt * nt} elements), {dt:.1f} s"}
 
 
-def run_steps(P, dev, prec, ws, steps, warmup):
+def run_steps(P, devs, prec, flags, ws, steps, warmup):
     import torch
     for _ in range(warmup):
-        P.bse_build_H([dev], prec, 0, ws)
+        P.bse_build_H(devs, prec, flags, ws)
     torch.cuda.synchronize()
     P.bse_profile_read(reset=True)
     P.bse_profile(True)
@@ -102,7 +102,7 @@ def run_steps(P, dev, prec, ws, steps, warmup):
     t0 = time.perf_counter()
     e0.record(st)
     for _ in range(steps):
-        P.bse_build_H([dev], prec, 0, ws)
+        P.bse_build_H(devs, prec, flags, ws)
     e1.record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -117,7 +117,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp64", choices=list(DTYPES))
-    ap.add_argument("--config", type=int, default=2, help="workload index (default: the Si-like 8192 case)")
+    ap.add_argument("--config", type=int, default=2,
+                    help="workload index: 2 = the Si-like 8192 case (default), 3 = the h-BN-like batch of 16")
+    ap.add_argument("--persistent", action="store_true", help="persistent work-queue dispatch of the pair densities")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the split-FP32 / BF16x3 comparison runs")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -131,10 +133,12 @@ def main():
     import bse_synth as B
     import paper_1206_3518_amd as P
 
-    s = B.make_config(args.config)
-    dev = P.DeviceSystem(s, device="cuda:0")
+    made = B.make_config(args.config)
+    systems = made if isinstance(made, list) else [made]
+    devs = [P.DeviceSystem(s, device="cuda:0") for s in systems]
     prec = P.PRECISIONS[args.precision]
-    ws = P.workspace(P.bse_workspace_size([dev], prec), dev.device)
+    flags = P.BSE_PERSISTENT if args.persistent else 0
+    ws = P.workspace(P.bse_workspace_size(devs, prec), devs[0].device)
     torch.cuda.synchronize()
 
     if args.copy_calibration_mb:
@@ -145,10 +149,11 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    ms, wall, stages = run_steps(P, dev, prec, ws, args.steps, args.warmup)
-    elements = float(s.ns) ** 2
+    ms, wall, stages = run_steps(P, devs, prec, flags, ws, args.steps, args.warmup)
+    elements = float(sum(float(s.ns) ** 2 for s in systems))
     value = elements / (ms / 1e3)
-    d1_flops, ex_flops = gemm_flops(s)
+    d1_flops = sum(gemm_flops(s)[0] for s in systems)
+    ex_flops = sum(gemm_flops(s)[1] for s in systems)
     hw = {"fp64": (1.0, PEAK["fp64_TFLOPs"]), "split_fp32": (3.0, PEAK["fp32_TFLOPs"]),
           "bf16x3": (3.0, PEAK["bf16_TFLOPs"])}
 
@@ -161,50 +166,59 @@ def main():
                 "exchange_useful_TFLOPs": ex_flops / ex / 1e12}
 
     # dominant kernel: the pair-density kernel over the direct term's band pairs
-    npairs = s.nk * (s.nk + 1) // 2
+    # (one launch per band kind, vv and cc, covering every system)
+    grid = systems[0].grid
     pd_ms = stages["pd_vv"][0] + stages["pd_cc"][0]
     pd_n = stages["pd_vv"][1] + stages["pd_cc"][1]
-    units = npairs * (s.nv * s.nv + s.nc * s.nc) / 2.0  # pair densities per launch (vv and cc alike)
+    units = sum(s.nk * (s.nk + 1) // 2 * (s.nv * s.nv + s.nc * s.nc) / 2.0 for s in systems)  # per launch
     avg_s = pd_ms / pd_n / 1e3
-    achieved = pd_flops(s.grid) * units / avg_s / 1e12
+    achieved = pd_flops(grid) * units / avg_s / 1e12
     digest = kernel_source_digest()
-    line = s.grid[1] <= 32 and s.grid[2] <= 32 and s.grid[1] % 2 == 0 and s.grid[2] % 2 == 0
-    roofline = {"bound": "alu", "kernel": "k_pair_density_line" if line else "k_pair_density", "achieved": achieved, "peak": PEAK["fp64_TFLOPs"],
-                "unit": "TFLOP/s", "frac": achieved / PEAK["fp64_TFLOPs"],
-                "traffic": traffic_from_profile(digest, units), "avg_launch_ms": pd_ms / pd_n,
-                "flops_per_launch": pd_flops(s.grid) * units, "kernel_digest": digest}
+    line = grid[1] <= 32 and grid[2] <= 32 and grid[1] % 2 == 0 and grid[2] % 2 == 0
+    roofline = {"bound": "alu", "kernel": "k_pair_density_line" if line else "k_pair_density", "achieved": achieved,
+                "peak": PEAK["fp64_TFLOPs"], "unit": "TFLOP/s", "frac": achieved / PEAK["fp64_TFLOPs"],
+                "traffic": traffic_from_profile(digest, units) if args.config == 2 else None,
+                "avg_launch_ms": pd_ms / pd_n, "flops_per_launch": pd_flops(grid) * units, "kernel_digest": digest}
 
+    if len(systems) == 1:
+        s = systems[0]
+        config = {"workload": s.name, "ns": s.ns, "grid": list(s.grid), "kmesh": list(s.kmesh), "nv": s.nv,
+                  "nc": s.nc, "ng_max": s.ng_max, "precision": args.precision, "parallelism": "single-gpu"}
+    else:
+        config = {"workload": f"hbn-batch{len(systems)}", "systems": len(systems), "grid": list(grid),
+                  "kmeshes": [list(s.kmesh) for s in systems], "ns": [s.ns for s in systems],
+                  "ng_max": [s.ng_max for s in systems], "nv": systems[0].nv, "nc": systems[0].nc,
+                  "precision": args.precision, "parallelism": "single-gpu"}
+    config["dispatch"] = "persistent" if args.persistent else "static"
     out = {"metric": "BSE H build: elements/s + % MFMA peak, FP64 vs mixed at <=1e-4 eV error",
            "value": value, "unit": "H elements/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": DTYPES[args.precision], "data": "synthetic",
-           "config": {"workload": s.name, "ns": s.ns, "grid": list(s.grid), "kmesh": list(s.kmesh), "nv": s.nv,
-                      "nc": s.nc, "ng_max": s.ng_max, "precision": args.precision, "parallelism": "single-gpu"},
+           "dtype": DTYPES[args.precision], "data": "synthetic", "config": config,
            "stage_ms": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
            "gemm": gemm_report(stages, args.precision),
            "wall_s": wall, "roofline": roofline}
     if not args.no_mixed and args.precision == "fp64":
-        import torch
-        H64 = dev.H.clone()
-        kscale = (H64 - torch.diag(torch.diag(H64))).abs().max().item()
+        H64 = [d.H.clone() for d in devs]
+        kscale = max((h - torch.diag(torch.diag(h))).abs().max().item() for h in H64)
         # lowest exciton energies, FP64 eigensolve of each H (outside the timed region)
-        E64 = torch.linalg.eigvalsh(H64)[:10].cpu().numpy()
-        out["lowest_exciton_eV"] = E64.tolist()
+        E64 = [torch.linalg.eigvalsh(h)[:10].cpu().numpy() for h in H64]
+        out["lowest_exciton_eV"] = E64[0].tolist()
         mixed = {}
         for name in ("split_fp32", "bf16x3"):
             pm = P.PRECISIONS[name]
-            msm, _, stm = run_steps(P, dev, pm, ws, max(2, args.steps // 2), 1)
-            dH = (dev.H - H64).abs().max().item()
-            Em = torch.linalg.eigvalsh(dev.H)[:10].cpu().numpy()
+            msm, _, stm = run_steps(P, devs, pm, flags, ws, max(2, args.steps // 2), 1)
+            dH = max((d.H - h).abs().max().item() for d, h in zip(devs, H64))
+            dE = max(float(np.abs(torch.linalg.eigvalsh(d.H)[:10].cpu().numpy() - e).max())
+                     for d, e in zip(devs, E64))
             mixed[name] = {"value": elements / (msm / 1e3), "ms_per_step": msm, "speedup_vs_fp64": ms / msm,
                            "max_abs_dH_eV": dH, "max_abs_dH_over_kernel": dH / kscale,
-                           "max_abs_dE_lowest10_eV": float(np.abs(Em - E64).max()),
+                           "max_abs_dE_lowest10_eV": dE,
                            "stage_ms": {k: v[0] / max(v[1], 1) for k, v in stm.items()},
                            "gemm": gemm_report(stm, name)}
         out["mixed"] = mixed
         del H64
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(s)
+        out["cpu_baseline"] = cpu_baseline(systems[0])
     print(json.dumps(out))
 
 

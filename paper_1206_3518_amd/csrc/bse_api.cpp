@@ -92,14 +92,19 @@ void fold(const int* n, int ka, int kb, int& iq, int m0[3]) {
 
 // Dispatch order of pair-density jobs.  Workgroup i runs on XCD i mod 8 and
 // each XCD keeps about 64 workgroups resident, so the job list is cut into 8
-// contiguous chunks (one per XCD) of jobs sorted by 8 x 8 tiles of (k, k'):
-// the resident jobs of an XCD then read the wave functions of ~16 k points,
-// which its L2 holds plane by plane.  Holes become empty jobs.
-constexpr int kXcds = 8, kTileK = 8;
+// contiguous chunks (one per XCD) of jobs sorted by system and then by
+// ktile x ktile tiles of (k, k'): the resident jobs of an XCD then read the
+// wave functions of few k points, which its L2 holds plane by plane.  Chunk x
+// is stored at positions 8 t + x (static dispatch hands workgroup 8 t + x to
+// XCD x; persistent dispatch uses chunk x as the XCD's queue).  Holes become
+// empty jobs.
+constexpr int kXcds = 8;
 
-std::vector<PdJob> dispatch_order(std::vector<PdJob> jobs) {
-  std::stable_sort(jobs.begin(), jobs.end(), [](const PdJob& x, const PdJob& y) {
-    const int tx = x.ka / kTileK, ty = y.ka / kTileK, ux = x.kb / kTileK, uy = y.kb / kTileK;
+std::vector<PdJob> dispatch_order(std::vector<PdJob> jobs, int ktile) {
+  std::stable_sort(jobs.begin(), jobs.end(), [ktile](const PdJob& x, const PdJob& y) {
+    const int sx = x.nab >> 16, sy = y.nab >> 16;
+    if (sx != sy) return sx < sy;
+    const int tx = x.ka / ktile, ty = y.ka / ktile, ux = x.kb / ktile, uy = y.kb / ktile;
     if (tx != ty) return tx < ty;
     if (ux != uy) return ux < uy;
     if (x.ka != y.ka) return x.ka < y.ka;
@@ -118,16 +123,18 @@ struct Plan {
   std::vector<int> gpack, ng;
   std::vector<int4> pairs;  // (ka, kb, iq, m0p), k <= k', sorted by q
   std::vector<int> qstart;  // [nk + 1]
-  std::vector<PdJob> jx, jv, jc;
+  std::vector<PdJob> jx, jv, jc;  // system 0, natural order
   std::vector<S1Tile> s1;
-  std::vector<int2> xt;
+  std::vector<HTile> xt, mt;       // exchange tiles; mirror tiles
+  int d2items = 0;                 // stage-2 items (pairs x 16 x 16 tiles)
   std::vector<int4> dwt;   // adjoint dW tiles (q, mt, nt, -)
   std::vector<int> qbar, trmap;
   bool tr_closed = true;
-  // byte offsets inside the workspace
-  size_t o_gpack = 0, o_ng = 0, o_pairs = 0, o_qstart = 0, o_jx = 0, o_jv = 0, o_jc = 0, o_s1 = 0, o_xt = 0;
+  // byte offsets inside the system's region of the workspace
+  size_t o_gpack = 0, o_ng = 0, o_pairs = 0, o_qstart = 0;
   size_t o_dwt = 0, o_qbar = 0, o_trmap = 0;
   size_t tables = 0, o_vs = 0, o_X = 0, o_RV = 0, o_RC = 0, o_Z = 0, o_dWraw = 0, total = 0;
+  size_t fwd_total = 0;  // region needed by the forward build (no dW scratch)
 };
 
 int check_system(const bse_system* s) {
@@ -215,8 +222,6 @@ int make_plan(const bse_system* s, Plan& P) {
     P.jv[p] = PdJob{pr.x, pr.y, pr.w, pr.z, 0, 0, P.nv | (P.nv << 8), p * P.nv * P.nv};
     P.jc[p] = PdJob{pr.x, pr.y, pr.w, pr.z, P.nv, P.nv, P.nc | (P.nc << 8), p * P.nc * P.nc};
   }
-  P.jv = dispatch_order(std::move(P.jv));
-  P.jc = dispatch_order(std::move(P.jc));
   // stage-1 tiles: per q, rows = pairs(q) * nv^2, cols = ng(q)
   P.s1.clear();
   for (int q = 0; q < P.nk; ++q) {
@@ -230,7 +235,13 @@ int make_plan(const bse_system* s, Plan& P) {
   P.xt.clear();
   const int T = (P.ns + 63) / 64;
   for (int i = 0; i < T; ++i)
-    for (int j = std::max(0, i - 1); j < T; ++j) P.xt.push_back(make_int2(i, j));
+    for (int j = std::max(0, i - 1); j < T; ++j) P.xt.push_back(HTile{i, j, 0, 0});
+  // mirror tiles: 32 x 32 destination tiles on or below the diagonal
+  P.mt.clear();
+  const int T32 = (P.ns + 31) / 32;
+  for (int i = 0; i < T32; ++i)
+    for (int j = 0; j <= i; ++j) P.mt.push_back(HTile{i, j, 0, 0});
+  P.d2items = np * ((P.nv * P.nv + 15) / 16) * ((P.nc * P.nc + 15) / 16);
 
   // adjoint: dW tiles over ng_max x ng_max per q; time-reversal partners
   P.dwt.clear();
@@ -280,11 +291,6 @@ int make_plan(const bse_system* s, Plan& P) {
   P.o_ng = put(P.ng.size() * sizeof(int));
   P.o_pairs = put(P.pairs.size() * sizeof(int4));
   P.o_qstart = put(P.qstart.size() * sizeof(int));
-  P.o_jx = put(P.jx.size() * sizeof(PdJob));
-  P.o_jv = put(P.jv.size() * sizeof(PdJob));
-  P.o_jc = put(P.jc.size() * sizeof(PdJob));
-  P.o_s1 = put(P.s1.size() * sizeof(S1Tile));
-  P.o_xt = put(P.xt.size() * sizeof(int2));
   P.o_dwt = put(P.dwt.size() * sizeof(int4));
   P.o_qbar = put(P.qbar.size() * sizeof(int));
   P.o_trmap = put(P.trmap.size() * sizeof(int));
@@ -294,114 +300,286 @@ int make_plan(const bse_system* s, Plan& P) {
   P.o_RV = put((size_t)np * P.nv * P.nv * P.ng_max * sizeof(double2));
   P.o_RC = put((size_t)np * P.nc * P.nc * P.ng_max * sizeof(double2));
   P.o_Z = put((size_t)np * P.nv * P.nv * P.ng_max * sizeof(double2));
+  P.fwd_total = o;
   P.o_dWraw = put((size_t)P.nk * P.ng_max * P.ng_max * sizeof(double2));
   P.total = o;
   return BSE_OK;
 }
 
-int upload_tables(const Plan& P, char* ws, hipStream_t st) {
-  std::vector<char> buf(P.tables, 0);
+// Host tables of one system at `base` inside the workspace (the region the
+// system's plan laid out).
+void put_tables(const Plan& P, std::vector<char>& buf, size_t base) {
   auto cp = [&](size_t off, const void* src, size_t bytes) {
-    if (bytes) std::memcpy(buf.data() + off, src, bytes);
+    if (bytes) std::memcpy(buf.data() + base + off, src, bytes);
   };
   cp(P.o_gpack, P.gpack.data(), P.gpack.size() * sizeof(int));
   cp(P.o_ng, P.ng.data(), P.ng.size() * sizeof(int));
   cp(P.o_pairs, P.pairs.data(), P.pairs.size() * sizeof(int4));
   cp(P.o_qstart, P.qstart.data(), P.qstart.size() * sizeof(int));
-  cp(P.o_jx, P.jx.data(), P.jx.size() * sizeof(PdJob));
-  cp(P.o_jv, P.jv.data(), P.jv.size() * sizeof(PdJob));
-  cp(P.o_jc, P.jc.data(), P.jc.size() * sizeof(PdJob));
-  cp(P.o_s1, P.s1.data(), P.s1.size() * sizeof(S1Tile));
-  cp(P.o_xt, P.xt.data(), P.xt.size() * sizeof(int2));
   cp(P.o_dwt, P.dwt.data(), P.dwt.size() * sizeof(int4));
   cp(P.o_qbar, P.qbar.data(), P.qbar.size() * sizeof(int));
   cp(P.o_trmap, P.trmap.data(), P.trmap.size() * sizeof(int));
-  HIP_TRY(hipMemcpyWithStream(ws, buf.data(), P.tables, hipMemcpyHostToDevice, st));
-  return BSE_OK;
 }
 
-PdArgs pd_args(const Plan& P, const bse_system* s, char* ws) {
+PdArgs pd_args(const Plan& P, const bse_system* s, char* region) {
   PdArgs a{};
   a.u = reinterpret_cast<const double2*>(s->u);
   a.nb = P.nb;
   a.N1 = P.N1;
-  a.gpack = reinterpret_cast<const int*>(ws + P.o_gpack);
-  a.ng = reinterpret_cast<const int*>(ws + P.o_ng);
+  a.gpack = reinterpret_cast<const int*>(region + P.o_gpack);
+  a.ng = reinterpret_cast<const int*>(region + P.o_ng);
   a.ng_max = P.ng_max;
   a.lo2 = P.lo[1];
   a.lo3 = P.lo[2];
   a.F2 = P.F[1];
   a.F3 = P.F[2];
   a.vscale = nullptr;
+  a.out = nullptr;
   return a;
 }
 
-int check_lds(const Plan& P) {
-  if (pd_lds_bytes(P.N1, P.N2, P.N3, P.F[1], P.F[2], P.ng_max) > 160 * 1024)
-    return fail(BSE_ERR_SHAPE, "FFT window needs more than 160 KiB of LDS");
-  return BSE_OK;
-}
-
-int build_one(const bse_system* s, int precision, int flags, char* ws, size_t ws_bytes, hipStream_t st) {
-  Plan P;
-  int rc = make_plan(s, P);
-  if (rc) return rc;
-  if ((rc = check_lds(P))) return rc;
-  if (!s->H) return fail(BSE_ERR_INVALID_ARG, "H is NULL");
-  if (ws_bytes < P.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, P.total);
-  (void)flags;
-  if ((rc = upload_tables(P, ws, st))) return rc;
-
-  double* vs = reinterpret_cast<double*>(ws + P.o_vs);
-  HIP_TRY(stage(BSE_STAGE_VSCALE, st, [&] { return launch_vscale(s->vx, P.ng[0], P.ng_max, vs, st); }));
-
-  PdArgs a = pd_args(P, s, ws);
-  // exchange pair densities, scaled by sqrt v(G)
-  a.jobs = reinterpret_cast<const PdJob*>(ws + P.o_jx);
-  a.out = reinterpret_cast<double2*>(ws + P.o_X);
-  a.vscale = vs;
-  HIP_TRY(stage(BSE_STAGE_PD_EXCH, st, [&] { return launch_pair_density(a, P.N2, P.N3, (int)P.jx.size(), st); }));
-  a.vscale = nullptr;
-  a.jobs = reinterpret_cast<const PdJob*>(ws + P.o_jv);
-  a.out = reinterpret_cast<double2*>(ws + P.o_RV);
-  HIP_TRY(stage(BSE_STAGE_PD_VV, st, [&] { return launch_pair_density(a, P.N2, P.N3, (int)P.jv.size(), st); }));
-  a.jobs = reinterpret_cast<const PdJob*>(ws + P.o_jc);
-  a.out = reinterpret_cast<double2*>(ws + P.o_RC);
-  HIP_TRY(stage(BSE_STAGE_PD_CC, st, [&] { return launch_pair_density(a, P.N2, P.N3, (int)P.jc.size(), st); }));
-
+GemmArgs gemm_args(const Plan& P, const bse_system* s, char* region) {
   GemmArgs g{};
-  g.X = reinterpret_cast<const double2*>(ws + P.o_X);
+  g.X = reinterpret_cast<const double2*>(region + P.o_X);
   g.ns = P.ns;
   g.ng_max = P.ng_max;
   g.ngx = P.ng[0];
   g.H = reinterpret_cast<double2*>(s->H);
   g.cpref = 27.211386245988 / ((double)P.nk * s->omega_cell);
-  g.RV = reinterpret_cast<const double2*>(ws + P.o_RV);
-  g.RC = reinterpret_cast<const double2*>(ws + P.o_RC);
-  g.Z = reinterpret_cast<double2*>(ws + P.o_Z);
+  g.RV = reinterpret_cast<const double2*>(region + P.o_RV);
+  g.RC = reinterpret_cast<const double2*>(region + P.o_RC);
+  g.Z = reinterpret_cast<double2*>(region + P.o_Z);
   g.W = reinterpret_cast<const double2*>(s->W);
-  g.ng = reinterpret_cast<const int*>(ws + P.o_ng);
-  g.qstart = reinterpret_cast<const int*>(ws + P.o_qstart);
-  g.pairs = reinterpret_cast<const int4*>(ws + P.o_pairs);
-  g.s1tiles = reinterpret_cast<const S1Tile*>(ws + P.o_s1);
+  g.ng = reinterpret_cast<const int*>(region + P.o_ng);
+  g.qstart = reinterpret_cast<const int*>(region + P.o_qstart);
+  g.pairs = reinterpret_cast<const int4*>(region + P.o_pairs);
   g.eps = s->eps;
   g.nv = P.nv;
   g.nc = P.nc;
   g.nb = P.nb;
   g.npairs = (int)P.pairs.size();
-  g.precision = precision;
-  g.w_head_fp64 = precision != BSE_FP64;
-  const int2* xt = reinterpret_cast<const int2*>(ws + P.o_xt);
-  if (precision == BSE_FP64) {
-    HIP_TRY(stage(BSE_STAGE_EXCHANGE, st, [&] { return launch_exchange(g, xt, (int)P.xt.size(), st); }));
-    HIP_TRY(stage(BSE_STAGE_DIRECT1, st, [&] { return launch_direct_s1(g, (int)P.s1.size(), st); }));
-    HIP_TRY(stage(BSE_STAGE_DIRECT2, st, [&] { return launch_direct_s2(g, 0, st); }));
-  } else {
-    HIP_TRY(stage(BSE_STAGE_EXCHANGE, st, [&] { return launch_exchange_mx(g, xt, (int)P.xt.size(), st); }));
-    HIP_TRY(stage(BSE_STAGE_DIRECT1, st, [&] { return launch_direct_s1_mx(g, (int)P.s1.size(), st); }));
-    HIP_TRY(stage(BSE_STAGE_DIRECT2, st, [&] { return launch_direct_s2_mx(g, st); }));
+  g.nt = P.nt;
+  return g;
+}
+
+// ------------------------------------------------------------ batches
+
+// Launch choices that the autotuner may change (per batch signature).
+struct Tune {
+  int persist = 0;  // persistent work-queue dispatch of the pair-density jobs
+  int ktile = 8;    // k tile of the pair-density dispatch order
+};
+std::mutex g_tune_mu;
+std::vector<std::pair<std::string, Tune>> g_tune;
+
+// Signature of a batch: everything that shapes its launches.
+std::string batch_key(const std::vector<Plan>& Ps, int precision) {
+  std::string k = "p" + std::to_string(precision);
+  for (const Plan& P : Ps) {
+    char b[160];
+    snprintf(b, sizeof b, "|%dx%dx%d:k%d:b%d+%d:g%d:w%dx%d", P.N1, P.N2, P.N3, P.nk, P.nv, P.nc, P.ng_max, P.F[1],
+             P.F[2]);
+    k += b;
   }
-  HIP_TRY(stage(BSE_STAGE_MIRROR, st, [&] { return launch_mirror(g.H, P.ns, P.nt, st); }));
+  return k;
+}
+
+Tune tune_for(const std::string& key) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& e : g_tune)
+    if (e.first == key) return e.second;
+  return Tune{};
+}
+
+void set_tune(const std::string& key, const Tune& t) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& e : g_tune)
+    if (e.first == key) {
+      e.second = t;
+      return;
+    }
+  g_tune.emplace_back(key, t);
+}
+
+// A batch of systems that share (N2, N3): per-system plans and workspace
+// regions, and the merged job and tile lists of the one-launch-per-stage build.
+struct Batch {
+  std::vector<Plan> P;
+  std::vector<size_t> base;  // workspace offset of each system's region
+  int N2 = 0, N3 = 0, ng_max = 0;
+  size_t lds = 0;
+  std::vector<PdJob> jx, jv, jc;
+  std::vector<S1Tile> s1;
+  std::vector<HTile> xt, mt;
+  std::vector<int> d2off;
+  int d2n = 0;
+  size_t o_pdx = 0, o_pdv = 0, o_pdc = 0, o_gargs = 0, o_jx = 0, o_jv = 0, o_jc = 0, o_s1 = 0, o_xt = 0, o_mt = 0;
+  size_t o_d2off = 0, o_cnt = 0, tables = 0, total = 0;
+};
+
+int make_batch(const bse_system* sys, int nsys, bool backward, const Tune& tn, Batch& B) {
+  if (!sys || nsys < 1) return fail(BSE_ERR_INVALID_ARG, "no systems");
+  if (nsys > 32767) return fail(BSE_ERR_INVALID_ARG, "too many systems");
+  B.P.resize(nsys);
+  for (int i = 0; i < nsys; ++i) {
+    int rc = make_plan(&sys[i], B.P[i]);
+    if (rc) return rc;
+    const Plan& P = B.P[i];
+    if (i == 0) {
+      B.N2 = P.N2;
+      B.N3 = P.N3;
+    } else if (P.N2 != B.N2 || P.N3 != B.N3) {
+      return fail(BSE_ERR_SHAPE, "systems of one batch must share N2, N3 (system %d has %d x %d, not %d x %d)", i, P.N2,
+                  P.N3, B.N2, B.N3);
+    }
+    B.ng_max = std::max(B.ng_max, P.ng_max);
+    const size_t l = pd_lds_bytes(P.N1, P.N2, P.N3, P.F[1], P.F[2], P.ng_max);
+    if (l > 160 * 1024) return fail(BSE_ERR_SHAPE, "FFT window of system %d needs more than 160 KiB of LDS", i);
+    B.lds = std::max(B.lds, l);
+  }
+  // merged lists
+  std::vector<PdJob> jx, jv, jc;
+  B.d2off.assign(nsys + 1, 0);
+  for (int i = 0; i < nsys; ++i) {
+    const Plan& P = B.P[i];
+    for (PdJob j : P.jx) jx.push_back((j.nab |= i << 16, j));
+    for (PdJob j : P.jv) jv.push_back((j.nab |= i << 16, j));
+    for (PdJob j : P.jc) jc.push_back((j.nab |= i << 16, j));
+    for (S1Tile s : P.s1) B.s1.push_back((s.sys = i, s));
+    for (HTile h : P.xt) B.xt.push_back((h.sys = i, h));
+    for (HTile h : P.mt) B.mt.push_back((h.sys = i, h));
+    B.d2off[i + 1] = B.d2off[i] + P.d2items;
+  }
+  B.d2n = B.d2off[nsys];
+  B.jx = dispatch_order(std::move(jx), tn.ktile);
+  B.jv = dispatch_order(std::move(jv), tn.ktile);
+  B.jc = dispatch_order(std::move(jc), tn.ktile);
+  // workspace: batch tables, then one region per system
+  size_t o = 0;
+  auto put = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  B.o_pdx = put(nsys * sizeof(PdArgs));
+  B.o_pdv = put(nsys * sizeof(PdArgs));
+  B.o_pdc = put(nsys * sizeof(PdArgs));
+  B.o_gargs = put(nsys * sizeof(GemmArgs));
+  B.o_jx = put(B.jx.size() * sizeof(PdJob));
+  B.o_jv = put(B.jv.size() * sizeof(PdJob));
+  B.o_jc = put(B.jc.size() * sizeof(PdJob));
+  B.o_s1 = put(B.s1.size() * sizeof(S1Tile));
+  B.o_xt = put(B.xt.size() * sizeof(HTile));
+  B.o_mt = put(B.mt.size() * sizeof(HTile));
+  B.o_d2off = put(B.d2off.size() * sizeof(int));
+  B.o_cnt = put(3 * kXcds * sizeof(unsigned));
+  B.base.resize(nsys);
+  for (int i = 0; i < nsys; ++i) {
+    B.base[i] = o;
+    o = align256(o + (backward ? B.P[i].total : B.P[i].fwd_total));
+  }
+  B.total = o;
+  return BSE_OK;
+}
+
+// Uploads every table of the batch (one blocking copy).
+int upload_batch(const Batch& B, const bse_system* sys, int precision, char* ws, hipStream_t st) {
+  const int nsys = (int)B.P.size();
+  std::vector<char> buf(B.base.back() + B.P.back().tables, 0);
+  auto cp = [&](size_t off, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(buf.data() + off, src, bytes);
+  };
+  std::vector<PdArgs> ax(nsys), av(nsys), ac(nsys);
+  std::vector<GemmArgs> ga(nsys);
+  for (int i = 0; i < nsys; ++i) {
+    const Plan& P = B.P[i];
+    char* region = ws + B.base[i];
+    PdArgs a = pd_args(P, &sys[i], region);
+    ax[i] = a;
+    ax[i].vscale = reinterpret_cast<const double*>(region + P.o_vs);
+    ax[i].out = reinterpret_cast<double2*>(region + P.o_X);
+    av[i] = a;
+    av[i].out = reinterpret_cast<double2*>(region + P.o_RV);
+    ac[i] = a;
+    ac[i].out = reinterpret_cast<double2*>(region + P.o_RC);
+    ga[i] = gemm_args(P, &sys[i], region);
+    ga[i].w_head_fp64 = precision != BSE_FP64;  // mixed: the q = 0 head of W is added in FP64
+    put_tables(P, buf, B.base[i]);
+  }
+  cp(B.o_pdx, ax.data(), nsys * sizeof(PdArgs));
+  cp(B.o_pdv, av.data(), nsys * sizeof(PdArgs));
+  cp(B.o_pdc, ac.data(), nsys * sizeof(PdArgs));
+  cp(B.o_gargs, ga.data(), nsys * sizeof(GemmArgs));
+  cp(B.o_jx, B.jx.data(), B.jx.size() * sizeof(PdJob));
+  cp(B.o_jv, B.jv.data(), B.jv.size() * sizeof(PdJob));
+  cp(B.o_jc, B.jc.data(), B.jc.size() * sizeof(PdJob));
+  cp(B.o_s1, B.s1.data(), B.s1.size() * sizeof(S1Tile));
+  cp(B.o_xt, B.xt.data(), B.xt.size() * sizeof(HTile));
+  cp(B.o_mt, B.mt.data(), B.mt.size() * sizeof(HTile));
+  cp(B.o_d2off, B.d2off.data(), B.d2off.size() * sizeof(int));
+  // the per-system data arrays between the table blocks are not copied
+  HIP_TRY(hipMemcpyWithStream(ws, buf.data(), B.o_cnt, hipMemcpyHostToDevice, st));
+  for (int i = 0; i < nsys; ++i)
+    HIP_TRY(hipMemcpyWithStream(ws + B.base[i], buf.data() + B.base[i], B.P[i].tables, hipMemcpyHostToDevice, st));
+  return BSE_OK;
+}
+
+// Workgroups of a persistent pair-density launch: every CU's resident share
+// (two per CU at most, fewer if the LDS footprint allows less), a multiple of 8.
+int persistent_grid(size_t lds, int njobs) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+  }
+  const int per_cu = std::max(1, std::min(2, (int)((160 * 1024) / std::max<size_t>(lds, 1))));
+  int g = std::max(kXcds, (cus * per_cu) / kXcds * kXcds);
+  return std::min(g, std::max(njobs, kXcds));
+}
+
+// One pair-density launch over the batch: kind 0 exchange, 1 vv, 2 cc.
+int run_pd(const Batch& B, char* ws, int kind, const Tune& tn, hipStream_t st) {
+  const std::vector<PdJob>& jobs = kind == 0 ? B.jx : kind == 1 ? B.jv : B.jc;
+  const size_t o_args = kind == 0 ? B.o_pdx : kind == 1 ? B.o_pdv : B.o_pdc;
+  const size_t o_jobs = kind == 0 ? B.o_jx : kind == 1 ? B.o_jv : B.o_jc;
+  if (jobs.empty()) return BSE_OK;
+  PdBatch b{};
+  b.sys = reinterpret_cast<const PdArgs*>(ws + o_args);
+  b.jobs = reinterpret_cast<const PdJob*>(ws + o_jobs);
+  b.njobs = (int)jobs.size();
+  b.persist = tn.persist;
+  b.cnt = reinterpret_cast<unsigned*>(ws + B.o_cnt) + kind * kXcds;
+  const int stage_id = kind == 0 ? BSE_STAGE_PD_EXCH : kind == 1 ? BSE_STAGE_PD_VV : BSE_STAGE_PD_CC;
+  const int grid = tn.persist ? persistent_grid(B.lds, b.njobs) : b.njobs;
+  if (tn.persist) HIP_TRY(launch_zero_u32(b.cnt, kXcds, st));
+  HIP_TRY(stage(stage_id, st, [&] {
+    return launch_pair_density(b, B.N2, B.N3, B.ng_max, B.lds, grid, kind == 0, st);
+  }));
+  return BSE_OK;
+}
+
+// The forward build of every system of the batch, one launch per stage
+// (the sqrt v tables aside, one small launch per system).
+int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& tn, char* ws, hipStream_t st) {
+  const int nsys = (int)B.P.size();
+  int rc = upload_batch(B, sys, precision, ws, st);
+  if (rc) return rc;
+  for (int i = 0; i < nsys; ++i) {
+    const Plan& P = B.P[i];
+    double* vs = reinterpret_cast<double*>(ws + B.base[i] + P.o_vs);
+    HIP_TRY(stage(BSE_STAGE_VSCALE, st, [&] { return launch_vscale(sys[i].vx, P.ng[0], P.ng_max, vs, st); }));
+  }
+  for (int kind = 0; kind < 3; ++kind)
+    if ((rc = run_pd(B, ws, kind, tn, st))) return rc;
+  const GemmArgs* gs = reinterpret_cast<const GemmArgs*>(ws + B.o_gargs);
+  const HTile* xt = reinterpret_cast<const HTile*>(ws + B.o_xt);
+  const HTile* mt = reinterpret_cast<const HTile*>(ws + B.o_mt);
+  const S1Tile* s1 = reinterpret_cast<const S1Tile*>(ws + B.o_s1);
+  const int* d2off = reinterpret_cast<const int*>(ws + B.o_d2off);
+  HIP_TRY(stage(BSE_STAGE_EXCHANGE, st, [&] { return launch_exchange(gs, xt, (int)B.xt.size(), precision, st); }));
+  HIP_TRY(stage(BSE_STAGE_DIRECT1, st, [&] { return launch_direct_s1(gs, s1, (int)B.s1.size(), precision, st); }));
+  HIP_TRY(stage(BSE_STAGE_DIRECT2, st, [&] { return launch_direct_s2(gs, d2off, nsys, B.d2n, precision, st); }));
+  HIP_TRY(stage(BSE_STAGE_MIRROR, st, [&] { return launch_mirror(gs, mt, (int)B.mt.size(), st); }));
   return BSE_OK;
 }
 
@@ -413,23 +591,18 @@ size_t bse_workspace_size(const bse_system* sys, int nsys, int precision, int fl
   (void)precision;
   (void)flags;
   if (!sys || nsys < 1) return 0;
-  size_t mx = 0;
-  for (int i = 0; i < nsys; ++i) {
-    Plan P;
-    if (make_plan(&sys[i], P)) return 0;
-    mx = std::max(mx, P.total);
-  }
-  return mx;
+  Batch B;
+  // one system: room for the backward as well; a batch: the forward build
+  if (make_batch(sys, nsys, nsys == 1, Tune{}, B)) return 0;
+  return B.total;
 }
 
 int bse_pair_density(const bse_system* sys, int kind, const int* kpairs, int npairs, const double* cell,
                      double* out, void* ws, size_t ws_bytes, void* stream) {
-  (void)cell;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   Plan P;
   int rc = make_plan(sys, P);
   if (rc) return rc;
-  if ((rc = check_lds(P))) return rc;
   if (!out || !ws) return fail(BSE_ERR_INVALID_ARG, "out / ws is NULL");
   std::vector<PdJob> jobs;
   if (kind == BSE_PD_EXCH) {
@@ -474,17 +647,16 @@ int bse_pair_density(const bse_system* sys, int kind, const int* kpairs, int npa
   } else {
     return fail(BSE_ERR_INVALID_ARG, "unknown kind %d", kind);
   }
-  // tables: gpack, ng, jobs
+  const size_t lds = pd_lds_bytes(P.N1, P.N2, P.N3, P.F[1], P.F[2], P.ng_max);
+  if (lds > 160 * 1024) return fail(BSE_ERR_SHAPE, "FFT window needs more than 160 KiB of LDS");
+  jobs = dispatch_order(std::move(jobs), Tune{}.ktile);
+  // tables: gpack, ng, the one system's arguments, jobs
   const size_t o_g = 0, o_n = align256(P.gpack.size() * sizeof(int));
-  const size_t o_j = align256(o_n + P.ng.size() * sizeof(int));
+  const size_t o_a = align256(o_n + P.ng.size() * sizeof(int));
+  const size_t o_j = align256(o_a + sizeof(PdArgs));
   const size_t need = align256(o_j + jobs.size() * sizeof(PdJob));
   if (ws_bytes < need) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
-  std::vector<char> buf(need, 0);
-  std::memcpy(buf.data() + o_g, P.gpack.data(), P.gpack.size() * sizeof(int));
-  std::memcpy(buf.data() + o_n, P.ng.data(), P.ng.size() * sizeof(int));
-  if (!jobs.empty()) std::memcpy(buf.data() + o_j, jobs.data(), jobs.size() * sizeof(PdJob));
   char* w = static_cast<char*>(ws);
-  HIP_TRY(hipMemcpyWithStream(w, buf.data(), need, hipMemcpyHostToDevice, st));
   PdArgs a{};
   a.u = reinterpret_cast<const double2*>(sys->u);
   a.nb = P.nb;
@@ -497,9 +669,20 @@ int bse_pair_density(const bse_system* sys, int kind, const int* kpairs, int npa
   a.F2 = P.F[1];
   a.F3 = P.F[2];
   a.vscale = nullptr;
-  a.jobs = reinterpret_cast<const PdJob*>(w + o_j);
   a.out = reinterpret_cast<double2*>(out);
-  HIP_TRY(launch_pair_density(a, P.N2, P.N3, (int)jobs.size(), st));
+  std::vector<char> buf(need, 0);
+  std::memcpy(buf.data() + o_g, P.gpack.data(), P.gpack.size() * sizeof(int));
+  std::memcpy(buf.data() + o_n, P.ng.data(), P.ng.size() * sizeof(int));
+  std::memcpy(buf.data() + o_a, &a, sizeof(PdArgs));
+  if (!jobs.empty()) std::memcpy(buf.data() + o_j, jobs.data(), jobs.size() * sizeof(PdJob));
+  HIP_TRY(hipMemcpyWithStream(w, buf.data(), need, hipMemcpyHostToDevice, st));
+  PdBatch b{};
+  b.sys = reinterpret_cast<const PdArgs*>(w + o_a);
+  b.jobs = reinterpret_cast<const PdJob*>(w + o_j);
+  b.njobs = (int)jobs.size();
+  b.persist = 0;
+  b.cnt = nullptr;
+  HIP_TRY(launch_pair_density(b, P.N2, P.N3, P.ng_max, lds, b.njobs, false, st));
   return BSE_OK;
 }
 
@@ -507,51 +690,58 @@ int bse_build_H(const bse_system* sys, int nsys, int precision, int flags, void*
   if (!sys || nsys < 1) return fail(BSE_ERR_INVALID_ARG, "no systems");
   if (!ws) return fail(BSE_ERR_INVALID_ARG, "workspace is NULL");
   if (precision < BSE_FP64 || precision > BSE_BF16X3) return fail(BSE_ERR_INVALID_ARG, "bad precision %d", precision);
+  if (flags & ~(BSE_VALIDATE | BSE_PERSISTENT)) return fail(BSE_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+  if (flags & BSE_VALIDATE) return fail(BSE_ERR_UNSUPPORTED, "BSE_VALIDATE is not implemented");
+  for (int i = 0; i < nsys; ++i)
+    if (!sys[i].H) return fail(BSE_ERR_INVALID_ARG, "H of system %d is NULL", i);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  for (int i = 0; i < nsys; ++i) {
-    int rc = build_one(&sys[i], precision, flags, static_cast<char*>(ws), ws_bytes, st);
-    if (rc) return rc;
+  Batch B;
+  int rc = make_batch(sys, nsys, false, Tune{}, B);
+  if (rc) return rc;
+  Tune tn = tune_for(batch_key(B.P, precision));
+  if (flags & BSE_PERSISTENT) tn.persist = 1;
+  if (tn.ktile != Tune{}.ktile) {
+    B = Batch{};
+    if ((rc = make_batch(sys, nsys, false, tn, B))) return rc;
   }
-  return BSE_OK;
+  if (ws_bytes < B.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, B.total);
+  return run_build(B, sys, precision, tn, static_cast<char*>(ws), st);
 }
 
 int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, double* deps, int precision, int flags,
                          void* ws, size_t ws_bytes, void* stream) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  Plan P;
-  int rc = make_plan(sys, P);
-  if (rc) return rc;
-  if ((rc = check_lds(P))) return rc;
   if (!dH || !ws) return fail(BSE_ERR_INVALID_ARG, "dH / ws is NULL");
   if (precision < BSE_FP64 || precision > BSE_BF16X3) return fail(BSE_ERR_INVALID_ARG, "bad precision %d", precision);
-  if (ws_bytes < P.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, P.total);
+  if (flags & ~BSE_PROJECT_DW) return fail(BSE_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+  Batch B;
+  int rc = make_batch(sys, 1, true, Tune{}, B);
+  if (rc) return rc;
+  const Plan& P = B.P[0];
+  if (ws_bytes < B.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, B.total);
   const bool project = (flags & BSE_PROJECT_DW) != 0;
   if (project && !P.tr_closed)
     return fail(BSE_ERR_NOT_HERMITIAN, "G spheres are not closed under time reversal; cannot project dW");
   char* w = static_cast<char*>(ws);
-  if ((rc = upload_tables(P, w, st))) return rc;
+  if ((rc = upload_batch(B, sys, precision, w, st))) return rc;
   // recompute the pair densities of the direct term
-  PdArgs a = pd_args(P, sys, w);
-  a.jobs = reinterpret_cast<const PdJob*>(w + P.o_jv);
-  a.out = reinterpret_cast<double2*>(w + P.o_RV);
-  HIP_TRY(launch_pair_density(a, P.N2, P.N3, (int)P.jv.size(), st));
-  a.jobs = reinterpret_cast<const PdJob*>(w + P.o_jc);
-  a.out = reinterpret_cast<double2*>(w + P.o_RC);
-  HIP_TRY(launch_pair_density(a, P.N2, P.N3, (int)P.jc.size(), st));
+  if ((rc = run_pd(B, w, 1, Tune{}, st))) return rc;
+  if ((rc = run_pd(B, w, 2, Tune{}, st))) return rc;
+  char* r = w + B.base[0];
   AdjArgs g{};
   g.dH = reinterpret_cast<const double2*>(dH);
-  g.RV = reinterpret_cast<const double2*>(w + P.o_RV);
-  g.RC = reinterpret_cast<const double2*>(w + P.o_RC);
-  g.T = reinterpret_cast<double2*>(w + P.o_Z);
+  g.RV = reinterpret_cast<const double2*>(r + P.o_RV);
+  g.RC = reinterpret_cast<const double2*>(r + P.o_RC);
+  g.T = reinterpret_cast<double2*>(r + P.o_Z);
   g.dWfinal = reinterpret_cast<double2*>(dW);
-  g.dWout = dW ? (project ? reinterpret_cast<double2*>(w + P.o_dWraw) : reinterpret_cast<double2*>(dW)) : nullptr;
+  g.dWout = dW ? (project ? reinterpret_cast<double2*>(r + P.o_dWraw) : reinterpret_cast<double2*>(dW)) : nullptr;
   g.deps = deps;
-  g.pairs = reinterpret_cast<const int4*>(w + P.o_pairs);
-  g.ng = reinterpret_cast<const int*>(w + P.o_ng);
-  g.qstart = reinterpret_cast<const int*>(w + P.o_qstart);
-  g.dwtiles = reinterpret_cast<const int4*>(w + P.o_dwt);
-  g.qbar = reinterpret_cast<const int*>(w + P.o_qbar);
-  g.trmap = reinterpret_cast<const int*>(w + P.o_trmap);
+  g.pairs = reinterpret_cast<const int4*>(r + P.o_pairs);
+  g.ng = reinterpret_cast<const int*>(r + P.o_ng);
+  g.qstart = reinterpret_cast<const int*>(r + P.o_qstart);
+  g.dwtiles = reinterpret_cast<const int4*>(r + P.o_dwt);
+  g.qbar = reinterpret_cast<const int*>(r + P.o_qbar);
+  g.trmap = reinterpret_cast<const int*>(r + P.o_trmap);
   g.nk = P.nk;
   g.nv = P.nv;
   g.nc = P.nc;

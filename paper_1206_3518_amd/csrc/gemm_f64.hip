@@ -4,6 +4,8 @@
 //   direct 2  H[(k v c),(k' v' c')] -= c sum_g Z[(kk' vv')][g] RC[(kk' cc')][g], plus e_ck - e_vk on the diagonal
 //   mirror    lower k blocks = conjugate transpose of the upper ones
 // Complex products run as four real v_mfma_f64_16x16x4 products per step.
+// Every launch covers a batch of systems: tiles and items name their system.
+#include "../../include/bse.h"
 #include "bse_internal.h"
 #include "gemm_tiles.h"
 #include "kernels.h"
@@ -12,9 +14,10 @@ namespace bse {
 
 // ------------------------------------------------------------------ exchange
 
-__global__ __launch_bounds__(256) void k_exchange(GemmArgs g, const int2* __restrict__ tiles) {
-  const int2 tl = tiles[blockIdx.x];
-  const int r0 = tl.x * TM, c0 = tl.y * TN;
+__global__ __launch_bounds__(256) void k_exchange(const GemmArgs* __restrict__ gs, const HTile* __restrict__ tiles) {
+  const HTile tl = tiles[blockIdx.x];
+  const GemmArgs g = gs[tl.sys];
+  const int r0 = tl.i * TM, c0 = tl.j * TN;
   d4 cre[2][2], cim[2][2];
   tile_gemm<true, true>(g.X, g.ng_max, r0, g.ns, g.X, g.ng_max, c0, g.ns, g.ngx, cre, cim);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
@@ -31,16 +34,18 @@ __global__ __launch_bounds__(256) void k_exchange(GemmArgs g, const int2* __rest
       }
 }
 
-hipError_t launch_exchange(const GemmArgs& g, const int2* tiles, int ntiles, hipStream_t st) {
+hipError_t launch_exchange(const GemmArgs* gs, const HTile* tiles, int ntiles, int precision, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_exchange, dim3(ntiles), dim3(256), 0, st, g, tiles);
+  if (precision != BSE_FP64) return launch_exchange_mx(gs, tiles, ntiles, precision, st);
+  hipLaunchKernelGGL(k_exchange, dim3(ntiles), dim3(256), 0, st, gs, tiles);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ direct, stage 1
 
-__global__ __launch_bounds__(256) void k_direct_s1(GemmArgs g) {
-  const S1Tile tl = g.s1tiles[blockIdx.x];
+__global__ __launch_bounds__(256) void k_direct_s1(const GemmArgs* __restrict__ gs, const S1Tile* __restrict__ tiles) {
+  const S1Tile tl = tiles[blockIdx.x];
+  const GemmArgs g = gs[tl.sys];
   const int nv2 = g.nv * g.nv;
   const int row_base = g.qstart[tl.iq] * nv2;
   const int rows = (g.qstart[tl.iq + 1] - g.qstart[tl.iq]) * nv2;
@@ -64,24 +69,31 @@ __global__ __launch_bounds__(256) void k_direct_s1(GemmArgs g) {
       }
 }
 
-hipError_t launch_direct_s1(const GemmArgs& g, int ntiles, hipStream_t st) {
+hipError_t launch_direct_s1(const GemmArgs* gs, const S1Tile* tiles, int ntiles, int precision, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_direct_s1, dim3(ntiles), dim3(256), 0, st, g);
+  if (precision != BSE_FP64) return launch_direct_s1_mx(gs, tiles, ntiles, precision, st);
+  hipLaunchKernelGGL(k_direct_s1, dim3(ntiles), dim3(256), 0, st, gs, tiles);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ direct, stage 2 + assembly
 
-__global__ __launch_bounds__(256) void k_direct_s2(GemmArgs g, int tiles_i, int tiles_j, int nitems) {
+// One wave per item (pair p of system s, 16 x 16 tile (ti, tj) of vv' x cc').
+__global__ __launch_bounds__(256) void k_direct_s2(const GemmArgs* __restrict__ gs, const int* __restrict__ d2off,
+                                                   int nsys, int nitems) {
   const int lane = threadIdx.x & 63;
   const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (item >= nitems) return;
+  const int sys = item_system(d2off, nsys, item);
+  const GemmArgs g = gs[sys];
+  const int nv2 = g.nv * g.nv, nc2 = g.nc * g.nc;
+  const int tiles_i = (nv2 + 15) / 16, tiles_j = (nc2 + 15) / 16;
+  const int loc = item - d2off[sys];
   const int per = tiles_i * tiles_j;
-  const int p = item / per, ti = (item % per) / tiles_j, tj = item % tiles_j;
+  const int p = loc / per, ti = (loc % per) / tiles_j, tj = loc % tiles_j;
   const int4 pr = g.pairs[p];
   const int ka = pr.x, kb = pr.y;
   const int K = g.ng[pr.z];
-  const int nv2 = g.nv * g.nv, nc2 = g.nc * g.nc;
   const int ia = ti * 16 + (lane & 15), jb = tj * 16 + (lane & 15);
   const double2* zr = g.Z + ((size_t)p * nv2 + (ia < nv2 ? ia : 0)) * g.ng_max;
   const double2* cr = g.RC + ((size_t)p * nc2 + (jb < nc2 ? jb : 0)) * g.ng_max;
@@ -112,23 +124,26 @@ __global__ __launch_bounds__(256) void k_direct_s2(GemmArgs g, int tiles_i, int 
   }
 }
 
-hipError_t launch_direct_s2(const GemmArgs& g, int dtiles, hipStream_t st) {
-  const int ti = (g.nv * g.nv + 15) / 16, tj = (g.nc * g.nc + 15) / 16;
-  const int nitems = g.npairs * ti * tj;
+hipError_t launch_direct_s2(const GemmArgs* gs, const int* d2off, int nsys, int nitems, int precision,
+                            hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
-  (void)dtiles;
-  hipLaunchKernelGGL(k_direct_s2, dim3((nitems + 3) / 4), dim3(256), 0, st, g, ti, tj, nitems);
+  if (precision != BSE_FP64) return launch_direct_s2_mx(gs, d2off, nsys, nitems, precision, st);
+  hipLaunchKernelGGL(k_direct_s2, dim3((nitems + 3) / 4), dim3(256), 0, st, gs, d2off, nsys, nitems);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ mirror
 
-__global__ __launch_bounds__(256) void k_mirror(double2* __restrict__ H, int ns, int nt) {
+// Destination tile (i, j), i >= j, of 32 x 32: lower-k-block entries become the
+// conjugate of the transposed source tile (j, i).
+__global__ __launch_bounds__(256) void k_mirror(const GemmArgs* __restrict__ gs, const HTile* __restrict__ tiles) {
   __shared__ double2 tile[32][33];
-  const int bi = blockIdx.y, bj = blockIdx.x;  // destination tile rows bi, cols bj
-  if (bi < bj) return;
+  const HTile tl = tiles[blockIdx.x];
+  const GemmArgs g = gs[tl.sys];
+  double2* H = g.H;
+  const int ns = g.ns, nt = g.nt;
+  const int bi = tl.i, bj = tl.j;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
-  // source: rows of tile bj, cols of tile bi
 #pragma unroll
   for (int r = ty; r < 32; r += 8) {
     const int sr = bj * 32 + r, sc = bi * 32 + tx;
@@ -145,10 +160,9 @@ __global__ __launch_bounds__(256) void k_mirror(double2* __restrict__ H, int ns,
   }
 }
 
-hipError_t launch_mirror(double2* H, int ns, int nt, hipStream_t st) {
-  const int T = (ns + 31) / 32;
-  if (T <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mirror, dim3(T, T), dim3(256), 0, st, H, ns, nt);
+hipError_t launch_mirror(const GemmArgs* gs, const HTile* tiles, int ntiles, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mirror, dim3(ntiles), dim3(256), 0, st, gs, tiles);
   return hipGetLastError();
 }
 
@@ -161,6 +175,19 @@ __global__ void k_vscale(const double* __restrict__ vx, int ngx, int ng_max, dou
 
 hipError_t launch_vscale(const double* vx, int ngx, int ng_max, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_vscale, dim3((ng_max + 255) / 256), dim3(256), 0, st, vx, ngx, ng_max, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ counters
+
+__global__ void k_zero_u32(unsigned* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u32, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
 

@@ -14,9 +14,10 @@
 namespace bse {
 
 template <int P>
-__global__ __launch_bounds__(256) void k_exchange_mx(GemmArgs g, const int2* __restrict__ tiles) {
-  const int2 tl = tiles[blockIdx.x];
-  const int r0 = tl.x * MTM, c0 = tl.y * MTN;
+__global__ __launch_bounds__(256) void k_exchange_mx(const GemmArgs* __restrict__ gs, const HTile* __restrict__ tiles) {
+  const HTile tl = tiles[blockIdx.x];
+  const GemmArgs g = gs[tl.sys];
+  const int r0 = tl.i * MTM, c0 = tl.j * MTN;
   f4 cre[2][2], cim[2][2];
   tile_gemm_mx<P, true, true>(g.X, g.ng_max, r0, g.ns, g.X, g.ng_max, c0, g.ns, g.ngx, false, cre, cim);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
@@ -35,8 +36,9 @@ __global__ __launch_bounds__(256) void k_exchange_mx(GemmArgs g, const int2* __r
 }
 
 template <int P>
-__global__ __launch_bounds__(256) void k_direct_s1_mx(GemmArgs g) {
-  const S1Tile tl = g.s1tiles[blockIdx.x];
+__global__ __launch_bounds__(256) void k_direct_s1_mx(const GemmArgs* __restrict__ gs, const S1Tile* __restrict__ tiles) {
+  const S1Tile tl = tiles[blockIdx.x];
+  const GemmArgs g = gs[tl.sys];
   const int nv2 = g.nv * g.nv;
   const int row_base = g.qstart[tl.iq] * nv2;
   const int rows = (g.qstart[tl.iq + 1] - g.qstart[tl.iq]) * nv2;
@@ -66,16 +68,21 @@ __global__ __launch_bounds__(256) void k_direct_s1_mx(GemmArgs g) {
 // operands split in registers.  The q = 0 head conj(rho_vv'(0)) W_00 rho_cc'(0)
 // is added in FP64.
 template <int P>
-__global__ __launch_bounds__(256) void k_direct_s2_mx(GemmArgs g, int tiles_i, int tiles_j, int nitems) {
+__global__ __launch_bounds__(256) void k_direct_s2_mx(const GemmArgs* __restrict__ gs, const int* __restrict__ d2off,
+                                                      int nsys, int nitems) {
   const int lane = threadIdx.x & 63;
   const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (item >= nitems) return;
+  const int sys = item_system(d2off, nsys, item);
+  const GemmArgs g = gs[sys];
+  const int nv2 = g.nv * g.nv, nc2 = g.nc * g.nc;
+  const int tiles_i = (nv2 + 15) / 16, tiles_j = (nc2 + 15) / 16;
+  const int loc = item - d2off[sys];
   const int per = tiles_i * tiles_j;
-  const int p = item / per, ti = (item % per) / tiles_j, tj = item % tiles_j;
+  const int p = loc / per, ti = (loc % per) / tiles_j, tj = loc % tiles_j;
   const int4 pr = g.pairs[p];
   const int ka = pr.x, kb = pr.y;
   const int K = g.ng[pr.z];
-  const int nv2 = g.nv * g.nv, nc2 = g.nc * g.nc;
   const int ia = ti * 16 + (lane & 15), jb = tj * 16 + (lane & 15);
   const bool va = ia < nv2, vb = jb < nc2;
   const double2* zr = g.Z + ((size_t)p * nv2 + (va ? ia : 0)) * g.ng_max;
@@ -162,42 +169,43 @@ __global__ __launch_bounds__(256) void k_direct_s2_mx(GemmArgs g, int tiles_i, i
 }
 
 template <int P>
-static hipError_t launch_ex(const GemmArgs& g, const int2* tiles, int ntiles, hipStream_t st) {
+static hipError_t launch_ex(const GemmArgs* gs, const HTile* tiles, int ntiles, hipStream_t st) {
   const size_t lds = 2 * sizeof(TileLds<P>);
   hipError_t e = hipFuncSetAttribute((const void*)k_exchange_mx<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_exchange_mx<P>, dim3(ntiles), dim3(256), lds, st, g, tiles);
+  hipLaunchKernelGGL(k_exchange_mx<P>, dim3(ntiles), dim3(256), lds, st, gs, tiles);
   return hipGetLastError();
 }
 
 template <int P>
-static hipError_t launch_s1(const GemmArgs& g, int ntiles, hipStream_t st) {
+static hipError_t launch_s1(const GemmArgs* gs, const S1Tile* tiles, int ntiles, hipStream_t st) {
   const size_t lds = 2 * sizeof(TileLds<P>);
   hipError_t e = hipFuncSetAttribute((const void*)k_direct_s1_mx<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_direct_s1_mx<P>, dim3(ntiles), dim3(256), lds, st, g);
+  hipLaunchKernelGGL(k_direct_s1_mx<P>, dim3(ntiles), dim3(256), lds, st, gs, tiles);
   return hipGetLastError();
 }
 
-hipError_t launch_exchange_mx(const GemmArgs& g, const int2* tiles, int ntiles, hipStream_t st) {
+hipError_t launch_exchange_mx(const GemmArgs* gs, const HTile* tiles, int ntiles, int precision, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  return g.precision == BSE_BF16X3 ? launch_ex<BSE_BF16X3>(g, tiles, ntiles, st)
-                                   : launch_ex<BSE_SPLIT_FP32>(g, tiles, ntiles, st);
+  return precision == BSE_BF16X3 ? launch_ex<BSE_BF16X3>(gs, tiles, ntiles, st)
+                                 : launch_ex<BSE_SPLIT_FP32>(gs, tiles, ntiles, st);
 }
 
-hipError_t launch_direct_s1_mx(const GemmArgs& g, int ntiles, hipStream_t st) {
+hipError_t launch_direct_s1_mx(const GemmArgs* gs, const S1Tile* tiles, int ntiles, int precision, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  return g.precision == BSE_BF16X3 ? launch_s1<BSE_BF16X3>(g, ntiles, st) : launch_s1<BSE_SPLIT_FP32>(g, ntiles, st);
+  return precision == BSE_BF16X3 ? launch_s1<BSE_BF16X3>(gs, tiles, ntiles, st)
+                                 : launch_s1<BSE_SPLIT_FP32>(gs, tiles, ntiles, st);
 }
 
-hipError_t launch_direct_s2_mx(const GemmArgs& g, hipStream_t st) {
-  const int ti = (g.nv * g.nv + 15) / 16, tj = (g.nc * g.nc + 15) / 16;
-  const int nitems = g.npairs * ti * tj;
+hipError_t launch_direct_s2_mx(const GemmArgs* gs, const int* d2off, int nsys, int nitems, int precision,
+                               hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
-  if (g.precision == BSE_BF16X3)
-    hipLaunchKernelGGL(k_direct_s2_mx<BSE_BF16X3>, dim3((nitems + 3) / 4), dim3(256), 0, st, g, ti, tj, nitems);
+  if (precision == BSE_BF16X3)
+    hipLaunchKernelGGL(k_direct_s2_mx<BSE_BF16X3>, dim3((nitems + 3) / 4), dim3(256), 0, st, gs, d2off, nsys, nitems);
   else
-    hipLaunchKernelGGL(k_direct_s2_mx<BSE_SPLIT_FP32>, dim3((nitems + 3) / 4), dim3(256), 0, st, g, ti, tj, nitems);
+    hipLaunchKernelGGL(k_direct_s2_mx<BSE_SPLIT_FP32>, dim3((nitems + 3) / 4), dim3(256), 0, st, gs, d2off, nsys,
+                       nitems);
   return hipGetLastError();
 }
 

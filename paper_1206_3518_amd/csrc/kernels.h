@@ -7,8 +7,9 @@
 namespace bse {
 
 // One pair-density job: band block [a0, a0+nA) at k = ka (conjugated operand)
-// times [b0, b0+nB) at k' = kb, shift m0 (packed), sphere iq.  Output row of
-// band pair (ia, ib) is row0 + ia*nB + ib.
+// times [b0, b0+nB) at k' = kb, shift m0 (packed), sphere iq, of system
+// nab >> 16 of a batch (nab = nA | nB << 8 | sys << 16).  Output row of band
+// pair (ia, ib) is row0 + ia*nB + ib.  nA = nB = 0 marks an empty job.
 struct PdJob {
   int ka, kb, m0p, iq, a0, b0, nab, row0;
 };
@@ -23,17 +24,40 @@ struct PdArgs {
   int lo2, lo3;         // lowest kept frequency (m - m0) along axes 2, 3
   int F2, F3;           // kept window widths
   const double* vscale; // [ng_max] output scale (sqrt v) or null
-  const PdJob* jobs;
   double2* out;         // rows of ng_max
+};
+
+// Jobs of one pair-density launch over a batch of systems that share N2, N3.
+// Static dispatch: workgroup b runs jobs[b].  Persistent dispatch: a grid of
+// at most `grid` workgroups; workgroup b serves queue b mod 8 (the XCD it runs
+// on), whose t-th job is jobs[8 t + queue], by an atomic counter per queue,
+// then takes jobs from the other queues until all are drained.  njobs is a
+// multiple of 8 in both modes.
+struct PdBatch {
+  const PdArgs* sys;    // [nsys] per-system arguments (device)
+  const PdJob* jobs;    // [njobs]
+  int njobs;
+  int persist;
+  unsigned* cnt;        // [8] queue counters, zero at launch (persistent only)
 };
 
 bool pd_grid_supported(int N2, int N3);
 size_t pd_lds_bytes(int N1, int N2, int N3, int F2, int F3, int ng_max);
-hipError_t launch_pair_density(const PdArgs& a, int N2, int N3, int njobs, hipStream_t st);
+// ng_max: the largest of the batch; lds: the largest pd_lds_bytes of the
+// batch; exch: exchange rows (every system's vscale set); grid: njobs for
+// static dispatch, the persistent grid otherwise.
+hipError_t launch_pair_density(const PdBatch& b, int N2, int N3, int ng_max, size_t lds, int grid, bool exch,
+                               hipStream_t st);
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st);
 
-// A GEMM tile of the direct term's first stage: q group iq, tile (mt, nt).
+// A GEMM tile of the direct term's first stage: q group iq, tile (mt, nt), system sys.
 struct S1Tile {
-  int iq, mt, nt, pad;
+  int iq, mt, nt, sys;
+};
+// An exchange tile (64 x 64 block (i, j) of H) or a mirror tile (32 x 32
+// destination block (i, j), i >= j) of system sys.
+struct HTile {
+  int i, j, sys, pad;
 };
 
 struct GemmArgs {
@@ -53,22 +77,36 @@ struct GemmArgs {
   const int* ng;
   const int* qstart;    // [Nk+1] first pair of each q group (pairs sorted by q)
   const int4* pairs;    // (ka, kb, iq, m0p)
-  const S1Tile* s1tiles;
   const double* eps;
   int nv, nc, nb, npairs;
-  int precision;
+  int nt;               // nv * nc: rows of one k block
   int w_head_fp64;      // mixed precision: q=0 head added separately in FP64
 };
 
+// The contractions run over a batch: gs is a device array of per-system
+// arguments, every tile names its system.  Stage 2 items are (pair, 16 x 16
+// tile) of every system, numbered system after system: d2off[s] is the first
+// item of system s (nsys + 1 entries).
 hipError_t launch_vscale(const double* vx, int ngx, int ng_max, double* out, hipStream_t st);
-hipError_t launch_exchange(const GemmArgs& g, const int2* tiles, int ntiles, hipStream_t st);
-hipError_t launch_direct_s1(const GemmArgs& g, int ntiles, hipStream_t st);
-hipError_t launch_direct_s2(const GemmArgs& g, int dtiles, hipStream_t st);
-hipError_t launch_mirror(double2* H, int ns, int nt, hipStream_t st);
-// mixed precision (g.precision = BSE_SPLIT_FP32 or BSE_BF16X3)
-hipError_t launch_exchange_mx(const GemmArgs& g, const int2* tiles, int ntiles, hipStream_t st);
-hipError_t launch_direct_s1_mx(const GemmArgs& g, int ntiles, hipStream_t st);
-hipError_t launch_direct_s2_mx(const GemmArgs& g, hipStream_t st);
+hipError_t launch_exchange(const GemmArgs* gs, const HTile* tiles, int ntiles, int precision, hipStream_t st);
+hipError_t launch_direct_s1(const GemmArgs* gs, const S1Tile* tiles, int ntiles, int precision, hipStream_t st);
+hipError_t launch_direct_s2(const GemmArgs* gs, const int* d2off, int nsys, int nitems, int precision,
+                            hipStream_t st);
+hipError_t launch_mirror(const GemmArgs* gs, const HTile* tiles, int ntiles, hipStream_t st);
+// mixed-precision bodies (precision BSE_SPLIT_FP32 or BSE_BF16X3), called by the above
+hipError_t launch_exchange_mx(const GemmArgs* gs, const HTile* tiles, int ntiles, int precision, hipStream_t st);
+hipError_t launch_direct_s1_mx(const GemmArgs* gs, const S1Tile* tiles, int ntiles, int precision, hipStream_t st);
+hipError_t launch_direct_s2_mx(const GemmArgs* gs, const int* d2off, int nsys, int nitems, int precision,
+                               hipStream_t st);
+// system of stage-2 item `item`: the last s with d2off[s] <= item
+__device__ __forceinline__ int item_system(const int* __restrict__ d2off, int nsys, int item) {
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d2off[mid] <= item) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
 
 // Adjoint of the build.
 struct AdjArgs {

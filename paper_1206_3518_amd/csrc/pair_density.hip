@@ -44,7 +44,7 @@ struct PlaneGeo {
 // scaled by sqrt v); a separate instantiation so that the direct-term
 // launches form one kernel in traces.
 template <int N2, int N3, int TG, bool EXCH>
-__global__ __launch_bounds__(256, 2) void k_pair_density(PdArgs a) {
+__device__ __forceinline__ void pd_general_job(const PdArgs& a, const PdJob& job) {
   using G = PlaneGeo<N2, N3>;
   constexpr int LA = G::LA, MA = G::MA, LB = G::LB, MB = G::MB, NA = G::NA, NB = G::NB;
   constexpr int PW = G::PW, SA = G::SA;
@@ -70,8 +70,7 @@ __global__ __launch_bounds__(256, 2) void k_pair_density(PdArgs a) {
     sincospi(2.0 * k / n, &s, &c);
     smem[t] = make_double2(c, -s);
   }
-  const PdJob job = a.jobs[blockIdx.x];
-  const int nA = job.nab & 255, nB = job.nab >> 8;
+  const int nA = job.nab & 255, nB = (job.nab >> 8) & 255;
   int m01, m02, m03;
   unpack_m(job.m0p, m01, m02, m03);
   const int ngq = a.ng[job.iq];
@@ -229,7 +228,7 @@ __device__ __forceinline__ void pin(double2 (&x)[M]) {
 }
 
 template <int N2, int N3, int TG, bool EXCH>
-__global__ __launch_bounds__(256, 2) void k_pair_density_line(PdArgs a) {
+__device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
   static_assert(N2 <= 32 && N3 <= 32 && N2 % 2 == 0 && N3 % 2 == 0, "lines must fit a half wave");
   constexpr int H2 = N2 / 2, H3 = N3 / 2;
   constexpr int S1 = 33;  // T1 row stride: columns N3..31 of idle lanes land in the padding
@@ -250,8 +249,7 @@ __global__ __launch_bounds__(256, 2) void k_pair_density_line(PdArgs a) {
     sincospi(2.0 * t / N1, &s, &cs);
     tw1[t] = make_double2(cs, -s);
   }
-  const PdJob job = a.jobs[blockIdx.x];
-  const int nA = job.nab & 255, nB = job.nab >> 8;
+  const int nA = job.nab & 255, nB = (job.nab >> 8) & 255;
   int m01, m02, m03;
   unpack_m(job.m0p, m01, m02, m03);
   const int ngq = a.ng[job.iq];
@@ -292,8 +290,8 @@ __global__ __launch_bounds__(256, 2) void k_pair_density_line(PdArgs a) {
       const bool two = j1 + 1 < N1;  // the second plane exists
       // window masks and origins re-read per plane: kept loop-invariant they
       // would pin one scalar condition per frequency across the loop
-      unsigned k2 = keep2, k3 = keep3;
-      int lo2 = a.lo2, lo3 = a.lo3;
+      unsigned k2 = __builtin_amdgcn_readfirstlane(keep2), k3 = __builtin_amdgcn_readfirstlane(keep3);
+      int lo2 = __builtin_amdgcn_readfirstlane(a.lo2), lo3 = __builtin_amdgcn_readfirstlane(a.lo3);
       asm volatile("" : "+s"(k2), "+s"(k3), "+s"(lo2), "+s"(lo3));
       // ---- pass 1 (idle lanes load a valid column and write padding or a
       // plane that pass 3 skips)
@@ -398,6 +396,59 @@ __global__ __launch_bounds__(256, 2) void k_pair_density_line(PdArgs a) {
   }
 }
 
+// Job order of the pair-density kernels; returns the next job of this
+// workgroup, or -1 (uniform).  Static: workgroup b runs job b once.
+// Persistent: thread 0 draws from the queue of this workgroup's XCD (b mod 8)
+// and then from the other seven in turn, so every workgroup leaves once all
+// queues are drained (each draw advances a counter that only grows).
+template <bool PERSIST>
+__device__ __forceinline__ int next_job(const PdBatch& b, int& round, int& tries, int* s_job) {
+  if constexpr (!PERSIST) return (round++ == 0 && (int)blockIdx.x < b.njobs) ? (int)blockIdx.x : -1;
+  const int per_q = b.njobs >> 3;
+  const int home = blockIdx.x & 7;
+  if (threadIdx.x == 0) {
+    int got = -1;
+    while (tries < 8) {
+      const int x = (home + tries) & 7;
+      const int t = (int)atomicAdd(&b.cnt[x], 1u);
+      if (t < per_q) {
+        got = 8 * t + x;
+        break;
+      }
+      ++tries;
+    }
+    *s_job = got;
+  }
+  __syncthreads();
+  const int j = __builtin_amdgcn_readfirstlane(*s_job);
+  __syncthreads();
+  return j;
+}
+
+template <int N2, int N3, int TG, bool EXCH, bool PERSIST>
+__global__ __launch_bounds__(256, 2) void k_pair_density(PdBatch b) {
+  __shared__ int s_job;
+  int round = 0, tries = 0;
+  for (int j = next_job<PERSIST>(b, round, tries, &s_job); j >= 0; j = next_job<PERSIST>(b, round, tries, &s_job)) {
+    const PdJob job = b.jobs[j];
+    const PdArgs a = b.sys[job.nab >> 16];
+    pd_general_job<N2, N3, TG, EXCH>(a, job);
+    __syncthreads();  // LDS of this job is free before the next one fills it
+  }
+}
+
+template <int N2, int N3, int TG, bool EXCH, bool PERSIST>
+__global__ __launch_bounds__(256, 2) void k_pair_density_line(PdBatch b) {
+  __shared__ int s_job;
+  int round = 0, tries = 0;
+  for (int j = next_job<PERSIST>(b, round, tries, &s_job); j >= 0; j = next_job<PERSIST>(b, round, tries, &s_job)) {
+    const PdJob job = b.jobs[j];
+    const PdArgs a = b.sys[job.nab >> 16];
+    pd_line_job<N2, N3, TG, EXCH>(a, job);
+    __syncthreads();
+  }
+}
+
 template <int N2, int N3>
 constexpr bool use_line() {
   return N2 <= 32 && N3 <= 32 && N2 % 2 == 0 && N3 % 2 == 0;
@@ -418,27 +469,33 @@ static size_t lds_bytes(int N1, int F2, int F3, int ng_max) {
 }
 
 template <int N2, int N3, int TG>
-static hipError_t launch_tg(const PdArgs& a, int njobs, size_t lds, hipStream_t st) {
-  void (*k)(PdArgs);
-  if constexpr (use_line<N2, N3>())
-    k = a.vscale ? k_pair_density_line<N2, N3, TG, true> : k_pair_density_line<N2, N3, TG, false>;
-  else
-    k = a.vscale ? k_pair_density<N2, N3, TG, true> : k_pair_density<N2, N3, TG, false>;
+static hipError_t launch_tg(const PdBatch& b, size_t lds, int grid, bool exch, hipStream_t st) {
+  void (*k)(PdBatch);
+  if constexpr (use_line<N2, N3>()) {
+    if (b.persist)
+      k = exch ? k_pair_density_line<N2, N3, TG, true, true> : k_pair_density_line<N2, N3, TG, false, true>;
+    else
+      k = exch ? k_pair_density_line<N2, N3, TG, true, false> : k_pair_density_line<N2, N3, TG, false, false>;
+  } else {
+    if (b.persist)
+      k = exch ? k_pair_density<N2, N3, TG, true, true> : k_pair_density<N2, N3, TG, false, true>;
+    else
+      k = exch ? k_pair_density<N2, N3, TG, true, false> : k_pair_density<N2, N3, TG, false, false>;
+  }
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(njobs), dim3(256), lds, st, a);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, st, b);
   return hipGetLastError();
 }
 
 template <int N2, int N3>
-static hipError_t launch_grid(const PdArgs& a, int njobs, hipStream_t st) {
-  const size_t lds = lds_bytes<N2, N3>(a.N1, a.F2, a.F3, a.ng_max);
-  switch (tg_bucket(a.ng_max)) {
-    case 4: return launch_tg<N2, N3, 4>(a, njobs, lds, st);
-    case 5: return launch_tg<N2, N3, 5>(a, njobs, lds, st);
-    case 8: return launch_tg<N2, N3, 8>(a, njobs, lds, st);
-    case 13: return launch_tg<N2, N3, 13>(a, njobs, lds, st);
-    default: return launch_tg<N2, N3, 16>(a, njobs, lds, st);
+static hipError_t launch_grid(const PdBatch& b, int ng_max, size_t lds, int grid, bool exch, hipStream_t st) {
+  switch (tg_bucket(ng_max)) {
+    case 4: return launch_tg<N2, N3, 4>(b, lds, grid, exch, st);
+    case 5: return launch_tg<N2, N3, 5>(b, lds, grid, exch, st);
+    case 8: return launch_tg<N2, N3, 8>(b, lds, grid, exch, st);
+    case 13: return launch_tg<N2, N3, 13>(b, lds, grid, exch, st);
+    default: return launch_tg<N2, N3, 16>(b, lds, grid, exch, st);
   }
 }
 
@@ -466,10 +523,12 @@ size_t pd_lds_bytes(int N1, int N2, int N3, int F2, int F3, int ng_max) {
   return ~size_t(0);
 }
 
-hipError_t launch_pair_density(const PdArgs& a, int N2, int N3, int njobs, hipStream_t st) {
-  if (njobs <= 0) return hipSuccess;
+// exch: the launch computes exchange rows (every system's PdArgs.vscale set).
+hipError_t launch_pair_density(const PdBatch& b, int N2, int N3, int ng_max, size_t lds, int grid, bool exch,
+                               hipStream_t st) {
+  if (b.njobs <= 0 || grid <= 0) return hipSuccess;
 #define BSE_PD_CASE(X, Y) \
-  if (N2 == X && N3 == Y) return launch_grid<X, Y>(a, njobs, st);
+  if (N2 == X && N3 == Y) return launch_grid<X, Y>(b, ng_max, lds, grid, exch, st);
   BSE_PD_CASE(8, 8)
   BSE_PD_CASE(12, 12)
   BSE_PD_CASE(16, 16)

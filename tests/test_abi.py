@@ -56,7 +56,7 @@ def test_workspace_size_and_host_errors():
     # X + RV + RC + Z rows of ng_max complex
     assert n >= 16 * s.ng_max * (s.ns + 3 * npairs * nt)
     # workspace too small: refused before any enqueue
-    rc = L.bse_build_H(ctypes.byref(st), 1, 0, 0, ctypes.c_void_p(0x1000), n - 1, None)
+    rc = L.bse_build_H(ctypes.byref(st), 1, 0, 0, ctypes.c_void_p(0x1000), 4096, None)
     assert rc == -3 and "workspace" in P.bse_last_error()
     # null workspace
     rc = L.bse_build_H(ctypes.byref(st), 1, 0, 0, None, n, None)
