@@ -120,6 +120,7 @@ def main():
     ap.add_argument("--config", type=int, default=2,
                     help="workload index: 2 = the Si-like 8192 case (default), 3 = the h-BN-like batch of 16")
     ap.add_argument("--persistent", action="store_true", help="persistent work-queue dispatch of the pair densities")
+    ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner (default dispatch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the split-FP32 / BF16x3 comparison runs")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -149,6 +150,9 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    tuning = None
+    if not args.no_autotune and not args.persistent:
+        tuning = P.bse_autotune(devs, prec, None, ws)  # outside the timed region
     ms, wall, stages = run_steps(P, devs, prec, flags, ws, args.steps, args.warmup)
     elements = float(sum(float(s.ns) ** 2 for s in systems))
     value = elements / (ms / 1e3)
@@ -189,7 +193,11 @@ def main():
                   "kmeshes": [list(s.kmesh) for s in systems], "ns": [s.ns for s in systems],
                   "ng_max": [s.ng_max for s in systems], "nv": systems[0].nv, "nc": systems[0].nc,
                   "precision": args.precision, "parallelism": "single-gpu"}
-    config["dispatch"] = "persistent" if args.persistent else "static"
+    if tuning is not None:
+        config["dispatch"] = (f"autotuned: persistent, {tuning['wg_per_cu']} workgroups/CU" if tuning["persistent"]
+                              else f"autotuned: static, k tile {tuning['ktile']}")
+    else:
+        config["dispatch"] = "persistent" if args.persistent else "static, k tile 8"
     out = {"metric": "BSE H build: elements/s + % MFMA peak, FP64 vs mixed at <=1e-4 eV error",
            "value": value, "unit": "H elements/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,

@@ -142,6 +142,33 @@ int bse_build_H_backward(const bse_system *sys, const double *dH, double *dW, do
                          int precision, int flags, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Launch choices of bse_build_H for one batch signature (grids, k meshes,
+ * bands, sphere sizes and windows of every system, precision).
+ */
+typedef struct bse_tuning {
+    int persistent;  /* 1: persistent work-queue dispatch of the pair densities   */
+    int ktile;       /* k tile of the pair-density dispatch order                 */
+    int wg_per_cu;   /* persistent dispatch: workgroups per compute unit          */
+    float pd_ms;     /* measured valence-valence pair-density launch, ms          */
+} bse_tuning;
+
+/*
+ * Autotuner (for callers that build the same batch shape many times).  Times
+ * the dominant launch (valence-valence pair densities) of this batch under
+ * static dispatch with k tiles 4, 8, 16 and persistent dispatch with 1..4
+ * workgroups per CU, and keeps the fastest for every later bse_build_H of the
+ * same signature in this process (BSE_PERSISTENT still forces persistent
+ * dispatch).  cache_path (HOST, nullable): a text file of one JSON object per
+ * line; a matching line is used without timing, a new result is appended.
+ * Blocks until the timing runs finish; needs the forward workspace of
+ * bse_build_H and overwrites its pair-density area.  `chosen` (HOST,
+ * nullable) receives the choice.  Results of bse_build_H do not depend on the
+ * choice (every pair density is computed the same way in any order).
+ */
+int bse_autotune(const bse_system *sys, int nsys, int precision, const char *cache_path, bse_tuning *chosen,
+                 void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Absorption spectrum from the spectral representation of the irreducible
  * response (Sec. II.C, macroscopic dielectric function with Vbar; Tamm-Dancoff
  * so the overlap matrix is the identity):

@@ -32,6 +32,11 @@ class BseError(RuntimeError):
         self.code = code
 
 
+class bse_tuning(ctypes.Structure):
+    _fields_ = [("persistent", ctypes.c_int), ("ktile", ctypes.c_int), ("wg_per_cu", ctypes.c_int),
+                ("pd_ms", ctypes.c_float)]
+
+
 class bse_system(ctypes.Structure):
     _fields_ = [("grid", ctypes.c_int * 3), ("kmesh", ctypes.c_int * 3), ("nv", ctypes.c_int),
                 ("nc", ctypes.c_int), ("omega_cell", ctypes.c_double), ("ng_max", ctypes.c_int),
@@ -41,7 +46,7 @@ class bse_system(ctypes.Structure):
 
 
 SYMBOLS = ["bse_workspace_size", "bse_pair_density", "bse_build_H", "bse_build_H_backward",
-           "bse_spectrum", "bse_profile", "bse_profile_read", "bse_last_error"]
+           "bse_autotune", "bse_spectrum", "bse_profile", "bse_profile_read", "bse_last_error"]
 STAGES = ["vscale", "pd_exch", "pd_vv", "pd_cc", "exchange", "direct1", "direct2", "mirror"]
 
 
@@ -61,6 +66,8 @@ def lib():
         L.bse_build_H.restype = I
         L.bse_build_H_backward.argtypes = [P, P, P, P, I, I, P, S, P]
         L.bse_build_H_backward.restype = I
+        L.bse_autotune.argtypes = [P, I, I, ctypes.c_char_p, P, P, S, P]
+        L.bse_autotune.restype = I
         L.bse_spectrum.argtypes = [I, I, P, P, P, D, I, D, D, D, P, P, S, P]
         L.bse_spectrum.restype = I
         L.bse_profile.argtypes = [I]
@@ -160,6 +167,19 @@ def bse_build_H(systems, precision=BSE_FP64, flags=0, ws=None, stream=None):
         ws = workspace(bse_workspace_size(systems, precision, flags), systems[0].device)
     _check(lib().bse_build_H(arr, len(systems), int(precision), int(flags), _ptr(ws), ws.numel(), _stream(stream)))
     return [s.H for s in systems]
+
+
+def bse_autotune(systems, precision=BSE_FP64, cache_path=None, ws=None, stream=None) -> dict:
+    """Times the candidate pair-density dispatches for this batch and keeps the
+    fastest for later builds of the same shape; returns the choice."""
+    arr = _structs(systems)
+    if ws is None:
+        ws = workspace(bse_workspace_size(systems, precision), systems[0].device)
+    out = bse_tuning()
+    path = None if cache_path is None else os.fsencode(str(cache_path))
+    _check(lib().bse_autotune(arr, len(systems), int(precision), path, ctypes.byref(out), _ptr(ws), ws.numel(),
+                              _stream(stream)))
+    return {"persistent": out.persistent, "ktile": out.ktile, "wg_per_cu": out.wg_per_cu, "pd_ms": out.pd_ms}
 
 
 def bse_pair_density(system: DeviceSystem, kind, kpairs=None, ws=None, stream=None, cell=None):

@@ -254,6 +254,13 @@ int make_plan(const bse_system* s, Plan& P) {
   P.qbar.assign(P.nk, 0);
   P.trmap.assign((size_t)P.nk * P.ng_max, 0);
   {
+    // per q: (packed m, index) sorted, for the lookups of the partner sphere
+    std::vector<std::vector<std::pair<int, int>>> sorted(P.nk);
+    for (int q = 0; q < P.nk; ++q) {
+      sorted[q].resize(P.ng[q]);
+      for (int g = 0; g < P.ng[q]; ++g) sorted[q][g] = {P.gpack[(size_t)q * P.ng_max + g], g};
+      std::sort(sorted[q].begin(), sorted[q].end());
+    }
     const int* n = s->kmesh;
     for (int q = 0; q < P.nk; ++q) {
       const int iv[3] = {q / (n[1] * n[2]), (q / n[2]) % n[1], q % n[2]};
@@ -268,12 +275,9 @@ int make_plan(const bse_system* s, Plan& P) {
         int m1, m2, m3;
         unpack_m(P.gpack[(size_t)q * P.ng_max + g], m1, m2, m3);
         const int want = pack_m(tt[0] - m1, tt[1] - m2, tt[2] - m3);
-        int found = -1;
-        for (int h = 0; h < P.ng[iqb]; ++h)
-          if (P.gpack[(size_t)iqb * P.ng_max + h] == want) {
-            found = h;
-            break;
-          }
+        const auto& sv = sorted[iqb];
+        const auto it = std::lower_bound(sv.begin(), sv.end(), std::make_pair(want, -1));
+        const int found = (it != sv.end() && it->first == want) ? it->second : -1;
         if (found < 0) P.tr_closed = false;
         P.trmap[(size_t)q * P.ng_max + g] = found < 0 ? 0 : found;
       }
@@ -366,8 +370,10 @@ GemmArgs gemm_args(const Plan& P, const bse_system* s, char* region) {
 
 // Launch choices that the autotuner may change (per batch signature).
 struct Tune {
-  int persist = 0;  // persistent work-queue dispatch of the pair-density jobs
-  int ktile = 8;    // k tile of the pair-density dispatch order
+  int persist = 0;    // persistent work-queue dispatch of the pair-density jobs
+  int ktile = 8;      // k tile of the pair-density dispatch order
+  int wg_per_cu = 2;  // persistent grid: workgroups per CU
+  float pd_ms = 0.f;  // measured time of the tuned pair-density launch (0: not measured)
 };
 std::mutex g_tune_mu;
 std::vector<std::pair<std::string, Tune>> g_tune;
@@ -485,7 +491,7 @@ int make_batch(const bse_system* sys, int nsys, bool backward, const Tune& tn, B
 // Uploads every table of the batch (one blocking copy).
 int upload_batch(const Batch& B, const bse_system* sys, int precision, char* ws, hipStream_t st) {
   const int nsys = (int)B.P.size();
-  std::vector<char> buf(B.base.back() + B.P.back().tables, 0);
+  std::vector<char> buf(B.o_cnt, 0);  // batch tables
   auto cp = [&](size_t off, const void* src, size_t bytes) {
     if (bytes) std::memcpy(buf.data() + off, src, bytes);
   };
@@ -504,7 +510,6 @@ int upload_batch(const Batch& B, const bse_system* sys, int precision, char* ws,
     ac[i].out = reinterpret_cast<double2*>(region + P.o_RC);
     ga[i] = gemm_args(P, &sys[i], region);
     ga[i].w_head_fp64 = precision != BSE_FP64;  // mixed: the q = 0 head of W is added in FP64
-    put_tables(P, buf, B.base[i]);
   }
   cp(B.o_pdx, ax.data(), nsys * sizeof(PdArgs));
   cp(B.o_pdv, av.data(), nsys * sizeof(PdArgs));
@@ -517,22 +522,25 @@ int upload_batch(const Batch& B, const bse_system* sys, int precision, char* ws,
   cp(B.o_xt, B.xt.data(), B.xt.size() * sizeof(HTile));
   cp(B.o_mt, B.mt.data(), B.mt.size() * sizeof(HTile));
   cp(B.o_d2off, B.d2off.data(), B.d2off.size() * sizeof(int));
-  // the per-system data arrays between the table blocks are not copied
   HIP_TRY(hipMemcpyWithStream(ws, buf.data(), B.o_cnt, hipMemcpyHostToDevice, st));
-  for (int i = 0; i < nsys; ++i)
-    HIP_TRY(hipMemcpyWithStream(ws + B.base[i], buf.data() + B.base[i], B.P[i].tables, hipMemcpyHostToDevice, st));
+  // each system's own tables sit at the start of its region
+  for (int i = 0; i < nsys; ++i) {
+    std::vector<char> tb(B.P[i].tables, 0);
+    put_tables(B.P[i], tb, 0);
+    HIP_TRY(hipMemcpyWithStream(ws + B.base[i], tb.data(), tb.size(), hipMemcpyHostToDevice, st));
+  }
   return BSE_OK;
 }
 
-// Workgroups of a persistent pair-density launch: every CU's resident share
-// (two per CU at most, fewer if the LDS footprint allows less), a multiple of 8.
-int persistent_grid(size_t lds, int njobs) {
+// Workgroups of a persistent pair-density launch: wg_per_cu per CU, fewer if
+// the LDS footprint allows fewer, a multiple of 8.
+int persistent_grid(size_t lds, int njobs, int wg_per_cu) {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
   }
-  const int per_cu = std::max(1, std::min(2, (int)((160 * 1024) / std::max<size_t>(lds, 1))));
+  const int per_cu = std::max(1, std::min(wg_per_cu, (int)((160 * 1024) / std::max<size_t>(lds, 1))));
   int g = std::max(kXcds, (cus * per_cu) / kXcds * kXcds);
   return std::min(g, std::max(njobs, kXcds));
 }
@@ -550,7 +558,7 @@ int run_pd(const Batch& B, char* ws, int kind, const Tune& tn, hipStream_t st) {
   b.persist = tn.persist;
   b.cnt = reinterpret_cast<unsigned*>(ws + B.o_cnt) + kind * kXcds;
   const int stage_id = kind == 0 ? BSE_STAGE_PD_EXCH : kind == 1 ? BSE_STAGE_PD_VV : BSE_STAGE_PD_CC;
-  const int grid = tn.persist ? persistent_grid(B.lds, b.njobs) : b.njobs;
+  const int grid = tn.persist ? persistent_grid(B.lds, b.njobs, tn.wg_per_cu) : b.njobs;
   if (tn.persist) HIP_TRY(launch_zero_u32(b.cnt, kXcds, st));
   HIP_TRY(stage(stage_id, st, [&] {
     return launch_pair_density(b, B.N2, B.N3, B.ng_max, B.lds, grid, kind == 0, st);
@@ -580,6 +588,103 @@ int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& 
   HIP_TRY(stage(BSE_STAGE_DIRECT1, st, [&] { return launch_direct_s1(gs, s1, (int)B.s1.size(), precision, st); }));
   HIP_TRY(stage(BSE_STAGE_DIRECT2, st, [&] { return launch_direct_s2(gs, d2off, nsys, B.d2n, precision, st); }));
   HIP_TRY(stage(BSE_STAGE_MIRROR, st, [&] { return launch_mirror(gs, mt, (int)B.mt.size(), st); }));
+  return BSE_OK;
+}
+
+// ------------------------------------------------------------ autotuning
+
+// Tuning cache: one line per batch signature,
+//   {"key": "<signature>", "persist": P, "ktile": T, "wg_per_cu": W, "pd_ms": M}
+bool cache_lookup(const char* path, const std::string& key, Tune& out) {
+  if (!path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char line[4096];
+  bool hit = false;
+  const std::string want = "{\"key\": \"" + key + "\",";
+  while (fgets(line, sizeof line, f)) {
+    if (std::strncmp(line, want.c_str(), want.size()) != 0) continue;
+    Tune t;
+    float ms = 0.f;
+    if (sscanf(line + want.size(), " \"persist\": %d, \"ktile\": %d, \"wg_per_cu\": %d, \"pd_ms\": %f", &t.persist,
+               &t.ktile, &t.wg_per_cu, &ms) == 4 &&
+        (t.persist == 0 || t.persist == 1) && t.ktile >= 1 && t.ktile <= 1024 && t.wg_per_cu >= 1 && t.wg_per_cu <= 8) {
+      t.pd_ms = ms;
+      out = t;
+      hit = true;  // the last matching line wins
+    }
+  }
+  fclose(f);
+  return hit;
+}
+
+void cache_store(const char* path, const std::string& key, const Tune& t) {
+  if (!path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "{\"key\": \"%s\", \"persist\": %d, \"ktile\": %d, \"wg_per_cu\": %d, \"pd_ms\": %.4f}\n", key.c_str(),
+          t.persist, t.ktile, t.wg_per_cu, (double)t.pd_ms);
+  fclose(f);
+}
+
+// Times the valence-valence pair-density launch (the dominant stage) of the
+// batch under each candidate dispatch and keeps the fastest.
+int autotune(const bse_system* sys, int nsys, int precision, const char* cache, Tune& best, char* ws, size_t ws_bytes,
+             hipStream_t st) {
+  Batch B0;
+  int rc = make_batch(sys, nsys, false, Tune{}, B0);
+  if (rc) return rc;
+  const std::string key = batch_key(B0.P, precision);
+  if (cache_lookup(cache, key, best)) {
+    set_tune(key, best);
+    return BSE_OK;
+  }
+  if (ws_bytes < B0.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, B0.total);
+  std::vector<Tune> cand;
+  for (int kt : {4, 8, 16}) {
+    Tune t;
+    t.ktile = kt;
+    cand.push_back(t);
+  }
+  for (int w : {1, 2, 3, 4}) {
+    Tune t;
+    t.persist = 1;
+    t.wg_per_cu = w;
+    cand.push_back(t);
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  best = Tune{};
+  best.pd_ms = -1.f;
+  for (const Tune& c : cand) {
+    Batch B;
+    if ((rc = make_batch(sys, nsys, false, c, B))) break;
+    if ((rc = upload_batch(B, sys, precision, ws, st))) break;
+    float ms = 0.f;
+    hipError_t e = hipSuccess;
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // the first run warms caches and code
+      if (e == hipSuccess) e = hipEventRecord(e0, st);
+      if (e == hipSuccess && (rc = run_pd(B, ws, 1, c, st))) break;
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    }
+    if (rc) break;
+    if (e != hipSuccess) {
+      rc = fail(BSE_ERR_HIP, "autotune timing: %s", hipGetErrorString(e));
+      break;
+    }
+    if (best.pd_ms < 0.f || ms < best.pd_ms) {
+      best = c;
+      best.pd_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  set_tune(key, best);
+  cache_store(cache, key, best);
   return BSE_OK;
 }
 
@@ -750,6 +855,24 @@ int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, do
   g.npairs = (int)P.pairs.size();
   g.cpref = 27.211386245988 / ((double)P.nk * sys->omega_cell);
   HIP_TRY(launch_adjoint(g, precision, (int)P.dwt.size(), project, st));
+  return BSE_OK;
+}
+
+int bse_autotune(const bse_system* sys, int nsys, int precision, const char* cache_path, bse_tuning* chosen,
+                 void* ws, size_t ws_bytes, void* stream) {
+  if (!sys || nsys < 1) return fail(BSE_ERR_INVALID_ARG, "no systems");
+  if (!ws) return fail(BSE_ERR_INVALID_ARG, "workspace is NULL");
+  if (precision < BSE_FP64 || precision > BSE_BF16X3) return fail(BSE_ERR_INVALID_ARG, "bad precision %d", precision);
+  Tune t;
+  int rc = autotune(sys, nsys, precision, cache_path, t, static_cast<char*>(ws), ws_bytes,
+                    reinterpret_cast<hipStream_t>(stream));
+  if (rc) return rc;
+  if (chosen) {
+    chosen->persistent = t.persist;
+    chosen->ktile = t.ktile;
+    chosen->wg_per_cu = t.wg_per_cu;
+    chosen->pd_ms = t.pd_ms;
+  }
   return BSE_OK;
 }
 

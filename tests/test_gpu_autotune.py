@@ -1,0 +1,48 @@
+"""The project autotuner: it picks one of its candidate dispatches, records
+it in the cache file, reuses the cached choice, and does not change H."""
+import json
+import sys
+
+import pytest
+
+import bse_synth as B
+
+pytestmark = pytest.mark.gpu
+
+
+def test_autotune_choice_cache_and_results(tmp_path):
+    import paper_1206_3518_amd as P
+    import torch
+    systems = [
+        B.make_system(B.cell_sc(10.0), (16, 16, 16), (2, 2, 2), 2, 2, 3.0, seed=51),
+        B.make_system(B.cell_fcc(9.0), (16, 16, 16), (3, 1, 1), 1, 3, 2.0, seed=52),
+    ]
+    devs = [P.DeviceSystem(s) for s in systems]
+    ws = P.workspace(P.bse_workspace_size(devs))
+    P.bse_build_H(devs, P.BSE_FP64, 0, ws)
+    torch.cuda.synchronize()
+    before = [d.H.clone() for d in devs]
+    cache = tmp_path / "tune.jsonl"
+    got = P.bse_autotune(devs, P.BSE_FP64, cache, ws)
+    print("autotune choice:", got, flush=True)
+    sys.stdout.flush()
+    assert got["persistent"] in (0, 1) and got["pd_ms"] > 0.0
+    if got["persistent"]:
+        assert got["wg_per_cu"] in (1, 2, 3, 4)
+    else:
+        assert got["ktile"] in (4, 8, 16)
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1
+    rec = json.loads(lines[0])
+    assert (rec["persist"], rec["ktile"], rec["wg_per_cu"]) == (got["persistent"], got["ktile"], got["wg_per_cu"])
+    # a second call takes the cached line without timing again
+    again = P.bse_autotune(devs, P.BSE_FP64, cache, ws)
+    assert again == got or abs(again["pd_ms"] - got["pd_ms"]) < 1e-3 * got["pd_ms"]
+    assert len(cache.read_text().splitlines()) == 1
+    # builds after tuning give the same H, bit for bit
+    for d in devs:
+        d.H.zero_()
+    P.bse_build_H(devs, P.BSE_FP64, 0, ws)
+    torch.cuda.synchronize()
+    for d, h in zip(devs, before):
+        assert torch.equal(d.H, h)
