@@ -159,6 +159,100 @@ def adjoint(sys, Gbar, qs=None, separable=True):
     return dW, deps
 
 
+def upper_pairs(nk):
+    """Ordered k pairs k <= k' in lexicographic order: the independent pair
+    densities when the lower k blocks of H are the mirror of the upper ones."""
+    return [(a, b) for a in range(nk) for b in range(a, nk)]
+
+
+def densities(sys, separable=True):
+    """The pair densities that H is made of (Sec. II.B): X [Nk][nv][nc][ng_max]
+    = n_{vk,ck} on S(0), and for every upper pair (k, k') (lexicographic)
+    rv [np][nv][nv][ng_max] = n_{vk,v'k'}, rc [np][nc][nc][ng_max] =
+    n_{ck,c'k'} on S(q(k, k'))."""
+    nk, nv, nc = sys.nk, sys.nv, sys.nc
+    xi = [(k, v, k, nv + c) for k in range(nk) for v in range(nv) for c in range(nc)]
+    X = pair_density_items(sys, xi, separable).reshape(nk, nv, nc, sys.ng_max)
+    items = []
+    for ka, kb in upper_pairs(nk):
+        items += [(ka, v, kb, v2) for v in range(nv) for v2 in range(nv)]
+        items += [(ka, nv + c1, kb, nv + c2) for c1 in range(nc) for c2 in range(nc)]
+    rho = pair_density_items(sys, items, separable)
+    per = nv * nv + nc * nc
+    rho = rho.reshape(-1, per, sys.ng_max)
+    rv = rho[:, : nv * nv].reshape(-1, nv, nv, sys.ng_max)
+    rc = rho[:, nv * nv:].reshape(-1, nc, nc, sys.ng_max)
+    return X, rv, rc
+
+
+def H_from_densities(sys, X, rv, rc):
+    """H of Sec. II.C assembled from given pair densities: the exchange over
+    every (k, k') block, the direct term over the upper pairs k <= k', and the
+    lower blocks of the direct term as the conjugate transpose of the upper
+    ones.  With the densities of ``densities`` and a Hermitian,
+    time-reversal symmetric W this is ``build_H``."""
+    nk, nv, nc = sys.nk, sys.nv, sys.nc
+    nt = nv * nc
+    c = HARTREE_EV / (nk * sys.omega_cell)
+    ng0 = sys.ng[0]
+    v = np.array(sys.vx[:ng0], dtype=np.float64)
+    v[0] = 0.0  # G = 0 left out of the exchange
+    N = X[..., :ng0].reshape(sys.ns, ng0)
+    H = 2.0 * c * (np.conj(N) * v) @ N.T
+    D = np.zeros_like(H)
+    for p, (ka, kb) in enumerate(upper_pairs(nk)):
+        iq, _ = fold(sys.kmesh, ka, kb)
+        ng = sys.ng[iq]
+        Wq = sys.W[iq, :ng, :ng]
+        blk = np.einsum("abg,gh,cdh->acbd", np.conj(rv[p, :, :, :ng]), Wq, rc[p, :, :, :ng]).reshape(nt, nt)
+        D[ka * nt:(ka + 1) * nt, kb * nt:(kb + 1) * nt] = blk
+        if ka != kb:
+            D[kb * nt:(kb + 1) * nt, ka * nt:(ka + 1) * nt] = np.conj(blk).T
+    H -= c * D
+    de = (sys.eps[:, nv:][:, None, :] - sys.eps[:, :nv][:, :, None]).reshape(-1)
+    H[np.diag_indices(sys.ns)] += de
+    return H
+
+
+def adjoint_densities(sys, Gbar, X=None, rv=None, rc=None):
+    """Gradient of L (dL = Re sum conj(Gbar) dH) with respect to the pair
+    densities that ``H_from_densities`` takes, in the PyTorch convention
+    dL/dz = dL/dRe z + i dL/dIm z:
+      dX_S(m)      = 2c v(m) sum_S' (conj(Gbar_SS') + Gbar_S'S) X_S'(m)      (m != 0)
+      drv_vv'(g)   = -c sum_cc' conj(Geff_SS') (W rc_cc')(g)
+      drc_cc'(g')  = -c sum_vv' Geff_SS' (W^H rv_vv')(g')
+    with Geff = Gbar + Gbar^H on the blocks k < k' (their mirror images
+    depend on the same densities) and Geff = Gbar on k = k'.
+    Returns (dX, drv, drc) shaped like (X, rv, rc)."""
+    if X is None:
+        X, rv, rc = densities(sys)
+    nk, nv, nc = sys.nk, sys.nv, sys.nc
+    nt = nv * nc
+    c = HARTREE_EV / (nk * sys.omega_cell)
+    ng0 = sys.ng[0]
+    v = np.array(sys.vx[:ng0], dtype=np.float64)
+    v[0] = 0.0
+    N = X[..., :ng0].reshape(sys.ns, ng0)
+    G2 = np.conj(Gbar) + Gbar.T
+    dX = np.zeros_like(X)
+    dX[..., :ng0] = (2.0 * c * v * (G2 @ N)).reshape(nk, nv, nc, ng0)
+    drv = np.zeros_like(rv)
+    drc = np.zeros_like(rc)
+    for p, (ka, kb) in enumerate(upper_pairs(nk)):
+        iq, _ = fold(sys.kmesh, ka, kb)
+        ng = sys.ng[iq]
+        Wq = sys.W[iq, :ng, :ng]
+        gb = Gbar[ka * nt:(ka + 1) * nt, kb * nt:(kb + 1) * nt]
+        if ka != kb:
+            gb = gb + np.conj(Gbar[kb * nt:(kb + 1) * nt, ka * nt:(ka + 1) * nt]).T
+        geff = gb.reshape(nv, nc, nv, nc)
+        wrc = np.einsum("gh,cdh->cdg", Wq, rc[p, :, :, :ng])
+        whrv = np.einsum("gh,abg->abh", np.conj(Wq), rv[p, :, :, :ng])
+        drv[p, :, :, :ng] = -c * np.einsum("acbd,cdg->abg", np.conj(geff), wrc)
+        drc[p, :, :, :ng] = -c * np.einsum("acbd,abh->cdh", geff, whrv)
+    return dX, drv, drc
+
+
 def tr_orbit(sys, iq, g, gp):
     """The entries of W tied to W_{g g'}(q) by Hermiticity and time reversal
     (Sec. III.A with T = 1), as (q, g, g', conjugated) tuples."""
