@@ -127,19 +127,29 @@ int bse_build_H(const bse_system *sys, int nsys, int precision, int flags,
 
 /*
  * Adjoint of bse_build_H for one system: given dL/dH (DEVICE [NS][NS] complex,
- * the PyTorch convention dL/dRe H + i dL/dIm H), returns
- *   dW   DEVICE [Nk][ng_max][ng_max] complex (nullable)  dL/dW_GG'(q), zero past ng(q)
- *   deps DEVICE [Nk][nb]             (nullable)          dL/de (eV/eV)
- * Only W and eps are differentiated (u, v and the cell are constants).
+ * the PyTorch convention dL/dRe H + i dL/dIm H), returns (every output
+ * DEVICE complex or real as shown, nullable, fully written when given):
+ *   dW      [Nk][ng_max][ng_max]     dL/dW_GG'(q), zero past ng(q)
+ *   deps    [Nk][nb] (real)          dL/de (eV/eV)
+ *   dX      [Nk][nv][nc][ng_max]     dL/dn_{vk,ck}(G) on S(0) (the pair density
+ *                                    itself, not scaled by v), zero at G = 0
+ *                                    and past ng(0)
+ *   drho_vv [npairs][nv][nv][ng_max] dL/dn_{vk,v'k'}(G) on S(q(k,k'))
+ *   drho_cc [npairs][nc][nc][ng_max] dL/dn_{ck,c'k'}(G), zero past ng(q)
+ * for the pairs k <= k' in lexicographic order (0,0), (0,1), ..., (Nk-1,Nk-1)
+ * (Sec. II.C: the lower k blocks of H are the conjugate transpose of the
+ * upper ones, so the densities of the upper pairs are the independent ones).
  * Pair densities are recomputed, not read from a previous build.  Without
  * BSE_PROJECT_DW, dW is the partial derivative of the map the build computes
  * (upper k blocks, lower ones mirrored); with it, dW is projected onto the
  * Hermitian, time-reversal symmetric W on which that map and the all-blocks
  * definition agree.  precision selects the arithmetic of the dW contraction
- * (its q = 0 head entry is FP64 in every mode); sys->H is not read.
+ * (its q = 0 head entry is FP64 in every mode); the density gradients are
+ * FP64.  sys->H is not read.
  */
-int bse_build_H_backward(const bse_system *sys, const double *dH, double *dW, double *deps,
-                         int precision, int flags, void *ws, size_t ws_bytes, void *stream);
+int bse_build_H_backward(const bse_system *sys, const double *dH, double *dW, double *deps, double *dX,
+                         double *drho_vv, double *drho_cc, int precision, int flags, void *ws, size_t ws_bytes,
+                         void *stream);
 
 /*
  * Launch choices of bse_build_H for one batch signature (grids, k meshes,

@@ -165,16 +165,18 @@ def upper_pairs(nk):
     return [(a, b) for a in range(nk) for b in range(a, nk)]
 
 
-def densities(sys, separable=True):
+def densities(sys, separable=True, pairs=None):
     """The pair densities that H is made of (Sec. II.B): X [Nk][nv][nc][ng_max]
     = n_{vk,ck} on S(0), and for every upper pair (k, k') (lexicographic)
     rv [np][nv][nv][ng_max] = n_{vk,v'k'}, rc [np][nc][nc][ng_max] =
-    n_{ck,c'k'} on S(q(k, k'))."""
+    n_{ck,c'k'} on S(q(k, k')); ``pairs`` (indices into ``upper_pairs``)
+    restricts rv and rc to those pairs."""
     nk, nv, nc = sys.nk, sys.nv, sys.nc
     xi = [(k, v, k, nv + c) for k in range(nk) for v in range(nv) for c in range(nc)]
     X = pair_density_items(sys, xi, separable).reshape(nk, nv, nc, sys.ng_max)
+    up = upper_pairs(nk)
     items = []
-    for ka, kb in upper_pairs(nk):
+    for ka, kb in (up if pairs is None else [up[p] for p in pairs]):
         items += [(ka, v, kb, v2) for v in range(nv) for v2 in range(nv)]
         items += [(ka, nv + c1, kb, nv + c2) for c1 in range(nc) for c2 in range(nc)]
     rho = pair_density_items(sys, items, separable)
@@ -214,7 +216,7 @@ def H_from_densities(sys, X, rv, rc):
     return H
 
 
-def adjoint_densities(sys, Gbar, X=None, rv=None, rc=None):
+def adjoint_densities(sys, Gbar, X=None, rv=None, rc=None, pairs=None):
     """Gradient of L (dL = Re sum conj(Gbar) dH) with respect to the pair
     densities that ``H_from_densities`` takes, in the PyTorch convention
     dL/dz = dL/dRe z + i dL/dIm z:
@@ -223,9 +225,10 @@ def adjoint_densities(sys, Gbar, X=None, rv=None, rc=None):
       drc_cc'(g')  = -c sum_vv' Geff_SS' (W^H rv_vv')(g')
     with Geff = Gbar + Gbar^H on the blocks k < k' (their mirror images
     depend on the same densities) and Geff = Gbar on k = k'.
+    ``pairs`` (indices into ``upper_pairs``) says which pairs rv and rc hold.
     Returns (dX, drv, drc) shaped like (X, rv, rc)."""
     if X is None:
-        X, rv, rc = densities(sys)
+        X, rv, rc = densities(sys, pairs=pairs)
     nk, nv, nc = sys.nk, sys.nv, sys.nc
     nt = nv * nc
     c = HARTREE_EV / (nk * sys.omega_cell)
@@ -238,7 +241,8 @@ def adjoint_densities(sys, Gbar, X=None, rv=None, rc=None):
     dX[..., :ng0] = (2.0 * c * v * (G2 @ N)).reshape(nk, nv, nc, ng0)
     drv = np.zeros_like(rv)
     drc = np.zeros_like(rc)
-    for p, (ka, kb) in enumerate(upper_pairs(nk)):
+    up = upper_pairs(nk)
+    for p, (ka, kb) in enumerate(up if pairs is None else [up[i] for i in pairs]):
         iq, _ = fold(sys.kmesh, ka, kb)
         ng = sys.ng[iq]
         Wq = sys.W[iq, :ng, :ng]

@@ -64,7 +64,7 @@ def lib():
         L.bse_pair_density.restype = I
         L.bse_build_H.argtypes = [P, I, I, I, P, S, P]
         L.bse_build_H.restype = I
-        L.bse_build_H_backward.argtypes = [P, P, P, P, I, I, P, S, P]
+        L.bse_build_H_backward.argtypes = [P, P, P, P, P, P, P, I, I, P, S, P]
         L.bse_build_H_backward.restype = I
         L.bse_autotune.argtypes = [P, I, I, ctypes.c_char_p, P, P, S, P]
         L.bse_autotune.restype = I
@@ -238,18 +238,31 @@ def build_H(sys_or_dev, precision="fp64", flags=0, ws=None):
 
 
 def bse_build_H_backward(system: DeviceSystem, dH, want_dW=True, want_deps=True, precision=BSE_FP64, flags=0,
-                         ws=None, stream=None):
-    """(dL/dW, dL/deps) for dL/dH = dH (complex128 [NS][NS], PyTorch convention)."""
+                         ws=None, stream=None, want_densities=False):
+    """(dL/dW, dL/deps) for dL/dH = dH (complex128 [NS][NS], PyTorch convention);
+    with want_densities also (dL/dX [Nk][nv][nc][ng_max], dL/drho_vv
+    [npairs][nv][nv][ng_max], dL/drho_cc [npairs][nc][nc][ng_max]) for the
+    pairs k <= k' in lexicographic order."""
     import torch
     p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     dH = dH.contiguous()
     dW = torch.empty_like(system.W) if want_dW else None
     deps = torch.empty_like(system.eps) if want_deps else None
+    dX = drv = drc = None
+    if want_densities:
+        nk, nv, nc, ngm = system.nk, system.nv, system.nc, system.ng_max
+        npairs = nk * (nk + 1) // 2
+        kw = dict(dtype=torch.complex128, device=system.W.device)
+        dX = torch.empty((nk, nv, nc, ngm), **kw)
+        drv = torch.empty((npairs, nv, nv, ngm), **kw)
+        drc = torch.empty((npairs, nc, nc, ngm), **kw)
     if ws is None:
         ws = workspace(bse_workspace_size([system], p, flags), system.device)
     st = system.struct()
-    _check(lib().bse_build_H_backward(ctypes.byref(st), _ptr(dH), _ptr(dW), _ptr(deps), p, int(flags), _ptr(ws),
-                                      ws.numel(), _stream(stream)))
+    _check(lib().bse_build_H_backward(ctypes.byref(st), _ptr(dH), _ptr(dW), _ptr(deps), _ptr(dX), _ptr(drv),
+                                      _ptr(drc), p, int(flags), _ptr(ws), ws.numel(), _stream(stream)))
+    if want_densities:
+        return dW, deps, dX, drv, drc
     return dW, deps
 
 

@@ -181,6 +181,139 @@ __global__ void k_adj_project(AdjArgs a, const double2* __restrict__ raw, double
   out[id] = make_double2(0.25 * (x0.x + x1.x + x2.x + x3.x), 0.25 * (x0.y - x1.y - x2.y + x3.y));
 }
 
+// ---------------------------------------------------------------- pair-density gradients
+// With dL = Re sum conj(Gbar) dH and Geff as above (Gbar + Gbar^H on k < k',
+// Gbar on k = k'), the densities of the upper pairs get
+//   dL/drho_cc'(g') = -c sum_vv' Geff_SS' conj(Z_vv'(g')),  Z = conj(rho_vv')^T W  (= conj(W^H rho_vv'))
+//   dL/drho_vv'(g)  = -c (W conj(T_vv'))(g),                 T = Geff conj(rho_cc')
+// and the exchange densities (every block of H depends on them directly)
+//   dL/dn_S(m)      = 2c sqrt v(m) [(conj(Gbar) + Gbar^T) Xs](S, m),  Xs = sqrt v n.
+
+// One k pair and one 16-row block of cc', all g'.  f64 MFMA: A[cc'][vv'] =
+// Geff_SS', B[vv'][g'] = conj(Z).
+__global__ __launch_bounds__(256) void k_adj_drc(AdjArgs a, int tiles_i, int nitems) {
+  const int lane = threadIdx.x & 63;
+  const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= nitems) return;
+  const int p = item / tiles_i, ti = item % tiles_i;
+  const int4 pr = a.pairs[p];
+  const int ka = pr.x, kb = pr.y;
+  const int K = a.ng[pr.z];
+  const int nv = a.nv, nc = a.nc, nv2 = nv * nv, nc2 = nc * nc, ns = a.ns;
+  const int i = ti * 16 + (lane & 15);  // cc' row of the A operand
+  const double2* Z = a.Z + (size_t)p * nv2 * a.ng_max;
+  double2* out = a.drc + (size_t)a.plex[p] * nc2 * a.ng_max;
+  for (int n0 = 0; n0 < a.ng_max; n0 += 16) {
+    d4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+    for (int kc = 0; kc < nv2; kc += 4) {
+      const int j = kc + (lane >> 4);  // vv'
+      double2 g = make_double2(0.0, 0.0);
+      if (i < nc2 && j < nv2) {
+        const int c = i / nc, c2 = i % nc, v = j / nv, v2 = j % nv;
+        const size_t S = ((size_t)ka * nv + v) * nc + c;
+        const size_t S2 = ((size_t)kb * nv + v2) * nc + c2;
+        g = a.dH[S * ns + S2];
+        if (ka != kb) {
+          const double2 h = a.dH[S2 * ns + S];
+          g.x += h.x;
+          g.y -= h.y;
+        }
+      }
+      const int n = n0 + (lane & 15);
+      double2 b = make_double2(0.0, 0.0);
+      if (j < nv2 && n < K) {
+        const double2 z = Z[(size_t)j * a.ng_max + n];
+        b = make_double2(z.x, -z.y);
+      }
+      cre = mfma64(g.x, b.x, cre);
+      cre = mfma64(-g.y, b.y, cre);
+      cim = mfma64(g.x, b.y, cim);
+      cim = mfma64(g.y, b.x, cim);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = ti * 16 + 4 * r + (lane >> 4);
+      const int col = n0 + (lane & 15);
+      if (row < nc2 && col < a.ng_max)
+        out[(size_t)row * a.ng_max + col] =
+            col < K ? make_double2(-a.cpref * cre[r], -a.cpref * cim[r]) : make_double2(0.0, 0.0);
+    }
+  }
+}
+
+// dL/drho_vv' tile of a q group: C = conj(T) W_q^T (A = T rows of the group,
+// B transposed), every column up to ng_max written.
+__global__ __launch_bounds__(256) void k_adj_drv(AdjArgs a) {
+  const int4 tl = a.rvtiles[blockIdx.x];
+  const int q = tl.x;
+  const int nv2 = a.nv * a.nv;
+  const int row_base = a.qstart[q] * nv2;
+  const int rows = (a.qstart[q + 1] - a.qstart[q]) * nv2;
+  const int K = a.ng[q];
+  const double2* A = a.T + (size_t)row_base * a.ng_max;
+  const double2* Wq = a.W + (size_t)q * a.ng_max * a.ng_max;
+  const int r0 = tl.y * 64, c0 = tl.z * 64;
+  d4 cre[2][2], cim[2][2];
+  tile_gemm<true, true>(A, a.ng_max, r0, rows, Wq, a.ng_max, c0, K, K, cre, cim);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + wr * 32 + i * 16 + 4 * r + (lane >> 4);
+        const int col = c0 + wc * 32 + j * 16 + (lane & 15);
+        if (row < rows && col < a.ng_max) {
+          const int p = a.qstart[q] + row / nv2;
+          double2* o = a.drv + ((size_t)a.plex[p] * nv2 + row % nv2) * a.ng_max;
+          o[col] = col < K ? make_double2(-a.cpref * cre[i][j][r], -a.cpref * cim[i][j][r]) : make_double2(0.0, 0.0);
+        }
+      }
+}
+
+// dL/dn_S(m) tile (64 S x 64 m): conj(Gbar) Xs + Gbar^T Xs, K = NS.
+__global__ __launch_bounds__(256) void k_adj_dx(AdjArgs a) {
+  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+  d4 cre[2][2], cim[2][2];
+  tile_gemm<true, false, false, true>(a.dH, a.ns, r0, a.ns, a.Xs, a.ng_max, c0, a.ngx, a.ns, cre, cim);
+  tile_gemm<false, false, true, false>(a.dH, a.ns, r0, a.ns, a.Xs, a.ng_max, c0, a.ngx, a.ns, cre, cim);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + wr * 32 + i * 16 + 4 * r + (lane >> 4);
+        const int col = c0 + wc * 32 + j * 16 + (lane & 15);
+        if (row < a.ns && col < a.ng_max) {
+          const double s = col < a.ngx ? 2.0 * a.cpref * a.vs[col] : 0.0;
+          a.dX[(size_t)row * a.ng_max + col] = make_double2(s * cre[i][j][r], s * cim[i][j][r]);
+        }
+      }
+}
+
+hipError_t launch_adj_drc(const AdjArgs& a, hipStream_t st) {
+  const int ti = (a.nc * a.nc + 15) / 16;
+  const int nitems = a.npairs * ti;
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_drc, dim3((nitems + 3) / 4), dim3(256), 0, st, a, ti, nitems);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_drv(const AdjArgs& a, int ntiles, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_drv, dim3(ntiles), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_dx(const AdjArgs& a, hipStream_t st) {
+  const dim3 grid((a.ng_max + 63) / 64, (a.ns + 63) / 64);
+  hipLaunchKernelGGL(k_adj_dx, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_adjoint(const AdjArgs& a, int precision, int ndw_tiles, bool project, hipStream_t st) {
   const int ti = (a.nv * a.nv + 15) / 16;
   const int nitems = a.npairs * ti;

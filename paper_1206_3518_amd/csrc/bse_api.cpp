@@ -128,11 +128,13 @@ struct Plan {
   std::vector<HTile> xt, mt;       // exchange tiles; mirror tiles
   int d2items = 0;                 // stage-2 items (pairs x 16 x 16 tiles)
   std::vector<int4> dwt;   // adjoint dW tiles (q, mt, nt, -)
+  std::vector<int4> rvt;   // adjoint drho_vv' tiles (q, mt, nt, -) over every column of ng_max
+  std::vector<int> plex;   // lexicographic position of each pair among k <= k'
   std::vector<int> qbar, trmap;
   bool tr_closed = true;
   // byte offsets inside the system's region of the workspace
   size_t o_gpack = 0, o_ng = 0, o_pairs = 0, o_qstart = 0;
-  size_t o_dwt = 0, o_qbar = 0, o_trmap = 0;
+  size_t o_dwt = 0, o_rvt = 0, o_plex = 0, o_qbar = 0, o_trmap = 0;
   size_t tables = 0, o_vs = 0, o_X = 0, o_RV = 0, o_RC = 0, o_Z = 0, o_dWraw = 0, total = 0;
   size_t fwd_total = 0;  // region needed by the forward build (no dW scratch)
 };
@@ -251,6 +253,20 @@ int make_plan(const bse_system* s, Plan& P) {
       for (int i = 0; i < T2; ++i)
         for (int j = 0; j < T2; ++j) P.dwt.push_back(make_int4(q, i, j, 0));
   }
+  P.rvt.clear();
+  {
+    const int T2 = (P.ng_max + 63) / 64;
+    for (int q = 0; q < P.nk; ++q) {
+      const int mt = ((P.qstart[q + 1] - P.qstart[q]) * P.nv * P.nv + 63) / 64;
+      for (int i = 0; i < mt; ++i)
+        for (int j = 0; j < T2; ++j) P.rvt.push_back(make_int4(q, i, j, 0));
+    }
+  }
+  P.plex.resize(np);
+  for (int p = 0; p < np; ++p) {
+    const long long a = P.pairs[p].x, b = P.pairs[p].y;
+    P.plex[p] = (int)(a * P.nk - a * (a - 1) / 2 + (b - a));
+  }
   P.qbar.assign(P.nk, 0);
   P.trmap.assign((size_t)P.nk * P.ng_max, 0);
   {
@@ -296,6 +312,8 @@ int make_plan(const bse_system* s, Plan& P) {
   P.o_pairs = put(P.pairs.size() * sizeof(int4));
   P.o_qstart = put(P.qstart.size() * sizeof(int));
   P.o_dwt = put(P.dwt.size() * sizeof(int4));
+  P.o_rvt = put(P.rvt.size() * sizeof(int4));
+  P.o_plex = put(P.plex.size() * sizeof(int));
   P.o_qbar = put(P.qbar.size() * sizeof(int));
   P.o_trmap = put(P.trmap.size() * sizeof(int));
   P.tables = o;
@@ -321,6 +339,8 @@ void put_tables(const Plan& P, std::vector<char>& buf, size_t base) {
   cp(P.o_pairs, P.pairs.data(), P.pairs.size() * sizeof(int4));
   cp(P.o_qstart, P.qstart.data(), P.qstart.size() * sizeof(int));
   cp(P.o_dwt, P.dwt.data(), P.dwt.size() * sizeof(int4));
+  cp(P.o_rvt, P.rvt.data(), P.rvt.size() * sizeof(int4));
+  cp(P.o_plex, P.plex.data(), P.plex.size() * sizeof(int));
   cp(P.o_qbar, P.qbar.data(), P.qbar.size() * sizeof(int));
   cp(P.o_trmap, P.trmap.data(), P.trmap.size() * sizeof(int));
 }
@@ -622,7 +642,7 @@ void cache_store(const char* path, const std::string& key, const Tune& t) {
   if (!path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "{\"key\": \"%s\", \"persist\": %d, \"ktile\": %d, \"wg_per_cu\": %d, \"pd_ms\": %.4f}\n", key.c_str(),
+  fprintf(f, "{\"key\": \"%s\", \"persist\": %d, \"ktile\": %d, \"wg_per_cu\": %d, \"pd_ms\": %.9g}\n", key.c_str(),
           t.persist, t.ktile, t.wg_per_cu, (double)t.pd_ms);
   fclose(f);
 }
@@ -813,8 +833,9 @@ int bse_build_H(const bse_system* sys, int nsys, int precision, int flags, void*
   return run_build(B, sys, precision, tn, static_cast<char*>(ws), st);
 }
 
-int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, double* deps, int precision, int flags,
-                         void* ws, size_t ws_bytes, void* stream) {
+int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, double* deps, double* dX,
+                         double* drho_vv, double* drho_cc, int precision, int flags, void* ws, size_t ws_bytes,
+                         void* stream) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (!dH || !ws) return fail(BSE_ERR_INVALID_ARG, "dH / ws is NULL");
   if (precision < BSE_FP64 || precision > BSE_BF16X3) return fail(BSE_ERR_INVALID_ARG, "bad precision %d", precision);
@@ -829,10 +850,15 @@ int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, do
     return fail(BSE_ERR_NOT_HERMITIAN, "G spheres are not closed under time reversal; cannot project dW");
   char* w = static_cast<char*>(ws);
   if ((rc = upload_batch(B, sys, precision, w, st))) return rc;
-  // recompute the pair densities of the direct term
+  // recompute the pair densities (exchange ones only for dX)
+  char* r = w + B.base[0];
+  if (dX) {
+    double* vs = reinterpret_cast<double*>(r + P.o_vs);
+    HIP_TRY(launch_vscale(sys->vx, P.ng[0], P.ng_max, vs, st));
+    if ((rc = run_pd(B, w, 0, Tune{}, st))) return rc;
+  }
   if ((rc = run_pd(B, w, 1, Tune{}, st))) return rc;
   if ((rc = run_pd(B, w, 2, Tune{}, st))) return rc;
-  char* r = w + B.base[0];
   AdjArgs g{};
   g.dH = reinterpret_cast<const double2*>(dH);
   g.RV = reinterpret_cast<const double2*>(r + P.o_RV);
@@ -854,7 +880,27 @@ int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, do
   g.ng_max = P.ng_max;
   g.npairs = (int)P.pairs.size();
   g.cpref = 27.211386245988 / ((double)P.nk * sys->omega_cell);
+  g.Z = reinterpret_cast<const double2*>(r + P.o_Z);
+  g.W = reinterpret_cast<const double2*>(sys->W);
+  g.Xs = reinterpret_cast<const double2*>(r + P.o_X);
+  g.vs = reinterpret_cast<const double*>(r + P.o_vs);
+  g.plex = reinterpret_cast<const int*>(r + P.o_plex);
+  g.rvtiles = reinterpret_cast<const int4*>(r + P.o_rvt);
+  g.ngx = P.ng[0];
+  g.dX = reinterpret_cast<double2*>(dX);
+  g.drv = reinterpret_cast<double2*>(drho_vv);
+  g.drc = reinterpret_cast<double2*>(drho_cc);
+  if (drho_cc) {
+    // Z = conj(rho_vv')^T W (the forward stage 1, FP64) into the Z area
+    const GemmArgs* gs = reinterpret_cast<const GemmArgs*>(w + B.o_gargs);
+    const S1Tile* s1 = reinterpret_cast<const S1Tile*>(w + B.o_s1);
+    HIP_TRY(launch_direct_s1(gs, s1, (int)B.s1.size(), BSE_FP64, st));
+    HIP_TRY(launch_adj_drc(g, st));
+  }
+  // T (over the Z area), dW, deps
   HIP_TRY(launch_adjoint(g, precision, (int)P.dwt.size(), project, st));
+  if (drho_vv) HIP_TRY(launch_adj_drv(g, (int)P.rvt.size(), st));
+  if (dX) HIP_TRY(launch_adj_dx(g, st));
   return BSE_OK;
 }
 

@@ -22,7 +22,8 @@ constexpr int TM = 64, TN = 64, KC = 16;
 // A[m][k] = Am[(a_off + m) * lda + k]   (A_T: Am[k * lda + a_off + m]), valid a_off + m < a_lim;
 // B[k][n] = Bm[k * ldb + b_off + n]     (B_T: Bm[(b_off + n) * ldb + k]), valid b_off + n < b_lim;
 // valid k < K.  The result lands in cre/cim (f64 MFMA accumulator layout).
-template <bool CONJ_A, bool B_T, bool A_T = false>
+// ZERO = false adds to the accumulators instead of starting from zero.
+template <bool CONJ_A, bool B_T, bool A_T = false, bool ZERO = true>
 __device__ __forceinline__ void tile_gemm(const double2* __restrict__ A, int lda, int a_off, int a_lim,
                                           const double2* __restrict__ B, int ldb, int b_off, int b_lim, int K,
                                           d4 (&cre)[2][2], d4 (&cim)[2][2]) {
@@ -30,13 +31,15 @@ __device__ __forceinline__ void tile_gemm(const double2* __restrict__ A, int lda
   __shared__ double Bs_re[KC][TN + 1], Bs_im[KC][TN + 1];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = w >> 1, wc = w & 1;
+  if constexpr (ZERO) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      cre[i][j] = d4{0, 0, 0, 0};
-      cim[i][j] = d4{0, 0, 0, 0};
-    }
+      for (int j = 0; j < 2; ++j) {
+        cre[i][j] = d4{0, 0, 0, 0};
+        cim[i][j] = d4{0, 0, 0, 0};
+      }
+  }
   for (int k0 = 0; k0 < K; k0 += KC) {
     if (!A_T) {  // A chunk: row t>>2, 4 consecutive k
       const int r = t >> 2, c0 = (t & 3) * 4;

@@ -125,6 +125,17 @@ struct AdjArgs {
   const int* trmap;    // [Nk][ng_max] index of t - m_g in the sphere of qbar
   int nk, nv, nc, ns, ng_max, npairs;
   double cpref;
+  // gradients with respect to the pair densities (nullable outputs)
+  const double2* Z;    // forward stage-1 product conj(rho_vv')^T W, rows like RV
+  const double2* W;    // [Nk][ng_max][ng_max]
+  const double2* Xs;   // exchange densities scaled by sqrt v, [NS][ng_max]
+  const double* vs;    // sqrt v on S(0), zero at G = 0
+  const int* plex;     // [npairs] lexicographic position of each pair (k <= k')
+  const int4* rvtiles; // (q, row tile, column tile, -) over every column of ng_max
+  int ngx;             // ng(q = 0)
+  double2* dX;         // [NS][ng_max]
+  double2* drv;        // [npairs][nv][nv][ng_max], lexicographic pairs
+  double2* drc;        // [npairs][nc][nc][ng_max]
 };
 // Reciprocal vectors (rows b_d, bohr^-1) for the gradient matrix elements.
 struct GradCell {
@@ -137,5 +148,11 @@ hipError_t launch_spectrum(int ns, int nlam, const double* E, const double2* A, 
                            int nw, double w0, double w1, double eta, double* t2, double* eps2, hipStream_t st);
 
 hipError_t launch_adjoint(const AdjArgs& a, int precision, int ndw_tiles, bool project, hipStream_t st);
+// dL/drho_cc' from Z (run before launch_adjoint overwrites Z with T)
+hipError_t launch_adj_drc(const AdjArgs& a, hipStream_t st);
+// dL/drho_vv' from T (after launch_adjoint)
+hipError_t launch_adj_drv(const AdjArgs& a, int ntiles, hipStream_t st);
+// dL/dn_{vk,ck} from the scaled exchange densities
+hipError_t launch_adj_dx(const AdjArgs& a, hipStream_t st);
 
 }  // namespace bse

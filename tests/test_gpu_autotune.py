@@ -37,7 +37,9 @@ def test_autotune_choice_cache_and_results(tmp_path):
     assert (rec["persist"], rec["ktile"], rec["wg_per_cu"]) == (got["persistent"], got["ktile"], got["wg_per_cu"])
     # a second call takes the cached line without timing again
     again = P.bse_autotune(devs, P.BSE_FP64, cache, ws)
-    assert again == got or abs(again["pd_ms"] - got["pd_ms"]) < 1e-3 * got["pd_ms"]
+    assert {k: again[k] for k in ("persistent", "ktile", "wg_per_cu")} == \
+        {k: got[k] for k in ("persistent", "ktile", "wg_per_cu")}
+    assert abs(again["pd_ms"] - got["pd_ms"]) <= 1e-6 * got["pd_ms"]
     assert len(cache.read_text().splitlines()) == 1
     # builds after tuning give the same H, bit for bit
     for d in devs:
