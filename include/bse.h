@@ -63,7 +63,12 @@ enum bse_precision {
 };
 
 enum bse_flags {
-    BSE_VALIDATE = 1,    /* scan inputs (synchronously) before enqueueing         */
+    BSE_VALIDATE = 1,    /* scan the inputs first and wait for the result:
+                            NaN/Inf in u, eps, vx or W -> BSE_ERR_NONFINITE;
+                            W(q) not Hermitian, or not obeying time reversal
+                            where the spheres allow the check, by more than
+                            1e-10 max|W| (|re| + |im| of the difference)
+                            -> BSE_ERR_NOT_HERMITIAN                             */
     BSE_PERSISTENT = 2,  /* build a batch of systems with one persistent launch   */
     BSE_PROJECT_DW = 4   /* backward: project dW onto Hermitian, time-reversal
                             symmetric W (group average of Sec. III.A, T = 1)     */

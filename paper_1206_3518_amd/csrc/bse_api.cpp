@@ -498,7 +498,7 @@ int make_batch(const bse_system* sys, int nsys, bool backward, const Tune& tn, B
   B.o_xt = put(B.xt.size() * sizeof(HTile));
   B.o_mt = put(B.mt.size() * sizeof(HTile));
   B.o_d2off = put(B.d2off.size() * sizeof(int));
-  B.o_cnt = put(3 * kXcds * sizeof(unsigned));
+  B.o_cnt = put(3 * kXcds * sizeof(unsigned) + 32 + 8 * sizeof(unsigned long long));  // queues, validation
   B.base.resize(nsys);
   for (int i = 0; i < nsys; ++i) {
     B.base[i] = o;
@@ -608,6 +608,43 @@ int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& 
   HIP_TRY(stage(BSE_STAGE_DIRECT1, st, [&] { return launch_direct_s1(gs, s1, (int)B.s1.size(), precision, st); }));
   HIP_TRY(stage(BSE_STAGE_DIRECT2, st, [&] { return launch_direct_s2(gs, d2off, nsys, B.d2n, precision, st); }));
   HIP_TRY(stage(BSE_STAGE_MIRROR, st, [&] { return launch_mirror(gs, mt, (int)B.mt.size(), st); }));
+  return BSE_OK;
+}
+
+// ------------------------------------------------------------ validation
+
+// BSE_VALIDATE: scans every system's inputs and waits for the result.
+int validate(const Batch& B, const bse_system* sys, char* ws, hipStream_t st) {
+  unsigned* bad = reinterpret_cast<unsigned*>(ws + B.o_cnt + 3 * kXcds * sizeof(unsigned));
+  unsigned long long* wstat = reinterpret_cast<unsigned long long*>(ws + B.o_cnt + 3 * kXcds * sizeof(unsigned) + 32);
+  for (size_t i = 0; i < B.P.size(); ++i) {
+    const Plan& P = B.P[i];
+    const bse_system& s = sys[i];
+    char* r = ws + B.base[i];
+    HIP_TRY(launch_zero_u32(bad, 8 + 16, st));  // the 3 flags and the 64-bit maxima after them
+    HIP_TRY(launch_validate(s.u, (size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * 2, s.eps, (size_t)P.nk * P.nb, s.vx,
+                            (size_t)P.ng[0], reinterpret_cast<const double2*>(s.W),
+                            reinterpret_cast<const int*>(r + P.o_ng), reinterpret_cast<const int*>(r + P.o_qbar),
+                            reinterpret_cast<const int*>(r + P.o_trmap), P.nk, P.ng_max, P.tr_closed ? 1 : 0, bad,
+                            wstat, st));
+    unsigned hb[3];
+    unsigned long long hw[3];
+    HIP_TRY(hipMemcpyAsync(hb, bad, sizeof hb, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hw, wstat, sizeof hw, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    double w[3];
+    std::memcpy(w, hw, sizeof w);
+    static const char* names[3] = {"u", "eps", "vx"};
+    for (int k = 0; k < 3; ++k)
+      if (hb[k]) return fail(BSE_ERR_NONFINITE, "system %zu: non-finite value in %s", i, names[k]);
+    if (!std::isfinite(w[0])) return fail(BSE_ERR_NONFINITE, "system %zu: non-finite value in W", i);
+    const double tol = 1e-10 * w[0];
+    if (w[1] > tol)
+      return fail(BSE_ERR_NOT_HERMITIAN, "system %zu: W(q) not Hermitian (deviation %.3e, max |W| %.3e)", i, w[1], w[0]);
+    if (w[2] > tol)
+      return fail(BSE_ERR_NOT_HERMITIAN, "system %zu: W violates time reversal (deviation %.3e, max |W| %.3e)", i, w[2],
+                  w[0]);
+  }
   return BSE_OK;
 }
 
@@ -816,7 +853,6 @@ int bse_build_H(const bse_system* sys, int nsys, int precision, int flags, void*
   if (!ws) return fail(BSE_ERR_INVALID_ARG, "workspace is NULL");
   if (precision < BSE_FP64 || precision > BSE_BF16X3) return fail(BSE_ERR_INVALID_ARG, "bad precision %d", precision);
   if (flags & ~(BSE_VALIDATE | BSE_PERSISTENT)) return fail(BSE_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
-  if (flags & BSE_VALIDATE) return fail(BSE_ERR_UNSUPPORTED, "BSE_VALIDATE is not implemented");
   for (int i = 0; i < nsys; ++i)
     if (!sys[i].H) return fail(BSE_ERR_INVALID_ARG, "H of system %d is NULL", i);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -830,6 +866,10 @@ int bse_build_H(const bse_system* sys, int nsys, int precision, int flags, void*
     if ((rc = make_batch(sys, nsys, false, tn, B))) return rc;
   }
   if (ws_bytes < B.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, B.total);
+  if (flags & BSE_VALIDATE) {
+    if ((rc = upload_batch(B, sys, precision, static_cast<char*>(ws), st))) return rc;
+    if ((rc = validate(B, sys, static_cast<char*>(ws), st))) return rc;
+  }
   return run_build(B, sys, precision, tn, static_cast<char*>(ws), st);
 }
 

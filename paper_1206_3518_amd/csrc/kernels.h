@@ -141,6 +141,12 @@ struct AdjArgs {
 struct GradCell {
   double b[3][3];
 };
+// BSE_VALIDATE scans: bad[0..2] get 1 on a non-finite value in u, eps, vx;
+// wstat[0..2] (zero on entry) the bit patterns of max |W|, max Hermiticity
+// deviation and max time-reversal deviation (abs(re) + abs(im) each).
+hipError_t launch_validate(const double* u, size_t nu, const double* eps, size_t ne, const double* vx, size_t nvx,
+                           const double2* W, const int* ng, const int* qbar, const int* trmap, int nk, int ng_max,
+                           int check_tr, unsigned* bad, unsigned long long* wstat, hipStream_t st);
 bool fft_len_supported(int N);
 hipError_t launch_grad(const double2* u, double2* scratch, int nk, int nb, int nv, int nc, int N1, int N2, int N3,
                        const GradCell& bc, double2* out, hipStream_t st);

@@ -96,3 +96,44 @@ def test_batch_rejects_mixed_grids_and_unknown_flags():
     with pytest.raises(P.BseError) as e:
         P.bse_build_H([da], P.BSE_FP64, 64, ws)
     assert e.value.code == -1  # BSE_ERR_INVALID_ARG
+
+
+def test_validate_flag():
+    import paper_1206_3518_amd as P
+    import torch
+    s = B.make_system(B.cell_sc(10.0), (16, 16, 16), (3, 1, 1), 2, 2, 3.0, seed=61)
+    d = P.DeviceSystem(s)
+    ws = P.workspace(P.bse_workspace_size([d]))
+    P.bse_build_H([d], P.BSE_FP64, 0, ws)
+    torch.cuda.synchronize()
+    ref = d.H.clone()
+    d.H.zero_()
+    P.bse_build_H([d], P.BSE_FP64, P.BSE_VALIDATE, ws)  # valid inputs: same H
+    torch.cuda.synchronize()
+    assert torch.equal(d.H, ref)
+    # a NaN in the wave functions
+    keep = d.u[1, 0, 5].clone()
+    d.u[1, 0, 5] = complex(float("nan"), 0.0)
+    with pytest.raises(P.BseError) as e:
+        P.bse_build_H([d], P.BSE_FP64, P.BSE_VALIDATE, ws)
+    assert e.value.code == -6 and "u" in str(e.value)
+    d.u[1, 0, 5] = keep
+    # W(q) made non-Hermitian in one entry
+    W0 = d.W.clone()
+    d.W[1, 2, 3] += 1e-3 * d.W.abs().max()
+    with pytest.raises(P.BseError) as e:
+        P.bse_build_H([d], P.BSE_FP64, P.BSE_VALIDATE, ws)
+    assert e.value.code == -5 and "Hermitian" in str(e.value)
+    # a Hermitian change at one q that breaks time reversal (on the 3 x 1 x 1
+    # mesh q = 1 and q = 2 are each other's partners)
+    d.W.copy_(W0)
+    z = 1e-3 * d.W.abs().max().item()
+    d.W[1, 2, 3] += z
+    d.W[1, 3, 2] += z
+    with pytest.raises(P.BseError) as e:
+        P.bse_build_H([d], P.BSE_FP64, P.BSE_VALIDATE, ws)
+    assert e.value.code == -5 and "time reversal" in str(e.value)
+    d.W.copy_(W0)
+    P.bse_build_H([d], P.BSE_FP64, P.BSE_VALIDATE, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(d.H, ref)
