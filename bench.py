@@ -153,6 +153,7 @@ def main():
     tuning = None
     if not args.no_autotune and not args.persistent:
         tuning = P.bse_autotune(devs, prec, None, ws)  # outside the timed region
+        tried = P.bse_autotune_last()
     ms, wall, stages = run_steps(P, devs, prec, flags, ws, args.steps, args.warmup)
     elements = float(sum(float(s.ns) ** 2 for s in systems))
     value = elements / (ms / 1e3)
@@ -194,6 +195,9 @@ def main():
                   "ng_max": [s.ng_max for s in systems], "nv": systems[0].nv, "nc": systems[0].nc,
                   "precision": args.precision, "parallelism": "single-gpu"}
     if tuning is not None:
+        config["autotune_candidates_ms"] = {
+            (f"persistent/{c['wg_per_cu']}" if c["persistent"] else f"static/k{c['ktile']}"): round(c["pd_ms"], 3)
+            for c in tried}
         config["dispatch"] = (f"autotuned: persistent, {tuning['wg_per_cu']} workgroups/CU" if tuning["persistent"]
                               else f"autotuned: static, k tile {tuning['ktile']}")
     else:

@@ -183,6 +183,11 @@ typedef struct bse_tuning {
 int bse_autotune(const bse_system *sys, int nsys, int precision, const char *cache_path, bse_tuning *chosen,
                  void *ws, size_t ws_bytes, void *stream);
 
+/* The candidates (with their times) that the last bse_autotune on this thread
+ * measured: writes up to max_tried entries to `tried` (HOST) and returns how
+ * many there were (0 after a cache hit), or a negative status. */
+int bse_autotune_last(bse_tuning *tried, int max_tried);
+
 /*
  * Absorption spectrum from the spectral representation of the irreducible
  * response (Sec. II.C, macroscopic dielectric function with Vbar; Tamm-Dancoff

@@ -46,7 +46,7 @@ class bse_system(ctypes.Structure):
 
 
 SYMBOLS = ["bse_workspace_size", "bse_pair_density", "bse_build_H", "bse_build_H_backward",
-           "bse_autotune", "bse_spectrum", "bse_profile", "bse_profile_read", "bse_last_error"]
+           "bse_autotune", "bse_autotune_last", "bse_spectrum", "bse_profile", "bse_profile_read", "bse_last_error"]
 STAGES = ["vscale", "pd_exch", "pd_vv", "pd_cc", "exchange", "direct1", "direct2", "mirror"]
 
 
@@ -68,6 +68,8 @@ def lib():
         L.bse_build_H_backward.restype = I
         L.bse_autotune.argtypes = [P, I, I, ctypes.c_char_p, P, P, S, P]
         L.bse_autotune.restype = I
+        L.bse_autotune_last.argtypes = [P, I]
+        L.bse_autotune_last.restype = I
         L.bse_spectrum.argtypes = [I, I, P, P, P, D, I, D, D, D, P, P, S, P]
         L.bse_spectrum.restype = I
         L.bse_profile.argtypes = [I]
@@ -180,6 +182,16 @@ def bse_autotune(systems, precision=BSE_FP64, cache_path=None, ws=None, stream=N
     _check(lib().bse_autotune(arr, len(systems), int(precision), path, ctypes.byref(out), _ptr(ws), ws.numel(),
                               _stream(stream)))
     return {"persistent": out.persistent, "ktile": out.ktile, "wg_per_cu": out.wg_per_cu, "pd_ms": out.pd_ms}
+
+
+def bse_autotune_last() -> list:
+    """The candidates the last bse_autotune (this thread) timed, with their times."""
+    arr = (bse_tuning * 32)()
+    n = lib().bse_autotune_last(arr, 32)
+    if n < 0:
+        raise BseError(n, bse_last_error())
+    return [{"persistent": arr[i].persistent, "ktile": arr[i].ktile, "wg_per_cu": arr[i].wg_per_cu,
+             "pd_ms": arr[i].pd_ms} for i in range(min(n, 32))]
 
 
 def bse_pair_density(system: DeviceSystem, kind, kpairs=None, ws=None, stream=None, cell=None):

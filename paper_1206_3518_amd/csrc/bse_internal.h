@@ -7,6 +7,31 @@
 
 namespace bse {
 
+// Global-memory access through pointers read from a table in memory (rather
+// than from the kernel arguments): the compiler treats those as generic and
+// emits flat accesses, which also wait on the LDS counter.  These casts give
+// global loads and stores.  gbl() is for scalar element types; complex
+// elements go through gld()/gst() on a builtin two-double vector.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gbl(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+typedef double gd2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 gld(const double2* p, size_t i) {
+  const gd2 v = ((const __attribute__((address_space(1))) gd2*)p)[i];
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void gst(double2* p, size_t i, double2 x) {
+  gd2 v;
+  v.x = x.x;
+  v.y = x.y;
+  ((__attribute__((address_space(1))) gd2*)p)[i] = v;
+}
+__device__ __forceinline__ int4 gld(const int4* p, size_t i) {
+  const int* q = reinterpret_cast<const int*>(p) + 4 * i;
+  return make_int4(gbl(q)[0], gbl(q)[1], gbl(q)[2], gbl(q)[3]);
+}
+
 // ---------------------------------------------------------------- complex
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }

@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void k_exchange(const GemmArgs* __restrict__ g
       for (int r = 0; r < 4; ++r) {
         const int row = r0 + wr * 32 + i * 16 + 4 * r + (lane >> 4);
         const int col = c0 + wc * 32 + j * 16 + (lane & 15);
-        if (row < g.ns && col < g.ns) g.H[(size_t)row * g.ns + col] = make_double2(s * cre[i][j][r], s * cim[i][j][r]);
+        if (row < g.ns && col < g.ns) gst(g.H, (size_t)row * g.ns + col, make_double2(s * cre[i][j][r], s * cim[i][j][r]));
       }
 }
 
@@ -47,9 +47,9 @@ __global__ __launch_bounds__(256) void k_direct_s1(const GemmArgs* __restrict__ 
   const S1Tile tl = tiles[blockIdx.x];
   const GemmArgs g = gs[tl.sys];
   const int nv2 = g.nv * g.nv;
-  const int row_base = g.qstart[tl.iq] * nv2;
-  const int rows = (g.qstart[tl.iq + 1] - g.qstart[tl.iq]) * nv2;
-  const int K = g.ng[tl.iq];
+  const int row_base = gbl(g.qstart)[tl.iq] * nv2;
+  const int rows = (gbl(g.qstart)[tl.iq + 1] - gbl(g.qstart)[tl.iq]) * nv2;
+  const int K = gbl(g.ng)[tl.iq];
   const double2* A = g.RV + (size_t)row_base * g.ng_max;
   const double2* Wq = g.W + (size_t)tl.iq * g.ng_max * g.ng_max;
   d4 cre[2][2], cim[2][2];
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void k_direct_s1(const GemmArgs* __restrict__ 
       for (int r = 0; r < 4; ++r) {
         const int row = r0 + wr * 32 + i * 16 + 4 * r + (lane >> 4);
         const int col = c0 + wc * 32 + j * 16 + (lane & 15);
-        if (row < rows && col < K) Z[(size_t)row * g.ng_max + col] = make_double2(cre[i][j][r], cim[i][j][r]);
+        if (row < rows && col < K) gst(Z, (size_t)row * g.ng_max + col, make_double2(cre[i][j][r], cim[i][j][r]));
       }
 }
 
@@ -91,17 +91,17 @@ __global__ __launch_bounds__(256) void k_direct_s2(const GemmArgs* __restrict__ 
   const int loc = item - d2off[sys];
   const int per = tiles_i * tiles_j;
   const int p = loc / per, ti = (loc % per) / tiles_j, tj = loc % tiles_j;
-  const int4 pr = g.pairs[p];
+  const int4 pr = gld(g.pairs, p);
   const int ka = pr.x, kb = pr.y;
-  const int K = g.ng[pr.z];
+  const int K = gbl(g.ng)[pr.z];
   const int ia = ti * 16 + (lane & 15), jb = tj * 16 + (lane & 15);
   const double2* zr = g.Z + ((size_t)p * nv2 + (ia < nv2 ? ia : 0)) * g.ng_max;
   const double2* cr = g.RC + ((size_t)p * nc2 + (jb < nc2 ? jb : 0)) * g.ng_max;
   d4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
   for (int k0 = 0; k0 < K; k0 += 4) {
     const int k = k0 + (lane >> 4);
-    const double2 a = (ia < nv2 && k < K) ? zr[k] : make_double2(0.0, 0.0);
-    const double2 b = (jb < nc2 && k < K) ? cr[k] : make_double2(0.0, 0.0);
+    const double2 a = (ia < nv2 && k < K) ? gld(zr, k) : make_double2(0.0, 0.0);
+    const double2 b = (jb < nc2 && k < K) ? gld(cr, k) : make_double2(0.0, 0.0);
     cre = mfma64(a.x, b.x, cre);
     cre = mfma64(-a.y, b.y, cre);
     cim = mfma64(a.x, b.y, cim);
@@ -115,11 +115,11 @@ __global__ __launch_bounds__(256) void k_direct_s2(const GemmArgs* __restrict__ 
       const int v = i / g.nv, v2 = i % g.nv, c = j / g.nc, c2 = j % g.nc;
       const size_t S = ((size_t)ka * g.nv + v) * g.nc + c;
       const size_t S2 = ((size_t)kb * g.nv + v2) * g.nc + c2;
-      double2 h = g.H[S * g.ns + S2];
+      double2 h = gld(g.H, S * g.ns + S2);
       h.x -= g.cpref * cre[r];
       h.y -= g.cpref * cim[r];
-      if (S == S2) h.x += g.eps[(size_t)ka * g.nb + g.nv + c] - g.eps[(size_t)ka * g.nb + v];
-      g.H[S * g.ns + S2] = h;
+      if (S == S2) h.x += gbl(g.eps)[(size_t)ka * g.nb + g.nv + c] - gbl(g.eps)[(size_t)ka * g.nb + v];
+      gst(g.H, S * g.ns + S2, h);
     }
   }
 }
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void k_mirror(const GemmArgs* __restrict__ gs,
 #pragma unroll
   for (int r = ty; r < 32; r += 8) {
     const int sr = bj * 32 + r, sc = bi * 32 + tx;
-    tile[r][tx] = (sr < ns && sc < ns) ? H[(size_t)sr * ns + sc] : make_double2(0.0, 0.0);
+    tile[r][tx] = (sr < ns && sc < ns) ? gld(H, (size_t)sr * ns + sc) : make_double2(0.0, 0.0);
   }
   __syncthreads();
 #pragma unroll
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256) void k_mirror(const GemmArgs* __restrict__ gs,
     const int dr = bi * 32 + r, dc = bj * 32 + tx;
     if (dr < ns && dc < ns && dr / nt > dc / nt) {
       const double2 v = tile[tx][r];
-      H[(size_t)dr * ns + dc] = make_double2(v.x, -v.y);
+      gst(H, (size_t)dr * ns + dc, make_double2(v.x, -v.y));
     }
   }
 }

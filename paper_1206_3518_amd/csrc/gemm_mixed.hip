@@ -31,7 +31,7 @@ __global__ __launch_bounds__(256) void k_exchange_mx(const GemmArgs* __restrict_
         const int row = r0 + wr * 32 + i * 16 + acc_row(lane, r);
         const int col = c0 + wc * 32 + j * 16 + (lane & 15);
         if (row < g.ns && col < g.ns)
-          g.H[(size_t)row * g.ns + col] = make_double2(s * (double)cre[i][j][r], s * (double)cim[i][j][r]);
+          gst(g.H, (size_t)row * g.ns + col, make_double2(s * (double)cre[i][j][r], s * (double)cim[i][j][r]));
       }
 }
 
@@ -40,9 +40,9 @@ __global__ __launch_bounds__(256) void k_direct_s1_mx(const GemmArgs* __restrict
   const S1Tile tl = tiles[blockIdx.x];
   const GemmArgs g = gs[tl.sys];
   const int nv2 = g.nv * g.nv;
-  const int row_base = g.qstart[tl.iq] * nv2;
-  const int rows = (g.qstart[tl.iq + 1] - g.qstart[tl.iq]) * nv2;
-  const int K = g.ng[tl.iq];
+  const int row_base = gbl(g.qstart)[tl.iq] * nv2;
+  const int rows = (gbl(g.qstart)[tl.iq + 1] - gbl(g.qstart)[tl.iq]) * nv2;
+  const int K = gbl(g.ng)[tl.iq];
   const double2* A = g.RV + (size_t)row_base * g.ng_max;
   const double2* Wq = g.W + (size_t)tl.iq * g.ng_max * g.ng_max;
   f4 cre[2][2], cim[2][2];
@@ -60,7 +60,7 @@ __global__ __launch_bounds__(256) void k_direct_s1_mx(const GemmArgs* __restrict
         const int row = r0 + wr * 32 + i * 16 + acc_row(lane, r);
         const int col = c0 + wc * 32 + j * 16 + (lane & 15);
         if (row < rows && col < K)
-          Z[(size_t)row * g.ng_max + col] = make_double2((double)cre[i][j][r], (double)cim[i][j][r]);
+          gst(Z, (size_t)row * g.ng_max + col, make_double2((double)cre[i][j][r], (double)cim[i][j][r]));
       }
 }
 
@@ -80,9 +80,9 @@ __global__ __launch_bounds__(256) void k_direct_s2_mx(const GemmArgs* __restrict
   const int loc = item - d2off[sys];
   const int per = tiles_i * tiles_j;
   const int p = loc / per, ti = (loc % per) / tiles_j, tj = loc % tiles_j;
-  const int4 pr = g.pairs[p];
+  const int4 pr = gld(g.pairs, p);
   const int ka = pr.x, kb = pr.y;
-  const int K = g.ng[pr.z];
+  const int K = gbl(g.ng)[pr.z];
   const int ia = ti * 16 + (lane & 15), jb = tj * 16 + (lane & 15);
   const bool va = ia < nv2, vb = jb < nc2;
   const double2* zr = g.Z + ((size_t)p * nv2 + (va ? ia : 0)) * g.ng_max;
@@ -94,8 +94,8 @@ __global__ __launch_bounds__(256) void k_direct_s2_mx(const GemmArgs* __restrict
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const int k = k0 + 8 * (lane >> 4) + i;
-        const double2 x = (va && k < K) ? zr[k] : make_double2(0.0, 0.0);
-        const double2 y = (vb && k < K) ? cr[k] : make_double2(0.0, 0.0);
+        const double2 x = (va && k < K) ? gld(zr, k) : make_double2(0.0, 0.0);
+        const double2 y = (vb && k < K) ? gld(cr, k) : make_double2(0.0, 0.0);
         unsigned short h, l;
         Split<P>::split(x.x, h, l); a[0][i] = (short)h; a[1][i] = (short)l;
         Split<P>::split(x.y, h, l); a[2][i] = (short)h; a[3][i] = (short)l;
@@ -119,8 +119,8 @@ __global__ __launch_bounds__(256) void k_direct_s2_mx(const GemmArgs* __restrict
   } else {
     for (int k0 = 0; k0 < K; k0 += 4) {
       const int k = k0 + (lane >> 4);
-      const double2 x = (va && k < K) ? zr[k] : make_double2(0.0, 0.0);
-      const double2 y = (vb && k < K) ? cr[k] : make_double2(0.0, 0.0);
+      const double2 x = (va && k < K) ? gld(zr, k) : make_double2(0.0, 0.0);
+      const double2 y = (vb && k < K) ? gld(cr, k) : make_double2(0.0, 0.0);
       float a[4], b[4];
       Split<P>::split(x.x, a[0], a[1]);
       Split<P>::split(x.y, a[2], a[3]);
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void k_direct_s2_mx(const GemmArgs* __restrict
   }
   // FP64 head of W at q = 0 (left out of both mixed GEMMs)
   const bool head = pr.z == 0 && g.w_head_fp64;
-  const double2 w00 = head ? g.W[0] : make_double2(0.0, 0.0);
+  const double2 w00 = head ? gld(g.W, 0) : make_double2(0.0, 0.0);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = ti * 16 + acc_row(lane, r);
@@ -150,8 +150,8 @@ __global__ __launch_bounds__(256) void k_direct_s2_mx(const GemmArgs* __restrict
     if (i < nv2 && j < nc2) {
       double dr = (double)dre[r], di = (double)dim[r];
       if (head) {
-        const double2 rv0 = g.RV[((size_t)p * nv2 + i) * g.ng_max];
-        const double2 rc0 = g.RC[((size_t)p * nc2 + j) * g.ng_max];
+        const double2 rv0 = gld(g.RV, ((size_t)p * nv2 + i) * g.ng_max);
+        const double2 rc0 = gld(g.RC, ((size_t)p * nc2 + j) * g.ng_max);
         const double2 hw = cmul(cconjmul(rv0, w00), rc0);
         dr += hw.x;
         di += hw.y;
@@ -159,11 +159,11 @@ __global__ __launch_bounds__(256) void k_direct_s2_mx(const GemmArgs* __restrict
       const int v = i / g.nv, v2 = i % g.nv, c = j / g.nc, c2 = j % g.nc;
       const size_t S = ((size_t)ka * g.nv + v) * g.nc + c;
       const size_t S2 = ((size_t)kb * g.nv + v2) * g.nc + c2;
-      double2 h = g.H[S * g.ns + S2];
+      double2 h = gld(g.H, S * g.ns + S2);
       h.x -= g.cpref * dr;
       h.y -= g.cpref * di;
-      if (S == S2) h.x += g.eps[(size_t)ka * g.nb + g.nv + c] - g.eps[(size_t)ka * g.nb + v];
-      g.H[S * g.ns + S2] = h;
+      if (S == S2) h.x += gbl(g.eps)[(size_t)ka * g.nb + g.nv + c] - gbl(g.eps)[(size_t)ka * g.nb + v];
+      gst(g.H, S * g.ns + S2, h);
     }
   }
 }

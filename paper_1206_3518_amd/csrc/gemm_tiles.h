@@ -23,6 +23,10 @@ constexpr int TM = 64, TN = 64, KC = 16;
 // B[k][n] = Bm[k * ldb + b_off + n]     (B_T: Bm[(b_off + n) * ldb + k]), valid b_off + n < b_lim;
 // valid k < K.  The result lands in cre/cim (f64 MFMA accumulator layout).
 // ZERO = false adds to the accumulators instead of starting from zero.
+// Each thread stages 4 elements of A and 4 of B per K chunk; the next chunk's
+// elements are loaded into registers while the MFMAs consume the current one
+// (out-of-range elements are read from the array start and replaced by zero,
+// so the loads need no branches).
 template <bool CONJ_A, bool B_T, bool A_T = false, bool ZERO = true>
 __device__ __forceinline__ void tile_gemm(const double2* __restrict__ A, int lda, int a_off, int a_lim,
                                           const double2* __restrict__ B, int ldb, int b_off, int b_lim, int K,
@@ -40,50 +44,71 @@ __device__ __forceinline__ void tile_gemm(const double2* __restrict__ A, int lda
         cim[i][j] = d4{0, 0, 0, 0};
       }
   }
+  // this thread's staging positions: A (row ar, k ac + i) or, transposed,
+  // (k ak, rows am + i); B (k bk, cols bc + i) or, transposed, (col bn, k bkc + i)
+  const int ar = t >> 2, ac = (t & 3) * 4;
+  const int ak = t >> 4, am = (t & 15) * 4;
+  const int bk = t >> 4, bc = (t & 15) * 4;
+  const int bn = t >> 2, bkc = (t & 3) * 4;
+  double2 ra[4], rb[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      bool ok;
+      size_t idx;
+      if constexpr (!A_T) {
+        const int gr = a_off + ar, k = k0 + ac + i;
+        ok = gr < a_lim && k < K;
+        idx = (size_t)gr * lda + k;
+      } else {
+        const int m = a_off + am + i, k = k0 + ak;
+        ok = m < a_lim && k < K;
+        idx = (size_t)k * lda + m;
+      }
+      const double2 v = gld(A, ok ? idx : 0);
+      ra[i] = make_double2(ok ? v.x : 0.0, ok ? v.y : 0.0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      bool ok;
+      size_t idx;
+      if constexpr (B_T) {
+        const int gn = b_off + bn, k = k0 + bkc + i;
+        ok = gn < b_lim && k < K;
+        idx = (size_t)gn * ldb + k;
+      } else {
+        const int n = b_off + bc + i, k = k0 + bk;
+        ok = k < K && n < b_lim;
+        idx = (size_t)k * ldb + n;
+      }
+      const double2 v = gld(B, ok ? idx : 0);
+      rb[i] = make_double2(ok ? v.x : 0.0, ok ? v.y : 0.0);
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if constexpr (!A_T) {
+        As_re[ar][ac + i] = ra[i].x;
+        As_im[ar][ac + i] = CONJ_A ? -ra[i].y : ra[i].y;
+      } else {
+        As_re[am + i][ak] = ra[i].x;
+        As_im[am + i][ak] = CONJ_A ? -ra[i].y : ra[i].y;
+      }
+      if constexpr (B_T) {
+        Bs_re[bkc + i][bn] = rb[i].x;
+        Bs_im[bkc + i][bn] = rb[i].y;
+      } else {
+        Bs_re[bk][bc + i] = rb[i].x;
+        Bs_im[bk][bc + i] = rb[i].y;
+      }
+    }
+  };
+  if (K > 0) load(0);
   for (int k0 = 0; k0 < K; k0 += KC) {
-    if (!A_T) {  // A chunk: row t>>2, 4 consecutive k
-      const int r = t >> 2, c0 = (t & 3) * 4;
-      const int gr = a_off + r;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int k = k0 + c0 + i;
-        double2 v = (gr < a_lim && k < K) ? A[(size_t)gr * lda + k] : make_double2(0.0, 0.0);
-        As_re[r][c0 + i] = v.x;
-        As_im[r][c0 + i] = CONJ_A ? -v.y : v.y;
-      }
-    } else {  // k row t>>4, 4 consecutive m
-      const int kr = t >> 4, m0 = (t & 15) * 4;
-      const int k = k0 + kr;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int m = a_off + m0 + i;
-        double2 v = (m < a_lim && k < K) ? A[(size_t)k * lda + m] : make_double2(0.0, 0.0);
-        As_re[m0 + i][kr] = v.x;
-        As_im[m0 + i][kr] = CONJ_A ? -v.y : v.y;
-      }
-    }
-    if (B_T) {
-      const int n = t >> 2, c0 = (t & 3) * 4;
-      const int gn = b_off + n;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int k = k0 + c0 + i;
-        double2 v = (gn < b_lim && k < K) ? B[(size_t)gn * ldb + k] : make_double2(0.0, 0.0);
-        Bs_re[c0 + i][n] = v.x;
-        Bs_im[c0 + i][n] = v.y;
-      }
-    } else {
-      const int kr = t >> 4, c0 = (t & 15) * 4;
-      const int k = k0 + kr;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int n = c0 + i;
-        double2 v = (k < K && b_off + n < b_lim) ? B[(size_t)k * ldb + b_off + n] : make_double2(0.0, 0.0);
-        Bs_re[kr][n] = v.x;
-        Bs_im[kr][n] = v.y;
-      }
-    }
+    store();
     __syncthreads();
+    if (k0 + KC < K) load(k0 + KC);  // in flight during the MFMAs below
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       double are[2], aim[2], bre[2], bim[2];
@@ -191,34 +216,34 @@ __device__ __forceinline__ void tile_gemm_mx(const double2* __restrict__ A, int 
       cim[i][j] = f4{0, 0, 0, 0};
     }
   const int r = t >> 2, kq = (t & 3) * 8;
+  // the next chunk's operands are loaded while the MFMAs consume the current
+  // one; out-of-range elements are read from the array start and zeroed
+  double2 xa[8], xb[8];
+  auto load = [&](int k0) {
+    const int gr = a_off + r;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int k = k0 + kq + i;
+      const bool ok = gr < a_lim && k < K;
+      const size_t idx = A_T ? (size_t)k * lda + gr : (size_t)gr * lda + k;
+      const double2 v = gld(A, ok ? idx : 0);
+      xa[i] = make_double2(ok ? v.x : 0.0, ok ? v.y : 0.0);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int k = k0 + kq + i;
+      const bool ok = b_off + r < b_lim && k < K && !(zero_head && k == 0 && b_off + r == 0);
+      const size_t idx = B_T ? (size_t)(b_off + r) * ldb + k : (size_t)k * ldb + b_off + r;
+      const double2 v = gld(B, ok ? idx : 0);
+      xb[i] = make_double2(ok ? v.x : 0.0, ok ? v.y : 0.0);
+    }
+  };
+  if (K > 0) load(0);
   for (int k0 = 0; k0 < K; k0 += MKC) {
-    {
-      double2 x[8];
-      const int gr = a_off + r;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int k = k0 + kq + i;
-        if (A_T)
-          x[i] = (gr < a_lim && k < K) ? A[(size_t)k * lda + gr] : make_double2(0.0, 0.0);
-        else
-          x[i] = (gr < a_lim && k < K) ? A[(size_t)gr * lda + k] : make_double2(0.0, 0.0);
-      }
-      put8<P>(As, r, kq, x, CONJ_A);
-    }
-    {
-      double2 x[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int k = k0 + kq + i;
-        if (B_T)
-          x[i] = (b_off + r < b_lim && k < K) ? B[(size_t)(b_off + r) * ldb + k] : make_double2(0.0, 0.0);
-        else
-          x[i] = (b_off + r < b_lim && k < K) ? B[(size_t)k * ldb + b_off + r] : make_double2(0.0, 0.0);
-        if (zero_head && k == 0 && b_off + r == 0) x[i] = make_double2(0.0, 0.0);
-      }
-      put8<P>(Bs, r, kq, x, false);
-    }
+    put8<P>(As, r, kq, xa, CONJ_A);
+    put8<P>(Bs, r, kq, xb, false);
     __syncthreads();
+    if (k0 + MKC < K) load(k0 + MKC);
     if constexpr (P == BSE_BF16X3) {
       s8 a[2][4], b[2][4];
 #pragma unroll

@@ -73,8 +73,8 @@ __device__ __forceinline__ void pd_general_job(const PdArgs& a, const PdJob& job
   const int nA = job.nab & 255, nB = (job.nab >> 8) & 255;
   int m01, m02, m03;
   unpack_m(job.m0p, m01, m02, m03);
-  const int ngq = a.ng[job.iq];
-  const int* gq = a.gpack + (size_t)job.iq * ngm;
+  const int ngq = gbl(a.ng)[job.iq];
+  const auto* gq = gbl(a.gpack + (size_t)job.iq * ngm);
   // sphere point g: offset of (fA, fB) in the column-major window, f1 mod N1
   for (int g = threadIdx.x; g < ngq; g += blockDim.x) {
     int m1, m2, m3;
@@ -123,17 +123,17 @@ __device__ __forceinline__ void pd_general_job(const PdArgs& a, const PdJob& job
         const int base = poff + G::at(ok ? line : 0, lA);
         double2 yb[MA];
 #pragma unroll
-        for (int s = 0; s < MA; ++s) yb[s] = ub0[base + G::at(0, LA * s)];
+        for (int s = 0; s < MA; ++s) yb[s] = gld(ub0, base + G::at(0, LA * s));
 #pragma unroll
         for (int w = 0; w < PW; ++w) {
           const double2* ua = w == 0 ? ua0 : ua1;
           double2 x[MA];
           if (w == 1 && !share_b) {
 #pragma unroll
-            for (int s = 0; s < MA; ++s) yb[s] = ub1[base + G::at(0, LA * s)];
+            for (int s = 0; s < MA; ++s) yb[s] = gld(ub1, base + G::at(0, LA * s));
           }
 #pragma unroll
-          for (int s = 0; s < MA; ++s) x[s] = cconjmul(ua[base + G::at(0, LA * s)], yb[s]);
+          for (int s = 0; s < MA; ++s) x[s] = cconjmul(gld(ua, base + G::at(0, LA * s)), yb[s]);
           row_fft<NA, LA, MA>(x, lA, twA);
           double2* T1w = T1 + w * per_pd;
           static_for<0, MA>([&](auto fc) {
@@ -191,10 +191,10 @@ __device__ __forceinline__ void pd_general_job(const PdArgs& a, const PdJob& job
       for (int t = 0; t < TG; ++t) {
         const int g = lane + 64 * t;
         if (g < ngq) {
-          const double sc = EXCH ? a.vscale[g] : 1.0;
-          o[g] = make_double2(acc[w][t].x * sc, acc[w][t].y * sc);
+          const double sc = EXCH ? gbl(a.vscale)[g] : 1.0;
+          gst(o, g, make_double2(acc[w][t].x * sc, acc[w][t].y * sc));
         } else if (g < ngm) {
-          o[g] = make_double2(0.0, 0.0);
+          gst(o, g, make_double2(0.0, 0.0));
         }
       }
     }
@@ -215,7 +215,9 @@ __device__ __forceinline__ void pd_general_job(const PdArgs& a, const PdJob& job
 // Element i of a wave-uniform array, addressed by a 32-bit byte offset so that
 // the load takes the scalar-base + 32-bit vector-offset form.
 __device__ __forceinline__ double2 ldg(const double2* base, unsigned i) {
-  return *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(base) + (size_t)(i * 16u));
+  const auto* b = gbl(reinterpret_cast<const char*>(base));
+  const gd2 v = *(const __attribute__((address_space(1))) gd2*)(b + (size_t)(i * 16u));
+  return make_double2(v.x, v.y);
 }
 
 // Materialise every value of x here: stops the optimiser from sinking the
@@ -252,8 +254,8 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
   const int nA = job.nab & 255, nB = (job.nab >> 8) & 255;
   int m01, m02, m03;
   unpack_m(job.m0p, m01, m02, m03);
-  const int ngq = a.ng[job.iq];
-  const int* gq = a.gpack + (size_t)job.iq * ngm;
+  const int ngq = gbl(a.ng)[job.iq];
+  const auto* gq = gbl(a.gpack + (size_t)job.iq * ngm);
   // sphere point g: offset of (f2, f3) in the window, f1 mod N1
   for (int g = threadIdx.x; g < ngq; g += blockDim.x) {
     int m1, m2, m3;
@@ -297,16 +299,25 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
       // plane that pass 3 skips)
       {
         const unsigned off = (unsigned)((c < N3 ? c : 0) + (two ? j1 + h : j1) * (N2 * N3));
-        // even rows: load, multiply
+        // even rows: every load in flight before the first product
         double2 E[H2], O[H2];
+        {
+          double2 ra[H2], rb[H2];
 #pragma unroll
-        for (int s = 0; s < H2; ++s) E[s] = cconjmul(ldg(ua, off + 2 * s * N3), ldg(ub, off + 2 * s * N3));
+          for (int s = 0; s < H2; ++s) {
+            ra[s] = ldg(ua, off + 2 * s * N3);
+            rb[s] = ldg(ub, off + 2 * s * N3);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int s = 0; s < H2; ++s) E[s] = cconjmul(ra[s], rb[s]);
+        }
         __builtin_amdgcn_sched_barrier(0);
-        // first half of the odd rows in flight during the even-row FFT; the
-        // second half after it, so that at most half the odd rows sit in raw
-        // registers next to the even-row transform
+        // half of the odd rows in flight during the even-row FFT, the other
+        // half after it: at most half the odd rows sit in raw registers next
+        // to the even-row transform
         constexpr int HO = H2 / 2;
-        double2 ra[HO], rb[HO];
+        double2 ra[H2], rb[H2];
 #pragma unroll
         for (int s = 0; s < HO; ++s) {
           ra[s] = ldg(ua, off + (2 * s + 1) * N3);
@@ -316,9 +327,13 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
         reg_fft<H2, 1, 0>(E);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int s = 0; s < HO; ++s) O[s] = cconjmul(ra[s], rb[s]);
+        for (int s = HO; s < H2; ++s) {
+          ra[s] = ldg(ua, off + (2 * s + 1) * N3);
+          rb[s] = ldg(ub, off + (2 * s + 1) * N3);
+        }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int s = HO; s < H2; ++s) O[s] = cconjmul(ldg(ua, off + (2 * s + 1) * N3), ldg(ub, off + (2 * s + 1) * N3));
+        for (int s = 0; s < H2; ++s) O[s] = cconjmul(ra[s], rb[s]);
         __builtin_amdgcn_sched_barrier(0);
         reg_fft<H2, 1, 0>(O);
         pin(E);
@@ -387,10 +402,10 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
     for (int t = 0; t < TG; ++t) {
       const int g = lane + 64 * t;
       if (g < ngq) {
-        const double sc = EXCH ? a.vscale[g] : 1.0;
-        o[g] = make_double2(acc[t].x * sc, acc[t].y * sc);
+        const double sc = EXCH ? gbl(a.vscale)[g] : 1.0;
+        gst(o, g, make_double2(acc[t].x * sc, acc[t].y * sc));
       } else if (g < ngm) {
-        o[g] = make_double2(0.0, 0.0);
+        gst(o, g, make_double2(0.0, 0.0));
       }
     }
   }
