@@ -279,6 +279,43 @@ def make_system(cell, grid, kmesh, nv, nc, ecut, *, coulomb_kind="bulk", slab_L=
                   u=u, eps=eps, W=W, seed=seed)
 
 
+def tr_partner(sys: System, iq: int):
+    """Index bookkeeping of time reversal on the q mesh and the spheres:
+    (qbar, perm) with -q = qbar + t (t a lattice vector) and perm[g] the
+    index of t - m_g in the sphere of qbar (-1 if it is not there)."""
+    n = np.array(sys.kmesh)
+    iv = ktriplet(sys.kmesh, iq)
+    qb = (-iv) % n
+    t = (-iv - qb) // n
+    iqb = kindex(sys.kmesh, qb)
+    lut = {tuple(m): i for i, m in enumerate(sys.gvec[iqb, :sys.ng[iqb]])}
+    perm = np.array([lut.get(tuple(t - m), -1) for m in sys.gvec[iq, :sys.ng[iq]]])
+    return iqb, perm
+
+
+def symmetric_direction(sys: System, iq: int, g: int, h: int, z: complex) -> np.ndarray:
+    """A change of W that keeps it Hermitian and time-reversal symmetric:
+    z at (q, g, h), conj(z) at (q, h, g), and the conjugate images at the
+    time-reversal partner; each distinct (entry, conjugated) image once, so
+    an entry that is its own image gets z + conj(z) (an imaginary z there
+    gives a zero direction)."""
+    D = np.zeros_like(sys.W)
+    for (q, a, b), v in symmetric_entries(sys, iq, g, h, z).items():
+        D[q, a, b] = v
+    return D
+
+
+def symmetric_entries(sys: System, iq: int, g: int, h: int, z: complex) -> dict:
+    """The non-zero entries {(q, g, g'): value} of ``symmetric_direction``."""
+    iqb, perm = tr_partner(sys, iq)
+    images = {(iq, g, h, False), (iq, h, g, True), (iqb, int(perm[g]), int(perm[h]), True),
+              (iqb, int(perm[h]), int(perm[g]), False)}
+    out = {}
+    for q, a, b, cj in images:
+        out[(q, a, b)] = out.get((q, a, b), 0.0) + (np.conj(z) if cj else z)
+    return {k: v for k, v in out.items() if v != 0}
+
+
 # ----------------------------------------------------------------------------
 # the named workloads
 
