@@ -288,6 +288,19 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
 #pragma unroll
     for (int t = 0; t < TG; ++t) acc[t] = make_double2(0.0, 0.0);
 
+    // even rows of a plane pair (lane: column c of plane j1 + h): issued one
+    // plane pair ahead, so that their latency hides behind pass 3
+    const int col = c < N3 ? c : 0;
+    double2 pa[H2], pb[H2];
+    auto load_even = [&](int jj) {
+      const unsigned o = (unsigned)(col + (jj + 1 < N1 ? jj + h : jj) * (N2 * N3));
+#pragma unroll
+      for (int s = 0; s < H2; ++s) {
+        pa[s] = ldg(ua, o + 2 * s * N3);
+        pb[s] = ldg(ub, o + 2 * s * N3);
+      }
+    };
+    load_even(0);
     for (int j1 = 0; j1 < N1; j1 += 2) {
       const bool two = j1 + 1 < N1;  // the second plane exists
       // window masks and origins re-read per plane: kept loop-invariant they
@@ -298,20 +311,10 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
       // ---- pass 1 (idle lanes load a valid column and write padding or a
       // plane that pass 3 skips)
       {
-        const unsigned off = (unsigned)((c < N3 ? c : 0) + (two ? j1 + h : j1) * (N2 * N3));
-        // even rows: every load in flight before the first product
+        const unsigned off = (unsigned)(col + (two ? j1 + h : j1) * (N2 * N3));
         double2 E[H2], O[H2];
-        {
-          double2 ra[H2], rb[H2];
 #pragma unroll
-          for (int s = 0; s < H2; ++s) {
-            ra[s] = ldg(ua, off + 2 * s * N3);
-            rb[s] = ldg(ub, off + 2 * s * N3);
-          }
-          __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-          for (int s = 0; s < H2; ++s) E[s] = cconjmul(ra[s], rb[s]);
-        }
+        for (int s = 0; s < H2; ++s) E[s] = cconjmul(pa[s], pb[s]);
         __builtin_amdgcn_sched_barrier(0);
         // half of the odd rows in flight during the even-row FFT, the other
         // half after it: at most half the odd rows sit in raw registers next
@@ -378,6 +381,10 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
         });
       }
       wave_sync();
+      // next plane pair, in flight during pass 3 (unconditional, so that the
+      // values just consumed are dead; the last pair re-reads a valid plane)
+      load_even(j1 + 2 < N1 ? j1 + 2 : j1);
+      __builtin_amdgcn_sched_barrier(0);
       // ---- pass 3
 #pragma unroll
       for (int t = 0; t < TG; ++t) {
