@@ -27,8 +27,9 @@
  *     allocates no device memory.
  *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
  *     on it and the call returns; the caller synchronises.  Host-side plan
- *     tables are uploaded with a copy that blocks the calling thread until
- *     the stream has consumed them.
+ *     tables go to the workspace by asynchronous copies from a pinned host
+ *     staging buffer that the library keeps per calling thread; the next
+ *     call on that thread waits for those copies before reusing it.
  *   - A non-zero return means nothing was enqueued (argument errors) or that
  *     a HIP call failed; bse_last_error() gives text for the calling thread.
  *   - Calls on one device that share a workspace must not overlap.

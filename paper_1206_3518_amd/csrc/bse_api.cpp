@@ -40,6 +40,46 @@ int fail(int code, const char* fmt, ...) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// ------------------------------------------------------------ table uploads
+// Plan tables go to the device by asynchronous copies from a pinned staging
+// buffer (one per thread, grown as needed, kept for the life of the process),
+// so the stream does not stall behind a pageable copy.  Before the buffer is
+// rewritten, the copies of the previous call are waited for.
+struct Staging {
+  char* buf = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+};
+thread_local Staging g_staging;
+
+// Returns a host buffer of n bytes that no pending copy reads.
+int staging_acquire(size_t n, char** out) {
+  Staging& S = g_staging;
+  if (S.pending) {
+    HIP_TRY(hipEventSynchronize(S.done));
+    S.pending = false;
+  }
+  if (!S.done) HIP_TRY(hipEventCreateWithFlags(&S.done, hipEventDisableTiming));
+  if (n > S.cap) {
+    if (S.buf) HIP_TRY(hipHostFree(S.buf));
+    S.buf = nullptr;
+    S.cap = 0;
+    const size_t want = std::max(n, size_t(1) << 20);
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&S.buf), want, hipHostMallocDefault));
+    S.cap = want;
+  }
+  *out = S.buf;
+  return BSE_OK;
+}
+
+// Marks the staging buffer as read by the copies just enqueued on st.
+int staging_release(hipStream_t st) {
+  HIP_TRY(hipEventRecord(g_staging.done, st));
+  g_staging.pending = true;
+  return BSE_OK;
+}
+
 // ------------------------------------------------------------ stage timing
 struct ProfRec {
   int stage;
@@ -508,12 +548,74 @@ int make_batch(const bse_system* sys, int nsys, bool backward, const Tune& tn, B
   return BSE_OK;
 }
 
+// Key of everything the host plan of a batch depends on: shapes, sphere
+// tables (hashed by content), the backward flag and the k tile.
+std::string plan_key(const bse_system* sys, int nsys, bool backward, int ktile) {
+  std::string k = std::to_string(nsys) + (backward ? "b" : "f") + std::to_string(ktile);
+  for (int i = 0; i < nsys; ++i) {
+    const bse_system& s = sys[i];
+    const int nk = s.kmesh[0] * s.kmesh[1] * s.kmesh[2];
+    unsigned long long h = 1469598103934665603ull;  // FNV-1a over the host tables
+    auto mix = [&](const void* p, size_t n) {
+      const unsigned char* b = static_cast<const unsigned char*>(p);
+      for (size_t j = 0; j < n; ++j) h = (h ^ b[j]) * 1099511628211ull;
+    };
+    if (s.ng) mix(s.ng, sizeof(int) * (size_t)std::max(nk, 0));
+    if (s.gvec && s.ng_max > 0) mix(s.gvec, sizeof(int) * 3 * (size_t)std::max(nk, 0) * s.ng_max);
+    char b[200];
+    snprintf(b, sizeof b, "|%d,%d,%d:%d,%d,%d:%d,%d:%d:%llx", s.grid[0], s.grid[1], s.grid[2], s.kmesh[0],
+             s.kmesh[1], s.kmesh[2], s.nv, s.nc, s.ng_max, h);
+    k += b;
+  }
+  return k;
+}
+
+// The last host plan built on this thread: a repeated build of the same batch
+// shape skips planning.
+struct PlanCache {
+  std::string key;
+  Batch B;
+};
+thread_local PlanCache g_plan;
+
+// make_batch through the cache.
+int cached_batch(const bse_system* sys, int nsys, bool backward, const Tune& tn, const Batch** out) {
+  if (nsys < 1 || !sys) return fail(BSE_ERR_INVALID_ARG, "no systems");
+  for (int i = 0; i < nsys; ++i) {
+    int rc = check_system(&sys[i]);
+    if (rc) return rc;
+  }
+  const std::string key = plan_key(sys, nsys, backward, tn.ktile);
+  if (key != g_plan.key) {
+    Batch B;
+    int rc = make_batch(sys, nsys, backward, tn, B);
+    if (rc) {
+      g_plan.key.clear();
+      return rc;
+    }
+    g_plan.B = std::move(B);
+    g_plan.key = key;
+  }
+  *out = &g_plan.B;
+  return BSE_OK;
+}
+
 // Uploads every table of the batch (one blocking copy).
 int upload_batch(const Batch& B, const bse_system* sys, int precision, char* ws, hipStream_t st) {
   const int nsys = (int)B.P.size();
-  std::vector<char> buf(B.o_cnt, 0);  // batch tables
+  // staging image: the batch tables, then each system's own tables
+  size_t n = B.o_cnt;
+  std::vector<size_t> at(nsys);
+  for (int i = 0; i < nsys; ++i) {
+    at[i] = n;
+    n += B.P[i].tables;
+  }
+  char* buf = nullptr;
+  int rc = staging_acquire(n, &buf);
+  if (rc) return rc;
+  std::memset(buf, 0, n);
   auto cp = [&](size_t off, const void* src, size_t bytes) {
-    if (bytes) std::memcpy(buf.data() + off, src, bytes);
+    if (bytes) std::memcpy(buf + off, src, bytes);
   };
   std::vector<PdArgs> ax(nsys), av(nsys), ac(nsys);
   std::vector<GemmArgs> ga(nsys);
@@ -542,14 +644,16 @@ int upload_batch(const Batch& B, const bse_system* sys, int precision, char* ws,
   cp(B.o_xt, B.xt.data(), B.xt.size() * sizeof(HTile));
   cp(B.o_mt, B.mt.data(), B.mt.size() * sizeof(HTile));
   cp(B.o_d2off, B.d2off.data(), B.d2off.size() * sizeof(int));
-  HIP_TRY(hipMemcpyWithStream(ws, buf.data(), B.o_cnt, hipMemcpyHostToDevice, st));
-  // each system's own tables sit at the start of its region
+  std::vector<char> tb;
   for (int i = 0; i < nsys; ++i) {
-    std::vector<char> tb(B.P[i].tables, 0);
+    tb.assign(B.P[i].tables, 0);
     put_tables(B.P[i], tb, 0);
-    HIP_TRY(hipMemcpyWithStream(ws + B.base[i], tb.data(), tb.size(), hipMemcpyHostToDevice, st));
+    cp(at[i], tb.data(), tb.size());
   }
-  return BSE_OK;
+  HIP_TRY(hipMemcpyAsync(ws, buf, B.o_cnt, hipMemcpyHostToDevice, st));
+  for (int i = 0; i < nsys; ++i)
+    HIP_TRY(hipMemcpyAsync(ws + B.base[i], buf + at[i], B.P[i].tables, hipMemcpyHostToDevice, st));
+  return staging_release(st);
 }
 
 // Workgroups of a persistent pair-density launch: wg_per_cu per CU, fewer if
@@ -840,12 +944,15 @@ int bse_pair_density(const bse_system* sys, int kind, const int* kpairs, int npa
   a.F3 = P.F[2];
   a.vscale = nullptr;
   a.out = reinterpret_cast<double2*>(out);
-  std::vector<char> buf(need, 0);
-  std::memcpy(buf.data() + o_g, P.gpack.data(), P.gpack.size() * sizeof(int));
-  std::memcpy(buf.data() + o_n, P.ng.data(), P.ng.size() * sizeof(int));
-  std::memcpy(buf.data() + o_a, &a, sizeof(PdArgs));
-  if (!jobs.empty()) std::memcpy(buf.data() + o_j, jobs.data(), jobs.size() * sizeof(PdJob));
-  HIP_TRY(hipMemcpyWithStream(w, buf.data(), need, hipMemcpyHostToDevice, st));
+  char* buf = nullptr;
+  if ((rc = staging_acquire(need, &buf))) return rc;
+  std::memset(buf, 0, need);
+  std::memcpy(buf + o_g, P.gpack.data(), P.gpack.size() * sizeof(int));
+  std::memcpy(buf + o_n, P.ng.data(), P.ng.size() * sizeof(int));
+  std::memcpy(buf + o_a, &a, sizeof(PdArgs));
+  if (!jobs.empty()) std::memcpy(buf + o_j, jobs.data(), jobs.size() * sizeof(PdJob));
+  HIP_TRY(hipMemcpyAsync(w, buf, need, hipMemcpyHostToDevice, st));
+  if ((rc = staging_release(st))) return rc;
   PdBatch b{};
   b.sys = reinterpret_cast<const PdArgs*>(w + o_a);
   b.jobs = reinterpret_cast<const PdJob*>(w + o_j);
@@ -864,15 +971,13 @@ int bse_build_H(const bse_system* sys, int nsys, int precision, int flags, void*
   for (int i = 0; i < nsys; ++i)
     if (!sys[i].H) return fail(BSE_ERR_INVALID_ARG, "H of system %d is NULL", i);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  Batch B;
-  int rc = make_batch(sys, nsys, false, Tune{}, B);
+  const Batch* Bp = nullptr;
+  int rc = cached_batch(sys, nsys, false, Tune{}, &Bp);
   if (rc) return rc;
-  Tune tn = tune_for(batch_key(B.P, precision));
+  Tune tn = tune_for(batch_key(Bp->P, precision));
   if (flags & BSE_PERSISTENT) tn.persist = 1;
-  if (tn.ktile != Tune{}.ktile) {
-    B = Batch{};
-    if ((rc = make_batch(sys, nsys, false, tn, B))) return rc;
-  }
+  if (tn.ktile != Tune{}.ktile && (rc = cached_batch(sys, nsys, false, tn, &Bp))) return rc;
+  const Batch& B = *Bp;
   if (ws_bytes < B.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, B.total);
   if (flags & BSE_VALIDATE) {
     if ((rc = upload_batch(B, sys, precision, static_cast<char*>(ws), st))) return rc;
