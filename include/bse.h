@@ -221,7 +221,9 @@ enum bse_stage {
     BSE_STAGE_DIRECT1 = 5,  /* direct term, conj(rho_vv') W(q)          */
     BSE_STAGE_DIRECT2 = 6,  /* direct term contraction + diagonal       */
     BSE_STAGE_MIRROR = 7,   /* lower blocks from the upper ones         */
-    BSE_NSTAGES = 8
+    BSE_STAGE_ROTATE = 8,   /* wave functions transposed for grids whose
+                               long axis is last (pair-density frame)    */
+    BSE_NSTAGES = 9
 };
 int bse_profile(int enable);
 int bse_profile_read(double *total_ms, long long *launches, int nstages, int reset);

@@ -158,6 +158,14 @@ std::vector<PdJob> dispatch_order(std::vector<PdJob> jobs, int ktile) {
 }
 
 struct Plan {
+  // N1, N2, N3 and every Miller index, shift and window below are in the
+  // pair-density frame: frame axis d is grid axis ax[d].  The frame is the
+  // grid itself unless the planes N2 x N3 are too long for the one-lane-per-
+  // line kernel while N1 x N2 planes are not; then the axes are rotated,
+  // (j1, j2, j3) -> (j3, j1, j2), and the wave functions are transposed once
+  // per build into the workspace (o_ut).
+  int ax[3] = {0, 1, 2};
+  bool rot = false;
   int N1 = 0, N2 = 0, N3 = 0, nk = 0, nv = 0, nc = 0, nb = 0, ng_max = 0, ns = 0, nt = 0;
   int lo[3] = {0, 0, 0}, F[3] = {0, 0, 0};
   std::vector<int> gpack, ng;
@@ -177,6 +185,7 @@ struct Plan {
   size_t o_dwt = 0, o_rvt = 0, o_plex = 0, o_qbar = 0, o_trmap = 0;
   size_t tables = 0, o_vs = 0, o_X = 0, o_RV = 0, o_RC = 0, o_Z = 0, o_dWraw = 0, total = 0;
   size_t fwd_total = 0;  // region needed by the forward build (no dW scratch)
+  size_t o_ut = 0;       // rotated wave functions (rot only; in the forward part)
 };
 
 int check_system(const bse_system* s) {
@@ -185,7 +194,7 @@ int check_system(const bse_system* s) {
     if (s->grid[d] < 1 || s->grid[d] > 4096) return fail(BSE_ERR_SHAPE, "grid[%d] = %d out of range", d, s->grid[d]);
     if (s->kmesh[d] < 1 || s->kmesh[d] > 1024) return fail(BSE_ERR_SHAPE, "kmesh[%d] = %d out of range", d, s->kmesh[d]);
   }
-  if (!pd_grid_supported(s->grid[1], s->grid[2]))
+  if (!pd_grid_supported(s->grid[1], s->grid[2]) && !(pd_line_grid(s->grid[0], s->grid[1]) && s->grid[2] <= 256))
     return fail(BSE_ERR_SHAPE, "grid (N2, N3) = (%d, %d) has no FFT kernel", s->grid[1], s->grid[2]);
   if (s->nv < 1 || s->nc < 1 || s->nv > 255 || s->nc > 255) return fail(BSE_ERR_SHAPE, "nv/nc out of range");
   if (s->ng_max < 1 || s->ng_max > 1024) return fail(BSE_ERR_SHAPE, "ng_max = %d out of range (1..1024)", s->ng_max);
@@ -198,9 +207,15 @@ int check_system(const bse_system* s) {
 int make_plan(const bse_system* s, Plan& P) {
   int rc = check_system(s);
   if (rc) return rc;
-  P.N1 = s->grid[0];
-  P.N2 = s->grid[1];
-  P.N3 = s->grid[2];
+  P.rot = !pd_line_grid(s->grid[1], s->grid[2]) && pd_line_grid(s->grid[0], s->grid[1]) && s->grid[2] <= 256;
+  if (P.rot) {
+    P.ax[0] = 2;
+    P.ax[1] = 0;
+    P.ax[2] = 1;
+  }
+  P.N1 = s->grid[P.ax[0]];
+  P.N2 = s->grid[P.ax[1]];
+  P.N3 = s->grid[P.ax[2]];
   P.nk = s->kmesh[0] * s->kmesh[1] * s->kmesh[2];
   P.nv = s->nv;
   P.nc = s->nc;
@@ -218,11 +233,12 @@ int make_plan(const bse_system* s, Plan& P) {
     for (int g = 0; g < P.ng[q]; ++g) {
       const int* m = s->gvec + ((size_t)q * P.ng_max + g) * 3;
       for (int d = 0; d < 3; ++d) {
-        if (m[d] < -500 || m[d] > 500) return fail(BSE_ERR_SHAPE, "Miller index out of range");
-        mlo[d] = std::min(mlo[d], m[d]);
-        mhi[d] = std::max(mhi[d], m[d]);
+        const int md = m[P.ax[d]];
+        if (md < -500 || md > 500) return fail(BSE_ERR_SHAPE, "Miller index out of range");
+        mlo[d] = std::min(mlo[d], md);
+        mhi[d] = std::max(mhi[d], md);
       }
-      P.gpack[(size_t)q * P.ng_max + g] = pack_m(m[0], m[1], m[2]);
+      P.gpack[(size_t)q * P.ng_max + g] = pack_m(m[P.ax[0]], m[P.ax[1]], m[P.ax[2]]);
     }
   }
   if (s->gvec[0] != 0 || s->gvec[1] != 0 || s->gvec[2] != 0)
@@ -231,7 +247,7 @@ int make_plan(const bse_system* s, Plan& P) {
   const int N[3] = {P.N1, P.N2, P.N3};
   for (int d = 0; d < 3; ++d) {
     P.lo[d] = mlo[d];
-    const int hi = mhi[d] + (s->kmesh[d] > 1 ? 1 : 0);
+    const int hi = mhi[d] + (s->kmesh[P.ax[d]] > 1 ? 1 : 0);
     P.F[d] = hi - P.lo[d] + 1;
     if (P.F[d] > N[d])
       return fail(BSE_ERR_SHAPE, "G-sphere window %d exceeds grid %d along axis %d", P.F[d], N[d], d);
@@ -243,7 +259,7 @@ int make_plan(const bse_system* s, Plan& P) {
     for (int kb = ka; kb < P.nk; ++kb) {
       int iq, m0[3];
       fold(s->kmesh, ka, kb, iq, m0);
-      byq[iq].push_back(make_int4(ka, kb, iq, pack_m(m0[0], m0[1], m0[2])));
+      byq[iq].push_back(make_int4(ka, kb, iq, pack_m(m0[P.ax[0]], m0[P.ax[1]], m0[P.ax[2]])));
     }
   P.qstart.assign(P.nk + 1, 0);
   P.pairs.clear();
@@ -330,7 +346,7 @@ int make_plan(const bse_system* s, Plan& P) {
       for (int g = 0; g < P.ng[q]; ++g) {
         int m1, m2, m3;
         unpack_m(P.gpack[(size_t)q * P.ng_max + g], m1, m2, m3);
-        const int want = pack_m(tt[0] - m1, tt[1] - m2, tt[2] - m3);
+        const int want = pack_m(tt[P.ax[0]] - m1, tt[P.ax[1]] - m2, tt[P.ax[2]] - m3);
         const auto& sv = sorted[iqb];
         const auto it = std::lower_bound(sv.begin(), sv.end(), std::make_pair(want, -1));
         const int found = (it != sv.end() && it->first == want) ? it->second : -1;
@@ -362,6 +378,7 @@ int make_plan(const bse_system* s, Plan& P) {
   P.o_RV = put((size_t)np * P.nv * P.nv * P.ng_max * sizeof(double2));
   P.o_RC = put((size_t)np * P.nc * P.nc * P.ng_max * sizeof(double2));
   P.o_Z = put((size_t)np * P.nv * P.nv * P.ng_max * sizeof(double2));
+  if (P.rot) P.o_ut = put((size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * sizeof(double2));
   P.fwd_total = o;
   P.o_dWraw = put((size_t)P.nk * P.ng_max * P.ng_max * sizeof(double2));
   P.total = o;
@@ -387,7 +404,7 @@ void put_tables(const Plan& P, std::vector<char>& buf, size_t base) {
 
 PdArgs pd_args(const Plan& P, const bse_system* s, char* region) {
   PdArgs a{};
-  a.u = reinterpret_cast<const double2*>(s->u);
+  a.u = P.rot ? reinterpret_cast<const double2*>(region + P.o_ut) : reinterpret_cast<const double2*>(s->u);
   a.nb = P.nb;
   a.N1 = P.N1;
   a.gpack = reinterpret_cast<const int*>(region + P.o_gpack);
@@ -690,6 +707,16 @@ int run_pd(const Batch& B, char* ws, int kind, const Tune& tn, hipStream_t st) {
   return BSE_OK;
 }
 
+// Wave functions in the pair-density frame, for systems whose axes are rotated.
+int rotate_if_needed(const Plan& P, const bse_system& s, char* region, hipStream_t st) {
+  if (!P.rot) return BSE_OK;
+  HIP_TRY(stage(BSE_STAGE_ROTATE, st, [&] {
+    return launch_rotate_axes(reinterpret_cast<const double2*>(s.u), reinterpret_cast<double2*>(region + P.o_ut),
+                              (long long)P.nk * P.nb, s.grid[0], s.grid[1], s.grid[2], st);
+  }));
+  return BSE_OK;
+}
+
 // The forward build of every system of the batch, one launch per stage
 // (the sqrt v tables aside, one small launch per system).
 int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& tn, char* ws, hipStream_t st) {
@@ -700,6 +727,7 @@ int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& 
     const Plan& P = B.P[i];
     double* vs = reinterpret_cast<double*>(ws + B.base[i] + P.o_vs);
     HIP_TRY(stage(BSE_STAGE_VSCALE, st, [&] { return launch_vscale(sys[i].vx, P.ng[0], P.ng_max, vs, st); }));
+    if ((rc = rotate_if_needed(P, sys[i], ws + B.base[i], st))) return rc;
   }
   for (int kind = 0; kind < 3; ++kind)
     if ((rc = run_pd(B, ws, kind, tn, st))) return rc;
@@ -889,12 +917,14 @@ int bse_pair_density(const bse_system* sys, int kind, const int* kpairs, int npa
       if (ka < 0 || kb < 0 || ka >= P.nk || kb >= P.nk) return fail(BSE_ERR_INVALID_ARG, "k pair %d out of range", i);
       int iq, m0[3];
       fold(sys->kmesh, ka, kb, iq, m0);
-      jobs.push_back(PdJob{ka, kb, pack_m(m0[0], m0[1], m0[2]), iq, b0, b0, nA | (nA << 8), i * nA * nA});
+      jobs.push_back(PdJob{ka, kb, pack_m(m0[P.ax[0]], m0[P.ax[1]], m0[P.ax[2]]), iq, b0, b0, nA | (nA << 8),
+                           i * nA * nA});
     }
   } else if (kind == BSE_PD_DIPOLE) {
     if (!cell) return fail(BSE_ERR_INVALID_ARG, "cell is NULL (needed for the dipole kind)");
-    if (!fft_len_supported(P.N1) || !fft_len_supported(P.N2) || !fft_len_supported(P.N3))
-      return fail(BSE_ERR_SHAPE, "grid (%d, %d, %d) has no full-grid FFT", P.N1, P.N2, P.N3);
+    const int G1 = sys->grid[0], G2 = sys->grid[1], G3 = sys->grid[2];  // grid order, not the pair-density frame
+    if (!fft_len_supported(G1) || !fft_len_supported(G2) || !fft_len_supported(G3))
+      return fail(BSE_ERR_SHAPE, "grid (%d, %d, %d) has no full-grid FFT", G1, G2, G3);
     if (P.nc > 8) return fail(BSE_ERR_SHAPE, "dipoles support at most 8 conduction bands");
     const size_t need = (size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * sizeof(double2);
     if (ws_bytes < need) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
@@ -916,7 +946,7 @@ int bse_pair_density(const bse_system* sys, int kind, const int* kpairs, int npa
     bc.b[2][1] = tp * (A[2] * A[3] - A[0] * A[5]);
     bc.b[2][2] = tp * (A[0] * A[4] - A[1] * A[3]);
     HIP_TRY(launch_grad(reinterpret_cast<const double2*>(sys->u), static_cast<double2*>(ws), P.nk, P.nb, P.nv, P.nc,
-                        P.N1, P.N2, P.N3, bc, reinterpret_cast<double2*>(out), st));
+                        G1, G2, G3, bc, reinterpret_cast<double2*>(out), st));
     return BSE_OK;
   } else {
     return fail(BSE_ERR_INVALID_ARG, "unknown kind %d", kind);
@@ -928,11 +958,16 @@ int bse_pair_density(const bse_system* sys, int kind, const int* kpairs, int npa
   const size_t o_g = 0, o_n = align256(P.gpack.size() * sizeof(int));
   const size_t o_a = align256(o_n + P.ng.size() * sizeof(int));
   const size_t o_j = align256(o_a + sizeof(PdArgs));
-  const size_t need = align256(o_j + jobs.size() * sizeof(PdJob));
+  const size_t tab = align256(o_j + jobs.size() * sizeof(PdJob));
+  const size_t ut_bytes = P.rot ? (size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * sizeof(double2) : 0;
+  const size_t need = tab + ut_bytes;  // tables, then the rotated wave functions
   if (ws_bytes < need) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
   char* w = static_cast<char*>(ws);
+  if (P.rot)
+    HIP_TRY(launch_rotate_axes(reinterpret_cast<const double2*>(sys->u), reinterpret_cast<double2*>(w + tab),
+                               (long long)P.nk * P.nb, sys->grid[0], sys->grid[1], sys->grid[2], st));
   PdArgs a{};
-  a.u = reinterpret_cast<const double2*>(sys->u);
+  a.u = P.rot ? reinterpret_cast<const double2*>(w + tab) : reinterpret_cast<const double2*>(sys->u);
   a.nb = P.nb;
   a.N1 = P.N1;
   a.gpack = reinterpret_cast<const int*>(w + o_g);
@@ -945,13 +980,13 @@ int bse_pair_density(const bse_system* sys, int kind, const int* kpairs, int npa
   a.vscale = nullptr;
   a.out = reinterpret_cast<double2*>(out);
   char* buf = nullptr;
-  if ((rc = staging_acquire(need, &buf))) return rc;
-  std::memset(buf, 0, need);
+  if ((rc = staging_acquire(tab, &buf))) return rc;
+  std::memset(buf, 0, tab);
   std::memcpy(buf + o_g, P.gpack.data(), P.gpack.size() * sizeof(int));
   std::memcpy(buf + o_n, P.ng.data(), P.ng.size() * sizeof(int));
   std::memcpy(buf + o_a, &a, sizeof(PdArgs));
   if (!jobs.empty()) std::memcpy(buf + o_j, jobs.data(), jobs.size() * sizeof(PdJob));
-  HIP_TRY(hipMemcpyAsync(w, buf, need, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(w, buf, tab, hipMemcpyHostToDevice, st));
   if ((rc = staging_release(st))) return rc;
   PdBatch b{};
   b.sys = reinterpret_cast<const PdArgs*>(w + o_a);
@@ -1005,6 +1040,7 @@ int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, do
   if ((rc = upload_batch(B, sys, precision, w, st))) return rc;
   // recompute the pair densities (exchange ones only for dX)
   char* r = w + B.base[0];
+  if ((rc = rotate_if_needed(P, *sys, r, st))) return rc;
   if (dX) {
     double* vs = reinterpret_cast<double*>(r + P.o_vs);
     HIP_TRY(launch_vscale(sys->vx, P.ng[0], P.ng_max, vs, st));

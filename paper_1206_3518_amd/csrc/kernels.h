@@ -42,6 +42,10 @@ struct PdBatch {
 };
 
 bool pd_grid_supported(int N2, int N3);
+// planes N2 x N3 that the one-lane-per-line kernel takes (both even, <= 32)
+bool pd_line_grid(int N2, int N3);
+// ut[g][j3][j1][j2] = u[g][j1][j2][j3] for ngrids grids of N1 x N2 x N3 (N1, N2 <= 32)
+hipError_t launch_rotate_axes(const double2* u, double2* ut, long long ngrids, int N1, int N2, int N3, hipStream_t st);
 size_t pd_lds_bytes(int N1, int N2, int N3, int F2, int F3, int ng_max);
 // ng_max: the largest of the batch; lds: the largest pd_lds_bytes of the
 // batch; exch: exchange rows (every system's vscale set); grid: njobs for

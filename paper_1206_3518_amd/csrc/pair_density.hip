@@ -527,6 +527,40 @@ bool pd_grid_supported(int N2, int N3) {
          (N2 == 24 && N3 == 96) || (N2 == 12 && N3 == 16) || (N2 == 16 && N3 == 24);
 }
 
+bool pd_line_grid(int N2, int N3) {
+  return pd_grid_supported(N2, N3) && N2 <= 32 && N3 <= 32 && N2 % 2 == 0 && N3 % 2 == 0;
+}
+
+// One workgroup per (grid, j1) plane: the N2 x N3 plane through LDS, written
+// as rows j2 of the slabs j3.
+__global__ __launch_bounds__(256) void k_rotate_axes(const double2* __restrict__ u, double2* __restrict__ ut, int N1,
+                                                     int N2, int N3) {
+  extern __shared__ double2 tile[];  // [N2][N3 + 1]
+  const long long gj = blockIdx.x;
+  const long long g = gj / N1;
+  const int j1 = (int)(gj % N1);
+  const int n = N2 * N3, S = N3 + 1;
+  const double2* src = u + (size_t)(g * N1 + j1) * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) tile[(i / N3) * S + i % N3] = src[i];
+  __syncthreads();
+  double2* dst = ut + (size_t)g * N1 * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int j3 = i / N2, j2 = i % N2;
+    dst[((size_t)j3 * N1 + j1) * N2 + j2] = tile[j2 * S + j3];
+  }
+}
+
+hipError_t launch_rotate_axes(const double2* u, double2* ut, long long ngrids, int N1, int N2, int N3,
+                              hipStream_t st) {
+  const size_t lds = sizeof(double2) * (size_t)N2 * (N3 + 1);
+  if (ngrids <= 0) return hipSuccess;
+  if (lds > 160 * 1024 || ngrids * N1 > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute((const void*)k_rotate_axes, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rotate_axes, dim3((unsigned)(ngrids * N1)), dim3(256), lds, st, u, ut, N1, N2, N3);
+  return hipGetLastError();
+}
+
 size_t pd_lds_bytes(int N1, int N2, int N3, int F2, int F3, int ng_max) {
 #define BSE_PD_LDS(X, Y) \
   if (N2 == X && N3 == Y) return lds_bytes<X, Y>(N1, F2, F3, ng_max);

@@ -66,7 +66,7 @@ def test_workspace_size_and_host_errors():
     assert rc == -1
     # unsupported grid
     st2, keep2 = _fake_struct(P, s)
-    st2.grid[2] = 20
+    st2.grid[0] = st2.grid[1] = st2.grid[2] = 20  # no plane kernel, directly or with rotated axes
     assert L.bse_build_H(ctypes.byref(st2), 1, 0, 0, ctypes.c_void_p(0x1000), n, None) == -2
     # null input pointer
     st3, keep3 = _fake_struct(P, s)

@@ -49,13 +49,15 @@ def _pd_case(s, rng, npairs=24):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("case", ["cfg0", "cfg1", "ragged"])
+@pytest.mark.parametrize("case", ["cfg0", "cfg1", "ragged", "hbn"])
 def test_pair_densities_match_oracle(case):
     rng = np.random.default_rng(1)
     if case == "cfg0":
         s = B.make_config(0)
     elif case == "cfg1":
         s = B.make_config(1)
+    elif case == "hbn":  # long last axis: the pair densities run on the rotated grid
+        s = B.make_hbn_batch(5, nsys=1, ecut=2.0, nv=2, nc=2, meshes=[3])[0]
     else:  # non-cubic grid, odd mesh, nv != nc
         s = B.make_system(B.cell_fcc(7.5), (10, 12, 16), (3, 1, 2), 3, 2, 3.0, seed=21)
     _say(f"pair densities {case}: grid {s.grid} kmesh {s.kmesh} ng_max {s.ng_max}")
