@@ -24,12 +24,14 @@ def _cmp(tag, got, ref):
     assert err <= 1e-12 * scale
 
 
-@pytest.mark.parametrize("case", ["cfg0", "ragged"])
+@pytest.mark.parametrize("case", ["cfg0", "ragged", "hbn"])
 def test_density_gradients_match_oracle(case):
     import paper_1206_3518_amd as P
     import torch
     if case == "cfg0":
         s = B.make_config(0)
+    elif case == "hbn":  # rotated pair-density frame
+        s = B.make_hbn_batch(5, nsys=1, ecut=1.5, nv=2, nc=2, meshes=[2])[0]
     else:
         s = B.make_system(B.cell_fcc(7.5), (10, 12, 16), (3, 1, 2), 3, 2, 3.0, seed=21)
     d = P.DeviceSystem(s)
