@@ -217,6 +217,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner (default dispatch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the split-FP32 / BF16x3 comparison runs")
+    ap.add_argument("--no-time-reversal", action="store_true",
+                    help="skip the run on time-reversal symmetric inputs with BSE_TIME_REVERSAL")
     ap.add_argument("--gradcheck", action="store_true",
                     help="instead of timing: finite differences of the lowest exciton energy vs the adjoint")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -328,9 +330,33 @@ def main():
                            "gemm": gemm_report(stm, name)}
         out["mixed"] = mixed
         del H64
+    if not args.no_time_reversal:
+        del devs, ws
+        out["time_reversal"] = time_reversal_leg(P, args, prec, flags, elements, ms)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(systems[0])
     print(json.dumps(out))
+
+
+def time_reversal_leg(P, args, prec, flags, elements, ms_general):
+    """The same workload with wave functions that obey time reversal, built
+    with BSE_TIME_REVERSAL (half the pair-density transforms, the rest
+    gathered) and once without it for comparison (untimed)."""
+    import torch
+    import bse_synth as B
+    made = B.make_config(args.config, time_reversal=True)
+    systems = made if isinstance(made, list) else [made]
+    devs = [P.DeviceSystem(s, device="cuda:0") for s in systems]
+    ws = P.workspace(P.bse_workspace_size(devs, prec), devs[0].device)
+    P.bse_build_H(devs, prec, flags, ws)
+    torch.cuda.synchronize()
+    Hg = [d.H.clone() for d in devs]
+    ms, _, stages = run_steps(P, devs, prec, flags | P.BSE_TIME_REVERSAL, ws, args.steps, args.warmup)
+    dH = max((d.H - h).abs().max().item() for d, h in zip(devs, Hg))
+    return {"value": elements / (ms / 1e3), "unit": "H elements/s", "ms_per_step": ms,
+            "speedup_vs_general": ms_general / ms, "max_abs_dH_vs_general_eV": dH,
+            "stage_ms": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
+            "inputs": "same shapes and generator, u at -k the time-reversal image of u at k"}
 
 
 if __name__ == "__main__":

@@ -171,7 +171,11 @@ def ktriplet(kmesh, k):
 
 def make_system(cell, grid, kmesh, nv, nc, ecut, *, coulomb_kind="bulk", slab_L=0.0,
                 head_factor=0.1, seed=1206, name="custom", wf="gaussian", wf_ecut=None,
-                ss: Optional[np.random.SeedSequence] = None) -> System:
+                time_reversal=False, ss: Optional[np.random.SeedSequence] = None) -> System:
+    """A synthetic system.  With ``time_reversal`` the wave functions and band
+    energies obey time reversal without spin-orbit coupling: for kbar the mesh
+    point of -k, -k = kbar - K with K a lattice vector (``k_partner``), and
+    u_{n,kbar}(r_j) = exp(-i K . r_j) conj(u_{n,k}(r_j)), eps_{n,kbar} = eps_{n,k}."""
     cell = np.asarray(cell, dtype=np.float64)
     grid = tuple(int(x) for x in grid)
     kmesh = tuple(int(x) for x in kmesh)
@@ -208,27 +212,44 @@ def make_system(cell, grid, kmesh, nv, nc, ecut, *, coulomb_kind="bulk", slab_L=
     # wave functions
     u = np.empty((nk, nb, nr), dtype=np.complex128)
     kids = ss_wf.spawn(nk)
+    if wf == "bandlimited":
+        msph = gsphere(cell, np.zeros(3), wf_ecut)
+    elif wf != "gaussian":
+        raise ValueError(wf)
     for k in range(nk):
+        kb, K = k_partner(kmesh, k)
+        if time_reversal and kb < k:
+            u[k] = u_partner(u[kb], grid, K)
+            continue
         rng = np.random.Generator(np.random.PCG64(kids[k]))
         if wf == "gaussian":
             z = rng.standard_normal((nr, nb)) + 1j * rng.standard_normal((nr, nb))
-        elif wf == "bandlimited":
+        else:
             # random coefficients on a small sphere of plane waves, then inverse DFT
-            msph = gsphere(cell, np.zeros(3), wf_ecut)
             c = rng.standard_normal((len(msph), nb)) + 1j * rng.standard_normal((len(msph), nb))
             spec = np.zeros(grid + (nb,), dtype=np.complex128)
             spec[msph[:, 0] % grid[0], msph[:, 1] % grid[1], msph[:, 2] % grid[2]] = c
             z = np.fft.ifftn(spec, axes=(0, 1, 2)).reshape(nr, nb)
+        if time_reversal and kb == k:
+            # u = exp(-i K.r / 2) y with y real satisfies the relation at its own partner
+            half = np.sqrt(tr_phase(grid, K))
+            y = np.real(z * np.conj(half)[:, None])
+            q, _ = np.linalg.qr(y)
+            u[k] = (q * half[:, None]).T
         else:
-            raise ValueError(wf)
-        q, _ = np.linalg.qr(z)
-        u[k] = q.T
+            q, _ = np.linalg.qr(z)
+            u[k] = q.T
 
     # energies
     rng = np.random.Generator(np.random.PCG64(ss_eps))
     eps = np.empty((nk, nb))
     eps[:, :nv] = rng.uniform(-3.0, 0.0, size=(nk, nv))
     eps[:, nv:] = rng.uniform(1.0, 4.0, size=(nk, nc))
+    if time_reversal:
+        for k in range(nk):
+            kb, _ = k_partner(kmesh, k)
+            if kb < k:
+                eps[k] = eps[kb]
 
     # screened interaction, one representative per time-reversal orbit
     W = np.zeros((nk, ng_max, ng_max), dtype=np.complex128)
@@ -277,6 +298,26 @@ def make_system(cell, grid, kmesh, nv, nc, ecut, *, coulomb_kind="bulk", slab_L=
     return System(name=name, cell=cell, grid=grid, kmesh=kmesh, nv=nv, nc=nc, ecut=ecut,
                   coulomb=coulomb_kind, slab_L=slab_L, head=head, ng=ng, gvec=gvec, vx=vx,
                   u=u, eps=eps, W=W, seed=seed)
+
+
+def k_partner(kmesh, k: int):
+    """(kbar, K): kbar the mesh index of -k, K the integer triplet with
+    -k = kbar - K in units of the mesh (each entry 0 or 1)."""
+    n = np.array(kmesh)
+    iv = ktriplet(kmesh, k)
+    kb = (-iv) % n
+    return kindex(kmesh, kb), (kb + iv) // n
+
+
+def tr_phase(grid, K) -> np.ndarray:
+    """exp(-i K . r_j) on the grid points r_j = j / N (flattened like u)."""
+    j = np.indices(grid).reshape(3, -1).T
+    return np.exp(-2j * np.pi * (j @ (np.asarray(K, dtype=np.float64) / np.array(grid))))
+
+
+def u_partner(uk: np.ndarray, grid, K) -> np.ndarray:
+    """Wave functions at kbar from those at k under time reversal: [nb, nr]."""
+    return np.conj(uk) * tr_phase(grid, K)[None, :]
 
 
 def tr_partner(sys: System, iq: int):
@@ -360,7 +401,7 @@ def hbn_draws(seed: int, nsys: int = 16) -> List[int]:
 
 
 def make_hbn_batch(seed: int, nsys: int = 16, grid=(24, 24, 96), ecut=9.0, nv=4, nc=4,
-                   meshes: Optional[Sequence[int]] = None) -> List[System]:
+                   meshes: Optional[Sequence[int]] = None, time_reversal=False) -> List[System]:
     ss = np.random.SeedSequence(seed)
     _, _, _, ss_sys = ss.spawn(4)
     kids = ss_sys.spawn(nsys)
@@ -371,5 +412,5 @@ def make_hbn_batch(seed: int, nsys: int = 16, grid=(24, 24, 96), ecut=9.0, nv=4,
         n = int(meshes[s])
         out.append(make_system(cell_hex(A_HBN, C_HBN), grid, (n, n, 1), nv, nc, ecut,
                                coulomb_kind="slab", slab_L=C_HBN, seed=seed,
-                               name=f"hbn{s}-k{n}", ss=kids[s]))
+                               name=f"hbn{s}-k{n}", ss=kids[s], time_reversal=time_reversal))
     return out

@@ -51,7 +51,9 @@ enum bse_status {
     BSE_ERR_HIP = -4,          /* a HIP runtime call failed                      */
     BSE_ERR_NOT_HERMITIAN = -5,/* BSE_VALIDATE: W(q) violates Hermiticity / TR   */
     BSE_ERR_NONFINITE = -6,    /* BSE_VALIDATE: NaN or Inf in an input           */
-    BSE_ERR_UNSUPPORTED = -7   /* mode not implemented                           */
+    BSE_ERR_UNSUPPORTED = -7,  /* mode not implemented                           */
+    BSE_ERR_NOT_SYMMETRIC = -8 /* BSE_VALIDATE with BSE_TIME_REVERSAL: u is not
+                                  time-reversal symmetric                        */
 };
 
 /* Arithmetic of the two dense contractions (exchange and direct term).
@@ -71,8 +73,23 @@ enum bse_flags {
                             1e-10 max|W| (|re| + |im| of the difference)
                             -> BSE_ERR_NOT_HERMITIAN                             */
     BSE_PERSISTENT = 2,  /* build a batch of systems with one persistent launch   */
-    BSE_PROJECT_DW = 4   /* backward: project dW onto Hermitian, time-reversal
+    BSE_PROJECT_DW = 4,  /* backward: project dW onto Hermitian, time-reversal
                             symmetric W (group average of Sec. III.A, T = 1)     */
+    BSE_TIME_REVERSAL = 8  /* bse_build_H: the inputs obey time reversal without
+                            spin-orbit coupling.  For kbar the mesh point of -k,
+                            with -k = kbar - K (K a lattice vector, entries 0 or
+                            1 in units of the mesh), u_{n,kbar}(r_j) =
+                            exp(-i K.r_j) conj(u_{n,k}(r_j)), r_j = j/N per axis.
+                            Then the pair densities of a k pair follow from those
+                            of its image (kbar, kbar') (Sec. III.A, the pair-
+                            density transformation with time reversal): of each
+                            pair and its image only one is transformed, the other
+                            is gathered from it (conjugate on the sphere map of
+                            W, or the two bands exchanged).  The G spheres must
+                            be closed under that map (else BSE_ERR_SHAPE).  With
+                            BSE_VALIDATE the relation of u is checked to
+                            1e-10 max|u| (else BSE_ERR_NOT_SYMMETRIC); without
+                            it, inputs that break it give a wrong H            */
 };
 
 enum bse_pd_kind {
@@ -106,7 +123,8 @@ typedef struct bse_system {
 } bse_system;
 
 /* Bytes of device workspace that bse_build_H / bse_pair_density /
- * bse_build_H_backward need for these systems, precision and flags. */
+ * bse_build_H_backward need for these systems, with or without
+ * BSE_TIME_REVERSAL (precision and flags are not used). */
 size_t bse_workspace_size(const bse_system *sys, int nsys, int precision, int flags);
 
 /*
@@ -223,7 +241,9 @@ enum bse_stage {
     BSE_STAGE_MIRROR = 7,   /* lower blocks from the upper ones         */
     BSE_STAGE_ROTATE = 8,   /* wave functions transposed for grids whose
                                long axis is last (pair-density frame)    */
-    BSE_NSTAGES = 9
+    BSE_STAGE_TR_FILL = 9,  /* BSE_TIME_REVERSAL: pair densities of the
+                               image pairs                               */
+    BSE_NSTAGES = 10
 };
 int bse_profile(int enable);
 int bse_profile_read(double *total_ms, long long *launches, int nstages, int reset);

@@ -20,7 +20,7 @@ _LIB = None
 
 BSE_OK = 0
 BSE_FP64, BSE_SPLIT_FP32, BSE_BF16X3 = 0, 1, 2
-BSE_VALIDATE, BSE_PERSISTENT = 1, 2
+BSE_VALIDATE, BSE_PERSISTENT, BSE_TIME_REVERSAL = 1, 2, 8
 BSE_PD_EXCH, BSE_PD_VV, BSE_PD_CC, BSE_PD_DIPOLE = 0, 1, 2, 3
 PRECISIONS = {"fp64": BSE_FP64, "split_fp32": BSE_SPLIT_FP32, "bf16x3": BSE_BF16X3}
 HARTREE_EV = 27.211386245988
@@ -47,7 +47,7 @@ class bse_system(ctypes.Structure):
 
 SYMBOLS = ["bse_workspace_size", "bse_pair_density", "bse_build_H", "bse_build_H_backward",
            "bse_autotune", "bse_autotune_last", "bse_spectrum", "bse_profile", "bse_profile_read", "bse_last_error"]
-STAGES = ["vscale", "pd_exch", "pd_vv", "pd_cc", "exchange", "direct1", "direct2", "mirror", "rotate"]
+STAGES = ["vscale", "pd_exch", "pd_vv", "pd_cc", "exchange", "direct1", "direct2", "mirror", "rotate", "tr_fill"]
 
 
 def lib():

@@ -180,9 +180,14 @@ struct Plan {
   std::vector<int> plex;   // lexicographic position of each pair among k <= k'
   std::vector<int> qbar, trmap;
   bool tr_closed = true;
+  // time reversal: per k, kbar | K << 24 (grid axes); the vv / cc jobs of the
+  // pairs that are computed, and (dst, src, mode, -) for their images
+  std::vector<int> ktr;
+  std::vector<PdJob> jv_tr, jc_tr;
+  std::vector<int4> trfill;
   // byte offsets inside the system's region of the workspace
   size_t o_gpack = 0, o_ng = 0, o_pairs = 0, o_qstart = 0;
-  size_t o_dwt = 0, o_rvt = 0, o_plex = 0, o_qbar = 0, o_trmap = 0;
+  size_t o_dwt = 0, o_rvt = 0, o_plex = 0, o_qbar = 0, o_trmap = 0, o_ktr = 0;
   size_t tables = 0, o_vs = 0, o_X = 0, o_RV = 0, o_RC = 0, o_Z = 0, o_dWraw = 0, total = 0;
   size_t fwd_total = 0;  // region needed by the forward build (no dW scratch)
   size_t o_ut = 0;       // rotated wave functions (rot only; in the forward part)
@@ -356,6 +361,39 @@ int make_plan(const bse_system* s, Plan& P) {
     }
   }
 
+  // time reversal on the k mesh: -k = kbar - K, and the image of each pair
+  // (k, k'): (kbar, kbar') if kbar <= kbar' (conjugate, sphere map of
+  // qbar), else (kbar', kbar) (bands exchanged).  Of a pair and its image the
+  // lower index is computed; pairs that are their own image are computed.
+  P.ktr.assign(P.nk, 0);
+  {
+    const int* n = s->kmesh;
+    for (int k = 0; k < P.nk; ++k) {
+      const int iv[3] = {k / (n[1] * n[2]), (k / n[2]) % n[1], k % n[2]};
+      int kb[3], bits = 0;
+      for (int d = 0; d < 3; ++d) {
+        kb[d] = imod(-iv[d], n[d]);
+        bits |= ((kb[d] + iv[d]) / n[d]) << (24 + d);
+      }
+      P.ktr[k] = ((kb[0] * n[1] + kb[1]) * n[2] + kb[2]) | bits;
+    }
+    std::vector<int> lex2p(np);
+    for (int p = 0; p < np; ++p) lex2p[P.plex[p]] = p;
+    P.jv_tr.clear();
+    P.jc_tr.clear();
+    P.trfill.clear();
+    for (int p = 0; p < np; ++p) {
+      const int x = P.ktr[P.pairs[p].x] & 0xffffff, y = P.ktr[P.pairs[p].y] & 0xffffff;
+      const int mode = x <= y ? 0 : 1;
+      const long long a = std::min(x, y), b = std::max(x, y);
+      const int img = lex2p[a * P.nk - a * (a - 1) / 2 + (b - a)];
+      if (img < p) continue;  // derived from its image
+      P.jv_tr.push_back(P.jv[p]);
+      P.jc_tr.push_back(P.jc[p]);
+      if (img != p) P.trfill.push_back(make_int4(img, p, mode, 0));
+    }
+  }
+
   // workspace layout
   size_t o = 0;
   auto put = [&](size_t bytes) {
@@ -372,6 +410,7 @@ int make_plan(const bse_system* s, Plan& P) {
   P.o_plex = put(P.plex.size() * sizeof(int));
   P.o_qbar = put(P.qbar.size() * sizeof(int));
   P.o_trmap = put(P.trmap.size() * sizeof(int));
+  P.o_ktr = put(P.ktr.size() * sizeof(int));
   P.tables = o;
   P.o_vs = put((size_t)P.ng_max * sizeof(double));
   P.o_X = put((size_t)P.ns * P.ng_max * sizeof(double2));
@@ -400,6 +439,7 @@ void put_tables(const Plan& P, std::vector<char>& buf, size_t base) {
   cp(P.o_plex, P.plex.data(), P.plex.size() * sizeof(int));
   cp(P.o_qbar, P.qbar.data(), P.qbar.size() * sizeof(int));
   cp(P.o_trmap, P.trmap.data(), P.trmap.size() * sizeof(int));
+  cp(P.o_ktr, P.ktr.data(), P.ktr.size() * sizeof(int));
 }
 
 PdArgs pd_args(const Plan& P, const bse_system* s, char* region) {
@@ -496,12 +536,15 @@ struct Batch {
   std::vector<HTile> xt, mt;
   std::vector<int> d2off;
   int d2n = 0;
+  bool tr = false;             // pair densities of time-reversal images derived
+  std::vector<int4> fill;      // (dst, src, mode, sys)
   size_t o_pdx = 0, o_pdv = 0, o_pdc = 0, o_gargs = 0, o_jx = 0, o_jv = 0, o_jc = 0, o_s1 = 0, o_xt = 0, o_mt = 0;
-  size_t o_d2off = 0, o_cnt = 0, tables = 0, total = 0;
+  size_t o_d2off = 0, o_cnt = 0, o_tra = 0, o_fill = 0, tables = 0, total = 0;
 };
 
-int make_batch(const bse_system* sys, int nsys, bool backward, const Tune& tn, Batch& B) {
+int make_batch(const bse_system* sys, int nsys, bool backward, const Tune& tn, bool tr, Batch& B) {
   if (!sys || nsys < 1) return fail(BSE_ERR_INVALID_ARG, "no systems");
+  B.tr = tr;
   if (nsys > 32767) return fail(BSE_ERR_INVALID_ARG, "too many systems");
   B.P.resize(nsys);
   for (int i = 0; i < nsys; ++i) {
@@ -519,6 +562,8 @@ int make_batch(const bse_system* sys, int nsys, bool backward, const Tune& tn, B
     const size_t l = pd_lds_bytes(P.N1, P.N2, P.N3, P.F[1], P.F[2], P.ng_max);
     if (l > 160 * 1024) return fail(BSE_ERR_SHAPE, "FFT window of system %d needs more than 160 KiB of LDS", i);
     B.lds = std::max(B.lds, l);
+    if (tr && !P.tr_closed)
+      return fail(BSE_ERR_SHAPE, "system %d: time reversal needs G spheres closed under G -> t - G (qbar = -q - t)", i);
   }
   // merged lists
   std::vector<PdJob> jx, jv, jc;
@@ -526,8 +571,10 @@ int make_batch(const bse_system* sys, int nsys, bool backward, const Tune& tn, B
   for (int i = 0; i < nsys; ++i) {
     const Plan& P = B.P[i];
     for (PdJob j : P.jx) jx.push_back((j.nab |= i << 16, j));
-    for (PdJob j : P.jv) jv.push_back((j.nab |= i << 16, j));
-    for (PdJob j : P.jc) jc.push_back((j.nab |= i << 16, j));
+    for (PdJob j : tr ? P.jv_tr : P.jv) jv.push_back((j.nab |= i << 16, j));
+    for (PdJob j : tr ? P.jc_tr : P.jc) jc.push_back((j.nab |= i << 16, j));
+    if (tr)
+      for (int4 f : P.trfill) B.fill.push_back((f.w = i, f));
     for (S1Tile s : P.s1) B.s1.push_back((s.sys = i, s));
     for (HTile h : P.xt) B.xt.push_back((h.sys = i, h));
     for (HTile h : P.mt) B.mt.push_back((h.sys = i, h));
@@ -555,6 +602,9 @@ int make_batch(const bse_system* sys, int nsys, bool backward, const Tune& tn, B
   B.o_xt = put(B.xt.size() * sizeof(HTile));
   B.o_mt = put(B.mt.size() * sizeof(HTile));
   B.o_d2off = put(B.d2off.size() * sizeof(int));
+  B.o_tra = put(tr ? nsys * sizeof(TrArgs) : 0);
+  B.o_fill = put(B.fill.size() * sizeof(int4));
+  // the tables above are uploaded as one image [0, o_cnt); the counters are not
   B.o_cnt = put(3 * kXcds * sizeof(unsigned) + 32 + 8 * sizeof(unsigned long long));  // queues, validation
   B.base.resize(nsys);
   for (int i = 0; i < nsys; ++i) {
@@ -567,8 +617,8 @@ int make_batch(const bse_system* sys, int nsys, bool backward, const Tune& tn, B
 
 // Key of everything the host plan of a batch depends on: shapes, sphere
 // tables (hashed by content), the backward flag and the k tile.
-std::string plan_key(const bse_system* sys, int nsys, bool backward, int ktile) {
-  std::string k = std::to_string(nsys) + (backward ? "b" : "f") + std::to_string(ktile);
+std::string plan_key(const bse_system* sys, int nsys, bool backward, int ktile, bool tr) {
+  std::string k = std::to_string(nsys) + (backward ? "b" : "f") + (tr ? "t" : "") + std::to_string(ktile);
   for (int i = 0; i < nsys; ++i) {
     const bse_system& s = sys[i];
     const int nk = s.kmesh[0] * s.kmesh[1] * s.kmesh[2];
@@ -587,33 +637,45 @@ std::string plan_key(const bse_system* sys, int nsys, bool backward, int ktile) 
   return k;
 }
 
-// The last host plan built on this thread: a repeated build of the same batch
-// shape skips planning.
+// The last few host plans built on this thread (least recently used one
+// replaced): a repeated build of the same batch shape skips planning, also
+// when a tuned k tile asks for a second plan of the same batch.
 struct PlanCache {
   std::string key;
   Batch B;
+  unsigned long long used = 0;
 };
-thread_local PlanCache g_plan;
+constexpr int kPlanSlots = 4;
+thread_local PlanCache g_plan[kPlanSlots];
+thread_local unsigned long long g_plan_clock = 0;
 
 // make_batch through the cache.
-int cached_batch(const bse_system* sys, int nsys, bool backward, const Tune& tn, const Batch** out) {
+int cached_batch(const bse_system* sys, int nsys, bool backward, const Tune& tn, bool tr, const Batch** out) {
   if (nsys < 1 || !sys) return fail(BSE_ERR_INVALID_ARG, "no systems");
   for (int i = 0; i < nsys; ++i) {
     int rc = check_system(&sys[i]);
     if (rc) return rc;
   }
-  const std::string key = plan_key(sys, nsys, backward, tn.ktile);
-  if (key != g_plan.key) {
+  const std::string key = plan_key(sys, nsys, backward, tn.ktile, tr);
+  PlanCache* slot = nullptr;
+  for (PlanCache& c : g_plan)
+    if (!c.key.empty() && c.key == key) slot = &c;
+  if (!slot) {
+    slot = &g_plan[0];
+    for (PlanCache& c : g_plan)
+      if (c.used < slot->used) slot = &c;
     Batch B;
-    int rc = make_batch(sys, nsys, backward, tn, B);
+    int rc = make_batch(sys, nsys, backward, tn, tr, B);
     if (rc) {
-      g_plan.key.clear();
+      slot->key.clear();
+      slot->used = 0;
       return rc;
     }
-    g_plan.B = std::move(B);
-    g_plan.key = key;
+    slot->B = std::move(B);
+    slot->key = key;
   }
-  *out = &g_plan.B;
+  slot->used = ++g_plan_clock;
+  *out = &slot->B;
   return BSE_OK;
 }
 
@@ -636,6 +698,7 @@ int upload_batch(const Batch& B, const bse_system* sys, int precision, char* ws,
   };
   std::vector<PdArgs> ax(nsys), av(nsys), ac(nsys);
   std::vector<GemmArgs> ga(nsys);
+  std::vector<TrArgs> ta(B.tr ? nsys : 0);
   for (int i = 0; i < nsys; ++i) {
     const Plan& P = B.P[i];
     char* region = ws + B.base[i];
@@ -649,6 +712,17 @@ int upload_batch(const Batch& B, const bse_system* sys, int precision, char* ws,
     ac[i].out = reinterpret_cast<double2*>(region + P.o_RC);
     ga[i] = gemm_args(P, &sys[i], region);
     ga[i].w_head_fp64 = precision != BSE_FP64;  // mixed: the q = 0 head of W is added in FP64
+    if (B.tr) {
+      TrArgs& r = ta[i];
+      r.rv = reinterpret_cast<double2*>(region + P.o_RV);
+      r.rc = reinterpret_cast<double2*>(region + P.o_RC);
+      r.ng = reinterpret_cast<const int*>(region + P.o_ng);
+      r.pairs = reinterpret_cast<const int4*>(region + P.o_pairs);
+      r.trmap = reinterpret_cast<const int*>(region + P.o_trmap);
+      r.ng_max = P.ng_max;
+      r.nv = P.nv;
+      r.nc = P.nc;
+    }
   }
   cp(B.o_pdx, ax.data(), nsys * sizeof(PdArgs));
   cp(B.o_pdv, av.data(), nsys * sizeof(PdArgs));
@@ -661,6 +735,8 @@ int upload_batch(const Batch& B, const bse_system* sys, int precision, char* ws,
   cp(B.o_xt, B.xt.data(), B.xt.size() * sizeof(HTile));
   cp(B.o_mt, B.mt.data(), B.mt.size() * sizeof(HTile));
   cp(B.o_d2off, B.d2off.data(), B.d2off.size() * sizeof(int));
+  cp(B.o_tra, ta.data(), ta.size() * sizeof(TrArgs));
+  cp(B.o_fill, B.fill.data(), B.fill.size() * sizeof(int4));
   std::vector<char> tb;
   for (int i = 0; i < nsys; ++i) {
     tb.assign(B.P[i].tables, 0);
@@ -707,6 +783,17 @@ int run_pd(const Batch& B, char* ws, int kind, const Tune& tn, hipStream_t st) {
   return BSE_OK;
 }
 
+// Pair densities of the time-reversal images (kind 1 vv, 2 cc), after the
+// pair-density launch of the same kind.
+int run_tr_fill(const Batch& B, char* ws, int kind, hipStream_t st) {
+  if (!B.tr || B.fill.empty() || kind == 0) return BSE_OK;
+  HIP_TRY(stage(BSE_STAGE_TR_FILL, st, [&] {
+    return launch_tr_fill(reinterpret_cast<const TrArgs*>(ws + B.o_tra), reinterpret_cast<const int4*>(ws + B.o_fill),
+                          (int)B.fill.size(), kind, st);
+  }));
+  return BSE_OK;
+}
+
 // Wave functions in the pair-density frame, for systems whose axes are rotated.
 int rotate_if_needed(const Plan& P, const bse_system& s, char* region, hipStream_t st) {
   if (!P.rot) return BSE_OK;
@@ -717,8 +804,8 @@ int rotate_if_needed(const Plan& P, const bse_system& s, char* region, hipStream
   return BSE_OK;
 }
 
-// The forward build of every system of the batch, one launch per stage
-// (the sqrt v tables aside, one small launch per system).
+// The forward build of every system of the batch, one launch per stage (the
+// sqrt v tables aside, one small launch per system), all on `st`.
 int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& tn, char* ws, hipStream_t st) {
   const int nsys = (int)B.P.size();
   int rc = upload_batch(B, sys, precision, ws, st);
@@ -729,13 +816,13 @@ int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& 
     HIP_TRY(stage(BSE_STAGE_VSCALE, st, [&] { return launch_vscale(sys[i].vx, P.ng[0], P.ng_max, vs, st); }));
     if ((rc = rotate_if_needed(P, sys[i], ws + B.base[i], st))) return rc;
   }
-  for (int kind = 0; kind < 3; ++kind)
-    if ((rc = run_pd(B, ws, kind, tn, st))) return rc;
   const GemmArgs* gs = reinterpret_cast<const GemmArgs*>(ws + B.o_gargs);
   const HTile* xt = reinterpret_cast<const HTile*>(ws + B.o_xt);
   const HTile* mt = reinterpret_cast<const HTile*>(ws + B.o_mt);
   const S1Tile* s1 = reinterpret_cast<const S1Tile*>(ws + B.o_s1);
   const int* d2off = reinterpret_cast<const int*>(ws + B.o_d2off);
+  for (int kind = 0; kind < 3; ++kind)
+    if ((rc = run_pd(B, ws, kind, tn, st)) || (rc = run_tr_fill(B, ws, kind, st))) return rc;
   HIP_TRY(stage(BSE_STAGE_EXCHANGE, st, [&] { return launch_exchange(gs, xt, (int)B.xt.size(), precision, st); }));
   HIP_TRY(stage(BSE_STAGE_DIRECT1, st, [&] { return launch_direct_s1(gs, s1, (int)B.s1.size(), precision, st); }));
   HIP_TRY(stage(BSE_STAGE_DIRECT2, st, [&] { return launch_direct_s2(gs, d2off, nsys, B.d2n, precision, st); }));
@@ -776,6 +863,18 @@ int validate(const Batch& B, const bse_system* sys, char* ws, hipStream_t st) {
     if (w[2] > tol)
       return fail(BSE_ERR_NOT_HERMITIAN, "system %zu: W violates time reversal (deviation %.3e, max |W| %.3e)", i, w[2],
                   w[0]);
+    if (B.tr) {
+      HIP_TRY(launch_validate_u_tr(reinterpret_cast<const double2*>(s.u), reinterpret_cast<const int*>(r + P.o_ktr),
+                                   P.nk, P.nb, s.grid[0], s.grid[1], s.grid[2], wstat, st));
+      unsigned long long hu[2];
+      HIP_TRY(hipMemcpyAsync(hu, wstat + 3, sizeof hu, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      double du[2];
+      std::memcpy(du, hu, sizeof du);
+      if (!(du[1] <= 1e-10 * du[0]))
+        return fail(BSE_ERR_NOT_SYMMETRIC, "system %zu: u violates time reversal (deviation %.3e, max |u| %.3e)", i,
+                    du[1], du[0]);
+    }
   }
   return BSE_OK;
 }
@@ -825,7 +924,7 @@ thread_local std::vector<Tune> g_tried;
 int autotune(const bse_system* sys, int nsys, int precision, const char* cache, Tune& best, char* ws, size_t ws_bytes,
              hipStream_t st) {
   Batch B0;
-  int rc = make_batch(sys, nsys, false, Tune{}, B0);
+  int rc = make_batch(sys, nsys, false, Tune{}, false, B0);
   if (rc) return rc;
   const std::string key = batch_key(B0.P, precision);
   if (cache_lookup(cache, key, best)) {
@@ -853,7 +952,7 @@ int autotune(const bse_system* sys, int nsys, int precision, const char* cache, 
   g_tried.clear();
   for (const Tune& c : cand) {
     Batch B;
-    if ((rc = make_batch(sys, nsys, false, c, B))) break;
+    if ((rc = make_batch(sys, nsys, false, c, false, B))) break;
     if ((rc = upload_batch(B, sys, precision, ws, st))) break;
     float ms = 0.f;
     hipError_t e = hipSuccess;
@@ -894,9 +993,15 @@ size_t bse_workspace_size(const bse_system* sys, int nsys, int precision, int fl
   (void)flags;
   if (!sys || nsys < 1) return 0;
   Batch B;
-  // one system: room for the backward as well; a batch: the forward build
-  if (make_batch(sys, nsys, nsys == 1, Tune{}, B)) return 0;
-  return B.total;
+  // one system: room for the backward as well; a batch: the forward build,
+  // with room for the time-reversal tables where the spheres allow them
+  if (make_batch(sys, nsys, nsys == 1, Tune{}, false, B)) return 0;
+  size_t total = B.total;
+  Batch Bt;
+  const std::string keep = g_err;  // spheres without time reversal are no error here
+  if (make_batch(sys, nsys, nsys == 1, Tune{}, true, Bt) == BSE_OK) total = std::max(total, Bt.total);
+  g_err = keep;
+  return total;
 }
 
 int bse_pair_density(const bse_system* sys, int kind, const int* kpairs, int npairs, const double* cell,
@@ -1002,16 +1107,18 @@ int bse_build_H(const bse_system* sys, int nsys, int precision, int flags, void*
   if (!sys || nsys < 1) return fail(BSE_ERR_INVALID_ARG, "no systems");
   if (!ws) return fail(BSE_ERR_INVALID_ARG, "workspace is NULL");
   if (precision < BSE_FP64 || precision > BSE_BF16X3) return fail(BSE_ERR_INVALID_ARG, "bad precision %d", precision);
-  if (flags & ~(BSE_VALIDATE | BSE_PERSISTENT)) return fail(BSE_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+  if (flags & ~(BSE_VALIDATE | BSE_PERSISTENT | BSE_TIME_REVERSAL))
+    return fail(BSE_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
   for (int i = 0; i < nsys; ++i)
     if (!sys[i].H) return fail(BSE_ERR_INVALID_ARG, "H of system %d is NULL", i);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const Batch* Bp = nullptr;
-  int rc = cached_batch(sys, nsys, false, Tune{}, &Bp);
+  const bool tr = (flags & BSE_TIME_REVERSAL) != 0;
+  int rc = cached_batch(sys, nsys, false, Tune{}, tr, &Bp);
   if (rc) return rc;
   Tune tn = tune_for(batch_key(Bp->P, precision));
   if (flags & BSE_PERSISTENT) tn.persist = 1;
-  if (tn.ktile != Tune{}.ktile && (rc = cached_batch(sys, nsys, false, tn, &Bp))) return rc;
+  if (tn.ktile != Tune{}.ktile && (rc = cached_batch(sys, nsys, false, tn, tr, &Bp))) return rc;
   const Batch& B = *Bp;
   if (ws_bytes < B.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, B.total);
   if (flags & BSE_VALIDATE) {
@@ -1029,7 +1136,7 @@ int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, do
   if (precision < BSE_FP64 || precision > BSE_BF16X3) return fail(BSE_ERR_INVALID_ARG, "bad precision %d", precision);
   if (flags & ~BSE_PROJECT_DW) return fail(BSE_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
   Batch B;
-  int rc = make_batch(sys, 1, true, Tune{}, B);
+  int rc = make_batch(sys, 1, true, Tune{}, false, B);
   if (rc) return rc;
   const Plan& P = B.P[0];
   if (ws_bytes < B.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, B.total);

@@ -151,6 +151,26 @@ struct GradCell {
 hipError_t launch_validate(const double* u, size_t nu, const double* eps, size_t ne, const double* vx, size_t nvx,
                            const double2* W, const int* ng, const int* qbar, const int* trmap, int nk, int ng_max,
                            int check_tr, unsigned* bad, unsigned long long* wstat, hipStream_t st);
+// Time reversal (BSE_TIME_REVERSAL): ktr[k] = kbar | K0 << 24 | K1 << 25 |
+// K2 << 26 with -k = kbar - K (grid axes).  wstat[3] gets max |u|, wstat[4]
+// max |u_{kbar}(r_j) - exp(-i K.r_j) conj(u_k(r_j))| (abs(re) + abs(im)); u in
+// grid order [k][band][j1][j2][j3].
+hipError_t launch_validate_u_tr(const double2* u, const int* ktr, int nk, int nb, int N1, int N2, int N3,
+                                unsigned long long* wstat, hipStream_t st);
+
+// Pair densities of the time-reversal images of computed k pairs.  Item
+// (dst, src, mode, sys): mode 0, rho_dst[ab][g] = conj(rho_src[ab][trmap[q_dst][g]]);
+// mode 1, rho_dst[a nB + b][g] = rho_src[b nB + a][g].  kind 1 fills the
+// valence pair densities, kind 2 the conduction ones.
+struct TrArgs {
+  double2* rv;
+  double2* rc;
+  const int* ng;
+  const int4* pairs;
+  const int* trmap;
+  int ng_max, nv, nc;
+};
+hipError_t launch_tr_fill(const TrArgs* as, const int4* items, int nitems, int kind, hipStream_t st);
 bool fft_len_supported(int N);
 hipError_t launch_grad(const double2* u, double2* scratch, int nk, int nb, int nv, int nc, int N1, int N2, int N3,
                        const GradCell& bc, double2* out, hipStream_t st);

@@ -51,6 +51,41 @@ __global__ void k_scan_W(const double2* __restrict__ W, const int* __restrict__ 
   }
 }
 
+// One thread per element of u: max |u| and max deviation from the
+// time-reversal image of the partner point.
+__global__ void k_scan_u_tr(const double2* __restrict__ u, const int* __restrict__ ktr, int nk, int nb, int N1,
+                            int N2, int N3, unsigned long long* __restrict__ out) {
+  const size_t nr = (size_t)N1 * N2 * N3, per = nr * nb;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < per * nk;
+       id += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(id / per);
+    const size_t rest = id % per;
+    const int j = (int)(rest % nr);
+    const int j1 = j / (N2 * N3), j2 = (j / N3) % N2, j3 = j % N3;
+    const int t = ktr[k];
+    const int kb = t & 0xffffff;
+    const double f = ((t >> 24) & 1) * (double)j1 / N1 + ((t >> 25) & 1) * (double)j2 / N2 +
+                     ((t >> 26) & 1) * (double)j3 / N3;
+    double s, c;
+    sincospi(-2.0 * f, &s, &c);
+    const double2 a = u[id];
+    const double2 b = u[(size_t)kb * per + rest];
+    // exp(-i K.r) conj(a)
+    const double ex = c * a.x + s * a.y, ey = s * a.x - c * a.y;
+    double m = fabs(a.x) + fabs(a.y);
+    double d = fabs(b.x - ex) + fabs(b.y - ey);
+    if (!isfinite(m) || !isfinite(d)) m = d = INFINITY;
+    amax(out + 3, m);
+    amax(out + 4, d);
+  }
+}
+
+hipError_t launch_validate_u_tr(const double2* u, const int* ktr, int nk, int nb, int N1, int N2, int N3,
+                                unsigned long long* wstat, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan_u_tr, dim3(2048), dim3(256), 0, st, u, ktr, nk, nb, N1, N2, N3, wstat);
+  return hipGetLastError();
+}
+
 hipError_t launch_validate(const double* u, size_t nu, const double* eps, size_t ne, const double* vx, size_t nvx,
                            const double2* W, const int* ng, const int* qbar, const int* trmap, int nk, int ng_max,
                            int check_tr, unsigned* bad, unsigned long long* wstat, hipStream_t st) {

@@ -79,6 +79,15 @@ def test_workspace_size_and_host_errors():
     keep4 = (keep4[0], gv)
     st4.gvec = gv.ctypes.data
     assert L.bse_build_H(ctypes.byref(st4), 1, 0, 0, ctypes.c_void_p(0x1000), n, None) == -2
+    # time reversal asked for on a sphere that is not closed under G -> -G:
+    # the last point of S(0) replaced by G = 0 leaves its partner without an image
+    st5, keep5 = _fake_struct(P, s)
+    gv = keep5[1].copy()
+    gv[0, s.ng[0] - 1] = (0, 0, 0)
+    keep5 = (keep5[0], gv)
+    st5.gvec = gv.ctypes.data
+    assert L.bse_build_H(ctypes.byref(st5), 1, 0, P.BSE_TIME_REVERSAL, ctypes.c_void_p(0x1000), n, None) == -2
+    assert "time reversal" in P.bse_last_error()
     # pair densities: bad kind and out-of-range k pair
     out = ctypes.c_void_p(0x1000)
     assert L.bse_pair_density(ctypes.byref(st), 9, None, 0, None, out, ctypes.c_void_p(0x1000), n, None) == -1

@@ -1,0 +1,73 @@
+"""Time reversal of the inputs and of the pair densities (Sec. III.A: the
+pair-density transformation, with T the identity combined with time
+reversal), checked on the oracle's densities, each computed from its
+definition.  For kbar the mesh point of -k and u_{kbar} = exp(-i K.r)
+conj(u_k), the image of the pair (k, k') is (kbar, kbar') or (kbar', kbar):
+  kbar <= kbar':  n_{a kbar, b kbar'}(G) = conj(n_{a k, b k'}(G'')), q + G'' = -(qbar + G)
+  kbar >  kbar':  n_{a kbar', b kbar}(G) = n_{b k, a k'}(G)
+which is what the GPU build relies on under BSE_TIME_REVERSAL."""
+import numpy as np
+import pytest
+
+import bse_synth as B
+import oracle as O
+
+
+def _system(tr, kmesh=(3, 2, 1)):
+    return B.make_system(B.cell_sc(10.0), (16, 16, 16), kmesh, 2, 2, 3.0, seed=77, time_reversal=tr)
+
+
+def test_generator_obeys_time_reversal():
+    s = _system(True, (4, 3, 1))
+    for k in range(s.nk):
+        kb, K = B.k_partner(s.kmesh, k)
+        assert B.k_partner(s.kmesh, kb)[0] == k
+        # -k = kbar - K on the mesh
+        iv, ivb = B.ktriplet(s.kmesh, k), B.ktriplet(s.kmesh, kb)
+        assert np.array_equal(-iv, ivb - K * np.array(s.kmesh))
+        np.testing.assert_allclose(s.u[kb], B.u_partner(s.u[k], s.grid, K), rtol=0, atol=1e-14)
+        np.testing.assert_allclose(s.u[k].conj() @ s.u[k].T, np.eye(s.nv + s.nc), atol=1e-12)
+        np.testing.assert_array_equal(s.eps[k], s.eps[kb])
+
+
+def _relation_errors(s):
+    """Largest deviation from the two relations over every upper pair, and
+    the number of pairs of each kind."""
+    _, rv, rc = O.densities(s)
+    up = O.upper_pairs(s.nk)
+    index = {p: i for i, p in enumerate(up)}
+    kbar = [B.k_partner(s.kmesh, k)[0] for k in range(s.nk)]
+    err, counts = 0.0, [0, 0, 0]
+    for i, (ka, kb) in enumerate(up):
+        x, y = kbar[ka], kbar[kb]
+        j = index[(min(x, y), max(x, y))]
+        if j == i:
+            counts[2] += 1
+        iq_i, _ = O.fold(s.kmesh, ka, kb)
+        iq_j, _ = O.fold(s.kmesh, min(x, y), max(x, y))
+        ng = s.ng[iq_j]
+        for rho in (rv, rc):
+            if x <= y:
+                qb, perm = B.tr_partner(s, iq_j)
+                assert qb == iq_i and perm.min() >= 0
+                want = np.conj(rho[i][:, :, perm])
+                counts[0] += 1
+            else:
+                assert iq_i == iq_j
+                want = np.swapaxes(rho[i], 0, 1)[:, :, :ng]
+                counts[1] += 1
+            err = max(err, float(np.abs(rho[j][:, :, :ng] - want).max()))
+    return err, counts
+
+
+def test_pair_density_images():
+    s = _system(True)
+    err, counts = _relation_errors(s)
+    assert counts[0] > 0 and counts[1] > 0  # both kinds of image occur on this mesh
+    assert err <= 1e-13, err
+
+
+def test_images_fail_without_time_reversal():
+    # the same relations do not hold for wave functions drawn independently at k and -k
+    err, _ = _relation_errors(_system(False))
+    assert err > 1e-3
