@@ -124,7 +124,6 @@ def test_full_size_si_blocks_match_oracle():
     for (ka, kb), r in zip(blocks, ref):
         g = H[ka * nt:(ka + 1) * nt, kb * nt:(kb + 1) * nt].cpu().numpy()
         assert np.abs(g - r).max() <= 1e-12 * max(np.abs(r).max(), 1.0), (ka, kb)
-    Hc = H.cpu().numpy() if False else None
     # Hermiticity on a sampled strip
     strip = H[:512].cpu().numpy()
     col = H[:, :512].cpu().numpy()

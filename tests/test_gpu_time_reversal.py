@@ -95,3 +95,38 @@ def test_tr_validate_rejects_inputs_without_time_reversal():
     torch.cuda.synchronize()
     ref = O.build_H(s)
     assert np.abs(d.H.cpu().numpy() - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1.0)
+
+
+def test_tr_full_size_si():
+    """Si-like 32^3 grid, 8^3 k mesh, 4+4 bands (H 8192 x 8192) with
+    time-reversal-symmetric inputs, in the launch configuration the benchmark
+    times: the whole H against the general build, and oracle blocks at k pairs
+    whose densities were gathered (and at their images, which were computed)."""
+    import paper_1206_3518_amd as P
+    import torch
+    s = B.make_config(2, time_reversal=True)
+    d = P.DeviceSystem(s)
+    ws = P.workspace(P.bse_workspace_size([d]))
+    _say(f"full size, time reversal: NS = {s.ns}")
+    P.bse_build_H([d], P.BSE_FP64, 0, ws)
+    torch.cuda.synchronize()
+    Hg = d.H.clone()
+    d.H.fill_(float("nan"))
+    P.bse_build_H([d], P.BSE_FP64, P.BSE_TIME_REVERSAL, ws)
+    torch.cuda.synchronize()
+    scale = Hg.abs().max().item()
+    diff = (d.H - Hg).abs().max().item()
+    _say(f"  max|dH| vs general build {diff:.3e} (max|H| {scale:.3e})")
+    assert diff <= 1e-13 * scale
+    nk, nt = s.nk, s.nv * s.nc
+    kbar = [B.k_partner(s.kmesh, k)[0] for k in range(nk)]
+    rng = np.random.default_rng(11)
+    blocks = []
+    for ka, kb in [(1, 2), (3, 200), (77, 77)] + [tuple(sorted(int(x) for x in rng.integers(0, nk, 2)))
+                                                  for _ in range(3)]:
+        x, y = kbar[ka], kbar[kb]
+        blocks += [(ka, kb), (min(x, y), max(x, y))]
+    ref = O.build_blocks(s, blocks)
+    for (ka, kb), r in zip(blocks, ref):
+        g = d.H[ka * nt:(ka + 1) * nt, kb * nt:(kb + 1) * nt].cpu().numpy()
+        assert np.abs(g - r).max() <= 1e-12 * max(np.abs(r).max(), 1.0), (ka, kb)
