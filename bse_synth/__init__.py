@@ -175,7 +175,9 @@ def make_system(cell, grid, kmesh, nv, nc, ecut, *, coulomb_kind="bulk", slab_L=
     """A synthetic system.  With ``time_reversal`` the wave functions and band
     energies obey time reversal without spin-orbit coupling: for kbar the mesh
     point of -k, -k = kbar - K with K a lattice vector (``k_partner``), and
-    u_{n,kbar}(r_j) = exp(-i K . r_j) conj(u_{n,k}(r_j)), eps_{n,kbar} = eps_{n,k}."""
+    u_{n,kbar}(r_j) = exp(-i K . r_j) conj(u_{n,k}(r_j)), eps_{n,kbar} = eps_{n,k}
+    for kbar != k.  At points that are their own partner u is drawn like any
+    other (an eigensolver leaves a free phase per band there)."""
     cell = np.asarray(cell, dtype=np.float64)
     grid = tuple(int(x) for x in grid)
     kmesh = tuple(int(x) for x in kmesh)
@@ -230,15 +232,8 @@ def make_system(cell, grid, kmesh, nv, nc, ecut, *, coulomb_kind="bulk", slab_L=
             spec = np.zeros(grid + (nb,), dtype=np.complex128)
             spec[msph[:, 0] % grid[0], msph[:, 1] % grid[1], msph[:, 2] % grid[2]] = c
             z = np.fft.ifftn(spec, axes=(0, 1, 2)).reshape(nr, nb)
-        if time_reversal and kb == k:
-            # u = exp(-i K.r / 2) y with y real satisfies the relation at its own partner
-            half = np.sqrt(tr_phase(grid, K))
-            y = np.real(z * np.conj(half)[:, None])
-            q, _ = np.linalg.qr(y)
-            u[k] = (q * half[:, None]).T
-        else:
-            q, _ = np.linalg.qr(z)
-            u[k] = q.T
+        q, _ = np.linalg.qr(z)
+        u[k] = q.T
 
     # energies
     rng = np.random.Generator(np.random.PCG64(ss_eps))

@@ -364,7 +364,9 @@ int make_plan(const bse_system* s, Plan& P) {
   // time reversal on the k mesh: -k = kbar - K, and the image of each pair
   // (k, k'): (kbar, kbar') if kbar <= kbar' (conjugate, sphere map of
   // qbar), else (kbar', kbar) (bands exchanged).  Of a pair and its image the
-  // lower index is computed; pairs that are their own image are computed.
+  // lower index is computed.  Pairs that touch a point that is its own
+  // partner (kbar = k) are computed: there the wave functions carry a free
+  // gauge phase per band, so no relation between u_k and conj(u_k) is assumed.
   P.ktr.assign(P.nk, 0);
   {
     const int* n = s->kmesh;
@@ -384,6 +386,11 @@ int make_plan(const bse_system* s, Plan& P) {
     P.trfill.clear();
     for (int p = 0; p < np; ++p) {
       const int x = P.ktr[P.pairs[p].x] & 0xffffff, y = P.ktr[P.pairs[p].y] & 0xffffff;
+      if (x == P.pairs[p].x || y == P.pairs[p].y) {
+        P.jv_tr.push_back(P.jv[p]);
+        P.jc_tr.push_back(P.jc[p]);
+        continue;
+      }
       const int mode = x <= y ? 0 : 1;
       const long long a = std::min(x, y), b = std::max(x, y);
       const int img = lex2p[a * P.nk - a * (a - 1) / 2 + (b - a)];

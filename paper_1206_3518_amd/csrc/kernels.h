@@ -152,9 +152,9 @@ hipError_t launch_validate(const double* u, size_t nu, const double* eps, size_t
                            const double2* W, const int* ng, const int* qbar, const int* trmap, int nk, int ng_max,
                            int check_tr, unsigned* bad, unsigned long long* wstat, hipStream_t st);
 // Time reversal (BSE_TIME_REVERSAL): ktr[k] = kbar | K0 << 24 | K1 << 25 |
-// K2 << 26 with -k = kbar - K (grid axes).  wstat[3] gets max |u|, wstat[4]
-// max |u_{kbar}(r_j) - exp(-i K.r_j) conj(u_k(r_j))| (abs(re) + abs(im)); u in
-// grid order [k][band][j1][j2][j3].
+// K2 << 26 with -k = kbar - K (grid axes).  Over the points with kbar != k,
+// wstat[3] gets max |u|, wstat[4] max |u_{kbar}(r_j) - exp(-i K.r_j)
+// conj(u_k(r_j))| (abs(re) + abs(im)); u in grid order [k][band][j1][j2][j3].
 hipError_t launch_validate_u_tr(const double2* u, const int* ktr, int nk, int nb, int N1, int N2, int N3,
                                 unsigned long long* wstat, hipStream_t st);
 

@@ -51,8 +51,8 @@ __global__ void k_scan_W(const double2* __restrict__ W, const int* __restrict__ 
   }
 }
 
-// One thread per element of u: max |u| and max deviation from the
-// time-reversal image of the partner point.
+// One thread per element of u at points k with kbar != k: max |u| and max
+// deviation from the time-reversal image of the partner point.
 __global__ void k_scan_u_tr(const double2* __restrict__ u, const int* __restrict__ ktr, int nk, int nb, int N1,
                             int N2, int N3, unsigned long long* __restrict__ out) {
   const size_t nr = (size_t)N1 * N2 * N3, per = nr * nb;
@@ -64,6 +64,7 @@ __global__ void k_scan_u_tr(const double2* __restrict__ u, const int* __restrict
     const int j1 = j / (N2 * N3), j2 = (j / N3) % N2, j3 = j % N3;
     const int t = ktr[k];
     const int kb = t & 0xffffff;
+    if (kb == k) continue;  // no relation is assumed at a point that is its own partner
     const double f = ((t >> 24) & 1) * (double)j1 / N1 + ((t >> 25) & 1) * (double)j2 / N2 +
                      ((t >> 26) & 1) * (double)j3 / N3;
     double s, c;
