@@ -317,9 +317,17 @@ def main():
         E64 = [torch.linalg.eigvalsh(h)[:10].cpu().numpy() for h in H64]
         out["lowest_exciton_eV"] = E64[0].tolist()
         mixed = {}
-        for name in ("split_fp32", "bf16x3"):
-            pm = P.PRECISIONS[name]
-            msm, _, stm = run_steps(P, devs, pm, flags, ws, max(2, args.steps // 2), 1)
+        ws32 = None
+        for name, mflags in (("split_fp32", 0), ("bf16x3", 0), ("split_fp32+fp32_pairdens", P.BSE_FP32_PAIRDENS),
+                             ("bf16x3+fp32_pairdens", P.BSE_FP32_PAIRDENS)):
+            pm = P.PRECISIONS[name.split("+")[0]]
+            if mflags and ws32 is None:
+                need = P.bse_workspace_size(devs, pm, mflags)
+                ws32 = ws if need <= ws.numel() else P.workspace(need, devs[0].device)
+            mtune = None
+            if mflags and not args.no_autotune and not args.persistent:
+                mtune = P.bse_autotune(devs, pm, None, ws32, flags=mflags)  # the FP32 kernel's own choice
+            msm, _, stm = run_steps(P, devs, pm, flags | mflags, ws32 if mflags else ws, max(2, args.steps // 2), 1)
             dH = max((d.H - h).abs().max().item() for d, h in zip(devs, H64))
             dE = max(float(np.abs(torch.linalg.eigvalsh(d.H)[:10].cpu().numpy() - e).max())
                      for d, e in zip(devs, E64))
@@ -327,8 +335,12 @@ def main():
                            "max_abs_dH_eV": dH, "max_abs_dH_over_kernel": dH / kscale,
                            "max_abs_dE_lowest10_eV": dE,
                            "stage_ms": {k: v[0] / max(v[1], 1) for k, v in stm.items()},
-                           "gemm": gemm_report(stm, name)}
+                           "gemm": gemm_report(stm, name.split("+")[0])}
+            if mtune is not None:
+                mixed[name]["dispatch"] = (f"autotuned: persistent, {mtune['wg_per_cu']} workgroups/CU"
+                                           if mtune["persistent"] else f"autotuned: static, k tile {mtune['ktile']}")
         out["mixed"] = mixed
+        del ws32
         del H64
     if not args.no_time_reversal:
         del devs, ws

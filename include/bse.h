@@ -57,8 +57,8 @@ enum bse_status {
 };
 
 /* Arithmetic of the two dense contractions (exchange and direct term).
- * Pair densities, the transition-energy diagonal and the q = 0 head of W
- * are always FP64. */
+ * Pair densities (unless BSE_FP32_PAIRDENS), the transition-energy diagonal
+ * and the q = 0 head of W are FP64. */
 enum bse_precision {
     BSE_FP64 = 0,       /* FP64 MFMA                                           */
     BSE_SPLIT_FP32 = 1, /* operands split into FP32 hi + lo, 3 products, FP32 acc */
@@ -75,7 +75,7 @@ enum bse_flags {
     BSE_PERSISTENT = 2,  /* build a batch of systems with one persistent launch   */
     BSE_PROJECT_DW = 4,  /* backward: project dW onto Hermitian, time-reversal
                             symmetric W (group average of Sec. III.A, T = 1)     */
-    BSE_TIME_REVERSAL = 8  /* bse_build_H: the inputs obey time reversal without
+    BSE_TIME_REVERSAL = 8, /* bse_build_H: the inputs obey time reversal without
                             spin-orbit coupling.  For kbar the mesh point of -k,
                             with -k = kbar - K (K a lattice vector, entries 0 or
                             1 in units of the mesh), u_{n,kbar}(r_j) =
@@ -94,6 +94,16 @@ enum bse_flags {
                             BSE_VALIDATE the relation of u is checked to
                             1e-10 max|u| (else BSE_ERR_NOT_SYMMETRIC); without
                             it, inputs that break it give a wrong H            */
+    BSE_FP32_PAIRDENS = 16 /* bse_build_H with BSE_SPLIT_FP32 or BSE_BF16X3 only
+                            (else BSE_ERR_INVALID_ARG): the valence-valence and
+                            conduction-conduction pair densities are transformed
+                            in FP32 from an FP32 copy of u (rounded to nearest,
+                            made once per call in the workspace) and stored as
+                            FP64; the exchange pair densities stay FP64.  Applies
+                            to grids whose pair-density planes (after the axis
+                            rotation) are at most 32 x 32 with even sides; other
+                            grids keep FP64.  Relative error of a density about
+                            1e-6; the workspace grows by Nk*nb*Nr*8 bytes      */
 };
 
 enum bse_pd_kind {
@@ -128,7 +138,8 @@ typedef struct bse_system {
 
 /* Bytes of device workspace that bse_build_H / bse_pair_density /
  * bse_build_H_backward need for these systems, with or without
- * BSE_TIME_REVERSAL (precision and flags are not used). */
+ * BSE_TIME_REVERSAL; with BSE_FP32_PAIRDENS in flags, also room for the FP32
+ * copy of u (precision and the other flags are not used). */
 size_t bse_workspace_size(const bse_system *sys, int nsys, int precision, int flags);
 
 /*
@@ -171,7 +182,9 @@ int bse_build_H(const bse_system *sys, int nsys, int precision, int flags,
  * BSE_PROJECT_DW, dW is the partial derivative of the map the build computes
  * (upper k blocks, lower ones mirrored); with it, dW is projected onto the
  * Hermitian, time-reversal symmetric W on which that map and the all-blocks
- * definition agree.  precision selects the arithmetic of the dW contraction
+ * definition agree.  With BSE_TIME_REVERSAL the recomputed pair densities
+ * use the time-reversal images as in bse_build_H (same contract on u, not
+ * checked here).  precision selects the arithmetic of the dW contraction
  * (its q = 0 head entry is FP64 in every mode); the density gradients are
  * FP64.  sys->H is not read.
  */
@@ -196,15 +209,16 @@ typedef struct bse_tuning {
  * static dispatch with k tiles 4, 8, 16 and persistent dispatch with 1..4
  * workgroups per CU, and keeps the fastest for every later bse_build_H of the
  * same signature in this process (BSE_PERSISTENT still forces persistent
- * dispatch).  cache_path (HOST, nullable): a text file of one JSON object per
+ * dispatch).  flags: 0, or BSE_FP32_PAIRDENS (with a mixed precision) to tune
+ * the FP32 pair-density kernel, whose builds then use that choice.  cache_path (HOST, nullable): a text file of one JSON object per
  * line; a matching line is used without timing, a new result is appended.
  * Blocks until the timing runs finish; needs the forward workspace of
  * bse_build_H and overwrites its pair-density area.  `chosen` (HOST,
  * nullable) receives the choice.  Results of bse_build_H do not depend on the
  * choice (every pair density is computed the same way in any order).
  */
-int bse_autotune(const bse_system *sys, int nsys, int precision, const char *cache_path, bse_tuning *chosen,
-                 void *ws, size_t ws_bytes, void *stream);
+int bse_autotune(const bse_system *sys, int nsys, int precision, int flags, const char *cache_path,
+                 bse_tuning *chosen, void *ws, size_t ws_bytes, void *stream);
 
 /* The candidates (with their times) that the last bse_autotune on this thread
  * measured: writes up to max_tried entries to `tried` (HOST) and returns how
@@ -247,7 +261,8 @@ enum bse_stage {
                                long axis is last (pair-density frame)    */
     BSE_STAGE_TR_FILL = 9,  /* BSE_TIME_REVERSAL: pair densities of the
                                image pairs                               */
-    BSE_NSTAGES = 10
+    BSE_STAGE_TO_F32 = 10,  /* BSE_FP32_PAIRDENS: FP32 copy of u          */
+    BSE_NSTAGES = 11
 };
 int bse_profile(int enable);
 int bse_profile_read(double *total_ms, long long *launches, int nstages, int reset);

@@ -20,7 +20,7 @@ _LIB = None
 
 BSE_OK = 0
 BSE_FP64, BSE_SPLIT_FP32, BSE_BF16X3 = 0, 1, 2
-BSE_VALIDATE, BSE_PERSISTENT, BSE_TIME_REVERSAL = 1, 2, 8
+BSE_VALIDATE, BSE_PERSISTENT, BSE_TIME_REVERSAL, BSE_FP32_PAIRDENS = 1, 2, 8, 16
 BSE_PD_EXCH, BSE_PD_VV, BSE_PD_CC, BSE_PD_DIPOLE = 0, 1, 2, 3
 PRECISIONS = {"fp64": BSE_FP64, "split_fp32": BSE_SPLIT_FP32, "bf16x3": BSE_BF16X3}
 HARTREE_EV = 27.211386245988
@@ -47,7 +47,7 @@ class bse_system(ctypes.Structure):
 
 SYMBOLS = ["bse_workspace_size", "bse_pair_density", "bse_build_H", "bse_build_H_backward",
            "bse_autotune", "bse_autotune_last", "bse_spectrum", "bse_profile", "bse_profile_read", "bse_last_error"]
-STAGES = ["vscale", "pd_exch", "pd_vv", "pd_cc", "exchange", "direct1", "direct2", "mirror", "rotate", "tr_fill"]
+STAGES = ["vscale", "pd_exch", "pd_vv", "pd_cc", "exchange", "direct1", "direct2", "mirror", "rotate", "tr_fill", "to_f32"]
 
 
 def lib():
@@ -66,7 +66,7 @@ def lib():
         L.bse_build_H.restype = I
         L.bse_build_H_backward.argtypes = [P, P, P, P, P, P, P, I, I, P, S, P]
         L.bse_build_H_backward.restype = I
-        L.bse_autotune.argtypes = [P, I, I, ctypes.c_char_p, P, P, S, P]
+        L.bse_autotune.argtypes = [P, I, I, I, ctypes.c_char_p, P, P, S, P]
         L.bse_autotune.restype = I
         L.bse_autotune_last.argtypes = [P, I]
         L.bse_autotune_last.restype = I
@@ -171,16 +171,17 @@ def bse_build_H(systems, precision=BSE_FP64, flags=0, ws=None, stream=None):
     return [s.H for s in systems]
 
 
-def bse_autotune(systems, precision=BSE_FP64, cache_path=None, ws=None, stream=None) -> dict:
+def bse_autotune(systems, precision=BSE_FP64, cache_path=None, ws=None, stream=None, flags=0) -> dict:
     """Times the candidate pair-density dispatches for this batch and keeps the
-    fastest for later builds of the same shape; returns the choice."""
+    fastest for later builds of the same shape; returns the choice.  flags:
+    BSE_FP32_PAIRDENS tunes the FP32 pair-density kernel (mixed precisions)."""
     arr = _structs(systems)
     if ws is None:
-        ws = workspace(bse_workspace_size(systems, precision), systems[0].device)
+        ws = workspace(bse_workspace_size(systems, precision, flags), systems[0].device)
     out = bse_tuning()
     path = None if cache_path is None else os.fsencode(str(cache_path))
-    _check(lib().bse_autotune(arr, len(systems), int(precision), path, ctypes.byref(out), _ptr(ws), ws.numel(),
-                              _stream(stream)))
+    _check(lib().bse_autotune(arr, len(systems), int(precision), int(flags), path, ctypes.byref(out), _ptr(ws),
+                              ws.numel(), _stream(stream)))
     return {"persistent": out.persistent, "ktile": out.ktile, "wg_per_cu": out.wg_per_cu, "pd_ms": out.pd_ms}
 
 

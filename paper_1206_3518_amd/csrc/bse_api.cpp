@@ -191,6 +191,8 @@ struct Plan {
   size_t tables = 0, o_vs = 0, o_X = 0, o_RV = 0, o_RC = 0, o_Z = 0, o_dWraw = 0, total = 0;
   size_t fwd_total = 0;  // region needed by the forward build (no dW scratch)
   size_t o_ut = 0;       // rotated wave functions (rot only; in the forward part)
+  bool pd32 = false;     // FP32 valence / conduction pair densities
+  size_t o_u32 = 0;      // FP32 copy of the wave functions in the frame (pd32 only)
 };
 
 int check_system(const bse_system* s) {
@@ -209,7 +211,14 @@ int check_system(const bse_system* s) {
   return BSE_OK;
 }
 
-int make_plan(const bse_system* s, Plan& P) {
+// What a batch is planned for besides its systems.
+struct BatchOpts {
+  bool backward = false;  // room for the adjoint's buffers
+  bool tr = false;        // time-reversal images gathered (BSE_TIME_REVERSAL)
+  bool pd32 = false;      // FP32 pair densities where the one-lane-per-line kernel applies
+};
+
+int make_plan(const bse_system* s, Plan& P, bool pd32) {
   int rc = check_system(s);
   if (rc) return rc;
   P.rot = !pd_line_grid(s->grid[1], s->grid[2]) && pd_line_grid(s->grid[0], s->grid[1]) && s->grid[2] <= 256;
@@ -425,6 +434,8 @@ int make_plan(const bse_system* s, Plan& P) {
   P.o_RC = put((size_t)np * P.nc * P.nc * P.ng_max * sizeof(double2));
   P.o_Z = put((size_t)np * P.nv * P.nv * P.ng_max * sizeof(double2));
   if (P.rot) P.o_ut = put((size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * sizeof(double2));
+  P.pd32 = pd32 && pd_line_grid(P.N2, P.N3);
+  if (P.pd32) P.o_u32 = put((size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * sizeof(float2));
   P.fwd_total = o;
   P.o_dWraw = put((size_t)P.nk * P.ng_max * P.ng_max * sizeof(double2));
   P.total = o;
@@ -463,6 +474,7 @@ PdArgs pd_args(const Plan& P, const bse_system* s, char* region) {
   a.F3 = P.F[2];
   a.vscale = nullptr;
   a.out = nullptr;
+  a.u32 = P.pd32 ? reinterpret_cast<const float2*>(region + P.o_u32) : nullptr;
   return a;
 }
 
@@ -503,8 +515,8 @@ std::mutex g_tune_mu;
 std::vector<std::pair<std::string, Tune>> g_tune;
 
 // Signature of a batch: everything that shapes its launches.
-std::string batch_key(const std::vector<Plan>& Ps, int precision) {
-  std::string k = "p" + std::to_string(precision);
+std::string batch_key(const std::vector<Plan>& Ps, int precision, bool pd32) {
+  std::string k = "p" + std::to_string(precision) + (pd32 ? "f32" : "");
   for (const Plan& P : Ps) {
     char b[160];
     snprintf(b, sizeof b, "|%dx%dx%d:k%d:b%d+%d:g%d:w%dx%d", P.N1, P.N2, P.N3, P.nk, P.nv, P.nc, P.ng_max, P.F[1],
@@ -544,18 +556,22 @@ struct Batch {
   std::vector<int> d2off;
   int d2n = 0;
   bool tr = false;             // pair densities of time-reversal images derived
+  bool pd32 = false;           // FP32 valence / conduction pair densities
+  size_t lds32 = 0;            // their LDS bytes
   std::vector<int4> fill;      // (dst, src, mode, sys)
   size_t o_pdx = 0, o_pdv = 0, o_pdc = 0, o_gargs = 0, o_jx = 0, o_jv = 0, o_jc = 0, o_s1 = 0, o_xt = 0, o_mt = 0;
   size_t o_d2off = 0, o_cnt = 0, o_tra = 0, o_fill = 0, tables = 0, total = 0;
 };
 
-int make_batch(const bse_system* sys, int nsys, bool backward, const Tune& tn, bool tr, Batch& B) {
+int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts& opt, Batch& B) {
   if (!sys || nsys < 1) return fail(BSE_ERR_INVALID_ARG, "no systems");
+  const bool backward = opt.backward, tr = opt.tr;
   B.tr = tr;
+  B.pd32 = opt.pd32;
   if (nsys > 32767) return fail(BSE_ERR_INVALID_ARG, "too many systems");
   B.P.resize(nsys);
   for (int i = 0; i < nsys; ++i) {
-    int rc = make_plan(&sys[i], B.P[i]);
+    int rc = make_plan(&sys[i], B.P[i], opt.pd32);
     if (rc) return rc;
     const Plan& P = B.P[i];
     if (i == 0) {
@@ -566,7 +582,9 @@ int make_batch(const bse_system* sys, int nsys, bool backward, const Tune& tn, b
                   P.N3, B.N2, B.N3);
     }
     B.ng_max = std::max(B.ng_max, P.ng_max);
-    const size_t l = pd_lds_bytes(P.N1, P.N2, P.N3, P.F[1], P.F[2], P.ng_max);
+    const size_t l = pd_lds_bytes(P.N1, P.N2, P.N3, P.F[1], P.F[2], P.ng_max, false);
+    B.pd32 = B.pd32 && P.pd32;
+    if (P.pd32) B.lds32 = std::max(B.lds32, pd_lds_bytes(P.N1, P.N2, P.N3, P.F[1], P.F[2], P.ng_max, true));
     if (l > 160 * 1024) return fail(BSE_ERR_SHAPE, "FFT window of system %d needs more than 160 KiB of LDS", i);
     B.lds = std::max(B.lds, l);
     if (tr && !P.tr_closed)
@@ -624,8 +642,9 @@ int make_batch(const bse_system* sys, int nsys, bool backward, const Tune& tn, b
 
 // Key of everything the host plan of a batch depends on: shapes, sphere
 // tables (hashed by content), the backward flag and the k tile.
-std::string plan_key(const bse_system* sys, int nsys, bool backward, int ktile, bool tr) {
-  std::string k = std::to_string(nsys) + (backward ? "b" : "f") + (tr ? "t" : "") + std::to_string(ktile);
+std::string plan_key(const bse_system* sys, int nsys, int ktile, const BatchOpts& o) {
+  std::string k = std::to_string(nsys) + (o.backward ? "b" : "f") + (o.tr ? "t" : "") + (o.pd32 ? "s" : "") +
+                  std::to_string(ktile);
   for (int i = 0; i < nsys; ++i) {
     const bse_system& s = sys[i];
     const int nk = s.kmesh[0] * s.kmesh[1] * s.kmesh[2];
@@ -657,13 +676,13 @@ thread_local PlanCache g_plan[kPlanSlots];
 thread_local unsigned long long g_plan_clock = 0;
 
 // make_batch through the cache.
-int cached_batch(const bse_system* sys, int nsys, bool backward, const Tune& tn, bool tr, const Batch** out) {
+int cached_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts& opt, const Batch** out) {
   if (nsys < 1 || !sys) return fail(BSE_ERR_INVALID_ARG, "no systems");
   for (int i = 0; i < nsys; ++i) {
     int rc = check_system(&sys[i]);
     if (rc) return rc;
   }
-  const std::string key = plan_key(sys, nsys, backward, tn.ktile, tr);
+  const std::string key = plan_key(sys, nsys, tn.ktile, opt);
   PlanCache* slot = nullptr;
   for (PlanCache& c : g_plan)
     if (!c.key.empty() && c.key == key) slot = &c;
@@ -672,7 +691,7 @@ int cached_batch(const bse_system* sys, int nsys, bool backward, const Tune& tn,
     for (PlanCache& c : g_plan)
       if (c.used < slot->used) slot = &c;
     Batch B;
-    int rc = make_batch(sys, nsys, backward, tn, tr, B);
+    int rc = make_batch(sys, nsys, tn, opt, B);
     if (rc) {
       slot->key.clear();
       slot->used = 0;
@@ -782,10 +801,12 @@ int run_pd(const Batch& B, char* ws, int kind, const Tune& tn, hipStream_t st) {
   b.persist = tn.persist;
   b.cnt = reinterpret_cast<unsigned*>(ws + B.o_cnt) + kind * kXcds;
   const int stage_id = kind == 0 ? BSE_STAGE_PD_EXCH : kind == 1 ? BSE_STAGE_PD_VV : BSE_STAGE_PD_CC;
-  const int grid = tn.persist ? persistent_grid(B.lds, b.njobs, tn.wg_per_cu) : b.njobs;
+  const bool f32 = B.pd32 && kind != 0;
+  const size_t lds = f32 ? B.lds32 : B.lds;
+  const int grid = tn.persist ? persistent_grid(lds, b.njobs, tn.wg_per_cu) : b.njobs;
   if (tn.persist) HIP_TRY(launch_zero_u32(b.cnt, kXcds, st));
   HIP_TRY(stage(stage_id, st, [&] {
-    return launch_pair_density(b, B.N2, B.N3, B.ng_max, B.lds, grid, kind == 0, st);
+    return launch_pair_density(b, B.N2, B.N3, B.ng_max, lds, grid, kind == 0, f32, st);
   }));
   return BSE_OK;
 }
@@ -811,6 +832,25 @@ int rotate_if_needed(const Plan& P, const bse_system& s, char* region, hipStream
   return BSE_OK;
 }
 
+// Wave functions in the form the pair-density launches read: rotated into the
+// frame where needed, and the FP32 copy for FP32 pair densities.
+int prepare_u(const Batch& B, const bse_system* sys, char* ws, hipStream_t st) {
+  for (size_t i = 0; i < B.P.size(); ++i) {
+    const Plan& P = B.P[i];
+    char* region = ws + B.base[i];
+    int rc = rotate_if_needed(P, sys[i], region, st);
+    if (rc) return rc;
+    if (!B.pd32) continue;
+    const double2* src =
+        P.rot ? reinterpret_cast<const double2*>(region + P.o_ut) : reinterpret_cast<const double2*>(sys[i].u);
+    HIP_TRY(stage(BSE_STAGE_TO_F32, st, [&] {
+      return launch_to_f32(src, reinterpret_cast<float2*>(region + P.o_u32), (size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3,
+                           st);
+    }));
+  }
+  return BSE_OK;
+}
+
 // The forward build of every system of the batch, one launch per stage (the
 // sqrt v tables aside, one small launch per system), all on `st`.
 int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& tn, char* ws, hipStream_t st) {
@@ -821,8 +861,8 @@ int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& 
     const Plan& P = B.P[i];
     double* vs = reinterpret_cast<double*>(ws + B.base[i] + P.o_vs);
     HIP_TRY(stage(BSE_STAGE_VSCALE, st, [&] { return launch_vscale(sys[i].vx, P.ng[0], P.ng_max, vs, st); }));
-    if ((rc = rotate_if_needed(P, sys[i], ws + B.base[i], st))) return rc;
   }
+  if ((rc = prepare_u(B, sys, ws, st))) return rc;
   const GemmArgs* gs = reinterpret_cast<const GemmArgs*>(ws + B.o_gargs);
   const HTile* xt = reinterpret_cast<const HTile*>(ws + B.o_xt);
   const HTile* mt = reinterpret_cast<const HTile*>(ws + B.o_mt);
@@ -928,12 +968,14 @@ thread_local std::vector<Tune> g_tried;
 
 // Times the valence-valence pair-density launch (the dominant stage) of the
 // batch under each candidate dispatch and keeps the fastest.
-int autotune(const bse_system* sys, int nsys, int precision, const char* cache, Tune& best, char* ws, size_t ws_bytes,
-             hipStream_t st) {
+int autotune(const bse_system* sys, int nsys, int precision, bool pd32, const char* cache, Tune& best, char* ws,
+             size_t ws_bytes, hipStream_t st) {
   Batch B0;
-  int rc = make_batch(sys, nsys, false, Tune{}, false, B0);
+  BatchOpts opt;
+  opt.pd32 = pd32;
+  int rc = make_batch(sys, nsys, Tune{}, opt, B0);
   if (rc) return rc;
-  const std::string key = batch_key(B0.P, precision);
+  const std::string key = batch_key(B0.P, precision, B0.pd32);
   if (cache_lookup(cache, key, best)) {
     set_tune(key, best);
     return BSE_OK;
@@ -959,8 +1001,9 @@ int autotune(const bse_system* sys, int nsys, int precision, const char* cache, 
   g_tried.clear();
   for (const Tune& c : cand) {
     Batch B;
-    if ((rc = make_batch(sys, nsys, false, c, false, B))) break;
+    if ((rc = make_batch(sys, nsys, c, opt, B))) break;
     if ((rc = upload_batch(B, sys, precision, ws, st))) break;
+    if ((rc = prepare_u(B, sys, ws, st))) break;
     float ms = 0.f;
     hipError_t e = hipSuccess;
     // the first run warms caches and code; the best of the other two counts
@@ -1002,11 +1045,15 @@ size_t bse_workspace_size(const bse_system* sys, int nsys, int precision, int fl
   Batch B;
   // one system: room for the backward as well; a batch: the forward build,
   // with room for the time-reversal tables where the spheres allow them
-  if (make_batch(sys, nsys, nsys == 1, Tune{}, false, B)) return 0;
+  BatchOpts o;
+  o.backward = nsys == 1;
+  o.pd32 = (flags & BSE_FP32_PAIRDENS) != 0;
+  if (make_batch(sys, nsys, Tune{}, o, B)) return 0;
   size_t total = B.total;
   Batch Bt;
+  o.tr = true;
   const std::string keep = g_err;  // spheres without time reversal are no error here
-  if (make_batch(sys, nsys, nsys == 1, Tune{}, true, Bt) == BSE_OK) total = std::max(total, Bt.total);
+  if (make_batch(sys, nsys, Tune{}, o, Bt) == BSE_OK) total = std::max(total, Bt.total);
   g_err = keep;
   return total;
 }
@@ -1015,7 +1062,7 @@ int bse_pair_density(const bse_system* sys, int kind, const int* kpairs, int npa
                      double* out, void* ws, size_t ws_bytes, void* stream) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   Plan P;
-  int rc = make_plan(sys, P);
+  int rc = make_plan(sys, P, false);
   if (rc) return rc;
   if (!out || !ws) return fail(BSE_ERR_INVALID_ARG, "out / ws is NULL");
   std::vector<PdJob> jobs;
@@ -1063,7 +1110,7 @@ int bse_pair_density(const bse_system* sys, int kind, const int* kpairs, int npa
   } else {
     return fail(BSE_ERR_INVALID_ARG, "unknown kind %d", kind);
   }
-  const size_t lds = pd_lds_bytes(P.N1, P.N2, P.N3, P.F[1], P.F[2], P.ng_max);
+  const size_t lds = pd_lds_bytes(P.N1, P.N2, P.N3, P.F[1], P.F[2], P.ng_max, false);
   if (lds > 160 * 1024) return fail(BSE_ERR_SHAPE, "FFT window needs more than 160 KiB of LDS");
   jobs = dispatch_order(std::move(jobs), Tune{}.ktile);
   // tables: gpack, ng, the one system's arguments, jobs
@@ -1106,7 +1153,7 @@ int bse_pair_density(const bse_system* sys, int kind, const int* kpairs, int npa
   b.njobs = (int)jobs.size();
   b.persist = 0;
   b.cnt = nullptr;
-  HIP_TRY(launch_pair_density(b, P.N2, P.N3, P.ng_max, lds, b.njobs, false, st));
+  HIP_TRY(launch_pair_density(b, P.N2, P.N3, P.ng_max, lds, b.njobs, false, false, st));
   return BSE_OK;
 }
 
@@ -1114,18 +1161,22 @@ int bse_build_H(const bse_system* sys, int nsys, int precision, int flags, void*
   if (!sys || nsys < 1) return fail(BSE_ERR_INVALID_ARG, "no systems");
   if (!ws) return fail(BSE_ERR_INVALID_ARG, "workspace is NULL");
   if (precision < BSE_FP64 || precision > BSE_BF16X3) return fail(BSE_ERR_INVALID_ARG, "bad precision %d", precision);
-  if (flags & ~(BSE_VALIDATE | BSE_PERSISTENT | BSE_TIME_REVERSAL))
+  if (flags & ~(BSE_VALIDATE | BSE_PERSISTENT | BSE_TIME_REVERSAL | BSE_FP32_PAIRDENS))
     return fail(BSE_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+  if ((flags & BSE_FP32_PAIRDENS) && precision == BSE_FP64)
+    return fail(BSE_ERR_INVALID_ARG, "BSE_FP32_PAIRDENS needs a mixed precision (split-FP32 or BF16x3)");
   for (int i = 0; i < nsys; ++i)
     if (!sys[i].H) return fail(BSE_ERR_INVALID_ARG, "H of system %d is NULL", i);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const Batch* Bp = nullptr;
-  const bool tr = (flags & BSE_TIME_REVERSAL) != 0;
-  int rc = cached_batch(sys, nsys, false, Tune{}, tr, &Bp);
+  BatchOpts opt;
+  opt.tr = (flags & BSE_TIME_REVERSAL) != 0;
+  opt.pd32 = (flags & BSE_FP32_PAIRDENS) != 0;
+  int rc = cached_batch(sys, nsys, Tune{}, opt, &Bp);
   if (rc) return rc;
-  Tune tn = tune_for(batch_key(Bp->P, precision));
+  Tune tn = tune_for(batch_key(Bp->P, precision, Bp->pd32));
   if (flags & BSE_PERSISTENT) tn.persist = 1;
-  if (tn.ktile != Tune{}.ktile && (rc = cached_batch(sys, nsys, false, tn, tr, &Bp))) return rc;
+  if (tn.ktile != Tune{}.ktile && (rc = cached_batch(sys, nsys, tn, opt, &Bp))) return rc;
   const Batch& B = *Bp;
   if (ws_bytes < B.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, B.total);
   if (flags & BSE_VALIDATE) {
@@ -1141,9 +1192,12 @@ int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, do
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (!dH || !ws) return fail(BSE_ERR_INVALID_ARG, "dH / ws is NULL");
   if (precision < BSE_FP64 || precision > BSE_BF16X3) return fail(BSE_ERR_INVALID_ARG, "bad precision %d", precision);
-  if (flags & ~BSE_PROJECT_DW) return fail(BSE_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+  if (flags & ~(BSE_PROJECT_DW | BSE_TIME_REVERSAL)) return fail(BSE_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
   Batch B;
-  int rc = make_batch(sys, 1, true, Tune{}, false, B);
+  BatchOpts opt;
+  opt.backward = true;
+  opt.tr = (flags & BSE_TIME_REVERSAL) != 0;
+  int rc = make_batch(sys, 1, Tune{}, opt, B);
   if (rc) return rc;
   const Plan& P = B.P[0];
   if (ws_bytes < B.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, B.total);
@@ -1160,8 +1214,8 @@ int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, do
     HIP_TRY(launch_vscale(sys->vx, P.ng[0], P.ng_max, vs, st));
     if ((rc = run_pd(B, w, 0, Tune{}, st))) return rc;
   }
-  if ((rc = run_pd(B, w, 1, Tune{}, st))) return rc;
-  if ((rc = run_pd(B, w, 2, Tune{}, st))) return rc;
+  for (int kind = 1; kind < 3; ++kind)
+    if ((rc = run_pd(B, w, kind, Tune{}, st)) || (rc = run_tr_fill(B, w, kind, st))) return rc;
   AdjArgs g{};
   g.dH = reinterpret_cast<const double2*>(dH);
   g.RV = reinterpret_cast<const double2*>(r + P.o_RV);
@@ -1207,14 +1261,17 @@ int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, do
   return BSE_OK;
 }
 
-int bse_autotune(const bse_system* sys, int nsys, int precision, const char* cache_path, bse_tuning* chosen,
-                 void* ws, size_t ws_bytes, void* stream) {
+int bse_autotune(const bse_system* sys, int nsys, int precision, int flags, const char* cache_path,
+                 bse_tuning* chosen, void* ws, size_t ws_bytes, void* stream) {
   if (!sys || nsys < 1) return fail(BSE_ERR_INVALID_ARG, "no systems");
   if (!ws) return fail(BSE_ERR_INVALID_ARG, "workspace is NULL");
   if (precision < BSE_FP64 || precision > BSE_BF16X3) return fail(BSE_ERR_INVALID_ARG, "bad precision %d", precision);
+  if (flags & ~BSE_FP32_PAIRDENS) return fail(BSE_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+  if ((flags & BSE_FP32_PAIRDENS) && precision == BSE_FP64)
+    return fail(BSE_ERR_INVALID_ARG, "BSE_FP32_PAIRDENS needs a mixed precision (split-FP32 or BF16x3)");
   Tune t;
-  int rc = autotune(sys, nsys, precision, cache_path, t, static_cast<char*>(ws), ws_bytes,
-                    reinterpret_cast<hipStream_t>(stream));
+  int rc = autotune(sys, nsys, precision, (flags & BSE_FP32_PAIRDENS) != 0, cache_path, t, static_cast<char*>(ws),
+                    ws_bytes, reinterpret_cast<hipStream_t>(stream));
   if (rc) return rc;
   if (chosen) {
     chosen->persistent = t.persist;

@@ -53,6 +53,25 @@ __device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 acc) {
   return make_double2(fma(a.x, b.x, fma(-a.y, b.y, acc.x)), fma(a.x, b.y, fma(a.y, b.x, acc.y)));
 }
 
+// The same in single precision (FP32 pair densities).
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cconjmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 acc) {
+  return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, acc.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, acc.y)));
+}
+
+// Complex value of the type of C from its parts.
+template <class C>
+__device__ __forceinline__ C mkc(double re, double im) {
+  if constexpr (sizeof(C) == 8)
+    return make_float2((float)re, (float)im);
+  else
+    return make_double2(re, im);
+}
+
 // ---------------------------------------------------------------- roots of unity
 // cos(2 pi k / 96) on the first quadrant; every twiddle of a transform whose
 // length divides 96 is one of these up to sign.
@@ -101,31 +120,42 @@ __device__ __forceinline__ void static_for(F&& f) {
 
 // x * exp(-2 pi i K / M), M dividing 96.  Multiples of a quarter and an eighth
 // turn need no general complex product.
-template <int M, int K>
-__device__ __forceinline__ double2 cmul_root(double2 x) {
+template <int M, int K, class C>
+__device__ __forceinline__ C cmul_root(C x) {
   static_assert(96 % M == 0, "transform length must divide 96");
+  using R = decltype(x.x);
   constexpr int k = ((K % M) + M) % M;
-  constexpr double r = 7.07106781186547524401e-1;
+  constexpr R r = (R)7.07106781186547524401e-1;
+  C y;
   if constexpr (k == 0) {
     return x;
   } else if constexpr (2 * k == M) {
-    return make_double2(-x.x, -x.y);
+    y.x = -x.x;
+    y.y = -x.y;
   } else if constexpr (4 * k == M) {  // -i
-    return make_double2(x.y, -x.x);
+    y.x = x.y;
+    y.y = -x.x;
   } else if constexpr (4 * k == 3 * M) {  // +i
-    return make_double2(-x.y, x.x);
+    y.x = -x.y;
+    y.y = x.x;
   } else if constexpr (8 * k == M) {
-    return make_double2(r * (x.x + x.y), r * (x.y - x.x));
+    y.x = r * (x.x + x.y);
+    y.y = r * (x.y - x.x);
   } else if constexpr (8 * k == 3 * M) {
-    return make_double2(r * (x.y - x.x), -r * (x.x + x.y));
+    y.x = r * (x.y - x.x);
+    y.y = -r * (x.x + x.y);
   } else if constexpr (8 * k == 5 * M) {
-    return make_double2(-r * (x.x + x.y), r * (x.x - x.y));
+    y.x = -r * (x.x + x.y);
+    y.y = r * (x.x - x.y);
   } else if constexpr (8 * k == 7 * M) {
-    return make_double2(r * (x.x - x.y), r * (x.x + x.y));
+    y.x = r * (x.x - x.y);
+    y.y = r * (x.x + x.y);
   } else {
-    constexpr double c = cos96(k * (96 / M)), s = -sin96(k * (96 / M));
-    return make_double2(fma(x.x, c, -x.y * s), fma(x.x, s, x.y * c));
+    constexpr R c = (R)cos96(k * (96 / M)), s = (R)-sin96(k * (96 / M));
+    y.x = fma(x.x, c, -x.y * s);
+    y.y = fma(x.x, s, x.y * c);
   }
+  return y;
 }
 
 // ---------------------------------------------------------------- register FFT
@@ -146,8 +176,9 @@ __host__ __device__ constexpr int fft_pos(int f) {
   }
 }
 
-template <int M, int S, int OFF, int N>
-__device__ __forceinline__ void reg_fft(double2 (&x)[N]) {
+template <int M, int S, int OFF, class C, int N>
+__device__ __forceinline__ void reg_fft(C (&x)[N]) {
+  using R = decltype(x[0].x);
   if constexpr (M == 1) {
     return;
   } else if constexpr (M % 2 == 0) {
@@ -157,8 +188,8 @@ __device__ __forceinline__ void reg_fft(double2 (&x)[N]) {
     static_for<0, H>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
       constexpr int pe = OFF + 2 * S * fft_pos<H>(k);  // E_k; O_k sits S further
-      const double2 e = x[pe];
-      const double2 o = cmul_root<M, k>(x[pe + S]);
+      const C e = x[pe];
+      const C o = cmul_root<M, k>(x[pe + S]);
       x[pe] = cadd(e, o);      // output k
       x[pe + S] = csub(e, o);  // output k + H
     });
@@ -168,17 +199,20 @@ __device__ __forceinline__ void reg_fft(double2 (&x)[N]) {
     reg_fft<T, 3 * S, OFF>(x);
     reg_fft<T, 3 * S, OFF + S>(x);
     reg_fft<T, 3 * S, OFF + 2 * S>(x);
-    constexpr double c3 = -0.5;                       // cos(2 pi / 3)
-    constexpr double s3 = 8.66025403784438646764e-1;  // sin(2 pi / 3)
+    constexpr R c3 = (R)-0.5;                        // cos(2 pi / 3)
+    constexpr R s3 = (R)8.66025403784438646764e-1;  // sin(2 pi / 3)
     static_for<0, T>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
       constexpr int pa = OFF + 3 * S * fft_pos<T>(k);
-      const double2 a = x[pa];
-      const double2 b = cmul_root<M, k>(x[pa + S]);
-      const double2 c = cmul_root<M, 2 * k>(x[pa + 2 * S]);
-      const double2 sbc = cadd(b, c), dbc = csub(b, c);
-      const double2 m = make_double2(fma(c3, sbc.x, a.x), fma(c3, sbc.y, a.y));
-      const double2 r = make_double2(s3 * dbc.y, -s3 * dbc.x);  // -i s3 (b - c)
+      const C a = x[pa];
+      const C b = cmul_root<M, k>(x[pa + S]);
+      const C c = cmul_root<M, 2 * k>(x[pa + 2 * S]);
+      const C sbc = cadd(b, c), dbc = csub(b, c);
+      C m, r;
+      m.x = fma(c3, sbc.x, a.x);
+      m.y = fma(c3, sbc.y, a.y);
+      r.x = s3 * dbc.y;  // -i s3 (b - c)
+      r.y = -s3 * dbc.x;
       x[pa] = cadd(a, sbc);         // output k
       x[pa + S] = cadd(m, r);       // output k + T
       x[pa + 2 * S] = csub(m, r);   // output k + 2T

@@ -25,6 +25,7 @@ struct PdArgs {
   int F2, F3;           // kept window widths
   const double* vscale; // [ng_max] output scale (sqrt v) or null
   double2* out;         // rows of ng_max
+  const float2* u32;    // FP32 copy of u (FP32 pair densities) or null
 };
 
 // Jobs of one pair-density launch over a batch of systems that share N2, N3.
@@ -46,12 +47,15 @@ bool pd_grid_supported(int N2, int N3);
 bool pd_line_grid(int N2, int N3);
 // ut[g][j3][j1][j2] = u[g][j1][j2][j3] for ngrids grids of N1 x N2 x N3 (N1, N2 <= 32)
 hipError_t launch_rotate_axes(const double2* u, double2* ut, long long ngrids, int N1, int N2, int N3, hipStream_t st);
-size_t pd_lds_bytes(int N1, int N2, int N3, int F2, int F3, int ng_max);
+size_t pd_lds_bytes(int N1, int N2, int N3, int F2, int F3, int ng_max, bool f32);
+// v = (float) u, n complex values
+hipError_t launch_to_f32(const double2* u, float2* v, size_t n, hipStream_t st);
 // ng_max: the largest of the batch; lds: the largest pd_lds_bytes of the
 // batch; exch: exchange rows (every system's vscale set); grid: njobs for
-// static dispatch, the persistent grid otherwise.
+// static dispatch, the persistent grid otherwise; f32: FP32 transforms from
+// PdArgs.u32 (one-lane-per-line planes and non-exchange rows only).
 hipError_t launch_pair_density(const PdBatch& b, int N2, int N3, int ng_max, size_t lds, int grid, bool exch,
-                               hipStream_t st);
+                               bool f32, hipStream_t st);
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st);
 
 // A GEMM tile of the direct term's first stage: q group iq, tile (mt, nt), system sys.

@@ -219,37 +219,48 @@ __device__ __forceinline__ double2 ldg(const double2* base, unsigned i) {
   const gd2 v = *(const __attribute__((address_space(1))) gd2*)(b + (size_t)(i * 16u));
   return make_double2(v.x, v.y);
 }
+typedef float gf2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ldg(const float2* base, unsigned i) {
+  const auto* b = gbl(reinterpret_cast<const char*>(base));
+  const gf2 v = *(const __attribute__((address_space(1))) gf2*)(b + (size_t)(i * 8u));
+  return make_float2(v.x, v.y);
+}
 
 // Materialise every value of x here: stops the optimiser from sinking the
 // last butterflies into the branches that pick the kept window, which would
 // keep their inputs live across all of them.
-template <int M>
-__device__ __forceinline__ void pin(double2 (&x)[M]) {
+template <class C, int M>
+__device__ __forceinline__ void pin(C (&x)[M]) {
 #pragma unroll
   for (int i = 0; i < M; ++i) asm volatile("" : "+v"(x[i].x), "+v"(x[i].y));
 }
 
-template <int N2, int N3, int TG, bool EXCH>
+// C: double2, or float2 for FP32 pair densities (wave functions read from the
+// FP32 copy, every pass in FP32, the sphere values written as FP64).
+template <int N2, int N3, int TG, bool EXCH, class C>
 __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
   static_assert(N2 <= 32 && N3 <= 32 && N2 % 2 == 0 && N3 % 2 == 0, "lines must fit a half wave");
+  constexpr bool F32 = sizeof(C) == 8;
+  static_assert(!(F32 && EXCH), "exchange pair densities are FP64");
   constexpr int H2 = N2 / 2, H3 = N3 / 2;
   constexpr int S1 = 33;  // T1 row stride: columns N3..31 of idle lanes land in the padding
-  extern __shared__ double2 smem[];
+  extern __shared__ char smem_raw[];
+  C* smem = reinterpret_cast<C*>(smem_raw);
   const int N1 = a.N1, ngm = a.ng_max;
   const int F2 = a.F2, F3 = a.F3;
-  double2* tw1 = smem;
+  C* tw1 = smem;
   // wave index made uniform so that band pointers live in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5, c = lane & 31;
   const int per_pl = F2 * S1;
-  double2* T1 = tw1 + N1 + wave * 2 * per_pl;
+  C* T1 = tw1 + N1 + wave * 2 * per_pl;
   int2* gtab = reinterpret_cast<int2*>(tw1 + N1 + 8 * per_pl);
 
   for (int t = threadIdx.x; t < N1; t += blockDim.x) {
     double s, cs;
     sincospi(2.0 * t / N1, &s, &cs);
-    tw1[t] = make_double2(cs, -s);
+    tw1[t] = mkc<C>(cs, -s);
   }
   const int nA = job.nab & 255, nB = (job.nab >> 8) & 255;
   int m01, m02, m03;
@@ -271,7 +282,7 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
 
   const int Nr = N1 * N2 * N3;
   const int npd = nA * nB;
-  double2* T1h = T1 + h * per_pl;
+  C* T1h = T1 + h * per_pl;
   // with an even number of bands on both sides the four waves of a step take
   // a 2 x 2 block of band pairs (four distinct grids per step instead of five)
   const bool blk = nA % 2 == 0 && nB % 2 == 0;
@@ -282,16 +293,21 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
       ia = 2 * (i / nb2) + (wave >> 1);
       ib = 2 * (i % nb2) + (wave & 1);
     }
-    const double2* ua = a.u + ((size_t)job.ka * a.nb + job.a0 + ia) * Nr;
-    const double2* ub = a.u + ((size_t)job.kb * a.nb + job.b0 + ib) * Nr;
-    double2 acc[TG];
+    const C* u;
+    if constexpr (F32)
+      u = a.u32;
+    else
+      u = a.u;
+    const C* ua = u + ((size_t)job.ka * a.nb + job.a0 + ia) * Nr;
+    const C* ub = u + ((size_t)job.kb * a.nb + job.b0 + ib) * Nr;
+    C acc[TG];
 #pragma unroll
-    for (int t = 0; t < TG; ++t) acc[t] = make_double2(0.0, 0.0);
+    for (int t = 0; t < TG; ++t) acc[t] = mkc<C>(0.0, 0.0);
 
     // even rows of a plane pair (lane: column c of plane j1 + h): issued one
     // plane pair ahead, so that their latency hides behind pass 3
     const int col = c < N3 ? c : 0;
-    double2 pa[H2], pb[H2];
+    C pa[H2], pb[H2];
     auto load_even = [&](int jj) {
       const unsigned o = (unsigned)(col + (jj + 1 < N1 ? jj + h : jj) * (N2 * N3));
 #pragma unroll
@@ -312,7 +328,7 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
       // plane that pass 3 skips)
       {
         const unsigned off = (unsigned)(col + (two ? j1 + h : j1) * (N2 * N3));
-        double2 E[H2], O[H2];
+        C E[H2], O[H2];
 #pragma unroll
         for (int s = 0; s < H2; ++s) E[s] = cconjmul(pa[s], pb[s]);
         __builtin_amdgcn_sched_barrier(0);
@@ -320,7 +336,7 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
         // half after it: at most half the odd rows sit in raw registers next
         // to the even-row transform
         constexpr int HO = H2 / 2;
-        double2 ra[H2], rb[H2];
+        C ra[H2], rb[H2];
 #pragma unroll
         for (int s = 0; s < HO; ++s) {
           ra[s] = ldg(ua, off + (2 * s + 1) * N3);
@@ -357,7 +373,7 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
       {
         const bool ok = c < F2;
         const int row = (ok ? c : 0) * S1;
-        double2 E[H3], O[H3];
+        C E[H3], O[H3];
 #pragma unroll
         for (int s = 0; s < H3; ++s) {
           E[s] = T1h[row + 2 * s];
@@ -375,7 +391,7 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
             r += r < 0 ? N3 : 0;
             r -= r >= N3 ? N3 : 0;
             constexpr int q = fft_pos<H3>(f % H3);
-            const double2 v = cadd(E[q], cmul_root<N3, f>(O[q]));
+            const C v = cadd(E[q], cmul_root<N3, f>(O[q]));
             if (ok) T1h[c * F3 + r] = v;
           }
         });
@@ -410,7 +426,7 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
       const int g = lane + 64 * t;
       if (g < ngq) {
         const double sc = EXCH ? gbl(a.vscale)[g] : 1.0;
-        gst(o, g, make_double2(acc[t].x * sc, acc[t].y * sc));
+        gst(o, g, make_double2((double)acc[t].x * sc, (double)acc[t].y * sc));
       } else if (g < ngm) {
         gst(o, g, make_double2(0.0, 0.0));
       }
@@ -466,7 +482,23 @@ __global__ __launch_bounds__(256, 2) void k_pair_density_line(PdBatch b) {
   for (int j = next_job<PERSIST>(b, round, tries, &s_job); j >= 0; j = next_job<PERSIST>(b, round, tries, &s_job)) {
     const PdJob job = b.jobs[j];
     const PdArgs a = b.sys[job.nab >> 16];
-    pd_line_job<N2, N3, TG, EXCH>(a, job);
+    pd_line_job<N2, N3, TG, EXCH, double2>(a, job);
+    __syncthreads();
+  }
+}
+
+// FP32 variant (valence-valence and conduction-conduction densities of the
+// mixed-precision modes): half the registers, so three workgroups per CU, or
+// four for static dispatch of planes up to 24 x 24 (at 32 x 32, or with the
+// persistent loop, a budget of 128 registers spills).
+template <int N2, int N3, int TG, bool PERSIST>
+__global__ __launch_bounds__(256, (PERSIST || N2 * N3 > 576) ? 3 : 4) void k_pair_density_line_f32(PdBatch b) {
+  __shared__ int s_job;
+  int round = 0, tries = 0;
+  for (int j = next_job<PERSIST>(b, round, tries, &s_job); j >= 0; j = next_job<PERSIST>(b, round, tries, &s_job)) {
+    const PdJob job = b.jobs[j];
+    const PdArgs a = b.sys[job.nab >> 16];
+    pd_line_job<N2, N3, TG, false, float2>(a, job);
     __syncthreads();
   }
 }
@@ -482,19 +514,22 @@ static int tg_bucket(int ng_max) {
 }
 
 template <int N2, int N3>
-static size_t lds_bytes(int N1, int F2, int F3, int ng_max) {
+static size_t lds_bytes(int N1, int F2, int F3, int ng_max, bool f32) {
   if constexpr (use_line<N2, N3>())
-    return sizeof(double2) * ((size_t)N1 + 8 * (size_t)F2 * 33) + sizeof(int2) * (size_t)ng_max;
+    return (f32 ? sizeof(float2) : sizeof(double2)) * ((size_t)N1 + 8 * (size_t)F2 * 33) +
+           sizeof(int2) * (size_t)ng_max;
   using G = PlaneGeo<N2, N3>;
   const int FA = G::AX == 2 ? F2 : F3;
   return sizeof(double2) * ((size_t)N1 + N2 + N3 + 4 * (size_t)G::PW * FA * G::SA) + sizeof(int2) * (size_t)ng_max;
 }
 
 template <int N2, int N3, int TG>
-static hipError_t launch_tg(const PdBatch& b, size_t lds, int grid, bool exch, hipStream_t st) {
+static hipError_t launch_tg(const PdBatch& b, size_t lds, int grid, bool exch, bool f32, hipStream_t st) {
   void (*k)(PdBatch);
   if constexpr (use_line<N2, N3>()) {
-    if (b.persist)
+    if (f32 && !exch)
+      k = b.persist ? k_pair_density_line_f32<N2, N3, TG, true> : k_pair_density_line_f32<N2, N3, TG, false>;
+    else if (b.persist)
       k = exch ? k_pair_density_line<N2, N3, TG, true, true> : k_pair_density_line<N2, N3, TG, false, true>;
     else
       k = exch ? k_pair_density_line<N2, N3, TG, true, false> : k_pair_density_line<N2, N3, TG, false, false>;
@@ -511,13 +546,14 @@ static hipError_t launch_tg(const PdBatch& b, size_t lds, int grid, bool exch, h
 }
 
 template <int N2, int N3>
-static hipError_t launch_grid(const PdBatch& b, int ng_max, size_t lds, int grid, bool exch, hipStream_t st) {
+static hipError_t launch_grid(const PdBatch& b, int ng_max, size_t lds, int grid, bool exch, bool f32,
+                              hipStream_t st) {
   switch (tg_bucket(ng_max)) {
-    case 4: return launch_tg<N2, N3, 4>(b, lds, grid, exch, st);
-    case 5: return launch_tg<N2, N3, 5>(b, lds, grid, exch, st);
-    case 8: return launch_tg<N2, N3, 8>(b, lds, grid, exch, st);
-    case 13: return launch_tg<N2, N3, 13>(b, lds, grid, exch, st);
-    default: return launch_tg<N2, N3, 16>(b, lds, grid, exch, st);
+    case 4: return launch_tg<N2, N3, 4>(b, lds, grid, exch, f32, st);
+    case 5: return launch_tg<N2, N3, 5>(b, lds, grid, exch, f32, st);
+    case 8: return launch_tg<N2, N3, 8>(b, lds, grid, exch, f32, st);
+    case 13: return launch_tg<N2, N3, 13>(b, lds, grid, exch, f32, st);
+    default: return launch_tg<N2, N3, 16>(b, lds, grid, exch, f32, st);
   }
 }
 
@@ -561,9 +597,23 @@ hipError_t launch_rotate_axes(const double2* u, double2* ut, long long ngrids, i
   return hipGetLastError();
 }
 
-size_t pd_lds_bytes(int N1, int N2, int N3, int F2, int F3, int ng_max) {
+// FP32 copy of the wave functions for the FP32 pair densities (round to nearest).
+__global__ __launch_bounds__(256) void k_to_f32(const double2* __restrict__ u, float2* __restrict__ v, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const double2 x = u[i];
+    v[i] = make_float2((float)x.x, (float)x.y);
+  }
+}
+
+hipError_t launch_to_f32(const double2* u, float2* v, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_to_f32, dim3(4096), dim3(256), 0, st, u, v, n);
+  return hipGetLastError();
+}
+
+size_t pd_lds_bytes(int N1, int N2, int N3, int F2, int F3, int ng_max, bool f32) {
 #define BSE_PD_LDS(X, Y) \
-  if (N2 == X && N3 == Y) return lds_bytes<X, Y>(N1, F2, F3, ng_max);
+  if (N2 == X && N3 == Y) return lds_bytes<X, Y>(N1, F2, F3, ng_max, f32);
   BSE_PD_LDS(8, 8)
   BSE_PD_LDS(12, 12)
   BSE_PD_LDS(16, 16)
@@ -581,10 +631,10 @@ size_t pd_lds_bytes(int N1, int N2, int N3, int F2, int F3, int ng_max) {
 
 // exch: the launch computes exchange rows (every system's PdArgs.vscale set).
 hipError_t launch_pair_density(const PdBatch& b, int N2, int N3, int ng_max, size_t lds, int grid, bool exch,
-                               hipStream_t st) {
+                               bool f32, hipStream_t st) {
   if (b.njobs <= 0 || grid <= 0) return hipSuccess;
 #define BSE_PD_CASE(X, Y) \
-  if (N2 == X && N3 == Y) return launch_grid<X, Y>(b, ng_max, lds, grid, exch, st);
+  if (N2 == X && N3 == Y) return launch_grid<X, Y>(b, ng_max, lds, grid, exch, f32, st);
   BSE_PD_CASE(8, 8)
   BSE_PD_CASE(12, 12)
   BSE_PD_CASE(16, 16)

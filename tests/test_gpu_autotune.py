@@ -48,3 +48,29 @@ def test_autotune_choice_cache_and_results(tmp_path):
     torch.cuda.synchronize()
     for d, h in zip(devs, before):
         assert torch.equal(d.H, h)
+
+
+def test_autotune_fp32_pairdens_separate_key(tmp_path):
+    """Tuning the FP32 pair-density kernel writes its own cache line and leaves
+    the FP64 build unchanged; the FP32 build after tuning is bit-identical to
+    the one before (the dispatch changes the order, not the arithmetic)."""
+    import paper_1206_3518_amd as P
+    import torch
+    s = B.make_system(B.cell_sc(10.0), (16, 16, 16), (2, 2, 2), 2, 2, 3.0, seed=53)
+    d = P.DeviceSystem(s)
+    ws = P.workspace(P.bse_workspace_size([d], P.BSE_BF16X3, P.BSE_FP32_PAIRDENS))
+    P.bse_build_H([d], P.BSE_BF16X3, P.BSE_FP32_PAIRDENS, ws)
+    torch.cuda.synchronize()
+    before = d.H.clone()
+    cache = tmp_path / "tune.jsonl"
+    P.bse_autotune([d], P.BSE_BF16X3, cache, ws)
+    got = P.bse_autotune([d], P.BSE_BF16X3, cache, ws, flags=P.BSE_FP32_PAIRDENS)
+    print("FP32 autotune choice:", got, flush=True)
+    lines = [json.loads(x) for x in cache.read_text().splitlines()]
+    assert len(lines) == 2 and lines[0]["key"] != lines[1]["key"] and "f32" in lines[1]["key"]
+    d.H.zero_()
+    P.bse_build_H([d], P.BSE_BF16X3, P.BSE_FP32_PAIRDENS, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(d.H, before)
+    with pytest.raises(P.BseError):
+        P.bse_autotune([d], P.BSE_FP64, None, ws, flags=P.BSE_FP32_PAIRDENS)

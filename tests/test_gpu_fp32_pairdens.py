@@ -1,0 +1,80 @@
+"""BSE_FP32_PAIRDENS: the valence-valence and conduction-conduction pair
+densities of the mixed-precision modes transformed in FP32.  Checked against
+the FP64 build to the mixed-precision bar (max |dH| <= 1e-4 eV and <= 1e-3 of
+the largest kernel element, lowest exciton energies within 1e-4 eV)."""
+import sys
+
+import numpy as np
+import pytest
+
+import bse_synth as B
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _check(devs, H64, tag):
+    import torch
+    for i, (d, h) in enumerate(zip(devs, H64)):
+        K = h - torch.diag(torch.diag(h))
+        kmax = K.abs().max().item()
+        dH = (d.H - h).abs().max().item()
+        dE = (torch.linalg.eigvalsh(d.H)[:10] - torch.linalg.eigvalsh(h)[:10]).abs().max().item()
+        _say(f"  {tag} system {i}: max|dH| {dH:.3e} eV = {dH / kmax:.2e} of max|K|, lowest-10 dE {dE:.2e} eV")
+        assert dH <= 1e-4 and dH <= 1e-3 * kmax
+        assert dE <= 1e-4
+
+
+def _run(systems, flags=0, tr_inputs=False):
+    import paper_1206_3518_amd as P
+    import torch
+    devs = [P.DeviceSystem(s) for s in systems]
+    ws = P.workspace(P.bse_workspace_size(devs, P.BSE_SPLIT_FP32, P.BSE_FP32_PAIRDENS))
+    P.bse_build_H(devs, P.BSE_FP64, flags, ws)
+    torch.cuda.synchronize()
+    H64 = [d.H.clone() for d in devs]
+    for prec, name in ((P.BSE_SPLIT_FP32, "split-FP32"), (P.BSE_BF16X3, "BF16x3")):
+        for d in devs:
+            d.H.fill_(float("nan"))
+        P.bse_build_H(devs, prec, flags | P.BSE_FP32_PAIRDENS, ws)
+        torch.cuda.synchronize()
+        _check(devs, H64, name + " + FP32 densities")
+
+
+def test_fp32_pairdens_ragged_cubic_batch():
+    _run([
+        B.make_system(B.cell_sc(10.0), (16, 16, 16), (2, 2, 2), 2, 2, 3.0, seed=41),
+        B.make_system(B.cell_fcc(9.0), (16, 16, 16), (3, 1, 1), 1, 3, 2.0, seed=42),
+        B.make_system(B.cell_sc(9.5), (16, 16, 16), (2, 2, 1), 3, 1, 4.0, seed=43),
+    ])
+
+
+def test_fp32_pairdens_hbn_rotated_persistent():
+    import paper_1206_3518_amd as P
+    _run(B.make_hbn_batch(7, nsys=3, ecut=1.5, nv=2, nc=2, meshes=[2, 3, 1]), flags=P.BSE_PERSISTENT)
+
+
+def test_fp32_pairdens_with_time_reversal():
+    import paper_1206_3518_amd as P
+    _run([B.make_system(B.cell_sc(10.0), (16, 16, 16), (4, 3, 1), 2, 2, 3.0, seed=86, time_reversal=True)],
+         flags=P.BSE_TIME_REVERSAL)
+
+
+def test_fp32_pairdens_full_size_si():
+    """Si-like 32^3 grid, 8^3 k mesh, 4+4 bands (H 8192 x 8192), in the launch
+    configuration the benchmark times."""
+    _run([B.make_config(2)])
+
+
+def test_fp32_pairdens_needs_mixed_precision():
+    import paper_1206_3518_amd as P
+    s = B.make_system(B.cell_sc(10.0), (16, 16, 16), (1, 1, 1), 1, 1, 2.0, seed=1)
+    d = P.DeviceSystem(s)
+    ws = P.workspace(P.bse_workspace_size([d], P.BSE_FP64, P.BSE_FP32_PAIRDENS))
+    with pytest.raises(P.BseError) as e:
+        P.bse_build_H([d], P.BSE_FP64, P.BSE_FP32_PAIRDENS, ws)
+    assert e.value.code == -1 and "mixed" in str(e.value)

@@ -130,3 +130,25 @@ def test_tr_full_size_si():
     for (ka, kb), r in zip(blocks, ref):
         g = d.H[ka * nt:(ka + 1) * nt, kb * nt:(kb + 1) * nt].cpu().numpy()
         assert np.abs(g - r).max() <= 1e-12 * max(np.abs(r).max(), 1.0), (ka, kb)
+
+
+def test_tr_backward_matches_general_backward():
+    """The adjoint recomputes the pair densities; under BSE_TIME_REVERSAL the
+    image pairs are gathered there too, with the same gradients."""
+    import paper_1206_3518_amd as P
+    import torch
+    s = B.make_system(B.cell_sc(10.0), (16, 16, 16), (4, 3, 1), 2, 2, 3.0, seed=85, time_reversal=True)
+    d = P.DeviceSystem(s)
+    g = torch.Generator().manual_seed(3)
+    G = torch.complex(torch.randn(s.ns, s.ns, generator=g, dtype=torch.float64),
+                      torch.randn(s.ns, s.ns, generator=g, dtype=torch.float64)).to(d.device)
+    ws = P.workspace(P.bse_workspace_size([d]))
+    for flags in (0, P.BSE_PROJECT_DW):
+        ref = P.bse_build_H_backward(d, G, flags=flags, ws=ws, want_densities=True)
+        ref = [x.clone() for x in ref]
+        got = P.bse_build_H_backward(d, G, flags=flags | P.BSE_TIME_REVERSAL, ws=ws, want_densities=True)
+        torch.cuda.synchronize()
+        for name, a, b in zip(("dW", "deps", "dX", "drho_vv", "drho_cc"), got, ref):
+            err = (a - b).abs().max().item()
+            _say(f"  flags {flags}: {name} max diff {err:.3e} (max {b.abs().max().item():.3e})")
+            assert err <= 1e-12 * max(b.abs().max().item(), 1e-30), name
