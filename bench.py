@@ -217,6 +217,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner (default dispatch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the split-FP32 / BF16x3 comparison runs")
+    ap.add_argument("--fp32-pairdens", action="store_true",
+                    help="FP32 pair densities in the timed run (with --precision split_fp32 or bf16x3)")
     ap.add_argument("--no-time-reversal", action="store_true",
                     help="skip the run on time-reversal symmetric inputs with BSE_TIME_REVERSAL")
     ap.add_argument("--gradcheck", action="store_true",
@@ -240,7 +242,12 @@ def main():
     devs = [P.DeviceSystem(s, device="cuda:0") for s in systems]
     prec = P.PRECISIONS[args.precision]
     flags = P.BSE_PERSISTENT if args.persistent else 0
-    ws = P.workspace(P.bse_workspace_size(devs, prec), devs[0].device)
+    if args.fp32_pairdens:
+        if args.precision == "fp64":
+            print(json.dumps({"error": "--fp32-pairdens needs --precision split_fp32 or bf16x3"}))
+            sys.exit(2)
+        flags |= P.BSE_FP32_PAIRDENS
+    ws = P.workspace(P.bse_workspace_size(devs, prec, flags), devs[0].device)
     torch.cuda.synchronize()
 
     if args.copy_calibration_mb:
@@ -253,7 +260,7 @@ def main():
 
     tuning = None
     if not args.no_autotune and not args.persistent:
-        tuning = P.bse_autotune(devs, prec, None, ws)  # outside the timed region
+        tuning = P.bse_autotune(devs, prec, None, ws, flags=flags & P.BSE_FP32_PAIRDENS)  # outside the timed region
         tried = P.bse_autotune_last()
     ms, wall, stages = run_steps(P, devs, prec, flags, ws, args.steps, args.warmup)
     elements = float(sum(float(s.ns) ** 2 for s in systems))
@@ -280,10 +287,15 @@ def main():
     avg_s = pd_ms / pd_n / 1e3
     achieved = pd_flops(grid) * units / avg_s / 1e12
     digest = kernel_source_digest()
-    line = grid[1] <= 32 and grid[2] <= 32 and grid[1] % 2 == 0 and grid[2] % 2 == 0
-    roofline = {"bound": "alu", "kernel": "k_pair_density_line" if line else "k_pair_density", "achieved": achieved,
-                "peak": PEAK["fp64_TFLOPs"], "unit": "TFLOP/s", "frac": achieved / PEAK["fp64_TFLOPs"],
-                "traffic": traffic_from_profile(digest, units) if args.config == 2 else None,
+    def line_planes(n2, n3):
+        return n2 <= 32 and n3 <= 32 and n2 % 2 == 0 and n3 % 2 == 0
+    line = line_planes(grid[1], grid[2]) or line_planes(grid[0], grid[1])  # directly or in the rotated frame
+    f32 = args.fp32_pairdens and line
+    peak = PEAK["fp32_TFLOPs"] if f32 else PEAK["fp64_TFLOPs"]
+    kname = "k_pair_density_line_f32" if f32 else "k_pair_density_line" if line else "k_pair_density"
+    roofline = {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak,
+                "traffic": traffic_from_profile(digest, units) if args.config == 2 and not f32 else None,
                 "avg_launch_ms": pd_ms / pd_n, "flops_per_launch": pd_flops(grid) * units, "kernel_digest": digest}
 
     if len(systems) == 1:
@@ -306,7 +318,8 @@ def main():
     out = {"metric": "BSE H build: elements/s + % MFMA peak, FP64 vs mixed at <=1e-4 eV error",
            "value": value, "unit": "H elements/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": DTYPES[args.precision], "data": "synthetic", "config": config,
+           "dtype": DTYPES[args.precision] + ("+f32 pair densities" if args.fp32_pairdens else ""),
+           "data": "synthetic", "config": config,
            "stage_ms": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
            "gemm": gemm_report(stages, args.precision),
            "wall_s": wall, "roofline": roofline}
@@ -331,7 +344,11 @@ def main():
             dH = max((d.H - h).abs().max().item() for d, h in zip(devs, H64))
             dE = max(float(np.abs(torch.linalg.eigvalsh(d.H)[:10].cpu().numpy() - e).max())
                      for d, e in zip(devs, E64))
+            pdm = (stm["pd_vv"][0] + stm["pd_cc"][0]) / max(stm["pd_vv"][1] + stm["pd_cc"][1], 1)
             mixed[name] = {"value": elements / (msm / 1e3), "ms_per_step": msm, "speedup_vs_fp64": ms / msm,
+                           "pair_density_launch": {
+                               "avg_launch_ms": pdm, "nominal_TFLOPs": pd_flops(grid) * units / (pdm / 1e3) / 1e12,
+                               "arithmetic": "fp32" if mflags else "fp64"},
                            "max_abs_dH_eV": dH, "max_abs_dH_over_kernel": dH / kscale,
                            "max_abs_dE_lowest10_eV": dE,
                            "stage_ms": {k: v[0] / max(v[1], 1) for k, v in stm.items()},
