@@ -237,7 +237,7 @@ __device__ __forceinline__ void pin(C (&x)[M]) {
 
 // C: double2, or float2 for FP32 pair densities (wave functions read from the
 // FP32 copy, every pass in FP32, the sphere values written as FP64).
-template <int N2, int N3, int TG, bool EXCH, class C>
+template <int N2, int N3, int TG, bool EXCH, class C, bool PF>
 __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
   static_assert(N2 <= 32 && N3 <= 32 && N2 % 2 == 0 && N3 % 2 == 0, "lines must fit a half wave");
   constexpr bool F32 = sizeof(C) == 8;
@@ -304,8 +304,8 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
 #pragma unroll
     for (int t = 0; t < TG; ++t) acc[t] = mkc<C>(0.0, 0.0);
 
-    // even rows of a plane pair (lane: column c of plane j1 + h): issued one
-    // plane pair ahead, so that their latency hides behind pass 3
+    // even rows of a plane pair (lane: column c of plane j1 + h): with PF issued
+    // one plane pair ahead, so that their latency hides behind pass 3
     const int col = c < N3 ? c : 0;
     C pa[H2], pb[H2];
     auto load_even = [&](int jj) {
@@ -316,8 +316,9 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
         pb[s] = ldg(ub, o + 2 * s * N3);
       }
     };
-    load_even(0);
+    if constexpr (PF) load_even(0);
     for (int j1 = 0; j1 < N1; j1 += 2) {
+      if constexpr (!PF) load_even(j1);
       const bool two = j1 + 1 < N1;  // the second plane exists
       // window masks and origins re-read per plane: kept loop-invariant they
       // would pin one scalar condition per frequency across the loop
@@ -399,7 +400,7 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
       wave_sync();
       // next plane pair, in flight during pass 3 (unconditional, so that the
       // values just consumed are dead; the last pair re-reads a valid plane)
-      load_even(j1 + 2 < N1 ? j1 + 2 : j1);
+      if constexpr (PF) load_even(j1 + 2 < N1 ? j1 + 2 : j1);
       __builtin_amdgcn_sched_barrier(0);
       // ---- pass 3
 #pragma unroll
@@ -482,23 +483,23 @@ __global__ __launch_bounds__(256, 2) void k_pair_density_line(PdBatch b) {
   for (int j = next_job<PERSIST>(b, round, tries, &s_job); j >= 0; j = next_job<PERSIST>(b, round, tries, &s_job)) {
     const PdJob job = b.jobs[j];
     const PdArgs a = b.sys[job.nab >> 16];
-    pd_line_job<N2, N3, TG, EXCH, double2>(a, job);
+    pd_line_job<N2, N3, TG, EXCH, double2, true>(a, job);
     __syncthreads();
   }
 }
 
 // FP32 variant (valence-valence and conduction-conduction densities of the
-// mixed-precision modes): half the registers, so three workgroups per CU, or
-// four for static dispatch of planes up to 24 x 24 (at 32 x 32, or with the
-// persistent loop, a budget of 128 registers spills).
+// mixed-precision modes): half the registers, so no next-plane prefetch (the
+// occupancy hides the load latency instead): four workgroups per CU under
+// static dispatch, three with the persistent loop, which needs more registers.
 template <int N2, int N3, int TG, bool PERSIST>
-__global__ __launch_bounds__(256, (PERSIST || N2 * N3 > 576) ? 3 : 4) void k_pair_density_line_f32(PdBatch b) {
+__global__ __launch_bounds__(256, PERSIST ? 3 : 4) void k_pair_density_line_f32(PdBatch b) {
   __shared__ int s_job;
   int round = 0, tries = 0;
   for (int j = next_job<PERSIST>(b, round, tries, &s_job); j >= 0; j = next_job<PERSIST>(b, round, tries, &s_job)) {
     const PdJob job = b.jobs[j];
     const PdArgs a = b.sys[job.nab >> 16];
-    pd_line_job<N2, N3, TG, false, float2>(a, job);
+    pd_line_job<N2, N3, TG, false, float2, false>(a, job);
     __syncthreads();
   }
 }
