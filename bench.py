@@ -370,7 +370,8 @@ def main():
 def time_reversal_leg(P, args, prec, flags, elements, ms_general):
     """The same workload with wave functions that obey time reversal, built
     with BSE_TIME_REVERSAL (half the pair-density transforms, the rest
-    gathered) and once without it for comparison (untimed)."""
+    gathered) and once without it for comparison (untimed); after an FP64
+    main run also with BF16x3 contractions and FP32 pair densities."""
     import torch
     import bse_synth as B
     made = B.make_config(args.config, time_reversal=True)
@@ -382,10 +383,25 @@ def time_reversal_leg(P, args, prec, flags, elements, ms_general):
     Hg = [d.H.clone() for d in devs]
     ms, _, stages = run_steps(P, devs, prec, flags | P.BSE_TIME_REVERSAL, ws, args.steps, args.warmup)
     dH = max((d.H - h).abs().max().item() for d, h in zip(devs, Hg))
-    return {"value": elements / (ms / 1e3), "unit": "H elements/s", "ms_per_step": ms,
-            "speedup_vs_general": ms_general / ms, "max_abs_dH_vs_general_eV": dH,
-            "stage_ms": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
-            "inputs": "same shapes and generator, u at -k the time-reversal image of u at k"}
+    out = {"value": elements / (ms / 1e3), "unit": "H elements/s", "ms_per_step": ms,
+           "speedup_vs_general": ms_general / ms, "max_abs_dH_vs_general_eV": dH,
+           "stage_ms": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
+           "inputs": "same shapes and generator, u at -k the time-reversal image of u at k"}
+    if prec == P.BSE_FP64 and not args.no_mixed:
+        # with BF16x3 contractions and FP32 pair densities as well
+        f = flags | P.BSE_TIME_REVERSAL | P.BSE_FP32_PAIRDENS
+        del ws
+        ws = P.workspace(P.bse_workspace_size(devs, P.BSE_BF16X3, P.BSE_FP32_PAIRDENS), devs[0].device)
+        if not args.no_autotune and not args.persistent:
+            P.bse_autotune(devs, P.BSE_BF16X3, None, ws, flags=P.BSE_FP32_PAIRDENS)
+        mm, _, sm = run_steps(P, devs, P.BSE_BF16X3, f, ws, max(2, args.steps // 2), 1)
+        K = max((h - torch.diag(torch.diag(h))).abs().max().item() for h in Hg)
+        dm = max((d.H - h).abs().max().item() for d, h in zip(devs, Hg))
+        out["bf16x3+fp32_pairdens"] = {
+            "value": elements / (mm / 1e3), "ms_per_step": mm, "speedup_vs_general_fp64": ms_general / mm,
+            "max_abs_dH_vs_fp64_eV": dm, "max_abs_dH_over_kernel": dm / K,
+            "stage_ms": {k: v[0] / max(v[1], 1) for k, v in sm.items()}}
+    return out
 
 
 if __name__ == "__main__":
