@@ -184,7 +184,8 @@ int bse_build_H(const bse_system *sys, int nsys, int precision, int flags,
  * Hermitian, time-reversal symmetric W on which that map and the all-blocks
  * definition agree.  With BSE_TIME_REVERSAL the recomputed pair densities
  * use the time-reversal images as in bse_build_H (same contract on u, not
- * checked here).  precision selects the arithmetic of the dW contraction
+ * checked here); with BSE_FP32_PAIRDENS (mixed precisions only) the valence
+ * and conduction densities are recomputed in FP32 as in bse_build_H.  precision selects the arithmetic of the dW contraction
  * (its q = 0 head entry is FP64 in every mode); the density gradients are
  * FP64.  sys->H is not read.
  */

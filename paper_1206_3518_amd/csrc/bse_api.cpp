@@ -1192,11 +1192,15 @@ int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, do
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (!dH || !ws) return fail(BSE_ERR_INVALID_ARG, "dH / ws is NULL");
   if (precision < BSE_FP64 || precision > BSE_BF16X3) return fail(BSE_ERR_INVALID_ARG, "bad precision %d", precision);
-  if (flags & ~(BSE_PROJECT_DW | BSE_TIME_REVERSAL)) return fail(BSE_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+  if (flags & ~(BSE_PROJECT_DW | BSE_TIME_REVERSAL | BSE_FP32_PAIRDENS))
+    return fail(BSE_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+  if ((flags & BSE_FP32_PAIRDENS) && precision == BSE_FP64)
+    return fail(BSE_ERR_INVALID_ARG, "BSE_FP32_PAIRDENS needs a mixed precision (split-FP32 or BF16x3)");
   Batch B;
   BatchOpts opt;
   opt.backward = true;
   opt.tr = (flags & BSE_TIME_REVERSAL) != 0;
+  opt.pd32 = (flags & BSE_FP32_PAIRDENS) != 0;
   int rc = make_batch(sys, 1, Tune{}, opt, B);
   if (rc) return rc;
   const Plan& P = B.P[0];
@@ -1208,7 +1212,7 @@ int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, do
   if ((rc = upload_batch(B, sys, precision, w, st))) return rc;
   // recompute the pair densities (exchange ones only for dX)
   char* r = w + B.base[0];
-  if ((rc = rotate_if_needed(P, *sys, r, st))) return rc;
+  if ((rc = prepare_u(B, sys, w, st))) return rc;
   if (dX) {
     double* vs = reinterpret_cast<double*>(r + P.o_vs);
     HIP_TRY(launch_vscale(sys->vx, P.ng[0], P.ng_max, vs, st));

@@ -78,3 +78,28 @@ def test_fp32_pairdens_needs_mixed_precision():
     with pytest.raises(P.BseError) as e:
         P.bse_build_H([d], P.BSE_FP64, P.BSE_FP32_PAIRDENS, ws)
     assert e.value.code == -1 and "mixed" in str(e.value)
+
+
+def test_fp32_pairdens_backward():
+    """The adjoint with FP32 recomputed densities against the one with FP64
+    densities (same split-FP32 dW contraction): within 1e-4 of each output's
+    largest entry; FP32 densities need a mixed precision here too."""
+    import paper_1206_3518_amd as P
+    import torch
+    s = B.make_system(B.cell_sc(10.0), (16, 16, 16), (3, 2, 1), 2, 2, 3.0, seed=87)
+    d = P.DeviceSystem(s)
+    g = torch.Generator().manual_seed(4)
+    G = torch.complex(torch.randn(s.ns, s.ns, generator=g, dtype=torch.float64),
+                      torch.randn(s.ns, s.ns, generator=g, dtype=torch.float64)).to(d.device)
+    ws = P.workspace(P.bse_workspace_size([d], P.BSE_SPLIT_FP32, P.BSE_FP32_PAIRDENS))
+    ref = [x.clone() for x in P.bse_build_H_backward(d, G, precision=P.BSE_SPLIT_FP32, ws=ws, want_densities=True)]
+    got = P.bse_build_H_backward(d, G, precision=P.BSE_SPLIT_FP32, flags=P.BSE_FP32_PAIRDENS, ws=ws,
+                                 want_densities=True)
+    torch.cuda.synchronize()
+    for name, a, b in zip(("dW", "deps", "dX", "drho_vv", "drho_cc"), got, ref):
+        err = (a - b).abs().max().item()
+        scale = b.abs().max().item()
+        _say(f"  {name}: max diff {err:.3e} (max {scale:.3e})")
+        assert err <= 1e-4 * scale, name
+    with pytest.raises(P.BseError):
+        P.bse_build_H_backward(d, G, precision=P.BSE_FP64, flags=P.BSE_FP32_PAIRDENS, ws=ws)
