@@ -139,6 +139,8 @@ void fold(const int* n, int ka, int kb, int& iq, int m0[3]) {
 // XCD x; persistent dispatch uses chunk x as the XCD's queue).  Holes become
 // empty jobs.
 constexpr int kXcds = 8;
+// queue counters of the three pair-density kinds, then the validation flags
+constexpr size_t kCntBytes = 3 * kXcds * kQueueStride * sizeof(unsigned);
 
 std::vector<PdJob> dispatch_order(std::vector<PdJob> jobs, int ktile) {
   std::stable_sort(jobs.begin(), jobs.end(), [ktile](const PdJob& x, const PdJob& y) {
@@ -630,7 +632,7 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
   B.o_tra = put(tr ? nsys * sizeof(TrArgs) : 0);
   B.o_fill = put(B.fill.size() * sizeof(int4));
   // the tables above are uploaded as one image [0, o_cnt); the counters are not
-  B.o_cnt = put(3 * kXcds * sizeof(unsigned) + 32 + 8 * sizeof(unsigned long long));  // queues, validation
+  B.o_cnt = put(kCntBytes + 32 + 8 * sizeof(unsigned long long));  // queues, validation
   B.base.resize(nsys);
   for (int i = 0; i < nsys; ++i) {
     B.base[i] = o;
@@ -799,12 +801,12 @@ int run_pd(const Batch& B, char* ws, int kind, const Tune& tn, hipStream_t st) {
   b.jobs = reinterpret_cast<const PdJob*>(ws + o_jobs);
   b.njobs = (int)jobs.size();
   b.persist = tn.persist;
-  b.cnt = reinterpret_cast<unsigned*>(ws + B.o_cnt) + kind * kXcds;
+  b.cnt = reinterpret_cast<unsigned*>(ws + B.o_cnt) + (size_t)kind * kXcds * kQueueStride;
   const int stage_id = kind == 0 ? BSE_STAGE_PD_EXCH : kind == 1 ? BSE_STAGE_PD_VV : BSE_STAGE_PD_CC;
   const bool f32 = B.pd32 && kind != 0;
   const size_t lds = f32 ? B.lds32 : B.lds;
   const int grid = tn.persist ? persistent_grid(lds, b.njobs, tn.wg_per_cu) : b.njobs;
-  if (tn.persist) HIP_TRY(launch_zero_u32(b.cnt, kXcds, st));
+  if (tn.persist) HIP_TRY(launch_zero_u32(b.cnt, kXcds * kQueueStride, st));
   HIP_TRY(stage(stage_id, st, [&] {
     return launch_pair_density(b, B.N2, B.N3, B.ng_max, lds, grid, kind == 0, f32, st);
   }));
@@ -881,8 +883,8 @@ int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& 
 
 // BSE_VALIDATE: scans every system's inputs and waits for the result.
 int validate(const Batch& B, const bse_system* sys, char* ws, hipStream_t st) {
-  unsigned* bad = reinterpret_cast<unsigned*>(ws + B.o_cnt + 3 * kXcds * sizeof(unsigned));
-  unsigned long long* wstat = reinterpret_cast<unsigned long long*>(ws + B.o_cnt + 3 * kXcds * sizeof(unsigned) + 32);
+  unsigned* bad = reinterpret_cast<unsigned*>(ws + B.o_cnt + kCntBytes);
+  unsigned long long* wstat = reinterpret_cast<unsigned long long*>(ws + B.o_cnt + kCntBytes + 32);
   for (size_t i = 0; i < B.P.size(); ++i) {
     const Plan& P = B.P[i];
     const bse_system& s = sys[i];

@@ -202,7 +202,8 @@ template <int P, bool CONJ_A, bool B_T, bool A_T = false>
 __device__ __forceinline__ void tile_gemm_mx(const double2* __restrict__ A, int lda, int a_off, int a_lim,
                                              const double2* __restrict__ B, int ldb, int b_off, int b_lim, int K,
                                              bool zero_head, f4 (&cre)[2][2], f4 (&cim)[2][2]) {
-  extern __shared__ char smem_mx[];
+  extern __shared__ double2 smem_mx_raw[];  // 16-byte aligned dynamic area
+  char* smem_mx = reinterpret_cast<char*>(smem_mx_raw);
   TileLds<P>& As = *reinterpret_cast<TileLds<P>*>(smem_mx);
   TileLds<P>& Bs = *reinterpret_cast<TileLds<P>*>(smem_mx + sizeof(TileLds<P>));
   constexpr int ST = TileLds<P>::STRIDE;

@@ -34,12 +34,17 @@ struct PdArgs {
 // on), whose t-th job is jobs[8 t + queue], by an atomic counter per queue,
 // then takes jobs from the other queues until all are drained.  njobs is a
 // multiple of 8 in both modes.
+// Queue counters of persistent dispatch sit kQueueStride unsigned apart, each
+// on a 256-byte line of its own, so that the queues of different XCDs share
+// no cache line.
+constexpr int kQueueStride = 64;
+
 struct PdBatch {
   const PdArgs* sys;    // [nsys] per-system arguments (device)
   const PdJob* jobs;    // [njobs]
   int njobs;
   int persist;
-  unsigned* cnt;        // [8] queue counters, zero at launch (persistent only)
+  unsigned* cnt;        // queue x at cnt[x * kQueueStride], x < 8, zero at launch (persistent only)
 };
 
 bool pd_grid_supported(int N2, int N3);

@@ -244,7 +244,9 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
   static_assert(!(F32 && EXCH), "exchange pair densities are FP64");
   constexpr int H2 = N2 / 2, H3 = N3 / 2;
   constexpr int S1 = 33;  // T1 row stride: columns N3..31 of idle lanes land in the padding
-  extern __shared__ char smem_raw[];
+  // declared as double2 for its 16-byte alignment: the dynamic area follows
+  // the static job word of the persistent loop
+  extern __shared__ double2 smem_raw[];
   C* smem = reinterpret_cast<C*>(smem_raw);
   const int N1 = a.N1, ngm = a.ng_max;
   const int F2 = a.F2, F3 = a.F3;
@@ -449,7 +451,7 @@ __device__ __forceinline__ int next_job(const PdBatch& b, int& round, int& tries
     int got = -1;
     while (tries < 8) {
       const int x = (home + tries) & 7;
-      const int t = (int)atomicAdd(&b.cnt[x], 1u);
+      const int t = (int)atomicAdd(&b.cnt[x * kQueueStride], 1u);
       if (t < per_q) {
         got = 8 * t + x;
         break;
