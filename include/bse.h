@@ -56,9 +56,11 @@ enum bse_status {
                                   time-reversal symmetric                        */
 };
 
-/* Arithmetic of the two dense contractions (exchange and direct term).
- * Pair densities (unless BSE_FP32_PAIRDENS), the transition-energy diagonal
- * and the q = 0 head of W are FP64. */
+/* Arithmetic of the two dense contractions: the exchange and the first stage
+ * of the direct term (conj(rho_vv')^T W(q) per q).  The second stage of the
+ * direct term (one pass over its operands, bound by memory bandwidth), the
+ * pair densities (unless BSE_FP32_PAIRDENS), the transition-energy diagonal
+ * and the q = 0 head of W are FP64 in every mode. */
 enum bse_precision {
     BSE_FP64 = 0,       /* FP64 MFMA                                           */
     BSE_SPLIT_FP32 = 1, /* operands split into FP32 hi + lo, 3 products, FP32 acc */

@@ -874,7 +874,7 @@ int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& 
     if ((rc = run_pd(B, ws, kind, tn, st)) || (rc = run_tr_fill(B, ws, kind, st))) return rc;
   HIP_TRY(stage(BSE_STAGE_EXCHANGE, st, [&] { return launch_exchange(gs, xt, (int)B.xt.size(), precision, st); }));
   HIP_TRY(stage(BSE_STAGE_DIRECT1, st, [&] { return launch_direct_s1(gs, s1, (int)B.s1.size(), precision, st); }));
-  HIP_TRY(stage(BSE_STAGE_DIRECT2, st, [&] { return launch_direct_s2(gs, d2off, nsys, B.d2n, precision, st); }));
+  HIP_TRY(stage(BSE_STAGE_DIRECT2, st, [&] { return launch_direct_s2(gs, d2off, nsys, B.d2n, st); }));
   HIP_TRY(stage(BSE_STAGE_MIRROR, st, [&] { return launch_mirror(gs, mt, (int)B.mt.size(), st); }));
   return BSE_OK;
 }

@@ -107,27 +107,38 @@ __global__ __launch_bounds__(256) void k_direct_s2(const GemmArgs* __restrict__ 
     cim = mfma64(a.x, b.y, cim);
     cim = mfma64(a.y, b.x, cim);
   }
+  // mixed precisions: the q = 0 head of W, left out of their stage 1, in FP64
+  const bool head = pr.z == 0 && g.w_head_fp64;
+  const double2 w00 = head ? gld(g.W, 0) : make_double2(0.0, 0.0);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = ti * 16 + 4 * r + (lane >> 4);
     const int j = tj * 16 + (lane & 15);
     if (i < nv2 && j < nc2) {
+      double dr = cre[r], di = cim[r];
+      if (head) {
+        const double2 rv0 = gld(g.RV, ((size_t)p * nv2 + i) * g.ng_max);
+        const double2 rc0 = gld(g.RC, ((size_t)p * nc2 + j) * g.ng_max);
+        const double2 hw = cmul(cconjmul(rv0, w00), rc0);
+        dr += hw.x;
+        di += hw.y;
+      }
       const int v = i / g.nv, v2 = i % g.nv, c = j / g.nc, c2 = j % g.nc;
       const size_t S = ((size_t)ka * g.nv + v) * g.nc + c;
       const size_t S2 = ((size_t)kb * g.nv + v2) * g.nc + c2;
       double2 h = gld(g.H, S * g.ns + S2);
-      h.x -= g.cpref * cre[r];
-      h.y -= g.cpref * cim[r];
+      h.x -= g.cpref * dr;
+      h.y -= g.cpref * di;
       if (S == S2) h.x += gbl(g.eps)[(size_t)ka * g.nb + g.nv + c] - gbl(g.eps)[(size_t)ka * g.nb + v];
       gst(g.H, S * g.ns + S2, h);
     }
   }
 }
 
-hipError_t launch_direct_s2(const GemmArgs* gs, const int* d2off, int nsys, int nitems, int precision,
-                            hipStream_t st) {
+// Stage 2 reads each Z and rho_cc' row once (HBM-bound), so it runs in FP64
+// in every precision mode.
+hipError_t launch_direct_s2(const GemmArgs* gs, const int* d2off, int nsys, int nitems, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
-  if (precision != BSE_FP64) return launch_direct_s2_mx(gs, d2off, nsys, nitems, precision, st);
   hipLaunchKernelGGL(k_direct_s2, dim3((nitems + 3) / 4), dim3(256), 0, st, gs, d2off, nsys, nitems);
   return hipGetLastError();
 }

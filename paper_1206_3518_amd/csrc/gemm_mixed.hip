@@ -68,107 +68,6 @@ __global__ __launch_bounds__(256) void k_direct_s1_mx(const GemmArgs* __restrict
 // operands split in registers.  The q = 0 head conj(rho_vv'(0)) W_00 rho_cc'(0)
 // is added in FP64.
 template <int P>
-__global__ __launch_bounds__(256) void k_direct_s2_mx(const GemmArgs* __restrict__ gs, const int* __restrict__ d2off,
-                                                      int nsys, int nitems) {
-  const int lane = threadIdx.x & 63;
-  const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (item >= nitems) return;
-  const int sys = item_system(d2off, nsys, item);
-  const GemmArgs g = gs[sys];
-  const int nv2 = g.nv * g.nv, nc2 = g.nc * g.nc;
-  const int tiles_i = (nv2 + 15) / 16, tiles_j = (nc2 + 15) / 16;
-  const int loc = item - d2off[sys];
-  const int per = tiles_i * tiles_j;
-  const int p = loc / per, ti = (loc % per) / tiles_j, tj = loc % tiles_j;
-  const int4 pr = gld(g.pairs, p);
-  const int ka = pr.x, kb = pr.y;
-  const int K = gbl(g.ng)[pr.z];
-  const int ia = ti * 16 + (lane & 15), jb = tj * 16 + (lane & 15);
-  const bool va = ia < nv2, vb = jb < nc2;
-  const double2* zr = g.Z + ((size_t)p * nv2 + (va ? ia : 0)) * g.ng_max;
-  const double2* cr = g.RC + ((size_t)p * nc2 + (vb ? jb : 0)) * g.ng_max;
-  f4 dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
-  if constexpr (P == BSE_BF16X3) {
-    for (int k0 = 0; k0 < K; k0 += 32) {
-      s8 a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int k = k0 + 8 * (lane >> 4) + i;
-        const double2 x = (va && k < K) ? gld(zr, k) : make_double2(0.0, 0.0);
-        const double2 y = (vb && k < K) ? gld(cr, k) : make_double2(0.0, 0.0);
-        unsigned short h, l;
-        Split<P>::split(x.x, h, l); a[0][i] = (short)h; a[1][i] = (short)l;
-        Split<P>::split(x.y, h, l); a[2][i] = (short)h; a[3][i] = (short)l;
-        Split<P>::split(y.x, h, l); b[0][i] = (short)h; b[1][i] = (short)l;
-        Split<P>::split(y.y, h, l); b[2][i] = (short)h; b[3][i] = (short)l;
-      }
-      const s8 nih = a[2] ^ (short)0x8000, nil = a[3] ^ (short)0x8000;
-      dre = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], dre, 0, 0, 0);
-      dre = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], dre, 0, 0, 0);
-      dre = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], dre, 0, 0, 0);
-      dre = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, b[2], dre, 0, 0, 0);
-      dre = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, b[3], dre, 0, 0, 0);
-      dre = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nil, b[2], dre, 0, 0, 0);
-      dim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2], dim, 0, 0, 0);
-      dim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[3], dim, 0, 0, 0);
-      dim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[2], dim, 0, 0, 0);
-      dim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], dim, 0, 0, 0);
-      dim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[1], dim, 0, 0, 0);
-      dim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[3], b[0], dim, 0, 0, 0);
-    }
-  } else {
-    for (int k0 = 0; k0 < K; k0 += 4) {
-      const int k = k0 + (lane >> 4);
-      const double2 x = (va && k < K) ? gld(zr, k) : make_double2(0.0, 0.0);
-      const double2 y = (vb && k < K) ? gld(cr, k) : make_double2(0.0, 0.0);
-      float a[4], b[4];
-      Split<P>::split(x.x, a[0], a[1]);
-      Split<P>::split(x.y, a[2], a[3]);
-      Split<P>::split(y.x, b[0], b[1]);
-      Split<P>::split(y.y, b[2], b[3]);
-      dre = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], dre, 0, 0, 0);
-      dre = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[1], dre, 0, 0, 0);
-      dre = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b[0], dre, 0, 0, 0);
-      dre = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[2], b[2], dre, 0, 0, 0);
-      dre = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[2], b[3], dre, 0, 0, 0);
-      dre = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[3], b[2], dre, 0, 0, 0);
-      dim = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[2], dim, 0, 0, 0);
-      dim = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[3], dim, 0, 0, 0);
-      dim = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b[2], dim, 0, 0, 0);
-      dim = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b[0], dim, 0, 0, 0);
-      dim = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b[1], dim, 0, 0, 0);
-      dim = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b[0], dim, 0, 0, 0);
-    }
-  }
-  // FP64 head of W at q = 0 (left out of both mixed GEMMs)
-  const bool head = pr.z == 0 && g.w_head_fp64;
-  const double2 w00 = head ? gld(g.W, 0) : make_double2(0.0, 0.0);
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = ti * 16 + acc_row(lane, r);
-    const int j = tj * 16 + (lane & 15);
-    if (i < nv2 && j < nc2) {
-      double dr = (double)dre[r], di = (double)dim[r];
-      if (head) {
-        const double2 rv0 = gld(g.RV, ((size_t)p * nv2 + i) * g.ng_max);
-        const double2 rc0 = gld(g.RC, ((size_t)p * nc2 + j) * g.ng_max);
-        const double2 hw = cmul(cconjmul(rv0, w00), rc0);
-        dr += hw.x;
-        di += hw.y;
-      }
-      const int v = i / g.nv, v2 = i % g.nv, c = j / g.nc, c2 = j % g.nc;
-      const size_t S = ((size_t)ka * g.nv + v) * g.nc + c;
-      const size_t S2 = ((size_t)kb * g.nv + v2) * g.nc + c2;
-      double2 h = gld(g.H, S * g.ns + S2);
-      h.x -= g.cpref * dr;
-      h.y -= g.cpref * di;
-      if (S == S2) h.x += gbl(g.eps)[(size_t)ka * g.nb + g.nv + c] - gbl(g.eps)[(size_t)ka * g.nb + v];
-      gst(g.H, S * g.ns + S2, h);
-    }
-  }
-}
-
-template <int P>
 static hipError_t launch_ex(const GemmArgs* gs, const HTile* tiles, int ntiles, hipStream_t st) {
   const size_t lds = 2 * sizeof(TileLds<P>);
   hipError_t e = hipFuncSetAttribute((const void*)k_exchange_mx<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -198,15 +97,5 @@ hipError_t launch_direct_s1_mx(const GemmArgs* gs, const S1Tile* tiles, int ntil
                                  : launch_s1<BSE_SPLIT_FP32>(gs, tiles, ntiles, st);
 }
 
-hipError_t launch_direct_s2_mx(const GemmArgs* gs, const int* d2off, int nsys, int nitems, int precision,
-                               hipStream_t st) {
-  if (nitems <= 0) return hipSuccess;
-  if (precision == BSE_BF16X3)
-    hipLaunchKernelGGL(k_direct_s2_mx<BSE_BF16X3>, dim3((nitems + 3) / 4), dim3(256), 0, st, gs, d2off, nsys, nitems);
-  else
-    hipLaunchKernelGGL(k_direct_s2_mx<BSE_SPLIT_FP32>, dim3((nitems + 3) / 4), dim3(256), 0, st, gs, d2off, nsys,
-                       nitems);
-  return hipGetLastError();
-}
 
 }  // namespace bse
