@@ -47,7 +47,7 @@ class bse_system(ctypes.Structure):
 
 SYMBOLS = ["bse_workspace_size", "bse_pair_density", "bse_build_H", "bse_build_H_backward",
            "bse_autotune", "bse_autotune_last", "bse_spectrum", "bse_profile", "bse_profile_read", "bse_last_error"]
-STAGES = ["vscale", "pd_exch", "pd_vv", "pd_cc", "exchange", "direct1", "direct2", "mirror", "rotate", "tr_fill", "to_f32"]
+STAGES = ["vscale", "pd_exch", "pd_vv", "pd_cc", "exchange", "direct1", "direct2", "mirror", "rotate", "tr_fill", "to_f32", "split_w"]
 
 
 def lib():

@@ -195,6 +195,8 @@ struct Plan {
   size_t o_ut = 0;       // rotated wave functions (rot only; in the forward part)
   bool pd32 = false;     // FP32 valence / conduction pair densities
   size_t o_u32 = 0;      // FP32 copy of the wave functions in the frame (pd32 only)
+  int kpad = 0;          // ng_max rounded up to a multiple of 32
+  size_t o_Ws = 0;       // W split for the mixed stage 1: [Nk][ng_max][4][kpad] of up to 4 bytes
 };
 
 int check_system(const bse_system* s) {
@@ -436,6 +438,8 @@ int make_plan(const bse_system* s, Plan& P, bool pd32) {
   P.o_RC = put((size_t)np * P.nc * P.nc * P.ng_max * sizeof(double2));
   P.o_Z = put((size_t)np * P.nv * P.nv * P.ng_max * sizeof(double2));
   if (P.rot) P.o_ut = put((size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * sizeof(double2));
+  P.kpad = (P.ng_max + 31) / 32 * 32;
+  P.o_Ws = put((size_t)P.nk * P.ng_max * 4 * P.kpad * sizeof(float));
   P.pd32 = pd32 && pd_line_grid(P.N2, P.N3);
   if (P.pd32) P.o_u32 = put((size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * sizeof(float2));
   P.fwd_total = o;
@@ -501,6 +505,8 @@ GemmArgs gemm_args(const Plan& P, const bse_system* s, char* region) {
   g.nb = P.nb;
   g.npairs = (int)P.pairs.size();
   g.nt = P.nt;
+  g.Ws = region + P.o_Ws;
+  g.kpad = P.kpad;
   return g;
 }
 
@@ -865,6 +871,16 @@ int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& 
     HIP_TRY(stage(BSE_STAGE_VSCALE, st, [&] { return launch_vscale(sys[i].vx, P.ng[0], P.ng_max, vs, st); }));
   }
   if ((rc = prepare_u(B, sys, ws, st))) return rc;
+  if (precision != BSE_FP64) {
+    for (int i = 0; i < nsys; ++i) {
+      const Plan& P = B.P[i];
+      char* region = ws + B.base[i];
+      HIP_TRY(stage(BSE_STAGE_SPLIT_W, st, [&] {
+        return launch_split_w(reinterpret_cast<const double2*>(sys[i].W), reinterpret_cast<const int*>(region + P.o_ng),
+                              P.nk, P.ng_max, P.kpad, 1, precision, region + P.o_Ws, st);
+      }));
+    }
+  }
   const GemmArgs* gs = reinterpret_cast<const GemmArgs*>(ws + B.o_gargs);
   const HTile* xt = reinterpret_cast<const HTile*>(ws + B.o_xt);
   const HTile* mt = reinterpret_cast<const HTile*>(ws + B.o_mt);

@@ -31,6 +31,12 @@ __device__ __forceinline__ int4 gld(const int4* p, size_t i) {
   const int* q = reinterpret_cast<const int*>(p) + 4 * i;
   return make_int4(gbl(q)[0], gbl(q)[1], gbl(q)[2], gbl(q)[3]);
 }
+// one 16-byte global load (p 16-byte aligned)
+typedef unsigned gu4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 gld16(const void* p) {
+  const gu4 v = *(const __attribute__((address_space(1))) gu4*)p;
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
 
 // ---------------------------------------------------------------- complex
 

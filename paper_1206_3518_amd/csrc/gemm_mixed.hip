@@ -47,8 +47,10 @@ __global__ __launch_bounds__(256) void k_direct_s1_mx(const GemmArgs* __restrict
   const double2* Wq = g.W + (size_t)tl.iq * g.ng_max * g.ng_max;
   f4 cre[2][2], cim[2][2];
   const int r0 = tl.mt * MTM, c0 = tl.nt * MTN;
-  tile_gemm_mx<P, true, false>(A, g.ng_max, r0, rows, Wq, g.ng_max, c0, K, K, tl.iq == 0 && g.w_head_fp64,
-                              cre, cim);
+  typedef typename Split<P>::T T;
+  const T* Wsq = reinterpret_cast<const T*>(g.Ws) + (size_t)tl.iq * g.ng_max * 4 * g.kpad;
+  tile_gemm_mx<P, true, false, false, true>(A, g.ng_max, r0, rows, Wq, g.ng_max, c0, K, K, false, cre, cim, Wsq,
+                                            g.kpad);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
   double2* Z = g.Z + (size_t)row_base * g.ng_max;
 #pragma unroll
@@ -67,6 +69,53 @@ __global__ __launch_bounds__(256) void k_direct_s1_mx(const GemmArgs* __restrict
 // Stage 2 per k pair: D[vv'][cc'] = sum_g Z[vv'][g] RC[cc'][g] (no conjugate),
 // operands split in registers.  The q = 0 head conj(rho_vv'(0)) W_00 rho_cc'(0)
 // is added in FP64.
+// W(q) split once per build and transposed so that the stage-1 tiles read
+// their B operand k-contiguous without converting it: one 32 x 32 tile of
+// (k, n) per workgroup through LDS.
+template <int P>
+__global__ __launch_bounds__(256) void k_split_w(const double2* __restrict__ W, const int* __restrict__ ng, int nk,
+                                                 int ng_max, int kpad, int head, typename Split<P>::T* __restrict__ Ws) {
+  __shared__ double2 tile[32][33];
+  const int n0 = blockIdx.x * 32, k0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int q = blockIdx.z; q < nk; q += gridDim.z) {
+  const int ngq = ng[q];
+  __syncthreads();  // the previous q's tile is read
+  for (int r = ty; r < 32; r += 8) {
+    const int k = k0 + r, n = n0 + tx;
+    double2 v = make_double2(0.0, 0.0);
+    if (k < ngq && n < ngq && !(head && q == 0 && k == 0 && n == 0))
+      v = W[((size_t)q * ng_max + k) * ng_max + n];
+    tile[r][tx] = v;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int n = n0 + r, k = k0 + tx;
+    if (n >= ng_max || k >= kpad) continue;
+    const double2 v = tile[tx][r];
+    typename Split<P>::T h[4];
+    Split<P>::split(v.x, h[0], h[1]);
+    Split<P>::split(v.y, h[2], h[3]);
+    typename Split<P>::T* row = Ws + ((size_t)q * ng_max + n) * 4 * kpad + k;
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) row[(size_t)pl * kpad] = h[pl];
+  }
+  }
+}
+
+hipError_t launch_split_w(const double2* W, const int* ng, int nk, int ng_max, int kpad, int head, int precision,
+                          void* Ws, hipStream_t st) {
+  if (nk <= 0) return hipSuccess;
+  const dim3 grid((ng_max + 31) / 32, kpad / 32, nk < 4096 ? nk : 4096);
+  if (precision == BSE_BF16X3)
+    hipLaunchKernelGGL(k_split_w<BSE_BF16X3>, grid, dim3(256), 0, st, W, ng, nk, ng_max, kpad, head,
+                       reinterpret_cast<unsigned short*>(Ws));
+  else
+    hipLaunchKernelGGL(k_split_w<BSE_SPLIT_FP32>, grid, dim3(256), 0, st, W, ng, nk, ng_max, kpad, head,
+                       reinterpret_cast<float*>(Ws));
+  return hipGetLastError();
+}
+
 template <int P>
 static hipError_t launch_ex(const GemmArgs* gs, const HTile* tiles, int ntiles, hipStream_t st) {
   const size_t lds = 2 * sizeof(TileLds<P>);

@@ -198,10 +198,14 @@ __device__ __forceinline__ void put8(TileLds<P>& L, int r, int k0, const double2
 // One 64x64 complex tile of C = op(A) * B with split operands; operand
 // addressing as in tile_gemm.  zero_head: B[0][0] := 0 when the tile holds it
 // (the q = 0 head is added in FP64 elsewhere).
-template <int P, bool CONJ_A, bool B_T, bool A_T = false>
+// B_PRE: B comes already split, as Bp[n][plane][k] (row stride 4 ldk, planes
+// re hi, re lo, im hi, im lo; zero for k >= K up to a multiple of 32), and is
+// copied to LDS without conversion (B, ldb, B_T and zero_head unused).
+template <int P, bool CONJ_A, bool B_T, bool A_T = false, bool B_PRE = false>
 __device__ __forceinline__ void tile_gemm_mx(const double2* __restrict__ A, int lda, int a_off, int a_lim,
                                              const double2* __restrict__ B, int ldb, int b_off, int b_lim, int K,
-                                             bool zero_head, f4 (&cre)[2][2], f4 (&cim)[2][2]) {
+                                             bool zero_head, f4 (&cre)[2][2], f4 (&cim)[2][2],
+                                             const typename Split<P>::T* __restrict__ Bp = nullptr, int ldk = 0) {
   extern __shared__ double2 smem_mx_raw[];  // 16-byte aligned dynamic area
   char* smem_mx = reinterpret_cast<char*>(smem_mx_raw);
   TileLds<P>& As = *reinterpret_cast<TileLds<P>*>(smem_mx);
@@ -219,7 +223,10 @@ __device__ __forceinline__ void tile_gemm_mx(const double2* __restrict__ A, int 
   const int r = t >> 2, kq = (t & 3) * 8;
   // the next chunk's operands are loaded while the MFMAs consume the current
   // one; out-of-range elements are read from the array start and zeroed
-  double2 xa[8], xb[8];
+  typedef typename Split<P>::T T;
+  constexpr int QW = sizeof(T) * 8 / 16;  // 16-byte words per plane row segment of 8 k
+  double2 xa[8], xb[B_PRE ? 1 : 8];
+  uint4 xp[B_PRE ? 4 * QW : 1];
   auto load = [&](int k0) {
     const int gr = a_off + r;
 #pragma unroll
@@ -230,19 +237,40 @@ __device__ __forceinline__ void tile_gemm_mx(const double2* __restrict__ A, int 
       const double2 v = gld(A, ok ? idx : 0);
       xa[i] = make_double2(ok ? v.x : 0.0, ok ? v.y : 0.0);
     }
+    if constexpr (B_PRE) {
+      const bool ok = b_off + r < b_lim;
+      const T* row = Bp + (ok ? (size_t)(b_off + r) * 4 * ldk : 0) + k0 + kq;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int k = k0 + kq + i;
-      const bool ok = b_off + r < b_lim && k < K && !(zero_head && k == 0 && b_off + r == 0);
-      const size_t idx = B_T ? (size_t)(b_off + r) * ldb + k : (size_t)k * ldb + b_off + r;
-      const double2 v = gld(B, ok ? idx : 0);
-      xb[i] = make_double2(ok ? v.x : 0.0, ok ? v.y : 0.0);
+      for (int pl = 0; pl < 4; ++pl)
+#pragma unroll
+        for (int w4 = 0; w4 < QW; ++w4) {
+          const uint4 v = gld16(reinterpret_cast<const uint4*>(row + (size_t)pl * ldk) + w4);
+          xp[pl * QW + w4] = ok ? v : make_uint4(0u, 0u, 0u, 0u);
+        }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int k = k0 + kq + i;
+        const bool ok = b_off + r < b_lim && k < K && !(zero_head && k == 0 && b_off + r == 0);
+        const size_t idx = B_T ? (size_t)(b_off + r) * ldb + k : (size_t)k * ldb + b_off + r;
+        const double2 v = gld(B, ok ? idx : 0);
+        xb[i] = make_double2(ok ? v.x : 0.0, ok ? v.y : 0.0);
+      }
     }
   };
   if (K > 0) load(0);
   for (int k0 = 0; k0 < K; k0 += MKC) {
     put8<P>(As, r, kq, xa, CONJ_A);
-    put8<P>(Bs, r, kq, xb, false);
+    if constexpr (B_PRE) {
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) {
+        const T* src = reinterpret_cast<const T*>(&xp[pl * QW]);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) Bs.v[pl][r * ST + kq + i] = src[i];
+      }
+    } else {
+      put8<P>(Bs, r, kq, xb, false);
+    }
     __syncthreads();
     if (k0 + MKC < K) load(k0 + MKC);
     if constexpr (P == BSE_BF16X3) {

@@ -94,6 +94,9 @@ struct GemmArgs {
   int nv, nc, nb, npairs;
   int nt;               // nv * nc: rows of one k block
   int w_head_fp64;      // mixed precision: q=0 head added separately in FP64
+  const void* Ws;       // mixed precision: W split and transposed, [Nk][ng_max][4][kpad] of the
+                        // split type (planes re hi, re lo, im hi, im lo), head left out
+  int kpad;             // ng_max rounded up to a multiple of 32
 };
 
 // The contractions run over a batch: gs is a device array of per-system
@@ -106,6 +109,11 @@ hipError_t launch_direct_s1(const GemmArgs* gs, const S1Tile* tiles, int ntiles,
 // stage 2 is FP64 in every mode (it adds the FP64 q = 0 head when w_head_fp64)
 hipError_t launch_direct_s2(const GemmArgs* gs, const int* d2off, int nsys, int nitems, hipStream_t st);
 hipError_t launch_mirror(const GemmArgs* gs, const HTile* tiles, int ntiles, hipStream_t st);
+// Ws[q][n][pl][k] = part pl of W[q][k][n] for k, n < ng(q), zero elsewhere up
+// to kpad (and at the q = 0 head when head != 0); precision BSE_SPLIT_FP32 or
+// BSE_BF16X3 (parts as in the mixed contractions).
+hipError_t launch_split_w(const double2* W, const int* ng, int nk, int ng_max, int kpad, int head, int precision,
+                          void* Ws, hipStream_t st);
 // mixed-precision bodies (precision BSE_SPLIT_FP32 or BSE_BF16X3), called by the above
 hipError_t launch_exchange_mx(const GemmArgs* gs, const HTile* tiles, int ntiles, int precision, hipStream_t st);
 hipError_t launch_direct_s1_mx(const GemmArgs* gs, const S1Tile* tiles, int ntiles, int precision, hipStream_t st);
