@@ -565,6 +565,7 @@ struct Batch {
   int d2n = 0;
   bool tr = false;             // pair densities of time-reversal images derived
   bool pd32 = false;           // FP32 valence / conduction pair densities
+  int np32 = 2;                // their planes per step: 4 when every window has F2 <= 16
   size_t lds32 = 0;            // their LDS bytes
   std::vector<int4> fill;      // (dst, src, mode, sys)
   size_t o_pdx = 0, o_pdv = 0, o_pdc = 0, o_gargs = 0, o_jx = 0, o_jv = 0, o_jc = 0, o_s1 = 0, o_xt = 0, o_mt = 0;
@@ -590,13 +591,23 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
                   P.N3, B.N2, B.N3);
     }
     B.ng_max = std::max(B.ng_max, P.ng_max);
-    const size_t l = pd_lds_bytes(P.N1, P.N2, P.N3, P.F[1], P.F[2], P.ng_max, false);
+    const size_t l = pd_lds_bytes(P.N1, P.N2, P.N3, P.F[1], P.F[2], P.ng_max, 0);
     B.pd32 = B.pd32 && P.pd32;
-    if (P.pd32) B.lds32 = std::max(B.lds32, pd_lds_bytes(P.N1, P.N2, P.N3, P.F[1], P.F[2], P.ng_max, true));
     if (l > 160 * 1024) return fail(BSE_ERR_SHAPE, "FFT window of system %d needs more than 160 KiB of LDS", i);
     B.lds = std::max(B.lds, l);
     if (tr && !P.tr_closed)
       return fail(BSE_ERR_SHAPE, "system %d: time reversal needs G spheres closed under G -> t - G (qbar = -q - t)", i);
+  }
+  if (B.pd32) {
+    B.np32 = 4;
+    for (const Plan& P : B.P) B.np32 = P.F[1] <= 16 ? B.np32 : 2;
+    for (int tries = 0; tries < 2; ++tries) {
+      B.lds32 = 0;
+      for (const Plan& P : B.P)
+        B.lds32 = std::max(B.lds32, pd_lds_bytes(P.N1, P.N2, P.N3, P.F[1], P.F[2], P.ng_max, B.np32));
+      if (B.lds32 <= 160 * 1024 || B.np32 == 2) break;
+      B.np32 = 2;  // four planes' windows do not fit the LDS
+    }
   }
   // merged lists
   std::vector<PdJob> jx, jv, jc;
@@ -811,10 +822,11 @@ int run_pd(const Batch& B, char* ws, int kind, const Tune& tn, hipStream_t st) {
   const int stage_id = kind == 0 ? BSE_STAGE_PD_EXCH : kind == 1 ? BSE_STAGE_PD_VV : BSE_STAGE_PD_CC;
   const bool f32 = B.pd32 && kind != 0;
   const size_t lds = f32 ? B.lds32 : B.lds;
+  const int f32_planes = f32 ? B.np32 : 0;
   const int grid = tn.persist ? persistent_grid(lds, b.njobs, tn.wg_per_cu) : b.njobs;
   if (tn.persist) HIP_TRY(launch_zero_u32(b.cnt, kXcds * kQueueStride, st));
   HIP_TRY(stage(stage_id, st, [&] {
-    return launch_pair_density(b, B.N2, B.N3, B.ng_max, lds, grid, kind == 0, f32, st);
+    return launch_pair_density(b, B.N2, B.N3, B.ng_max, lds, grid, kind == 0, f32_planes, st);
   }));
   return BSE_OK;
 }
@@ -1128,7 +1140,7 @@ int bse_pair_density(const bse_system* sys, int kind, const int* kpairs, int npa
   } else {
     return fail(BSE_ERR_INVALID_ARG, "unknown kind %d", kind);
   }
-  const size_t lds = pd_lds_bytes(P.N1, P.N2, P.N3, P.F[1], P.F[2], P.ng_max, false);
+  const size_t lds = pd_lds_bytes(P.N1, P.N2, P.N3, P.F[1], P.F[2], P.ng_max, 0);
   if (lds > 160 * 1024) return fail(BSE_ERR_SHAPE, "FFT window needs more than 160 KiB of LDS");
   jobs = dispatch_order(std::move(jobs), Tune{}.ktile);
   // tables: gpack, ng, the one system's arguments, jobs
@@ -1171,7 +1183,7 @@ int bse_pair_density(const bse_system* sys, int kind, const int* kpairs, int npa
   b.njobs = (int)jobs.size();
   b.persist = 0;
   b.cnt = nullptr;
-  HIP_TRY(launch_pair_density(b, P.N2, P.N3, P.ng_max, lds, b.njobs, false, false, st));
+  HIP_TRY(launch_pair_density(b, P.N2, P.N3, P.ng_max, lds, b.njobs, false, 0, st));
   return BSE_OK;
 }
 

@@ -52,15 +52,17 @@ bool pd_grid_supported(int N2, int N3);
 bool pd_line_grid(int N2, int N3);
 // ut[g][j3][j1][j2] = u[g][j1][j2][j3] for ngrids grids of N1 x N2 x N3 (N1, N2 <= 32)
 hipError_t launch_rotate_axes(const double2* u, double2* ut, long long ngrids, int N1, int N2, int N3, hipStream_t st);
-size_t pd_lds_bytes(int N1, int N2, int N3, int F2, int F3, int ng_max, bool f32);
+// f32_planes: 0 for FP64, else the planes per step of the FP32 kernel (2 or 4)
+size_t pd_lds_bytes(int N1, int N2, int N3, int F2, int F3, int ng_max, int f32_planes);
 // v = (float) u, n complex values
 hipError_t launch_to_f32(const double2* u, float2* v, size_t n, hipStream_t st);
 // ng_max: the largest of the batch; lds: the largest pd_lds_bytes of the
 // batch; exch: exchange rows (every system's vscale set); grid: njobs for
-// static dispatch, the persistent grid otherwise; f32: FP32 transforms from
-// PdArgs.u32 (one-lane-per-line planes and non-exchange rows only).
+// static dispatch, the persistent grid otherwise; f32_planes: 0, or FP32
+// transforms from PdArgs.u32 with 2 or 4 planes per step (one-lane-per-line
+// planes and non-exchange rows only; 4 needs every F2 <= 16).
 hipError_t launch_pair_density(const PdBatch& b, int N2, int N3, int ng_max, size_t lds, int grid, bool exch,
-                               bool f32, hipStream_t st);
+                               int f32_planes, hipStream_t st);
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st);
 
 // A GEMM tile of the direct term's first stage: q group iq, tile (mt, nt), system sys.

@@ -237,8 +237,12 @@ __device__ __forceinline__ void pin(C (&x)[M]) {
 
 // C: double2, or float2 for FP32 pair densities (wave functions read from the
 // FP32 copy, every pass in FP32, the sphere values written as FP64).
-template <int N2, int N3, int TG, bool EXCH, class C, bool PF>
+// NP planes per step (2 or 4): with 4, pass 1 runs twice per step and pass 2
+// takes the kept rows of all four planes at once (4 F2 <= 64 lanes), which
+// halves its issued instructions for windows of up to 16 rows.
+template <int N2, int N3, int TG, bool EXCH, class C, bool PF, int NP = 2>
 __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
+  static_assert(NP == 2 || (NP == 4 && !PF), "2 planes per step, or 4 without the prefetch");
   static_assert(N2 <= 32 && N3 <= 32 && N2 % 2 == 0 && N3 % 2 == 0, "lines must fit a half wave");
   constexpr bool F32 = sizeof(C) == 8;
   static_assert(!(F32 && EXCH), "exchange pair densities are FP64");
@@ -256,8 +260,8 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5, c = lane & 31;
   const int per_pl = F2 * S1;
-  C* T1 = tw1 + N1 + wave * 2 * per_pl;
-  int2* gtab = reinterpret_cast<int2*>(tw1 + N1 + 8 * per_pl);
+  C* T1 = tw1 + N1 + wave * NP * per_pl;
+  int2* gtab = reinterpret_cast<int2*>(tw1 + N1 + 4 * NP * per_pl);
 
   for (int t = threadIdx.x; t < N1; t += blockDim.x) {
     double s, cs;
@@ -285,6 +289,9 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
   const int Nr = N1 * N2 * N3;
   const int npd = nA * nB;
   C* T1h = T1 + h * per_pl;
+  // pass 2 with four planes: lane l takes kept row l mod F2 of plane l / F2
+  const bool ok4 = NP == 4 && lane < 4 * F2;
+  const int pl4 = ok4 ? lane / F2 : 0, rw4 = ok4 ? lane - pl4 * F2 : 0;
   // with an even number of bands on both sides the four waves of a step take
   // a 2 x 2 block of band pairs (four distinct grids per step instead of five)
   const bool blk = nA % 2 == 0 && nB % 2 == 0;
@@ -319,18 +326,22 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
       }
     };
     if constexpr (PF) load_even(0);
-    for (int j1 = 0; j1 < N1; j1 += 2) {
-      if constexpr (!PF) load_even(j1);
-      const bool two = j1 + 1 < N1;  // the second plane exists
+    for (int j1 = 0; j1 < N1; j1 += NP) {
       // window masks and origins re-read per plane: kept loop-invariant they
       // would pin one scalar condition per frequency across the loop
       unsigned k2 = __builtin_amdgcn_readfirstlane(keep2), k3 = __builtin_amdgcn_readfirstlane(keep3);
       int lo2 = __builtin_amdgcn_readfirstlane(a.lo2), lo3 = __builtin_amdgcn_readfirstlane(a.lo3);
       asm volatile("" : "+s"(k2), "+s"(k3), "+s"(lo2), "+s"(lo3));
       // ---- pass 1 (idle lanes load a valid column and write padding or a
-      // plane that pass 3 skips)
-      {
-        const unsigned off = (unsigned)(col + (two ? j1 + h : j1) * (N2 * N3));
+      // plane that pass 3 skips), once per two planes
+#pragma unroll
+      for (int hf = 0; hf < NP / 2; ++hf) {
+        const int jj = j1 + 2 * hf;
+        if (NP > 2 && jj >= N1) break;  // wave-uniform
+        if constexpr (!PF) load_even(jj);
+        const bool two = jj + 1 < N1;  // the second plane exists
+        C* T1w = T1 + (2 * hf + h) * per_pl;
+        const unsigned off = (unsigned)(col + (two ? jj + h : jj) * (N2 * N3));
         C E[H2], O[H2];
 #pragma unroll
         for (int s = 0; s < H2; ++s) E[s] = cconjmul(pa[s], pb[s]);
@@ -367,20 +378,22 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
             r += r < 0 ? N2 : 0;
             r -= r >= N2 ? N2 : 0;
             constexpr int q = fft_pos<H2>(f % H2);
-            T1h[r * S1 + c] = cadd(E[q], cmul_root<N2, f>(O[q]));
+            T1w[r * S1 + c] = cadd(E[q], cmul_root<N2, f>(O[q]));
           }
         });
       }
       wave_sync();
       // ---- pass 2
       {
-        const bool ok = c < F2;
-        const int row = (ok ? c : 0) * S1;
+        const bool ok = NP == 4 ? ok4 : c < F2;
+        const int rr = NP == 4 ? rw4 : (ok ? c : 0);
+        C* T2 = NP == 4 ? T1 + pl4 * per_pl : T1h;
+        const int row = rr * S1;
         C E[H3], O[H3];
 #pragma unroll
         for (int s = 0; s < H3; ++s) {
-          E[s] = T1h[row + 2 * s];
-          O[s] = T1h[row + 2 * s + 1];
+          E[s] = T2[row + 2 * s];
+          O[s] = T2[row + 2 * s + 1];
         }
         reg_fft<H3, 1, 0>(E);
         reg_fft<H3, 1, 0>(O);
@@ -395,13 +408,14 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
             r -= r >= N3 ? N3 : 0;
             constexpr int q = fft_pos<H3>(f % H3);
             const C v = cadd(E[q], cmul_root<N3, f>(O[q]));
-            if (ok) T1h[c * F3 + r] = v;
+            if (ok) T2[rr * F3 + r] = v;
           }
         });
       }
       wave_sync();
-      // next plane pair, in flight during pass 3 (unconditional, so that the
-      // values just consumed are dead; the last pair re-reads a valid plane)
+      // with PF, the next plane pair in flight during pass 3 (issued whether
+      // or not one is left, so that the values just consumed are dead; the
+      // last pair re-reads a valid plane)
       if constexpr (PF) load_even(j1 + 2 < N1 ? j1 + 2 : j1);
       __builtin_amdgcn_sched_barrier(0);
       // ---- pass 3
@@ -414,10 +428,13 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
           r += r < 0 ? N1 : 0;
           r -= r >= N1 ? N1 : 0;
           acc[t] = cfma(T1[e.x], tw1[r], acc[t]);
-          if (two) {
-            r += e.y;
-            r -= r >= N1 ? N1 : 0;
-            acc[t] = cfma(T1[per_pl + e.x], tw1[r], acc[t]);
+#pragma unroll
+          for (int pp = 1; pp < NP; ++pp) {
+            if (j1 + pp < N1) {
+              r += e.y;
+              r -= r >= N1 ? N1 : 0;
+              acc[t] = cfma(T1[pp * per_pl + e.x], tw1[r], acc[t]);
+            }
           }
         }
       }
@@ -492,16 +509,17 @@ __global__ __launch_bounds__(256, 2) void k_pair_density_line(PdBatch b) {
 
 // FP32 variant (valence-valence and conduction-conduction densities of the
 // mixed-precision modes): half the registers, so no next-plane prefetch (the
-// occupancy hides the load latency instead): four workgroups per CU under
-// static dispatch, three with the persistent loop, which needs more registers.
-template <int N2, int N3, int TG, bool PERSIST>
-__global__ __launch_bounds__(256, PERSIST ? 3 : 4) void k_pair_density_line_f32(PdBatch b) {
+// occupancy hides the load latency instead).  Two planes per step: four
+// workgroups per CU under static dispatch, three with the persistent loop,
+// which needs more registers.  Four planes per step: three (LDS).
+template <int N2, int N3, int TG, bool PERSIST, int NP>
+__global__ __launch_bounds__(256, (PERSIST || NP == 4) ? 3 : 4) void k_pair_density_line_f32(PdBatch b) {
   __shared__ int s_job;
   int round = 0, tries = 0;
   for (int j = next_job<PERSIST>(b, round, tries, &s_job); j >= 0; j = next_job<PERSIST>(b, round, tries, &s_job)) {
     const PdJob job = b.jobs[j];
     const PdArgs a = b.sys[job.nab >> 16];
-    pd_line_job<N2, N3, TG, false, float2, false>(a, job);
+    pd_line_job<N2, N3, TG, false, float2, false, NP>(a, job);
     __syncthreads();
   }
 }
@@ -517,21 +535,25 @@ static int tg_bucket(int ng_max) {
 }
 
 template <int N2, int N3>
-static size_t lds_bytes(int N1, int F2, int F3, int ng_max, bool f32) {
-  if constexpr (use_line<N2, N3>())
-    return (f32 ? sizeof(float2) : sizeof(double2)) * ((size_t)N1 + 8 * (size_t)F2 * 33) +
+static size_t lds_bytes(int N1, int F2, int F3, int ng_max, int f32_planes) {
+  if constexpr (use_line<N2, N3>()) {
+    const size_t np = f32_planes == 4 ? 4 : 2;
+    return (f32_planes ? sizeof(float2) : sizeof(double2)) * ((size_t)N1 + 4 * np * (size_t)F2 * 33) +
            sizeof(int2) * (size_t)ng_max;
+  }
   using G = PlaneGeo<N2, N3>;
   const int FA = G::AX == 2 ? F2 : F3;
   return sizeof(double2) * ((size_t)N1 + N2 + N3 + 4 * (size_t)G::PW * FA * G::SA) + sizeof(int2) * (size_t)ng_max;
 }
 
 template <int N2, int N3, int TG>
-static hipError_t launch_tg(const PdBatch& b, size_t lds, int grid, bool exch, bool f32, hipStream_t st) {
+static hipError_t launch_tg(const PdBatch& b, size_t lds, int grid, bool exch, int f32_planes, hipStream_t st) {
   void (*k)(PdBatch);
   if constexpr (use_line<N2, N3>()) {
-    if (f32 && !exch)
-      k = b.persist ? k_pair_density_line_f32<N2, N3, TG, true> : k_pair_density_line_f32<N2, N3, TG, false>;
+    if (f32_planes == 4 && !exch && !b.persist)  // (the persistent loop spills with four planes)
+      k = k_pair_density_line_f32<N2, N3, TG, false, 4>;
+    else if (f32_planes && !exch)
+      k = b.persist ? k_pair_density_line_f32<N2, N3, TG, true, 2> : k_pair_density_line_f32<N2, N3, TG, false, 2>;
     else if (b.persist)
       k = exch ? k_pair_density_line<N2, N3, TG, true, true> : k_pair_density_line<N2, N3, TG, false, true>;
     else
@@ -549,14 +571,14 @@ static hipError_t launch_tg(const PdBatch& b, size_t lds, int grid, bool exch, b
 }
 
 template <int N2, int N3>
-static hipError_t launch_grid(const PdBatch& b, int ng_max, size_t lds, int grid, bool exch, bool f32,
+static hipError_t launch_grid(const PdBatch& b, int ng_max, size_t lds, int grid, bool exch, int f32_planes,
                               hipStream_t st) {
   switch (tg_bucket(ng_max)) {
-    case 4: return launch_tg<N2, N3, 4>(b, lds, grid, exch, f32, st);
-    case 5: return launch_tg<N2, N3, 5>(b, lds, grid, exch, f32, st);
-    case 8: return launch_tg<N2, N3, 8>(b, lds, grid, exch, f32, st);
-    case 13: return launch_tg<N2, N3, 13>(b, lds, grid, exch, f32, st);
-    default: return launch_tg<N2, N3, 16>(b, lds, grid, exch, f32, st);
+    case 4: return launch_tg<N2, N3, 4>(b, lds, grid, exch, f32_planes, st);
+    case 5: return launch_tg<N2, N3, 5>(b, lds, grid, exch, f32_planes, st);
+    case 8: return launch_tg<N2, N3, 8>(b, lds, grid, exch, f32_planes, st);
+    case 13: return launch_tg<N2, N3, 13>(b, lds, grid, exch, f32_planes, st);
+    default: return launch_tg<N2, N3, 16>(b, lds, grid, exch, f32_planes, st);
   }
 }
 
@@ -614,9 +636,9 @@ hipError_t launch_to_f32(const double2* u, float2* v, size_t n, hipStream_t st) 
   return hipGetLastError();
 }
 
-size_t pd_lds_bytes(int N1, int N2, int N3, int F2, int F3, int ng_max, bool f32) {
+size_t pd_lds_bytes(int N1, int N2, int N3, int F2, int F3, int ng_max, int f32_planes) {
 #define BSE_PD_LDS(X, Y) \
-  if (N2 == X && N3 == Y) return lds_bytes<X, Y>(N1, F2, F3, ng_max, f32);
+  if (N2 == X && N3 == Y) return lds_bytes<X, Y>(N1, F2, F3, ng_max, f32_planes);
   BSE_PD_LDS(8, 8)
   BSE_PD_LDS(12, 12)
   BSE_PD_LDS(16, 16)
@@ -634,10 +656,10 @@ size_t pd_lds_bytes(int N1, int N2, int N3, int F2, int F3, int ng_max, bool f32
 
 // exch: the launch computes exchange rows (every system's PdArgs.vscale set).
 hipError_t launch_pair_density(const PdBatch& b, int N2, int N3, int ng_max, size_t lds, int grid, bool exch,
-                               bool f32, hipStream_t st) {
+                               int f32_planes, hipStream_t st) {
   if (b.njobs <= 0 || grid <= 0) return hipSuccess;
 #define BSE_PD_CASE(X, Y) \
-  if (N2 == X && N3 == Y) return launch_grid<X, Y>(b, ng_max, lds, grid, exch, f32, st);
+  if (N2 == X && N3 == Y) return launch_grid<X, Y>(b, ng_max, lds, grid, exch, f32_planes, st);
   BSE_PD_CASE(8, 8)
   BSE_PD_CASE(12, 12)
   BSE_PD_CASE(16, 16)
