@@ -103,3 +103,35 @@ def test_fp32_pairdens_backward():
         assert err <= 1e-4 * scale, name
     with pytest.raises(P.BseError):
         P.bse_build_H_backward(d, G, precision=P.BSE_FP64, flags=P.BSE_FP32_PAIRDENS, ws=ws)
+
+
+@pytest.mark.parametrize("case", ["planes_18", "planes_17", "wide_window"])
+def test_fp32_pairdens_corner_cases(case):
+    """Plane counts that four planes per step do not divide (18, 17), and a
+    window of more than 16 kept rows along the first in-plane axis (the two-
+    planes-per-step kernel).  The FP32 densities alone (BF16x3 with FP64
+    densities as reference) move H by far less than the mixed bar."""
+    import paper_1206_3518_amd as P
+    import torch
+    if case == "planes_18":
+        s = B.make_system(B.cell_sc(10.0), (18, 16, 16), (2, 2, 1), 2, 2, 3.0, seed=88)
+    elif case == "planes_17":
+        s = B.make_system(B.cell_sc(10.0), (17, 16, 16), (3, 1, 1), 2, 1, 3.0, seed=89)
+    else:
+        s = B.make_system(np.diag([10.0, 20.0, 10.0]), (16, 32, 32), (1, 2, 1), 1, 2, 3.0, seed=90)
+    d = P.DeviceSystem(s)
+    ws = P.workspace(P.bse_workspace_size([d], P.BSE_BF16X3, P.BSE_FP32_PAIRDENS))
+    P.bse_build_H([d], P.BSE_FP64, 0, ws)
+    torch.cuda.synchronize()
+    h64 = d.H.clone()
+    P.bse_build_H([d], P.BSE_BF16X3, 0, ws)
+    torch.cuda.synchronize()
+    hbf = d.H.clone()
+    d.H.fill_(float("nan"))
+    P.bse_build_H([d], P.BSE_BF16X3, P.BSE_FP32_PAIRDENS, ws)
+    torch.cuda.synchronize()
+    kmax = (h64 - torch.diag(torch.diag(h64))).abs().max().item()
+    d32 = (d.H - hbf).abs().max().item()
+    _say(f"  {case}: FP32 densities move H by {d32:.3e} eV = {d32 / kmax:.2e} of max|K|")
+    assert d32 <= 1e-5 * kmax
+    _check([d], [h64], case)
