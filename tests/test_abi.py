@@ -88,6 +88,20 @@ def test_workspace_size_and_host_errors():
     st5.gvec = gv.ctypes.data
     assert L.bse_build_H(ctypes.byref(st5), 1, 0, P.BSE_TIME_REVERSAL, ctypes.c_void_p(0x1000), n, None) == -2
     assert "time reversal" in P.bse_last_error()
+    # FP32 pair densities only with a mixed precision, in the build, the
+    # autotuner and the backward; the backward takes no build-only flag
+    assert L.bse_build_H(ctypes.byref(st), 1, P.BSE_FP64, P.BSE_FP32_PAIRDENS, ctypes.c_void_p(0x1000), n,
+                         None) == -1
+    assert "mixed" in P.bse_last_error()
+    assert L.bse_autotune(ctypes.byref(st), 1, P.BSE_FP64, P.BSE_FP32_PAIRDENS, None, None, ctypes.c_void_p(0x1000),
+                          n, None) == -1
+    assert L.bse_build_H_backward(ctypes.byref(st), ctypes.c_void_p(0x1000), None, None, None, None, None,
+                                  P.BSE_FP64, P.BSE_FP32_PAIRDENS, ctypes.c_void_p(0x1000), n, None) == -1
+    assert L.bse_build_H_backward(ctypes.byref(st), ctypes.c_void_p(0x1000), None, None, None, None, None,
+                                  P.BSE_FP64, P.BSE_VALIDATE, ctypes.c_void_p(0x1000), n, None) == -1
+    # the workspace grows for the FP32 copy of u
+    n32 = L.bse_workspace_size(ctypes.byref(st), 1, P.BSE_BF16X3, P.BSE_FP32_PAIRDENS)
+    assert n32 >= n + 8 * s.nk * (s.nv + s.nc) * int(np.prod(s.grid))
     # pair densities: bad kind and out-of-range k pair
     out = ctypes.c_void_p(0x1000)
     assert L.bse_pair_density(ctypes.byref(st), 9, None, 0, None, out, ctypes.c_void_p(0x1000), n, None) == -1
