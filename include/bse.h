@@ -77,26 +77,28 @@ enum bse_flags {
     BSE_PERSISTENT = 2,  /* build a batch of systems with one persistent launch   */
     BSE_PROJECT_DW = 4,  /* backward: project dW onto Hermitian, time-reversal
                             symmetric W (group average of Sec. III.A, T = 1)     */
-    BSE_TIME_REVERSAL = 8, /* bse_build_H: the inputs obey time reversal without
-                            spin-orbit coupling.  For kbar the mesh point of -k,
-                            with -k = kbar - K (K a lattice vector, entries 0 or
-                            1 in units of the mesh), u_{n,kbar}(r_j) =
-                            exp(-i K.r_j) conj(u_{n,k}(r_j)), r_j = j/N per axis,
-                            for every k with kbar != k (as when the wave functions
-                            at -k are made from those at k; nothing is assumed
-                            at points that are their own partner).  Then the
-                            pair densities of a k pair follow from those of its
-                            image (kbar, kbar') (Sec. III.A, the pair-density
-                            transformation with time reversal): of each pair and
-                            its image only one is transformed, the other is
-                            gathered from it (conjugate on the sphere map of W,
-                            or the two bands exchanged).  Pairs that touch a
-                            point with kbar = k are transformed directly.  The G spheres must
-                            be closed under that map (else BSE_ERR_SHAPE).  With
-                            BSE_VALIDATE the relation of u is checked to
-                            1e-10 max|u| (else BSE_ERR_NOT_SYMMETRIC); without
-                            it, inputs that break it give a wrong H            */
-    BSE_FP32_PAIRDENS = 16 /* bse_build_H with BSE_SPLIT_FP32 or BSE_BF16X3 only
+    BSE_TIME_REVERSAL = 8, /* bse_build_H (and the backward): the inputs obey
+                            time reversal without spin-orbit coupling.  For kbar
+                            the mesh point of -k, with -k = kbar - K (K a lattice
+                            vector, entries 0 or 1 in units of the mesh),
+                            u_{n,kbar}(r_j) = exp(-i K.r_j) conj(u_{n,k}(r_j)),
+                            r_j = j/N per axis, for every k with kbar != k (as
+                            when the wave functions at -k are made from those at
+                            k; nothing is assumed at points that are their own
+                            partner).  Then the pair densities of a k pair follow
+                            from those of its image (kbar, kbar') (Sec. III.A,
+                            the pair-density transformation with time reversal):
+                            of each pair and its image only one is transformed,
+                            the other is gathered from it (conjugate on the
+                            sphere map of W, or the two bands exchanged).  Pairs
+                            that touch a point with kbar = k are transformed
+                            directly.  The G spheres must be closed under that
+                            map (else BSE_ERR_SHAPE).  With BSE_VALIDATE the
+                            relation of u is checked to 1e-10 max|u| (else
+                            BSE_ERR_NOT_SYMMETRIC); without it, inputs that
+                            break it give a wrong H                            */
+    BSE_FP32_PAIRDENS = 16 /* bse_build_H, bse_autotune and the backward, with
+                            BSE_SPLIT_FP32 or BSE_BF16X3 only
                             (else BSE_ERR_INVALID_ARG): the valence-valence and
                             conduction-conduction pair densities are transformed
                             in FP32 from an FP32 copy of u (rounded to nearest,
