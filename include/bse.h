@@ -267,8 +267,9 @@ enum bse_stage {
     BSE_STAGE_TR_FILL = 9,  /* BSE_TIME_REVERSAL: pair densities of the
                                image pairs                               */
     BSE_STAGE_TO_F32 = 10,  /* BSE_FP32_PAIRDENS: FP32 copy of u          */
-    BSE_STAGE_SPLIT_W = 11, /* mixed precisions: W(q) split into parts
-                               once per call for the direct term          */
+    BSE_STAGE_SPLIT_W = 11, /* mixed precisions: W(q) and the valence
+                               pair densities split into parts once per
+                               call for the first stage of the direct term */
     BSE_NSTAGES = 12
 };
 int bse_profile(int enable);

@@ -197,6 +197,7 @@ struct Plan {
   size_t o_u32 = 0;      // FP32 copy of the wave functions in the frame (pd32 only)
   int kpad = 0;          // ng_max rounded up to a multiple of 32
   size_t o_Ws = 0;       // W split for the mixed stage 1: [Nk][ng_max][4][kpad] of up to 4 bytes
+  size_t o_RVs = 0;      // conj(RV) split for the mixed stage 1: [rows][4][kpad] of up to 4 bytes
 };
 
 int check_system(const bse_system* s) {
@@ -440,6 +441,7 @@ int make_plan(const bse_system* s, Plan& P, bool pd32) {
   if (P.rot) P.o_ut = put((size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * sizeof(double2));
   P.kpad = (P.ng_max + 31) / 32 * 32;
   P.o_Ws = put((size_t)P.nk * P.ng_max * 4 * P.kpad * sizeof(float));
+  P.o_RVs = put((size_t)np * P.nv * P.nv * 4 * P.kpad * sizeof(float));
   P.pd32 = pd32 && pd_line_grid(P.N2, P.N3);
   if (P.pd32) P.o_u32 = put((size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * sizeof(float2));
   P.fwd_total = o;
@@ -507,6 +509,7 @@ GemmArgs gemm_args(const Plan& P, const bse_system* s, char* region) {
   g.nt = P.nt;
   g.Ws = region + P.o_Ws;
   g.kpad = P.kpad;
+  g.RVs = region + P.o_RVs;
   return g;
 }
 
@@ -898,8 +901,22 @@ int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& 
   const HTile* mt = reinterpret_cast<const HTile*>(ws + B.o_mt);
   const S1Tile* s1 = reinterpret_cast<const S1Tile*>(ws + B.o_s1);
   const int* d2off = reinterpret_cast<const int*>(ws + B.o_d2off);
-  for (int kind = 0; kind < 3; ++kind)
+  for (int kind = 0; kind < 3; ++kind) {
     if ((rc = run_pd(B, ws, kind, tn, st)) || (rc = run_tr_fill(B, ws, kind, st))) return rc;
+    if (kind == 1 && precision != BSE_FP64) {
+      // the A operand of the mixed stage 1, split once
+      for (int i = 0; i < nsys; ++i) {
+        const Plan& P = B.P[i];
+        char* region = ws + B.base[i];
+        HIP_TRY(stage(BSE_STAGE_SPLIT_W, st, [&] {
+          return launch_split_rv(reinterpret_cast<const double2*>(region + P.o_RV),
+                                 reinterpret_cast<const int4*>(region + P.o_pairs),
+                                 reinterpret_cast<const int*>(region + P.o_ng), P.pairs.size() * P.nv * P.nv,
+                                 P.nv * P.nv, P.ng_max, P.kpad, precision, region + P.o_RVs, st);
+        }));
+      }
+    }
+  }
   HIP_TRY(stage(BSE_STAGE_EXCHANGE, st, [&] { return launch_exchange(gs, xt, (int)B.xt.size(), precision, st); }));
   HIP_TRY(stage(BSE_STAGE_DIRECT1, st, [&] { return launch_direct_s1(gs, s1, (int)B.s1.size(), precision, st); }));
   HIP_TRY(stage(BSE_STAGE_DIRECT2, st, [&] { return launch_direct_s2(gs, d2off, nsys, B.d2n, st); }));

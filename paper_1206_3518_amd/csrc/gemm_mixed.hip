@@ -49,8 +49,9 @@ __global__ __launch_bounds__(256) void k_direct_s1_mx(const GemmArgs* __restrict
   const int r0 = tl.mt * MTM, c0 = tl.nt * MTN;
   typedef typename Split<P>::T T;
   const T* Wsq = reinterpret_cast<const T*>(g.Ws) + (size_t)tl.iq * g.ng_max * 4 * g.kpad;
-  tile_gemm_mx<P, true, false, false, true>(A, g.ng_max, r0, rows, Wq, g.ng_max, c0, K, K, false, cre, cim, Wsq,
-                                            g.kpad);
+  const T* RVs = reinterpret_cast<const T*>(g.RVs) + (size_t)row_base * 4 * g.kpad;
+  tile_gemm_mx<P, true, false, false, true, true>(A, g.ng_max, r0, rows, Wq, g.ng_max, c0, K, K, false, cre, cim,
+                                                  Wsq, g.kpad, RVs);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
   double2* Z = g.Z + (size_t)row_base * g.ng_max;
 #pragma unroll
@@ -101,6 +102,42 @@ __global__ __launch_bounds__(256) void k_split_w(const double2* __restrict__ W, 
     for (int pl = 0; pl < 4; ++pl) row[(size_t)pl * kpad] = h[pl];
   }
   }
+}
+
+// The valence pair-density rows split, conjugated, into RVs[row][part][kpad]
+// (the A operand of stage 1): one thread per (row, k); a row of pair p holds
+// ng(q_p) values, the rest (and k >= ng_max) is written as zero, whatever the
+// row's tail in RV holds.
+template <int P>
+__global__ __launch_bounds__(256) void k_split_rv(const double2* __restrict__ RV, const int4* __restrict__ pairs,
+                                                  const int* __restrict__ ng, size_t nrows, int rows_per_pair,
+                                                  int ld, int kpad, typename Split<P>::T* __restrict__ Xs) {
+  const size_t n = nrows * (size_t)kpad;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const size_t row = i / kpad;
+    const int k = (int)(i - row * kpad);
+    const int valid = ng[pairs[row / rows_per_pair].z];
+    const double2 v = k < valid ? RV[row * ld + k] : make_double2(0.0, 0.0);
+    typename Split<P>::T h[4];
+    Split<P>::split(v.x, h[0], h[1]);
+    Split<P>::split(-v.y, h[2], h[3]);
+    typename Split<P>::T* o = Xs + row * 4 * kpad + k;
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) o[(size_t)pl * kpad] = h[pl];
+  }
+}
+
+hipError_t launch_split_rv(const double2* RV, const int4* pairs, const int* ng, size_t nrows, int rows_per_pair,
+                           int ld, int kpad, int precision, void* RVs, hipStream_t st) {
+  if (nrows == 0) return hipSuccess;
+  const dim3 grid(8192), blk(256);
+  if (precision == BSE_BF16X3)
+    hipLaunchKernelGGL(k_split_rv<BSE_BF16X3>, grid, blk, 0, st, RV, pairs, ng, nrows, rows_per_pair, ld, kpad,
+                       reinterpret_cast<unsigned short*>(RVs));
+  else
+    hipLaunchKernelGGL(k_split_rv<BSE_SPLIT_FP32>, grid, blk, 0, st, RV, pairs, ng, nrows, rows_per_pair, ld, kpad,
+                       reinterpret_cast<float*>(RVs));
+  return hipGetLastError();
 }
 
 hipError_t launch_split_w(const double2* W, const int* ng, int nk, int ng_max, int kpad, int head, int precision,

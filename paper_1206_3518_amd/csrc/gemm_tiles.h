@@ -201,11 +201,14 @@ __device__ __forceinline__ void put8(TileLds<P>& L, int r, int k0, const double2
 // B_PRE: B comes already split, as Bp[n][plane][k] (row stride 4 ldk, planes
 // re hi, re lo, im hi, im lo; zero for k >= K up to a multiple of 32), and is
 // copied to LDS without conversion (B, ldb, B_T and zero_head unused).
-template <int P, bool CONJ_A, bool B_T, bool A_T = false, bool B_PRE = false>
+// A_PRE: the same for A, Ap[m][plane][k] (already conjugated if it is to be;
+// A, lda, A_T and CONJ_A unused).
+template <int P, bool CONJ_A, bool B_T, bool A_T = false, bool B_PRE = false, bool A_PRE = false>
 __device__ __forceinline__ void tile_gemm_mx(const double2* __restrict__ A, int lda, int a_off, int a_lim,
                                              const double2* __restrict__ B, int ldb, int b_off, int b_lim, int K,
                                              bool zero_head, f4 (&cre)[2][2], f4 (&cim)[2][2],
-                                             const typename Split<P>::T* __restrict__ Bp = nullptr, int ldk = 0) {
+                                             const typename Split<P>::T* __restrict__ Bp = nullptr, int ldk = 0,
+                                             const typename Split<P>::T* __restrict__ Ap = nullptr) {
   extern __shared__ double2 smem_mx_raw[];  // 16-byte aligned dynamic area
   char* smem_mx = reinterpret_cast<char*>(smem_mx_raw);
   TileLds<P>& As = *reinterpret_cast<TileLds<P>*>(smem_mx);
@@ -225,17 +228,29 @@ __device__ __forceinline__ void tile_gemm_mx(const double2* __restrict__ A, int 
   // one; out-of-range elements are read from the array start and zeroed
   typedef typename Split<P>::T T;
   constexpr int QW = sizeof(T) * 8 / 16;  // 16-byte words per plane row segment of 8 k
-  double2 xa[8], xb[B_PRE ? 1 : 8];
-  uint4 xp[B_PRE ? 4 * QW : 1];
+  double2 xa[A_PRE ? 1 : 8], xb[B_PRE ? 1 : 8];
+  uint4 xp[B_PRE ? 4 * QW : 1], xq[A_PRE ? 4 * QW : 1];
   auto load = [&](int k0) {
     const int gr = a_off + r;
+    if constexpr (A_PRE) {
+      const bool ok = gr < a_lim;
+      const T* row = Ap + (ok ? (size_t)gr * 4 * ldk : 0) + k0 + kq;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int k = k0 + kq + i;
-      const bool ok = gr < a_lim && k < K;
-      const size_t idx = A_T ? (size_t)k * lda + gr : (size_t)gr * lda + k;
-      const double2 v = gld(A, ok ? idx : 0);
-      xa[i] = make_double2(ok ? v.x : 0.0, ok ? v.y : 0.0);
+      for (int pl = 0; pl < 4; ++pl)
+#pragma unroll
+        for (int w4 = 0; w4 < QW; ++w4) {
+          const uint4 v = gld16(reinterpret_cast<const uint4*>(row + (size_t)pl * ldk) + w4);
+          xq[pl * QW + w4] = ok ? v : make_uint4(0u, 0u, 0u, 0u);
+        }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int k = k0 + kq + i;
+        const bool ok = gr < a_lim && k < K;
+        const size_t idx = A_T ? (size_t)k * lda + gr : (size_t)gr * lda + k;
+        const double2 v = gld(A, ok ? idx : 0);
+        xa[i] = make_double2(ok ? v.x : 0.0, ok ? v.y : 0.0);
+      }
     }
     if constexpr (B_PRE) {
       const bool ok = b_off + r < b_lim;
@@ -260,7 +275,16 @@ __device__ __forceinline__ void tile_gemm_mx(const double2* __restrict__ A, int 
   };
   if (K > 0) load(0);
   for (int k0 = 0; k0 < K; k0 += MKC) {
-    put8<P>(As, r, kq, xa, CONJ_A);
+    if constexpr (A_PRE) {
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) {
+        const T* src = reinterpret_cast<const T*>(&xq[pl * QW]);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) As.v[pl][r * ST + kq + i] = src[i];
+      }
+    } else {
+      put8<P>(As, r, kq, xa, CONJ_A);
+    }
     if constexpr (B_PRE) {
 #pragma unroll
       for (int pl = 0; pl < 4; ++pl) {

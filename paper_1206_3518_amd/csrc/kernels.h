@@ -99,6 +99,7 @@ struct GemmArgs {
   const void* Ws;       // mixed precision: W split and transposed, [Nk][ng_max][4][kpad] of the
                         // split type (planes re hi, re lo, im hi, im lo), head left out
   int kpad;             // ng_max rounded up to a multiple of 32
+  const void* RVs;      // mixed precision: conj(RV) split, [rows][4][kpad] of the split type
 };
 
 // The contractions run over a batch: gs is a device array of per-system
@@ -114,6 +115,10 @@ hipError_t launch_mirror(const GemmArgs* gs, const HTile* tiles, int ntiles, hip
 // Ws[q][n][pl][k] = part pl of W[q][k][n] for k, n < ng(q), zero elsewhere up
 // to kpad (and at the q = 0 head when head != 0); precision BSE_SPLIT_FP32 or
 // BSE_BF16X3 (parts as in the mixed contractions).
+// RVs[row][pl][k] = part pl of conj(RV[row][k]) for k < ng(q of the row's
+// pair), zero up to kpad; rows_per_pair = nv^2.
+hipError_t launch_split_rv(const double2* RV, const int4* pairs, const int* ng, size_t nrows, int rows_per_pair,
+                           int ld, int kpad, int precision, void* RVs, hipStream_t st);
 hipError_t launch_split_w(const double2* W, const int* ng, int nk, int ng_max, int kpad, int head, int precision,
                           void* Ws, hipStream_t st);
 // mixed-precision bodies (precision BSE_SPLIT_FP32 or BSE_BF16X3), called by the above
