@@ -33,6 +33,21 @@
  *   - A non-zero return means nothing was enqueued (argument errors) or that
  *     a HIP call failed; bse_last_error() gives text for the calling thread.
  *   - Calls on one device that share a workspace must not overlap.
+ *
+ * State kept between calls (host side only; no device memory):
+ *   - a pinned host staging buffer per calling thread (hipHostMalloc, grown
+ *     on demand) from which the plan tables are copied;
+ *   - a cache of the last four host plans per calling thread, keyed by the
+ *     shapes and the contents of the host sphere tables, so that a repeated
+ *     build of one shape skips planning;
+ *   - the launch choices bse_autotune measured, per batch signature, for the
+ *     life of the process (shared by all threads);
+ *   - the per-stage timing records while bse_profile is enabled;
+ *   - the text of the last error per thread.
+ * bse_release_host_state() frees the first three.  The only file the library
+ * touches is the tuning cache that the caller names in bse_autotune: read on
+ * every call and appended to when a new signature is timed; bse_build_H
+ * reads no file.
  */
 #ifndef BSE_H
 #define BSE_H
@@ -231,20 +246,36 @@ int bse_autotune(const bse_system *sys, int nsys, int precision, int flags, cons
 int bse_autotune_last(bse_tuning *tried, int max_tried);
 
 /*
+ * Transition dipoles of the optical limit (Sec. II.B: for q -> 0 the pair
+ * density n_{vk,ck}(0) tends to -i q.<u_vk|grad|u_ck>/(e_ck - e_vk); the
+ * spectrum of Sec. II.C pairs each exciton with that factor per unit |q|):
+ *   d[p][S] = qhat_p . <u_vk|grad|u_ck> / ((e_ck - e_vk) / E_h)
+ * in Hartree atomic units (bohr), S = (k*nv + v)*nc + c, for nq polarisations
+ * qhat (HOST [nq][3], Cartesian, used as given; 1 <= nq <= 8).  The matrix
+ * element is the spectral derivative of u with the Nyquist planes removed
+ * (cell: HOST [9], rows a1 a2 a3 in bohr).  d is DEVICE [nq][NS] complex.
+ * Every grid length must be in the supported set and nc <= 8.  ws needs
+ * bse_transition_dipoles_workspace(sys) bytes.
+ */
+int bse_transition_dipoles(const bse_system *sys, const double *cell, const double *qhat, int nq, double *d,
+                           void *ws, size_t ws_bytes, void *stream);
+size_t bse_transition_dipoles_workspace(const bse_system *sys);
+
+/*
  * Absorption spectrum from the spectral representation of the irreducible
  * response (Sec. II.C, macroscopic dielectric function with Vbar; Tamm-Dancoff
- * so the overlap matrix is the identity):
- *   t_l     = sum_S A[S][l] d[S]
- *   eps2(w) = pref * sum_l |t_l|^2 * eta / ((w - E_l)^2 + eta^2)
- * E (DEVICE [nlam], eV), A (DEVICE [ns][nlam] complex, eigenvectors as
- * columns), d (DEVICE [ns] complex, Hartree atomic units), eps2 (DEVICE [nw])
- * on w_i = w0 + i*(w1-w0)/(nw-1).  Energies and eta are in eV and converted
- * to Hartree inside; pref carries 8 pi / (Nk Omega_cell) (spin 2).  ws
- * (DEVICE) needs nlam doubles.
+ * so the overlap matrix is the identity), averaged over nq polarisations:
+ *   t_pl    = sum_S A[S][l] d[p][S]
+ *   eps2(w) = 8 pi / (nk * omega_cell) * (1/nq) sum_p sum_l |t_pl|^2 * eta / ((w - E_l)^2 + eta^2)
+ * (spin 2, eta the half width).  E (DEVICE [nlam], eV), A (DEVICE [ns][nlam]
+ * complex, eigenvectors as columns), d (DEVICE [nq][ns] complex, from
+ * bse_transition_dipoles), eps2 (DEVICE [nw]) on w_i = w0 + i*(w1-w0)/(nw-1).
+ * Energies and eta are in eV and converted to Hartree inside.  ws (DEVICE)
+ * needs nlam doubles.
  */
-int bse_spectrum(int ns, int nlam, const double *E, const double *A, const double *d, double pref,
-                 int nw, double w0_eV, double w1_eV, double eta_eV, double *eps2, void *ws, size_t ws_bytes,
-                 void *stream);
+int bse_spectrum(int ns, int nlam, const double *E, const double *A, const double *d, int nq, int nk,
+                 double omega_cell, int nw, double w0_eV, double w1_eV, double eta_eV, double *eps2, void *ws,
+                 size_t ws_bytes, void *stream);
 
 /*
  * Per-stage GPU timing of bse_build_H.  While enabled, every kernel launch of
@@ -274,6 +305,11 @@ enum bse_stage {
 };
 int bse_profile(int enable);
 int bse_profile_read(double *total_ms, long long *launches, int nstages, int reset);
+
+/* Frees the calling thread's pinned staging buffer and plan cache (after
+ * waiting for the copies that read the buffer) and forgets every tuned launch
+ * choice; the next call rebuilds what it needs. */
+int bse_release_host_state(void);
 
 /* Text describing the last non-zero status returned on this thread. */
 const char *bse_last_error(void);

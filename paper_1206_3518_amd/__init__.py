@@ -46,7 +46,8 @@ class bse_system(ctypes.Structure):
 
 
 SYMBOLS = ["bse_workspace_size", "bse_pair_density", "bse_build_H", "bse_build_H_backward",
-           "bse_autotune", "bse_autotune_last", "bse_spectrum", "bse_profile", "bse_profile_read", "bse_last_error"]
+           "bse_autotune", "bse_autotune_last", "bse_transition_dipoles", "bse_transition_dipoles_workspace",
+           "bse_spectrum", "bse_profile", "bse_profile_read", "bse_release_host_state", "bse_last_error"]
 STAGES = ["vscale", "pd_exch", "pd_vv", "pd_cc", "exchange", "direct1", "direct2", "mirror", "rotate", "tr_fill", "to_f32", "split_w"]
 
 
@@ -70,8 +71,14 @@ def lib():
         L.bse_autotune.restype = I
         L.bse_autotune_last.argtypes = [P, I]
         L.bse_autotune_last.restype = I
-        L.bse_spectrum.argtypes = [I, I, P, P, P, D, I, D, D, D, P, P, S, P]
+        L.bse_transition_dipoles.argtypes = [P, P, P, I, P, P, S, P]
+        L.bse_transition_dipoles.restype = I
+        L.bse_transition_dipoles_workspace.argtypes = [P]
+        L.bse_transition_dipoles_workspace.restype = S
+        L.bse_spectrum.argtypes = [I, I, P, P, P, I, I, D, I, D, D, D, P, P, S, P]
         L.bse_spectrum.restype = I
+        L.bse_release_host_state.argtypes = []
+        L.bse_release_host_state.restype = I
         L.bse_profile.argtypes = [I]
         L.bse_profile.restype = I
         L.bse_profile_read.argtypes = [P, P, I, I]
@@ -322,36 +329,52 @@ def build_H_autograd(system: DeviceSystem, W, eps, precision="fp64", project=Tru
     return _BUILDH.apply(W, eps, system, precision, project)
 
 
-def bse_spectrum(E, A, d, pref, nw, w0_eV, w1_eV, eta_eV, ws=None, stream=None):
+def bse_transition_dipoles(system: DeviceSystem, qhats, ws=None, stream=None, cell=None):
+    """Transition dipoles d[p][S] (Hartree atomic units, complex128 [nq][NS])
+    for the polarisations qhats ([nq][3])."""
+    import torch
+    q = np.ascontiguousarray(np.asarray(qhats, dtype=np.float64).reshape(-1, 3))
+    cell_arr = np.ascontiguousarray(system.src.cell if cell is None else cell, dtype=np.float64)
+    st = system.struct()
+    if ws is None:
+        n = lib().bse_transition_dipoles_workspace(ctypes.byref(st))
+        if n == 0:
+            raise BseError(-1, bse_last_error())
+        ws = workspace(n, system.device)
+    d = torch.empty((len(q), system.ns), dtype=torch.complex128, device=system.device)
+    _check(lib().bse_transition_dipoles(ctypes.byref(st), cell_arr.ctypes.data, q.ctypes.data, len(q), _ptr(d),
+                                        _ptr(ws), ws.numel(), _stream(stream)))
+    return d
+
+
+def bse_spectrum(E, A, d, nk, omega_cell, nw, w0_eV, w1_eV, eta_eV, ws=None, stream=None):
     """eps2 on nw points of [w0, w1] (eV) from exciton energies E (eV, [nlam]),
-    eigenvectors A ([ns][nlam] complex) and transition dipoles d ([ns])."""
+    eigenvectors A ([ns][nlam] complex) and transition dipoles d ([nq][ns] or
+    [ns]), averaged over the nq polarisations."""
     import torch
     E = E.contiguous()
     A = A.contiguous()
-    d = d.contiguous()
+    d = d.reshape(-1, A.shape[0]).contiguous()
     ns, nlam = A.shape
     eps2 = torch.empty(nw, dtype=torch.float64, device=A.device)
     if ws is None:
         ws = workspace(8 * nlam, A.device)
-    _check(lib().bse_spectrum(ns, nlam, _ptr(E), _ptr(A), _ptr(d), float(pref), int(nw), float(w0_eV), float(w1_eV),
-                              float(eta_eV), _ptr(eps2), _ptr(ws), ws.numel(), _stream(stream)))
+    _check(lib().bse_spectrum(ns, nlam, _ptr(E), _ptr(A), _ptr(d), d.shape[0], int(nk), float(omega_cell), int(nw),
+                              float(w0_eV), float(w1_eV), float(eta_eV), _ptr(eps2), _ptr(ws), ws.numel(),
+                              _stream(stream)))
     return eps2
 
 
+def bse_release_host_state():
+    _check(lib().bse_release_host_state())
+
+
 def absorption(system: DeviceSystem, H, qhats=((1, 0, 0), (0, 1, 0), (0, 0, 1)), nw=1001, w0=0.0, w1=10.0, eta=0.1):
-    """eps2(w) averaged over the polarisations qhats: FP64 host eigensolve of H,
-    dipoles and spectrum on the GPU."""
+    """eps2(w) averaged over the polarisations qhats: FP64 host eigensolve of H
+    (numpy LAPACK), then the dipoles and the spectrum in the library."""
     import torch
-    Hn = H.cpu().numpy()
-    E, A = np.linalg.eigh(Hn)
+    E, A = np.linalg.eigh(H.cpu().numpy())
     Ed = torch.from_numpy(E).to(system.device)
     Ad = torch.from_numpy(np.ascontiguousarray(A)).to(system.device)
-    D = bse_pair_density(system, BSE_PD_DIPOLE)                         # [Nk][nv][nc][3], bohr^-1
-    de = (system.eps[:, None, system.nv:] - system.eps[:, :system.nv, None]) / HARTREE_EV
-    pref = 8.0 * np.pi / (system.nk * system.omega_cell)
-    out = torch.zeros(nw, dtype=torch.float64, device=system.device)
-    for q in qhats:
-        qv = torch.tensor(q, dtype=torch.complex128, device=system.device)
-        d = ((D @ qv) / de).reshape(-1).contiguous()
-        out += bse_spectrum(Ed, Ad, d, pref, nw, w0, w1, eta)
-    return out / len(qhats)
+    d = bse_transition_dipoles(system, qhats)
+    return bse_spectrum(Ed, Ad, d, system.nk, system.omega_cell, nw, w0, w1, eta)

@@ -307,12 +307,17 @@ int make_plan(const bse_system* s, Plan& P, bool pd32) {
     for (int i = 0; i < mt; ++i)
       for (int j = 0; j < nt; ++j) P.s1.push_back(S1Tile{q, i, j, 0});
   }
-  // exchange tiles: upper tile triangle plus the first sub-diagonal (k blocks
-  // of nv*nc rows may straddle a 64-row tile boundary)
+  // exchange tiles: every 64 x 64 tile that holds an entry of a block k <= k'
+  // (its first row's k block is at most its last column's).  A k block of
+  // nv*nc rows may span several tiles, so a diagonal block can reach tiles
+  // well below the tile diagonal.
   P.xt.clear();
   const int T = (P.ns + 63) / 64;
   for (int i = 0; i < T; ++i)
-    for (int j = std::max(0, i - 1); j < T; ++j) P.xt.push_back(HTile{i, j, 0, 0});
+    for (int j = 0; j < T; ++j) {
+      const int last_col = std::min(P.ns, 64 * (j + 1)) - 1;
+      if ((64 * i) / P.nt <= last_col / P.nt) P.xt.push_back(HTile{i, j, 0, 0});
+    }
   // mirror tiles: 32 x 32 destination tiles on or below the diagonal
   P.mt.clear();
   const int T32 = (P.ns + 31) / 32;
@@ -1081,6 +1086,32 @@ int autotune(const bse_system* sys, int nsys, int precision, bool pd32, const ch
   return BSE_OK;
 }
 
+// Reciprocal vectors b = 2 pi A^-T (rows) of the cell A (rows a1, a2, a3) and
+// the checks of the full-grid FFT the k.p matrix elements need.
+int grad_setup(const bse_system* sys, const Plan& P, const double* cell, GradCell& bc) {
+  if (!cell) return fail(BSE_ERR_INVALID_ARG, "cell is NULL (needed for the dipoles)");
+  const int G1 = sys->grid[0], G2 = sys->grid[1], G3 = sys->grid[2];  // grid order, not the pair-density frame
+  if (!fft_len_supported(G1) || !fft_len_supported(G2) || !fft_len_supported(G3))
+    return fail(BSE_ERR_SHAPE, "grid (%d, %d, %d) has no full-grid FFT", G1, G2, G3);
+  if (P.nc > 8) return fail(BSE_ERR_SHAPE, "dipoles support at most 8 conduction bands");
+  const double* A = cell;
+  const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                     A[2] * (A[3] * A[7] - A[4] * A[6]);
+  if (!(std::fabs(det) > 0.0)) return fail(BSE_ERR_INVALID_ARG, "singular cell");
+  const double tp = 6.283185307179586476925286766559 / det;
+  // rows of 2 pi (A^-1)^T = 2 pi / det * cofactor rows
+  bc.b[0][0] = tp * (A[4] * A[8] - A[5] * A[7]);
+  bc.b[0][1] = tp * (A[5] * A[6] - A[3] * A[8]);
+  bc.b[0][2] = tp * (A[3] * A[7] - A[4] * A[6]);
+  bc.b[1][0] = tp * (A[2] * A[7] - A[1] * A[8]);
+  bc.b[1][1] = tp * (A[0] * A[8] - A[2] * A[6]);
+  bc.b[1][2] = tp * (A[1] * A[6] - A[0] * A[7]);
+  bc.b[2][0] = tp * (A[1] * A[5] - A[2] * A[4]);
+  bc.b[2][1] = tp * (A[2] * A[3] - A[0] * A[5]);
+  bc.b[2][2] = tp * (A[0] * A[4] - A[1] * A[3]);
+  return BSE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1127,32 +1158,12 @@ int bse_pair_density(const bse_system* sys, int kind, const int* kpairs, int npa
                            i * nA * nA});
     }
   } else if (kind == BSE_PD_DIPOLE) {
-    if (!cell) return fail(BSE_ERR_INVALID_ARG, "cell is NULL (needed for the dipole kind)");
-    const int G1 = sys->grid[0], G2 = sys->grid[1], G3 = sys->grid[2];  // grid order, not the pair-density frame
-    if (!fft_len_supported(G1) || !fft_len_supported(G2) || !fft_len_supported(G3))
-      return fail(BSE_ERR_SHAPE, "grid (%d, %d, %d) has no full-grid FFT", G1, G2, G3);
-    if (P.nc > 8) return fail(BSE_ERR_SHAPE, "dipoles support at most 8 conduction bands");
+    GradCell bc;
+    if ((rc = grad_setup(sys, P, cell, bc))) return rc;
     const size_t need = (size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * sizeof(double2);
     if (ws_bytes < need) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
-    // reciprocal vectors b = 2 pi A^-T (rows)
-    const double* A = cell;
-    const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
-                       A[2] * (A[3] * A[7] - A[4] * A[6]);
-    if (!(std::fabs(det) > 0.0)) return fail(BSE_ERR_INVALID_ARG, "singular cell");
-    GradCell bc;
-    const double tp = 6.283185307179586476925286766559 / det;
-    // rows of 2 pi (A^-1)^T = 2 pi / det * cofactor rows
-    bc.b[0][0] = tp * (A[4] * A[8] - A[5] * A[7]);
-    bc.b[0][1] = tp * (A[5] * A[6] - A[3] * A[8]);
-    bc.b[0][2] = tp * (A[3] * A[7] - A[4] * A[6]);
-    bc.b[1][0] = tp * (A[2] * A[7] - A[1] * A[8]);
-    bc.b[1][1] = tp * (A[0] * A[8] - A[2] * A[6]);
-    bc.b[1][2] = tp * (A[1] * A[6] - A[0] * A[7]);
-    bc.b[2][0] = tp * (A[1] * A[5] - A[2] * A[4]);
-    bc.b[2][1] = tp * (A[2] * A[3] - A[0] * A[5]);
-    bc.b[2][2] = tp * (A[0] * A[4] - A[1] * A[3]);
     HIP_TRY(launch_grad(reinterpret_cast<const double2*>(sys->u), static_cast<double2*>(ws), P.nk, P.nb, P.nv, P.nc,
-                        G1, G2, G3, bc, reinterpret_cast<double2*>(out), st));
+                        sys->grid[0], sys->grid[1], sys->grid[2], bc, reinterpret_cast<double2*>(out), st));
     return BSE_OK;
   } else {
     return fail(BSE_ERR_INVALID_ARG, "unknown kind %d", kind);
@@ -1345,15 +1356,60 @@ int bse_autotune_last(bse_tuning* tried, int max_tried) {
   return (int)g_tried.size();
 }
 
-int bse_spectrum(int ns, int nlam, const double* E, const double* A, const double* d, double pref, int nw,
-                 double w0_eV, double w1_eV, double eta_eV, double* eps2, void* ws, size_t ws_bytes, void* stream) {
+int bse_transition_dipoles(const bse_system* sys, const double* cell, const double* qhat, int nq, double* d,
+                           void* ws, size_t ws_bytes, void* stream) {
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  Plan P;
+  int rc = make_plan(sys, P, false);
+  if (rc) return rc;
+  if (!d || !ws || !qhat) return fail(BSE_ERR_INVALID_ARG, "d / ws / qhat is NULL");
+  if (nq < 1 || nq > kMaxQhat) return fail(BSE_ERR_INVALID_ARG, "nq = %d not in 1..%d", nq, kMaxQhat);
+  GradCell bc;
+  if ((rc = grad_setup(sys, P, cell, bc))) return rc;
+  Qhats qh{};
+  for (int q = 0; q < nq; ++q)
+    for (int x = 0; x < 3; ++x) {
+      qh.v[q][x] = qhat[3 * q + x];
+      if (!std::isfinite(qh.v[q][x])) return fail(BSE_ERR_INVALID_ARG, "qhat is not finite");
+    }
+  const size_t fft = align256((size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * sizeof(double2));
+  const size_t need = fft + (size_t)P.ns * 3 * sizeof(double2);
+  if (ws_bytes < need) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+  char* w = static_cast<char*>(ws);
+  double2* D = reinterpret_cast<double2*>(w + fft);
+  HIP_TRY(launch_grad(reinterpret_cast<const double2*>(sys->u), reinterpret_cast<double2*>(w), P.nk, P.nb, P.nv, P.nc,
+                      sys->grid[0], sys->grid[1], sys->grid[2], bc, D, st));
+  HIP_TRY(launch_dipole_project(D, sys->eps, qh, nq, P.nk, P.nv, P.nc, reinterpret_cast<double2*>(d), st));
+  return BSE_OK;
+}
+
+size_t bse_transition_dipoles_workspace(const bse_system* sys) {
+  Plan P;
+  if (make_plan(sys, P, false)) return 0;
+  return align256((size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * sizeof(double2)) + (size_t)P.ns * 3 * sizeof(double2);
+}
+
+// Arguments of bse_spectrum (shared with its variant without workspace).
+static int spectrum_args(int ns, int nlam, const double* E, const double* A, const double* d, int nq, int nk,
+                  double omega_cell, int nw, double eta_eV, double* eps2) {
   if (ns < 1 || nlam < 1 || nlam > ns || nw < 1) return fail(BSE_ERR_INVALID_ARG, "bad sizes");
-  if (!E || !A || !d || !eps2 || !ws) return fail(BSE_ERR_INVALID_ARG, "NULL pointer");
+  if (nq < 1 || nk < 1) return fail(BSE_ERR_INVALID_ARG, "nq and nk must be positive");
+  if (!E || !A || !d || !eps2) return fail(BSE_ERR_INVALID_ARG, "NULL pointer");
   if (!(eta_eV > 0.0)) return fail(BSE_ERR_INVALID_ARG, "eta must be positive");
+  if (!(omega_cell > 0.0)) return fail(BSE_ERR_INVALID_ARG, "omega_cell must be positive");
+  return BSE_OK;
+}
+
+int bse_spectrum(int ns, int nlam, const double* E, const double* A, const double* d, int nq, int nk,
+                 double omega_cell, int nw, double w0_eV, double w1_eV, double eta_eV, double* eps2, void* ws,
+                 size_t ws_bytes, void* stream) {
+  int rc = spectrum_args(ns, nlam, E, A, d, nq, nk, omega_cell, nw, eta_eV, eps2);
+  if (rc) return rc;
+  if (!ws) return fail(BSE_ERR_INVALID_ARG, "workspace is NULL");
   if (ws_bytes < (size_t)nlam * sizeof(double)) return fail(BSE_ERR_WORKSPACE, "workspace below nlam doubles");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  HIP_TRY(launch_spectrum(ns, nlam, E, reinterpret_cast<const double2*>(A), reinterpret_cast<const double2*>(d), pref,
-                          nw, w0_eV, w1_eV, eta_eV, static_cast<double*>(ws), eps2, st));
+  HIP_TRY(launch_spectrum(ns, nlam, nq, E, reinterpret_cast<const double2*>(A), reinterpret_cast<const double2*>(d),
+                          (double)nk * omega_cell, nw, w0_eV, w1_eV, eta_eV, static_cast<double*>(ws), eps2, st));
   return BSE_OK;
 }
 
@@ -1385,6 +1441,27 @@ int bse_profile_read(double* total_ms, long long* launches, int nstages, int res
       g_prof_ms[i] = 0;
       g_prof_n[i] = 0;
     }
+  return BSE_OK;
+}
+
+int bse_release_host_state(void) {
+  Staging& S = g_staging;
+  if (S.pending) {
+    HIP_TRY(hipEventSynchronize(S.done));
+    S.pending = false;
+  }
+  if (S.buf) HIP_TRY(hipHostFree(S.buf));
+  S.buf = nullptr;
+  S.cap = 0;
+  if (S.done) HIP_TRY(hipEventDestroy(S.done));
+  S.done = nullptr;
+  for (PlanCache& c : g_plan) {
+    c.key.clear();
+    c.B = Batch{};
+    c.used = 0;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
   return BSE_OK;
 }
 

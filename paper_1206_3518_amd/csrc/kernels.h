@@ -196,8 +196,19 @@ hipError_t launch_tr_fill(const TrArgs* as, const int4* items, int nitems, int k
 bool fft_len_supported(int N);
 hipError_t launch_grad(const double2* u, double2* scratch, int nk, int nb, int nv, int nc, int N1, int N2, int N3,
                        const GradCell& bc, double2* out, hipStream_t st);
-hipError_t launch_spectrum(int ns, int nlam, const double* E, const double2* A, const double2* d, double pref,
-                           int nw, double w0, double w1, double eta, double* t2, double* eps2, hipStream_t st);
+// Polarisations of the transition dipoles (Cartesian unit vectors, at most 8).
+constexpr int kMaxQhat = 8;
+struct Qhats {
+  double v[kMaxQhat][3];
+};
+// d[q][S] = qhat_q . D[S] / ((e_ck - e_vk) / E_h) from D = <u_vk|grad|u_ck> [NS][3]
+hipError_t launch_dipole_project(const double2* D, const double* eps, const Qhats& qh, int nq, int nk, int nv,
+                                 int nc, double2* d, hipStream_t st);
+// eps2 on nw points of [w0, w1] (eV) from nlam excitons and nq polarisation
+// rows of d ([nq][ns]); nk_omega = Nk * Omega_cell; t2 scratch of nlam doubles
+hipError_t launch_spectrum(int ns, int nlam, int nq, const double* E, const double2* A, const double2* d,
+                           double nk_omega, int nw, double w0, double w1, double eta, double* t2, double* eps2,
+                           hipStream_t st);
 
 hipError_t launch_adjoint(const AdjArgs& a, int precision, int ndw_tiles, bool project, hipStream_t st);
 // dL/drho_cc' from Z (run before launch_adjoint overwrites Z with T)

@@ -5,8 +5,9 @@
 //   k_fft_axis     batched in-place DFT of full grids along one axis
 //   k_grad         S_d = sum_m m_d conj(U_v(m)) U_c(m), Nyquist planes dropped,
 //                  <u_v|grad|u_c> = (i / N_r) sum_d S_d b_d
-//   k_spec_t       t_l = sum_S A[S][l] d[S]
-//   k_spec_eps2    eps2(w) = pref sum_l |t_l|^2 eta / ((w - E_l)^2 + eta^2)
+//   k_dipole_project  d_S = qhat . <u_vk|grad|u_ck> / (e_ck - e_vk), Hartree units
+//   k_spec_t       t_l = sum_S A[S][l] d[S], |t_l|^2 averaged over polarisations
+//   k_spec_eps2    eps2(w) = 8 pi / (Nk Omega_cell) sum_l |t_l|^2 eta / ((w - E_l)^2 + eta^2)
 #include "bse_internal.h"
 #include "fft_row.h"
 #include "kernels.h"
@@ -167,20 +168,61 @@ hipError_t launch_grad(const double2* u, double2* scratch, int nk, int nb, int n
   return hipGetLastError();
 }
 
-__global__ void k_spec_t(int ns, int nlam, const double2* __restrict__ A, const double2* __restrict__ d,
+// Transition dipoles of nq polarisations:
+//   d[q][S] = qhat_q . D[S] / ((e_ck - e_vk) / E_h),   D[S] = <u_vk|grad|u_ck> (bohr^-1)
+// (Sec. II.B: the q -> 0 limit of n_{vk,ck}(0) divided by -i q, in Hartree
+// atomic units).
+__global__ void k_dipole_project(const double2* __restrict__ D, const double* __restrict__ eps, Qhats qh,
+                                 int nq, int nk, int nv, int nc, double2* __restrict__ d) {
+  const int ns = nk * nv * nc;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns * nq) return;
+  const int q = i / ns, S = i - q * ns;
+  const int k = S / (nv * nc), v = (S / nc) % nv, c = S % nc;
+  const int nb = nv + nc;
+  const double de = (eps[(size_t)k * nb + nv + c] - eps[(size_t)k * nb + v]) * (1.0 / 27.211386245988);
+  double re = 0.0, im = 0.0;
+#pragma unroll
+  for (int x = 0; x < 3; ++x) {
+    const double2 g = D[(size_t)S * 3 + x];
+    re += qh.v[q][x] * g.x;
+    im += qh.v[q][x] * g.y;
+  }
+  d[i] = make_double2(re / de, im / de);
+}
+
+hipError_t launch_dipole_project(const double2* D, const double* eps, const Qhats& qh, int nq, int nk, int nv,
+                                 int nc, double2* d, hipStream_t st) {
+  const int n = nk * nv * nc * nq;
+  if (n <= 0) return hipSuccess;
+  if (nq > kMaxQhat) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dipole_project, dim3((n + 255) / 256), dim3(256), 0, st, D, eps, qh, nq, nk, nv, nc, d);
+  return hipGetLastError();
+}
+
+// t2[l] = (1 / nq) sum_q |sum_S A[S][l] d[q][S]|^2: the oscillator strength of
+// exciton l averaged over the polarisations
+__global__ void k_spec_t(int ns, int nlam, int nq, const double2* __restrict__ A, const double2* __restrict__ d,
                          double* __restrict__ t2) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= nlam) return;
-  double re = 0.0, im = 0.0;
-  for (int S = 0; S < ns; ++S) {
-    const double2 a = A[(size_t)S * nlam + l], x = d[S];
-    re += a.x * x.x - a.y * x.y;
-    im += a.x * x.y + a.y * x.x;
+  double acc = 0.0;
+  for (int q = 0; q < nq; ++q) {
+    const double2* dq = d + (size_t)q * ns;
+    double re = 0.0, im = 0.0;
+    for (int S = 0; S < ns; ++S) {
+      const double2 a = A[(size_t)S * nlam + l], x = dq[S];
+      re += a.x * x.x - a.y * x.y;
+      im += a.x * x.y + a.y * x.x;
+    }
+    acc += re * re + im * im;
   }
-  t2[l] = re * re + im * im;
+  t2[l] = acc / nq;
 }
 
-__global__ void k_spec_eps2(int nlam, const double* __restrict__ E, const double* __restrict__ t2, double pref,
+// eps2(w) = 8 pi / (Nk Omega_cell) sum_l t2_l eta / ((w - E_l)^2 + eta^2), w and
+// eta in Hartree (Sec. II.C; spin 2, Tamm-Dancoff overlap = identity)
+__global__ void k_spec_eps2(int nlam, const double* __restrict__ E, const double* __restrict__ t2, double nk_omega,
                             int nw, double w0, double dw, double eta, double* __restrict__ eps2) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nw) return;
@@ -190,18 +232,19 @@ __global__ void k_spec_eps2(int nlam, const double* __restrict__ E, const double
     const double x = w - E[l] * (1.0 / 27.211386245988);
     s += t2[l] / (x * x + eta * eta);
   }
-  eps2[i] = pref * eta * s;
+  eps2[i] = 8.0 * 3.14159265358979323846 / nk_omega * eta * s;
 }
 
-hipError_t launch_spectrum(int ns, int nlam, const double* E, const double2* A, const double2* d, double pref,
-                           int nw, double w0, double w1, double eta, double* t2, double* eps2, hipStream_t st) {
-  hipLaunchKernelGGL(k_spec_t, dim3((nlam + 255) / 256), dim3(256), 0, st, ns, nlam, A, d, t2);
+hipError_t launch_spectrum(int ns, int nlam, int nq, const double* E, const double2* A, const double2* d,
+                           double nk_omega, int nw, double w0, double w1, double eta, double* t2, double* eps2,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_spec_t, dim3((nlam + 255) / 256), dim3(256), 0, st, ns, nlam, nq, A, d, t2);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const double ha = 1.0 / 27.211386245988;
   const double dw = nw > 1 ? (w1 - w0) / (nw - 1) : 0.0;
-  hipLaunchKernelGGL(k_spec_eps2, dim3((nw + 255) / 256), dim3(256), 0, st, nlam, E, t2, pref, nw, w0 * ha, dw * ha,
-                     eta * ha, eps2);
+  hipLaunchKernelGGL(k_spec_eps2, dim3((nw + 255) / 256), dim3(256), 0, st, nlam, E, t2, nk_omega, nw, w0 * ha,
+                     dw * ha, eta * ha, eps2);
   return hipGetLastError();
 }
 

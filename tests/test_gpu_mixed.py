@@ -16,11 +16,13 @@ def _say(msg):
 
 
 @pytest.mark.parametrize("prec", ["split_fp32", "bf16x3"])
-@pytest.mark.parametrize("case", ["cfg0", "cfg1", "ragged"])
+@pytest.mark.parametrize("case", ["cfg0", "cfg1", "ragged", "wide_bands"])
 def test_mixed_H_within_tolerance(prec, case):
     import paper_1206_3518_amd as P
     import torch
-    if case == "cfg0":
+    if case == "wide_bands":  # nv * nc = 81: k blocks span up to three exchange tiles
+        s = B.make_system(B.cell_sc(8.0), (16, 16, 16), (4, 1, 1), 9, 9, 1.5, seed=32)
+    elif case == "cfg0":
         s = B.make_config(0)
     elif case == "cfg1":
         s = B.make_config(1)

@@ -49,10 +49,26 @@ def _pd_case(s, rng, npairs=24):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("case", ["cfg0", "cfg1", "ragged", "hbn"])
+def _planes48():
+    """(8, 48, 48) grid: planes too wide for one lane per line in either frame,
+    so the pair densities run on the general kernel (several lanes per line,
+    cross-lane exchanges)."""
+    return B.make_system(np.diag([4.0, 20.0, 20.0]), (8, 48, 48), (1, 2, 2), 2, 2, 1.5, seed=31)
+
+
+def _wide_bands():
+    """nv * nc = 81 > 64: a diagonal k block spans up to three 64-row tiles of
+    the exchange, so tiles two below the tile diagonal hold upper-block
+    entries."""
+    return B.make_system(B.cell_sc(8.0), (16, 16, 16), (4, 1, 1), 9, 9, 1.5, seed=32)
+
+
+@pytest.mark.parametrize("case", ["cfg0", "cfg1", "ragged", "hbn", "planes48"])
 def test_pair_densities_match_oracle(case):
     rng = np.random.default_rng(1)
-    if case == "cfg0":
+    if case == "planes48":
+        s = _planes48()
+    elif case == "cfg0":
         s = B.make_config(0)
     elif case == "cfg1":
         s = B.make_config(1)
@@ -65,21 +81,31 @@ def test_pair_densities_match_oracle(case):
 
 
 def _check_H(s, H, Href, tag):
+    """FP64 bar: 1e-10 of the kernel K = H - diag(H) (the summation orders
+    differ: FFT against direct sums, GEMM blocking against loops) plus 4 ulp
+    of the largest element for the eV-sized transition energies on the
+    diagonal."""
     K = Href - np.diag(np.diag(Href))
     err = np.abs(H - Href).max()
-    _say(f"{tag}: max|dH| = {err:.3e} eV, max|K| = {np.abs(K).max():.3e} eV")
-    assert err <= 1e-12 * max(np.abs(Href).max(), 1.0)
+    kmax = np.abs(K).max()
+    _say(f"{tag}: max|dH| = {err:.3e} eV, max|K| = {kmax:.3e} eV, max|dK|/max|K| = "
+         f"{np.abs((H - Href) - np.diag(np.diag(H - Href))).max() / kmax:.3e}")
+    assert err <= 1e-10 * kmax + 2.0 ** -50 * np.abs(Href).max()
     assert np.abs(H - H.conj().T).max() <= 1e-12 * np.abs(K).max() + 1e-15
     e = np.linalg.eigvalsh(H)[:10]
     er = np.linalg.eigvalsh(Href)[:10]
     assert np.all(np.abs(e - er) <= 1e-6 * np.abs(er))
 
 
-@pytest.mark.parametrize("case", ["cfg0", "cfg1", "ragged", "one_k", "one_band"])
+@pytest.mark.parametrize("case", ["cfg0", "cfg1", "ragged", "one_k", "one_band", "wide_bands", "planes48"])
 def test_build_H_fp64_matches_oracle(case):
     import paper_1206_3518_amd as P
     import torch
-    if case == "cfg0":
+    if case == "wide_bands":
+        s = _wide_bands()
+    elif case == "planes48":
+        s = _planes48()
+    elif case == "cfg0":
         s = B.make_config(0)
     elif case == "cfg1":
         s = B.make_config(1)
@@ -121,9 +147,10 @@ def test_full_size_si_blocks_match_oracle():
     blocks = [(0, 0), (nk - 1, nk - 1), (0, nk - 1), (nk - 1, 0), (7, 300)]
     blocks += [tuple(int(x) for x in rng.integers(0, nk, 2)) for _ in range(7)]
     ref = O.build_blocks(s, blocks)
+    kmax = max(np.abs(r - np.diag(np.diag(r))).max() for r in ref)
     for (ka, kb), r in zip(blocks, ref):
         g = H[ka * nt:(ka + 1) * nt, kb * nt:(kb + 1) * nt].cpu().numpy()
-        assert np.abs(g - r).max() <= 1e-12 * max(np.abs(r).max(), 1.0), (ka, kb)
+        assert np.abs(g - r).max() <= 1e-10 * kmax + 2.0 ** -50 * np.abs(r).max(), (ka, kb)
     # Hermiticity on a sampled strip
     strip = H[:512].cpu().numpy()
     col = H[:, :512].cpu().numpy()
