@@ -123,7 +123,7 @@ def gradcheck(args):
     t0 = time.perf_counter()
     s = B.make_config(4)
     d = P.DeviceSystem(s, device="cuda:0")
-    ws = P.workspace(P.bse_workspace_size([d]), d.device)
+    ws = P.workspace(P.bse_workspace_size([d], P.BSE_FP64, P.BSE_PROJECT_DW), d.device)
 
     def e0():
         P.bse_build_H([d], P.BSE_FP64, 0, ws)
@@ -330,17 +330,19 @@ def main():
         E64 = [torch.linalg.eigvalsh(h)[:10].cpu().numpy() for h in H64]
         out["lowest_exciton_eV"] = E64[0].tolist()
         mixed = {}
-        ws32 = None
+        wsm = None
         for name, mflags in (("split_fp32", 0), ("bf16x3", 0), ("split_fp32+fp32_pairdens", P.BSE_FP32_PAIRDENS),
                              ("bf16x3+fp32_pairdens", P.BSE_FP32_PAIRDENS)):
             pm = P.PRECISIONS[name.split("+")[0]]
-            if mflags and ws32 is None:
-                need = P.bse_workspace_size(devs, pm, mflags)
-                ws32 = ws if need <= ws.numel() else P.workspace(need, devs[0].device)
+            need = P.bse_workspace_size(devs, pm, mflags)
+            if need > ws.numel() and (wsm is None or need > wsm.numel()):
+                wsm = None
+                wsm = P.workspace(need, devs[0].device)
+            wl = ws if need <= ws.numel() else wsm
             mtune = None
             if mflags and not args.no_autotune and not args.persistent:
-                mtune = P.bse_autotune(devs, pm, None, ws32, flags=mflags)  # the FP32 kernel's own choice
-            msm, _, stm = run_steps(P, devs, pm, flags | mflags, ws32 if mflags else ws, max(2, args.steps // 2), 1)
+                mtune = P.bse_autotune(devs, pm, None, wl, flags=mflags)  # the FP32 kernel's own choice
+            msm, _, stm = run_steps(P, devs, pm, flags | mflags, wl, max(2, args.steps // 2), 1)
             dH = max((d.H - h).abs().max().item() for d, h in zip(devs, H64))
             dE = max(float(np.abs(torch.linalg.eigvalsh(d.H)[:10].cpu().numpy() - e).max())
                      for d, e in zip(devs, E64))
@@ -357,7 +359,7 @@ def main():
                 mixed[name]["dispatch"] = (f"autotuned: persistent, {mtune['wg_per_cu']} workgroups/CU"
                                            if mtune["persistent"] else f"autotuned: static, k tile {mtune['ktile']}")
         out["mixed"] = mixed
-        del ws32
+        del wsm
         del H64
     if not args.no_time_reversal or (not args.no_mixed and len(systems) == 1 and args.precision == "fp64"):
         del devs, ws
@@ -382,7 +384,9 @@ def bandlimited_leg(P, args, flags):
     s = B.make_config(args.config, wf="bandlimited", wf_ecut=s0.ecut / 4.0)
     del s0
     d = P.DeviceSystem(s, device="cuda:0")
-    ws = P.workspace(P.bse_workspace_size([d], P.BSE_BF16X3, P.BSE_FP32_PAIRDENS), d.device)
+    ws = P.workspace(max(P.bse_workspace_size([d], p, f) for p, f in
+                         ((P.BSE_FP64, flags), (P.BSE_SPLIT_FP32, P.BSE_FP32_PAIRDENS),
+                          (P.BSE_BF16X3, P.BSE_FP32_PAIRDENS), (P.BSE_SPLIT_FP32, 0), (P.BSE_BF16X3, 0))), d.device)
     P.bse_build_H([d], P.BSE_FP64, flags, ws)
     torch.cuda.synchronize()
     h = d.H.clone()

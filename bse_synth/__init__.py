@@ -396,14 +396,18 @@ def hbn_draws(seed: int, nsys: int = 16) -> List[int]:
 
 
 def make_hbn_batch(seed: int, nsys: int = 16, grid=(24, 24, 96), ecut=9.0, nv=4, nc=4,
-                   meshes: Optional[Sequence[int]] = None, time_reversal=False) -> List[System]:
+                   meshes: Optional[Sequence[int]] = None, time_reversal=False,
+                   only: Optional[Sequence[int]] = None) -> List[System]:
+    """``nsys`` hexagonal cells with k meshes n x n x 1 (n drawn per system).
+    ``only``: generate just these members of the batch (identical to the
+    same members of the whole batch)."""
     ss = np.random.SeedSequence(seed)
     _, _, _, ss_sys = ss.spawn(4)
     kids = ss_sys.spawn(nsys)
     if meshes is None:
         meshes = hbn_draws(seed, nsys)
     out = []
-    for s in range(nsys):
+    for s in (range(nsys) if only is None else only):
         n = int(meshes[s])
         out.append(make_system(cell_hex(A_HBN, C_HBN), grid, (n, n, 1), nv, nc, ecut,
                                coulomb_kind="slab", slab_L=C_HBN, seed=seed,

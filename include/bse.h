@@ -278,6 +278,28 @@ int bse_spectrum(int ns, int nlam, const double *E, const double *A, const doubl
                  size_t ws_bytes, void *stream);
 
 /*
+ * The spectrum of bse_spectrum without the eigenpairs of H, for Hamiltonians
+ * too large to diagonalise: the resolvent of the appendix (Eq. resolvent,
+ * Tamm-Dancoff) in the state v = conj(d_p) satisfies
+ *   sum_l |t_pl|^2 eta / ((w - E_l)^2 + eta^2) = -Im v^H (w + i eta - H)^-1 v,
+ * evaluated by the Haydock recursion: niter steps of the Lanczos three-term
+ * recurrence from v/|v| (no reorthogonalisation; one pass over H per step for
+ * all polarisations together), then the continued fraction
+ *   g(z) = 1 / (z - a_0 - b_0^2 / (z - a_1 - ... / (z - a_{niter-1}))).
+ * The broadened spectrum converges with niter (bandwidth / niter well below
+ * eta; at most a few hundred steps for eta = 0.1 eV at the sizes here).
+ * H: DEVICE [ns][ns] complex, Hermitian, eV (e.g. from bse_build_H);
+ * d: DEVICE [nq][ns] complex (bse_transition_dipoles), 1 <= nq <= 8;
+ * eps2: DEVICE [nw] as in bse_spectrum (8 pi / (nk omega_cell), average over
+ * the polarisations); coef: DEVICE [nq][niter][2] (a_j, b_j in eV), nullable.
+ * ws: bse_haydock_workspace(ns, nq, niter) bytes.
+ */
+int bse_haydock_spectrum(int ns, const double *H, const double *d, int nq, int niter, int nk, double omega_cell,
+                         int nw, double w0_eV, double w1_eV, double eta_eV, double *eps2, double *coef, void *ws,
+                         size_t ws_bytes, void *stream);
+size_t bse_haydock_workspace(int ns, int nq, int niter);
+
+/*
  * Per-stage GPU timing of bse_build_H.  While enabled, every kernel launch of
  * bse_build_H is bracketed by two hipEvents recorded on the call's stream.
  * bse_profile_read waits for the recorded events, adds their elapsed times
@@ -305,6 +327,15 @@ enum bse_stage {
 };
 int bse_profile(int enable);
 int bse_profile_read(double *total_ms, long long *launches, int nstages, int reset);
+
+/* Budget of the per-pair arrays of a build: the k pairs k <= k' of a batch
+ * are processed in chunks (ranges of block rows of H) whose valence and
+ * conduction pair densities, first-stage products and, in the mixed
+ * precisions, split operands take about `bytes` together (0 = the default,
+ * 6 GiB).  Smaller budgets need less workspace and launch more, smaller
+ * kernels; H does not depend on it.  Applies to the plans made after the call
+ * (bse_workspace_size included), for every thread. */
+int bse_set_chunk_budget(size_t bytes);
 
 /* Frees the calling thread's pinned staging buffer and plan cache (after
  * waiting for the copies that read the buffer) and forgets every tuned launch

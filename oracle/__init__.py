@@ -328,3 +328,48 @@ def spectrum(E, A, d, pref, w):
     t = A.T @ d
     wt = np.abs(t) ** 2
     return pref * np.sum(wt[None, :] * eta / ((grid[:, None] - E[None, :]) ** 2 + eta ** 2), axis=1)
+
+
+def lanczos(H, v, m):
+    """The Lanczos three-term recurrence (Lanczos 1950) on the Hermitian H from
+    the start vector v, as the Haydock recursion method uses it for the
+    resolvent of Eq. resolvent (appendix; Tamm-Dancoff, overlap = identity):
+      q_0 = v / |v|,  w = H q_j - b_{j-1} q_{j-1},  a_j = Re q_j^H w,
+      w -= a_j q_j,  b_j = |w|,  q_{j+1} = w / b_j,
+    for j = 0 .. m-1, without reorthogonalisation.  Returns (a, b), length m."""
+    H = np.asarray(H)
+    q = np.asarray(v, dtype=np.complex128) / np.linalg.norm(v)
+    qp = np.zeros_like(q)
+    bp = 0.0
+    a = np.zeros(m)
+    b = np.zeros(m)
+    for j in range(m):
+        w = H @ q - bp * qp
+        a[j] = np.real(np.vdot(q, w))
+        w = w - a[j] * q
+        b[j] = np.linalg.norm(w)
+        qp, q, bp = q, (w / b[j] if b[j] > 0.0 else np.zeros_like(w)), b[j]
+    return a, b
+
+
+def continued_fraction(a, b, z):
+    """g(z) = 1 / (z - a_0 - b_0^2 / (z - a_1 - b_1^2 / (... / (z - a_{m-1})))):
+    the (0, 0) element of (z - T)^-1 for the tridiagonal T of the recurrence,
+    i.e. q_0^H (z - H)^-1 q_0 to the order the recurrence reaches."""
+    z = np.asarray(z, dtype=np.complex128)
+    t = 1.0 / (z - a[-1])
+    for j in range(len(a) - 2, -1, -1):
+        t = 1.0 / (z - a[j] - b[j] ** 2 * t)
+    return t
+
+
+def haydock_spectrum(H, d, pref, w, m):
+    """eps2(w) of ``spectrum`` from the resolvent instead of the eigenpairs:
+    sum_l |t_l|^2 eta / ((w - E_l)^2 + eta^2) = -Im v^H (w + i eta - H)^-1 v
+    with v = conj(d) (t_l = sum_S A[S][l] d_S), evaluated by ``lanczos`` from
+    v and ``continued_fraction``.  H, w and eta in Hartree; w = (grid, eta)."""
+    grid, eta = w
+    v = np.conj(np.asarray(d, dtype=np.complex128))
+    a, b = lanczos(H, v, m)
+    g = continued_fraction(a, b, grid + 1j * eta)
+    return pref * np.vdot(v, v).real * (-np.imag(g))

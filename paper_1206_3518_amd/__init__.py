@@ -47,7 +47,8 @@ class bse_system(ctypes.Structure):
 
 SYMBOLS = ["bse_workspace_size", "bse_pair_density", "bse_build_H", "bse_build_H_backward",
            "bse_autotune", "bse_autotune_last", "bse_transition_dipoles", "bse_transition_dipoles_workspace",
-           "bse_spectrum", "bse_profile", "bse_profile_read", "bse_release_host_state", "bse_last_error"]
+           "bse_spectrum", "bse_haydock_spectrum", "bse_haydock_workspace", "bse_profile", "bse_profile_read", "bse_set_chunk_budget", "bse_release_host_state",
+           "bse_last_error"]
 STAGES = ["vscale", "pd_exch", "pd_vv", "pd_cc", "exchange", "direct1", "direct2", "mirror", "rotate", "tr_fill", "to_f32", "split_w"]
 
 
@@ -77,6 +78,12 @@ def lib():
         L.bse_transition_dipoles_workspace.restype = S
         L.bse_spectrum.argtypes = [I, I, P, P, P, I, I, D, I, D, D, D, P, P, S, P]
         L.bse_spectrum.restype = I
+        L.bse_haydock_spectrum.argtypes = [I, P, P, I, I, I, D, I, D, D, D, P, P, P, S, P]
+        L.bse_haydock_spectrum.restype = I
+        L.bse_haydock_workspace.argtypes = [I, I, I]
+        L.bse_haydock_workspace.restype = S
+        L.bse_set_chunk_budget.argtypes = [S]
+        L.bse_set_chunk_budget.restype = I
         L.bse_release_host_state.argtypes = []
         L.bse_release_host_state.restype = I
         L.bse_profile.argtypes = [I]
@@ -363,6 +370,42 @@ def bse_spectrum(E, A, d, nk, omega_cell, nw, w0_eV, w1_eV, eta_eV, ws=None, str
                               float(w0_eV), float(w1_eV), float(eta_eV), _ptr(eps2), _ptr(ws), ws.numel(),
                               _stream(stream)))
     return eps2
+
+
+def bse_set_chunk_budget(nbytes=0):
+    """Bytes of per-pair arrays per chunk of k pairs (0: the library default)."""
+    _check(lib().bse_set_chunk_budget(int(nbytes)))
+
+
+def bse_haydock_spectrum(H, d, nk, omega_cell, niter, nw, w0_eV, w1_eV, eta_eV, want_coef=False, ws=None,
+                         stream=None):
+    """eps2 on nw points of [w0, w1] (eV) from H (complex128 [ns][ns], eV) and
+    the dipoles d ([nq][ns] or [ns]) by the Haydock recursion of niter steps;
+    with want_coef also the recurrence coefficients [nq][niter][2] (eV)."""
+    import torch
+    H = H.contiguous()
+    ns = H.shape[0]
+    d = d.reshape(-1, ns).contiguous()
+    nq = d.shape[0]
+    eps2 = torch.empty(nw, dtype=torch.float64, device=H.device)
+    coef = torch.empty((nq, niter, 2), dtype=torch.float64, device=H.device) if want_coef else None
+    if ws is None:
+        n = lib().bse_haydock_workspace(ns, nq, int(niter))
+        if n == 0:
+            raise BseError(-1, "bad Haydock sizes")
+        ws = workspace(n, H.device)
+    _check(lib().bse_haydock_spectrum(ns, _ptr(H), _ptr(d), nq, int(niter), int(nk), float(omega_cell), int(nw),
+                                      float(w0_eV), float(w1_eV), float(eta_eV), _ptr(eps2), _ptr(coef), _ptr(ws),
+                                      ws.numel(), _stream(stream)))
+    return (eps2, coef) if want_coef else eps2
+
+
+def absorption_haydock(system: DeviceSystem, H, qhats=((1, 0, 0), (0, 1, 0), (0, 0, 1)), niter=500, nw=1001,
+                       w0=0.0, w1=10.0, eta=0.1):
+    """eps2(w) averaged over the polarisations qhats without diagonalising H:
+    dipoles and the Haydock recursion in the library."""
+    d = bse_transition_dipoles(system, qhats)
+    return bse_haydock_spectrum(H, d, system.nk, system.omega_cell, niter, nw, w0, w1, eta)
 
 
 def bse_release_host_state():

@@ -16,14 +16,18 @@
 
 namespace bse {
 
+// The recomputed pair densities hold one chunk of k pairs at a time (rows of
+// pair p of the chunk start at (p - p0) * nv^2); dW is accumulated over the
+// chunks.
+//
 // T for one k pair and one 16-row block of vv', all g'.  f64 MFMA: A = Gbar_eff
 // block (16 x 16 over vv' x cc'), B[cc'][g'] = conj(rho_cc'(g')).
 __global__ __launch_bounds__(256) void k_adj_T(AdjArgs a, int tiles_i, int nitems) {
   const int lane = threadIdx.x & 63;
   const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (item >= nitems) return;
-  const int p = item / tiles_i, ti = item % tiles_i;
-  const int4 pr = a.pairs[p];
+  const int p = item / tiles_i, ti = item % tiles_i;  // p: pair of the chunk
+  const int4 pr = a.pairs[a.p0 + p];
   const int ka = pr.x, kb = pr.y;
   const int K = a.ng[pr.z];
   const int nv = a.nv, nc = a.nc, nv2 = nv * nv, nc2 = nc * nc, ns = a.ns;
@@ -67,13 +71,15 @@ __global__ __launch_bounds__(256) void k_adj_T(AdjArgs a, int tiles_i, int nitem
   }
 }
 
-// dW_q tile = -c RV_q^T T_q (A transposed: A[g][r] = RV[r][g]).
+// dW_q tile += -c RV_q^T T_q over the chunk's pairs of q (A transposed:
+// A[g][r] = RV[r][g]).  In the mixed precisions the q = 0 head entry is left
+// to k_adj_head (FP64).
 template <int P>
 __global__ __launch_bounds__(256) void k_adj_dW(AdjArgs a) {
   const int4 tl = a.dwtiles[blockIdx.x];
   const int q = tl.x;
   const int nv2 = a.nv * a.nv;
-  const int row_base = a.qstart[q] * nv2;
+  const int row_base = (a.qstart[q] - a.p0) * nv2;
   const int K = (a.qstart[q + 1] - a.qstart[q]) * nv2;
   const int ngq = a.ng[q];
   const double2* A = a.RV + (size_t)row_base * a.ng_max;
@@ -92,8 +98,12 @@ __global__ __launch_bounds__(256) void k_adj_dW(AdjArgs a) {
         for (int r = 0; r < 4; ++r) {
           const int row = r0 + wr * 32 + i * 16 + 4 * r + (lane >> 4);
           const int col = c0 + wc * 32 + j * 16 + (lane & 15);
-          if (row < a.ng_max && col < a.ng_max)
-            out[(size_t)row * a.ng_max + col] = make_double2(-a.cpref * cre[i][j][r], -a.cpref * cim[i][j][r]);
+          if (row < a.ng_max && col < a.ng_max) {
+            double2 o = out[(size_t)row * a.ng_max + col];
+            o.x -= a.cpref * cre[i][j][r];
+            o.y -= a.cpref * cim[i][j][r];
+            out[(size_t)row * a.ng_max + col] = o;
+          }
         }
   } else {
     f4 cre[2][2], cim[2][2];
@@ -106,20 +116,24 @@ __global__ __launch_bounds__(256) void k_adj_dW(AdjArgs a) {
         for (int r = 0; r < 4; ++r) {
           const int row = r0 + wr * 32 + i * 16 + acc_row(lane, r);
           const int col = c0 + wc * 32 + j * 16 + (lane & 15);
-          if (row < a.ng_max && col < a.ng_max)
-            out[(size_t)row * a.ng_max + col] =
-                make_double2(-a.cpref * (double)cre[i][j][r], -a.cpref * (double)cim[i][j][r]);
+          if (row < a.ng_max && col < a.ng_max && !(q == 0 && row == 0 && col == 0)) {
+            double2 o = out[(size_t)row * a.ng_max + col];
+            o.x -= a.cpref * (double)cre[i][j][r];
+            o.y -= a.cpref * (double)cim[i][j][r];
+            out[(size_t)row * a.ng_max + col] = o;
+          }
         }
   }
 }
 
-// FP64 head entry dW_0[0][0] (mixed precision): one workgroup reduction.
+// FP64 head entry dW_0[0][0] (mixed precision): one workgroup reduction over
+// the chunk's pairs of q = 0, added to the entry.
 __global__ __launch_bounds__(256) void k_adj_head(AdjArgs a) {
   __shared__ double sre[256], sim[256];
   const int nv2 = a.nv * a.nv;
   const int rows = (a.qstart[1] - a.qstart[0]) * nv2;
-  const double2* A = a.RV + (size_t)a.qstart[0] * nv2 * a.ng_max;
-  const double2* Bm = a.T + (size_t)a.qstart[0] * nv2 * a.ng_max;
+  const double2* A = a.RV + (size_t)(a.qstart[0] - a.p0) * nv2 * a.ng_max;
+  const double2* Bm = a.T + (size_t)(a.qstart[0] - a.p0) * nv2 * a.ng_max;
   double re = 0.0, im = 0.0;
   for (int r = threadIdx.x; r < rows; r += 256) {
     const double2 x = A[(size_t)r * a.ng_max], y = Bm[(size_t)r * a.ng_max];
@@ -136,7 +150,12 @@ __global__ __launch_bounds__(256) void k_adj_head(AdjArgs a) {
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) a.dWout[0] = make_double2(-a.cpref * sre[0], -a.cpref * sim[0]);
+  if (threadIdx.x == 0) {
+    double2 o = a.dWout[0];
+    o.x -= a.cpref * sre[0];
+    o.y -= a.cpref * sim[0];
+    a.dWout[0] = o;
+  }
 }
 
 __global__ void k_adj_deps(AdjArgs a) {
@@ -195,14 +214,14 @@ __global__ __launch_bounds__(256) void k_adj_drc(AdjArgs a, int tiles_i, int nit
   const int lane = threadIdx.x & 63;
   const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (item >= nitems) return;
-  const int p = item / tiles_i, ti = item % tiles_i;
-  const int4 pr = a.pairs[p];
+  const int p = item / tiles_i, ti = item % tiles_i;  // p: pair of the chunk
+  const int4 pr = a.pairs[a.p0 + p];
   const int ka = pr.x, kb = pr.y;
   const int K = a.ng[pr.z];
   const int nv = a.nv, nc = a.nc, nv2 = nv * nv, nc2 = nc * nc, ns = a.ns;
   const int i = ti * 16 + (lane & 15);  // cc' row of the A operand
   const double2* Z = a.Z + (size_t)p * nv2 * a.ng_max;
-  double2* out = a.drc + (size_t)a.plex[p] * nc2 * a.ng_max;
+  double2* out = a.drc + (size_t)a.plex[a.p0 + p] * nc2 * a.ng_max;
   for (int n0 = 0; n0 < a.ng_max; n0 += 16) {
     d4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
     for (int kc = 0; kc < nv2; kc += 4) {
@@ -247,7 +266,7 @@ __global__ __launch_bounds__(256) void k_adj_drv(AdjArgs a) {
   const int4 tl = a.rvtiles[blockIdx.x];
   const int q = tl.x;
   const int nv2 = a.nv * a.nv;
-  const int row_base = a.qstart[q] * nv2;
+  const int row_base = (a.qstart[q] - a.p0) * nv2;  // rows of the chunk
   const int rows = (a.qstart[q + 1] - a.qstart[q]) * nv2;
   const int K = a.ng[q];
   const double2* A = a.T + (size_t)row_base * a.ng_max;
@@ -314,7 +333,7 @@ hipError_t launch_adj_dx(const AdjArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint(const AdjArgs& a, int precision, int ndw_tiles, bool project, hipStream_t st) {
+hipError_t launch_adjoint(const AdjArgs& a, int precision, int ndw_tiles, bool has_q0, hipStream_t st) {
   const int ti = (a.nv * a.nv + 15) / 16;
   const int nitems = a.npairs * ti;
   if (nitems > 0) {
@@ -333,16 +352,18 @@ hipError_t launch_adjoint(const AdjArgs& a, int precision, int ndw_tiles, bool p
       hipLaunchKernelGGL(k, dim3(ndw_tiles), dim3(256), lds, st, a);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(k_adj_head, dim3(1), dim3(256), 0, st, a);
+      if (has_q0) hipLaunchKernelGGL(k_adj_head, dim3(1), dim3(256), 0, st, a);
     }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_finish(const AdjArgs& a, bool project, hipStream_t st) {
+  if (a.dWout && project) {
+    const size_t n = (size_t)a.nk * a.ng_max * a.ng_max;
+    hipLaunchKernelGGL(k_adj_project, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, a.dWout, a.dWfinal);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (project) {
-      const size_t n = (size_t)a.nk * a.ng_max * a.ng_max;
-      hipLaunchKernelGGL(k_adj_project, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, a.dWout, a.dWfinal);
-      e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    }
   }
   if (a.deps) {
     const int n = a.nk * (a.nv + a.nc);

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -159,6 +160,27 @@ std::vector<PdJob> dispatch_order(std::vector<PdJob> jobs, int ktile) {
   return out;
 }
 
+// The per-pair arrays of the build (RV, RC, Z and, in the mixed precisions,
+// the split copy of conj(RV)) hold one chunk of k pairs at a time.  A batch's
+// pairs are cut into chunks of about g_chunk_budget bytes of those arrays (all
+// systems together), so the workspace stays bounded as the k mesh grows.  A
+// chunk is a range of block rows: the pairs whose first k point falls in a
+// range (with time reversal, together with their images), so the dispatch
+// order keeps the k tiles whole.
+constexpr size_t kChunkBudget = size_t(6) << 30;
+std::atomic<size_t> g_chunk_budget{kChunkBudget};
+
+// One system's share of a chunk.
+struct Chunk {
+  int p0 = 0, np = 0;           // pairs [p0, p0 + np) in the system's pair order
+  std::vector<PdJob> jv, jc;    // pairs transformed, rows local to the chunk
+  std::vector<int4> fill;       // time-reversal images: (dst, src, q_dst << 1 | mode, sys), local pairs
+  std::vector<S1Tile> s1;       // stage-1 tiles (q groups of the chunk)
+  int d2items = 0;              // stage-2 items (pairs x 16 x 16 tiles)
+  std::vector<int4> dwt, rvt;   // adjoint tiles (q, row tile, column tile, -) of the q groups present
+  bool has_q0 = false;          // holds pairs of q = 0
+};
+
 struct Plan {
   // N1, N2, N3 and every Miller index, shift and window below are in the
   // pair-density frame: frame axis d is grid axis ax[d].  The frame is the
@@ -171,33 +193,27 @@ struct Plan {
   int N1 = 0, N2 = 0, N3 = 0, nk = 0, nv = 0, nc = 0, nb = 0, ng_max = 0, ns = 0, nt = 0;
   int lo[3] = {0, 0, 0}, F[3] = {0, 0, 0};
   std::vector<int> gpack, ng;
-  std::vector<int4> pairs;  // (ka, kb, iq, m0p), k <= k', sorted by q
-  std::vector<int> qstart;  // [nk + 1]
-  std::vector<PdJob> jx, jv, jc;  // system 0, natural order
-  std::vector<S1Tile> s1;
-  std::vector<HTile> xt, mt;       // exchange tiles; mirror tiles
-  int d2items = 0;                 // stage-2 items (pairs x 16 x 16 tiles)
-  std::vector<int4> dwt;   // adjoint dW tiles (q, mt, nt, -)
-  std::vector<int4> rvt;   // adjoint drho_vv' tiles (q, mt, nt, -) over every column of ng_max
-  std::vector<int> plex;   // lexicographic position of each pair among k <= k'
-  std::vector<int> qbar, trmap;
+  std::vector<PdJob> jx;           // exchange pair densities, natural order
+  std::vector<int> qbar, trmap;    // time-reversal partner of q; sphere map t - m
   bool tr_closed = true;
-  // time reversal: per k, kbar | K << 24 (grid axes); the vv / cc jobs of the
-  // pairs that are computed, and (dst, src, mode, -) for their images
-  std::vector<int> ktr;
-  std::vector<PdJob> jv_tr, jc_tr;
-  std::vector<int4> trfill;
+  std::vector<int> ktr;            // per k: kbar | K << 24 (grid axes)
+  // pairs k <= k', chunk after chunk, sorted by (q, k, k') inside a chunk
+  std::vector<int4> pairs;         // (ka, kb, iq, m0p)
+  std::vector<int> plex;           // lexicographic position of each pair among k <= k'
+  std::vector<int> qs;             // [nchunk][nk + 1] first pair of each q group of the chunk
+  std::vector<Chunk> ch;
+  int maxcp = 0;                   // pairs of the largest chunk
+  std::vector<HTile> xt, mt;       // exchange tiles; mirror tiles
+  bool pd32 = false;               // FP32 valence / conduction pair densities
+  bool mixed = false;              // split buffers of the mixed precisions reserved
+  int kpad = 0;                    // ng_max rounded up to a multiple of 32
   // byte offsets inside the system's region of the workspace
-  size_t o_gpack = 0, o_ng = 0, o_pairs = 0, o_qstart = 0;
-  size_t o_dwt = 0, o_rvt = 0, o_plex = 0, o_qbar = 0, o_trmap = 0, o_ktr = 0;
+  size_t o_gpack = 0, o_ng = 0, o_pairs = 0, o_qs = 0, o_plex = 0, o_qbar = 0, o_trmap = 0, o_ktr = 0;
   size_t tables = 0, o_vs = 0, o_X = 0, o_RV = 0, o_RC = 0, o_Z = 0, o_dWraw = 0, total = 0;
-  size_t fwd_total = 0;  // region needed by the forward build (no dW scratch)
-  size_t o_ut = 0;       // rotated wave functions (rot only; in the forward part)
-  bool pd32 = false;     // FP32 valence / conduction pair densities
-  size_t o_u32 = 0;      // FP32 copy of the wave functions in the frame (pd32 only)
-  int kpad = 0;          // ng_max rounded up to a multiple of 32
-  size_t o_Ws = 0;       // W split for the mixed stage 1: [Nk][ng_max][4][kpad] of up to 4 bytes
-  size_t o_RVs = 0;      // conj(RV) split for the mixed stage 1: [rows][4][kpad] of up to 4 bytes
+  size_t o_ut = 0;   // rotated wave functions (rot only)
+  size_t o_u32 = 0;  // FP32 copy of the wave functions in the frame (pd32 only)
+  size_t o_Ws = 0;   // W split for the mixed stage 1: [Nk][ng_max][4][kpad] of up to 4 bytes (mixed only)
+  size_t o_RVs = 0;  // conj(RV) split for the mixed stage 1: [rows][4][kpad] (mixed only)
 };
 
 int check_system(const bse_system* s) {
@@ -218,12 +234,15 @@ int check_system(const bse_system* s) {
 
 // What a batch is planned for besides its systems.
 struct BatchOpts {
-  bool backward = false;  // room for the adjoint's buffers
+  bool backward = false;  // room and tiles for the adjoint
+  bool project = false;   // backward with the projection of dW (its raw buffer)
   bool tr = false;        // time-reversal images gathered (BSE_TIME_REVERSAL)
   bool pd32 = false;      // FP32 pair densities where the one-lane-per-line kernel applies
+  bool mixed = false;     // split buffers of the mixed-precision stage 1
 };
 
-int make_plan(const bse_system* s, Plan& P, bool pd32) {
+// Frame, spheres, windows, exchange jobs and time-reversal maps of one system.
+int make_geometry(const bse_system* s, Plan& P) {
   int rc = check_system(s);
   if (rc) return rc;
   P.rot = !pd_line_grid(s->grid[1], s->grid[2]) && pd_line_grid(s->grid[0], s->grid[1]) && s->grid[2] <= 256;
@@ -271,86 +290,16 @@ int make_plan(const bse_system* s, Plan& P, bool pd32) {
     if (P.F[d] > N[d])
       return fail(BSE_ERR_SHAPE, "G-sphere window %d exceeds grid %d along axis %d", P.F[d], N[d], d);
   }
-
-  // k pairs k <= k' grouped by q
-  std::vector<std::vector<int4>> byq(P.nk);
-  for (int ka = 0; ka < P.nk; ++ka)
-    for (int kb = ka; kb < P.nk; ++kb) {
-      int iq, m0[3];
-      fold(s->kmesh, ka, kb, iq, m0);
-      byq[iq].push_back(make_int4(ka, kb, iq, pack_m(m0[P.ax[0]], m0[P.ax[1]], m0[P.ax[2]])));
-    }
-  P.qstart.assign(P.nk + 1, 0);
-  P.pairs.clear();
-  for (int q = 0; q < P.nk; ++q) {
-    P.qstart[q] = (int)P.pairs.size();
-    P.pairs.insert(P.pairs.end(), byq[q].begin(), byq[q].end());
-  }
-  P.qstart[P.nk] = (int)P.pairs.size();
-  const int np = (int)P.pairs.size();
-
   P.jx.resize(P.nk);
   for (int k = 0; k < P.nk; ++k)
     P.jx[k] = PdJob{k, k, pack_m(0, 0, 0), 0, 0, P.nv, P.nv | (P.nc << 8), k * P.nt};
-  P.jv.resize(np);
-  P.jc.resize(np);
-  for (int p = 0; p < np; ++p) {
-    const int4 pr = P.pairs[p];
-    P.jv[p] = PdJob{pr.x, pr.y, pr.w, pr.z, 0, 0, P.nv | (P.nv << 8), p * P.nv * P.nv};
-    P.jc[p] = PdJob{pr.x, pr.y, pr.w, pr.z, P.nv, P.nv, P.nc | (P.nc << 8), p * P.nc * P.nc};
-  }
-  // stage-1 tiles: per q, rows = pairs(q) * nv^2, cols = ng(q)
-  P.s1.clear();
-  for (int q = 0; q < P.nk; ++q) {
-    const int rows = (P.qstart[q + 1] - P.qstart[q]) * P.nv * P.nv;
-    const int mt = (rows + 63) / 64, nt = (P.ng[q] + 63) / 64;
-    for (int i = 0; i < mt; ++i)
-      for (int j = 0; j < nt; ++j) P.s1.push_back(S1Tile{q, i, j, 0});
-  }
-  // exchange tiles: every 64 x 64 tile that holds an entry of a block k <= k'
-  // (its first row's k block is at most its last column's).  A k block of
-  // nv*nc rows may span several tiles, so a diagonal block can reach tiles
-  // well below the tile diagonal.
-  P.xt.clear();
-  const int T = (P.ns + 63) / 64;
-  for (int i = 0; i < T; ++i)
-    for (int j = 0; j < T; ++j) {
-      const int last_col = std::min(P.ns, 64 * (j + 1)) - 1;
-      if ((64 * i) / P.nt <= last_col / P.nt) P.xt.push_back(HTile{i, j, 0, 0});
-    }
-  // mirror tiles: 32 x 32 destination tiles on or below the diagonal
-  P.mt.clear();
-  const int T32 = (P.ns + 31) / 32;
-  for (int i = 0; i < T32; ++i)
-    for (int j = 0; j <= i; ++j) P.mt.push_back(HTile{i, j, 0, 0});
-  P.d2items = np * ((P.nv * P.nv + 15) / 16) * ((P.nc * P.nc + 15) / 16);
 
-  // adjoint: dW tiles over ng_max x ng_max per q; time-reversal partners
-  P.dwt.clear();
-  {
-    const int T2 = (P.ng_max + 63) / 64;
-    for (int q = 0; q < P.nk; ++q)
-      for (int i = 0; i < T2; ++i)
-        for (int j = 0; j < T2; ++j) P.dwt.push_back(make_int4(q, i, j, 0));
-  }
-  P.rvt.clear();
-  {
-    const int T2 = (P.ng_max + 63) / 64;
-    for (int q = 0; q < P.nk; ++q) {
-      const int mt = ((P.qstart[q + 1] - P.qstart[q]) * P.nv * P.nv + 63) / 64;
-      for (int i = 0; i < mt; ++i)
-        for (int j = 0; j < T2; ++j) P.rvt.push_back(make_int4(q, i, j, 0));
-    }
-  }
-  P.plex.resize(np);
-  for (int p = 0; p < np; ++p) {
-    const long long a = P.pairs[p].x, b = P.pairs[p].y;
-    P.plex[p] = (int)(a * P.nk - a * (a - 1) / 2 + (b - a));
-  }
+  // time reversal on the q mesh: qbar = -q mod n, and the index of t - m_g in
+  // the sphere of qbar (-q = qbar + t)
   P.qbar.assign(P.nk, 0);
   P.trmap.assign((size_t)P.nk * P.ng_max, 0);
+  P.tr_closed = true;
   {
-    // per q: (packed m, index) sorted, for the lookups of the partner sphere
     std::vector<std::vector<std::pair<int, int>>> sorted(P.nk);
     for (int q = 0; q < P.nk; ++q) {
       sorted[q].resize(P.ng[q]);
@@ -379,13 +328,7 @@ int make_plan(const bse_system* s, Plan& P, bool pd32) {
       }
     }
   }
-
-  // time reversal on the k mesh: -k = kbar - K, and the image of each pair
-  // (k, k'): (kbar, kbar') if kbar <= kbar' (conjugate, sphere map of
-  // qbar), else (kbar', kbar) (bands exchanged).  Of a pair and its image the
-  // lower index is computed.  Pairs that touch a point that is its own
-  // partner (kbar = k) are computed: there the wave functions carry a free
-  // gauge phase per band, so no relation between u_k and conj(u_k) is assumed.
+  // time reversal on the k mesh: -k = kbar - K
   P.ktr.assign(P.nk, 0);
   {
     const int* n = s->kmesh;
@@ -398,27 +341,154 @@ int make_plan(const bse_system* s, Plan& P, bool pd32) {
       }
       P.ktr[k] = ((kb[0] * n[1] + kb[1]) * n[2] + kb[2]) | bits;
     }
-    std::vector<int> lex2p(np);
-    for (int p = 0; p < np; ++p) lex2p[P.plex[p]] = p;
-    P.jv_tr.clear();
-    P.jc_tr.clear();
-    P.trfill.clear();
-    for (int p = 0; p < np; ++p) {
-      const int x = P.ktr[P.pairs[p].x] & 0xffffff, y = P.ktr[P.pairs[p].y] & 0xffffff;
-      if (x == P.pairs[p].x || y == P.pairs[p].y) {
-        P.jv_tr.push_back(P.jv[p]);
-        P.jc_tr.push_back(P.jc[p]);
-        continue;
-      }
-      const int mode = x <= y ? 0 : 1;
-      const long long a = std::min(x, y), b = std::max(x, y);
-      const int img = lex2p[a * P.nk - a * (a - 1) / 2 + (b - a)];
-      if (img < p) continue;  // derived from its image
-      P.jv_tr.push_back(P.jv[p]);
-      P.jc_tr.push_back(P.jc[p]);
-      if (img != p) P.trfill.push_back(make_int4(img, p, mode, 0));
-    }
   }
+  return BSE_OK;
+}
+
+// Bytes of the per-pair arrays of one pair.
+size_t pair_bytes(const bse_system* s, bool mixed) {
+  const size_t ngm = (size_t)s->ng_max, kpad = (ngm + 31) / 32 * 32;
+  size_t b = sizeof(double2) * ngm * (2 * (size_t)s->nv * s->nv + (size_t)s->nc * s->nc);
+  if (mixed) b += (size_t)s->nv * s->nv * 4 * kpad * sizeof(float);
+  return b;
+}
+
+// The pairs k <= k' cut into at most `nchunk` chunks, their jobs and tiles,
+// and the workspace layout.  `sys` tags the jobs and fill items.
+int plan_pairs(const bse_system* s, Plan& P, const BatchOpts& opt, int nchunk, int sys) {
+  const int nk = P.nk, nv = P.nv, nc = P.nc;
+  const long long npl = (long long)nk * (nk + 1) / 2;
+  if (npl > (1LL << 30)) return fail(BSE_ERR_SHAPE, "too many k pairs (%lld)", npl);
+  const int np = (int)npl;
+  // lexicographic pairs (ka, kb), ka <= kb
+  auto lex = [nk](long long a, long long b) { return (int)(a * nk - a * (a - 1) / 2 + (b - a)); };
+  std::vector<int2> lp(np);
+  for (int a = 0, i = 0; a < nk; ++a)
+    for (int b = a; b < nk; ++b) lp[i++] = make_int2(a, b);
+  // units: a transformed pair and, with time reversal, the image gathered from it
+  struct Unit {
+    int rep, img, mode;
+  };
+  std::vector<Unit> units;
+  units.reserve(np);
+  for (int p = 0; p < np; ++p) {
+    if (!opt.tr) {
+      units.push_back(Unit{p, -1, 0});
+      continue;
+    }
+    const int ka = lp[p].x, kb = lp[p].y;
+    const int x = P.ktr[ka] & 0xffffff, y = P.ktr[kb] & 0xffffff;
+    if (x == ka || y == kb) {  // touches a point that is its own partner: transformed
+      units.push_back(Unit{p, -1, 0});
+      continue;
+    }
+    const int img = lex(std::min(x, y), std::max(x, y));
+    if (img < p) continue;  // gathered from its image
+    units.push_back(Unit{p, img == p ? -1 : img, x <= y ? 0 : 1});
+  }
+  // chunks: consecutive units, cut between block rows once a chunk holds its share
+  nchunk = std::max(1, std::min(nchunk, np));
+  const long long target = (npl + nchunk - 1) / nchunk;
+  std::vector<std::vector<const Unit*>> cu(1);
+  long long acc = 0;
+  for (size_t i = 0; i < units.size(); ++i) {
+    cu.back().push_back(&units[i]);
+    acc += units[i].img >= 0 ? 2 : 1;
+    const bool row_end = i + 1 == units.size() || lp[units[i + 1].rep].x != lp[units[i].rep].x;
+    if (row_end && acc >= target * (long long)cu.size() && (int)cu.size() < nchunk && i + 1 < units.size())
+      cu.emplace_back();
+  }
+  const int C = (int)cu.size();
+  P.pairs.assign(np, make_int4(0, 0, 0, 0));
+  P.plex.assign(np, 0);
+  P.qs.assign((size_t)C * (nk + 1), 0);
+  P.ch.assign(C, Chunk{});
+  std::vector<int> g_of_lex(np, -1);
+  int next = 0;
+  P.maxcp = 0;
+  const int T2 = (P.ng_max + 63) / 64;
+  for (int c = 0; c < C; ++c) {
+    Chunk& K = P.ch[c];
+    std::vector<int> members;
+    for (const Unit* u : cu[c]) {
+      members.push_back(u->rep);
+      if (u->img >= 0) members.push_back(u->img);
+    }
+    std::vector<int4> pr(members.size());
+    for (size_t i = 0; i < members.size(); ++i) {
+      const int ka = lp[members[i]].x, kb = lp[members[i]].y;
+      int iq, m0[3];
+      fold(s->kmesh, ka, kb, iq, m0);
+      pr[i] = make_int4(ka, kb, iq, members[i]);  // .w: lexicographic index for now
+    }
+    std::sort(pr.begin(), pr.end(), [](const int4& x, const int4& y) {
+      if (x.z != y.z) return x.z < y.z;
+      if (x.x != y.x) return x.x < y.x;
+      return x.y < y.y;
+    });
+    K.p0 = next;
+    K.np = (int)pr.size();
+    P.maxcp = std::max(P.maxcp, K.np);
+    if ((long long)K.np * std::max(nv * nv, nc * nc) >= (1LL << 31) / std::max(P.ng_max, 1))
+      return fail(BSE_ERR_SHAPE, "a chunk of %d k pairs is too large", K.np);
+    std::vector<int> cnt(nk, 0);
+    for (size_t i = 0; i < pr.size(); ++i) {
+      const int g = next + (int)i, l = pr[i].w;
+      int iq, m0[3];
+      fold(s->kmesh, pr[i].x, pr[i].y, iq, m0);
+      P.pairs[g] = make_int4(pr[i].x, pr[i].y, iq, pack_m(m0[P.ax[0]], m0[P.ax[1]], m0[P.ax[2]]));
+      P.plex[g] = l;
+      g_of_lex[l] = g;
+      cnt[iq]++;
+    }
+    int* qs = P.qs.data() + (size_t)c * (nk + 1);
+    qs[0] = next;
+    for (int q = 0; q < nk; ++q) qs[q + 1] = qs[q] + cnt[q];
+    K.has_q0 = cnt[0] > 0;
+    // jobs of the transformed pairs and the fill items of their images
+    for (const Unit* u : cu[c]) {
+      const int g = g_of_lex[u->rep], loc = g - next;
+      const int4 q4 = P.pairs[g];
+      K.jv.push_back(PdJob{q4.x, q4.y, q4.w, q4.z, 0, 0, nv | (nv << 8), loc * nv * nv});
+      K.jc.push_back(PdJob{q4.x, q4.y, q4.w, q4.z, nv, nv, nc | (nc << 8), loc * nc * nc});
+      if (u->img >= 0) {
+        const int gi = g_of_lex[u->img];
+        K.fill.push_back(make_int4(gi - next, loc, (P.pairs[gi].z << 1) | u->mode, sys));
+      }
+    }
+    // stage-1 tiles per q group: rows = pairs(q) * nv^2, columns = ng(q)
+    for (int q = 0; q < nk; ++q) {
+      if (!cnt[q]) continue;
+      const int rows = cnt[q] * nv * nv;
+      const int mt = (rows + 63) / 64, ntl = (P.ng[q] + 63) / 64;
+      for (int i = 0; i < mt; ++i)
+        for (int j = 0; j < ntl; ++j) K.s1.push_back(S1Tile{q, i, j, sys});
+      if (opt.backward) {
+        for (int i = 0; i < T2; ++i)
+          for (int j = 0; j < T2; ++j) K.dwt.push_back(make_int4(q, i, j, 0));
+        for (int i = 0; i < mt; ++i)
+          for (int j = 0; j < T2; ++j) K.rvt.push_back(make_int4(q, i, j, 0));
+      }
+    }
+    K.d2items = K.np * ((nv * nv + 15) / 16) * ((nc * nc + 15) / 16);
+    next += K.np;
+  }
+  // exchange tiles: every 64 x 64 tile that holds an entry of a block k <= k'
+  // (its first row's k block is at most its last column's).  A k block of
+  // nv*nc rows may span several tiles, so a diagonal block can reach tiles
+  // well below the tile diagonal.
+  P.xt.clear();
+  const int T = (P.ns + 63) / 64;
+  for (int i = 0; i < T; ++i)
+    for (int j = 0; j < T; ++j) {
+      const int last_col = std::min(P.ns, 64 * (j + 1)) - 1;
+      if ((64 * i) / P.nt <= last_col / P.nt) P.xt.push_back(HTile{i, j, sys, 0});
+    }
+  // mirror tiles: 32 x 32 destination tiles on or below the diagonal
+  P.mt.clear();
+  const int T32 = (P.ns + 31) / 32;
+  for (int i = 0; i < T32; ++i)
+    for (int j = 0; j <= i; ++j) P.mt.push_back(HTile{i, j, sys, 0});
 
   // workspace layout
   size_t o = 0;
@@ -430,27 +500,28 @@ int make_plan(const bse_system* s, Plan& P, bool pd32) {
   P.o_gpack = put(P.gpack.size() * sizeof(int));
   P.o_ng = put(P.ng.size() * sizeof(int));
   P.o_pairs = put(P.pairs.size() * sizeof(int4));
-  P.o_qstart = put(P.qstart.size() * sizeof(int));
-  P.o_dwt = put(P.dwt.size() * sizeof(int4));
-  P.o_rvt = put(P.rvt.size() * sizeof(int4));
+  P.o_qs = put(P.qs.size() * sizeof(int));
   P.o_plex = put(P.plex.size() * sizeof(int));
   P.o_qbar = put(P.qbar.size() * sizeof(int));
   P.o_trmap = put(P.trmap.size() * sizeof(int));
   P.o_ktr = put(P.ktr.size() * sizeof(int));
   P.tables = o;
+  const size_t mc = (size_t)P.maxcp;
   P.o_vs = put((size_t)P.ng_max * sizeof(double));
   P.o_X = put((size_t)P.ns * P.ng_max * sizeof(double2));
-  P.o_RV = put((size_t)np * P.nv * P.nv * P.ng_max * sizeof(double2));
-  P.o_RC = put((size_t)np * P.nc * P.nc * P.ng_max * sizeof(double2));
-  P.o_Z = put((size_t)np * P.nv * P.nv * P.ng_max * sizeof(double2));
+  P.o_RV = put(mc * nv * nv * P.ng_max * sizeof(double2));
+  P.o_RC = put(mc * nc * nc * P.ng_max * sizeof(double2));
+  P.o_Z = put(mc * nv * nv * P.ng_max * sizeof(double2));
   if (P.rot) P.o_ut = put((size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * sizeof(double2));
   P.kpad = (P.ng_max + 31) / 32 * 32;
-  P.o_Ws = put((size_t)P.nk * P.ng_max * 4 * P.kpad * sizeof(float));
-  P.o_RVs = put((size_t)np * P.nv * P.nv * 4 * P.kpad * sizeof(float));
-  P.pd32 = pd32 && pd_line_grid(P.N2, P.N3);
+  P.mixed = opt.mixed;
+  if (P.mixed) {
+    P.o_Ws = put((size_t)P.nk * P.ng_max * 4 * P.kpad * sizeof(float));
+    P.o_RVs = put(mc * nv * nv * 4 * P.kpad * sizeof(float));
+  }
+  P.pd32 = opt.pd32 && pd_line_grid(P.N2, P.N3);
   if (P.pd32) P.o_u32 = put((size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * sizeof(float2));
-  P.fwd_total = o;
-  P.o_dWraw = put((size_t)P.nk * P.ng_max * P.ng_max * sizeof(double2));
+  if (opt.backward && opt.project) P.o_dWraw = put((size_t)P.nk * P.ng_max * P.ng_max * sizeof(double2));
   P.total = o;
   return BSE_OK;
 }
@@ -464,9 +535,7 @@ void put_tables(const Plan& P, std::vector<char>& buf, size_t base) {
   cp(P.o_gpack, P.gpack.data(), P.gpack.size() * sizeof(int));
   cp(P.o_ng, P.ng.data(), P.ng.size() * sizeof(int));
   cp(P.o_pairs, P.pairs.data(), P.pairs.size() * sizeof(int4));
-  cp(P.o_qstart, P.qstart.data(), P.qstart.size() * sizeof(int));
-  cp(P.o_dwt, P.dwt.data(), P.dwt.size() * sizeof(int4));
-  cp(P.o_rvt, P.rvt.data(), P.rvt.size() * sizeof(int4));
+  cp(P.o_qs, P.qs.data(), P.qs.size() * sizeof(int));
   cp(P.o_plex, P.plex.data(), P.plex.size() * sizeof(int));
   cp(P.o_qbar, P.qbar.data(), P.qbar.size() * sizeof(int));
   cp(P.o_trmap, P.trmap.data(), P.trmap.size() * sizeof(int));
@@ -491,7 +560,9 @@ PdArgs pd_args(const Plan& P, const bse_system* s, char* region) {
   return a;
 }
 
-GemmArgs gemm_args(const Plan& P, const bse_system* s, char* region) {
+// Contraction arguments of chunk c of a system (chunk 0 for the exchange and
+// the mirror, which do not depend on it).
+GemmArgs gemm_args(const Plan& P, const bse_system* s, char* region, int c) {
   GemmArgs g{};
   g.X = reinterpret_cast<const double2*>(region + P.o_X);
   g.ns = P.ns;
@@ -504,17 +575,19 @@ GemmArgs gemm_args(const Plan& P, const bse_system* s, char* region) {
   g.Z = reinterpret_cast<double2*>(region + P.o_Z);
   g.W = reinterpret_cast<const double2*>(s->W);
   g.ng = reinterpret_cast<const int*>(region + P.o_ng);
-  g.qstart = reinterpret_cast<const int*>(region + P.o_qstart);
+  const int cc = c < (int)P.ch.size() ? c : 0;
+  g.qstart = reinterpret_cast<const int*>(region + P.o_qs) + (size_t)cc * (P.nk + 1);
   g.pairs = reinterpret_cast<const int4*>(region + P.o_pairs);
+  g.p0 = P.ch[cc].p0;
   g.eps = s->eps;
   g.nv = P.nv;
   g.nc = P.nc;
   g.nb = P.nb;
-  g.npairs = (int)P.pairs.size();
+  g.npairs = P.ch[cc].np;
   g.nt = P.nt;
-  g.Ws = region + P.o_Ws;
+  g.Ws = P.mixed ? region + P.o_Ws : nullptr;
   g.kpad = P.kpad;
-  g.RVs = region + P.o_RVs;
+  g.RVs = P.mixed ? region + P.o_RVs : nullptr;
   return g;
 }
 
@@ -559,6 +632,18 @@ void set_tune(const std::string& key, const Tune& t) {
   g_tune.emplace_back(key, t);
 }
 
+// One chunk of a batch: the merged launch lists of every system's share.
+struct BatchChunk {
+  std::vector<PdJob> jv, jc;
+  std::vector<int4> fill;
+  std::vector<S1Tile> s1;
+  std::vector<int> d2off;  // [nsys + 1]
+  int d2n = 0;
+  std::vector<int4> dwt, rvt;  // single system (backward)
+  bool has_q0 = false;         // single system (backward)
+  size_t o_jv = 0, o_jc = 0, o_fill = 0, o_s1 = 0, o_d2off = 0, o_gargs = 0, o_dwt = 0, o_rvt = 0;
+};
+
 // A batch of systems that share (N2, N3): per-system plans and workspace
 // regions, and the merged job and tile lists of the one-launch-per-stage build.
 struct Batch {
@@ -566,29 +651,35 @@ struct Batch {
   std::vector<size_t> base;  // workspace offset of each system's region
   int N2 = 0, N3 = 0, ng_max = 0;
   size_t lds = 0;
-  std::vector<PdJob> jx, jv, jc;
-  std::vector<S1Tile> s1;
+  std::vector<PdJob> jx;
   std::vector<HTile> xt, mt;
-  std::vector<int> d2off;
-  int d2n = 0;
+  std::vector<BatchChunk> C;
   bool tr = false;             // pair densities of time-reversal images derived
   bool pd32 = false;           // FP32 valence / conduction pair densities
   int np32 = 2;                // their planes per step: 4 when every window has F2 <= 16
   size_t lds32 = 0;            // their LDS bytes
-  std::vector<int4> fill;      // (dst, src, mode, sys)
-  size_t o_pdx = 0, o_pdv = 0, o_pdc = 0, o_gargs = 0, o_jx = 0, o_jv = 0, o_jc = 0, o_s1 = 0, o_xt = 0, o_mt = 0;
-  size_t o_d2off = 0, o_cnt = 0, o_tra = 0, o_fill = 0, tables = 0, total = 0;
+  size_t o_pdx = 0, o_pdv = 0, o_pdc = 0, o_jx = 0, o_xt = 0, o_mt = 0, o_tra = 0;
+  size_t o_cnt = 0, tables = 0, total = 0;
 };
 
 int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts& opt, Batch& B) {
   if (!sys || nsys < 1) return fail(BSE_ERR_INVALID_ARG, "no systems");
-  const bool backward = opt.backward, tr = opt.tr;
-  B.tr = tr;
+  B.tr = opt.tr;
   B.pd32 = opt.pd32;
   if (nsys > 32767) return fail(BSE_ERR_INVALID_ARG, "too many systems");
   B.P.resize(nsys);
+  // chunk count: the per-pair arrays of all systems over the budget
+  double bytes = 0.0;
   for (int i = 0; i < nsys; ++i) {
-    int rc = make_plan(&sys[i], B.P[i], opt.pd32);
+    int rc = check_system(&sys[i]);
+    if (rc) return rc;
+    const double nk = (double)sys[i].kmesh[0] * sys[i].kmesh[1] * sys[i].kmesh[2];
+    bytes += nk * (nk + 1) / 2 * (double)pair_bytes(&sys[i], opt.mixed);
+  }
+  const int nchunk = (int)std::min(1e6, std::max(1.0, std::ceil(bytes / (double)g_chunk_budget.load())));
+  for (int i = 0; i < nsys; ++i) {
+    int rc = make_geometry(&sys[i], B.P[i]);
+    if (!rc) rc = plan_pairs(&sys[i], B.P[i], opt, nchunk, i);
     if (rc) return rc;
     const Plan& P = B.P[i];
     if (i == 0) {
@@ -603,7 +694,7 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
     B.pd32 = B.pd32 && P.pd32;
     if (l > 160 * 1024) return fail(BSE_ERR_SHAPE, "FFT window of system %d needs more than 160 KiB of LDS", i);
     B.lds = std::max(B.lds, l);
-    if (tr && !P.tr_closed)
+    if (opt.tr && !P.tr_closed)
       return fail(BSE_ERR_SHAPE, "system %d: time reversal needs G spheres closed under G -> t - G (qbar = -q - t)", i);
   }
   if (B.pd32) {
@@ -618,24 +709,41 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
     }
   }
   // merged lists
-  std::vector<PdJob> jx, jv, jc;
-  B.d2off.assign(nsys + 1, 0);
+  int nc = 0;
+  for (const Plan& P : B.P) nc = std::max(nc, (int)P.ch.size());
+  B.C.assign(nc, BatchChunk{});
+  std::vector<PdJob> jx;
   for (int i = 0; i < nsys; ++i) {
     const Plan& P = B.P[i];
     for (PdJob j : P.jx) jx.push_back((j.nab |= i << 16, j));
-    for (PdJob j : tr ? P.jv_tr : P.jv) jv.push_back((j.nab |= i << 16, j));
-    for (PdJob j : tr ? P.jc_tr : P.jc) jc.push_back((j.nab |= i << 16, j));
-    if (tr)
-      for (int4 f : P.trfill) B.fill.push_back((f.w = i, f));
-    for (S1Tile s : P.s1) B.s1.push_back((s.sys = i, s));
-    for (HTile h : P.xt) B.xt.push_back((h.sys = i, h));
-    for (HTile h : P.mt) B.mt.push_back((h.sys = i, h));
-    B.d2off[i + 1] = B.d2off[i] + P.d2items;
+    B.xt.insert(B.xt.end(), P.xt.begin(), P.xt.end());
+    B.mt.insert(B.mt.end(), P.mt.begin(), P.mt.end());
   }
-  B.d2n = B.d2off[nsys];
   B.jx = dispatch_order(std::move(jx), tn.ktile);
-  B.jv = dispatch_order(std::move(jv), tn.ktile);
-  B.jc = dispatch_order(std::move(jc), tn.ktile);
+  for (int c = 0; c < nc; ++c) {
+    BatchChunk& K = B.C[c];
+    std::vector<PdJob> jv, jc;
+    K.d2off.assign(nsys + 1, 0);
+    for (int i = 0; i < nsys; ++i) {
+      const Plan& P = B.P[i];
+      K.d2off[i + 1] = K.d2off[i];
+      if (c >= (int)P.ch.size()) continue;
+      const Chunk& S = P.ch[c];
+      for (PdJob j : S.jv) jv.push_back((j.nab |= i << 16, j));
+      for (PdJob j : S.jc) jc.push_back((j.nab |= i << 16, j));
+      K.fill.insert(K.fill.end(), S.fill.begin(), S.fill.end());
+      K.s1.insert(K.s1.end(), S.s1.begin(), S.s1.end());
+      K.d2off[i + 1] += S.d2items;
+      if (nsys == 1) {
+        K.dwt = S.dwt;
+        K.rvt = S.rvt;
+        K.has_q0 = S.has_q0;
+      }
+    }
+    K.d2n = K.d2off[nsys];
+    K.jv = dispatch_order(std::move(jv), tn.ktile);
+    K.jc = dispatch_order(std::move(jc), tn.ktile);
+  }
   // workspace: batch tables, then one region per system
   size_t o = 0;
   auto put = [&](size_t bytes) {
@@ -646,32 +754,37 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
   B.o_pdx = put(nsys * sizeof(PdArgs));
   B.o_pdv = put(nsys * sizeof(PdArgs));
   B.o_pdc = put(nsys * sizeof(PdArgs));
-  B.o_gargs = put(nsys * sizeof(GemmArgs));
   B.o_jx = put(B.jx.size() * sizeof(PdJob));
-  B.o_jv = put(B.jv.size() * sizeof(PdJob));
-  B.o_jc = put(B.jc.size() * sizeof(PdJob));
-  B.o_s1 = put(B.s1.size() * sizeof(S1Tile));
   B.o_xt = put(B.xt.size() * sizeof(HTile));
   B.o_mt = put(B.mt.size() * sizeof(HTile));
-  B.o_d2off = put(B.d2off.size() * sizeof(int));
-  B.o_tra = put(tr ? nsys * sizeof(TrArgs) : 0);
-  B.o_fill = put(B.fill.size() * sizeof(int4));
+  B.o_tra = put(opt.tr ? nsys * sizeof(TrArgs) : 0);
+  for (BatchChunk& K : B.C) {
+    K.o_gargs = put(nsys * sizeof(GemmArgs));
+    K.o_jv = put(K.jv.size() * sizeof(PdJob));
+    K.o_jc = put(K.jc.size() * sizeof(PdJob));
+    K.o_fill = put(K.fill.size() * sizeof(int4));
+    K.o_s1 = put(K.s1.size() * sizeof(S1Tile));
+    K.o_d2off = put(K.d2off.size() * sizeof(int));
+    K.o_dwt = put(K.dwt.size() * sizeof(int4));
+    K.o_rvt = put(K.rvt.size() * sizeof(int4));
+  }
   // the tables above are uploaded as one image [0, o_cnt); the counters are not
   B.o_cnt = put(kCntBytes + 32 + 8 * sizeof(unsigned long long));  // queues, validation
   B.base.resize(nsys);
   for (int i = 0; i < nsys; ++i) {
     B.base[i] = o;
-    o = align256(o + (backward ? B.P[i].total : B.P[i].fwd_total));
+    o = align256(o + B.P[i].total);
   }
   B.total = o;
   return BSE_OK;
 }
 
 // Key of everything the host plan of a batch depends on: shapes, sphere
-// tables (hashed by content), the backward flag and the k tile.
+// tables (hashed by content), the options and the k tile.
 std::string plan_key(const bse_system* sys, int nsys, int ktile, const BatchOpts& o) {
-  std::string k = std::to_string(nsys) + (o.backward ? "b" : "f") + (o.tr ? "t" : "") + (o.pd32 ? "s" : "") +
-                  std::to_string(ktile);
+  std::string k = std::to_string(nsys) + (o.backward ? "b" : "f") + (o.project ? "p" : "") + (o.tr ? "t" : "") +
+                  (o.pd32 ? "s" : "") + (o.mixed ? "m" : "") + std::to_string(ktile) + "c" +
+                  std::to_string(g_chunk_budget.load());
   for (int i = 0; i < nsys; ++i) {
     const bse_system& s = sys[i];
     const int nk = s.kmesh[0] * s.kmesh[1] * s.kmesh[2];
@@ -732,7 +845,7 @@ int cached_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpt
   return BSE_OK;
 }
 
-// Uploads every table of the batch (one blocking copy).
+// Uploads every table of the batch (asynchronous copies from pinned staging).
 int upload_batch(const Batch& B, const bse_system* sys, int precision, char* ws, hipStream_t st) {
   const int nsys = (int)B.P.size();
   // staging image: the batch tables, then each system's own tables
@@ -750,7 +863,6 @@ int upload_batch(const Batch& B, const bse_system* sys, int precision, char* ws,
     if (bytes) std::memcpy(buf + off, src, bytes);
   };
   std::vector<PdArgs> ax(nsys), av(nsys), ac(nsys);
-  std::vector<GemmArgs> ga(nsys);
   std::vector<TrArgs> ta(B.tr ? nsys : 0);
   for (int i = 0; i < nsys; ++i) {
     const Plan& P = B.P[i];
@@ -763,14 +875,11 @@ int upload_batch(const Batch& B, const bse_system* sys, int precision, char* ws,
     av[i].out = reinterpret_cast<double2*>(region + P.o_RV);
     ac[i] = a;
     ac[i].out = reinterpret_cast<double2*>(region + P.o_RC);
-    ga[i] = gemm_args(P, &sys[i], region);
-    ga[i].w_head_fp64 = precision != BSE_FP64;  // mixed: the q = 0 head of W is added in FP64
     if (B.tr) {
       TrArgs& r = ta[i];
       r.rv = reinterpret_cast<double2*>(region + P.o_RV);
       r.rc = reinterpret_cast<double2*>(region + P.o_RC);
       r.ng = reinterpret_cast<const int*>(region + P.o_ng);
-      r.pairs = reinterpret_cast<const int4*>(region + P.o_pairs);
       r.trmap = reinterpret_cast<const int*>(region + P.o_trmap);
       r.ng_max = P.ng_max;
       r.nv = P.nv;
@@ -780,16 +889,26 @@ int upload_batch(const Batch& B, const bse_system* sys, int precision, char* ws,
   cp(B.o_pdx, ax.data(), nsys * sizeof(PdArgs));
   cp(B.o_pdv, av.data(), nsys * sizeof(PdArgs));
   cp(B.o_pdc, ac.data(), nsys * sizeof(PdArgs));
-  cp(B.o_gargs, ga.data(), nsys * sizeof(GemmArgs));
   cp(B.o_jx, B.jx.data(), B.jx.size() * sizeof(PdJob));
-  cp(B.o_jv, B.jv.data(), B.jv.size() * sizeof(PdJob));
-  cp(B.o_jc, B.jc.data(), B.jc.size() * sizeof(PdJob));
-  cp(B.o_s1, B.s1.data(), B.s1.size() * sizeof(S1Tile));
   cp(B.o_xt, B.xt.data(), B.xt.size() * sizeof(HTile));
   cp(B.o_mt, B.mt.data(), B.mt.size() * sizeof(HTile));
-  cp(B.o_d2off, B.d2off.data(), B.d2off.size() * sizeof(int));
   cp(B.o_tra, ta.data(), ta.size() * sizeof(TrArgs));
-  cp(B.o_fill, B.fill.data(), B.fill.size() * sizeof(int4));
+  std::vector<GemmArgs> ga(nsys);
+  for (size_t c = 0; c < B.C.size(); ++c) {
+    const BatchChunk& K = B.C[c];
+    for (int i = 0; i < nsys; ++i) {
+      ga[i] = gemm_args(B.P[i], &sys[i], ws + B.base[i], (int)c);
+      ga[i].w_head_fp64 = precision != BSE_FP64;  // mixed: the q = 0 head of W is added in FP64
+    }
+    cp(K.o_gargs, ga.data(), nsys * sizeof(GemmArgs));
+    cp(K.o_jv, K.jv.data(), K.jv.size() * sizeof(PdJob));
+    cp(K.o_jc, K.jc.data(), K.jc.size() * sizeof(PdJob));
+    cp(K.o_fill, K.fill.data(), K.fill.size() * sizeof(int4));
+    cp(K.o_s1, K.s1.data(), K.s1.size() * sizeof(S1Tile));
+    cp(K.o_d2off, K.d2off.data(), K.d2off.size() * sizeof(int));
+    cp(K.o_dwt, K.dwt.data(), K.dwt.size() * sizeof(int4));
+    cp(K.o_rvt, K.rvt.data(), K.rvt.size() * sizeof(int4));
+  }
   std::vector<char> tb;
   for (int i = 0; i < nsys; ++i) {
     tb.assign(B.P[i].tables, 0);
@@ -815,11 +934,12 @@ int persistent_grid(size_t lds, int njobs, int wg_per_cu) {
   return std::min(g, std::max(njobs, kXcds));
 }
 
-// One pair-density launch over the batch: kind 0 exchange, 1 vv, 2 cc.
-int run_pd(const Batch& B, char* ws, int kind, const Tune& tn, hipStream_t st) {
-  const std::vector<PdJob>& jobs = kind == 0 ? B.jx : kind == 1 ? B.jv : B.jc;
+// One pair-density launch over the batch: kind 0 exchange (every k), 1 vv and
+// 2 cc (the pairs of chunk c).
+int run_pd(const Batch& B, char* ws, int kind, int c, const Tune& tn, hipStream_t st) {
+  const std::vector<PdJob>& jobs = kind == 0 ? B.jx : kind == 1 ? B.C[c].jv : B.C[c].jc;
   const size_t o_args = kind == 0 ? B.o_pdx : kind == 1 ? B.o_pdv : B.o_pdc;
-  const size_t o_jobs = kind == 0 ? B.o_jx : kind == 1 ? B.o_jv : B.o_jc;
+  const size_t o_jobs = kind == 0 ? B.o_jx : kind == 1 ? B.C[c].o_jv : B.C[c].o_jc;
   if (jobs.empty()) return BSE_OK;
   PdBatch b{};
   b.sys = reinterpret_cast<const PdArgs*>(ws + o_args);
@@ -839,13 +959,13 @@ int run_pd(const Batch& B, char* ws, int kind, const Tune& tn, hipStream_t st) {
   return BSE_OK;
 }
 
-// Pair densities of the time-reversal images (kind 1 vv, 2 cc), after the
-// pair-density launch of the same kind.
-int run_tr_fill(const Batch& B, char* ws, int kind, hipStream_t st) {
-  if (!B.tr || B.fill.empty() || kind == 0) return BSE_OK;
+// Pair densities of the time-reversal images of chunk c (kind 1 vv, 2 cc),
+// after the pair-density launch of the same kind.
+int run_tr_fill(const Batch& B, char* ws, int kind, int c, hipStream_t st) {
+  if (!B.tr || kind == 0 || B.C[c].fill.empty()) return BSE_OK;
   HIP_TRY(stage(BSE_STAGE_TR_FILL, st, [&] {
-    return launch_tr_fill(reinterpret_cast<const TrArgs*>(ws + B.o_tra), reinterpret_cast<const int4*>(ws + B.o_fill),
-                          (int)B.fill.size(), kind, st);
+    return launch_tr_fill(reinterpret_cast<const TrArgs*>(ws + B.o_tra),
+                          reinterpret_cast<const int4*>(ws + B.C[c].o_fill), (int)B.C[c].fill.size(), kind, st);
   }));
   return BSE_OK;
 }
@@ -879,8 +999,10 @@ int prepare_u(const Batch& B, const bse_system* sys, char* ws, hipStream_t st) {
   return BSE_OK;
 }
 
-// The forward build of every system of the batch, one launch per stage (the
-// sqrt v tables aside, one small launch per system), all on `st`.
+// The forward build of every system of the batch, all on `st`: the exchange
+// densities and the exchange term once, then per chunk the valence and
+// conduction densities and the two stages of the direct term (one launch per
+// stage over all systems), then the mirror.
 int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& tn, char* ws, hipStream_t st) {
   const int nsys = (int)B.P.size();
   int rc = upload_batch(B, sys, precision, ws, st);
@@ -901,31 +1023,36 @@ int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& 
       }));
     }
   }
-  const GemmArgs* gs = reinterpret_cast<const GemmArgs*>(ws + B.o_gargs);
+  const GemmArgs* g0 = reinterpret_cast<const GemmArgs*>(ws + B.C[0].o_gargs);
   const HTile* xt = reinterpret_cast<const HTile*>(ws + B.o_xt);
   const HTile* mt = reinterpret_cast<const HTile*>(ws + B.o_mt);
-  const S1Tile* s1 = reinterpret_cast<const S1Tile*>(ws + B.o_s1);
-  const int* d2off = reinterpret_cast<const int*>(ws + B.o_d2off);
-  for (int kind = 0; kind < 3; ++kind) {
-    if ((rc = run_pd(B, ws, kind, tn, st)) || (rc = run_tr_fill(B, ws, kind, st))) return rc;
-    if (kind == 1 && precision != BSE_FP64) {
+  if ((rc = run_pd(B, ws, 0, 0, tn, st))) return rc;
+  HIP_TRY(stage(BSE_STAGE_EXCHANGE, st, [&] { return launch_exchange(g0, xt, (int)B.xt.size(), precision, st); }));
+  for (int c = 0; c < (int)B.C.size(); ++c) {
+    const BatchChunk& K = B.C[c];
+    const GemmArgs* gs = reinterpret_cast<const GemmArgs*>(ws + K.o_gargs);
+    if ((rc = run_pd(B, ws, 1, c, tn, st)) || (rc = run_tr_fill(B, ws, 1, c, st))) return rc;
+    if (precision != BSE_FP64) {
       // the A operand of the mixed stage 1, split once
       for (int i = 0; i < nsys; ++i) {
         const Plan& P = B.P[i];
+        if (c >= (int)P.ch.size()) continue;
         char* region = ws + B.base[i];
         HIP_TRY(stage(BSE_STAGE_SPLIT_W, st, [&] {
           return launch_split_rv(reinterpret_cast<const double2*>(region + P.o_RV),
-                                 reinterpret_cast<const int4*>(region + P.o_pairs),
-                                 reinterpret_cast<const int*>(region + P.o_ng), P.pairs.size() * P.nv * P.nv,
+                                 reinterpret_cast<const int4*>(region + P.o_pairs) + P.ch[c].p0,
+                                 reinterpret_cast<const int*>(region + P.o_ng), (size_t)P.ch[c].np * P.nv * P.nv,
                                  P.nv * P.nv, P.ng_max, P.kpad, precision, region + P.o_RVs, st);
         }));
       }
     }
+    if ((rc = run_pd(B, ws, 2, c, tn, st)) || (rc = run_tr_fill(B, ws, 2, c, st))) return rc;
+    const S1Tile* s1 = reinterpret_cast<const S1Tile*>(ws + K.o_s1);
+    const int* d2off = reinterpret_cast<const int*>(ws + K.o_d2off);
+    HIP_TRY(stage(BSE_STAGE_DIRECT1, st, [&] { return launch_direct_s1(gs, s1, (int)K.s1.size(), precision, st); }));
+    HIP_TRY(stage(BSE_STAGE_DIRECT2, st, [&] { return launch_direct_s2(gs, d2off, nsys, K.d2n, st); }));
   }
-  HIP_TRY(stage(BSE_STAGE_EXCHANGE, st, [&] { return launch_exchange(gs, xt, (int)B.xt.size(), precision, st); }));
-  HIP_TRY(stage(BSE_STAGE_DIRECT1, st, [&] { return launch_direct_s1(gs, s1, (int)B.s1.size(), precision, st); }));
-  HIP_TRY(stage(BSE_STAGE_DIRECT2, st, [&] { return launch_direct_s2(gs, d2off, nsys, B.d2n, st); }));
-  HIP_TRY(stage(BSE_STAGE_MIRROR, st, [&] { return launch_mirror(gs, mt, (int)B.mt.size(), st); }));
+  HIP_TRY(stage(BSE_STAGE_MIRROR, st, [&] { return launch_mirror(g0, mt, (int)B.mt.size(), st); }));
   return BSE_OK;
 }
 
@@ -1019,12 +1146,13 @@ void cache_store(const char* path, const std::string& key, const Tune& t) {
 thread_local std::vector<Tune> g_tried;
 
 // Times the valence-valence pair-density launch (the dominant stage) of the
-// batch under each candidate dispatch and keeps the fastest.
+// batch's first chunk under each candidate dispatch and keeps the fastest.
 int autotune(const bse_system* sys, int nsys, int precision, bool pd32, const char* cache, Tune& best, char* ws,
              size_t ws_bytes, hipStream_t st) {
   Batch B0;
   BatchOpts opt;
   opt.pd32 = pd32;
+  opt.mixed = precision != BSE_FP64;
   int rc = make_batch(sys, nsys, Tune{}, opt, B0);
   if (rc) return rc;
   const std::string key = batch_key(B0.P, precision, B0.pd32);
@@ -1062,7 +1190,7 @@ int autotune(const bse_system* sys, int nsys, int precision, bool pd32, const ch
     for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
       float m = 0.f;
       if (e == hipSuccess) e = hipEventRecord(e0, st);
-      if (e == hipSuccess && (rc = run_pd(B, ws, 1, c, st))) break;
+      if (e == hipSuccess && (rc = run_pd(B, ws, 1, 0, c, st))) break;
       if (e == hipSuccess) e = hipEventRecord(e1, st);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       if (e == hipSuccess) e = hipEventElapsedTime(&m, e0, e1);
@@ -1112,26 +1240,44 @@ int grad_setup(const bse_system* sys, const Plan& P, const double* cell, GradCel
   return BSE_OK;
 }
 
+// Arguments of bse_spectrum (shared with its variant without workspace).
+int spectrum_args(int ns, int nlam, const double* E, const double* A, const double* d, int nq, int nk,
+                  double omega_cell, int nw, double eta_eV, double* eps2) {
+  if (ns < 1 || nlam < 1 || nlam > ns || nw < 1) return fail(BSE_ERR_INVALID_ARG, "bad sizes");
+  if (nq < 1 || nk < 1) return fail(BSE_ERR_INVALID_ARG, "nq and nk must be positive");
+  if (!E || !A || !d || !eps2) return fail(BSE_ERR_INVALID_ARG, "NULL pointer");
+  if (!(eta_eV > 0.0)) return fail(BSE_ERR_INVALID_ARG, "eta must be positive");
+  if (!(omega_cell > 0.0)) return fail(BSE_ERR_INVALID_ARG, "omega_cell must be positive");
+  return BSE_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
 size_t bse_workspace_size(const bse_system* sys, int nsys, int precision, int flags) {
-  (void)precision;
-  (void)flags;
   if (!sys || nsys < 1) return 0;
-  Batch B;
-  // one system: room for the backward as well; a batch: the forward build,
-  // with room for the time-reversal tables where the spheres allow them
+  // the forward build, with room for the time-reversal tables where the
+  // spheres allow them; one system: the backward as well
   BatchOpts o;
-  o.backward = nsys == 1;
   o.pd32 = (flags & BSE_FP32_PAIRDENS) != 0;
+  o.mixed = precision != BSE_FP64;
+  Batch B;
   if (make_batch(sys, nsys, Tune{}, o, B)) return 0;
   size_t total = B.total;
-  Batch Bt;
-  o.tr = true;
   const std::string keep = g_err;  // spheres without time reversal are no error here
-  if (make_batch(sys, nsys, Tune{}, o, Bt) == BSE_OK) total = std::max(total, Bt.total);
+  for (int pass = 0; pass < 3; ++pass) {
+    BatchOpts x = o;
+    x.tr = pass != 1;
+    if (pass > 0) {
+      if (nsys != 1) continue;
+      x.backward = true;
+      x.project = (flags & BSE_PROJECT_DW) != 0;
+      x.mixed = false;  // the backward contracts unsplit operands
+    }
+    Batch Bx;
+    if (make_batch(sys, nsys, Tune{}, x, Bx) == BSE_OK) total = std::max(total, Bx.total);
+  }
   g_err = keep;
   return total;
 }
@@ -1140,7 +1286,7 @@ int bse_pair_density(const bse_system* sys, int kind, const int* kpairs, int npa
                      double* out, void* ws, size_t ws_bytes, void* stream) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   Plan P;
-  int rc = make_plan(sys, P, false);
+  int rc = make_geometry(sys, P);
   if (rc) return rc;
   if (!out || !ws) return fail(BSE_ERR_INVALID_ARG, "out / ws is NULL");
   std::vector<PdJob> jobs;
@@ -1230,6 +1376,7 @@ int bse_build_H(const bse_system* sys, int nsys, int precision, int flags, void*
   BatchOpts opt;
   opt.tr = (flags & BSE_TIME_REVERSAL) != 0;
   opt.pd32 = (flags & BSE_FP32_PAIRDENS) != 0;
+  opt.mixed = precision != BSE_FP64;
   int rc = cached_batch(sys, nsys, Tune{}, opt, &Bp);
   if (rc) return rc;
   Tune tn = tune_for(batch_key(Bp->P, precision, Bp->pd32));
@@ -1254,30 +1401,23 @@ int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, do
     return fail(BSE_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
   if ((flags & BSE_FP32_PAIRDENS) && precision == BSE_FP64)
     return fail(BSE_ERR_INVALID_ARG, "BSE_FP32_PAIRDENS needs a mixed precision (split-FP32 or BF16x3)");
+  const bool project = (flags & BSE_PROJECT_DW) != 0;
   Batch B;
   BatchOpts opt;
   opt.backward = true;
+  opt.project = project && dW;
   opt.tr = (flags & BSE_TIME_REVERSAL) != 0;
   opt.pd32 = (flags & BSE_FP32_PAIRDENS) != 0;
   int rc = make_batch(sys, 1, Tune{}, opt, B);
   if (rc) return rc;
   const Plan& P = B.P[0];
   if (ws_bytes < B.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, B.total);
-  const bool project = (flags & BSE_PROJECT_DW) != 0;
   if (project && !P.tr_closed)
     return fail(BSE_ERR_NOT_HERMITIAN, "G spheres are not closed under time reversal; cannot project dW");
   char* w = static_cast<char*>(ws);
-  if ((rc = upload_batch(B, sys, precision, w, st))) return rc;
-  // recompute the pair densities (exchange ones only for dX)
+  if ((rc = upload_batch(B, sys, BSE_FP64, w, st))) return rc;
   char* r = w + B.base[0];
   if ((rc = prepare_u(B, sys, w, st))) return rc;
-  if (dX) {
-    double* vs = reinterpret_cast<double*>(r + P.o_vs);
-    HIP_TRY(launch_vscale(sys->vx, P.ng[0], P.ng_max, vs, st));
-    if ((rc = run_pd(B, w, 0, Tune{}, st))) return rc;
-  }
-  for (int kind = 1; kind < 3; ++kind)
-    if ((rc = run_pd(B, w, kind, Tune{}, st)) || (rc = run_tr_fill(B, w, kind, st))) return rc;
   AdjArgs g{};
   g.dH = reinterpret_cast<const double2*>(dH);
   g.RV = reinterpret_cast<const double2*>(r + P.o_RV);
@@ -1288,8 +1428,6 @@ int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, do
   g.deps = deps;
   g.pairs = reinterpret_cast<const int4*>(r + P.o_pairs);
   g.ng = reinterpret_cast<const int*>(r + P.o_ng);
-  g.qstart = reinterpret_cast<const int*>(r + P.o_qstart);
-  g.dwtiles = reinterpret_cast<const int4*>(r + P.o_dwt);
   g.qbar = reinterpret_cast<const int*>(r + P.o_qbar);
   g.trmap = reinterpret_cast<const int*>(r + P.o_trmap);
   g.nk = P.nk;
@@ -1297,29 +1435,46 @@ int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, do
   g.nc = P.nc;
   g.ns = P.ns;
   g.ng_max = P.ng_max;
-  g.npairs = (int)P.pairs.size();
   g.cpref = 27.211386245988 / ((double)P.nk * sys->omega_cell);
   g.Z = reinterpret_cast<const double2*>(r + P.o_Z);
   g.W = reinterpret_cast<const double2*>(sys->W);
   g.Xs = reinterpret_cast<const double2*>(r + P.o_X);
   g.vs = reinterpret_cast<const double*>(r + P.o_vs);
   g.plex = reinterpret_cast<const int*>(r + P.o_plex);
-  g.rvtiles = reinterpret_cast<const int4*>(r + P.o_rvt);
   g.ngx = P.ng[0];
   g.dX = reinterpret_cast<double2*>(dX);
   g.drv = reinterpret_cast<double2*>(drho_vv);
   g.drc = reinterpret_cast<double2*>(drho_cc);
-  if (drho_cc) {
-    // Z = conj(rho_vv')^T W (the forward stage 1, FP64) into the Z area
-    const GemmArgs* gs = reinterpret_cast<const GemmArgs*>(w + B.o_gargs);
-    const S1Tile* s1 = reinterpret_cast<const S1Tile*>(w + B.o_s1);
-    HIP_TRY(launch_direct_s1(gs, s1, (int)B.s1.size(), BSE_FP64, st));
-    HIP_TRY(launch_adj_drc(g, st));
+  // the exchange densities (only for dX) and their gradient
+  if (dX) {
+    double* vs = reinterpret_cast<double*>(r + P.o_vs);
+    HIP_TRY(launch_vscale(sys->vx, P.ng[0], P.ng_max, vs, st));
+    if ((rc = run_pd(B, w, 0, 0, Tune{}, st))) return rc;
+    HIP_TRY(launch_adj_dx(g, st));
   }
-  // T (over the Z area), dW, deps
-  HIP_TRY(launch_adjoint(g, precision, (int)P.dwt.size(), project, st));
-  if (drho_vv) HIP_TRY(launch_adj_drv(g, (int)P.rvt.size(), st));
-  if (dX) HIP_TRY(launch_adj_dx(g, st));
+  if (g.dWout) HIP_TRY(launch_zero_f64(reinterpret_cast<double*>(g.dWout), (size_t)P.nk * P.ng_max * P.ng_max * 2, st));
+  // per chunk: recompute the pair densities, then the chunk's share of every gradient
+  for (int c = 0; c < (int)B.C.size(); ++c) {
+    const BatchChunk& K = B.C[c];
+    for (int kind = 1; kind < 3; ++kind)
+      if ((rc = run_pd(B, w, kind, c, Tune{}, st)) || (rc = run_tr_fill(B, w, kind, c, st))) return rc;
+    g.qstart = reinterpret_cast<const int*>(r + P.o_qs) + (size_t)c * (P.nk + 1);
+    g.p0 = P.ch[c].p0;
+    g.npairs = P.ch[c].np;
+    g.dwtiles = reinterpret_cast<const int4*>(w + K.o_dwt);
+    g.rvtiles = reinterpret_cast<const int4*>(w + K.o_rvt);
+    if (drho_cc) {
+      // Z = conj(rho_vv')^T W (the forward stage 1, FP64) into the Z area
+      const GemmArgs* gs = reinterpret_cast<const GemmArgs*>(w + K.o_gargs);
+      const S1Tile* s1 = reinterpret_cast<const S1Tile*>(w + K.o_s1);
+      HIP_TRY(launch_direct_s1(gs, s1, (int)K.s1.size(), BSE_FP64, st));
+      HIP_TRY(launch_adj_drc(g, st));
+    }
+    // T (over the Z area), the chunk's share of dW
+    HIP_TRY(launch_adjoint(g, precision, (int)K.dwt.size(), K.has_q0, st));
+    if (drho_vv) HIP_TRY(launch_adj_drv(g, (int)K.rvt.size(), st));
+  }
+  HIP_TRY(launch_adjoint_finish(g, project, st));
   return BSE_OK;
 }
 
@@ -1360,7 +1515,7 @@ int bse_transition_dipoles(const bse_system* sys, const double* cell, const doub
                            void* ws, size_t ws_bytes, void* stream) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   Plan P;
-  int rc = make_plan(sys, P, false);
+  int rc = make_geometry(sys, P);
   if (rc) return rc;
   if (!d || !ws || !qhat) return fail(BSE_ERR_INVALID_ARG, "d / ws / qhat is NULL");
   if (nq < 1 || nq > kMaxQhat) return fail(BSE_ERR_INVALID_ARG, "nq = %d not in 1..%d", nq, kMaxQhat);
@@ -1385,19 +1540,8 @@ int bse_transition_dipoles(const bse_system* sys, const double* cell, const doub
 
 size_t bse_transition_dipoles_workspace(const bse_system* sys) {
   Plan P;
-  if (make_plan(sys, P, false)) return 0;
+  if (make_geometry(sys, P)) return 0;
   return align256((size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * sizeof(double2)) + (size_t)P.ns * 3 * sizeof(double2);
-}
-
-// Arguments of bse_spectrum (shared with its variant without workspace).
-static int spectrum_args(int ns, int nlam, const double* E, const double* A, const double* d, int nq, int nk,
-                  double omega_cell, int nw, double eta_eV, double* eps2) {
-  if (ns < 1 || nlam < 1 || nlam > ns || nw < 1) return fail(BSE_ERR_INVALID_ARG, "bad sizes");
-  if (nq < 1 || nk < 1) return fail(BSE_ERR_INVALID_ARG, "nq and nk must be positive");
-  if (!E || !A || !d || !eps2) return fail(BSE_ERR_INVALID_ARG, "NULL pointer");
-  if (!(eta_eV > 0.0)) return fail(BSE_ERR_INVALID_ARG, "eta must be positive");
-  if (!(omega_cell > 0.0)) return fail(BSE_ERR_INVALID_ARG, "omega_cell must be positive");
-  return BSE_OK;
 }
 
 int bse_spectrum(int ns, int nlam, const double* E, const double* A, const double* d, int nq, int nk,
@@ -1410,6 +1554,35 @@ int bse_spectrum(int ns, int nlam, const double* E, const double* A, const doubl
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   HIP_TRY(launch_spectrum(ns, nlam, nq, E, reinterpret_cast<const double2*>(A), reinterpret_cast<const double2*>(d),
                           (double)nk * omega_cell, nw, w0_eV, w1_eV, eta_eV, static_cast<double*>(ws), eps2, st));
+  return BSE_OK;
+}
+
+size_t bse_haydock_workspace(int ns, int nq, int niter) {
+  if (ns < 1 || nq < 1 || nq > kMaxQhat || niter < 1) return 0;
+  return 3 * align256((size_t)nq * ns * sizeof(double2)) + align256((size_t)nq * niter * 2 * sizeof(double)) +
+         align256((size_t)nq * sizeof(double));
+}
+
+int bse_haydock_spectrum(int ns, const double* H, const double* d, int nq, int niter, int nk, double omega_cell,
+                         int nw, double w0_eV, double w1_eV, double eta_eV, double* eps2, double* coef, void* ws,
+                         size_t ws_bytes, void* stream) {
+  if (ns < 1 || nw < 1 || nk < 1 || niter < 1) return fail(BSE_ERR_INVALID_ARG, "bad sizes");
+  if (nq < 1 || nq > kMaxQhat) return fail(BSE_ERR_INVALID_ARG, "nq = %d not in 1..%d", nq, kMaxQhat);
+  if (!H || !d || !eps2 || !ws) return fail(BSE_ERR_INVALID_ARG, "NULL pointer");
+  if (!(eta_eV > 0.0)) return fail(BSE_ERR_INVALID_ARG, "eta must be positive");
+  if (!(omega_cell > 0.0)) return fail(BSE_ERR_INVALID_ARG, "omega_cell must be positive");
+  const size_t need = bse_haydock_workspace(ns, nq, niter);
+  if (ws_bytes < need) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+  char* w = static_cast<char*>(ws);
+  const size_t vec = align256((size_t)nq * ns * sizeof(double2));
+  double2* V0 = reinterpret_cast<double2*>(w);
+  double2* V1 = reinterpret_cast<double2*>(w + vec);
+  double2* Y = reinterpret_cast<double2*>(w + 2 * vec);
+  double* cf = reinterpret_cast<double*>(w + 3 * vec);
+  double* n2 = reinterpret_cast<double*>(w + 3 * vec + align256((size_t)nq * niter * 2 * sizeof(double)));
+  HIP_TRY(launch_haydock(ns, reinterpret_cast<const double2*>(H), reinterpret_cast<const double2*>(d), nq, niter,
+                         (double)nk * omega_cell, nw, w0_eV, w1_eV, eta_eV, eps2, coef ? coef : cf, V0, V1, Y, n2,
+                         reinterpret_cast<hipStream_t>(stream)));
   return BSE_OK;
 }
 
@@ -1441,6 +1614,11 @@ int bse_profile_read(double* total_ms, long long* launches, int nstages, int res
       g_prof_ms[i] = 0;
       g_prof_n[i] = 0;
     }
+  return BSE_OK;
+}
+
+int bse_set_chunk_budget(size_t bytes) {
+  g_chunk_budget.store(bytes ? bytes : kChunkBudget);
   return BSE_OK;
 }
 

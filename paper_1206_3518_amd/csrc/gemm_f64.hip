@@ -5,6 +5,8 @@
 //   mirror    lower k blocks = conjugate transpose of the upper ones
 // Complex products run as four real v_mfma_f64_16x16x4 products per step.
 // Every launch covers a batch of systems: tiles and items name their system.
+#include <algorithm>
+
 #include "../../include/bse.h"
 #include "bse_internal.h"
 #include "gemm_tiles.h"
@@ -47,7 +49,7 @@ __global__ __launch_bounds__(256) void k_direct_s1(const GemmArgs* __restrict__ 
   const S1Tile tl = tiles[blockIdx.x];
   const GemmArgs g = gs[tl.sys];
   const int nv2 = g.nv * g.nv;
-  const int row_base = gbl(g.qstart)[tl.iq] * nv2;
+  const int row_base = (gbl(g.qstart)[tl.iq] - g.p0) * nv2;  // rows of the chunk
   const int rows = (gbl(g.qstart)[tl.iq + 1] - gbl(g.qstart)[tl.iq]) * nv2;
   const int K = gbl(g.ng)[tl.iq];
   const double2* A = g.RV + (size_t)row_base * g.ng_max;
@@ -78,7 +80,8 @@ hipError_t launch_direct_s1(const GemmArgs* gs, const S1Tile* tiles, int ntiles,
 
 // ------------------------------------------------------------------ direct, stage 2 + assembly
 
-// One wave per item (pair p of system s, 16 x 16 tile (ti, tj) of vv' x cc').
+// One wave per item (pair p of the chunk of system s, 16 x 16 tile (ti, tj) of
+// vv' x cc').
 __global__ __launch_bounds__(256) void k_direct_s2(const GemmArgs* __restrict__ gs, const int* __restrict__ d2off,
                                                    int nsys, int nitems) {
   const int lane = threadIdx.x & 63;
@@ -90,8 +93,8 @@ __global__ __launch_bounds__(256) void k_direct_s2(const GemmArgs* __restrict__ 
   const int tiles_i = (nv2 + 15) / 16, tiles_j = (nc2 + 15) / 16;
   const int loc = item - d2off[sys];
   const int per = tiles_i * tiles_j;
-  const int p = loc / per, ti = (loc % per) / tiles_j, tj = loc % tiles_j;
-  const int4 pr = gld(g.pairs, p);
+  const int p = loc / per, ti = (loc % per) / tiles_j, tj = loc % tiles_j;  // p: pair of the chunk
+  const int4 pr = gld(g.pairs, (size_t)g.p0 + p);
   const int ka = pr.x, kb = pr.y;
   const int K = gbl(g.ng)[pr.z];
   const int ia = ti * 16 + (lane & 15), jb = tj * 16 + (lane & 15);
@@ -199,6 +202,18 @@ __global__ void k_zero_u32(unsigned* __restrict__ p, int n) {
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero_u32, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+__global__ void k_zero_f64(double* __restrict__ p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+hipError_t launch_zero_f64(double* p, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
 

@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void k_direct_s1_mx(const GemmArgs* __restrict
   const S1Tile tl = tiles[blockIdx.x];
   const GemmArgs g = gs[tl.sys];
   const int nv2 = g.nv * g.nv;
-  const int row_base = gbl(g.qstart)[tl.iq] * nv2;
+  const int row_base = (gbl(g.qstart)[tl.iq] - g.p0) * nv2;  // rows of the chunk
   const int rows = (gbl(g.qstart)[tl.iq + 1] - gbl(g.qstart)[tl.iq]) * nv2;
   const int K = gbl(g.ng)[tl.iq];
   const double2* A = g.RV + (size_t)row_base * g.ng_max;
@@ -67,9 +67,6 @@ __global__ __launch_bounds__(256) void k_direct_s1_mx(const GemmArgs* __restrict
       }
 }
 
-// Stage 2 per k pair: D[vv'][cc'] = sum_g Z[vv'][g] RC[cc'][g] (no conjugate),
-// operands split in registers.  The q = 0 head conj(rho_vv'(0)) W_00 rho_cc'(0)
-// is added in FP64.
 // W(q) split once per build and transposed so that the stage-1 tiles read
 // their B operand k-contiguous without converting it: one 32 x 32 tile of
 // (k, n) per workgroup through LDS.
@@ -104,10 +101,11 @@ __global__ __launch_bounds__(256) void k_split_w(const double2* __restrict__ W, 
   }
 }
 
-// The valence pair-density rows split, conjugated, into RVs[row][part][kpad]
-// (the A operand of stage 1): one thread per (row, k); a row of pair p holds
-// ng(q_p) values, the rest (and k >= ng_max) is written as zero, whatever the
-// row's tail in RV holds.
+// The valence pair-density rows of a chunk split, conjugated, into
+// RVs[row][part][kpad] (the A operand of stage 1): one thread per (row, k); a
+// row of pair p holds ng(q_p) values, the rest (and k >= ng_max) is written as
+// zero, whatever the row's tail in RV holds.  `pairs` starts at the chunk's
+// first pair.
 template <int P>
 __global__ __launch_bounds__(256) void k_split_rv(const double2* __restrict__ RV, const int4* __restrict__ pairs,
                                                   const int* __restrict__ ng, size_t nrows, int rows_per_pair,

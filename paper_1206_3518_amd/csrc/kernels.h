@@ -75,6 +75,8 @@ struct HTile {
   int i, j, sys, pad;
 };
 
+// The per-pair arrays (RV, RC, Z, RVs) hold one chunk of k pairs at a time:
+// row r of pair p of the chunk is row (p - p0) * nv^2 + r (nc^2 for RC).
 struct GemmArgs {
   // exchange:   H[S][S'] = cpref2 * sum_g conj(X[S][g]) X[S'][g], upper tiles
   // stage 1:    Z[r][n]  = sum_g conj(RV[r][g]) W[q][g][n], rows r of q group
@@ -90,8 +92,10 @@ struct GemmArgs {
   double2* Z;
   const double2* W;
   const int* ng;
-  const int* qstart;    // [Nk+1] first pair of each q group (pairs sorted by q)
-  const int4* pairs;    // (ka, kb, iq, m0p)
+  const int* qstart;    // [Nk+1] first pair of each q group of the chunk (global pair index;
+                        // the chunk's pairs are sorted by q), qstart[Nk] = end of the chunk
+  const int4* pairs;    // (ka, kb, iq, m0p), every pair of the system
+  int p0;               // first pair of the chunk
   const double* eps;
   int nv, nc, nb, npairs;
   int nt;               // nv * nc: rows of one k block
@@ -143,9 +147,10 @@ struct AdjArgs {
   double2* dWout;      // dW GEMM output (dW itself, or the raw gradient before projection)
   double2* dWfinal;    // projected dW
   double* deps;        // [Nk][nb]
-  const int4* pairs;
+  const int4* pairs;   // every pair of the system
   const int* ng;
-  const int* qstart;
+  const int* qstart;   // [Nk+1] q groups of the chunk (as in GemmArgs)
+  int p0;              // first pair of the chunk; RV, RC, T, Z hold the chunk's rows
   const int4* dwtiles; // (q, row tile, column tile, -)
   const int* qbar;     // [Nk] time-reversal partner of q
   const int* trmap;    // [Nk][ng_max] index of t - m_g in the sphere of qbar
@@ -181,14 +186,14 @@ hipError_t launch_validate_u_tr(const double2* u, const int* ktr, int nk, int nb
                                 unsigned long long* wstat, hipStream_t st);
 
 // Pair densities of the time-reversal images of computed k pairs.  Item
-// (dst, src, mode, sys): mode 0, rho_dst[ab][g] = conj(rho_src[ab][trmap[q_dst][g]]);
+// (dst, src, q_dst << 1 | mode, sys), dst and src pairs of the current chunk
+// (rows local to it): mode 0, rho_dst[ab][g] = conj(rho_src[ab][trmap[q_dst][g]]);
 // mode 1, rho_dst[a nB + b][g] = rho_src[b nB + a][g].  kind 1 fills the
 // valence pair densities, kind 2 the conduction ones.
 struct TrArgs {
   double2* rv;
   double2* rc;
   const int* ng;
-  const int4* pairs;
   const int* trmap;
   int ng_max, nv, nc;
 };
@@ -210,7 +215,21 @@ hipError_t launch_spectrum(int ns, int nlam, int nq, const double* E, const doub
                            double nk_omega, int nw, double w0, double w1, double eta, double* t2, double* eps2,
                            hipStream_t st);
 
-hipError_t launch_adjoint(const AdjArgs& a, int precision, int ndw_tiles, bool project, hipStream_t st);
+// Haydock recursion: niter steps of the Lanczos recurrence from conj(d_p)
+// for nq <= kMaxQhat polarisations (H [ns][ns] eV, d [nq][ns] Hartree units),
+// coefficients into coef [nq][niter][2] (a_j, b_j in eV), then eps2 on nw
+// points of [w0, w1] (eV) with half width eta (eV).  V0, V1, Y: nq * ns
+// complex each; norm2: nq doubles.
+hipError_t launch_haydock(int ns, const double2* H, const double2* d, int nq, int niter, double nk_omega, int nw,
+                          double w0, double w1, double eta, double* eps2, double* coef, double2* V0, double2* V1,
+                          double2* Y, double* norm2, hipStream_t st);
+// T (over Z) and the dW contraction of one chunk, added into dWout (zeroed
+// before the first chunk by launch_zero_f64); has_q0: the chunk holds pairs
+// of q = 0 (whose FP64 head entry the mixed precisions add separately)
+hipError_t launch_adjoint(const AdjArgs& a, int precision, int ndw_tiles, bool has_q0, hipStream_t st);
+// after the last chunk: the projection of dW (if asked) and dL/de
+hipError_t launch_adjoint_finish(const AdjArgs& a, bool project, hipStream_t st);
+hipError_t launch_zero_f64(double* p, size_t n, hipStream_t st);
 // dL/drho_cc' from Z (run before launch_adjoint overwrites Z with T)
 hipError_t launch_adj_drc(const AdjArgs& a, hipStream_t st);
 // dL/drho_vv' from T (after launch_adjoint)

@@ -13,14 +13,15 @@
 
 namespace bse {
 
-// One workgroup per item: every band pair row of the destination pair.
+// One workgroup per item: every band pair row of the destination pair (both
+// pairs of the current chunk).
 __global__ void __launch_bounds__(256) k_tr_fill(const TrArgs* __restrict__ as, const int4* __restrict__ items,
                                                  int kind) {
   const int4 it = items[blockIdx.x];
   const TrArgs a = as[it.w];
   const int n = kind == 1 ? a.nv : a.nc;
   const int ngm = a.ng_max;
-  const int q = gld(a.pairs, it.x).z;
+  const int q = it.z >> 1, mode = it.z & 1;
   const int ngq = gbl(a.ng)[q];
   const size_t rows = (size_t)n * n;
   const double2* src = (kind == 1 ? a.rv : a.rc) + (size_t)it.y * rows * ngm;
@@ -30,7 +31,7 @@ __global__ void __launch_bounds__(256) k_tr_fill(const TrArgs* __restrict__ as, 
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
     const int r = e / ngq, g = e - r * ngq;
     double2 v;
-    if (it.z == 0) {
+    if (mode == 0) {
       v = gld(src, (size_t)r * ngm + map[g]);
       v.y = -v.y;
     } else {

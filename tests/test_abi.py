@@ -108,3 +108,22 @@ def test_workspace_size_and_host_errors():
     kp = np.array([[0, s.nk]], dtype=np.int32)
     assert L.bse_pair_density(ctypes.byref(st), 1, kp.ctypes.data, 1, None, out, ctypes.c_void_p(0x1000), n,
                               None) == -1
+
+
+def test_chunk_budget_bounds_the_workspace():
+    """The per-pair arrays hold one chunk of k pairs: a smaller budget gives a
+    smaller workspace; the default comes back with 0."""
+    P, L = _lib()
+    s = B.make_config(0)
+    st, keep = _fake_struct(P, s)
+    n_default = L.bse_workspace_size(ctypes.byref(st), 1, 0, 0)
+    assert L.bse_set_chunk_budget(64 << 10) == 0
+    try:
+        n_small = L.bse_workspace_size(ctypes.byref(st), 1, 0, 0)
+    finally:
+        assert L.bse_set_chunk_budget(0) == 0
+    per_pair = 16 * s.ng_max * (2 * s.nv ** 2 + s.nc ** 2)
+    npairs = s.nk * (s.nk + 1) // 2
+    assert n_small < n_default
+    assert n_default - n_small >= per_pair * (npairs // 2)
+    assert L.bse_workspace_size(ctypes.byref(st), 1, 0, 0) == n_default

@@ -128,20 +128,30 @@ def test_adjoint_finite_differences_on_gpu_build():
 
 
 @pytest.mark.parametrize("prec", ["split_fp32", "bf16x3"])
-def test_mixed_adjoint_close_to_fp64(prec):
+def test_mixed_adjoint_against_oracle(prec):
+    """The mixed-precision dW contraction against the oracle's adjoint (both
+    projected), and against the FP64 GPU adjoint; the q = 0 head entry stays
+    FP64."""
     import paper_1206_3518_amd as P
     import torch
     s = B.make_config(1)
     d = P.DeviceSystem(s)
     H = P.build_H(d).cpu().numpy()
     e, x = np.linalg.eigh(H)
-    G = torch.from_numpy(np.outer(x[:, 0], np.conj(x[:, 0]))).cuda()
+    Gn = np.outer(x[:, 0], np.conj(x[:, 0]))
+    G = torch.from_numpy(Gn).cuda()
     a, _ = P.bse_build_H_backward(d, G, precision="fp64")
     b, _ = P.bse_build_H_backward(d, G, precision=prec)
+    bp, deps = P.bse_build_H_backward(d, G, precision=prec, flags=P.BSE_PROJECT_DW)
     torch.cuda.synchronize()
+    rW, reps = O.adjoint(s, Gn)
+    pr = project(s, rW)
+    bar = 1e-5 if prec == "split_fp32" else 1e-4
+    err = np.abs(bp.cpu().numpy() - pr).max() / np.abs(pr).max()
     rel = (a - b).abs().max().item() / a.abs().max().item()
-    _say(f"{prec} adjoint: max relative deviation from FP64 {rel:.2e}")
-    assert rel <= (1e-5 if prec == "split_fp32" else 1e-4)
+    _say(f"{prec} adjoint: projected vs oracle {err:.2e}, vs FP64 GPU {rel:.2e} (relative to max|dW|)")
+    assert err <= bar and rel <= bar
+    assert np.abs(deps.cpu().numpy() - reps).max() <= 1e-12
     assert torch.equal(a[0, 0, 0], b[0, 0, 0]) or abs((a[0, 0, 0] - b[0, 0, 0]).item()) <= 1e-14 * abs(a[0, 0, 0].item())
 
 

@@ -8,6 +8,7 @@ import pytest
 
 import bse_synth as B
 import oracle as O
+from bars import fp64_h_bar
 
 pytestmark = pytest.mark.gpu
 
@@ -53,7 +54,7 @@ def test_batch_equals_single_builds_and_oracle(persist):
         ref = O.build_H(s)
         err = np.abs(d.H.cpu().numpy() - ref).max()
         _say(f"  system {i}: max|dH| vs oracle = {err:.3e}")
-        assert err <= 1e-12 * max(np.abs(ref).max(), 1.0)
+        assert err <= fp64_h_bar(ref)
 
 
 def test_hbn_batch_fp64_and_split_fp32():
@@ -63,7 +64,7 @@ def test_hbn_batch_fp64_and_split_fp32():
     devs = [P.DeviceSystem(s) for s in systems]
     _say(f"h-BN batch: grid {systems[0].grid}, meshes {[s.kmesh for s in systems]}, "
          f"ng_max {[s.ng_max for s in systems]}")
-    ws = P.workspace(P.bse_workspace_size(devs))
+    ws = P.workspace(max(P.bse_workspace_size(devs, p) for p in (P.BSE_FP64, P.BSE_SPLIT_FP32)))
     P.bse_build_H(devs, P.BSE_FP64, P.BSE_PERSISTENT, ws)
     torch.cuda.synchronize()
     H64 = [d.H.clone() for d in devs]
@@ -71,7 +72,7 @@ def test_hbn_batch_fp64_and_split_fp32():
         ref = O.build_H(s)
         err = np.abs(h.cpu().numpy() - ref).max()
         _say(f"  system {i}: FP64 max|dH| vs oracle = {err:.3e}")
-        assert err <= 1e-12 * max(np.abs(ref).max(), 1.0)
+        assert err <= fp64_h_bar(ref)
     P.bse_build_H(devs, P.BSE_SPLIT_FP32, P.BSE_PERSISTENT, ws)
     torch.cuda.synchronize()
     for i, (d, h) in enumerate(zip(devs, H64)):
