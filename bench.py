@@ -19,7 +19,11 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"hbm_GBps": 8000.0, "fp64_TFLOPs": 78.6, "fp32_TFLOPs": 157.3, "bf16_TFLOPs": 2500.0}
+PEAK = {"hbm_GBps": 8000.0, "fp64_TFLOPs": 78.6, "fp32_TFLOPs": 157.3, "bf16_TFLOPs": 2500.0,
+        # FP32 vector arithmetic without the packed forms (which this build
+        # leaves out): 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz, the
+        # FP64 vector rate
+        "fp32_valu_unpacked_TFLOPs": 78.6}
 DTYPES = {"fp64": "f64", "split_fp32": "f32x3", "bf16x3": "bf16x3"}
 
 
@@ -28,6 +32,16 @@ def pd_flops(grid):
     N-point grid plus 6 N for the conjugate product."""
     n = int(np.prod(grid))
     return 5.0 * n * math.log2(n) + 6.0 * n
+
+
+def _pair_q(s):
+    """q index of every pair k <= k'."""
+    n = np.array(s.kmesh)
+    idx = np.arange(s.nk)
+    trip = np.stack([idx // (n[1] * n[2]), (idx // n[2]) % n[1], idx % n[2]], axis=1)
+    ka, kb = np.triu_indices(s.nk)
+    r = (trip[kb] - trip[ka]) % n
+    return (r[:, 0] * n[1] + r[:, 1]) * n[2] + r[:, 2]
 
 
 def gemm_flops(s):
@@ -54,16 +68,14 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel_digest, per_launch_units):
-    """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", "pair_density_si32_traffic.json")
+def profile_record(name, kernel_digest):
+    """A committed counter summary (profiles/<name>.json), if it was taken on
+    the current kernel source."""
+    p = os.path.join(ROOT, "profiles", name + ".json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if d.get("kernel_digest") != kernel_digest:
-        return None
-    return d.get("bytes_per_launch")
+    return d if d.get("kernel_digest") == kernel_digest else None
 
 
 def cpu_baseline(s, target_s=35.0):
@@ -221,6 +233,10 @@ def main():
                     help="FP32 pair densities in the timed run (with --precision split_fp32 or bf16x3)")
     ap.add_argument("--no-time-reversal", action="store_true",
                     help="skip the run on time-reversal symmetric inputs with BSE_TIME_REVERSAL")
+    ap.add_argument("--no-haydock", action="store_true", help="skip the Haydock spectrum leg")
+    ap.add_argument("--kmesh", type=int, default=0,
+                    help="with --config 2: an n x n x n k mesh instead of 8 x 8 x 8 (not the headline workload)")
+    ap.add_argument("--haydock-steps", type=int, default=500)
     ap.add_argument("--gradcheck", action="store_true",
                     help="instead of timing: finite differences of the lowest exciton energy vs the adjoint")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -237,7 +253,12 @@ def main():
     import bse_synth as B
     import paper_1206_3518_amd as P
 
-    made = B.make_config(args.config)
+    if args.kmesh and args.config == 2:
+        # the Si-like workload on a denser n x n x n mesh (N_S = 16 n^3)
+        made = B.make_config(2, kmesh=(args.kmesh,) * 3)
+        made.name = f"si-fcc32-k{args.kmesh}-b4x4"
+    else:
+        made = B.make_config(args.config)
     systems = made if isinstance(made, list) else [made]
     devs = [P.DeviceSystem(s, device="cuda:0") for s in systems]
     prec = P.PRECISIONS[args.precision]
@@ -279,34 +300,60 @@ def main():
                 "exchange_useful_TFLOPs": ex_flops / ex / 1e12}
 
     # dominant kernel: the pair-density kernel over the direct term's band pairs
-    # (one launch per band kind, vv and cc, covering every system)
+    # (vv and cc launches, one per chunk of k pairs and kind, covering every system)
     grid = systems[0].grid
     pd_ms = stages["pd_vv"][0] + stages["pd_cc"][0]
     pd_n = stages["pd_vv"][1] + stages["pd_cc"][1]
-    units = sum(s.nk * (s.nk + 1) // 2 * (s.nv * s.nv + s.nc * s.nc) / 2.0 for s in systems)  # per launch
+    launches_per_step = pd_n / args.steps
+    units_step = sum(s.nk * (s.nk + 1) // 2 * (s.nv * s.nv + s.nc * s.nc) for s in systems)
+    units = units_step / launches_per_step  # pair densities per launch
     avg_s = pd_ms / pd_n / 1e3
     achieved = pd_flops(grid) * units / avg_s / 1e12
+    # algorithmic bytes of a step: every valence and conduction grid read once
+    # per launch that needs it, and every sphere row written once
+    nr = int(np.prod(grid))
+    rows_bytes = sum(16.0 * (s.nv * s.nv + s.nc * s.nc) * float(np.sum(
+        np.bincount(_pair_q(s), minlength=s.nk) * s.ng)) for s in systems)
+    u_bytes = sum(16.0 * s.nk * (s.nv + s.nc) * nr for s in systems) * (launches_per_step / 2.0)
+    bytes_launch = (rows_bytes + u_bytes) / launches_per_step
     digest = kernel_source_digest()
     def line_planes(n2, n3):
         return n2 <= 32 and n3 <= 32 and n2 % 2 == 0 and n3 % 2 == 0
     line = line_planes(grid[1], grid[2]) or line_planes(grid[0], grid[1])  # directly or in the rotated frame
     f32 = args.fp32_pairdens and line
-    peak = PEAK["fp32_TFLOPs"] if f32 else PEAK["fp64_TFLOPs"]
+    # FP32 pair densities run on VALU FP32 without packed instructions
+    peak = PEAK["fp32_valu_unpacked_TFLOPs"] if f32 else PEAK["fp64_TFLOPs"]
     kname = "k_pair_density_line_f32" if f32 else "k_pair_density_line" if line else "k_pair_density"
+    prof = profile_record("pair_density_si32_counters", digest) if args.config == 2 and not f32 else None
     roofline = {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak,
-                "traffic": traffic_from_profile(digest, units) if args.config == 2 and not f32 else None,
-                "avg_launch_ms": pd_ms / pd_n, "flops_per_launch": pd_flops(grid) * units, "kernel_digest": digest}
+                "frac": achieved / peak, "traffic": None,
+                "achieved_is": "nominal FFT flops (5 N log2 N + 6 N per pair density) / launch time",
+                "avg_launch_ms": pd_ms / pd_n, "launches_per_step": launches_per_step,
+                "flops_per_launch": pd_flops(grid) * units, "kernel_digest": digest,
+                "algorithmic_bytes_per_launch": bytes_launch,
+                "hbm_GBps_algorithmic": bytes_launch / avg_s / 1e9,
+                "hbm_frac_algorithmic": bytes_launch / avg_s / 1e9 / PEAK["hbm_GBps"]}
+    if prof is not None:
+        # executed arithmetic from the VALU counters (64 lanes per instruction,
+        # FMA = 2), and HBM bytes from FETCH_SIZE / WRITE_SIZE (calibrated)
+        ex = prof["f64_flops_per_step"] / launches_per_step
+        roofline["executed_flops_per_launch"] = ex
+        roofline["executed_TFLOPs"] = ex / avg_s / 1e12
+        roofline["executed_frac"] = ex / avg_s / 1e12 / peak
+        if prof.get("bytes_per_step"):
+            roofline["traffic"] = prof["bytes_per_step"] / launches_per_step
+            roofline["traffic_over_algorithmic"] = roofline["traffic"] / bytes_launch
 
     if len(systems) == 1:
         s = systems[0]
         config = {"workload": s.name, "ns": s.ns, "grid": list(s.grid), "kmesh": list(s.kmesh), "nv": s.nv,
-                  "nc": s.nc, "ng_max": s.ng_max, "precision": args.precision, "parallelism": "single-gpu"}
+                  "nc": s.nc, "ng_max": s.ng_max, "precision": args.precision, "parallelism": "single-gpu",
+                  "workspace_GB": ws.numel() / 1e9}
     else:
         config = {"workload": f"hbn-batch{len(systems)}", "systems": len(systems), "grid": list(grid),
                   "kmeshes": [list(s.kmesh) for s in systems], "ns": [s.ns for s in systems],
                   "ng_max": [s.ng_max for s in systems], "nv": systems[0].nv, "nc": systems[0].nc,
-                  "precision": args.precision, "parallelism": "single-gpu"}
+                  "precision": args.precision, "parallelism": "single-gpu", "workspace_GB": ws.numel() / 1e9}
     if tuning is not None:
         config["autotune_candidates_ms"] = {
             (f"persistent/{c['wg_per_cu']}" if c["persistent"] else f"static/k{c['ktile']}"): round(c["pd_ms"], 3)
@@ -323,6 +370,8 @@ def main():
            "stage_ms": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
            "gemm": gemm_report(stages, args.precision),
            "wall_s": wall, "roofline": roofline}
+    if not args.no_haydock and len(systems) == 1:
+        out["haydock"] = haydock_leg(P, devs[0], systems[0], args.haydock_steps)
     if not args.no_mixed and args.precision == "fp64":
         H64 = [d.H.clone() for d in devs]
         kscale = max((h - torch.diag(torch.diag(h))).abs().max().item() for h in H64)
@@ -370,6 +419,42 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(systems[0])
     print(json.dumps(out))
+
+
+def haydock_leg(P, d, s, niter):
+    """The absorption spectrum of the H just built without its eigenpairs: the
+    Haydock recursion (niter Lanczos steps, one pass over H per step for the
+    three polarisations together) against the eigenpair route (GPU eigensolver
+    + bse_spectrum), timed with HIP events on the current stream."""
+    import torch
+    st = torch.cuda.current_stream()
+    qs = ([1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0])
+    dip = P.bse_transition_dipoles(d, qs)
+    ws = P.workspace(P.lib().bse_haydock_workspace(s.ns, len(qs), niter), d.device)
+    args = (d.H, dip, s.nk, s.omega_cell)
+    P.bse_haydock_spectrum(*args, 8, 1001, 0.0, 10.0, 0.1, ws=ws)  # warm-up
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    torch.cuda.synchronize()
+    e0.record(st)
+    eps_h = P.bse_haydock_spectrum(*args, niter, 1001, 0.0, 10.0, 0.1, ws=ws)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms_h = e0.elapsed_time(e1)
+    per = ms_h / niter
+    out = {"steps": niter, "polarisations": len(qs), "ms": ms_h, "ms_per_step": per,
+           "H_GBps_per_step": 16.0 * s.ns * s.ns / (per / 1e3) / 1e9}
+    if s.ns <= 16384:  # the eigenpair route needs the dense eigensolver
+        e0.record(st)
+        E, A = torch.linalg.eigh(d.H)
+        eps_e = P.bse_spectrum(E, A, dip, s.nk, s.omega_cell, 1001, 0.0, 10.0, 0.1)
+        e2.record(st)
+        torch.cuda.synchronize()
+        ms_e = e0.elapsed_time(e2)
+        out.update({"eigenpair_route_ms": ms_e, "speedup_vs_eigenpairs": ms_e / ms_h,
+                    "max_rel_diff_vs_eigenpair_spectrum":
+                        (eps_h - eps_e).abs().max().item() / eps_e.abs().max().item()})
+        del E, A
+    return out
 
 
 def bandlimited_leg(P, args, flags):

@@ -295,6 +295,19 @@ def make_system(cell, grid, kmesh, nv, nc, ecut, *, coulomb_kind="bulk", slab_L=
                   u=u, eps=eps, W=W, seed=seed)
 
 
+def coulomb_table(sys: System) -> np.ndarray:
+    """v(q + G) on the sphere of every q, [Nk][ng_max] (4 pi inside; bulk or
+    the slab's truncated form; zero at q = 0, G = 0 and in the padding): the
+    bare interaction that the screening turns into W."""
+    b = reciprocal(sys.cell)
+    out = np.zeros((sys.nk, sys.ng_max))
+    for iq in range(sys.nk):
+        g = sys.ng[iq]
+        p = q_vector(sys.cell, sys.kmesh, iq)[None, :] + sys.gvec[iq, :g] @ b
+        out[iq, :g] = coulomb(p, sys.coulomb, sys.slab_L)
+    return out
+
+
 def k_partner(kmesh, k: int):
     """(kbar, K): kbar the mesh index of -k, K the integer triplet with
     -k = kbar - K in units of the mesh (each entry 0 or 1)."""

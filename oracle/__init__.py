@@ -373,3 +373,48 @@ def haydock_spectrum(H, d, pref, w, m):
     a, b = lanczos(H, v, m)
     g = continued_fraction(a, b, grid + 1j * eta)
     return pref * np.vdot(v, v).real * (-np.imag(g))
+
+
+def screened_interaction(sys, vq, head):
+    """Static RPA screened interaction W(q) on the spheres of ``sys`` from its
+    nv occupied and nc empty bands (Eq. chi0_GG at omega = 0 with occupations
+    1 and 0, Eq. epsilon_-1 with the RPA kernel, Sec. III.A for W):
+      chi0_GG'(q) = (2 / Omega) sum_k sum_{n,n'} (f_nk - f_n'k+q) n(G) conj(n(G')) / (e_nk - e_n'k+q),
+      n = n_{nk,n'k+q} (the pair density of Sec. II.B), Omega = Nk Omega_cell,
+      eps_GG' = delta_GG' - v^1/2(q+G) chi0_GG' v^1/2(q+G'),
+      W_GG' = v^1/2(q+G) [eps^-1]_GG' v^1/2(q+G').
+    The n, n' sum runs over (occupied, empty) and (empty, occupied) pairs, the
+    only ones with f_nk != f_n'k+q.  vq [Nk][ng_max]: v(q+G) on each sphere
+    (4 pi inside; the entry of G = 0 at q = 0 is not used).  At q = 0 the
+    G = 0 row and column are left out of eps; W_00(0) = head and the wings are
+    zero (the divergent head of Sec. II.C is replaced by a given value).
+    Energies in eV, W in the units of v.  Returns W [Nk][ng_max][ng_max]."""
+    nk, nv, nc = sys.nk, sys.nv, sys.nc
+    n = np.array(sys.kmesh)
+    omega = nk * sys.omega_cell
+    W = np.zeros((nk, sys.ng_max, sys.ng_max), dtype=np.complex128)
+    for q in range(nk):
+        qv = np.array([q // (n[1] * n[2]), (q // n[2]) % n[1], q % n[2]])
+        items, wts = [], []
+        for k in range(nk):
+            kv = np.array([k // (n[1] * n[2]), (k // n[2]) % n[1], k % n[2]])
+            t = (kv + qv) % n
+            kq = int((t[0] * n[1] + t[1]) * n[2] + t[2])
+            for v in range(nv):
+                for c in range(nc):
+                    # occupied at k, empty at k + q
+                    items.append((k, v, kq, nv + c))
+                    wts.append(1.0 / ((sys.eps[k, v] - sys.eps[kq, nv + c]) / HARTREE_EV))
+                    # empty at k, occupied at k + q
+                    items.append((k, nv + c, kq, v))
+                    wts.append(-1.0 / ((sys.eps[k, nv + c] - sys.eps[kq, v]) / HARTREE_EV))
+        ng = sys.ng[q]
+        rho = pair_density_items(sys, items)[:, :ng]
+        chi0 = (2.0 / omega) * (rho.T * np.array(wts)) @ np.conj(rho)
+        sv = np.sqrt(vq[q, :ng])
+        g0 = 1 if q == 0 else 0
+        e = np.eye(ng - g0) - sv[g0:, None] * chi0[g0:, g0:] * sv[None, g0:]
+        W[q, g0:ng, g0:ng] = sv[g0:, None] * np.linalg.inv(e) * sv[None, g0:]
+        if q == 0:
+            W[0, 0, 0] = head
+    return W

@@ -27,7 +27,16 @@ def _say(msg):
 def case():
     g = json.load(open(GOLD))
     s = B.make_config(2)
-    assert s.digest() == g["inputs_digest"], "the seeded inputs changed since the record was written"
+    # the generator's factorisations round differently between machines: the
+    # inputs must agree with the record's to rounding, not bit for bit
+    f = g["inputs_fingerprint"]
+    for key, got in (("u_sum", [s.u.sum().real, s.u.sum().imag]), ("W_sum", [s.W.sum().real, s.W.sum().imag])):
+        assert np.allclose(got, f[key], rtol=1e-10, atol=1e-10 * f[key.replace("_sum", "_abs_sum")]
+                           if key == "W_sum" else 1e-9), key
+    assert abs(np.sum(np.abs(s.u) ** 4) - f["u_abs4_sum"]) <= 1e-10 * f["u_abs4_sum"]
+    assert abs(np.abs(s.W).sum() - f["W_abs_sum"]) <= 1e-10 * f["W_abs_sum"]
+    assert abs(s.eps.sum() - f["eps_sum"]) <= 1e-12 * abs(f["eps_sum"])
+    assert abs(s.vx.sum() - f["vx_sum"]) <= 1e-12 * abs(f["vx_sum"])
     return s, g
 
 
