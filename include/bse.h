@@ -300,6 +300,22 @@ int bse_haydock_spectrum(int ns, const double *H, const double *d, int nq, int n
 size_t bse_haydock_workspace(int ns, int nq, int niter);
 
 /*
+ * bse_spectrum without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments and result as bse_spectrum; the nlam
+ * partial results (one double per exciton) live in a static device array of
+ * BSE_NOALLOC_MAX_NLAM doubles (8 MiB) that each GPU the library runs on holds
+ * until the process ends.  nlam > BSE_NOALLOC_MAX_NLAM -> BSE_ERR_WORKSPACE
+ * (nothing enqueued).  Calls no allocating routine.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be ordered by the caller.
+ */
+#define BSE_NOALLOC_MAX_NLAM 1048576
+int bse_spectrum_noalloc(int ns, int nlam, const double *E, const double *A, const double *d, int nq, int nk,
+                         double omega_cell, int nw, double w0_eV, double w1_eV, double eta_eV, double *eps2,
+                         void *stream);
+
+/*
  * Per-stage GPU timing of bse_build_H.  While enabled, every kernel launch of
  * bse_build_H is bracketed by two hipEvents recorded on the call's stream.
  * bse_profile_read waits for the recorded events, adds their elapsed times

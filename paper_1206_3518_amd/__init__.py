@@ -47,7 +47,7 @@ class bse_system(ctypes.Structure):
 
 SYMBOLS = ["bse_workspace_size", "bse_pair_density", "bse_build_H", "bse_build_H_backward",
            "bse_autotune", "bse_autotune_last", "bse_transition_dipoles", "bse_transition_dipoles_workspace",
-           "bse_spectrum", "bse_haydock_spectrum", "bse_haydock_workspace", "bse_profile", "bse_profile_read", "bse_set_chunk_budget", "bse_release_host_state",
+           "bse_spectrum", "bse_haydock_spectrum", "bse_haydock_workspace", "bse_spectrum_noalloc", "bse_profile", "bse_profile_read", "bse_set_chunk_budget", "bse_release_host_state",
            "bse_last_error"]
 STAGES = ["vscale", "pd_exch", "pd_vv", "pd_cc", "exchange", "direct1", "direct2", "mirror", "rotate", "tr_fill", "to_f32", "split_w"]
 
@@ -82,6 +82,8 @@ def lib():
         L.bse_haydock_spectrum.restype = I
         L.bse_haydock_workspace.argtypes = [I, I, I]
         L.bse_haydock_workspace.restype = S
+        L.bse_spectrum_noalloc.argtypes = [I, I, P, P, P, I, I, D, I, D, D, D, P, P]
+        L.bse_spectrum_noalloc.restype = I
         L.bse_set_chunk_budget.argtypes = [S]
         L.bse_set_chunk_budget.restype = I
         L.bse_release_host_state.argtypes = []
@@ -406,6 +408,23 @@ def absorption_haydock(system: DeviceSystem, H, qhats=((1, 0, 0), (0, 1, 0), (0,
     dipoles and the Haydock recursion in the library."""
     d = bse_transition_dipoles(system, qhats)
     return bse_haydock_spectrum(H, d, system.nk, system.omega_cell, niter, nw, w0, w1, eta)
+
+
+NOALLOC_MAX_NLAM = 1048576
+
+
+def bse_spectrum_noalloc(E, A, d, nk, omega_cell, nw, w0_eV, w1_eV, eta_eV, eps2=None, stream=None):
+    """bse_spectrum without a workspace (the library's static device scratch);
+    eps2 may be given so that the call allocates nothing."""
+    import torch
+    d = d.reshape(-1, A.shape[0])
+    ns, nlam = A.shape
+    if eps2 is None:
+        eps2 = torch.empty(nw, dtype=torch.float64, device=A.device)
+    _check(lib().bse_spectrum_noalloc(ns, nlam, _ptr(E), _ptr(A), _ptr(d), d.shape[0], int(nk), float(omega_cell),
+                                      int(nw), float(w0_eV), float(w1_eV), float(eta_eV), _ptr(eps2),
+                                      _stream(stream)))
+    return eps2
 
 
 def bse_release_host_state():

@@ -1253,6 +1253,15 @@ int spectrum_args(int ns, int nlam, const double* E, const double* A, const doub
 
 }  // namespace
 
+// Used by the variant of bse_spectrum without workspace (noalloc.hip).
+namespace bse {
+int api_fail(int code, const char* msg) { return fail(code, "%s", msg); }
+int api_spectrum_args(int ns, int nlam, const double* E, const double* A, const double* d, int nq, int nk,
+                      double omega_cell, int nw, double eta_eV, double* eps2) {
+  return spectrum_args(ns, nlam, E, A, d, nq, nk, omega_cell, nw, eta_eV, eps2);
+}
+}  // namespace bse
+
 extern "C" {
 
 size_t bse_workspace_size(const bse_system* sys, int nsys, int precision, int flags) {
