@@ -220,12 +220,13 @@ typedef struct bse_tuning {
     int persistent;  /* 1: persistent work-queue dispatch of the pair densities   */
     int ktile;       /* k tile of the pair-density dispatch order                 */
     int wg_per_cu;   /* persistent dispatch: workgroups per compute unit          */
-    float pd_ms;     /* measured valence-valence pair-density launch, ms          */
+    float pd_ms;     /* measured pair-density launch (first chunk), ms            */
 } bse_tuning;
 
 /*
  * Autotuner (for callers that build the same batch shape many times).  Times
- * the dominant launch (valence-valence pair densities) of this batch under
+ * the dominant launch (the valence and conduction pair densities of the first
+ * chunk of k pairs) of this batch under
  * static dispatch with k tiles 4, 8, 16 and persistent dispatch with 1..4
  * workgroups per CU, and keeps the fastest for every later bse_build_H of the
  * same signature in this process (BSE_PERSISTENT still forces persistent
@@ -278,6 +279,32 @@ int bse_spectrum(int ns, int nlam, const double *E, const double *A, const doubl
                  size_t ws_bytes, void *stream);
 
 /*
+ * Static RPA screened interaction W(q) of bse_build_H from the wave
+ * functions (Sec. II.B: Eq. chi0_GG at omega = 0 and Eq. epsilon_-1 with the
+ * RPA kernel; Sec. III.A: W_GG' = 4 pi eps^-1_GG' / (|q+G||q+G'|)):
+ *   chi0_GG'(q) = (2/Omega) sum_k sum_{n,n'} (f_nk - f_n'k+q) n(G) conj(n(G')) / (e_nk - e_n'k+q),
+ *   n = n_{nk,n'k+q} (pair density), Omega = Nk * Omega_cell, f = 1 for the
+ *   nv occupied and 0 for the nc empty bands of sys (both orders of an
+ *   occupied-empty pair enter),
+ *   eps = 1 - v^1/2 chi0 v^1/2 (Hermitian positive definite),
+ *   W(q) = v^1/2 eps^-1 v^1/2, with v^1/2 = sqrt(vq[q][G]).
+ * At q = 0 the G = 0 row and column are left out of eps; W[0][0][0] = head
+ * and the wings W[0][0][G], W[0][G][0] are zero (the divergent head is
+ * integrated out in the paper; here it is a given value).
+ * sys: grid, kmesh, nv, nc, omega_cell, ng_max, ng, gvec, u and eps as for
+ * bse_build_H (empty bands at least 1 meV above every occupied one); W, vx
+ * and H are not read.  vq: DEVICE [Nk][ng_max], v(q+G) on each sphere (4 pi
+ * inside; bulk or truncated; the entry of G = 0 at q = 0 is not read).
+ * W: DEVICE [Nk][ng_max][ng_max] complex out, zero past ng(q); it is the
+ * input W of bse_build_H for the same spheres.  ws:
+ * bse_screening_workspace(sys) bytes (pair densities of a chunk of q, sized
+ * by bse_set_chunk_budget).  FP64 throughout.
+ */
+int bse_screening(const bse_system *sys, const double *vq, double head, double *W, void *ws, size_t ws_bytes,
+                  void *stream);
+size_t bse_screening_workspace(const bse_system *sys);
+
+/*
  * The spectrum of bse_spectrum without the eigenpairs of H, for Hamiltonians
  * too large to diagonalise: the resolvent of the appendix (Eq. resolvent,
  * Tamm-Dancoff) in the state v = conj(d_p) satisfies
@@ -325,8 +352,9 @@ int bse_spectrum_noalloc(int ns, int nlam, const double *E, const double *A, con
 enum bse_stage {
     BSE_STAGE_VSCALE = 0,   /* sqrt v(G) table                         */
     BSE_STAGE_PD_EXCH = 1,  /* pair densities n_{vk,ck}                 */
-    BSE_STAGE_PD_VV = 2,    /* pair densities n_{vk,v'k'}               */
-    BSE_STAGE_PD_CC = 3,    /* pair densities n_{ck,c'k'}               */
+    BSE_STAGE_PD_VV = 2,    /* pair densities n_{vk,v'k'} and n_{ck,c'k'}
+                               (one launch per chunk of k pairs)       */
+    BSE_STAGE_PD_CC = 3,    /* (no longer used: counted with PD_VV)    */
     BSE_STAGE_EXCHANGE = 4, /* exchange GEMM                            */
     BSE_STAGE_DIRECT1 = 5,  /* direct term, conj(rho_vv') W(q)          */
     BSE_STAGE_DIRECT2 = 6,  /* direct term contraction + diagonal       */

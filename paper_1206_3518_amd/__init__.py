@@ -47,7 +47,7 @@ class bse_system(ctypes.Structure):
 
 SYMBOLS = ["bse_workspace_size", "bse_pair_density", "bse_build_H", "bse_build_H_backward",
            "bse_autotune", "bse_autotune_last", "bse_transition_dipoles", "bse_transition_dipoles_workspace",
-           "bse_spectrum", "bse_haydock_spectrum", "bse_haydock_workspace", "bse_spectrum_noalloc", "bse_profile", "bse_profile_read", "bse_set_chunk_budget", "bse_release_host_state",
+           "bse_spectrum", "bse_screening", "bse_screening_workspace", "bse_haydock_spectrum", "bse_haydock_workspace", "bse_spectrum_noalloc", "bse_profile", "bse_profile_read", "bse_set_chunk_budget", "bse_release_host_state",
            "bse_last_error"]
 STAGES = ["vscale", "pd_exch", "pd_vv", "pd_cc", "exchange", "direct1", "direct2", "mirror", "rotate", "tr_fill", "to_f32", "split_w"]
 
@@ -78,6 +78,10 @@ def lib():
         L.bse_transition_dipoles_workspace.restype = S
         L.bse_spectrum.argtypes = [I, I, P, P, P, I, I, D, I, D, D, D, P, P, S, P]
         L.bse_spectrum.restype = I
+        L.bse_screening.argtypes = [P, P, D, P, P, S, P]
+        L.bse_screening.restype = I
+        L.bse_screening_workspace.argtypes = [P]
+        L.bse_screening_workspace.restype = S
         L.bse_haydock_spectrum.argtypes = [I, P, P, I, I, I, D, I, D, D, D, P, P, P, S, P]
         L.bse_haydock_spectrum.restype = I
         L.bse_haydock_workspace.argtypes = [I, I, I]
@@ -377,6 +381,24 @@ def bse_spectrum(E, A, d, nk, omega_cell, nw, w0_eV, w1_eV, eta_eV, ws=None, str
 def bse_set_chunk_budget(nbytes=0):
     """Bytes of per-pair arrays per chunk of k pairs (0: the library default)."""
     _check(lib().bse_set_chunk_budget(int(nbytes)))
+
+
+def bse_screening(system: DeviceSystem, vq, head, ws=None, stream=None):
+    """Static RPA W [Nk][ng_max][ng_max] (complex128, device) of ``system``'s
+    nv occupied and nc empty bands; vq [Nk][ng_max] the bare Coulomb table."""
+    import torch
+    vq = torch.as_tensor(np.ascontiguousarray(vq, dtype=np.float64)).to(system.device) \
+        if not isinstance(vq, torch.Tensor) else vq.contiguous()
+    st = system.struct()
+    if ws is None:
+        n = lib().bse_screening_workspace(ctypes.byref(st))
+        if n == 0:
+            raise BseError(-1, bse_last_error())
+        ws = workspace(n, system.device)
+    W = torch.empty((system.nk, system.ng_max, system.ng_max), dtype=torch.complex128, device=system.device)
+    _check(lib().bse_screening(ctypes.byref(st), _ptr(vq), float(head), _ptr(W), _ptr(ws), ws.numel(),
+                               _stream(stream)))
+    return W
 
 
 def bse_haydock_spectrum(H, d, nk, omega_cell, niter, nw, w0_eV, w1_eV, eta_eV, want_coef=False, ws=None,

@@ -10,7 +10,7 @@ OUT = os.path.join(HERE, "libbse.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["pair_density.hip", "gemm_f64.hip", "gemm_mixed.hip", "spectrum.hip", "backward.hip", "validate.hip",
-           "time_reversal.hip", "noalloc.hip", "haydock.hip", "bse_api.cpp"]
+           "time_reversal.hip", "noalloc.hip", "haydock.hip", "screening.hip", "bse_api.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # packed FP32 instructions are kept out of every kernel

@@ -216,7 +216,8 @@ struct Plan {
   size_t o_RVs = 0;  // conj(RV) split for the mixed stage 1: [rows][4][kpad] (mixed only)
 };
 
-int check_system(const bse_system* s) {
+// need_w: the build's inputs W and vx are required (not by the screening).
+int check_system(const bse_system* s, bool need_w = true) {
   if (!s) return fail(BSE_ERR_INVALID_ARG, "system pointer is NULL");
   for (int d = 0; d < 3; ++d) {
     if (s->grid[d] < 1 || s->grid[d] > 4096) return fail(BSE_ERR_SHAPE, "grid[%d] = %d out of range", d, s->grid[d]);
@@ -228,7 +229,8 @@ int check_system(const bse_system* s) {
   if (s->ng_max < 1 || s->ng_max > 1024) return fail(BSE_ERR_SHAPE, "ng_max = %d out of range (1..1024)", s->ng_max);
   if (!(s->omega_cell > 0.0)) return fail(BSE_ERR_INVALID_ARG, "omega_cell must be positive");
   if (!s->ng || !s->gvec) return fail(BSE_ERR_INVALID_ARG, "ng / gvec host tables are NULL");
-  if (!s->u || !s->eps || !s->W || !s->vx) return fail(BSE_ERR_INVALID_ARG, "a device input pointer is NULL");
+  if (!s->u || !s->eps || (need_w && (!s->W || !s->vx)))
+    return fail(BSE_ERR_INVALID_ARG, "a device input pointer is NULL");
   return BSE_OK;
 }
 
@@ -242,8 +244,8 @@ struct BatchOpts {
 };
 
 // Frame, spheres, windows, exchange jobs and time-reversal maps of one system.
-int make_geometry(const bse_system* s, Plan& P) {
-  int rc = check_system(s);
+int make_geometry(const bse_system* s, Plan& P, bool need_w = true) {
+  int rc = check_system(s, need_w);
   if (rc) return rc;
   P.rot = !pd_line_grid(s->grid[1], s->grid[2]) && pd_line_grid(s->grid[0], s->grid[1]) && s->grid[2] <= 256;
   if (P.rot) {
@@ -632,16 +634,18 @@ void set_tune(const std::string& key, const Tune& t) {
   g_tune.emplace_back(key, t);
 }
 
-// One chunk of a batch: the merged launch lists of every system's share.
+// One chunk of a batch: the merged launch lists of every system's share.  The
+// valence and conduction pair densities of a chunk are one launch: the jobs of
+// system i name argument set 2 i (valence rows) or 2 i + 1 (conduction rows).
 struct BatchChunk {
-  std::vector<PdJob> jv, jc;
+  std::vector<PdJob> jd;
   std::vector<int4> fill;
   std::vector<S1Tile> s1;
   std::vector<int> d2off;  // [nsys + 1]
   int d2n = 0;
   std::vector<int4> dwt, rvt;  // single system (backward)
   bool has_q0 = false;         // single system (backward)
-  size_t o_jv = 0, o_jc = 0, o_fill = 0, o_s1 = 0, o_d2off = 0, o_gargs = 0, o_dwt = 0, o_rvt = 0;
+  size_t o_jd = 0, o_fill = 0, o_s1 = 0, o_d2off = 0, o_gargs = 0, o_dwt = 0, o_rvt = 0;
 };
 
 // A batch of systems that share (N2, N3): per-system plans and workspace
@@ -658,7 +662,7 @@ struct Batch {
   bool pd32 = false;           // FP32 valence / conduction pair densities
   int np32 = 2;                // their planes per step: 4 when every window has F2 <= 16
   size_t lds32 = 0;            // their LDS bytes
-  size_t o_pdx = 0, o_pdv = 0, o_pdc = 0, o_jx = 0, o_xt = 0, o_mt = 0, o_tra = 0;
+  size_t o_pdx = 0, o_pdd = 0, o_jx = 0, o_xt = 0, o_mt = 0, o_tra = 0;
   size_t o_cnt = 0, tables = 0, total = 0;
 };
 
@@ -666,7 +670,7 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
   if (!sys || nsys < 1) return fail(BSE_ERR_INVALID_ARG, "no systems");
   B.tr = opt.tr;
   B.pd32 = opt.pd32;
-  if (nsys > 32767) return fail(BSE_ERR_INVALID_ARG, "too many systems");
+  if (nsys > 16383) return fail(BSE_ERR_INVALID_ARG, "too many systems");
   B.P.resize(nsys);
   // chunk count: the per-pair arrays of all systems over the budget
   double bytes = 0.0;
@@ -722,15 +726,15 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
   B.jx = dispatch_order(std::move(jx), tn.ktile);
   for (int c = 0; c < nc; ++c) {
     BatchChunk& K = B.C[c];
-    std::vector<PdJob> jv, jc;
+    std::vector<PdJob> jd;
     K.d2off.assign(nsys + 1, 0);
     for (int i = 0; i < nsys; ++i) {
       const Plan& P = B.P[i];
       K.d2off[i + 1] = K.d2off[i];
       if (c >= (int)P.ch.size()) continue;
       const Chunk& S = P.ch[c];
-      for (PdJob j : S.jv) jv.push_back((j.nab |= i << 16, j));
-      for (PdJob j : S.jc) jc.push_back((j.nab |= i << 16, j));
+      for (PdJob j : S.jv) jd.push_back((j.nab |= (2 * i) << 16, j));
+      for (PdJob j : S.jc) jd.push_back((j.nab |= (2 * i + 1) << 16, j));
       K.fill.insert(K.fill.end(), S.fill.begin(), S.fill.end());
       K.s1.insert(K.s1.end(), S.s1.begin(), S.s1.end());
       K.d2off[i + 1] += S.d2items;
@@ -741,8 +745,7 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
       }
     }
     K.d2n = K.d2off[nsys];
-    K.jv = dispatch_order(std::move(jv), tn.ktile);
-    K.jc = dispatch_order(std::move(jc), tn.ktile);
+    K.jd = dispatch_order(std::move(jd), tn.ktile);
   }
   // workspace: batch tables, then one region per system
   size_t o = 0;
@@ -752,16 +755,14 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
     return at;
   };
   B.o_pdx = put(nsys * sizeof(PdArgs));
-  B.o_pdv = put(nsys * sizeof(PdArgs));
-  B.o_pdc = put(nsys * sizeof(PdArgs));
+  B.o_pdd = put(2 * nsys * sizeof(PdArgs));
   B.o_jx = put(B.jx.size() * sizeof(PdJob));
   B.o_xt = put(B.xt.size() * sizeof(HTile));
   B.o_mt = put(B.mt.size() * sizeof(HTile));
   B.o_tra = put(opt.tr ? nsys * sizeof(TrArgs) : 0);
   for (BatchChunk& K : B.C) {
     K.o_gargs = put(nsys * sizeof(GemmArgs));
-    K.o_jv = put(K.jv.size() * sizeof(PdJob));
-    K.o_jc = put(K.jc.size() * sizeof(PdJob));
+    K.o_jd = put(K.jd.size() * sizeof(PdJob));
     K.o_fill = put(K.fill.size() * sizeof(int4));
     K.o_s1 = put(K.s1.size() * sizeof(S1Tile));
     K.o_d2off = put(K.d2off.size() * sizeof(int));
@@ -862,7 +863,7 @@ int upload_batch(const Batch& B, const bse_system* sys, int precision, char* ws,
   auto cp = [&](size_t off, const void* src, size_t bytes) {
     if (bytes) std::memcpy(buf + off, src, bytes);
   };
-  std::vector<PdArgs> ax(nsys), av(nsys), ac(nsys);
+  std::vector<PdArgs> ax(nsys), ad(2 * nsys);
   std::vector<TrArgs> ta(B.tr ? nsys : 0);
   for (int i = 0; i < nsys; ++i) {
     const Plan& P = B.P[i];
@@ -871,10 +872,10 @@ int upload_batch(const Batch& B, const bse_system* sys, int precision, char* ws,
     ax[i] = a;
     ax[i].vscale = reinterpret_cast<const double*>(region + P.o_vs);
     ax[i].out = reinterpret_cast<double2*>(region + P.o_X);
-    av[i] = a;
-    av[i].out = reinterpret_cast<double2*>(region + P.o_RV);
-    ac[i] = a;
-    ac[i].out = reinterpret_cast<double2*>(region + P.o_RC);
+    ad[2 * i] = a;
+    ad[2 * i].out = reinterpret_cast<double2*>(region + P.o_RV);
+    ad[2 * i + 1] = a;
+    ad[2 * i + 1].out = reinterpret_cast<double2*>(region + P.o_RC);
     if (B.tr) {
       TrArgs& r = ta[i];
       r.rv = reinterpret_cast<double2*>(region + P.o_RV);
@@ -887,8 +888,7 @@ int upload_batch(const Batch& B, const bse_system* sys, int precision, char* ws,
     }
   }
   cp(B.o_pdx, ax.data(), nsys * sizeof(PdArgs));
-  cp(B.o_pdv, av.data(), nsys * sizeof(PdArgs));
-  cp(B.o_pdc, ac.data(), nsys * sizeof(PdArgs));
+  cp(B.o_pdd, ad.data(), 2 * nsys * sizeof(PdArgs));
   cp(B.o_jx, B.jx.data(), B.jx.size() * sizeof(PdJob));
   cp(B.o_xt, B.xt.data(), B.xt.size() * sizeof(HTile));
   cp(B.o_mt, B.mt.data(), B.mt.size() * sizeof(HTile));
@@ -901,8 +901,7 @@ int upload_batch(const Batch& B, const bse_system* sys, int precision, char* ws,
       ga[i].w_head_fp64 = precision != BSE_FP64;  // mixed: the q = 0 head of W is added in FP64
     }
     cp(K.o_gargs, ga.data(), nsys * sizeof(GemmArgs));
-    cp(K.o_jv, K.jv.data(), K.jv.size() * sizeof(PdJob));
-    cp(K.o_jc, K.jc.data(), K.jc.size() * sizeof(PdJob));
+    cp(K.o_jd, K.jd.data(), K.jd.size() * sizeof(PdJob));
     cp(K.o_fill, K.fill.data(), K.fill.size() * sizeof(int4));
     cp(K.o_s1, K.s1.data(), K.s1.size() * sizeof(S1Tile));
     cp(K.o_d2off, K.d2off.data(), K.d2off.size() * sizeof(int));
@@ -934,12 +933,12 @@ int persistent_grid(size_t lds, int njobs, int wg_per_cu) {
   return std::min(g, std::max(njobs, kXcds));
 }
 
-// One pair-density launch over the batch: kind 0 exchange (every k), 1 vv and
-// 2 cc (the pairs of chunk c).
+// One pair-density launch over the batch: kind 0 the exchange densities (every
+// k), kind 1 the valence and conduction densities of the pairs of chunk c.
 int run_pd(const Batch& B, char* ws, int kind, int c, const Tune& tn, hipStream_t st) {
-  const std::vector<PdJob>& jobs = kind == 0 ? B.jx : kind == 1 ? B.C[c].jv : B.C[c].jc;
-  const size_t o_args = kind == 0 ? B.o_pdx : kind == 1 ? B.o_pdv : B.o_pdc;
-  const size_t o_jobs = kind == 0 ? B.o_jx : kind == 1 ? B.C[c].o_jv : B.C[c].o_jc;
+  const std::vector<PdJob>& jobs = kind == 0 ? B.jx : B.C[c].jd;
+  const size_t o_args = kind == 0 ? B.o_pdx : B.o_pdd;
+  const size_t o_jobs = kind == 0 ? B.o_jx : B.C[c].o_jd;
   if (jobs.empty()) return BSE_OK;
   PdBatch b{};
   b.sys = reinterpret_cast<const PdArgs*>(ws + o_args);
@@ -947,7 +946,7 @@ int run_pd(const Batch& B, char* ws, int kind, int c, const Tune& tn, hipStream_
   b.njobs = (int)jobs.size();
   b.persist = tn.persist;
   b.cnt = reinterpret_cast<unsigned*>(ws + B.o_cnt) + (size_t)kind * kXcds * kQueueStride;
-  const int stage_id = kind == 0 ? BSE_STAGE_PD_EXCH : kind == 1 ? BSE_STAGE_PD_VV : BSE_STAGE_PD_CC;
+  const int stage_id = kind == 0 ? BSE_STAGE_PD_EXCH : BSE_STAGE_PD_VV;
   const bool f32 = B.pd32 && kind != 0;
   const size_t lds = f32 ? B.lds32 : B.lds;
   const int f32_planes = f32 ? B.np32 : 0;
@@ -1031,7 +1030,9 @@ int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& 
   for (int c = 0; c < (int)B.C.size(); ++c) {
     const BatchChunk& K = B.C[c];
     const GemmArgs* gs = reinterpret_cast<const GemmArgs*>(ws + K.o_gargs);
-    if ((rc = run_pd(B, ws, 1, c, tn, st)) || (rc = run_tr_fill(B, ws, 1, c, st))) return rc;
+    if ((rc = run_pd(B, ws, 1, c, tn, st)) || (rc = run_tr_fill(B, ws, 1, c, st)) ||
+        (rc = run_tr_fill(B, ws, 2, c, st)))
+      return rc;
     if (precision != BSE_FP64) {
       // the A operand of the mixed stage 1, split once
       for (int i = 0; i < nsys; ++i) {
@@ -1046,13 +1047,94 @@ int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& 
         }));
       }
     }
-    if ((rc = run_pd(B, ws, 2, c, tn, st)) || (rc = run_tr_fill(B, ws, 2, c, st))) return rc;
     const S1Tile* s1 = reinterpret_cast<const S1Tile*>(ws + K.o_s1);
     const int* d2off = reinterpret_cast<const int*>(ws + K.o_d2off);
     HIP_TRY(stage(BSE_STAGE_DIRECT1, st, [&] { return launch_direct_s1(gs, s1, (int)K.s1.size(), precision, st); }));
     HIP_TRY(stage(BSE_STAGE_DIRECT2, st, [&] { return launch_direct_s2(gs, d2off, nsys, K.d2n, st); }));
   }
   HIP_TRY(stage(BSE_STAGE_MIRROR, st, [&] { return launch_mirror(g0, mt, (int)B.mt.size(), st); }));
+  return BSE_OK;
+}
+
+// ------------------------------------------------------------ screening
+
+// Plan of bse_screening: chunks of q whose pair densities (2 nv nc rows per
+// k) fit the chunk budget, their jobs, pair table and HERK tiles.
+struct ScrPlan {
+  Plan G;                               // geometry of the system
+  std::vector<std::vector<int>> qs;     // q of each chunk
+  std::vector<std::vector<PdJob>> jobs; // per chunk, dispatch order
+  std::vector<std::vector<int4>> pk;    // per chunk: (k, k + q, q, -) per (q_local, k)
+  std::vector<std::vector<int4>> tiles; // per chunk: (q, row tile, column tile, q_local)
+  size_t o_gpack = 0, o_ng = 0, o_vq = 0, o_args = 0, o_ut = 0, o_Y = 0, total = 0;
+  std::vector<size_t> o_jobs, o_pk, o_tiles;
+  size_t tables = 0;
+  int maxq = 0;                         // q per chunk, largest
+};
+
+int make_screening_plan(const bse_system* s, ScrPlan& S) {
+  int rc = make_geometry(s, S.G, false);
+  if (rc) return rc;
+  const Plan& P = S.G;
+  const int nk = P.nk, nv = P.nv, nc = P.nc;
+  const size_t rows_q = (size_t)nk * 2 * nv * nc;
+  const size_t bytes_q = rows_q * P.ng_max * sizeof(double2);
+  if (rows_q * P.ng_max >= (size_t(1) << 31)) return fail(BSE_ERR_SHAPE, "pair densities of one q too large");
+  if (P.ng_max > 1024) return fail(BSE_ERR_SHAPE, "ng_max above 1024");
+  const int per_chunk = (int)std::max<size_t>(1, std::min<size_t>(nk, g_chunk_budget.load() / std::max<size_t>(bytes_q, 1)));
+  const int nchunk = (nk + per_chunk - 1) / per_chunk;
+  S.maxq = per_chunk;
+  S.qs.assign(nchunk, {});
+  S.jobs.assign(nchunk, {});
+  S.pk.assign(nchunk, {});
+  S.tiles.assign(nchunk, {});
+  const int* n = s->kmesh;
+  const int T2 = (P.ng_max + 63) / 64;
+  for (int c = 0; c < nchunk; ++c) {
+    std::vector<PdJob> jobs;
+    for (int q = c * per_chunk; q < std::min(nk, (c + 1) * per_chunk); ++q) {
+      const int ql = (int)S.qs[c].size();
+      S.qs[c].push_back(q);
+      const int qv[3] = {q / (n[1] * n[2]), (q / n[2]) % n[1], q % n[2]};
+      for (int k = 0; k < nk; ++k) {
+        const int kv[3] = {k / (n[1] * n[2]), (k / n[2]) % n[1], k % n[2]};
+        const int kq = (((kv[0] + qv[0]) % n[0]) * n[1] + (kv[1] + qv[1]) % n[1]) * n[2] + (kv[2] + qv[2]) % n[2];
+        int iq, m0[3];
+        fold(s->kmesh, k, kq, iq, m0);
+        const int m0p = pack_m(m0[P.ax[0]], m0[P.ax[1]], m0[P.ax[2]]);
+        const int row0 = (ql * nk + k) * 2 * nv * nc;
+        // occupied at k x empty at k + q, then empty at k x occupied at k + q
+        jobs.push_back(PdJob{k, kq, m0p, iq, 0, nv, nv | (nc << 8), row0});
+        jobs.push_back(PdJob{k, kq, m0p, iq, nv, 0, nc | (nv << 8), row0 + nv * nc});
+        S.pk[c].push_back(make_int4(k, kq, q, 0));
+      }
+      for (int i = 0; i < T2; ++i)
+        for (int j = 0; j < T2; ++j) S.tiles[c].push_back(make_int4(q, i, j, ql));
+    }
+    S.jobs[c] = dispatch_order(std::move(jobs), Tune{}.ktile);
+  }
+  // workspace: tables, the rotated wave functions, the pair densities of a chunk
+  size_t o = 0;
+  auto put = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  S.o_gpack = put(P.gpack.size() * sizeof(int));
+  S.o_ng = put(P.ng.size() * sizeof(int));
+  S.o_args = put(sizeof(PdArgs));
+  S.o_jobs.resize(nchunk);
+  S.o_pk.resize(nchunk);
+  S.o_tiles.resize(nchunk);
+  for (int c = 0; c < nchunk; ++c) {
+    S.o_jobs[c] = put(S.jobs[c].size() * sizeof(PdJob));
+    S.o_pk[c] = put(S.pk[c].size() * sizeof(int4));
+    S.o_tiles[c] = put(S.tiles[c].size() * sizeof(int4));
+  }
+  S.tables = o;
+  if (P.rot) S.o_ut = put((size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * sizeof(double2));
+  S.o_Y = put((size_t)per_chunk * bytes_q);
+  S.total = o;
   return BSE_OK;
 }
 
@@ -1145,7 +1227,7 @@ void cache_store(const char* path, const std::string& key, const Tune& t) {
 // bse_autotune_last).
 thread_local std::vector<Tune> g_tried;
 
-// Times the valence-valence pair-density launch (the dominant stage) of the
+// Times the valence and conduction pair-density launch (the dominant stage) of the
 // batch's first chunk under each candidate dispatch and keeps the fastest.
 int autotune(const bse_system* sys, int nsys, int precision, bool pd32, const char* cache, Tune& best, char* ws,
              size_t ws_bytes, hipStream_t st) {
@@ -1465,8 +1547,9 @@ int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, do
   // per chunk: recompute the pair densities, then the chunk's share of every gradient
   for (int c = 0; c < (int)B.C.size(); ++c) {
     const BatchChunk& K = B.C[c];
-    for (int kind = 1; kind < 3; ++kind)
-      if ((rc = run_pd(B, w, kind, c, Tune{}, st)) || (rc = run_tr_fill(B, w, kind, c, st))) return rc;
+    if ((rc = run_pd(B, w, 1, c, Tune{}, st)) || (rc = run_tr_fill(B, w, 1, c, st)) ||
+        (rc = run_tr_fill(B, w, 2, c, st)))
+      return rc;
     g.qstart = reinterpret_cast<const int*>(r + P.o_qs) + (size_t)c * (P.nk + 1);
     g.p0 = P.ch[c].p0;
     g.npairs = P.ch[c].np;
@@ -1563,6 +1646,84 @@ int bse_spectrum(int ns, int nlam, const double* E, const double* A, const doubl
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   HIP_TRY(launch_spectrum(ns, nlam, nq, E, reinterpret_cast<const double2*>(A), reinterpret_cast<const double2*>(d),
                           (double)nk * omega_cell, nw, w0_eV, w1_eV, eta_eV, static_cast<double*>(ws), eps2, st));
+  return BSE_OK;
+}
+
+size_t bse_screening_workspace(const bse_system* sys) {
+  ScrPlan S;
+  if (make_screening_plan(sys, S)) return 0;
+  return S.total;
+}
+
+int bse_screening(const bse_system* sys, const double* vq, double head, double* W, void* ws, size_t ws_bytes,
+                  void* stream) {
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (!vq || !W || !ws) return fail(BSE_ERR_INVALID_ARG, "vq / W / ws is NULL");
+  if (!std::isfinite(head)) return fail(BSE_ERR_INVALID_ARG, "head is not finite");
+  ScrPlan S;
+  int rc = make_screening_plan(sys, S);
+  if (rc) return rc;
+  if (ws_bytes < S.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, S.total);
+  const Plan& P = S.G;
+  const size_t lds = pd_lds_bytes(P.N1, P.N2, P.N3, P.F[1], P.F[2], P.ng_max, 0);
+  if (lds > 160 * 1024) return fail(BSE_ERR_SHAPE, "FFT window needs more than 160 KiB of LDS");
+  char* w = static_cast<char*>(ws);
+  PdArgs a{};
+  a.u = P.rot ? reinterpret_cast<const double2*>(w + S.o_ut) : reinterpret_cast<const double2*>(sys->u);
+  a.nb = P.nb;
+  a.N1 = P.N1;
+  a.gpack = reinterpret_cast<const int*>(w + S.o_gpack);
+  a.ng = reinterpret_cast<const int*>(w + S.o_ng);
+  a.ng_max = P.ng_max;
+  a.lo2 = P.lo[1];
+  a.lo3 = P.lo[2];
+  a.F2 = P.F[1];
+  a.F3 = P.F[2];
+  a.vscale = nullptr;
+  a.out = reinterpret_cast<double2*>(w + S.o_Y);
+  a.u32 = nullptr;
+  char* buf = nullptr;
+  if ((rc = staging_acquire(S.tables, &buf))) return rc;
+  std::memset(buf, 0, S.tables);
+  std::memcpy(buf + S.o_gpack, P.gpack.data(), P.gpack.size() * sizeof(int));
+  std::memcpy(buf + S.o_ng, P.ng.data(), P.ng.size() * sizeof(int));
+  std::memcpy(buf + S.o_args, &a, sizeof(PdArgs));
+  for (size_t c = 0; c < S.qs.size(); ++c) {
+    std::memcpy(buf + S.o_jobs[c], S.jobs[c].data(), S.jobs[c].size() * sizeof(PdJob));
+    std::memcpy(buf + S.o_pk[c], S.pk[c].data(), S.pk[c].size() * sizeof(int4));
+    std::memcpy(buf + S.o_tiles[c], S.tiles[c].data(), S.tiles[c].size() * sizeof(int4));
+  }
+  HIP_TRY(hipMemcpyAsync(w, buf, S.tables, hipMemcpyHostToDevice, st));
+  if ((rc = staging_release(st))) return rc;
+  if (P.rot)
+    HIP_TRY(launch_rotate_axes(reinterpret_cast<const double2*>(sys->u), reinterpret_cast<double2*>(w + S.o_ut),
+                               (long long)P.nk * P.nb, sys->grid[0], sys->grid[1], sys->grid[2], st));
+  RpaArgs r{};
+  r.Y = reinterpret_cast<double2*>(w + S.o_Y);
+  r.M = reinterpret_cast<double2*>(W);
+  r.ng = reinterpret_cast<const int*>(w + S.o_ng);
+  r.eps = sys->eps;
+  r.vq = vq;
+  r.nv = P.nv;
+  r.nc = P.nc;
+  r.nk = P.nk;
+  r.ng_max = P.ng_max;
+  r.omega = (double)P.nk * sys->omega_cell;
+  HIP_TRY(launch_rpa_init(r.M, r.ng, P.nk, P.ng_max, st));
+  for (size_t c = 0; c < S.qs.size(); ++c) {
+    PdBatch b{};
+    b.sys = reinterpret_cast<const PdArgs*>(w + S.o_args);
+    b.jobs = reinterpret_cast<const PdJob*>(w + S.o_jobs[c]);
+    b.njobs = (int)S.jobs[c].size();
+    b.persist = 0;
+    b.cnt = nullptr;
+    HIP_TRY(launch_pair_density(b, P.N2, P.N3, P.ng_max, lds, b.njobs, false, 0, st));
+    r.pk = reinterpret_cast<const int4*>(w + S.o_pk[c]);
+    HIP_TRY(launch_rpa_scale(r, (int)S.pk[c].size(), st));
+    HIP_TRY(launch_rpa_herk(r, reinterpret_cast<const int4*>(w + S.o_tiles[c]), (int)S.tiles[c].size(), st));
+  }
+  HIP_TRY(launch_rpa_invert(r.M, r.ng, P.nk, P.ng_max, st));
+  HIP_TRY(launch_rpa_w(r.M, r.ng, vq, P.nk, P.ng_max, head, st));
   return BSE_OK;
 }
 

@@ -215,6 +215,27 @@ hipError_t launch_spectrum(int ns, int nlam, int nq, const double* E, const doub
                            double nk_omega, int nw, double w0, double w1, double eta, double* t2, double* eps2,
                            hipStream_t st);
 
+// Static RPA screening (bse_screening).  Y: pair densities of a chunk of q,
+// rows ((q_local * nk + k) * 2 + type) * nv * nc + band pair, scaled in place;
+// M: [Nk][ng_max][ng_max], eps(q) then W(q); pk: (k, k + q, q, -) per
+// (q_local, k); omega = Nk * Omega_cell.
+struct RpaArgs {
+  double2* Y;
+  double2* M;
+  const int4* pk;
+  const int* ng;
+  const double* eps;
+  const double* vq;
+  int nv, nc, nk, ng_max;
+  double omega;
+};
+hipError_t launch_rpa_scale(const RpaArgs& a, int npairs, hipStream_t st);
+hipError_t launch_rpa_init(double2* M, const int* ng, int nk, int ng_max, hipStream_t st);
+// tiles (q, row tile, column tile, q_local) of 64 x 64 over ng_max x ng_max
+hipError_t launch_rpa_herk(const RpaArgs& a, const int4* tiles, int ntiles, hipStream_t st);
+hipError_t launch_rpa_invert(double2* M, const int* ng, int nk, int ng_max, hipStream_t st);
+hipError_t launch_rpa_w(double2* M, const int* ng, const double* vq, int nk, int ng_max, double head,
+                        hipStream_t st);
 // Haydock recursion: niter steps of the Lanczos recurrence from conj(d_p)
 // for nq <= kMaxQhat polarisations (H [ns][ns] eV, d [nq][ns] Hartree units),
 // coefficients into coef [nq][niter][2] (a_j, b_j in eV), then eps2 on nw
