@@ -234,6 +234,7 @@ def main():
     ap.add_argument("--no-time-reversal", action="store_true",
                     help="skip the run on time-reversal symmetric inputs with BSE_TIME_REVERSAL")
     ap.add_argument("--no-haydock", action="store_true", help="skip the Haydock spectrum leg")
+    ap.add_argument("--no-screening", action="store_true", help="skip the RPA screening leg")
     ap.add_argument("--chunk-budget-gb", type=float, default=32.0,
                     help="GiB of per-pair arrays per chunk of k pairs for the timed build (0: the library "
                          "default, 6 GiB); the default keeps the Si 32^3 build in one chunk, which the "
@@ -440,6 +441,8 @@ def main():
         out["time_reversal"] = time_reversal_leg(P, args, prec, flags, elements, ms)
     if not args.no_mixed and len(systems) == 1 and args.precision == "fp64":
         out["bandlimited_accuracy"] = bandlimited_leg(P, args, flags)
+    if not args.no_screening and args.config == 2 and not args.kmesh:
+        out["screening"] = screening_leg(P)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(systems[0])
     print(json.dumps(out))
@@ -479,6 +482,36 @@ def haydock_leg(P, d, s, niter):
                         (eps_h - eps_e).abs().max().item() / eps_e.abs().max().item()})
         del E, A
     return out
+
+
+def screening_leg(P, n_empty=60):
+    """The static RPA screened interaction of the 24^3 Si-like shape (fcc
+    a = 10.26 bohr, 4 x 4 x 4 k, 6 Ha: 169-200 plane waves per q) from 4
+    occupied and n_empty empty bands (the paper takes 60-90 empty bands,
+    Sec. IV.B): pair densities of every (k, k+q), the chi0 contraction on
+    FP64 MFMA and the inversion of eps per q, timed with HIP events."""
+    import torch
+    import bse_synth as B
+    s = B.make_system(B.cell_fcc(B.A_SI), (24, 24, 24), (4, 4, 4), 4, n_empty, 6.0, seed=1300,
+                      name="si-fcc24-k4-screening")
+    d = P.DeviceSystem(s, device="cuda:0")
+    vq = torch.from_numpy(B.coulomb_table(s)).to(d.device)
+    st = torch.cuda.current_stream()
+    ws = P.workspace(P.bse_screening_workspace(d), d.device)
+    P.bse_screening(d, vq, s.head, ws=ws)  # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    W = P.bse_screening(d, vq, s.head, ws=ws)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    npd = s.nk * s.nk * 2 * s.nv * s.nc
+    herk = float(np.sum(8.0 * (s.nk * 2 * s.nv * s.nc) * s.ng.astype(np.float64) ** 2))
+    return {"workload": s.name, "nv": s.nv, "n_empty": s.nc, "ng": [int(s.ng.min()), int(s.ng.max())],
+            "ms": ms, "pair_densities": npd, "pair_densities_per_s": npd / (ms / 1e3),
+            "chi0_flops": herk, "workspace_GB": ws.numel() / 1e9,
+            "W_hermitian_dev": float((W - W.conj().transpose(1, 2)).abs().max().item())}
 
 
 def bandlimited_leg(P, args, flags):

@@ -383,6 +383,14 @@ def bse_set_chunk_budget(nbytes=0):
     _check(lib().bse_set_chunk_budget(int(nbytes)))
 
 
+def bse_screening_workspace(system: DeviceSystem) -> int:
+    st = system.struct()
+    n = lib().bse_screening_workspace(ctypes.byref(st))
+    if n == 0:
+        raise BseError(-1, bse_last_error())
+    return int(n)
+
+
 def bse_screening(system: DeviceSystem, vq, head, ws=None, stream=None):
     """Static RPA W [Nk][ng_max][ng_max] (complex128, device) of ``system``'s
     nv occupied and nc empty bands; vq [Nk][ng_max] the bare Coulomb table."""
@@ -391,10 +399,7 @@ def bse_screening(system: DeviceSystem, vq, head, ws=None, stream=None):
         if not isinstance(vq, torch.Tensor) else vq.contiguous()
     st = system.struct()
     if ws is None:
-        n = lib().bse_screening_workspace(ctypes.byref(st))
-        if n == 0:
-            raise BseError(-1, bse_last_error())
-        ws = workspace(n, system.device)
+        ws = workspace(bse_screening_workspace(system), system.device)
     W = torch.empty((system.nk, system.ng_max, system.ng_max), dtype=torch.complex128, device=system.device)
     _check(lib().bse_screening(ctypes.byref(st), _ptr(vq), float(head), _ptr(W), _ptr(ws), ws.numel(),
                                _stream(stream)))
