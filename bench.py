@@ -123,100 +123,6 @@ def run_steps(P, devs, prec, flags, ws, steps, warmup):
     return e0.elapsed_time(e1) / steps, wall, stages
 
 
-def gradcheck(args):
-    """Central differences of the lowest exciton energy E0 of the GPU-built H
-    against the adjoint (dL/dW projected onto symmetric W, dL/de), for
-    L = E0 at the Si 32^3 shape: 10 symmetric W directions and 10 band
-    energies, at the specified step and at a plateau step, FP64 and split-FP32
-    adjoints.  Prints one JSON line."""
-    import torch
-    import bse_synth as B
-    import paper_1206_3518_amd as P
-    t0 = time.perf_counter()
-    s = B.make_config(4)
-    d = P.DeviceSystem(s, device="cuda:0")
-    ws = P.workspace(P.bse_workspace_size([d], P.BSE_FP64, P.BSE_PROJECT_DW), d.device)
-
-    def e0():
-        P.bse_build_H([d], P.BSE_FP64, 0, ws)
-        return torch.linalg.eigvalsh(d.H)[0].item()
-
-    P.bse_build_H([d], P.BSE_FP64, 0, ws)
-    e, V = torch.linalg.eigh(d.H)
-    gap = (e[1] - e[0]).item()
-    x = V[:, 0]
-    G = torch.outer(x, x.conj())
-    grads = {}
-    for prec in ("fp64", "split_fp32"):
-        dW, deps = P.bse_build_H_backward(d, G, precision=prec, flags=P.BSE_PROJECT_DW, ws=ws)
-        grads[prec] = (dW.cpu().numpy(), deps.cpu().numpy())
-    del V, G
-    dW64, deps64 = grads["fp64"]
-    rng = np.random.default_rng(17)
-    gmax_w, gmax_e = np.abs(dW64).max(), np.abs(deps64).max()
-    rows = []
-    mag = np.abs(dW64)
-    mag[0, 0, 0] = 0.0  # the q = 0 head stands apart; sample the rest
-    cand = np.argwhere(mag > 1e-3 * mag.max())
-    W0 = d.W.clone()
-    for trial, ci in enumerate(rng.choice(len(cand), size=min(10, len(cand)), replace=False)):
-        q, g, h = (int(v) for v in cand[int(ci)])
-        z = 1.0 if trial % 2 == 0 else 1j
-        ent = B.symmetric_entries(s, q, g, h, z)
-        if not ent:
-            continue
-        row = {"kind": "W", "entry": [q, g, h], "z": "1" if z == 1.0 else "i"}
-        for prec in ("fp64", "split_fp32"):
-            row["ad_" + prec] = float(sum(np.real(np.conj(grads[prec][0][k]) * v) for k, v in ent.items()))
-        for step in (1e-6, 1e-2):
-            vals = []
-            for sgn in (1.0, -1.0):
-                d.W.copy_(W0)
-                for (qq, a, b), v in ent.items():
-                    d.W[qq, a, b] += sgn * step * complex(v)
-                vals.append(e0())
-            row[f"fd_{step:g}"] = (vals[0] - vals[1]) / (2 * step)
-        d.W.copy_(W0)
-        rows.append(row)
-    eps0 = d.eps.clone()
-    cand = np.argwhere(np.abs(deps64) > 1e-6 * gmax_e)
-    for ci in rng.choice(len(cand), size=min(10, len(cand)), replace=False):
-        k, b = (int(v) for v in cand[int(ci)])
-        row = {"kind": "eps", "entry": [k, b]}
-        for prec in ("fp64", "split_fp32"):
-            row["ad_" + prec] = float(grads[prec][1][k, b])
-        for step in (1e-6, 1e-4):
-            vals = []
-            for sgn in (1.0, -1.0):
-                d.eps.copy_(eps0)
-                d.eps[k, b] += sgn * step
-                vals.append(e0())
-            row[f"fd_{step:g}"] = (vals[0] - vals[1]) / (2 * step)
-        d.eps.copy_(eps0)
-        rows.append(row)
-
-    # rounding of E0 through the eigensolver, divided by the step: the size of
-    # difference-quotient noise
-    noise = lambda step: s.ns * 2.2e-16 * abs(e[0].item()) / step
-
-    def worst(kind, step, prec):
-        rel, ok = 0.0, True
-        for r in rows:
-            if r["kind"] != kind:
-                continue
-            err = abs(r[f"fd_{step:g}"] - r["ad_" + prec])
-            rel = max(rel, err / abs(r["ad_" + prec]))
-            ok = ok and err <= 1e-5 * abs(r["ad_" + prec]) + noise(step)
-        return {"max_rel_err": rel, "noise_floor": noise(step), "within_1e-5_or_noise": ok}
-
-    summary = {f"{kind}_step{step:g}_{prec}": worst(kind, step, prec)
-               for kind, steps in (("W", (1e-6, 1e-2)), ("eps", (1e-6, 1e-4)))
-               for step in steps for prec in ("fp64", "split_fp32")}
-    print(json.dumps({"gradcheck": "lowest exciton energy vs adjoint", "workload": s.name, "ns": s.ns,
-                      "E0_eV": e[0].item(), "gap_eV": gap, "summary": summary, "entries": rows,
-                      "wall_s": time.perf_counter() - t0}))
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,16 +150,12 @@ def main():
     ap.add_argument("--kmesh", type=int, default=0,
                     help="with --config 2: an n x n x n k mesh instead of 8 x 8 x 8 (not the headline workload)")
     ap.add_argument("--haydock-steps", type=int, default=500)
-    ap.add_argument("--gradcheck", action="store_true",
-                    help="instead of timing: finite differences of the lowest exciton energy vs the adjoint")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run one plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
-    if args.gradcheck:
-        gradcheck(args)
         return
 
     import torch
@@ -335,7 +237,9 @@ def main():
     # FP32 pair densities run on VALU FP32 without packed instructions
     peak = PEAK["fp32_valu_unpacked_TFLOPs"] if f32 else PEAK["fp64_TFLOPs"]
     kname = "k_pair_density_line_f32" if f32 else "k_pair_density_line" if line else "k_pair_density"
-    prof = profile_record("pair_density_si32_counters", digest) if args.config == 2 and not f32 else None
+    prof = profile_record("pair_density_si32_counters", digest) if args.config == 2 and not f32 and not args.kmesh else None
+    if prof is not None and prof.get("launches_per_step") != launches_per_step:
+        prof = None  # taken on another chunking of the same workload
     roofline = {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": None,
                 "achieved_is": "nominal FFT flops (5 N log2 N + 6 N per pair density) / launch time",
