@@ -58,6 +58,8 @@ class System:
     eps: np.ndarray           # float64 [Nk][nb] eV, bands 0..nv-1 valence
     W: np.ndarray             # complex128 [Nk][ng_max][ng_max], padding zero
     seed: int
+    qexc: int = 0             # exciton momentum Q as a q-mesh index (0: optical limit);
+                              # vx then holds v(Q+G) on the sphere of Q
 
     @property
     def nk(self) -> int:
@@ -306,6 +308,22 @@ def coulomb_table(sys: System) -> np.ndarray:
         p = q_vector(sys.cell, sys.kmesh, iq)[None, :] + sys.gvec[iq, :g] @ b
         out[iq, :g] = coulomb(p, sys.coulomb, sys.slab_L)
     return out
+
+
+def k_plus(kmesh, k: int, q: int) -> int:
+    """Mesh index of k + q (each component modulo the mesh)."""
+    n = np.array(kmesh)
+    return kindex(kmesh, (ktriplet(kmesh, k) + ktriplet(kmesh, q)) % n)
+
+
+def with_exciton_momentum(sys: System, qexc: int) -> System:
+    """The same inputs with exciton momentum Q = q-mesh point ``qexc``: the
+    electron of S = (k, v, c) sits at k + Q, and vx becomes v(Q + G) on the
+    sphere of Q (the entry of G = 0 set to zero, wherever it sits)."""
+    vx = coulomb_table(sys)[qexc].copy()
+    g0 = np.flatnonzero(np.all(sys.gvec[qexc, : sys.ng[qexc]] == 0, axis=1))
+    vx[g0] = 0.0
+    return dataclasses.replace(sys, qexc=int(qexc), vx=vx, name=f"{sys.name}-Q{qexc}")
 
 
 def k_partner(kmesh, k: int):
