@@ -140,6 +140,7 @@ def main():
     ap.add_argument("--no-time-reversal", action="store_true",
                     help="skip the run on time-reversal symmetric inputs with BSE_TIME_REVERSAL")
     ap.add_argument("--no-haydock", action="store_true", help="skip the Haydock spectrum leg")
+    ap.add_argument("--no-exciton-momentum", action="store_true", help="skip the finite exciton momentum leg")
     ap.add_argument("--no-screening", action="store_true", help="skip the RPA screening leg")
     ap.add_argument("--chunk-budget-gb", type=float, default=32.0,
                     help="GiB of per-pair arrays per chunk of k pairs for the timed build (0: the library "
@@ -345,6 +346,9 @@ def main():
         out["time_reversal"] = time_reversal_leg(P, args, prec, flags, elements, ms)
     if not args.no_mixed and len(systems) == 1 and args.precision == "fp64":
         out["bandlimited_accuracy"] = bandlimited_leg(P, args, flags)
+    if not args.no_exciton_momentum and len(systems) == 1 and not args.kmesh:
+        out["exciton_momentum"] = exciton_momentum_leg(P, args, prec, flags, elements, ms,
+                                                       out.get("lowest_exciton_eV"))
     if not args.no_screening and args.config == 2 and not args.kmesh:
         out["screening"] = screening_leg(P)
     if not args.no_cpu_baseline:
@@ -448,6 +452,36 @@ def bandlimited_leg(P, args, flags):
         dH = (d.H - h).abs().max().item()
         dE = (torch.linalg.eigvalsh(d.H)[:10] - e64).abs().max().item()
         out[name] = {"max_abs_dH_eV": dH, "max_abs_dH_over_kernel": dH / kmax, "max_abs_dE_lowest10_eV": dE}
+    return out
+
+
+def exciton_momentum_leg(P, args, prec, flags, elements, ms_optical, E_optical):
+    """The same workload at the finite exciton momentum Q = b1 / n1 (the
+    first q-mesh point along b1): the hole at k, the electron at k + Q, so the
+    exchange runs over the sphere of Q and the conduction densities pair
+    (k + Q, k' + Q).  Same count of transforms and contractions as Q = 0."""
+    import torch
+    import bse_synth as B
+    s0 = B.make_config(args.config)
+    Q = int(B.kindex(s0.kmesh, (1, 0, 0)))
+    s = B.with_exciton_momentum(s0, Q)
+    del s0
+    d = P.DeviceSystem(s, device="cuda:0")
+    ws = P.workspace(P.bse_workspace_size([d], prec), d.device)
+    steps = max(2, args.steps // 2)
+    ms, _, stages = run_steps(P, [d], prec, flags, ws, steps, 1)
+    del ws
+    strip = d.H[:512]
+    herm = (strip[:, :512] - d.H[:512, :512].conj().T).abs().max().item()
+    out = {"q_index": Q, "q_frac": [1.0 / s.kmesh[0], 0.0, 0.0], "value": elements / (ms / 1e3),
+           "unit": "H elements/s", "ms_per_step": ms, "vs_optical": ms_optical / ms,
+           "max_abs_H_minus_HH_512": herm,
+           "stage_ms": {k: v[0] / steps for k, v in stages.items() if v[1]}}
+    if prec == P.BSE_FP64:
+        E = torch.linalg.eigvalsh(d.H)[:10].cpu().numpy()
+        out["lowest_exciton_eV"] = E.tolist()
+        if E_optical is not None:
+            out["lowest_exciton_shift_vs_optical_eV"] = float(E[0] - E_optical[0])
     return out
 
 

@@ -145,14 +145,24 @@ typedef struct bse_system {
     int ng_max;           /* row stride of gvec, W and every pair-density row               */
     const int *ng;        /* HOST  [Nk]               sphere size N_G(q), q indexed like k     */
     const int *gvec;      /* HOST  [Nk][ng_max][3]    Miller indices; gvec[0][0] = (0,0,0)     */
-    const double *vx;     /* DEVICE [ng_max]          Coulomb v(G) on S(0) (4 pi inside), Ha*bohr^3
-                                                      units of W; entry 0 is not read            */
+    const double *vx;     /* DEVICE [ng_max]          Coulomb v(Q+G) on S(Q), the sphere of the
+                                                      exciton momentum (4 pi inside), units of W;
+                                                      the entry of G = 0 is not read            */
     const double *u;      /* DEVICE [Nk][nb][Nr] complex  periodic parts, sum_r |u|^2 = 1      */
     const double *eps;    /* DEVICE [Nk][nb]           band energies in eV                       */
     const double *W;      /* DEVICE [Nk][ng_max][ng_max] complex, W[q][G][G'] (4 pi inside);
                                                       Hermitian and obeying time reversal;
                                                       entries past ng(q) are not read           */
     double *H;            /* DEVICE [NS][NS] complex, out, eV; every element is written        */
+    int qexc;             /* exciton momentum Q as a q-mesh index (0: the optical limit).  The
+                             e-h basis of the BSE eigenproblem (Sec. II.C) pairs the hole at k
+                             with the electron at k + Q: S = (k, v, c) stands for (v k, c k+Q),
+                             the transition energy is e_{c,k+Q} - e_{v,k}, the exchange runs
+                             over S(Q) without G = 0 with the densities n_{vk,c k+Q}, and the
+                             direct term pairs n_{vk,v'k'} with n_{c k+Q, c' k'+Q} (Eqs. V_eh,
+                             W_SS).  Q != 0: BSE_TIME_REVERSAL -> BSE_ERR_INVALID_ARG, the
+                             backward -> BSE_ERR_UNSUPPORTED; BSE_PD_EXCH then gives
+                             n_{vk, c k+Q}.  Out of range -> BSE_ERR_INVALID_ARG.          */
 } bse_system;
 
 /* Bytes of device workspace that bse_build_H / bse_pair_density /

@@ -123,52 +123,64 @@ def k_plus_q(kmesh, k: int, q: int) -> int:
     return (a * n2 + b) * n3 + c
 
 
-def build_H_exciton(sys, separable=True):
-    """The Hamiltonian at exciton momentum Q = q-mesh point ``sys.qexc`` (the
-    e-h basis S = (n k, m k+q) of the BSE eigenproblem of Sec. II.C, written
-    out in the Tamm-Dancoff block: hole v at k, electron c at k + Q):
+def build_blocks_exciton(sys, blocks, separable=True):
+    """Blocks (k, k') of the Hamiltonian at exciton momentum Q = q-mesh point
+    ``sys.qexc`` (the e-h basis S = (n k, m k+q) of the BSE eigenproblem of
+    Sec. II.C, written out in the Tamm-Dancoff block: hole v at k, electron c
+    at k + Q), each [nv*nc][nv*nc] in eV:
 
       H_SS' = (e_{c,k+Q} - e_{v,k}) delta_SS' + c (2 Vbar_SS' - D_SS')
       Vbar_SS' = sum_{G in S(Q), G != 0} conj(n_{vk,c k+Q}(G)) v(Q+G) n_{v'k',c'k'+Q}(G)
       D_SS'    = sum_{G,G' in S(q)} conj(n_{vk,v'k'}(G)) W_GG'(q) n_{c k+Q,c'k'+Q}(G'),
 
     k' - k = q + G0 (Eqs. V_eh and W_SS; sys.vx holds v(Q+G) on the sphere of
-    Q).  Every ordered (k, k') block is computed on its own from the direct
-    sums of the pair density, each pair with the fold of its own two k points
-    (so the conduction densities of (k+Q, k'+Q) carry their own G0).  Q = 0
-    is the Hamiltonian of ``build_H``."""
-    nk, nv, nc, nb = sys.nk, sys.nv, sys.nc, sys.nb
+    Q).  Each block comes from the direct sums of the pair density, each pair
+    with the fold of its own two k points (so the conduction densities of
+    (k+Q, k'+Q) carry their own G0)."""
+    blocks = [(int(a), int(b)) for a, b in np.asarray(blocks).reshape(-1, 2)]
+    nk, nv, nc = sys.nk, sys.nv, sys.nc
     nt = nv * nc
     Q = int(getattr(sys, "qexc", 0))
     kq = [k_plus_q(sys.kmesh, k, Q) for k in range(nk)]
     c = HARTREE_EV / (nk * sys.omega_cell)
-    # exchange rows n_{vk, c k+Q} on the sphere of Q
-    items = [(k, v, kq[k], nv + cc) for k in range(nk) for v in range(nv) for cc in range(nc)]
-    for k in range(nk):
-        assert fold(sys.kmesh, k, kq[k])[0] == Q
     ngq = int(sys.ng[Q])
-    X = pair_density_items(sys, items, separable)[:, :ngq]
     v = np.array(sys.vx[:ngq], dtype=np.float64)
     v[np.all(sys.gvec[Q, :ngq] == 0, axis=1)] = 0.0  # G = 0 left out (Vbar)
-    H = 2.0 * c * (np.conj(X) * v) @ X.T
-    # direct term, every ordered block
-    D = np.zeros_like(H)
-    for ka in range(nk):
-        for kb in range(nk):
-            iq, _ = fold(sys.kmesh, ka, kb)
-            assert fold(sys.kmesh, kq[ka], kq[kb])[0] == iq
-            ng = int(sys.ng[iq])
-            it = [(ka, a, kb, b) for a in range(nv) for b in range(nv)]
-            it += [(kq[ka], nv + a, kq[kb], nv + b) for a in range(nc) for b in range(nc)]
-            n = pair_density_items(sys, it, separable)[:, :ng]
-            rv = n[: nv * nv].reshape(nv, nv, ng)
-            rc = n[nv * nv:].reshape(nc, nc, ng)
-            blk = np.einsum("abg,gh,cdh->acbd", np.conj(rv), sys.W[iq, :ng, :ng], rc).reshape(nt, nt)
-            D[ka * nt:(ka + 1) * nt, kb * nt:(kb + 1) * nt] = blk
-    H -= c * D
-    de = (np.asarray(sys.eps)[kq, nv:][:, None, :] - np.asarray(sys.eps)[:, :nv][:, :, None]).reshape(-1)
-    H[np.diag_indices(sys.ns)] += de
-    return H
+    ks = sorted({k for b in blocks for k in b})
+    # exchange rows n_{vk, c k+Q} on the sphere of Q
+    items = [(k, a, kq[k], nv + b) for k in ks for a in range(nv) for b in range(nc)]
+    for k in ks:
+        assert fold(sys.kmesh, k, kq[k])[0] == Q
+    Xr = pair_density_items(sys, items, separable)[:, :ngq].reshape(len(ks), nt, ngq)
+    X = {k: Xr[i] for i, k in enumerate(ks)}
+    out = np.zeros((len(blocks), nt, nt), dtype=np.complex128)
+    for bi, (ka, kb) in enumerate(blocks):
+        iq, _ = fold(sys.kmesh, ka, kb)
+        assert fold(sys.kmesh, kq[ka], kq[kb])[0] == iq
+        ng = int(sys.ng[iq])
+        it = [(ka, a, kb, b) for a in range(nv) for b in range(nv)]
+        it += [(kq[ka], nv + a, kq[kb], nv + b) for a in range(nc) for b in range(nc)]
+        n = pair_density_items(sys, it, separable)[:, :ng]
+        rv = n[: nv * nv].reshape(nv, nv, ng)
+        rc = n[nv * nv:].reshape(nc, nc, ng)
+        D = np.einsum("abg,gh,cdh->acbd", np.conj(rv), sys.W[iq, :ng, :ng], rc).reshape(nt, nt)
+        V = (np.conj(X[ka]) * v) @ X[kb].T
+        blk = c * (2.0 * V - D)
+        if ka == kb:
+            de = (sys.eps[kq[ka], nv:][None, :] - sys.eps[ka, :nv][:, None]).reshape(-1)
+            blk[np.diag_indices(nt)] += de
+        out[bi] = blk
+    return out
+
+
+def build_H_exciton(sys, separable=True):
+    """The whole Hamiltonian at exciton momentum ``sys.qexc``: every one of
+    the Nk^2 blocks of ``build_blocks_exciton``.  Q = 0 is ``build_H``."""
+    nk, nt = sys.nk, sys.nv * sys.nc
+    blocks = [(a, b) for a in range(nk) for b in range(nk)]
+    out = build_blocks_exciton(sys, blocks, separable)
+    H = out.reshape(nk, nk, nt, nt).transpose(0, 2, 1, 3).reshape(nk * nt, nk * nt)
+    return np.ascontiguousarray(H)
 
 
 def exciton_energies(H, n=10):

@@ -42,7 +42,7 @@ class bse_system(ctypes.Structure):
                 ("nc", ctypes.c_int), ("omega_cell", ctypes.c_double), ("ng_max", ctypes.c_int),
                 ("ng", ctypes.c_void_p), ("gvec", ctypes.c_void_p), ("vx", ctypes.c_void_p),
                 ("u", ctypes.c_void_p), ("eps", ctypes.c_void_p), ("W", ctypes.c_void_p),
-                ("H", ctypes.c_void_p)]
+                ("H", ctypes.c_void_p), ("qexc", ctypes.c_int)]
 
 
 SYMBOLS = ["bse_workspace_size", "bse_pair_density", "bse_build_H", "bse_build_H_backward",
@@ -141,6 +141,7 @@ class DeviceSystem:
         self.vx = torch.from_numpy(np.ascontiguousarray(sys.vx, dtype=np.float64)).to(self.device)
         self.nk = int(np.prod(self.kmesh))
         self.ns = self.nk * self.nv * self.nc
+        self.qexc = int(getattr(sys, "qexc", 0))  # exciton momentum (q-mesh index); vx is v(Q+G) on S(Q)
         self.H = H if H is not None else torch.empty((self.ns, self.ns), dtype=torch.complex128, device=self.device)
 
     def struct(self) -> bse_system:
@@ -157,6 +158,7 @@ class DeviceSystem:
         s.eps = self.eps.data_ptr()
         s.W = self.W.data_ptr()
         s.H = self.H.data_ptr() if self.H is not None else None
+        s.qexc = self.qexc
         return s
 
 

@@ -193,7 +193,10 @@ struct Plan {
   int N1 = 0, N2 = 0, N3 = 0, nk = 0, nv = 0, nc = 0, nb = 0, ng_max = 0, ns = 0, nt = 0;
   int lo[3] = {0, 0, 0}, F[3] = {0, 0, 0};
   std::vector<int> gpack, ng;
-  std::vector<PdJob> jx;           // exchange pair densities, natural order
+  std::vector<PdJob> jx;           // exchange pair densities (k, k+Q), natural order
+  int qexc = 0;                    // exciton momentum Q (q-mesh index)
+  std::vector<int> kq;             // per k: mesh index of k + Q
+  int g0x = 0;                     // position of G = 0 in the sphere of Q (-1: absent)
   std::vector<int> qbar, trmap;    // time-reversal partner of q; sphere map t - m
   bool tr_closed = true;
   std::vector<int> ktr;            // per k: kbar | K << 24 (grid axes)
@@ -208,7 +211,7 @@ struct Plan {
   bool mixed = false;              // split buffers of the mixed precisions reserved
   int kpad = 0;                    // ng_max rounded up to a multiple of 32
   // byte offsets inside the system's region of the workspace
-  size_t o_gpack = 0, o_ng = 0, o_pairs = 0, o_qs = 0, o_plex = 0, o_qbar = 0, o_trmap = 0, o_ktr = 0;
+  size_t o_gpack = 0, o_ng = 0, o_pairs = 0, o_qs = 0, o_plex = 0, o_qbar = 0, o_trmap = 0, o_ktr = 0, o_kq = 0;
   size_t tables = 0, o_vs = 0, o_X = 0, o_RV = 0, o_RC = 0, o_Z = 0, o_dWraw = 0, total = 0;
   size_t o_ut = 0;   // rotated wave functions (rot only)
   size_t o_u32 = 0;  // FP32 copy of the wave functions in the frame (pd32 only)
@@ -231,6 +234,8 @@ int check_system(const bse_system* s, bool need_w = true) {
   if (!s->ng || !s->gvec) return fail(BSE_ERR_INVALID_ARG, "ng / gvec host tables are NULL");
   if (!s->u || !s->eps || (need_w && (!s->W || !s->vx)))
     return fail(BSE_ERR_INVALID_ARG, "a device input pointer is NULL");
+  const long long nk = (long long)s->kmesh[0] * s->kmesh[1] * s->kmesh[2];
+  if (s->qexc < 0 || s->qexc >= nk) return fail(BSE_ERR_INVALID_ARG, "qexc = %d not in 0..Nk-1", s->qexc);
   return BSE_OK;
 }
 
@@ -292,9 +297,33 @@ int make_geometry(const bse_system* s, Plan& P, bool need_w = true) {
     if (P.F[d] > N[d])
       return fail(BSE_ERR_SHAPE, "G-sphere window %d exceeds grid %d along axis %d", P.F[d], N[d], d);
   }
+  // exciton momentum: the electron of S = (k, v, c) sits at k + Q, so the
+  // exchange densities pair (k, k + Q) on the sphere of Q
+  P.qexc = s->qexc;
+  P.kq.resize(P.nk);
+  {
+    const int* n = s->kmesh;
+    const int Q = P.qexc, q1 = Q / (n[1] * n[2]), q2 = (Q / n[2]) % n[1], q3 = Q % n[2];
+    for (int k = 0; k < P.nk; ++k) {
+      const int a = (k / (n[1] * n[2]) + q1) % n[0], b = ((k / n[2]) % n[1] + q2) % n[1], c = (k % n[2] + q3) % n[2];
+      P.kq[k] = (a * n[1] + b) * n[2] + c;
+    }
+  }
+  P.g0x = -1;
+  for (int g = 0; g < P.ng[P.qexc]; ++g) {
+    const int* m = s->gvec + ((size_t)P.qexc * P.ng_max + g) * 3;
+    if (m[0] == 0 && m[1] == 0 && m[2] == 0) {
+      P.g0x = g;
+      break;
+    }
+  }
   P.jx.resize(P.nk);
-  for (int k = 0; k < P.nk; ++k)
-    P.jx[k] = PdJob{k, k, pack_m(0, 0, 0), 0, 0, P.nv, P.nv | (P.nc << 8), k * P.nt};
+  for (int k = 0; k < P.nk; ++k) {
+    int iq, m0[3];
+    fold(s->kmesh, k, P.kq[k], iq, m0);
+    P.jx[k] = PdJob{k, P.kq[k], pack_m(m0[P.ax[0]], m0[P.ax[1]], m0[P.ax[2]]), iq, 0, P.nv, P.nv | (P.nc << 8),
+                    k * P.nt};
+  }
 
   // time reversal on the q mesh: qbar = -q mod n, and the index of t - m_g in
   // the sphere of qbar (-q = qbar + t)
@@ -452,7 +481,15 @@ int plan_pairs(const bse_system* s, Plan& P, const BatchOpts& opt, int nchunk, i
       const int g = g_of_lex[u->rep], loc = g - next;
       const int4 q4 = P.pairs[g];
       K.jv.push_back(PdJob{q4.x, q4.y, q4.w, q4.z, 0, 0, nv | (nv << 8), loc * nv * nv});
-      K.jc.push_back(PdJob{q4.x, q4.y, q4.w, q4.z, nv, nv, nc | (nc << 8), loc * nc * nc});
+      if (P.qexc == 0) {
+        K.jc.push_back(PdJob{q4.x, q4.y, q4.w, q4.z, nv, nv, nc | (nc << 8), loc * nc * nc});
+      } else {  // conduction pair (k + Q, k' + Q), folded on its own (same q, its own G0)
+        int iq, m0[3];
+        fold(s->kmesh, P.kq[q4.x], P.kq[q4.y], iq, m0);
+        if (iq != q4.z) return fail(BSE_ERR_INVALID_ARG, "internal: shifted pair changes q");
+        K.jc.push_back(PdJob{P.kq[q4.x], P.kq[q4.y], pack_m(m0[P.ax[0]], m0[P.ax[1]], m0[P.ax[2]]), iq, nv, nv,
+                             nc | (nc << 8), loc * nc * nc});
+      }
       if (u->img >= 0) {
         const int gi = g_of_lex[u->img];
         K.fill.push_back(make_int4(gi - next, loc, (P.pairs[gi].z << 1) | u->mode, sys));
@@ -507,6 +544,7 @@ int plan_pairs(const bse_system* s, Plan& P, const BatchOpts& opt, int nchunk, i
   P.o_qbar = put(P.qbar.size() * sizeof(int));
   P.o_trmap = put(P.trmap.size() * sizeof(int));
   P.o_ktr = put(P.ktr.size() * sizeof(int));
+  P.o_kq = put(P.kq.size() * sizeof(int));
   P.tables = o;
   const size_t mc = (size_t)P.maxcp;
   P.o_vs = put((size_t)P.ng_max * sizeof(double));
@@ -542,6 +580,7 @@ void put_tables(const Plan& P, std::vector<char>& buf, size_t base) {
   cp(P.o_qbar, P.qbar.data(), P.qbar.size() * sizeof(int));
   cp(P.o_trmap, P.trmap.data(), P.trmap.size() * sizeof(int));
   cp(P.o_ktr, P.ktr.data(), P.ktr.size() * sizeof(int));
+  cp(P.o_kq, P.kq.data(), P.kq.size() * sizeof(int));
 }
 
 PdArgs pd_args(const Plan& P, const bse_system* s, char* region) {
@@ -569,7 +608,8 @@ GemmArgs gemm_args(const Plan& P, const bse_system* s, char* region, int c) {
   g.X = reinterpret_cast<const double2*>(region + P.o_X);
   g.ns = P.ns;
   g.ng_max = P.ng_max;
-  g.ngx = P.ng[0];
+  g.ngx = P.ng[P.qexc];
+  g.kq = P.qexc ? reinterpret_cast<const int*>(region + P.o_kq) : nullptr;
   g.H = reinterpret_cast<double2*>(s->H);
   g.cpref = 27.211386245988 / ((double)P.nk * s->omega_cell);
   g.RV = reinterpret_cast<const double2*>(region + P.o_RV);
@@ -683,8 +723,12 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
   const int nchunk = (int)std::min(1e6, std::max(1.0, std::ceil(bytes / (double)g_chunk_budget.load())));
   for (int i = 0; i < nsys; ++i) {
     int rc = make_geometry(&sys[i], B.P[i]);
-    if (!rc) rc = plan_pairs(&sys[i], B.P[i], opt, nchunk, i);
     if (rc) return rc;
+    if (B.P[i].qexc && opt.tr)
+      return fail(BSE_ERR_INVALID_ARG, "system %d: BSE_TIME_REVERSAL needs exciton momentum Q = 0", i);
+    if (B.P[i].qexc && opt.backward)
+      return fail(BSE_ERR_UNSUPPORTED, "system %d: the backward needs exciton momentum Q = 0", i);
+    if ((rc = plan_pairs(&sys[i], B.P[i], opt, nchunk, i))) return rc;
     const Plan& P = B.P[i];
     if (i == 0) {
       B.N2 = P.N2;
@@ -797,8 +841,8 @@ std::string plan_key(const bse_system* sys, int nsys, int ktile, const BatchOpts
     if (s.ng) mix(s.ng, sizeof(int) * (size_t)std::max(nk, 0));
     if (s.gvec && s.ng_max > 0) mix(s.gvec, sizeof(int) * 3 * (size_t)std::max(nk, 0) * s.ng_max);
     char b[200];
-    snprintf(b, sizeof b, "|%d,%d,%d:%d,%d,%d:%d,%d:%d:%llx", s.grid[0], s.grid[1], s.grid[2], s.kmesh[0],
-             s.kmesh[1], s.kmesh[2], s.nv, s.nc, s.ng_max, h);
+    snprintf(b, sizeof b, "|%d,%d,%d:%d,%d,%d:%d,%d:%d:%llx:Q%d", s.grid[0], s.grid[1], s.grid[2], s.kmesh[0],
+             s.kmesh[1], s.kmesh[2], s.nv, s.nc, s.ng_max, h, s.qexc);
     k += b;
   }
   return k;
@@ -1009,7 +1053,8 @@ int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& 
   for (int i = 0; i < nsys; ++i) {
     const Plan& P = B.P[i];
     double* vs = reinterpret_cast<double*>(ws + B.base[i] + P.o_vs);
-    HIP_TRY(stage(BSE_STAGE_VSCALE, st, [&] { return launch_vscale(sys[i].vx, P.ng[0], P.ng_max, vs, st); }));
+    HIP_TRY(stage(BSE_STAGE_VSCALE, st,
+                  [&] { return launch_vscale(sys[i].vx, P.ng[P.qexc], P.ng_max, P.g0x, vs, st); }));
   }
   if ((rc = prepare_u(B, sys, ws, st))) return rc;
   if (precision != BSE_FP64) {
@@ -1150,7 +1195,7 @@ int validate(const Batch& B, const bse_system* sys, char* ws, hipStream_t st) {
     char* r = ws + B.base[i];
     HIP_TRY(launch_zero_u32(bad, 8 + 16, st));  // the 3 flags and the 64-bit maxima after them
     HIP_TRY(launch_validate(s.u, (size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * 2, s.eps, (size_t)P.nk * P.nb, s.vx,
-                            (size_t)P.ng[0], reinterpret_cast<const double2*>(s.W),
+                            (size_t)P.ng[P.qexc], reinterpret_cast<const double2*>(s.W),
                             reinterpret_cast<const int*>(r + P.o_ng), reinterpret_cast<const int*>(r + P.o_qbar),
                             reinterpret_cast<const int*>(r + P.o_trmap), P.nk, P.ng_max, P.tr_closed ? 1 : 0, bad,
                             wstat, st));
@@ -1539,7 +1584,7 @@ int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, do
   // the exchange densities (only for dX) and their gradient
   if (dX) {
     double* vs = reinterpret_cast<double*>(r + P.o_vs);
-    HIP_TRY(launch_vscale(sys->vx, P.ng[0], P.ng_max, vs, st));
+    HIP_TRY(launch_vscale(sys->vx, P.ng[P.qexc], P.ng_max, P.g0x, vs, st));
     if ((rc = run_pd(B, w, 0, 0, Tune{}, st))) return rc;
     HIP_TRY(launch_adj_dx(g, st));
   }

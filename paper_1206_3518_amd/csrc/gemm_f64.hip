@@ -132,7 +132,10 @@ __global__ __launch_bounds__(256) void k_direct_s2(const GemmArgs* __restrict__ 
       double2 h = gld(g.H, S * g.ns + S2);
       h.x -= g.cpref * dr;
       h.y -= g.cpref * di;
-      if (S == S2) h.x += gbl(g.eps)[(size_t)ka * g.nb + g.nv + c] - gbl(g.eps)[(size_t)ka * g.nb + v];
+      if (S == S2) {  // e_{c,k+Q} - e_{v,k}
+        const int kc = g.kq ? gbl(g.kq)[ka] : ka;
+        h.x += gbl(g.eps)[(size_t)kc * g.nb + g.nv + c] - gbl(g.eps)[(size_t)ka * g.nb + v];
+      }
       gst(g.H, S * g.ns + S2, h);
     }
   }
@@ -182,13 +185,15 @@ hipError_t launch_mirror(const GemmArgs* gs, const HTile* tiles, int ntiles, hip
 
 // ------------------------------------------------------------------ sqrt v(G)
 
-__global__ void k_vscale(const double* __restrict__ vx, int ngx, int ng_max, double* __restrict__ out) {
+// The short-range exchange of Eq. V_eh leaves out G = 0 (entry g0 of the
+// sphere of the exciton momentum; -1 when that sphere does not hold it).
+__global__ void k_vscale(const double* __restrict__ vx, int ngx, int ng_max, int g0, double* __restrict__ out) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < ng_max) out[g] = (g == 0 || g >= ngx) ? 0.0 : sqrt(vx[g]);
+  if (g < ng_max) out[g] = (g == g0 || g >= ngx) ? 0.0 : sqrt(vx[g]);
 }
 
-hipError_t launch_vscale(const double* vx, int ngx, int ng_max, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_vscale, dim3((ng_max + 255) / 256), dim3(256), 0, st, vx, ngx, ng_max, out);
+hipError_t launch_vscale(const double* vx, int ngx, int ng_max, int g0, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_vscale, dim3((ng_max + 255) / 256), dim3(256), 0, st, vx, ngx, ng_max, g0, out);
   return hipGetLastError();
 }
 

@@ -84,7 +84,8 @@ struct GemmArgs {
   const double2* X;
   int ns;
   int ng_max;
-  int ngx;              // K of the exchange (= ng(q=0))
+  int ngx;              // K of the exchange (= ng(Q), the sphere of the exciton momentum)
+  const int* kq;        // [Nk] mesh index of k + Q (null: Q = 0), for the transition energies
   double2* H;
   double cpref;         // E_h / (Nk Omega_cell)
   const double2* RV;
@@ -110,7 +111,8 @@ struct GemmArgs {
 // arguments, every tile names its system.  Stage 2 items are (pair, 16 x 16
 // tile) of every system, numbered system after system: d2off[s] is the first
 // item of system s (nsys + 1 entries).
-hipError_t launch_vscale(const double* vx, int ngx, int ng_max, double* out, hipStream_t st);
+// out[g] = sqrt(vx[g]) for g < ngx, zero at g = g0 (G = 0; -1: none) and past ngx
+hipError_t launch_vscale(const double* vx, int ngx, int ng_max, int g0, double* out, hipStream_t st);
 hipError_t launch_exchange(const GemmArgs* gs, const HTile* tiles, int ntiles, int precision, hipStream_t st);
 hipError_t launch_direct_s1(const GemmArgs* gs, const S1Tile* tiles, int ntiles, int precision, hipStream_t st);
 // stage 2 is FP64 in every mode (it adds the FP64 q = 0 head when w_head_fp64)

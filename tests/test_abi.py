@@ -99,6 +99,17 @@ def test_workspace_size_and_host_errors():
                                   P.BSE_FP64, P.BSE_FP32_PAIRDENS, ctypes.c_void_p(0x1000), n, None) == -1
     assert L.bse_build_H_backward(ctypes.byref(st), ctypes.c_void_p(0x1000), None, None, None, None, None,
                                   P.BSE_FP64, P.BSE_VALIDATE, ctypes.c_void_p(0x1000), n, None) == -1
+    # exciton momentum: out of range; with time reversal; in the backward
+    st6, keep6 = _fake_struct(P, s)
+    st6.qexc = s.nk
+    assert L.bse_build_H(ctypes.byref(st6), 1, 0, 0, ctypes.c_void_p(0x1000), n, None) == -1
+    assert "qexc" in P.bse_last_error()
+    st6.qexc = 1
+    assert L.bse_build_H(ctypes.byref(st6), 1, 0, P.BSE_TIME_REVERSAL, ctypes.c_void_p(0x1000), n, None) == -1
+    assert "TIME_REVERSAL" in P.bse_last_error()
+    assert L.bse_build_H_backward(ctypes.byref(st6), ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), None, None,
+                                  None, None, P.BSE_FP64, 0, ctypes.c_void_p(0x1000), n, None) == -7
+    assert "momentum" in P.bse_last_error()
     # the workspace grows for the FP32 copy of u
     n32 = L.bse_workspace_size(ctypes.byref(st), 1, P.BSE_BF16X3, P.BSE_FP32_PAIRDENS)
     assert n32 >= n + 8 * s.nk * (s.nv + s.nc) * int(np.prod(s.grid))

@@ -1,0 +1,125 @@
+"""The HIP build at finite exciton momentum Q (hole at k, electron at k + Q)
+against the oracle's, on the same seeded inputs: FP64 at the FP64 bar, the
+mixed modes at theirs; Q = 0 through the same inputs; chunks and batches."""
+import sys
+
+import numpy as np
+import pytest
+
+import bse_synth as B
+import oracle as O
+from bars import fp64_h_bar
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _fcc3():
+    """fcc, 16^3 grid, 3 x 1 x 1 k mesh: pairs (k+Q, k'+Q) and (k, k+Q) wrap
+    around the mesh differently from (k, k'), so the conduction densities and
+    the exchange rows carry their own G0."""
+    return B.make_system(B.cell_fcc(7.0), (16, 16, 16), (3, 1, 1), 2, 3, 3.0, seed=61)
+
+
+CASES = [("sc16", lambda: B.make_config(0), (1, 3, 7)),
+         ("fcc3", _fcc3, (1, 2)),
+         ("si24", lambda: B.make_config(1), (5, 37))]
+
+
+@pytest.mark.parametrize("name,make,qs", CASES, ids=[c[0] for c in CASES])
+def test_finite_momentum_fp64_matches_oracle(name, make, qs):
+    import paper_1206_3518_amd as P
+    import torch
+    s0 = make()
+    for Q in qs:
+        s = B.with_exciton_momentum(s0, Q)
+        H = P.build_H(s, "fp64")
+        torch.cuda.synchronize()
+        Hc = H.cpu().numpy()
+        if s.nk <= 8:
+            ref = O.build_H_exciton(s)
+            err = np.abs(Hc - ref).max()
+            bar = fp64_h_bar(ref)
+        else:  # oracle blocks on a sample of ordered k pairs
+            rng = np.random.default_rng(Q)
+            nk, nt = s.nk, s.nv * s.nc
+            blocks = [(0, 0), (nk - 1, nk - 1), (0, nk - 1), (nk - 1, 0)]
+            blocks += [tuple(int(x) for x in rng.integers(0, nk, 2)) for _ in range(8)]
+            ref = O.build_blocks_exciton(s, blocks)
+            kmax = max(np.abs(r - np.diag(np.diag(r))).max() for r in ref)
+            bar = 1e-10 * kmax + 2.0 ** -50 * max(np.abs(r).max() for r in ref)
+            err = max(np.abs(Hc[a * nt:(a + 1) * nt, b * nt:(b + 1) * nt] - r).max()
+                      for (a, b), r in zip(blocks, ref))
+        herm = np.abs(Hc - Hc.conj().T).max()
+        _say(f"{name} Q={Q}: max|H - H_oracle| {err:.3e} eV (bar {bar:.3e}); max|H - H^H| {herm:.3e}")
+        assert err <= bar
+        assert herm <= bar
+
+
+@pytest.mark.parametrize("prec", ["split_fp32", "bf16x3"])
+def test_finite_momentum_mixed_against_oracle(prec):
+    import paper_1206_3518_amd as P
+    import torch
+    s = B.with_exciton_momentum(_fcc3(), 2)
+    ref = O.build_H_exciton(s)
+    H = P.build_H(s, prec).cpu().numpy()
+    torch.cuda.synchronize()
+    kmax = np.abs(ref - np.diag(np.diag(ref))).max()
+    err = np.abs(H - ref).max()
+    _say(f"{prec} Q=2: max|dH| {err:.3e} eV = {err / kmax:.2e} of max|K|")
+    assert err <= 1e-4 and err <= 1e-3 * kmax
+
+
+def test_zero_momentum_inputs_give_the_optical_build():
+    """Q = 0 through the finite-Q inputs (the same vx) is the optical build, bit for bit."""
+    import paper_1206_3518_amd as P
+    import torch
+    s = B.make_config(0)
+    a = P.build_H(s, "fp64").clone()
+    b = P.build_H(B.with_exciton_momentum(s, 0), "fp64")
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_finite_momentum_chunks_and_batch():
+    """Many chunks equal one chunk, and a batch holding systems at two
+    different Q equals their single builds, bit for bit."""
+    import paper_1206_3518_amd as P
+    import torch
+    s1 = B.with_exciton_momentum(B.make_config(1), 5)
+    s2 = B.with_exciton_momentum(B.make_system(B.cell_fcc(B.A_SI), (24, 24, 24), (2, 2, 2), 3, 3, 6.0, seed=62), 3)
+    d1 = P.DeviceSystem(s1)
+    P.bse_build_H([d1], P.BSE_FP64, 0)
+    one = d1.H.clone()
+    try:
+        P.bse_set_chunk_budget(64 << 20)  # many chunks
+        d1.H.zero_()
+        P.bse_build_H([d1], P.BSE_FP64, 0)
+        torch.cuda.synchronize()
+        assert torch.equal(d1.H, one)
+    finally:
+        P.bse_set_chunk_budget(0)
+    d2 = P.DeviceSystem(s2)
+    P.bse_build_H([d2], P.BSE_FP64, 0)
+    single2 = d2.H.clone()
+    d1.H.zero_()
+    d2.H.zero_()
+    P.bse_build_H([d1, d2], P.BSE_FP64, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(d1.H, one) and torch.equal(d2.H, single2)
+
+
+def test_finite_momentum_refuses_time_reversal_and_backward():
+    import paper_1206_3518_amd as P
+    s = B.with_exciton_momentum(B.make_config(0), 1)
+    d = P.DeviceSystem(s)
+    with pytest.raises(P.BseError):
+        P.bse_build_H([d], P.BSE_FP64, P.BSE_TIME_REVERSAL)
+    P.bse_build_H([d], P.BSE_FP64, 0)
+    import torch
+    with pytest.raises(P.BseError):
+        P.bse_build_H_backward(d, torch.zeros_like(d.H))
