@@ -183,6 +183,61 @@ def build_H_exciton(sys, separable=True):
     return np.ascontiguousarray(H)
 
 
+def build_H_full(sys, separable=True):
+    """The Bethe-Salpeter Hamiltonian beyond the Tamm-Dancoff approximation
+    (optical limit, Q = 0), from the general definition of Sec. II.C and the
+    appendix over the basis of e-h states (n = v, m = c) and h-e states
+    (n = c, m = v), S = (n k, m k):
+
+      H_ab = (e_{m_a} - e_{n_a}) delta_ab - (f_{m_a} - f_{n_a}) K_ab,   f_v = 1, f_c = 0,
+      K_ab = c (2 Vbar_ab - D_ab),
+      Vbar_ab = sum_{G != 0} conj(n_{n_a k_a, m_a k_a}(G)) v(G) n_{n_b k_b, m_b k_b}(G),
+      D_ab    = sum_{G,G'} conj(n_{n_a k_a, n_b k_b}(G)) W_GG'(q) n_{m_a k_a, m_b k_b}(G'),
+
+    k_b - k_a = q + G0 (Eqs. V_eh and W_SS).  States are ordered e-h first,
+    then h-e, each as S = (k nv + v) nc + c; the result is [2 NS][2 NS] in eV.
+    Every block is computed from its own pair densities: no symmetry of the
+    blocks is assumed (the e-h block is the Tamm-Dancoff H)."""
+    nk, nv, nc, nb = sys.nk, sys.nv, sys.nc, sys.nb
+    ns = sys.ns
+    c = HARTREE_EV / (nk * sys.omega_cell)
+    # states: (kind, k, v, c) -> (n band, m band, factor -(f_m - f_n), energy)
+    st = []
+    for kind in (0, 1):
+        for k in range(nk):
+            for v in range(nv):
+                for cc in range(nc):
+                    n, m = (v, nv + cc) if kind == 0 else (nv + cc, v)
+                    fac = 1.0 if kind == 0 else -1.0  # -(f_m - f_n)
+                    st.append((k, n, m, fac, sys.eps[k, m] - sys.eps[k, n]))
+    ng0 = int(sys.ng[0])
+    v0 = np.array(sys.vx[:ng0], dtype=np.float64)
+    v0[np.all(sys.gvec[0, :ng0] == 0, axis=1)] = 0.0
+    items = [(k, n, k, m) for (k, n, m, _, _) in st]
+    X = pair_density_items(sys, items, separable)[:, :ng0]
+    K = 2.0 * c * (np.conj(X) * v0) @ X.T
+    # direct term: every band pair of every ordered (k, k')
+    D = np.zeros_like(K)
+    idx = {}
+    for a, (k, n, m, _, _) in enumerate(st):
+        idx.setdefault(k, []).append((a, n, m))
+    for ka in range(nk):
+        for kb in range(nk):
+            iq, _ = fold(sys.kmesh, ka, kb)
+            ng = int(sys.ng[iq])
+            it = [(ka, i, kb, j) for i in range(nb) for j in range(nb)]
+            rho = pair_density_items(sys, it, separable)[:, :ng].reshape(nb, nb, ng)
+            Z = np.einsum("ijg,gh->ijh", np.conj(rho), sys.W[iq, :ng, :ng])
+            for a, na, ma in idx[ka]:
+                for b, nb_, mb in idx[kb]:
+                    D[a, b] = np.dot(Z[na, nb_], rho[ma, mb])
+    K -= c * D
+    fac = np.array([x[3] for x in st])
+    H = fac[:, None] * K
+    H[np.diag_indices(2 * ns)] += np.array([x[4] for x in st])
+    return H
+
+
 def exciton_energies(H, n=10):
     """Lowest n eigenvalues of the Hermitian H (LAPACK zheevd through numpy)."""
     return np.linalg.eigvalsh(H)[:n]
