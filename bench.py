@@ -141,6 +141,7 @@ def main():
                     help="skip the run on time-reversal symmetric inputs with BSE_TIME_REVERSAL")
     ap.add_argument("--no-haydock", action="store_true", help="skip the Haydock spectrum leg")
     ap.add_argument("--no-exciton-momentum", action="store_true", help="skip the finite exciton momentum leg")
+    ap.add_argument("--no-beyond-tda", action="store_true", help="skip the beyond-Tamm-Dancoff leg")
     ap.add_argument("--no-screening", action="store_true", help="skip the RPA screening leg")
     ap.add_argument("--chunk-budget-gb", type=float, default=32.0,
                     help="GiB of per-pair arrays per chunk of k pairs for the timed build (0: the library "
@@ -349,6 +350,8 @@ def main():
     if not args.no_exciton_momentum and len(systems) == 1 and not args.kmesh:
         out["exciton_momentum"] = exciton_momentum_leg(P, args, prec, flags, elements, ms,
                                                        out.get("lowest_exciton_eV"))
+    if not args.no_beyond_tda and len(systems) == 1 and not args.kmesh and args.precision == "fp64":
+        out["beyond_tda"] = beyond_tda_leg(P, args, ms)
     if not args.no_screening and args.config == 2 and not args.kmesh:
         out["screening"] = screening_leg(P)
     if not args.no_cpu_baseline:
@@ -452,6 +455,40 @@ def bandlimited_leg(P, args, flags):
         dH = (d.H - h).abs().max().item()
         dE = (torch.linalg.eigvalsh(d.H)[:10] - e64).abs().max().item()
         out[name] = {"max_abs_dH_eV": dH, "max_abs_dH_over_kernel": dH / kmax, "max_abs_dE_lowest10_eV": dE}
+    return out
+
+
+def beyond_tda_leg(P, args, ms_tda):
+    """The Hamiltonian beyond the Tamm-Dancoff approximation of the same
+    workload, [[A, B], [-B^H, -conj(A)]] (2 NS x 2 NS, FP64): the resonant
+    block by the Tamm-Dancoff stages, the coupling block by the same stages
+    over every ordered k pair, the lower half by one pass."""
+    import torch
+    import bse_synth as B
+    s = B.make_config(args.config)
+    d = P.DeviceSystem(s, device="cuda:0", H=torch.empty(0, dtype=torch.complex128, device="cuda:0"))
+    ws = P.workspace(P.bse_build_H_full_workspace(d), d.device)
+    H2 = torch.empty((2 * s.ns, 2 * s.ns), dtype=torch.complex128, device=d.device)
+    P.bse_build_H_full(d, H2, ws=ws)  # warm-up
+    torch.cuda.synchronize()
+    P.bse_profile_read(reset=True)
+    P.bse_profile(True)
+    steps = 2
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        P.bse_build_H_full(d, H2, ws=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    P.bse_profile(False)
+    stages = P.bse_profile_read(reset=True)
+    ms = e0.elapsed_time(e1) / steps
+    ns = s.ns
+    rel = (H2[ns:ns + 512, :512] + H2[:512, ns:ns + 512].conj().T).abs().max().item()
+    out = {"matrix": f"{2 * ns} x {2 * ns}", "ms_per_build": ms, "value": (2 * ns) ** 2 / (ms / 1e3),
+           "unit": "H elements/s", "vs_tda_time": ms / ms_tda, "workspace_GB": ws.numel() / 1e9,
+           "max_abs_coupling_eV": H2[:ns, ns:].abs().max().item(), "lower_half_relation_dev": rel,
+           "stage_ms": {k: v[0] / steps for k, v in stages.items() if v[1]}}
     return out
 
 

@@ -257,6 +257,25 @@ int bse_autotune(const bse_system *sys, int nsys, int precision, int flags, cons
 int bse_autotune_last(bse_tuning *tried, int max_tried);
 
 /*
+ * The Bethe-Salpeter Hamiltonian beyond the Tamm-Dancoff approximation in the
+ * optical limit (Sec. II.C and the appendix: e-h states (v k, c k) and h-e
+ * states (c k, v k), whose kernel rows carry the opposite occupation factor):
+ *   H2 = [[A, B], [-B^H, -conj(A)]],  A = the H of bse_build_H,
+ *   B[(k v c)][(k' v' c')] = c (2 Vbar - D) between (v k, c k) and (c' k', v' k'):
+ *     Vbar = sum_{G != 0} conj(n_{vk,ck}(G)) v(G) n_{c'k',v'k'}(G),
+ *     D    = sum_{G,G'} conj(n_{vk,c'k'}(G)) W_GG'(k'-k) n_{ck,v'k'}(G').
+ * The lower blocks follow from the upper ones for Hermitian,
+ * time-reversal-consistent W, a q = 0 sphere closed under G -> -G (else
+ * BSE_ERR_SHAPE) and v(-G) = v(G).  H2: DEVICE [2 NS][2 NS] complex, eV,
+ * every element written; sys->H is not used.  FP64 only (else
+ * BSE_ERR_UNSUPPORTED), sys->qexc = 0 (else BSE_ERR_UNSUPPORTED); flags 0,
+ * BSE_VALIDATE, BSE_PERSISTENT.  ws: bse_build_H_full_workspace(sys) bytes.
+ */
+int bse_build_H_full(const bse_system *sys, double *H2, int precision, int flags, void *ws, size_t ws_bytes,
+                     void *stream);
+size_t bse_build_H_full_workspace(const bse_system *sys);
+
+/*
  * Transition dipoles of the optical limit (Sec. II.B: for q -> 0 the pair
  * density n_{vk,ck}(0) tends to -i q.<u_vk|grad|u_ck>/(e_ck - e_vk); the
  * spectrum of Sec. II.C pairs each exciton with that factor per unit |q|):

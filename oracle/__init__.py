@@ -238,6 +238,44 @@ def build_H_full(sys, separable=True):
     return H
 
 
+def coupling_blocks(sys, blocks, separable=True):
+    """Blocks (k, k') of the coupling block B of ``build_H_full`` (e-h row
+    (v k, c k), h-e column (c' k', v' k')), each [nv*nc][nv*nc] in eV, rows
+    (v, c) and columns (v', c'):
+
+      B = c (2 Vbar - D),
+      Vbar = sum_{G != 0} conj(n_{vk,ck}(G)) v(G) n_{c'k',v'k'}(G),
+      D    = sum_{G,G'} conj(n_{vk,c'k'}(G)) W_GG'(q) n_{ck,v'k'}(G'),  k' - k = q + G0,
+
+    from the direct sums of the pair density (Eqs. V_eh and W_SS)."""
+    blocks = [(int(a), int(b)) for a, b in np.asarray(blocks).reshape(-1, 2)]
+    nk, nv, nc = sys.nk, sys.nv, sys.nc
+    nt = nv * nc
+    c = HARTREE_EV / (nk * sys.omega_cell)
+    ng0 = int(sys.ng[0])
+    v0 = np.array(sys.vx[:ng0], dtype=np.float64)
+    v0[np.all(sys.gvec[0, :ng0] == 0, axis=1)] = 0.0
+    ks = sorted({k for b in blocks for k in b})
+    eh = [(k, a, k, nv + b) for k in ks for a in range(nv) for b in range(nc)]   # n_{vk, ck}
+    he = [(k, nv + b, k, a) for k in ks for a in range(nv) for b in range(nc)]   # n_{ck, vk}, rows (v, c)
+    Xe = pair_density_items(sys, eh, separable)[:, :ng0].reshape(len(ks), nt, ng0)
+    Xh = pair_density_items(sys, he, separable)[:, :ng0].reshape(len(ks), nt, ng0)
+    at = {k: i for i, k in enumerate(ks)}
+    out = np.zeros((len(blocks), nt, nt), dtype=np.complex128)
+    for bi, (ka, kb) in enumerate(blocks):
+        iq, _ = fold(sys.kmesh, ka, kb)
+        ng = int(sys.ng[iq])
+        it = [(ka, a, kb, nv + b) for a in range(nv) for b in range(nc)]      # n_{vk, c'k'}
+        it += [(ka, nv + b, kb, a) for b in range(nc) for a in range(nv)]     # n_{ck, v'k'}
+        n = pair_density_items(sys, it, separable)[:, :ng]
+        rvc = n[:nt].reshape(nv, nc, ng)
+        rcv = n[nt:].reshape(nc, nv, ng)
+        D = np.einsum("axg,gh,cbh->acbx", np.conj(rvc), sys.W[iq, :ng, :ng], rcv).reshape(nt, nt)
+        V = (np.conj(Xe[at[ka]]) * v0) @ Xh[at[kb]].T
+        out[bi] = c * (2.0 * V - D)
+    return out
+
+
 def exciton_energies(H, n=10):
     """Lowest n eigenvalues of the Hermitian H (LAPACK zheevd through numpy)."""
     return np.linalg.eigvalsh(H)[:n]

@@ -47,7 +47,7 @@ class bse_system(ctypes.Structure):
 
 SYMBOLS = ["bse_workspace_size", "bse_pair_density", "bse_build_H", "bse_build_H_backward",
            "bse_autotune", "bse_autotune_last", "bse_transition_dipoles", "bse_transition_dipoles_workspace",
-           "bse_spectrum", "bse_screening", "bse_screening_workspace", "bse_haydock_spectrum", "bse_haydock_workspace", "bse_spectrum_noalloc", "bse_profile", "bse_profile_read", "bse_set_chunk_budget", "bse_release_host_state",
+           "bse_spectrum", "bse_screening", "bse_screening_workspace", "bse_haydock_spectrum", "bse_haydock_workspace", "bse_spectrum_noalloc", "bse_build_H_full", "bse_build_H_full_workspace", "bse_profile", "bse_profile_read", "bse_set_chunk_budget", "bse_release_host_state",
            "bse_last_error"]
 STAGES = ["vscale", "pd_exch", "pd_vv", "pd_cc", "exchange", "direct1", "direct2", "mirror", "rotate", "tr_fill", "to_f32", "split_w"]
 
@@ -82,6 +82,10 @@ def lib():
         L.bse_screening.restype = I
         L.bse_screening_workspace.argtypes = [P]
         L.bse_screening_workspace.restype = S
+        L.bse_build_H_full.argtypes = [P, P, I, I, P, S, P]
+        L.bse_build_H_full.restype = I
+        L.bse_build_H_full_workspace.argtypes = [P]
+        L.bse_build_H_full_workspace.restype = S
         L.bse_haydock_spectrum.argtypes = [I, P, P, I, I, I, D, I, D, D, D, P, P, P, S, P]
         L.bse_haydock_spectrum.restype = I
         L.bse_haydock_workspace.argtypes = [I, I, I]
@@ -383,6 +387,29 @@ def bse_spectrum(E, A, d, nk, omega_cell, nw, w0_eV, w1_eV, eta_eV, ws=None, str
 def bse_set_chunk_budget(nbytes=0):
     """Bytes of per-pair arrays per chunk of k pairs (0: the library default)."""
     _check(lib().bse_set_chunk_budget(int(nbytes)))
+
+
+def bse_build_H_full_workspace(system: DeviceSystem) -> int:
+    st = system.struct()
+    n = lib().bse_build_H_full_workspace(ctypes.byref(st))
+    if n == 0:
+        raise BseError(-1, bse_last_error())
+    return int(n)
+
+
+def bse_build_H_full(system: DeviceSystem, H2=None, flags=0, ws=None, stream=None):
+    """The Hamiltonian beyond the Tamm-Dancoff approximation, [[A, B],
+    [-B^H, -conj(A)]] (complex128 [2 NS][2 NS] on the GPU), FP64."""
+    import torch
+    ns = system.ns
+    if H2 is None:
+        H2 = torch.empty((2 * ns, 2 * ns), dtype=torch.complex128, device=system.device)
+    if ws is None:
+        ws = workspace(bse_build_H_full_workspace(system), system.device)
+    st = system.struct()
+    _check(lib().bse_build_H_full(ctypes.byref(st), _ptr(H2), BSE_FP64, int(flags), _ptr(ws), ws.numel(),
+                                  _stream(stream)))
+    return H2
 
 
 def bse_screening_workspace(system: DeviceSystem) -> int:

@@ -197,6 +197,11 @@ struct Plan {
   int qexc = 0;                    // exciton momentum Q (q-mesh index)
   std::vector<int> kq;             // per k: mesh index of k + Q
   int g0x = 0;                     // position of G = 0 in the sphere of Q (-1: absent)
+  // coupling block of the beyond-TDA matrix: every ordered pair, rows (v, c') and (c, v')
+  bool coupling = false;
+  int ldh = 0;                     // row stride of the output matrix
+  int rv_rows = 0, rc_rows = 0;    // rows per pair of RV / Z and of RC
+  std::vector<int> inv0;           // coupling: position of -G in the q = 0 sphere
   std::vector<int> qbar, trmap;    // time-reversal partner of q; sphere map t - m
   bool tr_closed = true;
   std::vector<int> ktr;            // per k: kbar | K << 24 (grid axes)
@@ -212,6 +217,7 @@ struct Plan {
   int kpad = 0;                    // ng_max rounded up to a multiple of 32
   // byte offsets inside the system's region of the workspace
   size_t o_gpack = 0, o_ng = 0, o_pairs = 0, o_qs = 0, o_plex = 0, o_qbar = 0, o_trmap = 0, o_ktr = 0, o_kq = 0;
+  size_t o_inv0 = 0, o_Xb = 0;     // coupling only
   size_t tables = 0, o_vs = 0, o_X = 0, o_RV = 0, o_RC = 0, o_Z = 0, o_dWraw = 0, total = 0;
   size_t o_ut = 0;   // rotated wave functions (rot only)
   size_t o_u32 = 0;  // FP32 copy of the wave functions in the frame (pd32 only)
@@ -246,6 +252,8 @@ struct BatchOpts {
   bool tr = false;        // time-reversal images gathered (BSE_TIME_REVERSAL)
   bool pd32 = false;      // FP32 pair densities where the one-lane-per-line kernel applies
   bool mixed = false;     // split buffers of the mixed-precision stage 1
+  bool coupling = false;  // the coupling block of the beyond-TDA matrix (FP64, Q = 0)
+  int ldh = 0;            // row stride of the output (0: NS)
 };
 
 // Frame, spheres, windows, exchange jobs and time-reversal maps of one system.
@@ -377,8 +385,9 @@ int make_geometry(const bse_system* s, Plan& P, bool need_w = true) {
 }
 
 // Bytes of the per-pair arrays of one pair.
-size_t pair_bytes(const bse_system* s, bool mixed) {
+size_t pair_bytes(const bse_system* s, bool mixed, bool coupling = false) {
   const size_t ngm = (size_t)s->ng_max, kpad = (ngm + 31) / 32 * 32;
+  if (coupling) return sizeof(double2) * ngm * 3 * (size_t)s->nv * s->nc;  // RV, RC and Z rows
   size_t b = sizeof(double2) * ngm * (2 * (size_t)s->nv * s->nv + (size_t)s->nc * s->nc);
   if (mixed) b += (size_t)s->nv * s->nv * 4 * kpad * sizeof(float);
   return b;
@@ -388,14 +397,19 @@ size_t pair_bytes(const bse_system* s, bool mixed) {
 // and the workspace layout.  `sys` tags the jobs and fill items.
 int plan_pairs(const bse_system* s, Plan& P, const BatchOpts& opt, int nchunk, int sys) {
   const int nk = P.nk, nv = P.nv, nc = P.nc;
-  const long long npl = (long long)nk * (nk + 1) / 2;
+  P.coupling = opt.coupling;
+  P.ldh = opt.ldh > 0 ? opt.ldh : P.ns;
+  P.rv_rows = P.coupling ? nv * nc : nv * nv;
+  P.rc_rows = P.coupling ? nc * nv : nc * nc;
+  // the coupling block has no symmetry between (k, k') and (k', k): every ordered pair
+  const long long npl = P.coupling ? (long long)nk * nk : (long long)nk * (nk + 1) / 2;
   if (npl > (1LL << 30)) return fail(BSE_ERR_SHAPE, "too many k pairs (%lld)", npl);
   const int np = (int)npl;
-  // lexicographic pairs (ka, kb), ka <= kb
+  // lexicographic pairs (ka, kb), ka <= kb (coupling: every kb)
   auto lex = [nk](long long a, long long b) { return (int)(a * nk - a * (a - 1) / 2 + (b - a)); };
   std::vector<int2> lp(np);
   for (int a = 0, i = 0; a < nk; ++a)
-    for (int b = a; b < nk; ++b) lp[i++] = make_int2(a, b);
+    for (int b = P.coupling ? 0 : a; b < nk; ++b) lp[i++] = make_int2(a, b);
   // units: a transformed pair and, with time reversal, the image gathered from it
   struct Unit {
     int rep, img, mode;
@@ -460,7 +474,7 @@ int plan_pairs(const bse_system* s, Plan& P, const BatchOpts& opt, int nchunk, i
     K.p0 = next;
     K.np = (int)pr.size();
     P.maxcp = std::max(P.maxcp, K.np);
-    if ((long long)K.np * std::max(nv * nv, nc * nc) >= (1LL << 31) / std::max(P.ng_max, 1))
+    if ((long long)K.np * std::max(P.rv_rows, P.rc_rows) >= (1LL << 31) / std::max(P.ng_max, 1))
       return fail(BSE_ERR_SHAPE, "a chunk of %d k pairs is too large", K.np);
     std::vector<int> cnt(nk, 0);
     for (size_t i = 0; i < pr.size(); ++i) {
@@ -480,6 +494,11 @@ int plan_pairs(const bse_system* s, Plan& P, const BatchOpts& opt, int nchunk, i
     for (const Unit* u : cu[c]) {
       const int g = g_of_lex[u->rep], loc = g - next;
       const int4 q4 = P.pairs[g];
+      if (P.coupling) {  // n_{vk, c'k'} and n_{ck, v'k'}
+        K.jv.push_back(PdJob{q4.x, q4.y, q4.w, q4.z, 0, nv, nv | (nc << 8), loc * nv * nc});
+        K.jc.push_back(PdJob{q4.x, q4.y, q4.w, q4.z, nv, 0, nc | (nv << 8), loc * nc * nv});
+        continue;
+      }
       K.jv.push_back(PdJob{q4.x, q4.y, q4.w, q4.z, 0, 0, nv | (nv << 8), loc * nv * nv});
       if (P.qexc == 0) {
         K.jc.push_back(PdJob{q4.x, q4.y, q4.w, q4.z, nv, nv, nc | (nc << 8), loc * nc * nc});
@@ -498,7 +517,7 @@ int plan_pairs(const bse_system* s, Plan& P, const BatchOpts& opt, int nchunk, i
     // stage-1 tiles per q group: rows = pairs(q) * nv^2, columns = ng(q)
     for (int q = 0; q < nk; ++q) {
       if (!cnt[q]) continue;
-      const int rows = cnt[q] * nv * nv;
+      const int rows = cnt[q] * P.rv_rows;
       const int mt = (rows + 63) / 64, ntl = (P.ng[q] + 63) / 64;
       for (int i = 0; i < mt; ++i)
         for (int j = 0; j < ntl; ++j) K.s1.push_back(S1Tile{q, i, j, sys});
@@ -509,7 +528,7 @@ int plan_pairs(const bse_system* s, Plan& P, const BatchOpts& opt, int nchunk, i
           for (int j = 0; j < T2; ++j) K.rvt.push_back(make_int4(q, i, j, 0));
       }
     }
-    K.d2items = K.np * ((nv * nv + 15) / 16) * ((nc * nc + 15) / 16);
+    K.d2items = K.np * ((P.rv_rows + 15) / 16) * ((P.rc_rows + 15) / 16);
     next += K.np;
   }
   // exchange tiles: every 64 x 64 tile that holds an entry of a block k <= k'
@@ -521,13 +540,32 @@ int plan_pairs(const bse_system* s, Plan& P, const BatchOpts& opt, int nchunk, i
   for (int i = 0; i < T; ++i)
     for (int j = 0; j < T; ++j) {
       const int last_col = std::min(P.ns, 64 * (j + 1)) - 1;
-      if ((64 * i) / P.nt <= last_col / P.nt) P.xt.push_back(HTile{i, j, sys, 0});
+      if (P.coupling || (64 * i) / P.nt <= last_col / P.nt) P.xt.push_back(HTile{i, j, sys, 0});
     }
-  // mirror tiles: 32 x 32 destination tiles on or below the diagonal
+  // mirror tiles: 32 x 32 destination tiles on or below the diagonal (none for the coupling block)
   P.mt.clear();
   const int T32 = (P.ns + 31) / 32;
-  for (int i = 0; i < T32; ++i)
+  for (int i = 0; i < T32 && !P.coupling; ++i)
     for (int j = 0; j <= i; ++j) P.mt.push_back(HTile{i, j, sys, 0});
+  // coupling: -G of every G of the q = 0 sphere (the h-e exchange densities)
+  P.inv0.clear();
+  if (P.coupling) {
+    const int n0 = P.ng[0];
+    P.inv0.assign(n0, -1);
+    for (int g = 0; g < n0; ++g) {
+      int a1, a2, a3;
+      unpack_m(P.gpack[g], a1, a2, a3);
+      for (int h = 0; h < n0; ++h) {
+        int b1, b2, b3;
+        unpack_m(P.gpack[h], b1, b2, b3);
+        if (a1 == -b1 && a2 == -b2 && a3 == -b3) {
+          P.inv0[g] = h;
+          break;
+        }
+      }
+      if (P.inv0[g] < 0) return fail(BSE_ERR_SHAPE, "the q = 0 sphere is not closed under G -> -G");
+    }
+  }
 
   // workspace layout
   size_t o = 0;
@@ -545,13 +583,15 @@ int plan_pairs(const bse_system* s, Plan& P, const BatchOpts& opt, int nchunk, i
   P.o_trmap = put(P.trmap.size() * sizeof(int));
   P.o_ktr = put(P.ktr.size() * sizeof(int));
   P.o_kq = put(P.kq.size() * sizeof(int));
+  P.o_inv0 = put(P.inv0.size() * sizeof(int));
   P.tables = o;
   const size_t mc = (size_t)P.maxcp;
   P.o_vs = put((size_t)P.ng_max * sizeof(double));
   P.o_X = put((size_t)P.ns * P.ng_max * sizeof(double2));
-  P.o_RV = put(mc * nv * nv * P.ng_max * sizeof(double2));
-  P.o_RC = put(mc * nc * nc * P.ng_max * sizeof(double2));
-  P.o_Z = put(mc * nv * nv * P.ng_max * sizeof(double2));
+  P.o_RV = put(mc * P.rv_rows * P.ng_max * sizeof(double2));
+  P.o_RC = put(mc * P.rc_rows * P.ng_max * sizeof(double2));
+  P.o_Z = put(mc * P.rv_rows * P.ng_max * sizeof(double2));
+  if (P.coupling) P.o_Xb = put((size_t)P.ns * P.ng_max * sizeof(double2));
   if (P.rot) P.o_ut = put((size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * sizeof(double2));
   P.kpad = (P.ng_max + 31) / 32 * 32;
   P.mixed = opt.mixed;
@@ -581,6 +621,7 @@ void put_tables(const Plan& P, std::vector<char>& buf, size_t base) {
   cp(P.o_trmap, P.trmap.data(), P.trmap.size() * sizeof(int));
   cp(P.o_ktr, P.ktr.data(), P.ktr.size() * sizeof(int));
   cp(P.o_kq, P.kq.data(), P.kq.size() * sizeof(int));
+  cp(P.o_inv0, P.inv0.data(), P.inv0.size() * sizeof(int));
 }
 
 PdArgs pd_args(const Plan& P, const bse_system* s, char* region) {
@@ -630,6 +671,11 @@ GemmArgs gemm_args(const Plan& P, const bse_system* s, char* region, int c) {
   g.Ws = P.mixed ? region + P.o_Ws : nullptr;
   g.kpad = P.kpad;
   g.RVs = P.mixed ? region + P.o_RVs : nullptr;
+  g.ldh = P.ldh;
+  g.rv_rows = P.rv_rows;
+  g.rc_rows = P.rc_rows;
+  g.coupling = P.coupling;
+  g.Xb = P.coupling ? reinterpret_cast<const double2*>(region + P.o_Xb) : nullptr;
   return g;
 }
 
@@ -718,7 +764,7 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
     int rc = check_system(&sys[i]);
     if (rc) return rc;
     const double nk = (double)sys[i].kmesh[0] * sys[i].kmesh[1] * sys[i].kmesh[2];
-    bytes += nk * (nk + 1) / 2 * (double)pair_bytes(&sys[i], opt.mixed);
+    bytes += (opt.coupling ? nk * nk : nk * (nk + 1) / 2) * (double)pair_bytes(&sys[i], opt.mixed, opt.coupling);
   }
   const int nchunk = (int)std::min(1e6, std::max(1.0, std::ceil(bytes / (double)g_chunk_budget.load())));
   for (int i = 0; i < nsys; ++i) {
@@ -828,8 +874,8 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
 // tables (hashed by content), the options and the k tile.
 std::string plan_key(const bse_system* sys, int nsys, int ktile, const BatchOpts& o) {
   std::string k = std::to_string(nsys) + (o.backward ? "b" : "f") + (o.project ? "p" : "") + (o.tr ? "t" : "") +
-                  (o.pd32 ? "s" : "") + (o.mixed ? "m" : "") + std::to_string(ktile) + "c" +
-                  std::to_string(g_chunk_budget.load());
+                  (o.pd32 ? "s" : "") + (o.mixed ? "m" : "") + (o.coupling ? "x" : "") + "l" + std::to_string(o.ldh) +
+                  std::to_string(ktile) + "c" + std::to_string(g_chunk_budget.load());
   for (int i = 0; i < nsys; ++i) {
     const bse_system& s = sys[i];
     const int nk = s.kmesh[0] * s.kmesh[1] * s.kmesh[2];
@@ -1071,6 +1117,13 @@ int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& 
   const HTile* xt = reinterpret_cast<const HTile*>(ws + B.o_xt);
   const HTile* mt = reinterpret_cast<const HTile*>(ws + B.o_mt);
   if ((rc = run_pd(B, ws, 0, 0, tn, st))) return rc;
+  for (int i = 0; i < nsys; ++i) {  // coupling block: the h-e exchange rows from the e-h ones
+    const Plan& P = B.P[i];
+    if (!P.coupling) continue;
+    char* region = ws + B.base[i];
+    HIP_TRY(launch_xbar(reinterpret_cast<const double2*>(region + P.o_X), reinterpret_cast<const int*>(region + P.o_inv0),
+                        P.ns, P.ng[0], P.ng_max, reinterpret_cast<double2*>(region + P.o_Xb), st));
+  }
   HIP_TRY(stage(BSE_STAGE_EXCHANGE, st, [&] { return launch_exchange(g0, xt, (int)B.xt.size(), precision, st); }));
   for (int c = 0; c < (int)B.C.size(); ++c) {
     const BatchChunk& K = B.C[c];
@@ -1389,6 +1442,25 @@ int api_spectrum_args(int ns, int nlam, const double* E, const double* A, const 
 }
 }  // namespace bse
 
+// The beyond-TDA matrix: the resonant block by the Tamm-Dancoff build and
+// the coupling block by the same stages over every ordered k pair, both
+// written into H2 (row stride 2 NS), then the lower half.
+int full_batches(const bse_system* sys, int precision, int flags, const Batch** BA, const Batch** BB) {
+  if (!sys) return fail(BSE_ERR_INVALID_ARG, "system pointer is NULL");
+  if (precision != BSE_FP64) return fail(BSE_ERR_UNSUPPORTED, "the beyond-TDA build is FP64 only");
+  if (flags & ~(BSE_VALIDATE | BSE_PERSISTENT)) return fail(BSE_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+  if (sys->qexc != 0) return fail(BSE_ERR_UNSUPPORTED, "the beyond-TDA build needs exciton momentum Q = 0");
+  const long long ns = (long long)sys->kmesh[0] * sys->kmesh[1] * sys->kmesh[2] * sys->nv * sys->nc;
+  if (ns < 1 || 2 * ns > (1LL << 20)) return fail(BSE_ERR_SHAPE, "2 NS = %lld out of range", 2 * ns);
+  BatchOpts a;
+  a.ldh = (int)(2 * ns);
+  BatchOpts b = a;
+  b.coupling = true;
+  int rc = cached_batch(sys, 1, Tune{}, a, BA);
+  if (!rc) rc = cached_batch(sys, 1, Tune{}, b, BB);
+  return rc;
+}
+
 extern "C" {
 
 size_t bse_workspace_size(const bse_system* sys, int nsys, int precision, int flags) {
@@ -1525,6 +1597,41 @@ int bse_build_H(const bse_system* sys, int nsys, int precision, int flags, void*
     if ((rc = validate(B, sys, static_cast<char*>(ws), st))) return rc;
   }
   return run_build(B, sys, precision, tn, static_cast<char*>(ws), st);
+}
+
+size_t bse_build_H_full_workspace(const bse_system* sys) {
+  const Batch *BA = nullptr, *BB = nullptr;
+  if (full_batches(sys, BSE_FP64, 0, &BA, &BB)) return 0;
+  return std::max(BA->total, BB->total);
+}
+
+int bse_build_H_full(const bse_system* sys, double* H2, int precision, int flags, void* ws, size_t ws_bytes,
+                     void* stream) {
+  if (!H2 || !ws) return fail(BSE_ERR_INVALID_ARG, "H2 / ws is NULL");
+  const Batch *BA = nullptr, *BB = nullptr;
+  int rc = full_batches(sys, precision, flags, &BA, &BB);
+  if (rc) return rc;
+  // (the plan cache keeps its four most recent plans, so the second lookup
+  // cannot evict the first)
+  const Batch& A = *BA;
+  const Batch& Bc = *BB;
+  const size_t need = std::max(A.total, Bc.total);
+  if (ws_bytes < need) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  const int ns = A.P[0].ns;
+  bse_system s = *sys;
+  s.H = H2;
+  Tune tn;
+  if (flags & BSE_PERSISTENT) tn.persist = 1;
+  if (flags & BSE_VALIDATE) {
+    if ((rc = upload_batch(A, &s, BSE_FP64, w, st)) || (rc = validate(A, &s, w, st))) return rc;
+  }
+  if ((rc = run_build(A, &s, BSE_FP64, tn, w, st))) return rc;
+  s.H = H2 + 2 * (size_t)ns;  // the coupling block starts at column NS
+  if ((rc = run_build(Bc, &s, BSE_FP64, tn, w, st))) return rc;
+  HIP_TRY(launch_full_lower(reinterpret_cast<double2*>(H2), ns, st));
+  return BSE_OK;
 }
 
 int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, double* deps, double* dX,

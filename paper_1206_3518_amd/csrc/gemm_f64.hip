@@ -21,7 +21,7 @@ __global__ __launch_bounds__(256) void k_exchange(const GemmArgs* __restrict__ g
   const GemmArgs g = gs[tl.sys];
   const int r0 = tl.i * TM, c0 = tl.j * TN;
   d4 cre[2][2], cim[2][2];
-  tile_gemm<true, true>(g.X, g.ng_max, r0, g.ns, g.X, g.ng_max, c0, g.ns, g.ngx, cre, cim);
+  tile_gemm<true, true>(g.X, g.ng_max, r0, g.ns, g.Xb ? g.Xb : g.X, g.ng_max, c0, g.ns, g.ngx, cre, cim);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
   const double s = 2.0 * g.cpref;
 #pragma unroll
@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256) void k_exchange(const GemmArgs* __restrict__ g
       for (int r = 0; r < 4; ++r) {
         const int row = r0 + wr * 32 + i * 16 + 4 * r + (lane >> 4);
         const int col = c0 + wc * 32 + j * 16 + (lane & 15);
-        if (row < g.ns && col < g.ns) gst(g.H, (size_t)row * g.ns + col, make_double2(s * cre[i][j][r], s * cim[i][j][r]));
+        if (row < g.ns && col < g.ns) gst(g.H, (size_t)row * g.ldh + col, make_double2(s * cre[i][j][r], s * cim[i][j][r]));
       }
 }
 
@@ -48,7 +48,7 @@ hipError_t launch_exchange(const GemmArgs* gs, const HTile* tiles, int ntiles, i
 __global__ __launch_bounds__(256) void k_direct_s1(const GemmArgs* __restrict__ gs, const S1Tile* __restrict__ tiles) {
   const S1Tile tl = tiles[blockIdx.x];
   const GemmArgs g = gs[tl.sys];
-  const int nv2 = g.nv * g.nv;
+  const int nv2 = g.rv_rows;
   const int row_base = (gbl(g.qstart)[tl.iq] - g.p0) * nv2;  // rows of the chunk
   const int rows = (gbl(g.qstart)[tl.iq + 1] - gbl(g.qstart)[tl.iq]) * nv2;
   const int K = gbl(g.ng)[tl.iq];
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void k_direct_s2(const GemmArgs* __restrict__ 
   if (item >= nitems) return;
   const int sys = item_system(d2off, nsys, item);
   const GemmArgs g = gs[sys];
-  const int nv2 = g.nv * g.nv, nc2 = g.nc * g.nc;
+  const int nv2 = g.rv_rows, nc2 = g.rc_rows;
   const int tiles_i = (nv2 + 15) / 16, tiles_j = (nc2 + 15) / 16;
   const int loc = item - d2off[sys];
   const int per = tiles_i * tiles_j;
@@ -126,17 +126,19 @@ __global__ __launch_bounds__(256) void k_direct_s2(const GemmArgs* __restrict__ 
         dr += hw.x;
         di += hw.y;
       }
-      const int v = i / g.nv, v2 = i % g.nv, c = j / g.nc, c2 = j % g.nc;
+      // direct term: rows (v, v') and (c, c'); coupling block: rows (v, c') and (c, v')
+      const int v = g.coupling ? i / g.nc : i / g.nv, v2 = g.coupling ? j % g.nv : i % g.nv;
+      const int c = g.coupling ? j / g.nv : j / g.nc, c2 = g.coupling ? i % g.nc : j % g.nc;
       const size_t S = ((size_t)ka * g.nv + v) * g.nc + c;
       const size_t S2 = ((size_t)kb * g.nv + v2) * g.nc + c2;
-      double2 h = gld(g.H, S * g.ns + S2);
+      double2 h = gld(g.H, S * g.ldh + S2);
       h.x -= g.cpref * dr;
       h.y -= g.cpref * di;
-      if (S == S2) {  // e_{c,k+Q} - e_{v,k}
+      if (S == S2 && !g.coupling) {  // e_{c,k+Q} - e_{v,k}
         const int kc = g.kq ? gbl(g.kq)[ka] : ka;
         h.x += gbl(g.eps)[(size_t)kc * g.nb + g.nv + c] - gbl(g.eps)[(size_t)ka * g.nb + v];
       }
-      gst(g.H, S * g.ns + S2, h);
+      gst(g.H, S * g.ldh + S2, h);
     }
   }
 }
@@ -159,12 +161,13 @@ __global__ __launch_bounds__(256) void k_mirror(const GemmArgs* __restrict__ gs,
   const GemmArgs g = gs[tl.sys];
   double2* H = g.H;
   const int ns = g.ns, nt = g.nt;
+  const size_t ld = g.ldh;
   const int bi = tl.i, bj = tl.j;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
 #pragma unroll
   for (int r = ty; r < 32; r += 8) {
     const int sr = bj * 32 + r, sc = bi * 32 + tx;
-    tile[r][tx] = (sr < ns && sc < ns) ? gld(H, (size_t)sr * ns + sc) : make_double2(0.0, 0.0);
+    tile[r][tx] = (sr < ns && sc < ns) ? gld(H, (size_t)sr * ld + sc) : make_double2(0.0, 0.0);
   }
   __syncthreads();
 #pragma unroll
@@ -172,7 +175,7 @@ __global__ __launch_bounds__(256) void k_mirror(const GemmArgs* __restrict__ gs,
     const int dr = bi * 32 + r, dc = bj * 32 + tx;
     if (dr < ns && dc < ns && dr / nt > dc / nt) {
       const double2 v = tile[tx][r];
-      gst(H, (size_t)dr * ns + dc, make_double2(v.x, -v.y));
+      gst(H, (size_t)dr * ld + dc, make_double2(v.x, -v.y));
     }
   }
 }
@@ -180,6 +183,71 @@ __global__ __launch_bounds__(256) void k_mirror(const GemmArgs* __restrict__ gs,
 hipError_t launch_mirror(const GemmArgs* gs, const HTile* tiles, int ntiles, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_mirror, dim3(ntiles), dim3(256), 0, st, gs, tiles);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ beyond Tamm-Dancoff
+
+// Exchange B operand of the coupling block: the h-e densities n_{ck,vk}(G) =
+// conj(n_{vk,ck}(-G)), scaled like X (v is even in G).
+__global__ void k_xbar(const double2* __restrict__ X, const int* __restrict__ inv, int ns, int ng0, int ng_max,
+                       double2* __restrict__ Xb) {
+  const size_t n = (size_t)ns * ng_max;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += (size_t)gridDim.x * blockDim.x) {
+    const int g = (int)(id % ng_max);
+    double2 v = make_double2(0.0, 0.0);
+    if (g < ng0) {
+      const double2 x = gld(X, id - g + gbl(inv)[g]);
+      v = make_double2(x.x, -x.y);
+    }
+    gst(Xb, id, v);
+  }
+}
+
+hipError_t launch_xbar(const double2* X, const int* inv, int ns, int ng0, int ng_max, double2* Xb, hipStream_t st) {
+  hipLaunchKernelGGL(k_xbar, dim3(4096), dim3(256), 0, st, X, inv, ns, ng0, ng_max, Xb);
+  return hipGetLastError();
+}
+
+// Lower half of H2 = [[A, B], [-B^H, -conj(A)]] (the h-e rows of Sec. II.C's
+// basis carry the opposite occupation factor; with Hermitian,
+// time-reversal-consistent W the h-e kernel blocks are those of the e-h rows
+// conjugated).  32 x 32 tiles through LDS for the transposed block.
+__global__ __launch_bounds__(256) void k_full_lower(double2* __restrict__ H2, int ns) {
+  __shared__ double2 tile[32][33];
+  const int T = (ns + 31) / 32;
+  const int bi = blockIdx.x / T, bj = blockIdx.x % T;
+  const size_t ld = 2 * (size_t)ns;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  // -conj(A) into the bottom-right block
+#pragma unroll
+  for (int r = ty; r < 32; r += 8) {
+    const int i = bi * 32 + r, j = bj * 32 + tx;
+    if (i < ns && j < ns) {
+      const double2 a = gld(H2, (size_t)i * ld + j);
+      gst(H2, (size_t)(ns + i) * ld + ns + j, make_double2(-a.x, a.y));
+    }
+  }
+  // -B^H into the bottom-left block: element (i, j) from B[j][i]
+#pragma unroll
+  for (int r = ty; r < 32; r += 8) {
+    const int sr = bj * 32 + r, sc = bi * 32 + tx;
+    tile[r][tx] = (sr < ns && sc < ns) ? gld(H2, (size_t)sr * ld + ns + sc) : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = ty; r < 32; r += 8) {
+    const int i = bi * 32 + r, j = bj * 32 + tx;
+    if (i < ns && j < ns) {
+      const double2 b = tile[tx][r];
+      gst(H2, (size_t)(ns + i) * ld + j, make_double2(-b.x, b.y));
+    }
+  }
+}
+
+hipError_t launch_full_lower(double2* H2, int ns, hipStream_t st) {
+  const int T = (ns + 31) / 32;
+  hipLaunchKernelGGL(k_full_lower, dim3(T * T), dim3(256), 0, st, H2, ns);
   return hipGetLastError();
 }
 

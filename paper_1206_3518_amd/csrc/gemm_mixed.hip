@@ -31,7 +31,7 @@ __global__ __launch_bounds__(256) void k_exchange_mx(const GemmArgs* __restrict_
         const int row = r0 + wr * 32 + i * 16 + acc_row(lane, r);
         const int col = c0 + wc * 32 + j * 16 + (lane & 15);
         if (row < g.ns && col < g.ns)
-          gst(g.H, (size_t)row * g.ns + col, make_double2(s * (double)cre[i][j][r], s * (double)cim[i][j][r]));
+          gst(g.H, (size_t)row * g.ldh + col, make_double2(s * (double)cre[i][j][r], s * (double)cim[i][j][r]));
       }
 }
 
@@ -39,7 +39,7 @@ template <int P>
 __global__ __launch_bounds__(256) void k_direct_s1_mx(const GemmArgs* __restrict__ gs, const S1Tile* __restrict__ tiles) {
   const S1Tile tl = tiles[blockIdx.x];
   const GemmArgs g = gs[tl.sys];
-  const int nv2 = g.nv * g.nv;
+  const int nv2 = g.rv_rows;
   const int row_base = (gbl(g.qstart)[tl.iq] - g.p0) * nv2;  // rows of the chunk
   const int rows = (gbl(g.qstart)[tl.iq + 1] - gbl(g.qstart)[tl.iq]) * nv2;
   const int K = gbl(g.ng)[tl.iq];

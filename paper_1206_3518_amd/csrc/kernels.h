@@ -105,6 +105,11 @@ struct GemmArgs {
                         // split type (planes re hi, re lo, im hi, im lo), head left out
   int kpad;             // ng_max rounded up to a multiple of 32
   const void* RVs;      // mixed precision: conj(RV) split, [rows][4][kpad] of the split type
+  int ldh;              // row stride of H (ns, or 2 ns inside the beyond-TDA matrix)
+  int rv_rows, rc_rows; // rows per pair of RV and Z, and of RC (nv^2, nc^2; coupling: nv nc both)
+  int coupling;         // coupling block: RV rows (v, c') = n_{vk,c'k'}, RC rows (c, v') = n_{ck,v'k'},
+                        // output H[(k v c)][(k' v' c')], no transition energies
+  const double2* Xb;    // exchange B operand (coupling: conj(X) at -G); null: X
 };
 
 // The contractions run over a batch: gs is a device array of per-system
@@ -118,6 +123,12 @@ hipError_t launch_direct_s1(const GemmArgs* gs, const S1Tile* tiles, int ntiles,
 // stage 2 is FP64 in every mode (it adds the FP64 q = 0 head when w_head_fp64)
 hipError_t launch_direct_s2(const GemmArgs* gs, const int* d2off, int nsys, int nitems, hipStream_t st);
 hipError_t launch_mirror(const GemmArgs* gs, const HTile* tiles, int ntiles, hipStream_t st);
+// Xb[S][g] = conj(X[S][inv[g]]) for g < ng0 (inv: position of -G in the q = 0
+// sphere), zero past it; ns rows of stride ng_max
+hipError_t launch_xbar(const double2* X, const int* inv, int ns, int ng0, int ng_max, double2* Xb, hipStream_t st);
+// lower half of the beyond-TDA matrix H2 [2ns][2ns] from its upper half:
+// H2[ns+i][ns+j] = -conj(H2[i][j]), H2[ns+i][j] = -conj(H2[j][ns+i])
+hipError_t launch_full_lower(double2* H2, int ns, hipStream_t st);
 // Ws[q][n][pl][k] = part pl of W[q][k][n] for k, n < ng(q), zero elsewhere up
 // to kpad (and at the q = 0 head when head != 0); precision BSE_SPLIT_FP32 or
 // BSE_BF16X3 (parts as in the mixed contractions).

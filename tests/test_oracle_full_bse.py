@@ -102,3 +102,16 @@ def test_coupling_block_full_grid_closed_form():
                             want = c * (2 * Vb - D)
                             got = H[ka * nt + v * nc + c1, ns + kb * nt + v2 * nc + c2]
                             assert abs(got - want) < 1e-12 * max(1.0, abs(want))
+
+
+def test_sampled_coupling_blocks_equal_the_whole_matrix():
+    """The block-by-block coupling oracle (used on large shapes) against the
+    coupling block of the whole beyond-TDA matrix."""
+    for s in (B.make_config(0), small_system(kmesh=(3, 1, 1))):
+        H = O.build_H_full(s)
+        ns, nt = s.ns, s.nv * s.nc
+        blocks = [(a, b) for a in range(s.nk) for b in range(s.nk)]
+        got = O.coupling_blocks(s, blocks)
+        scale = np.abs(H[:ns, ns:]).max()
+        for (a, b), blk in zip(blocks, got):
+            assert np.abs(H[a * nt:(a + 1) * nt, ns + b * nt:ns + (b + 1) * nt] - blk).max() <= 1e-12 * scale
