@@ -142,6 +142,8 @@ def main():
     ap.add_argument("--no-haydock", action="store_true", help="skip the Haydock spectrum leg")
     ap.add_argument("--no-exciton-momentum", action="store_true", help="skip the finite exciton momentum leg")
     ap.add_argument("--no-beyond-tda", action="store_true", help="skip the beyond-Tamm-Dancoff leg")
+    ap.add_argument("--no-point-group", action="store_true",
+                    help="skip the leg with W given at the irreducible q points only")
     ap.add_argument("--no-screening", action="store_true", help="skip the RPA screening leg")
     ap.add_argument("--chunk-budget-gb", type=float, default=32.0,
                     help="GiB of per-pair arrays per chunk of k pairs for the timed build (0: the library "
@@ -352,6 +354,8 @@ def main():
                                                        out.get("lowest_exciton_eV"))
     if not args.no_beyond_tda and len(systems) == 1 and not args.kmesh and args.precision == "fp64":
         out["beyond_tda"] = beyond_tda_leg(P, args, ms)
+    if not args.no_point_group and len(systems) == 1 and not args.kmesh and args.config == 2:
+        out["point_group"] = point_group_leg(P, args, prec, flags, elements)
     if not args.no_screening and args.config == 2 and not args.kmesh:
         out["screening"] = screening_leg(P)
     if not args.no_cpu_baseline:
@@ -519,6 +523,34 @@ def exciton_momentum_leg(P, args, prec, flags, elements, ms_optical, E_optical):
         out["lowest_exciton_eV"] = E.tolist()
         if E_optical is not None:
             out["lowest_exciton_shift_vs_optical_eV"] = float(E[0] - E_optical[0])
+    return out
+
+
+def point_group_leg(P, args, prec, flags, elements):
+    """W of the same workload made symmetric under the cubic rotations and
+    time reversal, given once at every q and once at the irreducible q points
+    only (the library reads W(q) through the sphere maps of Sec. III.A); both
+    timed, H compared bit for bit."""
+    import torch
+    import bse_synth as B
+    s = B.with_point_group_W(B.make_config(args.config), proper=True)
+    steps = max(2, args.steps // 2)
+    out = {"group": "cubic rotations + time reversal", "nirr": int(len(s.W_irr)), "nq": int(s.nk),
+           "W_bytes_every_q": int(s.W.nbytes), "W_bytes_irreducible": int(s.W_irr.nbytes)}
+    H = None
+    for name, irr in (("every_q", False), ("irreducible", True)):
+        d = P.DeviceSystem(s, device="cuda:0", irreducible_W=irr)
+        ws = P.workspace(P.bse_workspace_size([d], prec), d.device)
+        ms, _, stages = run_steps(P, [d], prec, flags, ws, steps, 1)
+        torch.cuda.synchronize()
+        out[name] = {"ms_per_step": ms, "value": elements / (ms / 1e3), "unit": "H elements/s",
+                     "stage_ms": {k: v[0] / steps for k, v in stages.items() if v[1]}}
+        if H is None:
+            H = d.H.clone()
+        else:
+            out["bit_identical"] = bool(torch.equal(H, d.H))
+        del d, ws
+    del H
     return out
 
 

@@ -60,6 +60,12 @@ class System:
     seed: int
     qexc: int = 0             # exciton momentum Q as a q-mesh index (0: optical limit);
                               # vx then holds v(Q+G) on the sphere of Q
+    # W from the irreducible q points (with_point_group_W): W_irr [nirr][ng_max][ng_max],
+    # wsrc [Nk][2] = (irreducible index, 1 if conjugated), wmap [Nk][ng_max] = position in
+    # the irreducible sphere of +-T^-1 (G + G0) for each G of the sphere of q (-1: padding)
+    W_irr: Optional[np.ndarray] = None
+    wsrc: Optional[np.ndarray] = None
+    wmap: Optional[np.ndarray] = None
 
     @property
     def nk(self) -> int:
@@ -308,6 +314,139 @@ def coulomb_table(sys: System) -> np.ndarray:
         p = q_vector(sys.cell, sys.kmesh, iq)[None, :] + sys.gvec[iq, :g] @ b
         out[iq, :g] = coulomb(p, sys.coulomb, sys.slab_L)
     return out
+
+
+# ----------------------------------------------------------------------------
+# point-group symmetry of the q mesh (Sec. III.A)
+
+def point_group(cell: np.ndarray, kmesh, proper: bool = False) -> List[np.ndarray]:
+    """The cubic point-group operations (the 48 signed permutations of the
+    Cartesian axes; with ``proper`` only the 24 rotations, the group of a
+    crystal without inversion) that map the reciprocal lattice and the
+    Gamma-centred mesh onto themselves, as integer matrices M acting on
+    coordinates in the basis of the reciprocal vectors: T q has coordinates
+    M f when q has f.  The identity comes first."""
+    b = reciprocal(cell)                 # rows b_d: q = f @ b
+    n = np.array(kmesh)
+    ops = []
+    for perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+        for sg in range(8):
+            R = np.zeros((3, 3))
+            for i in range(3):
+                R[i, perm[i]] = -1.0 if (sg >> i) & 1 else 1.0
+            if proper and np.linalg.det(R) < 0:
+                continue
+            M = np.linalg.solve(b.T, R @ b.T)  # b^T M = R b^T
+            Mi = np.rint(M)
+            if np.abs(M - Mi).max() > 1e-9:
+                continue
+            Mi = Mi.astype(np.int64)
+            # the mesh i / n maps onto itself: M diag(1/n) i must stay on it
+            if np.any((Mi * n[None, :]) % n[:, None] != 0):
+                continue
+            ops.append(Mi)
+    return ops
+
+
+def irreducible_q(cell: np.ndarray, kmesh, proper: bool = False):
+    """Irreducible q points of the mesh under the point group and time
+    reversal: (ops, reps, assign) with, for every q, assign[q] = (rep, op
+    index, s, G0) such that q = s T_op q_rep + G0 (s = -1: the time-reversed
+    image), G0 in reciprocal-lattice coordinates.  Each irreducible point is
+    the first mesh point of its orbit and maps to itself by the identity."""
+    ops = point_group(cell, kmesh, proper)
+    n = np.array(kmesh)
+    if not (n[0] == n[1] == n[2]):
+        raise ValueError("the cubic point group needs an n x n x n mesh")
+    nk = int(np.prod(n))
+    assign = [None] * nk
+    reps = []
+    for q in range(nk):
+        if assign[q] is not None:
+            continue
+        reps.append(q)
+        iq = ktriplet(kmesh, q)
+        for oi, M in enumerate(ops):
+            for s in (1, -1):
+                # s T q_rep in mesh units: s M i / n (a uniform mesh, so M commutes with 1/n);
+                # the mesh point it folds to, and G0 = q - s T q_rep
+                tm = s * (M @ iq)
+                tgt = kindex(kmesh, tm % n)
+                if assign[tgt] is None:
+                    assign[tgt] = (q, oi, s, ((tm % n) - tm) // n)
+    return ops, reps, assign
+
+
+def _sphere_map(sys: System, ops_inv, q, rep, oi, s, g0):
+    """Position in the sphere of rep of s T^-1 (G + G0) for each G of the
+    sphere of q (-1 past ng(q))."""
+    ng = int(sys.ng[q])
+    if ng != int(sys.ng[rep]):
+        raise ValueError(f"spheres of q = {q} and its irreducible point {rep} differ in size")
+    pos = {tuple(m): g for g, m in enumerate(sys.gvec[rep, :ng])}
+    out = np.full(sys.ng_max, -1, dtype=np.int32)
+    for g in range(ng):
+        m = s * (ops_inv[oi] @ (sys.gvec[q, g].astype(np.int64) + g0))
+        out[g] = pos[tuple(int(x) for x in m)]
+    return out
+
+
+def point_group_maps(sys: System, proper: bool = False):
+    """The index maps that give W at every q from W at the irreducible q
+    points (Sec. III.A): (reps, wsrc [Nk][2], wmap [Nk][ng_max]) with
+    wsrc[q] = (position of the irreducible point in reps, 1 for the
+    time-reversed relation) and wmap[q][G] the position of s T^-1(G + G0) in
+    the sphere of the irreducible point (-1 past ng(q))."""
+    ops, reps, assign = irreducible_q(sys.cell, sys.kmesh, proper)
+    inv = [np.rint(np.linalg.inv(M)).astype(np.int64) for M in ops]
+    at = {q: i for i, q in enumerate(reps)}
+    wsrc = np.zeros((sys.nk, 2), dtype=np.int32)
+    wmap = np.full((sys.nk, sys.ng_max), -1, dtype=np.int32)
+    for q in range(sys.nk):
+        rep, oi, s, g0 = assign[q]
+        wsrc[q] = (at[rep], 1 if s < 0 else 0)
+        wmap[q] = _sphere_map(sys, inv, q, rep, oi, s, g0)
+    return reps, wsrc, wmap
+
+
+def with_point_group_W(sys: System, proper: bool = False) -> System:
+    """The same inputs with W made symmetric under the cubic point group (or
+    its rotations only, ``proper``) and time reversal, stored both ways: W at
+    every q, and W_irr at the irreducible q points with the maps of
+    ``point_group_maps``.  W at each irreducible point is the average of W
+    over the operations that leave that point in place (images taken as in
+    Sec. III.A); every other W(q) is its image through the maps."""
+    ops, reps, assign = irreducible_q(sys.cell, sys.kmesh, proper)
+    inv = [np.rint(np.linalg.inv(M)).astype(np.int64) for M in ops]
+    reps2, wsrc, wmap = point_group_maps(sys, proper)
+    assert reps2 == reps
+    n = np.array(sys.kmesh)
+    ngm = sys.ng_max
+
+    def image(Wr, mp, ng, conj):
+        X = np.zeros((ngm, ngm), dtype=np.complex128)
+        X[:ng, :ng] = Wr[np.ix_(mp[:ng], mp[:ng])]
+        return np.conj(X) if conj else X
+
+    W_irr = np.zeros((len(reps), ngm, ngm), dtype=np.complex128)
+    for i, q in enumerate(reps):
+        iq = ktriplet(sys.kmesh, q)
+        ng = int(sys.ng[q])
+        acc = np.zeros((ngm, ngm), dtype=np.complex128)
+        cnt = 0
+        for oi, M in enumerate(ops):
+            for s in (1, -1):
+                tm = s * (M @ iq)
+                if kindex(sys.kmesh, tm % n) != q:
+                    continue
+                acc += image(sys.W[q], _sphere_map(sys, inv, q, q, oi, s, ((tm % n) - tm) // n), ng, s < 0)
+                cnt += 1
+        W_irr[i] = acc / cnt
+    W = np.zeros_like(sys.W)
+    for q in range(sys.nk):
+        W[q] = image(W_irr[wsrc[q, 0]], wmap[q], int(sys.ng[q]), wsrc[q, 1] != 0)
+    tag = "-ibzO" if proper else "-ibz"
+    return dataclasses.replace(sys, W=W, W_irr=W_irr, wsrc=wsrc, wmap=wmap, name=f"{sys.name}{tag}")
 
 
 def k_plus(kmesh, k: int, q: int) -> int:

@@ -163,6 +163,25 @@ typedef struct bse_system {
                              W_SS).  Q != 0: BSE_TIME_REVERSAL -> BSE_ERR_INVALID_ARG, the
                              backward -> BSE_ERR_UNSUPPORTED; BSE_PD_EXCH then gives
                              n_{vk, c k+Q}.  Out of range -> BSE_ERR_INVALID_ARG.          */
+    /* W from the irreducible q points only (Sec. III.A).  nirr = 0: W holds W(q) for every q
+     * as above.  nirr > 0: W holds nirr matrices [nirr][ng_max][ng_max], the screened
+     * interaction at the irreducible q points, and every W(q) is unfolded from them by the
+     * point-group and time-reversal relations of Sec. III.A:
+     *   q =  T q_IBZ + G0:  W_GG'(q) = W_{T^-1(G+G0), T^-1(G'+G0)}(q_IBZ),
+     *   q = -T q_IBZ + G0:  W_GG'(q) = conj(W_{-T^-1(G+G0), -T^-1(G'+G0)}(q_IBZ)),
+     * given as index maps: W_GG'(q) = W[wsrc[q][0]][wmap[q][G]][wmap[q][G']], conjugated
+     * when wsrc[q][1] != 0.  The FP64 contraction reads W through the maps (no unfolded copy);
+     * the mixed modes unfold while they split W.  Every q mapped to one matrix has the same
+     * ng(q), row q of wmap is a permutation of 0..ng(q)-1 (else BSE_ERR_SHAPE), and
+     * wmap[0][0] = 0 (G = 0 of q = 0 stays in place).  BSE_VALIDATE then checks the nirr
+     * matrices for finiteness and Hermiticity; the time-reversal relation holds by
+     * construction of the maps and is not checked.  nirr > 0 with bse_build_H_backward ->
+     * BSE_ERR_UNSUPPORTED; nirr < 0 or > Nk, a NULL map, or a map entry out of range ->
+     * BSE_ERR_INVALID_ARG.  The maps are HOST memory, read while the call plans.          */
+    int nirr;
+    const int *wsrc;      /* HOST [Nk][2]       (source matrix, conjugate flag) per q            */
+    const int *wmap;      /* HOST [Nk][ng_max]  position of +-T^-1(G + G0) in the source sphere;
+                                                entries past ng(q) are not read              */
 } bse_system;
 
 /* Bytes of device workspace that bse_build_H / bse_pair_density /

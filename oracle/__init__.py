@@ -580,3 +580,23 @@ def screened_interaction(sys, vq, head):
         if q == 0:
             W[0, 0, 0] = head
     return W
+
+
+def unfold_W(W_irr, wsrc, wmap, ng):
+    """W(q) at every q of the mesh from the matrices at the irreducible q
+    points (Sec. III.A).  For q = T q_IBZ + G0 the screened interaction is that
+    of q_IBZ at the rotated vectors T^-1(G + G0); for q = -T q_IBZ + G0 it is
+    the complex conjugate at -T^-1(G + G0).  The rotated vectors are given as
+    positions in the sphere of q_IBZ, wmap[q][G], with wsrc[q] = (index of
+    q_IBZ, 1 when the time-reversed relation applies).  Entries past ng(q)
+    stay zero.  Returns [Nk][ng_max][ng_max]."""
+    nk, ngm = len(ng), W_irr.shape[1]
+    W = np.zeros((nk, ngm, ngm), dtype=np.complex128)
+    for q in range(nk):
+        src, tr = int(wsrc[q][0]), int(wsrc[q][1])
+        n = int(ng[q])
+        for g in range(n):
+            for gp in range(n):
+                w = W_irr[src, wmap[q][g], wmap[q][gp]]
+                W[q, g, gp] = np.conj(w) if tr else w
+    return W

@@ -42,7 +42,8 @@ class bse_system(ctypes.Structure):
                 ("nc", ctypes.c_int), ("omega_cell", ctypes.c_double), ("ng_max", ctypes.c_int),
                 ("ng", ctypes.c_void_p), ("gvec", ctypes.c_void_p), ("vx", ctypes.c_void_p),
                 ("u", ctypes.c_void_p), ("eps", ctypes.c_void_p), ("W", ctypes.c_void_p),
-                ("H", ctypes.c_void_p), ("qexc", ctypes.c_int)]
+                ("H", ctypes.c_void_p), ("qexc", ctypes.c_int), ("nirr", ctypes.c_int),
+                ("wsrc", ctypes.c_void_p), ("wmap", ctypes.c_void_p)]
 
 
 SYMBOLS = ["bse_workspace_size", "bse_pair_density", "bse_build_H", "bse_build_H_backward",
@@ -126,9 +127,12 @@ def _ptr(t):
 
 
 class DeviceSystem:
-    """Device-resident inputs of one crystal (and its output H)."""
+    """Device-resident inputs of one crystal (and its output H).  With
+    ``irreducible_W`` (a system carrying W_irr, wsrc, wmap), only the W
+    matrices of the irreducible q points go to the device and the library
+    unfolds W(q) through the maps."""
 
-    def __init__(self, sys, device="cuda", H=None):
+    def __init__(self, sys, device="cuda", H=None, irreducible_W=False):
         import torch
         self.src = sys
         self.device = torch.device(device)
@@ -141,7 +145,16 @@ class DeviceSystem:
         self.gvec = np.ascontiguousarray(sys.gvec, dtype=np.int32)
         self.u = torch.from_numpy(np.ascontiguousarray(sys.u)).to(self.device)
         self.eps = torch.from_numpy(np.ascontiguousarray(sys.eps, dtype=np.float64)).to(self.device)
-        self.W = torch.from_numpy(np.ascontiguousarray(sys.W)).to(self.device)
+        self.nirr, self.wsrc, self.wmap = 0, None, None
+        if irreducible_W:
+            if getattr(sys, "W_irr", None) is None:
+                raise ValueError("irreducible_W needs a system with W_irr, wsrc and wmap")
+            self.W = torch.from_numpy(np.ascontiguousarray(sys.W_irr)).to(self.device)
+            self.nirr = int(sys.W_irr.shape[0])
+            self.wsrc = np.ascontiguousarray(sys.wsrc, dtype=np.int32)
+            self.wmap = np.ascontiguousarray(sys.wmap, dtype=np.int32)
+        else:
+            self.W = torch.from_numpy(np.ascontiguousarray(sys.W)).to(self.device)
         self.vx = torch.from_numpy(np.ascontiguousarray(sys.vx, dtype=np.float64)).to(self.device)
         self.nk = int(np.prod(self.kmesh))
         self.ns = self.nk * self.nv * self.nc
@@ -163,6 +176,9 @@ class DeviceSystem:
         s.W = self.W.data_ptr()
         s.H = self.H.data_ptr() if self.H is not None else None
         s.qexc = self.qexc
+        s.nirr = self.nirr
+        s.wsrc = self.wsrc.ctypes.data if self.wsrc is not None else None
+        s.wmap = self.wmap.ctypes.data if self.wmap is not None else None
         return s
 
 

@@ -203,6 +203,10 @@ struct Plan {
   int rv_rows = 0, rc_rows = 0;    // rows per pair of RV / Z and of RC
   std::vector<int> inv0;           // coupling: position of -G in the q = 0 sphere
   std::vector<int> qbar, trmap;    // time-reversal partner of q; sphere map t - m
+  // W from the irreducible q points: (source, conjugate) per q, the sphere maps, and
+  // the sphere size of every source matrix (0: no q maps to it)
+  int nirr = 0;
+  std::vector<int> wsrc, wmap, ngirr;
   bool tr_closed = true;
   std::vector<int> ktr;            // per k: kbar | K << 24 (grid axes)
   // pairs k <= k', chunk after chunk, sorted by (q, k, k') inside a chunk
@@ -218,6 +222,7 @@ struct Plan {
   // byte offsets inside the system's region of the workspace
   size_t o_gpack = 0, o_ng = 0, o_pairs = 0, o_qs = 0, o_plex = 0, o_qbar = 0, o_trmap = 0, o_ktr = 0, o_kq = 0;
   size_t o_inv0 = 0, o_Xb = 0;     // coupling only
+  size_t o_wsrc = 0, o_wmap = 0, o_ngirr = 0;  // nirr > 0 only
   size_t tables = 0, o_vs = 0, o_X = 0, o_RV = 0, o_RC = 0, o_Z = 0, o_dWraw = 0, total = 0;
   size_t o_ut = 0;   // rotated wave functions (rot only)
   size_t o_u32 = 0;  // FP32 copy of the wave functions in the frame (pd32 only)
@@ -242,6 +247,8 @@ int check_system(const bse_system* s, bool need_w = true) {
     return fail(BSE_ERR_INVALID_ARG, "a device input pointer is NULL");
   const long long nk = (long long)s->kmesh[0] * s->kmesh[1] * s->kmesh[2];
   if (s->qexc < 0 || s->qexc >= nk) return fail(BSE_ERR_INVALID_ARG, "qexc = %d not in 0..Nk-1", s->qexc);
+  if (s->nirr < 0 || s->nirr > nk) return fail(BSE_ERR_INVALID_ARG, "nirr = %d not in 0..Nk", s->nirr);
+  if (s->nirr > 0 && (!s->wsrc || !s->wmap)) return fail(BSE_ERR_INVALID_ARG, "nirr > 0 needs the wsrc and wmap tables");
   return BSE_OK;
 }
 
@@ -296,6 +303,35 @@ int make_geometry(const bse_system* s, Plan& P, bool need_w = true) {
   }
   if (s->gvec[0] != 0 || s->gvec[1] != 0 || s->gvec[2] != 0)
     return fail(BSE_ERR_SHAPE, "gvec[0][0] must be G = 0");
+  // W of the irreducible q points: every source index, flag and map entry in
+  // range (the gathers rely on it), one sphere size per source, maps bijective
+  P.nirr = s->nirr;
+  P.wsrc.clear();
+  P.wmap.clear();
+  P.ngirr.clear();
+  if (P.nirr > 0) {
+    P.wsrc.assign(s->wsrc, s->wsrc + 2 * (size_t)P.nk);
+    P.wmap.assign((size_t)P.nk * P.ng_max, 0);
+    P.ngirr.assign(P.nirr, 0);
+    std::vector<int> seen(P.ng_max);
+    for (int q = 0; q < P.nk; ++q) {
+      const int src = P.wsrc[2 * q], cj = P.wsrc[2 * q + 1];
+      if (src < 0 || src >= P.nirr || (cj != 0 && cj != 1))
+        return fail(BSE_ERR_INVALID_ARG, "wsrc[%d] = (%d, %d): source not in 0..nirr-1 or flag not 0/1", q, src, cj);
+      if (P.ngirr[src] && P.ngirr[src] != P.ng[q])
+        return fail(BSE_ERR_SHAPE, "q = %d maps to W matrix %d with ng %d, another q with ng %d", q, src, P.ng[q],
+                    P.ngirr[src]);
+      P.ngirr[src] = P.ng[q];
+      std::fill(seen.begin(), seen.end(), 0);
+      for (int g = 0; g < P.ng[q]; ++g) {
+        const int m = s->wmap[(size_t)q * P.ng_max + g];
+        if (m < 0 || m >= P.ng[q]) return fail(BSE_ERR_INVALID_ARG, "wmap[%d][%d] = %d not in 0..ng(q)-1", q, g, m);
+        if (seen[m]++) return fail(BSE_ERR_SHAPE, "wmap[%d] is not a permutation (entry %d twice)", q, m);
+        P.wmap[(size_t)q * P.ng_max + g] = m;
+      }
+    }
+    if (P.wmap[0] != 0) return fail(BSE_ERR_SHAPE, "wmap[0][0] must be 0 (G = 0 of q = 0)");
+  }
   // kept frequencies f = m - m0 with m0 in {-1, 0} along axes with more than one k
   const int N[3] = {P.N1, P.N2, P.N3};
   for (int d = 0; d < 3; ++d) {
@@ -584,6 +620,9 @@ int plan_pairs(const bse_system* s, Plan& P, const BatchOpts& opt, int nchunk, i
   P.o_ktr = put(P.ktr.size() * sizeof(int));
   P.o_kq = put(P.kq.size() * sizeof(int));
   P.o_inv0 = put(P.inv0.size() * sizeof(int));
+  P.o_wsrc = put(P.wsrc.size() * sizeof(int));
+  P.o_wmap = put(P.wmap.size() * sizeof(int));
+  P.o_ngirr = put(P.ngirr.size() * sizeof(int));
   P.tables = o;
   const size_t mc = (size_t)P.maxcp;
   P.o_vs = put((size_t)P.ng_max * sizeof(double));
@@ -622,6 +661,9 @@ void put_tables(const Plan& P, std::vector<char>& buf, size_t base) {
   cp(P.o_ktr, P.ktr.data(), P.ktr.size() * sizeof(int));
   cp(P.o_kq, P.kq.data(), P.kq.size() * sizeof(int));
   cp(P.o_inv0, P.inv0.data(), P.inv0.size() * sizeof(int));
+  cp(P.o_wsrc, P.wsrc.data(), P.wsrc.size() * sizeof(int));
+  cp(P.o_wmap, P.wmap.data(), P.wmap.size() * sizeof(int));
+  cp(P.o_ngirr, P.ngirr.data(), P.ngirr.size() * sizeof(int));
 }
 
 PdArgs pd_args(const Plan& P, const bse_system* s, char* region) {
@@ -657,6 +699,9 @@ GemmArgs gemm_args(const Plan& P, const bse_system* s, char* region, int c) {
   g.RC = reinterpret_cast<const double2*>(region + P.o_RC);
   g.Z = reinterpret_cast<double2*>(region + P.o_Z);
   g.W = reinterpret_cast<const double2*>(s->W);
+  g.wsrc = P.nirr ? reinterpret_cast<const int*>(region + P.o_wsrc) : nullptr;
+  g.wmap = P.nirr ? reinterpret_cast<const int*>(region + P.o_wmap) : nullptr;
+  g.W0 = g.W + (P.nirr ? (size_t)P.wsrc[0] * P.ng_max * P.ng_max : 0);
   g.ng = reinterpret_cast<const int*>(region + P.o_ng);
   const int cc = c < (int)P.ch.size() ? c : 0;
   g.qstart = reinterpret_cast<const int*>(region + P.o_qs) + (size_t)cc * (P.nk + 1);
@@ -746,6 +791,7 @@ struct Batch {
   std::vector<BatchChunk> C;
   bool tr = false;             // pair densities of time-reversal images derived
   bool pd32 = false;           // FP32 valence / conduction pair densities
+  bool mapped = false;         // some system gives W at the irreducible q points only
   int np32 = 2;                // their planes per step: 4 when every window has F2 <= 16
   size_t lds32 = 0;            // their LDS bytes
   size_t o_pdx = 0, o_pdd = 0, o_jx = 0, o_xt = 0, o_mt = 0, o_tra = 0;
@@ -774,6 +820,8 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
       return fail(BSE_ERR_INVALID_ARG, "system %d: BSE_TIME_REVERSAL needs exciton momentum Q = 0", i);
     if (B.P[i].qexc && opt.backward)
       return fail(BSE_ERR_UNSUPPORTED, "system %d: the backward needs exciton momentum Q = 0", i);
+    if (B.P[i].nirr && opt.backward)
+      return fail(BSE_ERR_UNSUPPORTED, "system %d: the backward needs W at every q (nirr = 0)", i);
     if ((rc = plan_pairs(&sys[i], B.P[i], opt, nchunk, i))) return rc;
     const Plan& P = B.P[i];
     if (i == 0) {
@@ -784,6 +832,7 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
                   P.N3, B.N2, B.N3);
     }
     B.ng_max = std::max(B.ng_max, P.ng_max);
+    B.mapped = B.mapped || P.nirr > 0;
     const size_t l = pd_lds_bytes(P.N1, P.N2, P.N3, P.F[1], P.F[2], P.ng_max, 0);
     B.pd32 = B.pd32 && P.pd32;
     if (l > 160 * 1024) return fail(BSE_ERR_SHAPE, "FFT window of system %d needs more than 160 KiB of LDS", i);
@@ -886,6 +935,11 @@ std::string plan_key(const bse_system* sys, int nsys, int ktile, const BatchOpts
     };
     if (s.ng) mix(s.ng, sizeof(int) * (size_t)std::max(nk, 0));
     if (s.gvec && s.ng_max > 0) mix(s.gvec, sizeof(int) * 3 * (size_t)std::max(nk, 0) * s.ng_max);
+    if (s.nirr > 0 && s.wsrc && s.wmap && s.ng_max > 0) {
+      mix(&s.nirr, sizeof(int));
+      mix(s.wsrc, sizeof(int) * 2 * (size_t)std::max(nk, 0));
+      mix(s.wmap, sizeof(int) * (size_t)std::max(nk, 0) * s.ng_max);
+    }
     char b[200];
     snprintf(b, sizeof b, "|%d,%d,%d:%d,%d,%d:%d,%d:%d:%llx:Q%d", s.grid[0], s.grid[1], s.grid[2], s.kmesh[0],
              s.kmesh[1], s.kmesh[2], s.nv, s.nc, s.ng_max, h, s.qexc);
@@ -1109,7 +1163,9 @@ int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& 
       char* region = ws + B.base[i];
       HIP_TRY(stage(BSE_STAGE_SPLIT_W, st, [&] {
         return launch_split_w(reinterpret_cast<const double2*>(sys[i].W), reinterpret_cast<const int*>(region + P.o_ng),
-                              P.nk, P.ng_max, P.kpad, 1, precision, region + P.o_Ws, st);
+                              P.nirr ? reinterpret_cast<const int*>(region + P.o_wsrc) : nullptr,
+                              P.nirr ? reinterpret_cast<const int*>(region + P.o_wmap) : nullptr, P.nk, P.ng_max,
+                              P.kpad, 1, precision, region + P.o_Ws, st);
       }));
     }
   }
@@ -1147,7 +1203,8 @@ int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& 
     }
     const S1Tile* s1 = reinterpret_cast<const S1Tile*>(ws + K.o_s1);
     const int* d2off = reinterpret_cast<const int*>(ws + K.o_d2off);
-    HIP_TRY(stage(BSE_STAGE_DIRECT1, st, [&] { return launch_direct_s1(gs, s1, (int)K.s1.size(), precision, st); }));
+    HIP_TRY(stage(BSE_STAGE_DIRECT1, st,
+                  [&] { return launch_direct_s1(gs, s1, (int)K.s1.size(), precision, B.mapped ? 1 : 0, st); }));
     HIP_TRY(stage(BSE_STAGE_DIRECT2, st, [&] { return launch_direct_s2(gs, d2off, nsys, K.d2n, st); }));
   }
   HIP_TRY(stage(BSE_STAGE_MIRROR, st, [&] { return launch_mirror(g0, mt, (int)B.mt.size(), st); }));
@@ -1247,11 +1304,13 @@ int validate(const Batch& B, const bse_system* sys, char* ws, hipStream_t st) {
     const bse_system& s = sys[i];
     char* r = ws + B.base[i];
     HIP_TRY(launch_zero_u32(bad, 8 + 16, st));  // the 3 flags and the 64-bit maxima after them
+    // W of the irreducible q points: its nirr matrices on their own sphere sizes; time
+    // reversal then holds by construction of the maps
     HIP_TRY(launch_validate(s.u, (size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * 2, s.eps, (size_t)P.nk * P.nb, s.vx,
                             (size_t)P.ng[P.qexc], reinterpret_cast<const double2*>(s.W),
-                            reinterpret_cast<const int*>(r + P.o_ng), reinterpret_cast<const int*>(r + P.o_qbar),
-                            reinterpret_cast<const int*>(r + P.o_trmap), P.nk, P.ng_max, P.tr_closed ? 1 : 0, bad,
-                            wstat, st));
+                            reinterpret_cast<const int*>(r + (P.nirr ? P.o_ngirr : P.o_ng)),
+                            reinterpret_cast<const int*>(r + P.o_qbar), reinterpret_cast<const int*>(r + P.o_trmap),
+                            P.nirr ? P.nirr : P.nk, P.ng_max, P.tr_closed && !P.nirr ? 1 : 0, bad, wstat, st));
     unsigned hb[3];
     unsigned long long hw[3];
     HIP_TRY(hipMemcpyAsync(hb, bad, sizeof hb, hipMemcpyDeviceToHost, st));
@@ -1711,7 +1770,7 @@ int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, do
       // Z = conj(rho_vv')^T W (the forward stage 1, FP64) into the Z area
       const GemmArgs* gs = reinterpret_cast<const GemmArgs*>(w + K.o_gargs);
       const S1Tile* s1 = reinterpret_cast<const S1Tile*>(w + K.o_s1);
-      HIP_TRY(launch_direct_s1(gs, s1, (int)K.s1.size(), BSE_FP64, st));
+      HIP_TRY(launch_direct_s1(gs, s1, (int)K.s1.size(), BSE_FP64, 0, st));
       HIP_TRY(launch_adj_drc(g, st));
     }
     // T (over the Z area), the chunk's share of dW

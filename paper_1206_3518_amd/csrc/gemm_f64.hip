@@ -45,6 +45,10 @@ hipError_t launch_exchange(const GemmArgs* gs, const HTile* tiles, int ntiles, i
 
 // ------------------------------------------------------------------ direct, stage 1
 
+// MAP: some system of the batch gives W at the irreducible q points only; its
+// W(q) is read from the source matrix through the sphere map of q (Sec. III.A),
+// conjugated for the time-reversed images.
+template <bool MAP>
 __global__ __launch_bounds__(256) void k_direct_s1(const GemmArgs* __restrict__ gs, const S1Tile* __restrict__ tiles) {
   const S1Tile tl = tiles[blockIdx.x];
   const GemmArgs g = gs[tl.sys];
@@ -53,10 +57,17 @@ __global__ __launch_bounds__(256) void k_direct_s1(const GemmArgs* __restrict__ 
   const int rows = (gbl(g.qstart)[tl.iq + 1] - gbl(g.qstart)[tl.iq]) * nv2;
   const int K = gbl(g.ng)[tl.iq];
   const double2* A = g.RV + (size_t)row_base * g.ng_max;
-  const double2* Wq = g.W + (size_t)tl.iq * g.ng_max * g.ng_max;
   d4 cre[2][2], cim[2][2];
   const int r0 = tl.mt * TM, c0 = tl.nt * TN;
-  tile_gemm<true, false>(A, g.ng_max, r0, rows, Wq, g.ng_max, c0, K, K, cre, cim);
+  if (MAP && g.wmap) {
+    const int src = gbl(g.wsrc)[2 * tl.iq], cj = gbl(g.wsrc)[2 * tl.iq + 1];
+    tile_gemm<true, false, false, true, true>(A, g.ng_max, r0, rows, g.W + (size_t)src * g.ng_max * g.ng_max,
+                                              g.ng_max, c0, K, K, cre, cim, g.wmap + (size_t)tl.iq * g.ng_max,
+                                              cj != 0);
+  } else {
+    const double2* Wq = g.W + (size_t)tl.iq * g.ng_max * g.ng_max;
+    tile_gemm<true, false>(A, g.ng_max, r0, rows, Wq, g.ng_max, c0, K, K, cre, cim);
+  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
   double2* Z = g.Z + (size_t)row_base * g.ng_max;
 #pragma unroll
@@ -71,10 +82,14 @@ __global__ __launch_bounds__(256) void k_direct_s1(const GemmArgs* __restrict__ 
       }
 }
 
-hipError_t launch_direct_s1(const GemmArgs* gs, const S1Tile* tiles, int ntiles, int precision, hipStream_t st) {
+hipError_t launch_direct_s1(const GemmArgs* gs, const S1Tile* tiles, int ntiles, int precision, int mapped,
+                            hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
   if (precision != BSE_FP64) return launch_direct_s1_mx(gs, tiles, ntiles, precision, st);
-  hipLaunchKernelGGL(k_direct_s1, dim3(ntiles), dim3(256), 0, st, gs, tiles);
+  if (mapped)
+    hipLaunchKernelGGL(k_direct_s1<true>, dim3(ntiles), dim3(256), 0, st, gs, tiles);
+  else
+    hipLaunchKernelGGL(k_direct_s1<false>, dim3(ntiles), dim3(256), 0, st, gs, tiles);
   return hipGetLastError();
 }
 
@@ -112,7 +127,7 @@ __global__ __launch_bounds__(256) void k_direct_s2(const GemmArgs* __restrict__ 
   }
   // mixed precisions: the q = 0 head of W, left out of their stage 1, in FP64
   const bool head = pr.z == 0 && g.w_head_fp64;
-  const double2 w00 = head ? gld(g.W, 0) : make_double2(0.0, 0.0);
+  const double2 w00 = head ? gld(g.W0, 0) : make_double2(0.0, 0.0);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = ti * 16 + 4 * r + (lane >> 4);

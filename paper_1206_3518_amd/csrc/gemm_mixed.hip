@@ -70,20 +70,29 @@ __global__ __launch_bounds__(256) void k_direct_s1_mx(const GemmArgs* __restrict
 // W(q) split once per build and transposed so that the stage-1 tiles read
 // their B operand k-contiguous without converting it: one 32 x 32 tile of
 // (k, n) per workgroup through LDS.
+// W of the irreducible q points (wmap): W(q) is gathered from its source
+// matrix through the sphere map and conjugated where the map says so.
 template <int P>
-__global__ __launch_bounds__(256) void k_split_w(const double2* __restrict__ W, const int* __restrict__ ng, int nk,
+__global__ __launch_bounds__(256) void k_split_w(const double2* __restrict__ W, const int* __restrict__ ng,
+                                                 const int* __restrict__ wsrc, const int* __restrict__ wmap, int nk,
                                                  int ng_max, int kpad, int head, typename Split<P>::T* __restrict__ Ws) {
   __shared__ double2 tile[32][33];
   const int n0 = blockIdx.x * 32, k0 = blockIdx.y * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (int q = blockIdx.z; q < nk; q += gridDim.z) {
   const int ngq = ng[q];
+  const int src = wmap ? wsrc[2 * q] : q;
+  const bool cj = wmap && wsrc[2 * q + 1];
+  const int* mq = wmap ? wmap + (size_t)q * ng_max : nullptr;
   __syncthreads();  // the previous q's tile is read
   for (int r = ty; r < 32; r += 8) {
     const int k = k0 + r, n = n0 + tx;
     double2 v = make_double2(0.0, 0.0);
-    if (k < ngq && n < ngq && !(head && q == 0 && k == 0 && n == 0))
-      v = W[((size_t)q * ng_max + k) * ng_max + n];
+    if (k < ngq && n < ngq && !(head && q == 0 && k == 0 && n == 0)) {
+      const int ks = mq ? mq[k] : k, ns = mq ? mq[n] : n;
+      v = W[((size_t)src * ng_max + ks) * ng_max + ns];
+      if (cj) v.y = -v.y;
+    }
     tile[r][tx] = v;
   }
   __syncthreads();
@@ -138,15 +147,15 @@ hipError_t launch_split_rv(const double2* RV, const int4* pairs, const int* ng, 
   return hipGetLastError();
 }
 
-hipError_t launch_split_w(const double2* W, const int* ng, int nk, int ng_max, int kpad, int head, int precision,
-                          void* Ws, hipStream_t st) {
+hipError_t launch_split_w(const double2* W, const int* ng, const int* wsrc, const int* wmap, int nk, int ng_max,
+                          int kpad, int head, int precision, void* Ws, hipStream_t st) {
   if (nk <= 0) return hipSuccess;
   const dim3 grid((ng_max + 31) / 32, kpad / 32, nk < 4096 ? nk : 4096);
   if (precision == BSE_BF16X3)
-    hipLaunchKernelGGL(k_split_w<BSE_BF16X3>, grid, dim3(256), 0, st, W, ng, nk, ng_max, kpad, head,
+    hipLaunchKernelGGL(k_split_w<BSE_BF16X3>, grid, dim3(256), 0, st, W, ng, wsrc, wmap, nk, ng_max, kpad, head,
                        reinterpret_cast<unsigned short*>(Ws));
   else
-    hipLaunchKernelGGL(k_split_w<BSE_SPLIT_FP32>, grid, dim3(256), 0, st, W, ng, nk, ng_max, kpad, head,
+    hipLaunchKernelGGL(k_split_w<BSE_SPLIT_FP32>, grid, dim3(256), 0, st, W, ng, wsrc, wmap, nk, ng_max, kpad, head,
                        reinterpret_cast<float*>(Ws));
   return hipGetLastError();
 }

@@ -23,14 +23,19 @@ constexpr int TM = 64, TN = 64, KC = 16;
 // B[k][n] = Bm[k * ldb + b_off + n]     (B_T: Bm[(b_off + n) * ldb + k]), valid b_off + n < b_lim;
 // valid k < K.  The result lands in cre/cim (f64 MFMA accumulator layout).
 // ZERO = false adds to the accumulators instead of starting from zero.
+// B_MAP (B not transposed): B[k][n] = Bm[bmap[k] * ldb + bmap[n]], conjugated
+// when bconj (a matrix read through a permutation of its rows and columns);
+// bmap holds at least max(K, b_lim) entries.
 // Each thread stages 4 elements of A and 4 of B per K chunk; the next chunk's
 // elements are loaded into registers while the MFMAs consume the current one
 // (out-of-range elements are read from the array start and replaced by zero,
 // so the loads need no branches).
-template <bool CONJ_A, bool B_T, bool A_T = false, bool ZERO = true>
+template <bool CONJ_A, bool B_T, bool A_T = false, bool ZERO = true, bool B_MAP = false>
 __device__ __forceinline__ void tile_gemm(const double2* __restrict__ A, int lda, int a_off, int a_lim,
                                           const double2* __restrict__ B, int ldb, int b_off, int b_lim, int K,
-                                          d4 (&cre)[2][2], d4 (&cim)[2][2]) {
+                                          d4 (&cre)[2][2], d4 (&cim)[2][2], const int* __restrict__ bmap = nullptr,
+                                          bool bconj = false) {
+  static_assert(!(B_MAP && B_T), "the mapped B operand is read untransposed");
   __shared__ double As_re[TM][KC + 1], As_im[TM][KC + 1];
   __shared__ double Bs_re[KC][TN + 1], Bs_im[KC][TN + 1];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -51,6 +56,11 @@ __device__ __forceinline__ void tile_gemm(const double2* __restrict__ A, int lda
   const int bk = t >> 4, bc = (t & 15) * 4;
   const int bn = t >> 2, bkc = (t & 3) * 4;
   double2 ra[4], rb[4];
+  int mn[B_MAP ? 4 : 1];  // mapped columns of this thread's B elements (fixed over k)
+  if constexpr (B_MAP) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) mn[i] = b_off + bc + i < b_lim ? bmap[b_off + bc + i] : 0;
+  }
   auto load = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -76,13 +86,17 @@ __device__ __forceinline__ void tile_gemm(const double2* __restrict__ A, int lda
         const int gn = b_off + bn, k = k0 + bkc + i;
         ok = gn < b_lim && k < K;
         idx = (size_t)gn * ldb + k;
+      } else if constexpr (B_MAP) {
+        const int n = b_off + bc + i, k = k0 + bk;
+        ok = k < K && n < b_lim;
+        idx = (size_t)(k < K ? bmap[k] : 0) * ldb + mn[i];
       } else {
         const int n = b_off + bc + i, k = k0 + bk;
         ok = k < K && n < b_lim;
         idx = (size_t)k * ldb + n;
       }
       const double2 v = gld(B, ok ? idx : 0);
-      rb[i] = make_double2(ok ? v.x : 0.0, ok ? v.y : 0.0);
+      rb[i] = make_double2(ok ? v.x : 0.0, ok ? (B_MAP && bconj ? -v.y : v.y) : 0.0);
     }
   };
   auto store = [&]() {

@@ -91,7 +91,10 @@ struct GemmArgs {
   const double2* RV;
   const double2* RC;
   double2* Z;
-  const double2* W;
+  const double2* W;     // W(q) for every q, or (wmap) the matrices of the irreducible q points
+  const int* wsrc;      // null, or [Nk][2] (source matrix, conjugate) of W(q)
+  const int* wmap;      // null, or [Nk][ng_max]: W_GG'(q) = W[wsrc[q][0]][wmap[q][G]][wmap[q][G']]
+  const double2* W0;    // W(q = 0) (its G = 0 entry is the head)
   const int* ng;
   const int* qstart;    // [Nk+1] first pair of each q group of the chunk (global pair index;
                         // the chunk's pairs are sorted by q), qstart[Nk] = end of the chunk
@@ -119,7 +122,10 @@ struct GemmArgs {
 // out[g] = sqrt(vx[g]) for g < ngx, zero at g = g0 (G = 0; -1: none) and past ngx
 hipError_t launch_vscale(const double* vx, int ngx, int ng_max, int g0, double* out, hipStream_t st);
 hipError_t launch_exchange(const GemmArgs* gs, const HTile* tiles, int ntiles, int precision, hipStream_t st);
-hipError_t launch_direct_s1(const GemmArgs* gs, const S1Tile* tiles, int ntiles, int precision, hipStream_t st);
+// mapped: some system reads W through its sphere maps (FP64; the mixed modes
+// unfold W while they split it)
+hipError_t launch_direct_s1(const GemmArgs* gs, const S1Tile* tiles, int ntiles, int precision, int mapped,
+                            hipStream_t st);
 // stage 2 is FP64 in every mode (it adds the FP64 q = 0 head when w_head_fp64)
 hipError_t launch_direct_s2(const GemmArgs* gs, const int* d2off, int nsys, int nitems, hipStream_t st);
 hipError_t launch_mirror(const GemmArgs* gs, const HTile* tiles, int ntiles, hipStream_t st);
@@ -131,13 +137,14 @@ hipError_t launch_xbar(const double2* X, const int* inv, int ns, int ng0, int ng
 hipError_t launch_full_lower(double2* H2, int ns, hipStream_t st);
 // Ws[q][n][pl][k] = part pl of W[q][k][n] for k, n < ng(q), zero elsewhere up
 // to kpad (and at the q = 0 head when head != 0); precision BSE_SPLIT_FP32 or
-// BSE_BF16X3 (parts as in the mixed contractions).
+// BSE_BF16X3 (parts as in the mixed contractions).  With wmap, W[q][k][n] is
+// W[wsrc[q][0]][wmap[q][k]][wmap[q][n]], conjugated when wsrc[q][1] != 0.
 // RVs[row][pl][k] = part pl of conj(RV[row][k]) for k < ng(q of the row's
 // pair), zero up to kpad; rows_per_pair = nv^2.
 hipError_t launch_split_rv(const double2* RV, const int4* pairs, const int* ng, size_t nrows, int rows_per_pair,
                            int ld, int kpad, int precision, void* RVs, hipStream_t st);
-hipError_t launch_split_w(const double2* W, const int* ng, int nk, int ng_max, int kpad, int head, int precision,
-                          void* Ws, hipStream_t st);
+hipError_t launch_split_w(const double2* W, const int* ng, const int* wsrc, const int* wmap, int nk, int ng_max,
+                          int kpad, int head, int precision, void* Ws, hipStream_t st);
 // mixed-precision bodies (precision BSE_SPLIT_FP32 or BSE_BF16X3), called by the above
 hipError_t launch_exchange_mx(const GemmArgs* gs, const HTile* tiles, int ntiles, int precision, hipStream_t st);
 hipError_t launch_direct_s1_mx(const GemmArgs* gs, const S1Tile* tiles, int ntiles, int precision, hipStream_t st);

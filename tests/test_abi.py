@@ -110,6 +110,36 @@ def test_workspace_size_and_host_errors():
     assert L.bse_build_H_backward(ctypes.byref(st6), ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), None, None,
                                   None, None, P.BSE_FP64, 0, ctypes.c_void_p(0x1000), n, None) == -7
     assert "momentum" in P.bse_last_error()
+    # W of the irreducible q points: maps missing, out of range, not bijective,
+    # moving G = 0 of q = 0, two sphere sizes on one source; the backward refuses it
+    s7 = B.make_system(B.cell_fcc(7.0), (16, 16, 16), (2, 2, 2), 2, 2, 3.0, seed=71)
+    reps, wsrc, wmap = B.point_group_maps(s7)
+    n7 = None
+    for mutate, code, word in [
+            (lambda ws, wm: None, 0, None),
+            (lambda ws, wm: ws.__setitem__((1, 0), len(reps)), -1, "wsrc"),
+            (lambda ws, wm: ws.__setitem__((1, 1), 2), -1, "wsrc"),
+            (lambda ws, wm: wm.__setitem__((2, 0), s7.ng[2]), -1, "wmap"),
+            (lambda ws, wm: wm.__setitem__((2, 1), wm[2, 2]), -2, "permutation"),
+            (lambda ws, wm: wm.__setitem__((0, slice(0, 2)), wm[0, 1::-1].copy()), -2, "wmap[0][0]")]:
+        ws_, wm_ = wsrc.copy(), wmap.copy()
+        mutate(ws_, wm_)
+        st7, keep7 = _fake_struct(P, s7)
+        st7.nirr, st7.wsrc, st7.wmap = len(reps), ws_.ctypes.data, wm_.ctypes.data
+        if code == 0:
+            n7 = L.bse_workspace_size(ctypes.byref(st7), 1, 0, 0)
+            assert n7 > 0
+            assert L.bse_build_H_backward(ctypes.byref(st7), ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), None,
+                                          None, None, None, P.BSE_FP64, 0, ctypes.c_void_p(0x1000), 1 << 40, None) == -7
+            assert "nirr" in P.bse_last_error()
+            st7.nirr = s7.nk + 1
+            assert L.bse_build_H(ctypes.byref(st7), 1, 0, 0, ctypes.c_void_p(0x1000), n7, None) == -1
+            assert "nirr" in P.bse_last_error()
+            st7.nirr, st7.wmap = len(reps), None
+            assert L.bse_build_H(ctypes.byref(st7), 1, 0, 0, ctypes.c_void_p(0x1000), n7, None) == -1
+            continue
+        assert L.bse_build_H(ctypes.byref(st7), 1, 0, 0, ctypes.c_void_p(0x1000), 1 << 40, None) == code
+        assert word in P.bse_last_error()
     # the workspace grows for the FP32 copy of u
     n32 = L.bse_workspace_size(ctypes.byref(st), 1, P.BSE_BF16X3, P.BSE_FP32_PAIRDENS)
     assert n32 >= n + 8 * s.nk * (s.nv + s.nc) * int(np.prod(s.grid))

@@ -1,0 +1,120 @@
+"""The HIP build with W given at the irreducible q points only (Sec. III.A,
+unfolded inside the library through the caller's sphere maps) against the
+build with W at every q and against the oracle on the unfolded W."""
+import sys
+
+import numpy as np
+import pytest
+
+import bse_synth as B
+import oracle as O
+from bars import fp64_h_bar
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _fcc2():
+    return B.make_system(B.cell_fcc(7.0), (16, 16, 16), (2, 2, 2), 2, 3, 3.0, seed=72)
+
+
+CASES = [("fcc2-O", _fcc2, True), ("si24-O", lambda: B.make_config(1), True),
+         ("si24-Oh", lambda: B.make_config(1), False)]
+
+
+@pytest.mark.parametrize("name,make,proper", CASES, ids=[c[0] for c in CASES])
+def test_irreducible_W_equals_the_full_W_build(name, make, proper):
+    """Every precision: the maps read the same values the unfolded W holds, so
+    the build is bit-identical to the one from W at every q."""
+    import paper_1206_3518_amd as P
+    import torch
+    s = B.with_point_group_W(make(), proper=proper)
+    for prec in ("fp64", "split_fp32", "bf16x3"):
+        a = P.build_H(P.DeviceSystem(s), prec).clone()
+        d = P.DeviceSystem(s, irreducible_W=True)
+        b = P.build_H(d, prec)
+        torch.cuda.synchronize()
+        _say(f"{name} {prec}: {d.nirr} of {s.nk} W matrices; equal {torch.equal(a, b)}")
+        assert d.W.shape[0] == len(s.W_irr) < s.nk
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("name,make,proper", CASES[:2], ids=[c[0] for c in CASES[:2]])
+def test_irreducible_W_matches_oracle(name, make, proper):
+    """FP64 parity with the oracle on W unfolded by the oracle itself."""
+    import dataclasses
+
+    import paper_1206_3518_amd as P
+    import torch
+    s = B.with_point_group_W(make(), proper=proper)
+    ref_sys = dataclasses.replace(s, W=O.unfold_W(s.W_irr, s.wsrc, s.wmap, s.ng))
+    H = P.build_H(P.DeviceSystem(s, irreducible_W=True), "fp64")
+    torch.cuda.synchronize()
+    Hc = H.cpu().numpy()
+    nk, nt = s.nk, s.nv * s.nc
+    if nk <= 8:
+        ref = O.build_H(ref_sys)
+        err, bar = np.abs(Hc - ref).max(), fp64_h_bar(ref)
+    else:
+        rng = np.random.default_rng(5)
+        blocks = [(0, 0), (0, nk - 1), (nk - 1, nk - 1), (3, 17)]
+        blocks += [tuple(sorted(int(x) for x in rng.integers(0, nk, 2))) for _ in range(6)]
+        ref = O.build_blocks(ref_sys, blocks)
+        kmax = max(np.abs(r - np.diag(np.diag(r))).max() for r in ref)
+        bar = 1e-10 * kmax + 2.0 ** -50 * max(np.abs(r).max() for r in ref)
+        err = max(np.abs(Hc[a * nt:(a + 1) * nt, b * nt:(b + 1) * nt] - r).max() for (a, b), r in zip(blocks, ref))
+    _say(f"{name}: max|H - H_oracle| {err:.3e} eV (bar {bar:.3e})")
+    assert err <= bar
+
+
+def test_irreducible_W_with_time_reversal_chunks_and_batch():
+    """BSE_TIME_REVERSAL and many chunks give the same H as the plain build;
+    a batch mixing a system with W at every q and one with W at the
+    irreducible points equals their single builds."""
+    import paper_1206_3518_amd as P
+    import torch
+    s = B.with_point_group_W(B.make_config(1, time_reversal=True), proper=True)
+    d = P.DeviceSystem(s, irreducible_W=True)
+    P.bse_build_H([d], P.BSE_FP64, 0)
+    one = d.H.clone()
+    P.bse_build_H([d], P.BSE_FP64, P.BSE_TIME_REVERSAL | P.BSE_VALIDATE)
+    torch.cuda.synchronize()
+    tr_err = (d.H - one).abs().max().item()
+    try:
+        P.bse_set_chunk_budget(64 << 20)
+        d.H.zero_()
+        P.bse_build_H([d], P.BSE_FP64, 0)
+        torch.cuda.synchronize()
+        assert torch.equal(d.H, one)
+    finally:
+        P.bse_set_chunk_budget(0)
+    e = P.DeviceSystem(B.make_system(B.cell_fcc(B.A_SI), (24, 24, 24), (2, 2, 2), 3, 3, 6.0, seed=62))
+    P.bse_build_H([e], P.BSE_FP64, 0)
+    single = e.H.clone()
+    d.H.zero_()
+    e.H.zero_()
+    P.bse_build_H([e, d], P.BSE_FP64, 0)
+    torch.cuda.synchronize()
+    _say(f"time reversal: max|dH| {tr_err:.3e} eV")
+    assert tr_err <= 1e-10 * one.abs().max().item()
+    assert torch.equal(d.H, one) and torch.equal(e.H, single)
+
+
+def test_irreducible_W_validation_and_backward():
+    """BSE_VALIDATE accepts the irreducible matrices and catches a
+    non-Hermitian one; the backward refuses W at the irreducible points."""
+    import paper_1206_3518_amd as P
+    import torch
+    s = B.with_point_group_W(_fcc2(), proper=True)
+    d = P.DeviceSystem(s, irreducible_W=True)
+    P.bse_build_H([d], P.BSE_FP64, P.BSE_VALIDATE)
+    d.W[1, 2, 3] += 0.5
+    with pytest.raises(P.BseError) as ei:
+        P.bse_build_H([d], P.BSE_FP64, P.BSE_VALIDATE)
+    assert "Hermitian" in str(ei.value)
+    with pytest.raises(P.BseError):
+        P.bse_build_H_backward(d, torch.zeros_like(d.H))
