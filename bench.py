@@ -423,10 +423,26 @@ def screening_leg(P, n_empty=60):
     ms = e0.elapsed_time(e1)
     npd = s.nk * s.nk * 2 * s.nv * s.nc
     herk = float(np.sum(8.0 * (s.nk * 2 * s.nv * s.nc) * s.ng.astype(np.float64) ** 2))
-    return {"workload": s.name, "nv": s.nv, "n_empty": s.nc, "ng": [int(s.ng.min()), int(s.ng.max())],
-            "ms": ms, "pair_densities": npd, "pair_densities_per_s": npd / (ms / 1e3),
-            "chi0_flops": herk, "workspace_GB": ws.numel() / 1e9,
-            "W_hermitian_dev": float((W - W.conj().transpose(1, 2)).abs().max().item())}
+    out = {"workload": s.name, "nv": s.nv, "n_empty": s.nc, "ng": [int(s.ng.min()), int(s.ng.max())],
+           "ms": ms, "pair_densities": npd, "pair_densities_per_s": npd / (ms / 1e3),
+           "chi0_flops": herk, "workspace_GB": ws.numel() / 1e9,
+           "W_hermitian_dev": float((W - W.conj().transpose(1, 2)).abs().max().item())}
+    # the irreducible q points only (cubic group with time reversal): the same
+    # matrices there, every other W(q) left to the build's sphere maps
+    si = B.with_point_group_W(s, proper=True)
+    di = P.DeviceSystem(si, device="cuda:0", irreducible_W=True)
+    reps, _, _ = B.point_group_maps(s, proper=True)
+    P.bse_screening(di, vq, s.head, ws=ws)
+    torch.cuda.synchronize()
+    e0.record(st)
+    Wi = P.bse_screening(di, vq, s.head, ws=ws)
+    e1.record(st)
+    torch.cuda.synchronize()
+    msi = e0.elapsed_time(e1)
+    out["irreducible"] = {"nirr": len(reps), "ms": msi, "speedup": ms / msi,
+                          "equal_to_full_at_the_points": bool(all(torch.equal(Wi[i], W[q])
+                                                                  for i, q in enumerate(reps)))}
+    return out
 
 
 def bandlimited_leg(P, args, flags):

@@ -344,9 +344,14 @@ int bse_spectrum(int ns, int nlam, const double *E, const double *A, const doubl
  * and H are not read.  vq: DEVICE [Nk][ng_max], v(q+G) on each sphere (4 pi
  * inside; bulk or truncated; the entry of G = 0 at q = 0 is not read).
  * W: DEVICE [Nk][ng_max][ng_max] complex out, zero past ng(q); it is the
- * input W of bse_build_H for the same spheres.  ws:
- * bse_screening_workspace(sys) bytes (pair densities of a chunk of q, sized
- * by bse_set_chunk_budget).  FP64 throughout.
+ * input W of bse_build_H for the same spheres.  With sys->nirr > 0 only the
+ * irreducible q points are computed (Sec. III.A: the q sum is reduced by the
+ * symmetry, every other W(q) is its image): W is then [nirr][ng_max][ng_max],
+ * matrix i at the q that sys->wsrc / sys->wmap map to matrix i without
+ * conjugation by the identity map (the lowest such q; none ->
+ * BSE_ERR_SHAPE), which is the input W of bse_build_H with the same maps.
+ * ws: bse_screening_workspace(sys) bytes (pair densities of a chunk of q,
+ * sized by bse_set_chunk_budget).  FP64 throughout.
  */
 int bse_screening(const bse_system *sys, const double *vq, double head, double *W, void *ws, size_t ws_bytes,
                   void *stream);

@@ -438,14 +438,17 @@ def bse_screening_workspace(system: DeviceSystem) -> int:
 
 def bse_screening(system: DeviceSystem, vq, head, ws=None, stream=None):
     """Static RPA W [Nk][ng_max][ng_max] (complex128, device) of ``system``'s
-    nv occupied and nc empty bands; vq [Nk][ng_max] the bare Coulomb table."""
+    nv occupied and nc empty bands; vq [Nk][ng_max] the bare Coulomb table.
+    A system made with ``irreducible_W`` gets W at its irreducible q points
+    only, [nirr][ng_max][ng_max]."""
     import torch
     vq = torch.as_tensor(np.ascontiguousarray(vq, dtype=np.float64)).to(system.device) \
         if not isinstance(vq, torch.Tensor) else vq.contiguous()
     st = system.struct()
     if ws is None:
         ws = workspace(bse_screening_workspace(system), system.device)
-    W = torch.empty((system.nk, system.ng_max, system.ng_max), dtype=torch.complex128, device=system.device)
+    nw = system.nirr if system.nirr > 0 else system.nk
+    W = torch.empty((nw, system.ng_max, system.ng_max), dtype=torch.complex128, device=system.device)
     _check(lib().bse_screening(ctypes.byref(st), _ptr(vq), float(head), _ptr(W), _ptr(ws), ws.numel(),
                                _stream(stream)))
     return W

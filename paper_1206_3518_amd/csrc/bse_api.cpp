@@ -1214,14 +1214,17 @@ int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& 
 // ------------------------------------------------------------ screening
 
 // Plan of bse_screening: chunks of q whose pair densities (2 nv nc rows per
-// k) fit the chunk budget, their jobs, pair table and HERK tiles.
+// k) fit the chunk budget, their jobs, pair table and HERK tiles.  The q
+// points are every q of the mesh, or (nirr > 0) the irreducible ones: output
+// matrix (slot) i is W at qof[i].
 struct ScrPlan {
   Plan G;                               // geometry of the system
+  std::vector<int> qof;                 // q of each output slot
   std::vector<std::vector<int>> qs;     // q of each chunk
   std::vector<std::vector<PdJob>> jobs; // per chunk, dispatch order
   std::vector<std::vector<int4>> pk;    // per chunk: (k, k + q, q, -) per (q_local, k)
-  std::vector<std::vector<int4>> tiles; // per chunk: (q, row tile, column tile, q_local)
-  size_t o_gpack = 0, o_ng = 0, o_vq = 0, o_args = 0, o_ut = 0, o_Y = 0, total = 0;
+  std::vector<std::vector<int4>> tiles; // per chunk: (slot, row tile, column tile, q_local)
+  size_t o_gpack = 0, o_ng = 0, o_vq = 0, o_args = 0, o_ut = 0, o_Y = 0, o_qof = 0, total = 0;
   std::vector<size_t> o_jobs, o_pk, o_tiles;
   size_t tables = 0;
   int maxq = 0;                         // q per chunk, largest
@@ -1236,8 +1239,28 @@ int make_screening_plan(const bse_system* s, ScrPlan& S) {
   const size_t bytes_q = rows_q * P.ng_max * sizeof(double2);
   if (rows_q * P.ng_max >= (size_t(1) << 31)) return fail(BSE_ERR_SHAPE, "pair densities of one q too large");
   if (P.ng_max > 1024) return fail(BSE_ERR_SHAPE, "ng_max above 1024");
-  const int per_chunk = (int)std::max<size_t>(1, std::min<size_t>(nk, g_chunk_budget.load() / std::max<size_t>(bytes_q, 1)));
-  const int nchunk = (nk + per_chunk - 1) / per_chunk;
+  // output slots: every q, or the q that maps to source matrix i by the identity
+  // (not conjugated; the lowest such q)
+  S.qof.clear();
+  if (P.nirr == 0) {
+    for (int q = 0; q < nk; ++q) S.qof.push_back(q);
+  } else {
+    for (int i = 0; i < P.nirr; ++i) {
+      int found = -1;
+      for (int q = 0; q < nk && found < 0; ++q) {
+        if (P.wsrc[2 * q] != i || P.wsrc[2 * q + 1] != 0) continue;
+        bool ident = true;
+        for (int g = 0; g < P.ng[q] && ident; ++g) ident = P.wmap[(size_t)q * P.ng_max + g] == g;
+        if (ident) found = q;
+      }
+      if (found < 0)
+        return fail(BSE_ERR_SHAPE, "no q maps to W matrix %d by the identity (its irreducible point is unknown)", i);
+      S.qof.push_back(found);
+    }
+  }
+  const int nq = (int)S.qof.size();
+  const int per_chunk = (int)std::max<size_t>(1, std::min<size_t>(nq, g_chunk_budget.load() / std::max<size_t>(bytes_q, 1)));
+  const int nchunk = (nq + per_chunk - 1) / per_chunk;
   S.maxq = per_chunk;
   S.qs.assign(nchunk, {});
   S.jobs.assign(nchunk, {});
@@ -1247,7 +1270,8 @@ int make_screening_plan(const bse_system* s, ScrPlan& S) {
   const int T2 = (P.ng_max + 63) / 64;
   for (int c = 0; c < nchunk; ++c) {
     std::vector<PdJob> jobs;
-    for (int q = c * per_chunk; q < std::min(nk, (c + 1) * per_chunk); ++q) {
+    for (int slot = c * per_chunk; slot < std::min(nq, (c + 1) * per_chunk); ++slot) {
+      const int q = S.qof[slot];
       const int ql = (int)S.qs[c].size();
       S.qs[c].push_back(q);
       const int qv[3] = {q / (n[1] * n[2]), (q / n[2]) % n[1], q % n[2]};
@@ -1264,7 +1288,7 @@ int make_screening_plan(const bse_system* s, ScrPlan& S) {
         S.pk[c].push_back(make_int4(k, kq, q, 0));
       }
       for (int i = 0; i < T2; ++i)
-        for (int j = 0; j < T2; ++j) S.tiles[c].push_back(make_int4(q, i, j, ql));
+        for (int j = 0; j < T2; ++j) S.tiles[c].push_back(make_int4(slot, i, j, ql));
     }
     S.jobs[c] = dispatch_order(std::move(jobs), Tune{}.ktile);
   }
@@ -1278,6 +1302,7 @@ int make_screening_plan(const bse_system* s, ScrPlan& S) {
   S.o_gpack = put(P.gpack.size() * sizeof(int));
   S.o_ng = put(P.ng.size() * sizeof(int));
   S.o_args = put(sizeof(PdArgs));
+  S.o_qof = put(S.qof.size() * sizeof(int));
   S.o_jobs.resize(nchunk);
   S.o_pk.resize(nchunk);
   S.o_tiles.resize(nchunk);
@@ -1899,6 +1924,7 @@ int bse_screening(const bse_system* sys, const double* vq, double head, double* 
   std::memcpy(buf + S.o_gpack, P.gpack.data(), P.gpack.size() * sizeof(int));
   std::memcpy(buf + S.o_ng, P.ng.data(), P.ng.size() * sizeof(int));
   std::memcpy(buf + S.o_args, &a, sizeof(PdArgs));
+  std::memcpy(buf + S.o_qof, S.qof.data(), S.qof.size() * sizeof(int));
   for (size_t c = 0; c < S.qs.size(); ++c) {
     std::memcpy(buf + S.o_jobs[c], S.jobs[c].data(), S.jobs[c].size() * sizeof(PdJob));
     std::memcpy(buf + S.o_pk[c], S.pk[c].data(), S.pk[c].size() * sizeof(int4));
@@ -1920,7 +1946,9 @@ int bse_screening(const bse_system* sys, const double* vq, double head, double* 
   r.nk = P.nk;
   r.ng_max = P.ng_max;
   r.omega = (double)P.nk * sys->omega_cell;
-  HIP_TRY(launch_rpa_init(r.M, r.ng, P.nk, P.ng_max, st));
+  r.qof = reinterpret_cast<const int*>(w + S.o_qof);
+  const int nslot = (int)S.qof.size();
+  HIP_TRY(launch_rpa_init(r.M, r.ng, r.qof, nslot, P.ng_max, st));
   for (size_t c = 0; c < S.qs.size(); ++c) {
     PdBatch b{};
     b.sys = reinterpret_cast<const PdArgs*>(w + S.o_args);
@@ -1933,8 +1961,8 @@ int bse_screening(const bse_system* sys, const double* vq, double head, double* 
     HIP_TRY(launch_rpa_scale(r, (int)S.pk[c].size(), st));
     HIP_TRY(launch_rpa_herk(r, reinterpret_cast<const int4*>(w + S.o_tiles[c]), (int)S.tiles[c].size(), st));
   }
-  HIP_TRY(launch_rpa_invert(r.M, r.ng, P.nk, P.ng_max, st));
-  HIP_TRY(launch_rpa_w(r.M, r.ng, vq, P.nk, P.ng_max, head, st));
+  HIP_TRY(launch_rpa_invert(r.M, r.ng, r.qof, nslot, P.ng_max, st));
+  HIP_TRY(launch_rpa_w(r.M, r.ng, r.qof, vq, nslot, P.ng_max, head, st));
   return BSE_OK;
 }
 

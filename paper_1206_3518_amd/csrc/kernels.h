@@ -241,21 +241,22 @@ hipError_t launch_spectrum(int ns, int nlam, int nq, const double* E, const doub
 // (q_local, k); omega = Nk * Omega_cell.
 struct RpaArgs {
   double2* Y;
-  double2* M;
+  double2* M;           // [nslot][ng_max][ng_max]: slot i holds q = qof[i]
   const int4* pk;
   const int* ng;
+  const int* qof;       // [nslot] q of each output slot
   const double* eps;
   const double* vq;
   int nv, nc, nk, ng_max;
   double omega;
 };
 hipError_t launch_rpa_scale(const RpaArgs& a, int npairs, hipStream_t st);
-hipError_t launch_rpa_init(double2* M, const int* ng, int nk, int ng_max, hipStream_t st);
-// tiles (q, row tile, column tile, q_local) of 64 x 64 over ng_max x ng_max
+hipError_t launch_rpa_init(double2* M, const int* ng, const int* qof, int nslot, int ng_max, hipStream_t st);
+// tiles (slot, row tile, column tile, q_local) of 64 x 64 over ng_max x ng_max
 hipError_t launch_rpa_herk(const RpaArgs& a, const int4* tiles, int ntiles, hipStream_t st);
-hipError_t launch_rpa_invert(double2* M, const int* ng, int nk, int ng_max, hipStream_t st);
-hipError_t launch_rpa_w(double2* M, const int* ng, const double* vq, int nk, int ng_max, double head,
-                        hipStream_t st);
+hipError_t launch_rpa_invert(double2* M, const int* ng, const int* qof, int nslot, int ng_max, hipStream_t st);
+hipError_t launch_rpa_w(double2* M, const int* ng, const int* qof, const double* vq, int nslot, int ng_max,
+                        double head, hipStream_t st);
 // Haydock recursion: niter steps of the Lanczos recurrence from conj(d_p)
 // for nq <= kMaxQhat polarisations (H [ns][ns] eV, d [nq][ns] Hartree units),
 // coefficients into coef [nq][niter][2] (a_j, b_j in eV), then eps2 on nw

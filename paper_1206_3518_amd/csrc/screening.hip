@@ -13,6 +13,8 @@
 //   k_rpa_invert  eps(q)^-1 in place by Gauss-Jordan elimination (Hermitian
 //                 positive definite: no pivoting)
 //   k_rpa_w       W = v^1/2 eps^-1 v^1/2, the q = 0 head set, wings zero
+// The output holds one matrix per slot, slot i for q = qof[i] (every q, or
+// only the irreducible q points of Sec. III.A).
 #include "bse_internal.h"
 #include "gemm_tiles.h"
 #include "kernels.h"
@@ -47,28 +49,29 @@ __global__ __launch_bounds__(256) void k_rpa_scale(RpaArgs a) {
   }
 }
 
-__global__ void k_rpa_init(double2* __restrict__ M, const int* __restrict__ ng, int nk, int ng_max) {
+__global__ void k_rpa_init(double2* __restrict__ M, const int* __restrict__ ng, const int* __restrict__ qof,
+                           int nslot, int ng_max) {
   const size_t per = (size_t)ng_max * ng_max;
-  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < per * nk;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < per * nslot;
        id += (size_t)gridDim.x * blockDim.x) {
-    const int q = (int)(id / per);
+    const int q = qof[id / per];
     const int g = (int)((id % per) / ng_max), h = (int)(id % ng_max);
     M[id] = make_double2((g == h && g < ng[q]) ? 1.0 : 0.0, 0.0);
   }
 }
 
-// Tile (q, i, j) of 64 x 64: M_q[G][G'] += conj(sum_r conj(Y_r(G)) Y_r(G')) over
-// the rows of q in the chunk (A transposed: A[G][r] = Y[r][G]).
+// Tile (slot, i, j) of 64 x 64: M_q[G][G'] += conj(sum_r conj(Y_r(G)) Y_r(G'))
+// over the rows of q = qof[slot] in the chunk (A transposed: A[G][r] = Y[r][G]).
 __global__ __launch_bounds__(256) void k_rpa_herk(RpaArgs a, const int4* __restrict__ tiles) {
-  const int4 tl = tiles[blockIdx.x];  // (q, row tile, column tile, q_local)
-  const int q = tl.x, ql = tl.w;
+  const int4 tl = tiles[blockIdx.x];  // (slot, row tile, column tile, q_local)
+  const int slot = tl.x, q = a.qof[slot], ql = tl.w;
   const int ngm = a.ng_max, ngq = a.ng[q];
   const int rows = a.nk * 2 * a.nv * a.nc;
   const double2* Yq = a.Y + (size_t)ql * rows * ngm;
   const int r0 = tl.y * 64, c0 = tl.z * 64;
   d4 cre[2][2], cim[2][2];
   tile_gemm<true, false, true>(Yq, ngm, r0, ngq, Yq, ngm, c0, ngq, rows, cre, cim);
-  double2* M = a.M + (size_t)q * ngm * ngm;
+  double2* M = a.M + (size_t)slot * ngm * ngm;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -93,10 +96,10 @@ __global__ __launch_bounds__(256) void k_rpa_herk(RpaArgs a, const int4* __restr
 // M[i][k] times the new row k (entry k: -M[i][k] / p).
 constexpr int kRpaMaxG = 1024;
 __global__ __launch_bounds__(1024) void k_rpa_invert(double2* __restrict__ M, const int* __restrict__ ng,
-                                                     int ng_max) {
+                                                     const int* __restrict__ qof, int ng_max) {
   __shared__ double2 col[kRpaMaxG], row[kRpaMaxG];
-  const int q = blockIdx.x, n = ng[q];
-  double2* A = M + (size_t)q * ng_max * ng_max;
+  const int slot = blockIdx.x, n = ng[qof[slot]];
+  double2* A = M + (size_t)slot * ng_max * ng_max;
   for (int k = 0; k < n; ++k) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
       col[i] = A[(size_t)i * ng_max + k];
@@ -123,12 +126,12 @@ __global__ __launch_bounds__(1024) void k_rpa_invert(double2* __restrict__ M, co
   }
 }
 
-__global__ void k_rpa_w(double2* __restrict__ M, const int* __restrict__ ng, const double* __restrict__ vq, int nk,
-                        int ng_max, double head) {
+__global__ void k_rpa_w(double2* __restrict__ M, const int* __restrict__ ng, const int* __restrict__ qof,
+                        const double* __restrict__ vq, int nslot, int ng_max, double head) {
   const size_t per = (size_t)ng_max * ng_max;
-  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < per * nk;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < per * nslot;
        id += (size_t)gridDim.x * blockDim.x) {
-    const int q = (int)(id / per);
+    const int q = qof[id / per];
     const int g = (int)((id % per) / ng_max), h = (int)(id % ng_max);
     const int n = ng[q];
     double2 w = make_double2(0.0, 0.0);
@@ -151,8 +154,8 @@ hipError_t launch_rpa_scale(const RpaArgs& a, int npairs, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_rpa_init(double2* M, const int* ng, int nk, int ng_max, hipStream_t st) {
-  hipLaunchKernelGGL(k_rpa_init, dim3(8192), dim3(256), 0, st, M, ng, nk, ng_max);
+hipError_t launch_rpa_init(double2* M, const int* ng, const int* qof, int nslot, int ng_max, hipStream_t st) {
+  hipLaunchKernelGGL(k_rpa_init, dim3(8192), dim3(256), 0, st, M, ng, qof, nslot, ng_max);
   return hipGetLastError();
 }
 
@@ -162,15 +165,15 @@ hipError_t launch_rpa_herk(const RpaArgs& a, const int4* tiles, int ntiles, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_rpa_invert(double2* M, const int* ng, int nk, int ng_max, hipStream_t st) {
+hipError_t launch_rpa_invert(double2* M, const int* ng, const int* qof, int nslot, int ng_max, hipStream_t st) {
   if (ng_max > kRpaMaxG) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_rpa_invert, dim3(nk), dim3(1024), 0, st, M, ng, ng_max);
+  hipLaunchKernelGGL(k_rpa_invert, dim3(nslot), dim3(1024), 0, st, M, ng, qof, ng_max);
   return hipGetLastError();
 }
 
-hipError_t launch_rpa_w(double2* M, const int* ng, const double* vq, int nk, int ng_max, double head,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(k_rpa_w, dim3(8192), dim3(256), 0, st, M, ng, vq, nk, ng_max, head);
+hipError_t launch_rpa_w(double2* M, const int* ng, const int* qof, const double* vq, int nslot, int ng_max,
+                        double head, hipStream_t st) {
+  hipLaunchKernelGGL(k_rpa_w, dim3(8192), dim3(256), 0, st, M, ng, qof, vq, nslot, ng_max, head);
   return hipGetLastError();
 }
 

@@ -137,6 +137,12 @@ def test_workspace_size_and_host_errors():
             assert "nirr" in P.bse_last_error()
             st7.nirr, st7.wmap = len(reps), None
             assert L.bse_build_H(ctypes.byref(st7), 1, 0, 0, ctypes.c_void_p(0x1000), n7, None) == -1
+            # the screening needs, per matrix, a q that maps to it by the identity
+            st7.wmap = wm_.ctypes.data
+            assert L.bse_screening_workspace(ctypes.byref(st7)) > 0
+            ws_[:, 1] = 1
+            assert L.bse_screening_workspace(ctypes.byref(st7)) == 0
+            assert "identity" in P.bse_last_error()
             continue
         assert L.bse_build_H(ctypes.byref(st7), 1, 0, 0, ctypes.c_void_p(0x1000), 1 << 40, None) == code
         assert word in P.bse_last_error()

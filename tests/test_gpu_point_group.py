@@ -118,3 +118,41 @@ def test_irreducible_W_validation_and_backward():
     assert "Hermitian" in str(ei.value)
     with pytest.raises(P.BseError):
         P.bse_build_H_backward(d, torch.zeros_like(d.H))
+
+
+def test_screening_at_the_irreducible_points():
+    """bse_screening with the maps computes W at the irreducible q points only:
+    matrix i equals the oracle's W at that point and the full screening's W
+    there; the H built from those matrices through the maps matches the
+    oracle's H on W unfolded by the oracle from its own matrices."""
+    import dataclasses
+
+    import paper_1206_3518_amd as P
+    import torch
+    s0 = B.make_system(B.cell_fcc(7.0), (16, 16, 16), (2, 2, 2), 2, 6, 2.0, seed=73)
+    s = B.with_point_group_W(s0, proper=True)
+    reps, _, _ = B.point_group_maps(s0, proper=True)
+    vq = B.coulomb_table(s)
+    d = P.DeviceSystem(s, irreducible_W=True)
+    Wi = P.bse_screening(d, vq, s.head)
+    Wf = P.bse_screening(P.DeviceSystem(s), vq, s.head)
+    torch.cuda.synchronize()
+    assert Wi.shape[0] == len(reps) < s.nk
+    same = all(torch.equal(Wi[i], Wf[q]) for i, q in enumerate(reps))
+    ref = O.screened_interaction(s, vq, s.head)
+    err = max(np.abs(Wi[i].cpu().numpy() - ref[q]).max() for i, q in enumerate(reps))
+    scale = np.abs(ref).max()
+    _say(f"irreducible screening: {len(reps)} of {s.nk} q; max|dW| {err:.3e} (max|W| {scale:.3e}); "
+         f"equal to the full screening there: {same}")
+    assert err <= 1e-11 * scale
+    assert same
+    # the BSE of the first 2 empty bands on those matrices
+    nb = s.nv + 2
+    cut = dict(nc=2, u=np.ascontiguousarray(s.u[:, :nb]), eps=np.ascontiguousarray(s.eps[:, :nb]))
+    sg = dataclasses.replace(s, W_irr=Wi.cpu().numpy(), **cut)
+    H = P.build_H(P.DeviceSystem(sg, irreducible_W=True)).cpu().numpy()
+    W_or = O.unfold_W(np.array([ref[q] for q in reps]), s.wsrc, s.wmap, s.ng)
+    Href = O.build_H(dataclasses.replace(s, W=W_or, **cut))
+    dh = np.abs(H - Href).max()
+    _say(f"H from the irreducible screened W: max|dH| vs oracle {dh:.3e} eV")
+    assert dh <= fp64_h_bar(Href) + 1e-11 * np.abs(Href - np.diag(np.diag(Href))).max()
