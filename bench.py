@@ -276,9 +276,12 @@ def main():
     if tuning is not None:
         config["autotune_candidates_ms"] = {
             (f"persistent/{c['wg_per_cu']}" if c["persistent"] else f"static/k{c['ktile']}"): round(c["pd_ms"], 3)
-            for c in tried}
+            for c in tried if c["s1_ms"] == 0}
+        config["autotune_stage1_tiles_ms"] = {f"{c['s1_rows']}x64": round(c["s1_ms"], 3) for c in tried
+                                              if c["s1_ms"] > 0}
         config["dispatch"] = (f"autotuned: persistent, {tuning['wg_per_cu']} workgroups/CU" if tuning["persistent"]
                               else f"autotuned: static, k tile {tuning['ktile']}")
+        config["stage1_tile"] = f"autotuned: {tuning['s1_rows']} x 64"
     else:
         config["dispatch"] = "persistent" if args.persistent else "static, k tile 8"
     config["chunk_budget_GiB"] = args.chunk_budget_gb or 6.0
@@ -322,8 +325,9 @@ def main():
                 wsm = P.workspace(need, devs[0].device)
             wl = ws if need <= ws.numel() else wsm
             mtune = None
-            if mflags and not args.no_autotune and not args.persistent:
-                mtune = P.bse_autotune(devs, pm, None, wl, flags=mflags)  # the FP32 kernel's own choice
+            if not args.no_autotune and not args.persistent:
+                # this mode's own choices (the FP32 kernel's dispatch, the stage-1 tile)
+                mtune = P.bse_autotune(devs, pm, None, wl, flags=mflags)
             msm, _, stm = run_steps(P, devs, pm, flags | mflags, wl, max(2, args.steps // 2), 1)
             dH = max((d.H - h).abs().max().item() for d, h in zip(devs, H64))
             dE = max(float(np.abs(torch.linalg.eigvalsh(d.H)[:10].cpu().numpy() - e).max())
@@ -340,6 +344,7 @@ def main():
             if mtune is not None:
                 mixed[name]["dispatch"] = (f"autotuned: persistent, {mtune['wg_per_cu']} workgroups/CU"
                                            if mtune["persistent"] else f"autotuned: static, k tile {mtune['ktile']}")
+                mixed[name]["stage1_tile"] = f"autotuned: {mtune['s1_rows']} x 64 ({mtune['s1_ms']:.3f} ms)"
         out["mixed"] = mixed
         del wsm
         del H64

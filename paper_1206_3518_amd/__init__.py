@@ -34,7 +34,7 @@ class BseError(RuntimeError):
 
 class bse_tuning(ctypes.Structure):
     _fields_ = [("persistent", ctypes.c_int), ("ktile", ctypes.c_int), ("wg_per_cu", ctypes.c_int),
-                ("pd_ms", ctypes.c_float)]
+                ("pd_ms", ctypes.c_float), ("s1_rows", ctypes.c_int), ("s1_ms", ctypes.c_float)]
 
 
 class bse_system(ctypes.Structure):
@@ -214,9 +214,10 @@ def bse_build_H(systems, precision=BSE_FP64, flags=0, ws=None, stream=None):
 
 
 def bse_autotune(systems, precision=BSE_FP64, cache_path=None, ws=None, stream=None, flags=0) -> dict:
-    """Times the candidate pair-density dispatches for this batch and keeps the
-    fastest for later builds of the same shape; returns the choice.  flags:
-    BSE_FP32_PAIRDENS tunes the FP32 pair-density kernel (mixed precisions)."""
+    """Times the candidate pair-density dispatches for this batch, then the
+    stage-1 contraction tile shapes, and keeps the fastest for later builds of
+    the same shape; returns the choice.  flags: BSE_FP32_PAIRDENS tunes the
+    FP32 pair-density kernel (mixed precisions)."""
     arr = _structs(systems)
     if ws is None:
         ws = workspace(bse_workspace_size(systems, precision, flags), systems[0].device)
@@ -224,7 +225,8 @@ def bse_autotune(systems, precision=BSE_FP64, cache_path=None, ws=None, stream=N
     path = None if cache_path is None else os.fsencode(str(cache_path))
     _check(lib().bse_autotune(arr, len(systems), int(precision), int(flags), path, ctypes.byref(out), _ptr(ws),
                               ws.numel(), _stream(stream)))
-    return {"persistent": out.persistent, "ktile": out.ktile, "wg_per_cu": out.wg_per_cu, "pd_ms": out.pd_ms}
+    return {"persistent": out.persistent, "ktile": out.ktile, "wg_per_cu": out.wg_per_cu, "pd_ms": out.pd_ms,
+            "s1_rows": out.s1_rows, "s1_ms": out.s1_ms}
 
 
 def bse_autotune_last() -> list:
@@ -234,7 +236,7 @@ def bse_autotune_last() -> list:
     if n < 0:
         raise BseError(n, bse_last_error())
     return [{"persistent": arr[i].persistent, "ktile": arr[i].ktile, "wg_per_cu": arr[i].wg_per_cu,
-             "pd_ms": arr[i].pd_ms} for i in range(min(n, 32))]
+             "pd_ms": arr[i].pd_ms, "s1_rows": arr[i].s1_rows, "s1_ms": arr[i].s1_ms} for i in range(min(n, 32))]
 
 
 def bse_pair_density(system: DeviceSystem, kind, kpairs=None, ws=None, stream=None, cell=None):

@@ -431,7 +431,7 @@ size_t pair_bytes(const bse_system* s, bool mixed, bool coupling = false) {
 
 // The pairs k <= k' cut into at most `nchunk` chunks, their jobs and tiles,
 // and the workspace layout.  `sys` tags the jobs and fill items.
-int plan_pairs(const bse_system* s, Plan& P, const BatchOpts& opt, int nchunk, int sys) {
+int plan_pairs(const bse_system* s, Plan& P, const BatchOpts& opt, int nchunk, int sys, int s1_rows) {
   const int nk = P.nk, nv = P.nv, nc = P.nc;
   P.coupling = opt.coupling;
   P.ldh = opt.ldh > 0 ? opt.ldh : P.ns;
@@ -554,10 +554,11 @@ int plan_pairs(const bse_system* s, Plan& P, const BatchOpts& opt, int nchunk, i
     for (int q = 0; q < nk; ++q) {
       if (!cnt[q]) continue;
       const int rows = cnt[q] * P.rv_rows;
-      const int mt = (rows + 63) / 64, ntl = (P.ng[q] + 63) / 64;
+      const int mt = (rows + s1_rows - 1) / s1_rows, ntl = (P.ng[q] + 63) / 64;
       for (int i = 0; i < mt; ++i)
         for (int j = 0; j < ntl; ++j) K.s1.push_back(S1Tile{q, i, j, sys});
       if (opt.backward) {
+        const int mt = (rows + 63) / 64;  // the backward's own tiles are 64 rows
         for (int i = 0; i < T2; ++i)
           for (int j = 0; j < T2; ++j) K.dwt.push_back(make_int4(q, i, j, 0));
         for (int i = 0; i < mt; ++i)
@@ -732,6 +733,8 @@ struct Tune {
   int ktile = 8;      // k tile of the pair-density dispatch order
   int wg_per_cu = 2;  // persistent grid: workgroups per CU
   float pd_ms = 0.f;  // measured time of the tuned pair-density launch (0: not measured)
+  int s1_rows = 64;   // rows per tile of the direct term's first contraction (64 or 128)
+  float s1_ms = 0.f;  // measured time of that launch (0: not measured)
 };
 std::mutex g_tune_mu;
 std::vector<std::pair<std::string, Tune>> g_tune;
@@ -792,6 +795,7 @@ struct Batch {
   bool tr = false;             // pair densities of time-reversal images derived
   bool pd32 = false;           // FP32 valence / conduction pair densities
   bool mapped = false;         // some system gives W at the irreducible q points only
+  int s1_rows = 64;            // rows per tile of the first direct-term contraction
   int np32 = 2;                // their planes per step: 4 when every window has F2 <= 16
   size_t lds32 = 0;            // their LDS bytes
   size_t o_pdx = 0, o_pdd = 0, o_jx = 0, o_xt = 0, o_mt = 0, o_tra = 0;
@@ -802,6 +806,8 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
   if (!sys || nsys < 1) return fail(BSE_ERR_INVALID_ARG, "no systems");
   B.tr = opt.tr;
   B.pd32 = opt.pd32;
+  if (tn.s1_rows != 64 && tn.s1_rows != 128) return fail(BSE_ERR_INVALID_ARG, "stage-1 tile rows must be 64 or 128");
+  B.s1_rows = tn.s1_rows;
   if (nsys > 16383) return fail(BSE_ERR_INVALID_ARG, "too many systems");
   B.P.resize(nsys);
   // chunk count: the per-pair arrays of all systems over the budget
@@ -822,7 +828,7 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
       return fail(BSE_ERR_UNSUPPORTED, "system %d: the backward needs exciton momentum Q = 0", i);
     if (B.P[i].nirr && opt.backward)
       return fail(BSE_ERR_UNSUPPORTED, "system %d: the backward needs W at every q (nirr = 0)", i);
-    if ((rc = plan_pairs(&sys[i], B.P[i], opt, nchunk, i))) return rc;
+    if ((rc = plan_pairs(&sys[i], B.P[i], opt, nchunk, i, B.s1_rows))) return rc;
     const Plan& P = B.P[i];
     if (i == 0) {
       B.N2 = P.N2;
@@ -921,10 +927,11 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
 
 // Key of everything the host plan of a batch depends on: shapes, sphere
 // tables (hashed by content), the options and the k tile.
-std::string plan_key(const bse_system* sys, int nsys, int ktile, const BatchOpts& o) {
+std::string plan_key(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts& o) {
   std::string k = std::to_string(nsys) + (o.backward ? "b" : "f") + (o.project ? "p" : "") + (o.tr ? "t" : "") +
                   (o.pd32 ? "s" : "") + (o.mixed ? "m" : "") + (o.coupling ? "x" : "") + "l" + std::to_string(o.ldh) +
-                  std::to_string(ktile) + "c" + std::to_string(g_chunk_budget.load());
+                  "k" + std::to_string(tn.ktile) + "r" + std::to_string(tn.s1_rows) + "c" +
+                  std::to_string(g_chunk_budget.load());
   for (int i = 0; i < nsys; ++i) {
     const bse_system& s = sys[i];
     const int nk = s.kmesh[0] * s.kmesh[1] * s.kmesh[2];
@@ -967,7 +974,7 @@ int cached_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpt
     int rc = check_system(&sys[i]);
     if (rc) return rc;
   }
-  const std::string key = plan_key(sys, nsys, tn.ktile, opt);
+  const std::string key = plan_key(sys, nsys, tn, opt);
   PlanCache* slot = nullptr;
   for (PlanCache& c : g_plan)
     if (!c.key.empty() && c.key == key) slot = &c;
@@ -1146,6 +1153,41 @@ int prepare_u(const Batch& B, const bse_system* sys, char* ws, hipStream_t st) {
 // densities and the exchange term once, then per chunk the valence and
 // conduction densities and the two stages of the direct term (one launch per
 // stage over all systems), then the mirror.
+// Mixed precisions: W of every system split (and unfolded through its maps)
+// once per build, the B operand of the first direct-term contraction.
+int split_w_all(const Batch& B, const bse_system* sys, int precision, char* ws, hipStream_t st) {
+  if (precision == BSE_FP64) return BSE_OK;
+  for (size_t i = 0; i < B.P.size(); ++i) {
+    const Plan& P = B.P[i];
+    char* region = ws + B.base[i];
+    HIP_TRY(stage(BSE_STAGE_SPLIT_W, st, [&] {
+      return launch_split_w(reinterpret_cast<const double2*>(sys[i].W), reinterpret_cast<const int*>(region + P.o_ng),
+                            P.nirr ? reinterpret_cast<const int*>(region + P.o_wsrc) : nullptr,
+                            P.nirr ? reinterpret_cast<const int*>(region + P.o_wmap) : nullptr, P.nk, P.ng_max,
+                            P.kpad, 1, precision, region + P.o_Ws, st);
+    }));
+  }
+  return BSE_OK;
+}
+
+// Mixed precisions: the valence pair-density rows of chunk c split once, the A
+// operand of the first direct-term contraction.
+int split_rv_chunk(const Batch& B, int precision, char* ws, int c, hipStream_t st) {
+  if (precision == BSE_FP64) return BSE_OK;
+  for (size_t i = 0; i < B.P.size(); ++i) {
+    const Plan& P = B.P[i];
+    if (c >= (int)P.ch.size()) continue;
+    char* region = ws + B.base[i];
+    HIP_TRY(stage(BSE_STAGE_SPLIT_W, st, [&] {
+      return launch_split_rv(reinterpret_cast<const double2*>(region + P.o_RV),
+                             reinterpret_cast<const int4*>(region + P.o_pairs) + P.ch[c].p0,
+                             reinterpret_cast<const int*>(region + P.o_ng), (size_t)P.ch[c].np * P.rv_rows,
+                             P.rv_rows, P.ng_max, P.kpad, precision, region + P.o_RVs, st);
+    }));
+  }
+  return BSE_OK;
+}
+
 int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& tn, char* ws, hipStream_t st) {
   const int nsys = (int)B.P.size();
   int rc = upload_batch(B, sys, precision, ws, st);
@@ -1157,18 +1199,7 @@ int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& 
                   [&] { return launch_vscale(sys[i].vx, P.ng[P.qexc], P.ng_max, P.g0x, vs, st); }));
   }
   if ((rc = prepare_u(B, sys, ws, st))) return rc;
-  if (precision != BSE_FP64) {
-    for (int i = 0; i < nsys; ++i) {
-      const Plan& P = B.P[i];
-      char* region = ws + B.base[i];
-      HIP_TRY(stage(BSE_STAGE_SPLIT_W, st, [&] {
-        return launch_split_w(reinterpret_cast<const double2*>(sys[i].W), reinterpret_cast<const int*>(region + P.o_ng),
-                              P.nirr ? reinterpret_cast<const int*>(region + P.o_wsrc) : nullptr,
-                              P.nirr ? reinterpret_cast<const int*>(region + P.o_wmap) : nullptr, P.nk, P.ng_max,
-                              P.kpad, 1, precision, region + P.o_Ws, st);
-      }));
-    }
-  }
+  if ((rc = split_w_all(B, sys, precision, ws, st))) return rc;
   const GemmArgs* g0 = reinterpret_cast<const GemmArgs*>(ws + B.C[0].o_gargs);
   const HTile* xt = reinterpret_cast<const HTile*>(ws + B.o_xt);
   const HTile* mt = reinterpret_cast<const HTile*>(ws + B.o_mt);
@@ -1187,24 +1218,13 @@ int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& 
     if ((rc = run_pd(B, ws, 1, c, tn, st)) || (rc = run_tr_fill(B, ws, 1, c, st)) ||
         (rc = run_tr_fill(B, ws, 2, c, st)))
       return rc;
-    if (precision != BSE_FP64) {
-      // the A operand of the mixed stage 1, split once
-      for (int i = 0; i < nsys; ++i) {
-        const Plan& P = B.P[i];
-        if (c >= (int)P.ch.size()) continue;
-        char* region = ws + B.base[i];
-        HIP_TRY(stage(BSE_STAGE_SPLIT_W, st, [&] {
-          return launch_split_rv(reinterpret_cast<const double2*>(region + P.o_RV),
-                                 reinterpret_cast<const int4*>(region + P.o_pairs) + P.ch[c].p0,
-                                 reinterpret_cast<const int*>(region + P.o_ng), (size_t)P.ch[c].np * P.nv * P.nv,
-                                 P.nv * P.nv, P.ng_max, P.kpad, precision, region + P.o_RVs, st);
-        }));
-      }
-    }
+    if ((rc = split_rv_chunk(B, precision, ws, c, st))) return rc;
     const S1Tile* s1 = reinterpret_cast<const S1Tile*>(ws + K.o_s1);
     const int* d2off = reinterpret_cast<const int*>(ws + K.o_d2off);
     HIP_TRY(stage(BSE_STAGE_DIRECT1, st,
-                  [&] { return launch_direct_s1(gs, s1, (int)K.s1.size(), precision, B.mapped ? 1 : 0, st); }));
+                  [&] {
+                    return launch_direct_s1(gs, s1, (int)K.s1.size(), precision, B.mapped ? 1 : 0, B.s1_rows, st);
+                  }));
     HIP_TRY(stage(BSE_STAGE_DIRECT2, st, [&] { return launch_direct_s2(gs, d2off, nsys, K.d2n, st); }));
   }
   HIP_TRY(stage(BSE_STAGE_MIRROR, st, [&] { return launch_mirror(g0, mt, (int)B.mt.size(), st); }));
@@ -1372,7 +1392,7 @@ int validate(const Batch& B, const bse_system* sys, char* ws, hipStream_t st) {
 // ------------------------------------------------------------ autotuning
 
 // Tuning cache: one line per batch signature,
-//   {"key": "<signature>", "persist": P, "ktile": T, "wg_per_cu": W, "pd_ms": M}
+//   {"key": "<signature>", "persist": P, "ktile": T, "wg_per_cu": W, "pd_ms": M, "s1_rows": R, "s1_ms": S}
 bool cache_lookup(const char* path, const std::string& key, Tune& out) {
   if (!path) return false;
   FILE* f = fopen(path, "r");
@@ -1383,11 +1403,14 @@ bool cache_lookup(const char* path, const std::string& key, Tune& out) {
   while (fgets(line, sizeof line, f)) {
     if (std::strncmp(line, want.c_str(), want.size()) != 0) continue;
     Tune t;
-    float ms = 0.f;
-    if (sscanf(line + want.size(), " \"persist\": %d, \"ktile\": %d, \"wg_per_cu\": %d, \"pd_ms\": %f", &t.persist,
-               &t.ktile, &t.wg_per_cu, &ms) == 4 &&
-        (t.persist == 0 || t.persist == 1) && t.ktile >= 1 && t.ktile <= 1024 && t.wg_per_cu >= 1 && t.wg_per_cu <= 8) {
+    float ms = 0.f, s1ms = 0.f;
+    if (sscanf(line + want.size(),
+               " \"persist\": %d, \"ktile\": %d, \"wg_per_cu\": %d, \"pd_ms\": %f, \"s1_rows\": %d, \"s1_ms\": %f",
+               &t.persist, &t.ktile, &t.wg_per_cu, &ms, &t.s1_rows, &s1ms) == 6 &&
+        (t.persist == 0 || t.persist == 1) && t.ktile >= 1 && t.ktile <= 1024 && t.wg_per_cu >= 1 && t.wg_per_cu <= 8 &&
+        (t.s1_rows == 64 || t.s1_rows == 128)) {
       t.pd_ms = ms;
+      t.s1_ms = s1ms;
       out = t;
       hit = true;  // the last matching line wins
     }
@@ -1400,8 +1423,8 @@ void cache_store(const char* path, const std::string& key, const Tune& t) {
   if (!path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "{\"key\": \"%s\", \"persist\": %d, \"ktile\": %d, \"wg_per_cu\": %d, \"pd_ms\": %.9g}\n", key.c_str(),
-          t.persist, t.ktile, t.wg_per_cu, (double)t.pd_ms);
+  fprintf(f, "{\"key\": \"%s\", \"persist\": %d, \"ktile\": %d, \"wg_per_cu\": %d, \"pd_ms\": %.9g, \"s1_rows\": %d, "
+          "\"s1_ms\": %.9g}\n", key.c_str(), t.persist, t.ktile, t.wg_per_cu, (double)t.pd_ms, t.s1_rows, (double)t.s1_ms);
   fclose(f);
 }
 
@@ -1469,6 +1492,50 @@ int autotune(const bse_system* sys, int nsys, int precision, bool pd32, const ch
     rec.pd_ms = ms;
     g_tried.push_back(rec);
     if (best.pd_ms < 0.f || ms < best.pd_ms) best = rec;
+  }
+  // the first direct-term contraction of the first chunk (its operands made by
+  // the chosen dispatch) with 64- and 128-row tiles
+  if (!rc) {
+    float s1_best = -1.f;
+    int rows_best = 64;
+    for (int rows : {64, 128}) {
+      if (rows == 128 && precision == BSE_SPLIT_FP32) continue;  // FP32 parts: 64-row tiles only
+      Tune c = best;
+      c.s1_rows = rows;
+      Batch B;
+      if ((rc = make_batch(sys, nsys, c, opt, B))) break;
+      if ((rc = upload_batch(B, sys, precision, ws, st)) || (rc = prepare_u(B, sys, ws, st)) ||
+          (rc = split_w_all(B, sys, precision, ws, st)) || (rc = run_pd(B, ws, 1, 0, c, st)) ||
+          (rc = split_rv_chunk(B, precision, ws, 0, st)))
+        break;
+      const BatchChunk& K = B.C[0];
+      const GemmArgs* gs = reinterpret_cast<const GemmArgs*>(ws + K.o_gargs);
+      const S1Tile* s1 = reinterpret_cast<const S1Tile*>(ws + K.o_s1);
+      float ms = 0.f;
+      hipError_t e = hipSuccess;
+      for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+        float m = 0.f;
+        e = hipEventRecord(e0, st);
+        if (e == hipSuccess) e = launch_direct_s1(gs, s1, (int)K.s1.size(), precision, B.mapped ? 1 : 0, rows, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&m, e0, e1);
+        if (rep == 1 || (rep == 2 && m < ms)) ms = m;
+      }
+      if (e != hipSuccess) {
+        rc = fail(BSE_ERR_HIP, "autotune timing: %s", hipGetErrorString(e));
+        break;
+      }
+      Tune rec = c;
+      rec.s1_ms = ms;
+      g_tried.push_back(rec);
+      if (s1_best < 0.f || ms < s1_best) {
+        s1_best = ms;
+        rows_best = rows;
+      }
+    }
+    best.s1_rows = rows_best;
+    best.s1_ms = s1_best;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1673,7 +1740,9 @@ int bse_build_H(const bse_system* sys, int nsys, int precision, int flags, void*
   if (rc) return rc;
   Tune tn = tune_for(batch_key(Bp->P, precision, Bp->pd32));
   if (flags & BSE_PERSISTENT) tn.persist = 1;
-  if (tn.ktile != Tune{}.ktile && (rc = cached_batch(sys, nsys, tn, opt, &Bp))) return rc;
+  if (precision == BSE_SPLIT_FP32) tn.s1_rows = 64;  // FP32 parts: 64-row tiles only
+  if ((tn.ktile != Tune{}.ktile || tn.s1_rows != Tune{}.s1_rows) && (rc = cached_batch(sys, nsys, tn, opt, &Bp)))
+    return rc;
   const Batch& B = *Bp;
   if (ws_bytes < B.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, B.total);
   if (flags & BSE_VALIDATE) {
@@ -1795,7 +1864,7 @@ int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, do
       // Z = conj(rho_vv')^T W (the forward stage 1, FP64) into the Z area
       const GemmArgs* gs = reinterpret_cast<const GemmArgs*>(w + K.o_gargs);
       const S1Tile* s1 = reinterpret_cast<const S1Tile*>(w + K.o_s1);
-      HIP_TRY(launch_direct_s1(gs, s1, (int)K.s1.size(), BSE_FP64, 0, st));
+      HIP_TRY(launch_direct_s1(gs, s1, (int)K.s1.size(), BSE_FP64, 0, B.s1_rows, st));
       HIP_TRY(launch_adj_drc(g, st));
     }
     // T (over the Z area), the chunk's share of dW
@@ -1823,6 +1892,8 @@ int bse_autotune(const bse_system* sys, int nsys, int precision, int flags, cons
     chosen->ktile = t.ktile;
     chosen->wg_per_cu = t.wg_per_cu;
     chosen->pd_ms = t.pd_ms;
+    chosen->s1_rows = t.s1_rows;
+    chosen->s1_ms = t.s1_ms;
   }
   return BSE_OK;
 }
@@ -1835,6 +1906,8 @@ int bse_autotune_last(bse_tuning* tried, int max_tried) {
     tried[i].ktile = g_tried[i].ktile;
     tried[i].wg_per_cu = g_tried[i].wg_per_cu;
     tried[i].pd_ms = g_tried[i].pd_ms;
+    tried[i].s1_rows = g_tried[i].s1_rows;
+    tried[i].s1_ms = g_tried[i].s1_ms;
   }
   return (int)g_tried.size();
 }

@@ -35,8 +35,12 @@ __global__ __launch_bounds__(256) void k_exchange_mx(const GemmArgs* __restrict_
       }
 }
 
-template <int P>
-__global__ __launch_bounds__(256) void k_direct_s1_mx(const GemmArgs* __restrict__ gs, const S1Tile* __restrict__ tiles) {
+// 128-row tiles (MR = 2) for BF16 parts only: with FP32 parts they do not fit
+// two waves per SIMD without spilling.
+template <int P, int MR>
+__global__ __launch_bounds__(256, MR == 1 ? 1 : 2) void k_direct_s1_mx(const GemmArgs* __restrict__ gs,
+                                                                       const S1Tile* __restrict__ tiles) {
+  static_assert(MR == 1 || P == BSE_BF16X3, "128-row tiles with BF16 parts only");
   const S1Tile tl = tiles[blockIdx.x];
   const GemmArgs g = gs[tl.sys];
   const int nv2 = g.rv_rows;
@@ -45,22 +49,22 @@ __global__ __launch_bounds__(256) void k_direct_s1_mx(const GemmArgs* __restrict
   const int K = gbl(g.ng)[tl.iq];
   const double2* A = g.RV + (size_t)row_base * g.ng_max;
   const double2* Wq = g.W + (size_t)tl.iq * g.ng_max * g.ng_max;
-  f4 cre[2][2], cim[2][2];
-  const int r0 = tl.mt * MTM, c0 = tl.nt * MTN;
+  f4 cre[2 * MR][2], cim[2 * MR][2];
+  const int r0 = tl.mt * MTM * MR, c0 = tl.nt * MTN;
   typedef typename Split<P>::T T;
   const T* Wsq = reinterpret_cast<const T*>(g.Ws) + (size_t)tl.iq * g.ng_max * 4 * g.kpad;
   const T* RVs = reinterpret_cast<const T*>(g.RVs) + (size_t)row_base * 4 * g.kpad;
-  tile_gemm_mx<P, true, false, false, true, true>(A, g.ng_max, r0, rows, Wq, g.ng_max, c0, K, K, false, cre, cim,
-                                                  Wsq, g.kpad, RVs);
+  tile_gemm_mx<P, true, false, false, true, true, MR>(A, g.ng_max, r0, rows, Wq, g.ng_max, c0, K, K, false, cre,
+                                                      cim, Wsq, g.kpad, RVs);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
   double2* Z = g.Z + (size_t)row_base * g.ng_max;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 2 * MR; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = r0 + wr * 32 + i * 16 + acc_row(lane, r);
+        const int row = r0 + wr * 32 * MR + i * 16 + acc_row(lane, r);
         const int col = c0 + wc * 32 + j * 16 + (lane & 15);
         if (row < rows && col < K)
           gst(Z, (size_t)row * g.ng_max + col, make_double2((double)cre[i][j][r], (double)cim[i][j][r]));
@@ -169,12 +173,13 @@ static hipError_t launch_ex(const GemmArgs* gs, const HTile* tiles, int ntiles, 
   return hipGetLastError();
 }
 
-template <int P>
+template <int P, int MR>
 static hipError_t launch_s1(const GemmArgs* gs, const S1Tile* tiles, int ntiles, hipStream_t st) {
-  const size_t lds = 2 * sizeof(TileLds<P>);
-  hipError_t e = hipFuncSetAttribute((const void*)k_direct_s1_mx<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const size_t lds = tile_mx_lds<P, MR>();
+  void (*k)(const GemmArgs*, const S1Tile*) = k_direct_s1_mx<P, MR>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_direct_s1_mx<P>, dim3(ntiles), dim3(256), lds, st, gs, tiles);
+  hipLaunchKernelGGL(k, dim3(ntiles), dim3(256), lds, st, gs, tiles);
   return hipGetLastError();
 }
 
@@ -184,10 +189,13 @@ hipError_t launch_exchange_mx(const GemmArgs* gs, const HTile* tiles, int ntiles
                                  : launch_ex<BSE_SPLIT_FP32>(gs, tiles, ntiles, st);
 }
 
-hipError_t launch_direct_s1_mx(const GemmArgs* gs, const S1Tile* tiles, int ntiles, int precision, hipStream_t st) {
+hipError_t launch_direct_s1_mx(const GemmArgs* gs, const S1Tile* tiles, int ntiles, int precision, int rows,
+                               hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  return precision == BSE_BF16X3 ? launch_s1<BSE_BF16X3>(gs, tiles, ntiles, st)
-                                 : launch_s1<BSE_SPLIT_FP32>(gs, tiles, ntiles, st);
+  if (rows == 128)
+    return precision == BSE_BF16X3 ? launch_s1<BSE_BF16X3, 2>(gs, tiles, ntiles, st) : hipErrorInvalidValue;
+  return precision == BSE_BF16X3 ? launch_s1<BSE_BF16X3, 1>(gs, tiles, ntiles, st)
+                                 : launch_s1<BSE_SPLIT_FP32, 1>(gs, tiles, ntiles, st);
 }
 
 

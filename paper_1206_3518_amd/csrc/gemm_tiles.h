@@ -1,5 +1,6 @@
-// Tile engines of the MFMA contractions: a 64 x 64 complex output tile per
-// 256-thread workgroup (4 waves, 32 x 32 each), operands staged through LDS.
+// Tile engines of the MFMA contractions: a (64 MR) x 64 complex output tile
+// per 256-thread workgroup (4 waves, (32 MR) x 32 each; MR = 1 or 2),
+// operands staged through LDS.
 //   tile_gemm     FP64: four real v_mfma_f64_16x16x4 products per step
 //   tile_gemm_mx  split operands (FP32 or BF16 hi + lo), FP32 accumulation
 #pragma once
@@ -18,65 +19,72 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
 
 constexpr int TM = 64, TN = 64, KC = 16;
 
-// 64x64 complex tile of C = op(A) * B with op(A) = conj(A) if CONJ_A.
+// (64 MR) x 64 complex tile of C = op(A) * B with op(A) = conj(A) if CONJ_A.
 // A[m][k] = Am[(a_off + m) * lda + k]   (A_T: Am[k * lda + a_off + m]), valid a_off + m < a_lim;
 // B[k][n] = Bm[k * ldb + b_off + n]     (B_T: Bm[(b_off + n) * ldb + k]), valid b_off + n < b_lim;
 // valid k < K.  The result lands in cre/cim (f64 MFMA accumulator layout).
 // ZERO = false adds to the accumulators instead of starting from zero.
 // B_MAP (B not transposed): B[k][n] = Bm[bmap[k] * ldb + bmap[n]], conjugated
 // when bconj (a matrix read through a permutation of its rows and columns);
-// bmap holds at least max(K, b_lim) entries.
+// bmap holds at least max(K, b_lim) entries, or is null (B read directly, so
+// that one instantiation, with one set of LDS arrays, serves both).
 // Each thread stages 4 elements of A and 4 of B per K chunk; the next chunk's
 // elements are loaded into registers while the MFMAs consume the current one
 // (out-of-range elements are read from the array start and replaced by zero,
 // so the loads need no branches).
-template <bool CONJ_A, bool B_T, bool A_T = false, bool ZERO = true, bool B_MAP = false>
+template <bool CONJ_A, bool B_T, bool A_T = false, bool ZERO = true, bool B_MAP = false, int MR = 1>
 __device__ __forceinline__ void tile_gemm(const double2* __restrict__ A, int lda, int a_off, int a_lim,
                                           const double2* __restrict__ B, int ldb, int b_off, int b_lim, int K,
-                                          d4 (&cre)[2][2], d4 (&cim)[2][2], const int* __restrict__ bmap = nullptr,
-                                          bool bconj = false) {
+                                          d4 (&cre)[2 * MR][2], d4 (&cim)[2 * MR][2],
+                                          const int* __restrict__ bmap = nullptr, bool bconj = false) {
   static_assert(!(B_MAP && B_T), "the mapped B operand is read untransposed");
-  __shared__ double As_re[TM][KC + 1], As_im[TM][KC + 1];
+  static_assert(MR == 1 || MR == 2, "64 or 128 rows per tile");
+  __shared__ double As_re[TM * MR][KC + 1], As_im[TM * MR][KC + 1];
   __shared__ double Bs_re[KC][TN + 1], Bs_im[KC][TN + 1];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = w >> 1, wc = w & 1;
   if constexpr (ZERO) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2 * MR; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         cre[i][j] = d4{0, 0, 0, 0};
         cim[i][j] = d4{0, 0, 0, 0};
       }
   }
-  // this thread's staging positions: A (row ar, k ac + i) or, transposed,
-  // (k ak, rows am + i); B (k bk, cols bc + i) or, transposed, (col bn, k bkc + i)
+  // this thread's staging positions: A (rows ar + 64 m, k ac + i) or,
+  // transposed, (k ak, rows am + 64 m + i); B (k bk, cols bc + i) or,
+  // transposed, (col bn, k bkc + i)
   const int ar = t >> 2, ac = (t & 3) * 4;
   const int ak = t >> 4, am = (t & 15) * 4;
   const int bk = t >> 4, bc = (t & 15) * 4;
   const int bn = t >> 2, bkc = (t & 3) * 4;
-  double2 ra[4], rb[4];
+  double2 ra[4 * MR], rb[4];
   int mn[B_MAP ? 4 : 1];  // mapped columns of this thread's B elements (fixed over k)
   if constexpr (B_MAP) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) mn[i] = b_off + bc + i < b_lim ? bmap[b_off + bc + i] : 0;
+    for (int i = 0; i < 4; ++i) {
+      const int n = b_off + bc + i;
+      mn[i] = n < b_lim ? (bmap ? bmap[n] : n) : 0;
+    }
   }
   auto load = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int e = 0; e < 4 * MR; ++e) {
+      const int i = e & 3, m64 = (e >> 2) * 64;
       bool ok;
       size_t idx;
       if constexpr (!A_T) {
-        const int gr = a_off + ar, k = k0 + ac + i;
+        const int gr = a_off + ar + m64, k = k0 + ac + i;
         ok = gr < a_lim && k < K;
         idx = (size_t)gr * lda + k;
       } else {
-        const int m = a_off + am + i, k = k0 + ak;
+        const int m = a_off + am + m64 + i, k = k0 + ak;
         ok = m < a_lim && k < K;
         idx = (size_t)k * lda + m;
       }
       const double2 v = gld(A, ok ? idx : 0);
-      ra[i] = make_double2(ok ? v.x : 0.0, ok ? v.y : 0.0);
+      ra[e] = make_double2(ok ? v.x : 0.0, ok ? v.y : 0.0);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -89,7 +97,7 @@ __device__ __forceinline__ void tile_gemm(const double2* __restrict__ A, int lda
       } else if constexpr (B_MAP) {
         const int n = b_off + bc + i, k = k0 + bk;
         ok = k < K && n < b_lim;
-        idx = (size_t)(k < K ? bmap[k] : 0) * ldb + mn[i];
+        idx = (size_t)(k < K ? (bmap ? bmap[k] : k) : 0) * ldb + mn[i];
       } else {
         const int n = b_off + bc + i, k = k0 + bk;
         ok = k < K && n < b_lim;
@@ -101,14 +109,18 @@ __device__ __forceinline__ void tile_gemm(const double2* __restrict__ A, int lda
   };
   auto store = [&]() {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int e = 0; e < 4 * MR; ++e) {
+      const int i = e & 3, m64 = (e >> 2) * 64;
       if constexpr (!A_T) {
-        As_re[ar][ac + i] = ra[i].x;
-        As_im[ar][ac + i] = CONJ_A ? -ra[i].y : ra[i].y;
+        As_re[ar + m64][ac + i] = ra[e].x;
+        As_im[ar + m64][ac + i] = CONJ_A ? -ra[e].y : ra[e].y;
       } else {
-        As_re[am + i][ak] = ra[i].x;
-        As_im[am + i][ak] = CONJ_A ? -ra[i].y : ra[i].y;
+        As_re[am + m64 + i][ak] = ra[e].x;
+        As_im[am + m64 + i][ak] = CONJ_A ? -ra[e].y : ra[e].y;
       }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
       if constexpr (B_T) {
         Bs_re[bkc + i][bn] = rb[i].x;
         Bs_im[bkc + i][bn] = rb[i].y;
@@ -125,16 +137,19 @@ __device__ __forceinline__ void tile_gemm(const double2* __restrict__ A, int lda
     if (k0 + KC < K) load(k0 + KC);  // in flight during the MFMAs below
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
-      double are[2], aim[2], bre[2], bim[2];
+      double are[2 * MR], aim[2 * MR], bre[2], bim[2];
+#pragma unroll
+      for (int i = 0; i < 2 * MR; ++i) {
+        are[i] = As_re[wr * 32 * MR + i * 16 + (lane & 15)][kk + (lane >> 4)];
+        aim[i] = As_im[wr * 32 * MR + i * 16 + (lane & 15)][kk + (lane >> 4)];
+      }
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        are[i] = As_re[wr * 32 + i * 16 + (lane & 15)][kk + (lane >> 4)];
-        aim[i] = As_im[wr * 32 + i * 16 + (lane & 15)][kk + (lane >> 4)];
         bre[i] = Bs_re[kk + (lane >> 4)][wc * 32 + i * 16 + (lane & 15)];
         bim[i] = Bs_im[kk + (lane >> 4)][wc * 32 + i * 16 + (lane & 15)];
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2 * MR; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           cre[i][j] = mfma64(are[i], bre[j], cre[i][j]);
@@ -184,18 +199,23 @@ struct Split<BSE_BF16X3> {
   }
 };
 
-// LDS image of a 64 x 32 complex operand tile: 4 planes (re hi, re lo, im hi,
-// im lo), each [64 rows][32 k] with k contiguous, row stride padded.
-template <int P>
+// LDS image of an R x 32 complex operand tile: 4 planes (re hi, re lo, im hi,
+// im lo), each [R rows][32 k] with k contiguous, row stride padded.
+template <int P, int R = 64>
 struct TileLds {
   typedef typename Split<P>::T T;
   static constexpr int STRIDE = P == BSE_BF16X3 ? 40 : 33;
-  T v[4][64 * STRIDE];
+  T v[4][R * STRIDE];
 };
+// Dynamic LDS bytes of tile_gemm_mx with MR.
+template <int P, int MR>
+constexpr size_t tile_mx_lds() {
+  return sizeof(TileLds<P, 64 * MR>) + sizeof(TileLds<P>);
+}
 
 // Stores 8 consecutive k values (row r, k0..k0+7) of one operand after the split.
-template <int P>
-__device__ __forceinline__ void put8(TileLds<P>& L, int r, int k0, const double2 (&x)[8], bool conj) {
+template <int P, int R>
+__device__ __forceinline__ void put8(TileLds<P, R>& L, int r, int k0, const double2* x, bool conj) {
   typedef typename Split<P>::T T;
   T h[4][8];
 #pragma unroll
@@ -206,32 +226,33 @@ __device__ __forceinline__ void put8(TileLds<P>& L, int r, int k0, const double2
 #pragma unroll
   for (int pl = 0; pl < 4; ++pl)
 #pragma unroll
-    for (int i = 0; i < 8; ++i) L.v[pl][r * TileLds<P>::STRIDE + k0 + i] = h[pl][i];
+    for (int i = 0; i < 8; ++i) L.v[pl][r * TileLds<P, R>::STRIDE + k0 + i] = h[pl][i];
 }
 
-// One 64x64 complex tile of C = op(A) * B with split operands; operand
-// addressing as in tile_gemm.  zero_head: B[0][0] := 0 when the tile holds it
+// One (64 MR) x 64 complex tile of C = op(A) * B with split operands; operand
+// addressing as in tile_gemm; dynamic LDS of tile_mx_lds<P, MR>() bytes.  zero_head: B[0][0] := 0 when the tile holds it
 // (the q = 0 head is added in FP64 elsewhere).
 // B_PRE: B comes already split, as Bp[n][plane][k] (row stride 4 ldk, planes
 // re hi, re lo, im hi, im lo; zero for k >= K up to a multiple of 32), and is
 // copied to LDS without conversion (B, ldb, B_T and zero_head unused).
 // A_PRE: the same for A, Ap[m][plane][k] (already conjugated if it is to be;
 // A, lda, A_T and CONJ_A unused).
-template <int P, bool CONJ_A, bool B_T, bool A_T = false, bool B_PRE = false, bool A_PRE = false>
+template <int P, bool CONJ_A, bool B_T, bool A_T = false, bool B_PRE = false, bool A_PRE = false, int MR = 1>
 __device__ __forceinline__ void tile_gemm_mx(const double2* __restrict__ A, int lda, int a_off, int a_lim,
                                              const double2* __restrict__ B, int ldb, int b_off, int b_lim, int K,
-                                             bool zero_head, f4 (&cre)[2][2], f4 (&cim)[2][2],
+                                             bool zero_head, f4 (&cre)[2 * MR][2], f4 (&cim)[2 * MR][2],
                                              const typename Split<P>::T* __restrict__ Bp = nullptr, int ldk = 0,
                                              const typename Split<P>::T* __restrict__ Ap = nullptr) {
+  static_assert(MR == 1 || MR == 2, "64 or 128 rows per tile");
   extern __shared__ double2 smem_mx_raw[];  // 16-byte aligned dynamic area
   char* smem_mx = reinterpret_cast<char*>(smem_mx_raw);
-  TileLds<P>& As = *reinterpret_cast<TileLds<P>*>(smem_mx);
-  TileLds<P>& Bs = *reinterpret_cast<TileLds<P>*>(smem_mx + sizeof(TileLds<P>));
+  TileLds<P, 64 * MR>& As = *reinterpret_cast<TileLds<P, 64 * MR>*>(smem_mx);
+  TileLds<P>& Bs = *reinterpret_cast<TileLds<P>*>(smem_mx + sizeof(TileLds<P, 64 * MR>));
   constexpr int ST = TileLds<P>::STRIDE;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = w >> 1, wc = w & 1;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 2 * MR; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       cre[i][j] = f4{0, 0, 0, 0};
@@ -242,28 +263,31 @@ __device__ __forceinline__ void tile_gemm_mx(const double2* __restrict__ A, int 
   // one; out-of-range elements are read from the array start and zeroed
   typedef typename Split<P>::T T;
   constexpr int QW = sizeof(T) * 8 / 16;  // 16-byte words per plane row segment of 8 k
-  double2 xa[A_PRE ? 1 : 8], xb[B_PRE ? 1 : 8];
-  uint4 xp[B_PRE ? 4 * QW : 1], xq[A_PRE ? 4 * QW : 1];
+  double2 xa[A_PRE ? 1 : 8 * MR], xb[B_PRE ? 1 : 8];
+  uint4 xp[B_PRE ? 4 * QW : 1], xq[A_PRE ? 4 * QW * MR : 1];
   auto load = [&](int k0) {
-    const int gr = a_off + r;
-    if constexpr (A_PRE) {
-      const bool ok = gr < a_lim;
-      const T* row = Ap + (ok ? (size_t)gr * 4 * ldk : 0) + k0 + kq;
 #pragma unroll
-      for (int pl = 0; pl < 4; ++pl)
+    for (int m = 0; m < MR; ++m) {
+      const int gr = a_off + r + 64 * m;
+      if constexpr (A_PRE) {
+        const bool ok = gr < a_lim;
+        const T* row = Ap + (ok ? (size_t)gr * 4 * ldk : 0) + k0 + kq;
 #pragma unroll
-        for (int w4 = 0; w4 < QW; ++w4) {
-          const uint4 v = gld16(reinterpret_cast<const uint4*>(row + (size_t)pl * ldk) + w4);
-          xq[pl * QW + w4] = ok ? v : make_uint4(0u, 0u, 0u, 0u);
+        for (int pl = 0; pl < 4; ++pl)
+#pragma unroll
+          for (int w4 = 0; w4 < QW; ++w4) {
+            const uint4 v = gld16(reinterpret_cast<const uint4*>(row + (size_t)pl * ldk) + w4);
+            xq[(m * 4 + pl) * QW + w4] = ok ? v : make_uint4(0u, 0u, 0u, 0u);
+          }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int k = k0 + kq + i;
+          const bool ok = gr < a_lim && k < K;
+          const size_t idx = A_T ? (size_t)k * lda + gr : (size_t)gr * lda + k;
+          const double2 v = gld(A, ok ? idx : 0);
+          xa[m * 8 + i] = make_double2(ok ? v.x : 0.0, ok ? v.y : 0.0);
         }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int k = k0 + kq + i;
-        const bool ok = gr < a_lim && k < K;
-        const size_t idx = A_T ? (size_t)k * lda + gr : (size_t)gr * lda + k;
-        const double2 v = gld(A, ok ? idx : 0);
-        xa[i] = make_double2(ok ? v.x : 0.0, ok ? v.y : 0.0);
       }
     }
     if constexpr (B_PRE) {
@@ -289,15 +313,18 @@ __device__ __forceinline__ void tile_gemm_mx(const double2* __restrict__ A, int 
   };
   if (K > 0) load(0);
   for (int k0 = 0; k0 < K; k0 += MKC) {
-    if constexpr (A_PRE) {
 #pragma unroll
-      for (int pl = 0; pl < 4; ++pl) {
-        const T* src = reinterpret_cast<const T*>(&xq[pl * QW]);
+    for (int m = 0; m < MR; ++m) {
+      if constexpr (A_PRE) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) As.v[pl][r * ST + kq + i] = src[i];
+        for (int pl = 0; pl < 4; ++pl) {
+          const T* src = reinterpret_cast<const T*>(&xq[(m * 4 + pl) * QW]);
+#pragma unroll
+          for (int i = 0; i < 8; ++i) As.v[pl][(r + 64 * m) * ST + kq + i] = src[i];
+        }
+      } else {
+        put8<P>(As, r + 64 * m, kq, xa + 8 * m, CONJ_A);
       }
-    } else {
-      put8<P>(As, r, kq, xa, CONJ_A);
     }
     if constexpr (B_PRE) {
 #pragma unroll
@@ -312,16 +339,20 @@ __device__ __forceinline__ void tile_gemm_mx(const double2* __restrict__ A, int 
     __syncthreads();
     if (k0 + MKC < K) load(k0 + MKC);
     if constexpr (P == BSE_BF16X3) {
-      s8 a[2][4], b[2][4];
+      s8 a[2 * MR][4], b[2][4];
+#pragma unroll
+      for (int i = 0; i < 2 * MR; ++i)
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl)
+          a[i][pl] =
+              *reinterpret_cast<const s8*>(&As.v[pl][(wr * 32 * MR + i * 16 + (lane & 15)) * ST + 8 * (lane >> 4)]);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int pl = 0; pl < 4; ++pl) {
-          a[i][pl] = *reinterpret_cast<const s8*>(&As.v[pl][(wr * 32 + i * 16 + (lane & 15)) * ST + 8 * (lane >> 4)]);
+        for (int pl = 0; pl < 4; ++pl)
           b[i][pl] = *reinterpret_cast<const s8*>(&Bs.v[pl][(wc * 32 + i * 16 + (lane & 15)) * ST + 8 * (lane >> 4)]);
-        }
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < 2 * MR; ++i) {
         s8 nih = a[i][2] ^ (short)0x8000, nil = a[i][3] ^ (short)0x8000;  // -Im(a) parts
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -345,16 +376,19 @@ __device__ __forceinline__ void tile_gemm_mx(const double2* __restrict__ A, int 
     } else {
 #pragma unroll
       for (int kk = 0; kk < MKC; kk += 4) {
-        float a[2][4], b[2][4];
+        float a[2 * MR][4], b[2][4];
+#pragma unroll
+        for (int i = 0; i < 2 * MR; ++i)
+#pragma unroll
+          for (int pl = 0; pl < 4; ++pl)
+            a[i][pl] = As.v[pl][(wr * 32 * MR + i * 16 + (lane & 15)) * ST + kk + (lane >> 4)];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-          for (int pl = 0; pl < 4; ++pl) {
-            a[i][pl] = As.v[pl][(wr * 32 + i * 16 + (lane & 15)) * ST + kk + (lane >> 4)];
+          for (int pl = 0; pl < 4; ++pl)
             b[i][pl] = Bs.v[pl][(wc * 32 + i * 16 + (lane & 15)) * ST + kk + (lane >> 4)];
-          }
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2 * MR; ++i)
 #pragma unroll
           for (int j = 0; j < 2; ++j) {
             f4 cr = cre[i][j], ci = cim[i][j];

@@ -123,9 +123,10 @@ struct GemmArgs {
 hipError_t launch_vscale(const double* vx, int ngx, int ng_max, int g0, double* out, hipStream_t st);
 hipError_t launch_exchange(const GemmArgs* gs, const HTile* tiles, int ntiles, int precision, hipStream_t st);
 // mapped: some system reads W through its sphere maps (FP64; the mixed modes
-// unfold W while they split it)
+// unfold W while they split it).  rows: 64 or 128 rows per tile, as the tile
+// list was made (tile mt covers rows [rows mt, rows (mt + 1))).
 hipError_t launch_direct_s1(const GemmArgs* gs, const S1Tile* tiles, int ntiles, int precision, int mapped,
-                            hipStream_t st);
+                            int rows, hipStream_t st);
 // stage 2 is FP64 in every mode (it adds the FP64 q = 0 head when w_head_fp64)
 hipError_t launch_direct_s2(const GemmArgs* gs, const int* d2off, int nsys, int nitems, hipStream_t st);
 hipError_t launch_mirror(const GemmArgs* gs, const HTile* tiles, int ntiles, hipStream_t st);
@@ -147,7 +148,8 @@ hipError_t launch_split_w(const double2* W, const int* ng, const int* wsrc, cons
                           int kpad, int head, int precision, void* Ws, hipStream_t st);
 // mixed-precision bodies (precision BSE_SPLIT_FP32 or BSE_BF16X3), called by the above
 hipError_t launch_exchange_mx(const GemmArgs* gs, const HTile* tiles, int ntiles, int precision, hipStream_t st);
-hipError_t launch_direct_s1_mx(const GemmArgs* gs, const S1Tile* tiles, int ntiles, int precision, hipStream_t st);
+hipError_t launch_direct_s1_mx(const GemmArgs* gs, const S1Tile* tiles, int ntiles, int precision, int rows,
+                               hipStream_t st);
 // system of stage-2 item `item`: the last s with d2off[s] <= item
 __device__ __forceinline__ int item_system(const int* __restrict__ d2off, int nsys, int item) {
   int lo = 0, hi = nsys - 1;
