@@ -199,6 +199,7 @@ struct Plan {
   int g0x = 0;                     // position of G = 0 in the sphere of Q (-1: absent)
   // coupling block of the beyond-TDA matrix: every ordered pair, rows (v, c') and (c, v')
   bool coupling = false;
+  bool cswap = false;              // coupling: the (c, v') rows of (k, k') gathered from the (v, c') rows of (k', k)
   int ldh = 0;                     // row stride of the output matrix
   int rv_rows = 0, rc_rows = 0;    // rows per pair of RV / Z and of RC
   std::vector<int> inv0;           // coupling: position of -G in the q = 0 sphere
@@ -446,13 +447,24 @@ int plan_pairs(const bse_system* s, Plan& P, const BatchOpts& opt, int nchunk, i
   std::vector<int2> lp(np);
   for (int a = 0, i = 0; a < nk; ++a)
     for (int b = P.coupling ? 0 : a; b < nk; ++b) lp[i++] = make_int2(a, b);
-  // units: a transformed pair and, with time reversal, the image gathered from it
+  // units: a transformed pair and, with time reversal, the image gathered from it.
+  // Coupling block with spheres closed under G -> t - G: the unit is (k, k') with
+  // k <= k' and its reverse (k', k); only their (v, c') rows are transformed, and
+  // n_{ck, v'k'}(G) = conj(n_{v'k', ck}(t - G)) (-q = qbar + t) gives the (c, v')
+  // rows of each from the other's (of itself when k = k').
   struct Unit {
     int rep, img, mode;
   };
   std::vector<Unit> units;
   units.reserve(np);
+  P.cswap = P.coupling && P.tr_closed;
   for (int p = 0; p < np; ++p) {
+    if (P.cswap) {
+      const int ka = lp[p].x, kb = lp[p].y;
+      if (ka > kb) continue;  // the reverse of a unit
+      units.push_back(Unit{p, ka < kb ? kb * nk + ka : -1, 0});
+      continue;
+    }
     if (!opt.tr) {
       units.push_back(Unit{p, -1, 0});
       continue;
@@ -530,6 +542,17 @@ int plan_pairs(const bse_system* s, Plan& P, const BatchOpts& opt, int nchunk, i
     for (const Unit* u : cu[c]) {
       const int g = g_of_lex[u->rep], loc = g - next;
       const int4 q4 = P.pairs[g];
+      if (P.cswap) {  // n_{vk, c'k'} of the pair and of its reverse; the (c, v') rows of each from the other
+        K.jv.push_back(PdJob{q4.x, q4.y, q4.w, q4.z, 0, nv, nv | (nc << 8), loc * nv * nc});
+        const int gi = u->img >= 0 ? g_of_lex[u->img] : g, li = gi - next;
+        if (u->img >= 0) {
+          const int4 r4 = P.pairs[gi];
+          K.jv.push_back(PdJob{r4.x, r4.y, r4.w, r4.z, 0, nv, nv | (nc << 8), li * nv * nc});
+          K.fill.push_back(make_int4(li, loc, r4.z << 1, sys));
+        }
+        K.fill.push_back(make_int4(loc, li, q4.z << 1, sys));
+        continue;
+      }
       if (P.coupling) {  // n_{vk, c'k'} and n_{ck, v'k'}
         K.jv.push_back(PdJob{q4.x, q4.y, q4.w, q4.z, 0, nv, nv | (nc << 8), loc * nv * nc});
         K.jc.push_back(PdJob{q4.x, q4.y, q4.w, q4.z, nv, 0, nc | (nv << 8), loc * nc * nv});
@@ -795,6 +818,7 @@ struct Batch {
   bool tr = false;             // pair densities of time-reversal images derived
   bool pd32 = false;           // FP32 valence / conduction pair densities
   bool mapped = false;         // some system gives W at the irreducible q points only
+  bool cswap = false;          // coupling rows gathered from the reversed pairs (fill kind 3)
   int s1_rows = 64;            // rows per tile of the first direct-term contraction
   int np32 = 2;                // their planes per step: 4 when every window has F2 <= 16
   size_t lds32 = 0;            // their LDS bytes
@@ -839,6 +863,7 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
     }
     B.ng_max = std::max(B.ng_max, P.ng_max);
     B.mapped = B.mapped || P.nirr > 0;
+    B.cswap = B.cswap || P.cswap;
     const size_t l = pd_lds_bytes(P.N1, P.N2, P.N3, P.F[1], P.F[2], P.ng_max, 0);
     B.pd32 = B.pd32 && P.pd32;
     if (l > 160 * 1024) return fail(BSE_ERR_SHAPE, "FFT window of system %d needs more than 160 KiB of LDS", i);
@@ -904,7 +929,7 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
   B.o_jx = put(B.jx.size() * sizeof(PdJob));
   B.o_xt = put(B.xt.size() * sizeof(HTile));
   B.o_mt = put(B.mt.size() * sizeof(HTile));
-  B.o_tra = put(opt.tr ? nsys * sizeof(TrArgs) : 0);
+  B.o_tra = put(opt.tr || B.cswap ? nsys * sizeof(TrArgs) : 0);
   for (BatchChunk& K : B.C) {
     K.o_gargs = put(nsys * sizeof(GemmArgs));
     K.o_jd = put(K.jd.size() * sizeof(PdJob));
@@ -1015,7 +1040,7 @@ int upload_batch(const Batch& B, const bse_system* sys, int precision, char* ws,
     if (bytes) std::memcpy(buf + off, src, bytes);
   };
   std::vector<PdArgs> ax(nsys), ad(2 * nsys);
-  std::vector<TrArgs> ta(B.tr ? nsys : 0);
+  std::vector<TrArgs> ta(B.tr || B.cswap ? nsys : 0);
   for (int i = 0; i < nsys; ++i) {
     const Plan& P = B.P[i];
     char* region = ws + B.base[i];
@@ -1027,7 +1052,7 @@ int upload_batch(const Batch& B, const bse_system* sys, int precision, char* ws,
     ad[2 * i].out = reinterpret_cast<double2*>(region + P.o_RV);
     ad[2 * i + 1] = a;
     ad[2 * i + 1].out = reinterpret_cast<double2*>(region + P.o_RC);
-    if (B.tr) {
+    if (B.tr || B.cswap) {
       TrArgs& r = ta[i];
       r.rv = reinterpret_cast<double2*>(region + P.o_RV);
       r.rc = reinterpret_cast<double2*>(region + P.o_RC);
@@ -1111,8 +1136,10 @@ int run_pd(const Batch& B, char* ws, int kind, int c, const Tune& tn, hipStream_
 
 // Pair densities of the time-reversal images of chunk c (kind 1 vv, 2 cc),
 // after the pair-density launch of the same kind.
+// kind 1, 2: time-reversal images (valence, conduction rows); kind 3: the
+// coupling block's (c, v') rows from the reversed pairs' (v, c') rows.
 int run_tr_fill(const Batch& B, char* ws, int kind, int c, hipStream_t st) {
-  if (!B.tr || kind == 0 || B.C[c].fill.empty()) return BSE_OK;
+  if (!(kind == 3 ? B.cswap : B.tr) || kind == 0 || B.C[c].fill.empty()) return BSE_OK;
   HIP_TRY(stage(BSE_STAGE_TR_FILL, st, [&] {
     return launch_tr_fill(reinterpret_cast<const TrArgs*>(ws + B.o_tra),
                           reinterpret_cast<const int4*>(ws + B.C[c].o_fill), (int)B.C[c].fill.size(), kind, st);
@@ -1216,7 +1243,7 @@ int run_build(const Batch& B, const bse_system* sys, int precision, const Tune& 
     const BatchChunk& K = B.C[c];
     const GemmArgs* gs = reinterpret_cast<const GemmArgs*>(ws + K.o_gargs);
     if ((rc = run_pd(B, ws, 1, c, tn, st)) || (rc = run_tr_fill(B, ws, 1, c, st)) ||
-        (rc = run_tr_fill(B, ws, 2, c, st)))
+        (rc = run_tr_fill(B, ws, 2, c, st)) || (rc = run_tr_fill(B, ws, 3, c, st)))
       return rc;
     if ((rc = split_rv_chunk(B, precision, ws, c, st))) return rc;
     const S1Tile* s1 = reinterpret_cast<const S1Tile*>(ws + K.o_s1);
