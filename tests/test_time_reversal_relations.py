@@ -75,3 +75,29 @@ def test_images_fail_without_time_reversal():
     # the same relations do not hold for wave functions drawn independently at k and -k
     err, _ = _relation_errors(_system(False))
     assert err > 1e-3
+
+
+@pytest.mark.parametrize("tr", [False, True])
+def test_reversed_pair_conjugation(tr):
+    """Without any symmetry of u: n_{ck,v'k'}(G) = conj(n_{v'k',ck}(G'')),
+    G'' = t - G with -q = qbar + t (the sphere map of W), for every ordered
+    pair, the diagonal ones included; the GPU's beyond-TDA coupling block
+    gathers its (c, v') rows by it.  A plain conjugate on the same G fails."""
+    s = _system(tr, (3, 2, 1))
+    nv, nc = s.nv, s.nc
+    worst, naive = 0.0, 0.0
+    for ka in range(s.nk):
+        for kb in range(s.nk):
+            iq, _ = O.fold(s.kmesh, ka, kb)
+            iqr, _ = O.fold(s.kmesh, kb, ka)
+            qb, perm = B.tr_partner(s, iq)
+            assert qb == iqr and perm.min() >= 0
+            ng = s.ng[iq]
+            items = [(ka, nv + c, kb, v) for c in range(nc) for v in range(nv)]
+            rev = [(kb, v, ka, nv + c) for c in range(nc) for v in range(nv)]
+            a = O.pair_density_items(s, items)[:, :ng]
+            b = O.pair_density_items(s, rev)
+            worst = max(worst, float(np.abs(a - np.conj(b[:, perm[:ng]])).max()))
+            naive = max(naive, float(np.abs(a - np.conj(b[:, :ng])).max()))
+    assert worst <= 1e-14, worst
+    assert naive > 1e-3
