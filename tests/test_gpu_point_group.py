@@ -156,3 +156,22 @@ def test_screening_at_the_irreducible_points():
     dh = np.abs(H - Href).max()
     _say(f"H from the irreducible screened W: max|dH| vs oracle {dh:.3e} eV")
     assert dh <= fp64_h_bar(Href) + 1e-11 * np.abs(Href - np.diag(np.diag(Href))).max()
+
+
+def test_irreducible_W_at_finite_momentum_and_beyond_tda():
+    """The mapped W loader in the other builds that run the direct term: at
+    finite exciton momentum, and in the coupling block of the beyond-TDA
+    matrix, W through the maps gives the same matrix as W at every q."""
+    import paper_1206_3518_amd as P
+    import torch
+    s = B.with_point_group_W(_fcc2(), proper=True)
+    sq = B.with_exciton_momentum(s, 3)
+    a = P.build_H(P.DeviceSystem(sq), "fp64").clone()
+    b = P.build_H(P.DeviceSystem(sq, irreducible_W=True), "fp64")
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    f1 = P.bse_build_H_full(P.DeviceSystem(s)).clone()
+    f2 = P.bse_build_H_full(P.DeviceSystem(s, irreducible_W=True))
+    torch.cuda.synchronize()
+    _say(f"finite Q and beyond-TDA with irreducible W: equal {torch.equal(a, b)}, {torch.equal(f1, f2)}")
+    assert torch.equal(f1, f2)
