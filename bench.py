@@ -20,8 +20,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"hbm_GBps": 8000.0, "fp64_TFLOPs": 78.6, "fp32_TFLOPs": 157.3, "bf16_TFLOPs": 2500.0,
-        # FP32 vector arithmetic without the packed forms (which this build
-        # leaves out): 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz, the
+        # FP32 vector arithmetic without the packed forms (which the library
+        # is compiled without): 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz, the
         # FP64 vector rate
         "fp32_valu_unpacked_TFLOPs": 78.6}
 DTYPES = {"fp64": "f64", "split_fp32": "f32x3", "bf16x3": "bf16x3"}
@@ -158,7 +158,7 @@ def main():
                     help="also run one plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
         return
 
