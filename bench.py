@@ -275,12 +275,15 @@ def main():
                   "precision": args.precision, "parallelism": "single-gpu", "workspace_GB": ws.numel() / 1e9}
     if tuning is not None:
         config["autotune_candidates_ms"] = {
-            (f"persistent/{c['wg_per_cu']}" if c["persistent"] else f"static/k{c['ktile']}"): round(c["pd_ms"], 3)
+            (f"persistent/{c['wg_per_cu']}" if c["persistent"]
+             else f"static/k{c['ktile']}" + ("", "/interleaved", "/kind-major")[c["order"]]): round(c["pd_ms"], 3)
             for c in tried if c["s1_ms"] == 0}
         config["autotune_stage1_tiles_ms"] = {f"{c['s1_rows']}x64": round(c["s1_ms"], 3) for c in tried
                                               if c["s1_ms"] > 0}
         config["dispatch"] = (f"autotuned: persistent, {tuning['wg_per_cu']} workgroups/CU" if tuning["persistent"]
-                              else f"autotuned: static, k tile {tuning['ktile']}")
+                              else f"autotuned: static, k tile {tuning['ktile']}"
+                              + (", one segment per XCD", ", interleaved across XCDs",
+                                 ", one segment per XCD, kind-major")[tuning["order"]])
         config["stage1_tile"] = f"autotuned: {tuning['s1_rows']} x 64"
     else:
         config["dispatch"] = "persistent" if args.persistent else "static, k tile 8"

@@ -254,14 +254,18 @@ typedef struct bse_tuning {
                         direct-term contraction conj(rho_vv')^T W(q)             */
     float s1_ms;     /* measured launch of that contraction (first chunk), ms;
                         0 in the entries that time the pair densities          */
+    int order;       /* static pair-density job order: 0 one contiguous segment
+                        of k tiles per XCD; 1 the tiles dealt in order across
+                        the XCDs; 2 as 0 with the valence-pair jobs of a
+                        system before its conduction-pair jobs                 */
 } bse_tuning;
 
 /*
  * Autotuner (for callers that build the same batch shape many times).  Times
  * the dominant launch (the valence and conduction pair densities of the first
  * chunk of k pairs) of this batch under
- * static dispatch with k tiles 4, 8, 16 and persistent dispatch with 1..4
- * workgroups per CU; then, with the fastest of those, the first direct-term
+ * static dispatch with k tiles 4, 8, 16 in each job order (field order of
+ * bse_tuning), and persistent dispatch with 1..4 workgroups per CU; then, with the fastest of those, the first direct-term
  * contraction of that chunk (in the given precision) with workgroup tiles of
  * 64 x 64 and 128 x 64 complex outputs.  It keeps both choices for every
  * later bse_build_H of the same signature in this process (BSE_PERSISTENT

@@ -34,7 +34,8 @@ class BseError(RuntimeError):
 
 class bse_tuning(ctypes.Structure):
     _fields_ = [("persistent", ctypes.c_int), ("ktile", ctypes.c_int), ("wg_per_cu", ctypes.c_int),
-                ("pd_ms", ctypes.c_float), ("s1_rows", ctypes.c_int), ("s1_ms", ctypes.c_float)]
+                ("pd_ms", ctypes.c_float), ("s1_rows", ctypes.c_int), ("s1_ms", ctypes.c_float),
+                ("order", ctypes.c_int)]
 
 
 class bse_system(ctypes.Structure):
@@ -226,7 +227,7 @@ def bse_autotune(systems, precision=BSE_FP64, cache_path=None, ws=None, stream=N
     _check(lib().bse_autotune(arr, len(systems), int(precision), int(flags), path, ctypes.byref(out), _ptr(ws),
                               ws.numel(), _stream(stream)))
     return {"persistent": out.persistent, "ktile": out.ktile, "wg_per_cu": out.wg_per_cu, "pd_ms": out.pd_ms,
-            "s1_rows": out.s1_rows, "s1_ms": out.s1_ms}
+            "s1_rows": out.s1_rows, "s1_ms": out.s1_ms, "order": out.order}
 
 
 def bse_autotune_last() -> list:
@@ -236,7 +237,8 @@ def bse_autotune_last() -> list:
     if n < 0:
         raise BseError(n, bse_last_error())
     return [{"persistent": arr[i].persistent, "ktile": arr[i].ktile, "wg_per_cu": arr[i].wg_per_cu,
-             "pd_ms": arr[i].pd_ms, "s1_rows": arr[i].s1_rows, "s1_ms": arr[i].s1_ms} for i in range(min(n, 32))]
+             "pd_ms": arr[i].pd_ms, "s1_rows": arr[i].s1_rows, "s1_ms": arr[i].s1_ms,
+             "order": arr[i].order} for i in range(min(n, 32))]
 
 
 def bse_pair_density(system: DeviceSystem, kind, kpairs=None, ws=None, stream=None, cell=None):

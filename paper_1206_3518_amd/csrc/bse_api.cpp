@@ -138,15 +138,19 @@ void fold(const int* n, int ka, int kb, int& iq, int m0[3]) {
 // wave functions of few k points, which its L2 holds plane by plane.  Chunk x
 // is stored at positions 8 t + x (static dispatch hands workgroup 8 t + x to
 // XCD x; persistent dispatch uses chunk x as the XCD's queue).  Holes become
-// empty jobs.
+// empty jobs.  Tuning choices (order): 0 as above; 1 interleaved, the sorted
+// jobs in order, so that the eight XCDs work through the same tiles at once;
+// 2 kind-major, the valence-pair jobs of a system before its conduction-pair
+// jobs, so that the resident jobs of an XCD read the grids of one band set.
 constexpr int kXcds = 8;
 // queue counters of the three pair-density kinds, then the validation flags
 constexpr size_t kCntBytes = 3 * kXcds * kQueueStride * sizeof(unsigned);
 
-std::vector<PdJob> dispatch_order(std::vector<PdJob> jobs, int ktile) {
-  std::stable_sort(jobs.begin(), jobs.end(), [ktile](const PdJob& x, const PdJob& y) {
+std::vector<PdJob> dispatch_order(std::vector<PdJob> jobs, int ktile, int order = 0) {
+  std::stable_sort(jobs.begin(), jobs.end(), [ktile, order](const PdJob& x, const PdJob& y) {
     const int sx = x.nab >> 16, sy = y.nab >> 16;
     if (sx != sy) return sx < sy;
+    if (order == 2 && (x.a0 != 0) != (y.a0 != 0)) return x.a0 == 0;  // valence-pair jobs first
     const int tx = x.ka / ktile, ty = y.ka / ktile, ux = x.kb / ktile, uy = y.kb / ktile;
     if (tx != ty) return tx < ty;
     if (ux != uy) return ux < uy;
@@ -154,6 +158,10 @@ std::vector<PdJob> dispatch_order(std::vector<PdJob> jobs, int ktile) {
     return x.kb < y.kb;
   });
   const size_t n = jobs.size(), c = (n + kXcds - 1) / kXcds;
+  if (order == 1) {
+    jobs.resize(c * kXcds, PdJob{0, 0, pack_m(0, 0, 0), 0, 0, 0, 0, 0});
+    return jobs;
+  }
   std::vector<PdJob> out(c * kXcds, PdJob{0, 0, pack_m(0, 0, 0), 0, 0, 0, 0, 0});
   for (size_t x = 0; x < (size_t)kXcds; ++x)
     for (size_t t = 0; t < c && x * c + t < n; ++t) out[t * kXcds + x] = jobs[x * c + t];
@@ -758,6 +766,7 @@ struct Tune {
   float pd_ms = 0.f;  // measured time of the tuned pair-density launch (0: not measured)
   int s1_rows = 64;   // rows per tile of the direct term's first contraction (64 or 128)
   float s1_ms = 0.f;  // measured time of that launch (0: not measured)
+  int order = 0;      // pair-density job order: 0 per-XCD segments, 1 interleaved, 2 kind-major segments
 };
 std::mutex g_tune_mu;
 std::vector<std::pair<std::string, Tune>> g_tune;
@@ -893,7 +902,7 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
     B.xt.insert(B.xt.end(), P.xt.begin(), P.xt.end());
     B.mt.insert(B.mt.end(), P.mt.begin(), P.mt.end());
   }
-  B.jx = dispatch_order(std::move(jx), tn.ktile);
+  B.jx = dispatch_order(std::move(jx), tn.ktile, tn.order);
   for (int c = 0; c < nc; ++c) {
     BatchChunk& K = B.C[c];
     std::vector<PdJob> jd;
@@ -915,7 +924,7 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
       }
     }
     K.d2n = K.d2off[nsys];
-    K.jd = dispatch_order(std::move(jd), tn.ktile);
+    K.jd = dispatch_order(std::move(jd), tn.ktile, tn.order);
   }
   // workspace: batch tables, then one region per system
   size_t o = 0;
@@ -955,7 +964,8 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
 std::string plan_key(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts& o) {
   std::string k = std::to_string(nsys) + (o.backward ? "b" : "f") + (o.project ? "p" : "") + (o.tr ? "t" : "") +
                   (o.pd32 ? "s" : "") + (o.mixed ? "m" : "") + (o.coupling ? "x" : "") + "l" + std::to_string(o.ldh) +
-                  "k" + std::to_string(tn.ktile) + "r" + std::to_string(tn.s1_rows) + "c" +
+                  "k" + std::to_string(tn.ktile) + "r" + std::to_string(tn.s1_rows) + "o" +
+                  std::to_string(tn.order) + "c" +
                   std::to_string(g_chunk_budget.load());
   for (int i = 0; i < nsys; ++i) {
     const bse_system& s = sys[i];
@@ -1419,7 +1429,8 @@ int validate(const Batch& B, const bse_system* sys, char* ws, hipStream_t st) {
 // ------------------------------------------------------------ autotuning
 
 // Tuning cache: one line per batch signature,
-//   {"key": "<signature>", "persist": P, "ktile": T, "wg_per_cu": W, "pd_ms": M, "s1_rows": R, "s1_ms": S}
+//   {"key": "<signature>", "persist": P, "ktile": T, "wg_per_cu": W, "pd_ms": M, "s1_rows": R, "s1_ms": S,
+//    "order": O}
 bool cache_lookup(const char* path, const std::string& key, Tune& out) {
   if (!path) return false;
   FILE* f = fopen(path, "r");
@@ -1432,10 +1443,11 @@ bool cache_lookup(const char* path, const std::string& key, Tune& out) {
     Tune t;
     float ms = 0.f, s1ms = 0.f;
     if (sscanf(line + want.size(),
-               " \"persist\": %d, \"ktile\": %d, \"wg_per_cu\": %d, \"pd_ms\": %f, \"s1_rows\": %d, \"s1_ms\": %f",
-               &t.persist, &t.ktile, &t.wg_per_cu, &ms, &t.s1_rows, &s1ms) == 6 &&
+               " \"persist\": %d, \"ktile\": %d, \"wg_per_cu\": %d, \"pd_ms\": %f, \"s1_rows\": %d, \"s1_ms\": %f, "
+               "\"order\": %d",
+               &t.persist, &t.ktile, &t.wg_per_cu, &ms, &t.s1_rows, &s1ms, &t.order) == 7 &&
         (t.persist == 0 || t.persist == 1) && t.ktile >= 1 && t.ktile <= 1024 && t.wg_per_cu >= 1 && t.wg_per_cu <= 8 &&
-        (t.s1_rows == 64 || t.s1_rows == 128)) {
+        (t.s1_rows == 64 || t.s1_rows == 128) && (t.order >= 0 && t.order <= 2)) {
       t.pd_ms = ms;
       t.s1_ms = s1ms;
       out = t;
@@ -1451,7 +1463,8 @@ void cache_store(const char* path, const std::string& key, const Tune& t) {
   FILE* f = fopen(path, "a");
   if (!f) return;
   fprintf(f, "{\"key\": \"%s\", \"persist\": %d, \"ktile\": %d, \"wg_per_cu\": %d, \"pd_ms\": %.9g, \"s1_rows\": %d, "
-          "\"s1_ms\": %.9g}\n", key.c_str(), t.persist, t.ktile, t.wg_per_cu, (double)t.pd_ms, t.s1_rows, (double)t.s1_ms);
+          "\"s1_ms\": %.9g, \"order\": %d}\n", key.c_str(), t.persist, t.ktile, t.wg_per_cu, (double)t.pd_ms, t.s1_rows,
+          (double)t.s1_ms, t.order);
   fclose(f);
 }
 
@@ -1476,11 +1489,13 @@ int autotune(const bse_system* sys, int nsys, int precision, bool pd32, const ch
   }
   if (ws_bytes < B0.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, B0.total);
   std::vector<Tune> cand;
-  for (int kt : {4, 8, 16}) {
-    Tune t;
-    t.ktile = kt;
-    cand.push_back(t);
-  }
+  for (int od : {0, 2, 1})
+    for (int kt : {4, 8, 16}) {
+      Tune t;
+      t.ktile = kt;
+      t.order = od;
+      cand.push_back(t);
+    }
   for (int w : {1, 2, 3, 4}) {
     Tune t;
     t.persist = 1;
@@ -1768,7 +1783,8 @@ int bse_build_H(const bse_system* sys, int nsys, int precision, int flags, void*
   Tune tn = tune_for(batch_key(Bp->P, precision, Bp->pd32));
   if (flags & BSE_PERSISTENT) tn.persist = 1;
   if (precision == BSE_SPLIT_FP32) tn.s1_rows = 64;  // FP32 parts: 64-row tiles only
-  if ((tn.ktile != Tune{}.ktile || tn.s1_rows != Tune{}.s1_rows) && (rc = cached_batch(sys, nsys, tn, opt, &Bp)))
+  if ((tn.ktile != Tune{}.ktile || tn.s1_rows != Tune{}.s1_rows || tn.order != Tune{}.order) &&
+      (rc = cached_batch(sys, nsys, tn, opt, &Bp)))
     return rc;
   const Batch& B = *Bp;
   if (ws_bytes < B.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, B.total);
@@ -1921,6 +1937,7 @@ int bse_autotune(const bse_system* sys, int nsys, int precision, int flags, cons
     chosen->pd_ms = t.pd_ms;
     chosen->s1_rows = t.s1_rows;
     chosen->s1_ms = t.s1_ms;
+    chosen->order = t.order;
   }
   return BSE_OK;
 }
@@ -1935,6 +1952,7 @@ int bse_autotune_last(bse_tuning* tried, int max_tried) {
     tried[i].pd_ms = g_tried[i].pd_ms;
     tried[i].s1_rows = g_tried[i].s1_rows;
     tried[i].s1_ms = g_tried[i].s1_ms;
+    tried[i].order = g_tried[i].order;
   }
   return (int)g_tried.size();
 }

@@ -24,8 +24,12 @@ def test_autotune_choice_cache_and_results(tmp_path):
     before = [d.H.clone() for d in devs]
     cache = tmp_path / "tune.jsonl"
     got = P.bse_autotune(devs, P.BSE_FP64, cache, ws)
+    tried = P.bse_autotune_last()
     print("autotune choice:", got, flush=True)
     sys.stdout.flush()
+    pd = [t for t in tried if t["s1_ms"] == 0]
+    assert len(pd) == 13 and sorted(t["order"] for t in pd if not t["persistent"]) == [0, 0, 0, 1, 1, 1, 2, 2, 2]
+    assert got["order"] in (0, 1, 2) and (got["order"] == 0 or not got["persistent"])
     assert got["persistent"] in (0, 1) and got["pd_ms"] > 0.0
     if got["persistent"]:
         assert got["wg_per_cu"] in (1, 2, 3, 4)
