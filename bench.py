@@ -411,8 +411,10 @@ def screening_leg(P, n_empty=60):
     """The static RPA screened interaction of the 24^3 Si-like shape (fcc
     a = 10.26 bohr, 4 x 4 x 4 k, 6 Ha: 169-200 plane waves per q) from 4
     occupied and n_empty empty bands (the paper takes 60-90 empty bands,
-    Sec. IV.B): pair densities of every (k, k+q), the chi0 contraction on
-    FP64 MFMA and the inversion of eps per q, timed with HIP events."""
+    Sec. IV.B): pair densities of every (k, k+q) (occupied x empty; the
+    empty x occupied ones gathered from the partner q), the chi0
+    contraction on FP64 MFMA and the inversion of eps per q, timed with HIP
+    events."""
     import torch
     import bse_synth as B
     s = B.make_system(B.cell_fcc(B.A_SI), (24, 24, 24), (4, 4, 4), 4, n_empty, 6.0, seed=1300,
@@ -448,8 +450,9 @@ def screening_leg(P, n_empty=60):
     torch.cuda.synchronize()
     msi = e0.elapsed_time(e1)
     out["irreducible"] = {"nirr": len(reps), "ms": msi, "speedup": ms / msi,
-                          "equal_to_full_at_the_points": bool(all(torch.equal(Wi[i], W[q])
-                                                                  for i, q in enumerate(reps)))}
+                          "max_abs_dW_vs_full_at_the_points": max((Wi[i] - W[q]).abs().max().item()
+                                                                  for i, q in enumerate(reps)),
+                          "max_abs_W": W.abs().max().item()}
     return out
 
 

@@ -1281,8 +1281,12 @@ struct ScrPlan {
   std::vector<std::vector<PdJob>> jobs; // per chunk, dispatch order
   std::vector<std::vector<int4>> pk;    // per chunk: (k, k + q, q, -) per (q_local, k)
   std::vector<std::vector<int4>> tiles; // per chunk: (slot, row tile, column tile, q_local)
-  size_t o_gpack = 0, o_ng = 0, o_vq = 0, o_args = 0, o_ut = 0, o_Y = 0, o_qof = 0, total = 0;
-  std::vector<size_t> o_jobs, o_pk, o_tiles;
+  // the empty x occupied rows gathered from the partner q's occupied x empty rows:
+  // per chunk (destination row base, source row base, q, -), rows of Y
+  bool gather = false;
+  std::vector<std::vector<int4>> fill;
+  size_t o_gpack = 0, o_ng = 0, o_vq = 0, o_args = 0, o_ut = 0, o_Y = 0, o_qof = 0, o_trmap = 0, total = 0;
+  std::vector<size_t> o_jobs, o_pk, o_tiles, o_fill;
   size_t tables = 0;
   int maxq = 0;                         // q per chunk, largest
 };
@@ -1317,17 +1321,47 @@ int make_screening_plan(const bse_system* s, ScrPlan& S) {
   }
   const int nq = (int)S.qof.size();
   const int per_chunk = (int)std::max<size_t>(1, std::min<size_t>(nq, g_chunk_budget.load() / std::max<size_t>(bytes_q, 1)));
-  const int nchunk = (nq + per_chunk - 1) / per_chunk;
-  S.maxq = per_chunk;
+  // every q of the mesh with spheres closed under G -> t - G: n_{ck, v k+q}(G) =
+  // conj(n_{v k+q, c k}(t - G)) (-q = qbar + t), the occupied x empty density of
+  // the pair (k + q, k), whose transfer is qbar; so q and qbar share a chunk and
+  // only occupied x empty pairs are transformed
+  S.gather = P.nirr == 0 && P.tr_closed;
+  std::vector<std::vector<int>> chunk_slots(1);
+  {
+    std::vector<int> slot_of(nk, -1);
+    for (int i = 0; i < nq; ++i) slot_of[S.qof[i]] = i;
+    std::vector<char> placed(nq, 0);
+    for (int i = 0; i < nq; ++i) {
+      if (placed[i]) continue;
+      std::vector<int> unit{i};
+      placed[i] = 1;
+      if (S.gather) {
+        const int j = slot_of[P.qbar[S.qof[i]]];
+        if (j != i) {
+          unit.push_back(j);
+          placed[j] = 1;
+        }
+      }
+      if (!chunk_slots.back().empty() && (int)(chunk_slots.back().size() + unit.size()) > per_chunk)
+        chunk_slots.emplace_back();
+      chunk_slots.back().insert(chunk_slots.back().end(), unit.begin(), unit.end());
+    }
+  }
+  const int nchunk = (int)chunk_slots.size();
+  S.maxq = 0;
+  for (const auto& cs : chunk_slots) S.maxq = std::max(S.maxq, (int)cs.size());
   S.qs.assign(nchunk, {});
   S.jobs.assign(nchunk, {});
   S.pk.assign(nchunk, {});
   S.tiles.assign(nchunk, {});
+  S.fill.assign(nchunk, {});
   const int* n = s->kmesh;
   const int T2 = (P.ng_max + 63) / 64;
   for (int c = 0; c < nchunk; ++c) {
     std::vector<PdJob> jobs;
-    for (int slot = c * per_chunk; slot < std::min(nq, (c + 1) * per_chunk); ++slot) {
+    std::vector<int> ql_of(nk, -1);  // position of each q in the chunk
+    for (size_t i = 0; i < chunk_slots[c].size(); ++i) ql_of[S.qof[chunk_slots[c][i]]] = (int)i;
+    for (int slot : chunk_slots[c]) {
       const int q = S.qof[slot];
       const int ql = (int)S.qs[c].size();
       S.qs[c].push_back(q);
@@ -1339,9 +1373,13 @@ int make_screening_plan(const bse_system* s, ScrPlan& S) {
         fold(s->kmesh, k, kq, iq, m0);
         const int m0p = pack_m(m0[P.ax[0]], m0[P.ax[1]], m0[P.ax[2]]);
         const int row0 = (ql * nk + k) * 2 * nv * nc;
-        // occupied at k x empty at k + q, then empty at k x occupied at k + q
+        // occupied at k x empty at k + q, then empty at k x occupied at k + q (or
+        // gathered: the first rows of the pair (k + q, k) of qbar)
         jobs.push_back(PdJob{k, kq, m0p, iq, 0, nv, nv | (nc << 8), row0});
-        jobs.push_back(PdJob{k, kq, m0p, iq, nv, 0, nc | (nv << 8), row0 + nv * nc});
+        if (S.gather)
+          S.fill[c].push_back(make_int4(row0 + nv * nc, (ql_of[P.qbar[q]] * nk + kq) * 2 * nv * nc, q, 0));
+        else
+          jobs.push_back(PdJob{k, kq, m0p, iq, nv, 0, nc | (nv << 8), row0 + nv * nc});
         S.pk[c].push_back(make_int4(k, kq, q, 0));
       }
       for (int i = 0; i < T2; ++i)
@@ -1360,17 +1398,20 @@ int make_screening_plan(const bse_system* s, ScrPlan& S) {
   S.o_ng = put(P.ng.size() * sizeof(int));
   S.o_args = put(sizeof(PdArgs));
   S.o_qof = put(S.qof.size() * sizeof(int));
+  S.o_trmap = put(S.gather ? P.trmap.size() * sizeof(int) : 0);
   S.o_jobs.resize(nchunk);
   S.o_pk.resize(nchunk);
   S.o_tiles.resize(nchunk);
+  S.o_fill.resize(nchunk);
   for (int c = 0; c < nchunk; ++c) {
     S.o_jobs[c] = put(S.jobs[c].size() * sizeof(PdJob));
     S.o_pk[c] = put(S.pk[c].size() * sizeof(int4));
     S.o_tiles[c] = put(S.tiles[c].size() * sizeof(int4));
+    S.o_fill[c] = put(S.fill[c].size() * sizeof(int4));
   }
   S.tables = o;
   if (P.rot) S.o_ut = put((size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * sizeof(double2));
-  S.o_Y = put((size_t)per_chunk * bytes_q);
+  S.o_Y = put((size_t)S.maxq * bytes_q);
   S.total = o;
   return BSE_OK;
 }
@@ -2043,10 +2084,12 @@ int bse_screening(const bse_system* sys, const double* vq, double head, double* 
   std::memcpy(buf + S.o_ng, P.ng.data(), P.ng.size() * sizeof(int));
   std::memcpy(buf + S.o_args, &a, sizeof(PdArgs));
   std::memcpy(buf + S.o_qof, S.qof.data(), S.qof.size() * sizeof(int));
+  if (S.gather) std::memcpy(buf + S.o_trmap, P.trmap.data(), P.trmap.size() * sizeof(int));
   for (size_t c = 0; c < S.qs.size(); ++c) {
     std::memcpy(buf + S.o_jobs[c], S.jobs[c].data(), S.jobs[c].size() * sizeof(PdJob));
     std::memcpy(buf + S.o_pk[c], S.pk[c].data(), S.pk[c].size() * sizeof(int4));
     std::memcpy(buf + S.o_tiles[c], S.tiles[c].data(), S.tiles[c].size() * sizeof(int4));
+    if (!S.fill[c].empty()) std::memcpy(buf + S.o_fill[c], S.fill[c].data(), S.fill[c].size() * sizeof(int4));
   }
   HIP_TRY(hipMemcpyAsync(w, buf, S.tables, hipMemcpyHostToDevice, st));
   if ((rc = staging_release(st))) return rc;
@@ -2075,6 +2118,9 @@ int bse_screening(const bse_system* sys, const double* vq, double head, double* 
     b.persist = 0;
     b.cnt = nullptr;
     HIP_TRY(launch_pair_density(b, P.N2, P.N3, P.ng_max, lds, b.njobs, false, 0, st));
+    if (S.gather)
+      HIP_TRY(launch_rpa_fill(r.Y, reinterpret_cast<const int4*>(w + S.o_fill[c]), (int)S.fill[c].size(),
+                              reinterpret_cast<const int*>(w + S.o_trmap), r.ng, P.nv, P.nc, P.ng_max, st));
     r.pk = reinterpret_cast<const int4*>(w + S.o_pk[c]);
     HIP_TRY(launch_rpa_scale(r, (int)S.pk[c].size(), st));
     HIP_TRY(launch_rpa_herk(r, reinterpret_cast<const int4*>(w + S.o_tiles[c]), (int)S.tiles[c].size(), st));

@@ -254,6 +254,10 @@ struct RpaArgs {
 };
 hipError_t launch_rpa_scale(const RpaArgs& a, int npairs, hipStream_t st);
 hipError_t launch_rpa_init(double2* M, const int* ng, const int* qof, int nslot, int ng_max, hipStream_t st);
+// items (destination row base, source row base, q, -): rows (c, v) of the
+// destination = conj of rows (v, c) of the source at the sphere map t - G of q
+hipError_t launch_rpa_fill(double2* Y, const int4* items, int nitems, const int* trmap, const int* ng, int nv, int nc,
+                          int ng_max, hipStream_t st);
 // tiles (slot, row tile, column tile, q_local) of 64 x 64 over ng_max x ng_max
 hipError_t launch_rpa_herk(const RpaArgs& a, const int4* tiles, int ntiles, hipStream_t st);
 hipError_t launch_rpa_invert(double2* M, const int* ng, const int* qof, int nslot, int ng_max, hipStream_t st);

@@ -15,6 +15,10 @@
 //   k_rpa_w       W = v^1/2 eps^-1 v^1/2, the q = 0 head set, wings zero
 // The output holds one matrix per slot, slot i for q = qof[i] (every q, or
 // only the irreducible q points of Sec. III.A).
+//   k_rpa_fill    the empty x occupied rows of (k, k+q) from the occupied x
+//                 empty rows of (k+q, k), whose transfer is qbar = -q - t:
+//                 n_{ck, v k+q}(G) = conj(n_{v k+q, c k}(t - G)) (conjugating
+//                 the integrand exchanges the states and reverses the transfer)
 #include "bse_internal.h"
 #include "gemm_tiles.h"
 #include "kernels.h"
@@ -46,6 +50,30 @@ __global__ __launch_bounds__(256) void k_rpa_scale(RpaArgs a) {
     if (g < ngq && !(q == 0 && g == 0)) s = sqrt(2.0 / (a.omega * dh) * a.vq[(size_t)q * ngm + g]);
     const double2 x = Y[e];
     Y[e] = make_double2(x.x * s, x.y * s);
+  }
+}
+
+// One workgroup per item (destination row base, source row base, q): the nc nv
+// rows (c, v) from the source's nv nc rows (v, c), raw densities (before
+// k_rpa_scale); entries past ng(q) are zero.
+__global__ __launch_bounds__(256) void k_rpa_fill(double2* __restrict__ Y, const int4* __restrict__ items,
+                                                  const int* __restrict__ trmap, const int* __restrict__ ng, int nv,
+                                                  int nc, int ng_max) {
+  const int4 it = items[blockIdx.x];
+  const int q = it.z, ngq = ng[q];
+  const int* map = trmap + (size_t)q * ng_max;
+  double2* dst = Y + (size_t)it.x * ng_max;
+  const double2* src = Y + (size_t)it.y * ng_max;
+  const int total = nv * nc * ng_max;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int r = e / ng_max, g = e - r * ng_max;  // r = c nv + v
+    const int c = r / nv, v = r - c * nv;
+    double2 x = make_double2(0.0, 0.0);
+    if (g < ngq) {
+      x = src[(size_t)(v * nc + c) * ng_max + map[g]];
+      x.y = -x.y;
+    }
+    dst[(size_t)r * ng_max + g] = x;
   }
 }
 
@@ -151,6 +179,13 @@ __global__ void k_rpa_w(double2* __restrict__ M, const int* __restrict__ ng, con
 hipError_t launch_rpa_scale(const RpaArgs& a, int npairs, hipStream_t st) {
   if (npairs <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_rpa_scale, dim3(npairs), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_rpa_fill(double2* Y, const int4* items, int nitems, const int* trmap, const int* ng, int nv, int nc,
+                          int ng_max, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rpa_fill, dim3(nitems), dim3(256), 0, st, Y, items, trmap, ng, nv, nc, ng_max);
   return hipGetLastError();
 }
 

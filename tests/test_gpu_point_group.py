@@ -138,14 +138,16 @@ def test_screening_at_the_irreducible_points():
     Wf = P.bse_screening(P.DeviceSystem(s), vq, s.head)
     torch.cuda.synchronize()
     assert Wi.shape[0] == len(reps) < s.nk
-    same = all(torch.equal(Wi[i], Wf[q]) for i, q in enumerate(reps))
+    # the full screening gathers its empty x occupied densities from the partner
+    # q's transforms, the irreducible one transforms both orders: equal to rounding
+    dfull = max((Wi[i] - Wf[q]).abs().max().item() for i, q in enumerate(reps))
     ref = O.screened_interaction(s, vq, s.head)
     err = max(np.abs(Wi[i].cpu().numpy() - ref[q]).max() for i, q in enumerate(reps))
     scale = np.abs(ref).max()
     _say(f"irreducible screening: {len(reps)} of {s.nk} q; max|dW| {err:.3e} (max|W| {scale:.3e}); "
-         f"equal to the full screening there: {same}")
+         f"max|dW| against the full screening there {dfull:.3e}")
     assert err <= 1e-11 * scale
-    assert same
+    assert dfull <= 1e-12 * scale
     # the BSE of the first 2 empty bands on those matrices
     nb = s.nv + 2
     cut = dict(nc=2, u=np.ascontiguousarray(s.u[:, :nb]), eps=np.ascontiguousarray(s.eps[:, :nb]))
