@@ -1382,8 +1382,8 @@ int make_screening_plan(const bse_system* s, ScrPlan& S) {
           jobs.push_back(PdJob{k, kq, m0p, iq, nv, 0, nc | (nv << 8), row0 + nv * nc});
         S.pk[c].push_back(make_int4(k, kq, q, 0));
       }
-      for (int i = 0; i < T2; ++i)
-        for (int j = 0; j < T2; ++j) S.tiles[c].push_back(make_int4(slot, i, j, ql));
+      for (int i = 0; i < T2; ++i)  // eps is Hermitian: the tiles on and above the diagonal
+        for (int j = i; j < T2; ++j) S.tiles[c].push_back(make_int4(slot, i, j, ql));
     }
     S.jobs[c] = dispatch_order(std::move(jobs), Tune{}.ktile);
   }
@@ -2125,6 +2125,7 @@ int bse_screening(const bse_system* sys, const double* vq, double head, double* 
     HIP_TRY(launch_rpa_scale(r, (int)S.pk[c].size(), st));
     HIP_TRY(launch_rpa_herk(r, reinterpret_cast<const int4*>(w + S.o_tiles[c]), (int)S.tiles[c].size(), st));
   }
+  HIP_TRY(launch_rpa_mirror(r.M, r.ng, r.qof, nslot, P.ng_max, st));
   HIP_TRY(launch_rpa_invert(r.M, r.ng, r.qof, nslot, P.ng_max, st));
   HIP_TRY(launch_rpa_w(r.M, r.ng, r.qof, vq, nslot, P.ng_max, head, st));
   return BSE_OK;

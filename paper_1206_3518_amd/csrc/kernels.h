@@ -260,6 +260,8 @@ hipError_t launch_rpa_fill(double2* Y, const int4* items, int nitems, const int*
                           int ng_max, hipStream_t st);
 // tiles (slot, row tile, column tile, q_local) of 64 x 64 over ng_max x ng_max
 hipError_t launch_rpa_herk(const RpaArgs& a, const int4* tiles, int ntiles, hipStream_t st);
+// the 64 x 64 tiles below the diagonal of each eps(q) from those above (conjugate transpose)
+hipError_t launch_rpa_mirror(double2* M, const int* ng, const int* qof, int nslot, int ng_max, hipStream_t st);
 hipError_t launch_rpa_invert(double2* M, const int* ng, const int* qof, int nslot, int ng_max, hipStream_t st);
 hipError_t launch_rpa_w(double2* M, const int* ng, const int* qof, const double* vq, int nslot, int ng_max,
                         double head, hipStream_t st);

@@ -9,7 +9,9 @@
 // (k, k+q), occupied x empty and empty x occupied band blocks).
 //   k_rpa_scale   Y rows from the pair densities, in place
 //   k_rpa_init    eps(q) = identity on the sphere (zero padding)
-//   k_rpa_herk    eps(q) += conj(Y^H Y) over the chunk's rows of q (FP64 MFMA)
+//   k_rpa_herk    eps(q) += conj(Y^H Y) over the chunk's rows of q (FP64 MFMA),
+//                 64 x 64 tiles on and above the diagonal
+//   k_rpa_mirror  the tiles below the diagonal as the conjugate transpose
 //   k_rpa_invert  eps(q)^-1 in place by Gauss-Jordan elimination (Hermitian
 //                 positive definite: no pivoting)
 //   k_rpa_w       W = v^1/2 eps^-1 v^1/2, the q = 0 head set, wings zero
@@ -90,7 +92,9 @@ __global__ void k_rpa_init(double2* __restrict__ M, const int* __restrict__ ng, 
 
 // Tile (slot, i, j) of 64 x 64: M_q[G][G'] += conj(sum_r conj(Y_r(G)) Y_r(G'))
 // over the rows of q = qof[slot] in the chunk (A transposed: A[G][r] = Y[r][G]).
-__global__ __launch_bounds__(256) void k_rpa_herk(RpaArgs a, const int4* __restrict__ tiles) {
+// Three waves per SIMD: the upper tiles of every q of a chunk then run in one
+// round of workgroups (each sums over all rows of its q, so rounds dominate).
+__global__ __launch_bounds__(256, 3) void k_rpa_herk(RpaArgs a, const int4* __restrict__ tiles) {
   const int4 tl = tiles[blockIdx.x];  // (slot, row tile, column tile, q_local)
   const int slot = tl.x, q = a.qof[slot], ql = tl.w;
   const int ngm = a.ng_max, ngq = a.ng[q];
@@ -116,6 +120,21 @@ __global__ __launch_bounds__(256) void k_rpa_herk(RpaArgs a, const int4* __restr
           M[(size_t)row * ngm + col] = m;
         }
       }
+}
+
+// Entries in 64 x 64 tiles below the diagonal: M[h][g] = conj(M[g][h]).
+__global__ void k_rpa_mirror(double2* __restrict__ M, const int* __restrict__ ng, const int* __restrict__ qof,
+                             int nslot, int ng_max) {
+  const size_t per = (size_t)ng_max * ng_max;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < per * nslot;
+       id += (size_t)gridDim.x * blockDim.x) {
+    const size_t slot = id / per;
+    const int h = (int)((id % per) / ng_max), g = (int)(id % ng_max);
+    const int n = ng[qof[slot]];
+    if (h >= n || g >= n || (h >> 6) <= (g >> 6)) continue;
+    const double2 v = M[slot * per + (size_t)g * ng_max + h];
+    M[id] = make_double2(v.x, -v.y);
+  }
 }
 
 // In-place inverse of the Hermitian positive definite M_q (n = ng(q), leading
@@ -197,6 +216,11 @@ hipError_t launch_rpa_init(double2* M, const int* ng, const int* qof, int nslot,
 hipError_t launch_rpa_herk(const RpaArgs& a, const int4* tiles, int ntiles, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_rpa_herk, dim3(ntiles), dim3(256), 0, st, a, tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_rpa_mirror(double2* M, const int* ng, const int* qof, int nslot, int ng_max, hipStream_t st) {
+  hipLaunchKernelGGL(k_rpa_mirror, dim3(8192), dim3(256), 0, st, M, ng, qof, nslot, ng_max);
   return hipGetLastError();
 }
 
