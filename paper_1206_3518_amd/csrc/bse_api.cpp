@@ -1285,6 +1285,13 @@ struct ScrPlan {
   // per chunk (destination row base, source row base, q, -), rows of Y
   bool gather = false;
   std::vector<std::vector<int4>> fill;
+  // HERK slices per chunk (a chunk of few q splits its row sums to fill the
+  // GPU) and the slot of each q_local
+  std::vector<int> nsplit;
+  std::vector<std::vector<int>> cslot;
+  size_t o_part = 0;
+  std::vector<size_t> o_cslot;
+  int max_part_q = 0, max_split = 1;
   size_t o_gpack = 0, o_ng = 0, o_vq = 0, o_args = 0, o_ut = 0, o_Y = 0, o_qof = 0, o_trmap = 0, total = 0;
   std::vector<size_t> o_jobs, o_pk, o_tiles, o_fill;
   size_t tables = 0;
@@ -1387,6 +1394,34 @@ int make_screening_plan(const bse_system* s, ScrPlan& S) {
     }
     S.jobs[c] = dispatch_order(std::move(jobs), Tune{}.ktile);
   }
+  // the HERK runs three workgroups per CU; a call with fewer tiles than about
+  // two rounds of that splits every row sum into slices (at most 8).  The
+  // count follows the whole call, not its chunks, so that W does not depend
+  // on the chunk budget.
+  constexpr int kHerkSlots = 3 * 256;
+  size_t nt_all = 0;
+  for (int c = 0; c < nchunk; ++c) nt_all += S.tiles[c].size();
+  const int ns = nt_all >= 2 * kHerkSlots / 3
+                     ? 1
+                     : (int)std::min<size_t>(8, (kHerkSlots + nt_all - 1) / std::max<size_t>(nt_all, 1));
+  S.nsplit.assign(nchunk, 1);
+  S.cslot.assign(nchunk, {});
+  S.max_part_q = 0;
+  S.max_split = 1;
+  for (int c = 0; c < nchunk; ++c) {
+    S.cslot[c] = chunk_slots[c];
+    const int nt = (int)S.tiles[c].size();
+    S.nsplit[c] = ns;
+    if (ns > 1) {
+      std::vector<int4> t;
+      t.reserve((size_t)nt * ns);
+      for (int sl = 0; sl < ns; ++sl)
+        for (const int4& x : S.tiles[c]) t.push_back(make_int4(x.x, x.y | (sl << 8), x.z, x.w));
+      S.tiles[c].swap(t);
+      S.max_split = std::max(S.max_split, ns);
+      S.max_part_q = std::max(S.max_part_q, (int)chunk_slots[c].size());
+    }
+  }
   // workspace: tables, the rotated wave functions, the pair densities of a chunk
   size_t o = 0;
   auto put = [&](size_t bytes) {
@@ -1403,15 +1438,18 @@ int make_screening_plan(const bse_system* s, ScrPlan& S) {
   S.o_pk.resize(nchunk);
   S.o_tiles.resize(nchunk);
   S.o_fill.resize(nchunk);
+  S.o_cslot.resize(nchunk);
   for (int c = 0; c < nchunk; ++c) {
     S.o_jobs[c] = put(S.jobs[c].size() * sizeof(PdJob));
     S.o_pk[c] = put(S.pk[c].size() * sizeof(int4));
     S.o_tiles[c] = put(S.tiles[c].size() * sizeof(int4));
     S.o_fill[c] = put(S.fill[c].size() * sizeof(int4));
+    S.o_cslot[c] = put(S.cslot[c].size() * sizeof(int));
   }
   S.tables = o;
   if (P.rot) S.o_ut = put((size_t)P.nk * P.nb * P.N1 * P.N2 * P.N3 * sizeof(double2));
   S.o_Y = put((size_t)S.maxq * bytes_q);
+  S.o_part = put(S.max_split > 1 ? (size_t)S.max_split * S.max_part_q * P.ng_max * P.ng_max * sizeof(double2) : 0);
   S.total = o;
   return BSE_OK;
 }
@@ -2090,6 +2128,7 @@ int bse_screening(const bse_system* sys, const double* vq, double head, double* 
     std::memcpy(buf + S.o_pk[c], S.pk[c].data(), S.pk[c].size() * sizeof(int4));
     std::memcpy(buf + S.o_tiles[c], S.tiles[c].data(), S.tiles[c].size() * sizeof(int4));
     if (!S.fill[c].empty()) std::memcpy(buf + S.o_fill[c], S.fill[c].data(), S.fill[c].size() * sizeof(int4));
+    std::memcpy(buf + S.o_cslot[c], S.cslot[c].data(), S.cslot[c].size() * sizeof(int));
   }
   HIP_TRY(hipMemcpyAsync(w, buf, S.tables, hipMemcpyHostToDevice, st));
   if ((rc = staging_release(st))) return rc;
@@ -2123,7 +2162,11 @@ int bse_screening(const bse_system* sys, const double* vq, double head, double* 
                               reinterpret_cast<const int*>(w + S.o_trmap), r.ng, P.nv, P.nc, P.ng_max, st));
     r.pk = reinterpret_cast<const int4*>(w + S.o_pk[c]);
     HIP_TRY(launch_rpa_scale(r, (int)S.pk[c].size(), st));
+    r.nsplit = S.nsplit[c];
+    r.part = reinterpret_cast<double2*>(w + S.o_part);
+    r.part_q = S.max_part_q;
     HIP_TRY(launch_rpa_herk(r, reinterpret_cast<const int4*>(w + S.o_tiles[c]), (int)S.tiles[c].size(), st));
+    HIP_TRY(launch_rpa_reduce(r, reinterpret_cast<const int*>(w + S.o_cslot[c]), (int)S.cslot[c].size(), st));
   }
   HIP_TRY(launch_rpa_mirror(r.M, r.ng, r.qof, nslot, P.ng_max, st));
   HIP_TRY(launch_rpa_invert(r.M, r.ng, r.qof, nslot, P.ng_max, st));

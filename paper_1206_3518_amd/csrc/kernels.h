@@ -247,6 +247,9 @@ struct RpaArgs {
   const int4* pk;
   const int* ng;
   const int* qof;       // [nslot] q of each output slot
+  int nsplit;           // slices of the row sum per HERK tile (1: accumulate into M)
+  double2* part;        // nsplit > 1: partial sums [nsplit][part_q][ng_max][ng_max]
+  int part_q;           // q_local stride of part
   const double* eps;
   const double* vq;
   int nv, nc, nk, ng_max;
@@ -258,8 +261,10 @@ hipError_t launch_rpa_init(double2* M, const int* ng, const int* qof, int nslot,
 // destination = conj of rows (v, c) of the source at the sphere map t - G of q
 hipError_t launch_rpa_fill(double2* Y, const int4* items, int nitems, const int* trmap, const int* ng, int nv, int nc,
                           int ng_max, hipStream_t st);
-// tiles (slot, row tile, column tile, q_local) of 64 x 64 over ng_max x ng_max
+// tiles (slot, row tile | slice << 8, column tile, q_local) of 64 x 64 over ng_max x ng_max
 hipError_t launch_rpa_herk(const RpaArgs& a, const int4* tiles, int ntiles, hipStream_t st);
+// with a.nsplit > 1: eps of the chunk's q (cslot: slot of each q_local) += the partial sums
+hipError_t launch_rpa_reduce(const RpaArgs& a, const int* cslot, int nql, hipStream_t st);
 // the 64 x 64 tiles below the diagonal of each eps(q) from those above (conjugate transpose)
 hipError_t launch_rpa_mirror(double2* M, const int* ng, const int* qof, int nslot, int ng_max, hipStream_t st);
 hipError_t launch_rpa_invert(double2* M, const int* ng, const int* qof, int nslot, int ng_max, hipStream_t st);

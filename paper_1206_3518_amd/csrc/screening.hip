@@ -94,16 +94,22 @@ __global__ void k_rpa_init(double2* __restrict__ M, const int* __restrict__ ng, 
 // over the rows of q = qof[slot] in the chunk (A transposed: A[G][r] = Y[r][G]).
 // Three waves per SIMD: the upper tiles of every q of a chunk then run in one
 // round of workgroups (each sums over all rows of its q, so rounds dominate).
+// A chunk of few q splits the row sum into nsplit slices (a tile per slice):
+// slice s writes its partial sum to part[s][q_local], and k_rpa_reduce adds
+// the slices to eps in slice order.
 __global__ __launch_bounds__(256, 3) void k_rpa_herk(RpaArgs a, const int4* __restrict__ tiles) {
-  const int4 tl = tiles[blockIdx.x];  // (slot, row tile, column tile, q_local)
-  const int slot = tl.x, q = a.qof[slot], ql = tl.w;
+  const int4 tl = tiles[blockIdx.x];  // (slot, row tile | slice << 8, column tile, q_local)
+  const int slot = tl.x, q = a.qof[slot], ql = tl.w, sl = tl.y >> 8;
   const int ngm = a.ng_max, ngq = a.ng[q];
   const int rows = a.nk * 2 * a.nv * a.nc;
-  const double2* Yq = a.Y + (size_t)ql * rows * ngm;
-  const int r0 = tl.y * 64, c0 = tl.z * 64;
+  const int rs = (rows + 16 * a.nsplit - 1) / (16 * a.nsplit) * 16;  // rows per slice
+  const int rb = min(rows, sl * rs), re = min(rows, rb + rs);
+  const double2* Yq = a.Y + ((size_t)ql * rows + rb) * ngm;
+  const int r0 = (tl.y & 255) * 64, c0 = tl.z * 64;
   d4 cre[2][2], cim[2][2];
-  tile_gemm<true, false, true>(Yq, ngm, r0, ngq, Yq, ngm, c0, ngq, rows, cre, cim);
-  double2* M = a.M + (size_t)slot * ngm * ngm;
+  tile_gemm<true, false, true>(Yq, ngm, r0, ngq, Yq, ngm, c0, ngq, re - rb, cre, cim);
+  const bool split = a.nsplit > 1;
+  double2* M = split ? a.part + ((size_t)sl * a.part_q + ql) * ngm * ngm : a.M + (size_t)slot * ngm * ngm;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -114,12 +120,39 @@ __global__ __launch_bounds__(256, 3) void k_rpa_herk(RpaArgs a, const int4* __re
         const int row = r0 + wr * 32 + i * 16 + 4 * r + (lane >> 4);
         const int col = c0 + wc * 32 + j * 16 + (lane & 15);
         if (row < ngq && col < ngq) {
-          double2 m = M[(size_t)row * ngm + col];
+          double2 m = split ? make_double2(0.0, 0.0) : M[(size_t)row * ngm + col];
           m.x += cre[i][j][r];
           m.y -= cim[i][j][r];
           M[(size_t)row * ngm + col] = m;
         }
       }
+}
+
+// eps of the chunk's q (cslot: slot of each q_local) += the nsplit partial
+// sums, slice after slice, on the tiles on and above the diagonal.
+__global__ void k_rpa_reduce(RpaArgs a, const int* __restrict__ cslot, int nql) {
+  const int ngm = a.ng_max;
+  const size_t per = (size_t)ngm * ngm;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < per * nql;
+       id += (size_t)gridDim.x * blockDim.x) {
+    const int ql = (int)(id / per);
+    const int g = (int)((id % per) / ngm), h = (int)(id % ngm);
+    const int slot = cslot[ql], n = a.ng[a.qof[slot]];
+    if (g >= n || h >= n || (g >> 6) > (h >> 6)) continue;
+    double2 m = a.M[(size_t)slot * per + (size_t)g * ngm + h];
+    for (int sl = 0; sl < a.nsplit; ++sl) {
+      const double2 v = a.part[((size_t)sl * a.part_q + ql) * per + (size_t)g * ngm + h];
+      m.x += v.x;
+      m.y += v.y;
+    }
+    a.M[(size_t)slot * per + (size_t)g * ngm + h] = m;
+  }
+}
+
+hipError_t launch_rpa_reduce(const RpaArgs& a, const int* cslot, int nql, hipStream_t st) {
+  if (nql <= 0 || a.nsplit <= 1) return hipSuccess;
+  hipLaunchKernelGGL(k_rpa_reduce, dim3(4096), dim3(256), 0, st, a, cslot, nql);
+  return hipGetLastError();
 }
 
 // Entries in 64 x 64 tiles below the diagonal: M[h][g] = conj(M[g][h]).

@@ -148,6 +148,15 @@ def test_screening_at_the_irreducible_points():
          f"max|dW| against the full screening there {dfull:.3e}")
     assert err <= 1e-11 * scale
     assert dfull <= 1e-12 * scale
+    # few q: the row sums are split into slices and reduced in order, the same
+    # in any chunking
+    try:
+        P.bse_set_chunk_budget(1 << 20)
+        Wc = P.bse_screening(d, vq, s.head)
+        torch.cuda.synchronize()
+    finally:
+        P.bse_set_chunk_budget(0)
+    assert torch.equal(Wc, Wi)
     # the BSE of the first 2 empty bands on those matrices
     nb = s.nv + 2
     cut = dict(nc=2, u=np.ascontiguousarray(s.u[:, :nb]), eps=np.ascontiguousarray(s.eps[:, :nb]))
