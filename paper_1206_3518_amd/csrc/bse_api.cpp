@@ -522,13 +522,20 @@ int plan_pairs(const bse_system* s, Plan& P, const BatchOpts& opt, int nchunk, i
       fold(s->kmesh, ka, kb, iq, m0);
       pr[i] = make_int4(ka, kb, iq, members[i]);  // .w: lexicographic index for now
     }
-    std::sort(pr.begin(), pr.end(), [](const int4& x, const int4& y) {
+    // coupling with gathered rows: B is symmetric (B^T = B for Hermitian,
+    // time-reversal-consistent W and even v, as the lower half of H2 assumes),
+    // so only the pairs k <= k' are contracted; the reversed pairs, whose
+    // densities are gather sources only, come after them
+    const bool csym = P.cswap;
+    std::sort(pr.begin(), pr.end(), [csym](const int4& x, const int4& y) {
+      if (csym && (x.x > x.y) != (y.x > y.y)) return y.x > y.y;
       if (x.z != y.z) return x.z < y.z;
       if (x.x != y.x) return x.x < y.x;
       return x.y < y.y;
     });
     K.p0 = next;
     K.np = (int)pr.size();
+    int ncontract = 0;  // pairs of the chunk whose blocks are contracted (the first ones)
     P.maxcp = std::max(P.maxcp, K.np);
     if ((long long)K.np * std::max(P.rv_rows, P.rc_rows) >= (1LL << 31) / std::max(P.ng_max, 1))
       return fail(BSE_ERR_SHAPE, "a chunk of %d k pairs is too large", K.np);
@@ -540,7 +547,10 @@ int plan_pairs(const bse_system* s, Plan& P, const BatchOpts& opt, int nchunk, i
       P.pairs[g] = make_int4(pr[i].x, pr[i].y, iq, pack_m(m0[P.ax[0]], m0[P.ax[1]], m0[P.ax[2]]));
       P.plex[g] = l;
       g_of_lex[l] = g;
-      cnt[iq]++;
+      if (!(csym && pr[i].x > pr[i].y)) {
+        cnt[iq]++;
+        ++ncontract;
+      }
     }
     int* qs = P.qs.data() + (size_t)c * (nk + 1);
     qs[0] = next;
@@ -556,9 +566,8 @@ int plan_pairs(const bse_system* s, Plan& P, const BatchOpts& opt, int nchunk, i
         if (u->img >= 0) {
           const int4 r4 = P.pairs[gi];
           K.jv.push_back(PdJob{r4.x, r4.y, r4.w, r4.z, 0, nv, nv | (nc << 8), li * nv * nc});
-          K.fill.push_back(make_int4(li, loc, r4.z << 1, sys));
         }
-        K.fill.push_back(make_int4(loc, li, q4.z << 1, sys));
+        K.fill.push_back(make_int4(loc, li, q4.z << 1, sys));  // (the reversed pair's block is mirrored)
         continue;
       }
       if (P.coupling) {  // n_{vk, c'k'} and n_{ck, v'k'}
@@ -596,7 +605,7 @@ int plan_pairs(const bse_system* s, Plan& P, const BatchOpts& opt, int nchunk, i
           for (int j = 0; j < T2; ++j) K.rvt.push_back(make_int4(q, i, j, 0));
       }
     }
-    K.d2items = K.np * ((P.rv_rows + 15) / 16) * ((P.rc_rows + 15) / 16);
+    K.d2items = ncontract * ((P.rv_rows + 15) / 16) * ((P.rc_rows + 15) / 16);
     next += K.np;
   }
   // exchange tiles: every 64 x 64 tile that holds an entry of a block k <= k'
@@ -608,12 +617,13 @@ int plan_pairs(const bse_system* s, Plan& P, const BatchOpts& opt, int nchunk, i
   for (int i = 0; i < T; ++i)
     for (int j = 0; j < T; ++j) {
       const int last_col = std::min(P.ns, 64 * (j + 1)) - 1;
-      if (P.coupling || (64 * i) / P.nt <= last_col / P.nt) P.xt.push_back(HTile{i, j, sys, 0});
+      if ((P.coupling && !P.cswap) || (64 * i) / P.nt <= last_col / P.nt) P.xt.push_back(HTile{i, j, sys, 0});
     }
-  // mirror tiles: 32 x 32 destination tiles on or below the diagonal (none for the coupling block)
+  // mirror tiles: 32 x 32 destination tiles on or below the diagonal (the
+  // coupling block: a plain transpose, when only its upper blocks are contracted)
   P.mt.clear();
   const int T32 = (P.ns + 31) / 32;
-  for (int i = 0; i < T32 && !P.coupling; ++i)
+  for (int i = 0; i < T32 && (!P.coupling || P.cswap); ++i)
     for (int j = 0; j <= i; ++j) P.mt.push_back(HTile{i, j, sys, 0});
   // coupling: -G of every G of the q = 0 sphere (the h-e exchange densities)
   P.inv0.clear();
@@ -752,6 +762,7 @@ GemmArgs gemm_args(const Plan& P, const bse_system* s, char* region, int c) {
   g.rv_rows = P.rv_rows;
   g.rc_rows = P.rc_rows;
   g.coupling = P.coupling;
+  g.mirror_plain = P.coupling ? 1 : 0;
   g.Xb = P.coupling ? reinterpret_cast<const double2*>(region + P.o_Xb) : nullptr;
   return g;
 }

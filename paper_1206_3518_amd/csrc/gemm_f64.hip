@@ -2,7 +2,8 @@
 //   exchange  H[S][S'] = 2c sum_g conj(X[S][g]) X[S'][g]     (X scaled by sqrt v(G), G = 0 left out)
 //   direct 1  Z[r][n]  = sum_g conj(RV[r][g]) W_q[g][n]       (rows r: band pairs vv' of the k pairs of q)
 //   direct 2  H[(k v c),(k' v' c')] -= c sum_g Z[(kk' vv')][g] RC[(kk' cc')][g], plus e_ck - e_vk on the diagonal
-//   mirror    lower k blocks = conjugate transpose of the upper ones
+//   mirror    lower k blocks = conjugate transpose of the upper ones (plain transpose
+//             for the symmetric coupling block of the beyond-TDA matrix)
 // Complex products run as four real v_mfma_f64_16x16x4 products per step.
 // Every launch covers a batch of systems: tiles and items name their system.
 #include <algorithm>
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(256) void k_mirror(const GemmArgs* __restrict__ gs,
     const int dr = bi * 32 + r, dc = bj * 32 + tx;
     if (dr < ns && dc < ns && dr / nt > dc / nt) {
       const double2 v = tile[tx][r];
-      gst(H, (size_t)dr * ld + dc, make_double2(v.x, -v.y));
+      gst(H, (size_t)dr * ld + dc, make_double2(v.x, g.mirror_plain ? v.y : -v.y));
     }
   }
 }

@@ -113,6 +113,7 @@ struct GemmArgs {
   int coupling;         // coupling block: RV rows (v, c') = n_{vk,c'k'}, RC rows (c, v') = n_{ck,v'k'},
                         // output H[(k v c)][(k' v' c')], no transition energies
   const double2* Xb;    // exchange B operand (coupling: conj(X) at -G); null: X
+  int mirror_plain;     // mirror lower blocks as the transpose (symmetric coupling block), not its conjugate
 };
 
 // The contractions run over a batch: gs is a device array of per-system
