@@ -53,6 +53,19 @@ def test_relation_fails_without_time_reversal_of_W():
     A, Bc, C, Dm = _blocks(H, s.ns)
     K = np.abs(A - np.diag(np.diag(A))).max()
     assert np.abs(C + Bc.conj().T).max() > 1e-3 * K
+    assert np.abs(Bc - Bc.T).max() > 1e-3 * K  # nor is the coupling block symmetric
+
+
+def test_coupling_block_is_symmetric():
+    """B^T = B (not B^H) for Hermitian, time-reversal-consistent W and an even
+    v, with wave functions that carry no symmetry: the GPU contracts only the
+    blocks k <= k' of B and writes the others as their transposes."""
+    for s in (B.make_config(0), small_system(kmesh=(3, 1, 1)), small_system(kmesh=(2, 2, 1))):
+        H = O.build_H_full(s)
+        A, Bc, _, _ = _blocks(H, s.ns)
+        K = np.abs(A - np.diag(np.diag(A))).max()
+        assert np.abs(Bc - Bc.T).max() <= 1e-12 * K
+        assert np.abs(Bc - Bc.conj().T).max() > 1e-3 * np.abs(Bc).max()
 
 
 def test_zero_interaction_gives_plus_and_minus_transition_energies():
