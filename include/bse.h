@@ -175,9 +175,13 @@ typedef struct bse_system {
      * ng(q), row q of wmap is a permutation of 0..ng(q)-1 (else BSE_ERR_SHAPE), and
      * wmap[0][0] = 0 (G = 0 of q = 0 stays in place).  BSE_VALIDATE then checks the nirr
      * matrices for finiteness and Hermiticity; the time-reversal relation holds by
-     * construction of the maps and is not checked.  nirr > 0 with bse_build_H_backward ->
-     * BSE_ERR_UNSUPPORTED; nirr < 0 or > Nk, a NULL map, or a map entry out of range ->
-     * BSE_ERR_INVALID_ARG.  The maps are HOST memory, read while the call plans.          */
+     * construction of the maps and is not checked.  bse_build_H_backward then returns dW as
+     * [nirr][ng_max][ng_max], the gradient with respect to those matrices: the adjoint of the
+     * unfolding, dW_s[a][b] = sum over the q and G, G' that read entry (a, b) of matrix s of
+     * dW(q)[G][G'], conjugated for the time-reversed images (it unfolds W into its workspace,
+     * which grows by 2 Nk ng_max^2 complex values).  nirr < 0 or > Nk, a NULL map, or a map
+     * entry out of range -> BSE_ERR_INVALID_ARG.  The maps are HOST memory, read while the
+     * call plans.                                                                        */
     int nirr;
     const int *wsrc;      /* HOST [Nk][2]       (source matrix, conjugate flag) per q            */
     const int *wmap;      /* HOST [Nk][ng_max]  position of +-T^-1(G + G0) in the source sphere;
@@ -216,7 +220,8 @@ int bse_build_H(const bse_system *sys, int nsys, int precision, int flags,
  * Adjoint of bse_build_H for one system: given dL/dH (DEVICE [NS][NS] complex,
  * the PyTorch convention dL/dRe H + i dL/dIm H), returns (every output
  * DEVICE complex or real as shown, nullable, fully written when given):
- *   dW      [Nk][ng_max][ng_max]     dL/dW_GG'(q), zero past ng(q)
+ *   dW      [Nk][ng_max][ng_max]     dL/dW_GG'(q), zero past ng(q) ([nirr][ng_max][ng_max] with W given
+ *                                    at the irreducible q points: see bse_system.nirr)
  *   deps    [Nk][nb] (real)          dL/de (eV/eV)
  *   dX      [Nk][nv][nc][ng_max]     dL/dn_{vk,ck}(G) on S(0) (the pair density
  *                                    itself, not scaled by v), zero at G = 0

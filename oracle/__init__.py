@@ -600,3 +600,23 @@ def unfold_W(W_irr, wsrc, wmap, ng):
                 w = W_irr[src, wmap[q][g], wmap[q][gp]]
                 W[q, g, gp] = np.conj(w) if tr else w
     return W
+
+
+def fold_dW(dW, wsrc, wmap, ng, nirr, ng_max):
+    """Gradient of a real L with respect to the matrices at the irreducible q
+    points (the PyTorch convention dL/dRe + i dL/dIm), given its gradient
+    with respect to W(q) at every q: the adjoint of the real-linear map of
+    ``unfold_W`` (Sec. III.A).  Each entry (G, G') of W(q) reads the source
+    entry (wmap[q][G], wmap[q][G']) itself, or its complex conjugate for the
+    time-reversed images, so the source entry collects dW(q)[G][G'], or its
+    conjugate, from every q and entry that read it.  Returns
+    [nirr][ng_max][ng_max]."""
+    out = np.zeros((nirr, ng_max, ng_max), dtype=np.complex128)
+    for q in range(len(ng)):
+        src, tr = int(wsrc[q][0]), int(wsrc[q][1])
+        n = int(ng[q])
+        for g in range(n):
+            for gp in range(n):
+                v = dW[q, g, gp]
+                out[src, wmap[q][g], wmap[q][gp]] += np.conj(v) if tr else v
+    return out

@@ -372,4 +372,64 @@ hipError_t launch_adjoint_finish(const AdjArgs& a, bool project, hipStream_t st)
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ W at the irreducible q points
+
+// W(q) at every q from the matrices at the irreducible points (Sec. III.A):
+// Wf[q][g][h] = W[src][map g][map h], conjugated for time-reversed images,
+// zero past ng(q).
+__global__ void k_unfold_w(const double2* __restrict__ W, const int* __restrict__ wsrc, const int* __restrict__ wmap,
+                           const int* __restrict__ ng, int nk, int ng_max, double2* __restrict__ Wf) {
+  const size_t per = (size_t)ng_max * ng_max;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < per * nk;
+       id += (size_t)gridDim.x * blockDim.x) {
+    const int q = (int)(id / per);
+    const int g = (int)((id % per) / ng_max), h = (int)(id % ng_max);
+    double2 v = make_double2(0.0, 0.0);
+    if (g < ng[q] && h < ng[q]) {
+      const int* mq = wmap + (size_t)q * ng_max;
+      v = W[(size_t)wsrc[2 * q] * per + (size_t)mq[g] * ng_max + mq[h]];
+      if (wsrc[2 * q + 1]) v.y = -v.y;
+    }
+    Wf[id] = v;
+  }
+}
+
+// The adjoint of the unfolding: dW[s][a][b] = sum over the q that map to s (in
+// increasing q: qlist[csr[s]] .. qlist[csr[s+1]-1]) of dWf[q][inv a][inv b],
+// conjugated for time-reversed images (PyTorch convention: conj(W) has the
+// conjugate gradient); zero past the source's sphere.
+__global__ void k_fold_dw(const double2* __restrict__ dWf, const int* __restrict__ csr, const int* __restrict__ qlist,
+                          const int* __restrict__ wsrc, const int* __restrict__ winv, const int* __restrict__ ngirr,
+                          int nirr, int ng_max, double2* __restrict__ dW) {
+  const size_t per = (size_t)ng_max * ng_max;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < per * nirr;
+       id += (size_t)gridDim.x * blockDim.x) {
+    const int sidx = (int)(id / per);
+    const int a = (int)((id % per) / ng_max), b = (int)(id % ng_max);
+    double2 acc = make_double2(0.0, 0.0);
+    if (a < ngirr[sidx] && b < ngirr[sidx]) {
+      for (int t = csr[sidx]; t < csr[sidx + 1]; ++t) {
+        const int q = qlist[t];
+        const int* iq = winv + (size_t)q * ng_max;
+        const double2 v = dWf[(size_t)q * per + (size_t)iq[a] * ng_max + iq[b]];
+        acc.x += v.x;
+        acc.y += wsrc[2 * q + 1] ? -v.y : v.y;
+      }
+    }
+    dW[id] = acc;
+  }
+}
+
+hipError_t launch_unfold_w(const double2* W, const int* wsrc, const int* wmap, const int* ng, int nk, int ng_max,
+                           double2* Wf, hipStream_t st) {
+  hipLaunchKernelGGL(k_unfold_w, dim3(8192), dim3(256), 0, st, W, wsrc, wmap, ng, nk, ng_max, Wf);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_dw(const double2* dWf, const int* csr, const int* qlist, const int* wsrc, const int* winv,
+                          const int* ngirr, int nirr, int ng_max, double2* dW, hipStream_t st) {
+  hipLaunchKernelGGL(k_fold_dw, dim3(8192), dim3(256), 0, st, dWf, csr, qlist, wsrc, winv, ngirr, nirr, ng_max, dW);
+  return hipGetLastError();
+}
+
 }  // namespace bse

@@ -1714,6 +1714,149 @@ int spectrum_args(int ns, int nlam, const double* E, const double* A, const doub
   return BSE_OK;
 }
 
+// The adjoint for a system with W at every q.
+int backward_impl(const bse_system* sys, const double* dH, double* dW, double* deps, double* dX, double* drho_vv,
+                  double* drho_cc, int precision, int flags, void* ws, size_t ws_bytes, hipStream_t st) {
+  if (!dH || !ws) return fail(BSE_ERR_INVALID_ARG, "dH / ws is NULL");
+  if (precision < BSE_FP64 || precision > BSE_BF16X3) return fail(BSE_ERR_INVALID_ARG, "bad precision %d", precision);
+  if (flags & ~(BSE_PROJECT_DW | BSE_TIME_REVERSAL | BSE_FP32_PAIRDENS))
+    return fail(BSE_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+  if ((flags & BSE_FP32_PAIRDENS) && precision == BSE_FP64)
+    return fail(BSE_ERR_INVALID_ARG, "BSE_FP32_PAIRDENS needs a mixed precision (split-FP32 or BF16x3)");
+  const bool project = (flags & BSE_PROJECT_DW) != 0;
+  Batch B;
+  BatchOpts opt;
+  opt.backward = true;
+  opt.project = project && dW;
+  opt.tr = (flags & BSE_TIME_REVERSAL) != 0;
+  opt.pd32 = (flags & BSE_FP32_PAIRDENS) != 0;
+  int rc = make_batch(sys, 1, Tune{}, opt, B);
+  if (rc) return rc;
+  const Plan& P = B.P[0];
+  if (ws_bytes < B.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, B.total);
+  if (project && !P.tr_closed)
+    return fail(BSE_ERR_NOT_HERMITIAN, "G spheres are not closed under time reversal; cannot project dW");
+  char* w = static_cast<char*>(ws);
+  if ((rc = upload_batch(B, sys, BSE_FP64, w, st))) return rc;
+  char* r = w + B.base[0];
+  if ((rc = prepare_u(B, sys, w, st))) return rc;
+  AdjArgs g{};
+  g.dH = reinterpret_cast<const double2*>(dH);
+  g.RV = reinterpret_cast<const double2*>(r + P.o_RV);
+  g.RC = reinterpret_cast<const double2*>(r + P.o_RC);
+  g.T = reinterpret_cast<double2*>(r + P.o_Z);
+  g.dWfinal = reinterpret_cast<double2*>(dW);
+  g.dWout = dW ? (project ? reinterpret_cast<double2*>(r + P.o_dWraw) : reinterpret_cast<double2*>(dW)) : nullptr;
+  g.deps = deps;
+  g.pairs = reinterpret_cast<const int4*>(r + P.o_pairs);
+  g.ng = reinterpret_cast<const int*>(r + P.o_ng);
+  g.qbar = reinterpret_cast<const int*>(r + P.o_qbar);
+  g.trmap = reinterpret_cast<const int*>(r + P.o_trmap);
+  g.nk = P.nk;
+  g.nv = P.nv;
+  g.nc = P.nc;
+  g.ns = P.ns;
+  g.ng_max = P.ng_max;
+  g.cpref = 27.211386245988 / ((double)P.nk * sys->omega_cell);
+  g.Z = reinterpret_cast<const double2*>(r + P.o_Z);
+  g.W = reinterpret_cast<const double2*>(sys->W);
+  g.Xs = reinterpret_cast<const double2*>(r + P.o_X);
+  g.vs = reinterpret_cast<const double*>(r + P.o_vs);
+  g.plex = reinterpret_cast<const int*>(r + P.o_plex);
+  g.ngx = P.ng[0];
+  g.dX = reinterpret_cast<double2*>(dX);
+  g.drv = reinterpret_cast<double2*>(drho_vv);
+  g.drc = reinterpret_cast<double2*>(drho_cc);
+  // the exchange densities (only for dX) and their gradient
+  if (dX) {
+    double* vs = reinterpret_cast<double*>(r + P.o_vs);
+    HIP_TRY(launch_vscale(sys->vx, P.ng[P.qexc], P.ng_max, P.g0x, vs, st));
+    if ((rc = run_pd(B, w, 0, 0, Tune{}, st))) return rc;
+    HIP_TRY(launch_adj_dx(g, st));
+  }
+  if (g.dWout) HIP_TRY(launch_zero_f64(reinterpret_cast<double*>(g.dWout), (size_t)P.nk * P.ng_max * P.ng_max * 2, st));
+  // per chunk: recompute the pair densities, then the chunk's share of every gradient
+  for (int c = 0; c < (int)B.C.size(); ++c) {
+    const BatchChunk& K = B.C[c];
+    if ((rc = run_pd(B, w, 1, c, Tune{}, st)) || (rc = run_tr_fill(B, w, 1, c, st)) ||
+        (rc = run_tr_fill(B, w, 2, c, st)))
+      return rc;
+    g.qstart = reinterpret_cast<const int*>(r + P.o_qs) + (size_t)c * (P.nk + 1);
+    g.p0 = P.ch[c].p0;
+    g.npairs = P.ch[c].np;
+    g.dwtiles = reinterpret_cast<const int4*>(w + K.o_dwt);
+    g.rvtiles = reinterpret_cast<const int4*>(w + K.o_rvt);
+    if (drho_cc) {
+      // Z = conj(rho_vv')^T W (the forward stage 1, FP64) into the Z area
+      const GemmArgs* gs = reinterpret_cast<const GemmArgs*>(w + K.o_gargs);
+      const S1Tile* s1 = reinterpret_cast<const S1Tile*>(w + K.o_s1);
+      HIP_TRY(launch_direct_s1(gs, s1, (int)K.s1.size(), BSE_FP64, 0, B.s1_rows, st));
+      HIP_TRY(launch_adj_drc(g, st));
+    }
+    // T (over the Z area), the chunk's share of dW
+    HIP_TRY(launch_adjoint(g, precision, (int)K.dwt.size(), K.has_q0, st));
+    if (drho_vv) HIP_TRY(launch_adj_drv(g, (int)K.rvt.size(), st));
+  }
+  HIP_TRY(launch_adjoint_finish(g, project, st));
+  return BSE_OK;
+}
+
+// The backward with W at the irreducible q points runs the adjoint above on W
+// unfolded into the workspace and folds dW back onto the nirr matrices.
+// Workspace: [fold tables | unfolded W | dW at every q | the adjoint's own].
+struct IrrBackward {
+  Plan G;                       // geometry, with the validated maps
+  std::vector<int> tab;         // wsrc [2 Nk], wmap, winv [Nk][ng_max], csr [nirr + 1], qlist [Nk], ngirr, ng
+  size_t t_wsrc = 0, t_wmap = 0, t_winv = 0, t_csr = 0, t_qlist = 0, t_ngirr = 0, t_ng = 0;  // int offsets
+  size_t o_Wf = 0, o_dWf = 0, extra = 0;
+};
+
+int plan_irr_backward(const bse_system* sys, bool want_dw, IrrBackward& R) {
+  int rc = make_geometry(sys, R.G);
+  if (rc) return rc;
+  const Plan& P = R.G;
+  const int nk = P.nk, ngm = P.ng_max, nirr = P.nirr;
+  R.tab.clear();
+  auto take = [&](size_t n) {
+    const size_t at = R.tab.size();
+    R.tab.resize(at + n, 0);
+    return at;
+  };
+  R.t_wsrc = take(2 * (size_t)nk);
+  R.t_wmap = take((size_t)nk * ngm);
+  R.t_winv = take((size_t)nk * ngm);
+  R.t_csr = take((size_t)nirr + 1);
+  R.t_qlist = take(nk);
+  R.t_ngirr = take(nirr);
+  R.t_ng = take(nk);
+  std::copy(P.wsrc.begin(), P.wsrc.end(), R.tab.begin() + R.t_wsrc);
+  std::copy(P.wmap.begin(), P.wmap.end(), R.tab.begin() + R.t_wmap);
+  for (int q = 0; q < nk; ++q)
+    for (int g = 0; g < P.ng[q]; ++g) R.tab[R.t_winv + (size_t)q * ngm + P.wmap[(size_t)q * ngm + g]] = g;
+  std::vector<int> cnt(nirr, 0);
+  for (int q = 0; q < nk; ++q) cnt[P.wsrc[2 * q]]++;
+  for (int i = 0; i < nirr; ++i) R.tab[R.t_csr + i + 1] = R.tab[R.t_csr + i] + cnt[i];
+  std::vector<int> fillp(R.tab.begin() + R.t_csr, R.tab.begin() + R.t_csr + nirr);
+  for (int q = 0; q < nk; ++q) R.tab[R.t_qlist + fillp[P.wsrc[2 * q]]++] = q;  // increasing q per source
+  std::copy(P.ngirr.begin(), P.ngirr.end(), R.tab.begin() + R.t_ngirr);
+  std::copy(P.ng.begin(), P.ng.end(), R.tab.begin() + R.t_ng);
+  const size_t mat = (size_t)nk * ngm * ngm * sizeof(double2);
+  R.o_Wf = align256(R.tab.size() * sizeof(int));
+  R.o_dWf = align256(R.o_Wf + mat);
+  R.extra = align256(R.o_dWf + (want_dw ? mat : 0));
+  return BSE_OK;
+}
+
+// sys with W at every q in the unfolded area (the plan's view of the system).
+bse_system unfolded_view(const bse_system* sys, const double* Wf) {
+  bse_system s = *sys;
+  s.nirr = 0;
+  s.wsrc = nullptr;
+  s.wmap = nullptr;
+  s.W = Wf;
+  return s;
+}
+
 }  // namespace
 
 // Used by the variant of bse_spectrum without workspace (noalloc.hip).
@@ -1767,6 +1910,13 @@ size_t bse_workspace_size(const bse_system* sys, int nsys, int precision, int fl
       x.mixed = false;  // the backward contracts unsplit operands
     }
     Batch Bx;
+    if (pass > 0 && sys->nirr > 0) {  // the backward runs on W unfolded into the workspace
+      IrrBackward R;
+      if (plan_irr_backward(sys, true, R) != BSE_OK) continue;
+      const bse_system s2 = unfolded_view(sys, sys->W);
+      if (make_batch(&s2, 1, Tune{}, x, Bx) == BSE_OK) total = std::max(total, R.extra + Bx.total);
+      continue;
+    }
     if (make_batch(sys, nsys, Tune{}, x, Bx) == BSE_OK) total = std::max(total, Bx.total);
   }
   g_err = keep;
@@ -1924,87 +2074,33 @@ int bse_build_H_backward(const bse_system* sys, const double* dH, double* dW, do
                          double* drho_vv, double* drho_cc, int precision, int flags, void* ws, size_t ws_bytes,
                          void* stream) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (!sys) return fail(BSE_ERR_INVALID_ARG, "system pointer is NULL");
+  if (sys->nirr <= 0)
+    return backward_impl(sys, dH, dW, deps, dX, drho_vv, drho_cc, precision, flags, ws, ws_bytes, st);
   if (!dH || !ws) return fail(BSE_ERR_INVALID_ARG, "dH / ws is NULL");
-  if (precision < BSE_FP64 || precision > BSE_BF16X3) return fail(BSE_ERR_INVALID_ARG, "bad precision %d", precision);
-  if (flags & ~(BSE_PROJECT_DW | BSE_TIME_REVERSAL | BSE_FP32_PAIRDENS))
-    return fail(BSE_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
-  if ((flags & BSE_FP32_PAIRDENS) && precision == BSE_FP64)
-    return fail(BSE_ERR_INVALID_ARG, "BSE_FP32_PAIRDENS needs a mixed precision (split-FP32 or BF16x3)");
-  const bool project = (flags & BSE_PROJECT_DW) != 0;
-  Batch B;
-  BatchOpts opt;
-  opt.backward = true;
-  opt.project = project && dW;
-  opt.tr = (flags & BSE_TIME_REVERSAL) != 0;
-  opt.pd32 = (flags & BSE_FP32_PAIRDENS) != 0;
-  int rc = make_batch(sys, 1, Tune{}, opt, B);
+  IrrBackward R;
+  int rc = plan_irr_backward(sys, dW != nullptr, R);
   if (rc) return rc;
-  const Plan& P = B.P[0];
-  if (ws_bytes < B.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, B.total);
-  if (project && !P.tr_closed)
-    return fail(BSE_ERR_NOT_HERMITIAN, "G spheres are not closed under time reversal; cannot project dW");
+  if (ws_bytes < R.extra) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, R.extra);
   char* w = static_cast<char*>(ws);
-  if ((rc = upload_batch(B, sys, BSE_FP64, w, st))) return rc;
-  char* r = w + B.base[0];
-  if ((rc = prepare_u(B, sys, w, st))) return rc;
-  AdjArgs g{};
-  g.dH = reinterpret_cast<const double2*>(dH);
-  g.RV = reinterpret_cast<const double2*>(r + P.o_RV);
-  g.RC = reinterpret_cast<const double2*>(r + P.o_RC);
-  g.T = reinterpret_cast<double2*>(r + P.o_Z);
-  g.dWfinal = reinterpret_cast<double2*>(dW);
-  g.dWout = dW ? (project ? reinterpret_cast<double2*>(r + P.o_dWraw) : reinterpret_cast<double2*>(dW)) : nullptr;
-  g.deps = deps;
-  g.pairs = reinterpret_cast<const int4*>(r + P.o_pairs);
-  g.ng = reinterpret_cast<const int*>(r + P.o_ng);
-  g.qbar = reinterpret_cast<const int*>(r + P.o_qbar);
-  g.trmap = reinterpret_cast<const int*>(r + P.o_trmap);
-  g.nk = P.nk;
-  g.nv = P.nv;
-  g.nc = P.nc;
-  g.ns = P.ns;
-  g.ng_max = P.ng_max;
-  g.cpref = 27.211386245988 / ((double)P.nk * sys->omega_cell);
-  g.Z = reinterpret_cast<const double2*>(r + P.o_Z);
-  g.W = reinterpret_cast<const double2*>(sys->W);
-  g.Xs = reinterpret_cast<const double2*>(r + P.o_X);
-  g.vs = reinterpret_cast<const double*>(r + P.o_vs);
-  g.plex = reinterpret_cast<const int*>(r + P.o_plex);
-  g.ngx = P.ng[0];
-  g.dX = reinterpret_cast<double2*>(dX);
-  g.drv = reinterpret_cast<double2*>(drho_vv);
-  g.drc = reinterpret_cast<double2*>(drho_cc);
-  // the exchange densities (only for dX) and their gradient
-  if (dX) {
-    double* vs = reinterpret_cast<double*>(r + P.o_vs);
-    HIP_TRY(launch_vscale(sys->vx, P.ng[P.qexc], P.ng_max, P.g0x, vs, st));
-    if ((rc = run_pd(B, w, 0, 0, Tune{}, st))) return rc;
-    HIP_TRY(launch_adj_dx(g, st));
-  }
-  if (g.dWout) HIP_TRY(launch_zero_f64(reinterpret_cast<double*>(g.dWout), (size_t)P.nk * P.ng_max * P.ng_max * 2, st));
-  // per chunk: recompute the pair densities, then the chunk's share of every gradient
-  for (int c = 0; c < (int)B.C.size(); ++c) {
-    const BatchChunk& K = B.C[c];
-    if ((rc = run_pd(B, w, 1, c, Tune{}, st)) || (rc = run_tr_fill(B, w, 1, c, st)) ||
-        (rc = run_tr_fill(B, w, 2, c, st)))
-      return rc;
-    g.qstart = reinterpret_cast<const int*>(r + P.o_qs) + (size_t)c * (P.nk + 1);
-    g.p0 = P.ch[c].p0;
-    g.npairs = P.ch[c].np;
-    g.dwtiles = reinterpret_cast<const int4*>(w + K.o_dwt);
-    g.rvtiles = reinterpret_cast<const int4*>(w + K.o_rvt);
-    if (drho_cc) {
-      // Z = conj(rho_vv')^T W (the forward stage 1, FP64) into the Z area
-      const GemmArgs* gs = reinterpret_cast<const GemmArgs*>(w + K.o_gargs);
-      const S1Tile* s1 = reinterpret_cast<const S1Tile*>(w + K.o_s1);
-      HIP_TRY(launch_direct_s1(gs, s1, (int)K.s1.size(), BSE_FP64, 0, B.s1_rows, st));
-      HIP_TRY(launch_adj_drc(g, st));
-    }
-    // T (over the Z area), the chunk's share of dW
-    HIP_TRY(launch_adjoint(g, precision, (int)K.dwt.size(), K.has_q0, st));
-    if (drho_vv) HIP_TRY(launch_adj_drv(g, (int)K.rvt.size(), st));
-  }
-  HIP_TRY(launch_adjoint_finish(g, project, st));
+  const int* dt = reinterpret_cast<const int*>(w);
+  char* buf = nullptr;
+  if ((rc = staging_acquire(R.tab.size() * sizeof(int), &buf))) return rc;
+  std::memcpy(buf, R.tab.data(), R.tab.size() * sizeof(int));
+  HIP_TRY(hipMemcpyAsync(w, buf, R.tab.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  if ((rc = staging_release(st))) return rc;
+  const Plan& P = R.G;
+  double2* Wf = reinterpret_cast<double2*>(w + R.o_Wf);
+  HIP_TRY(launch_unfold_w(reinterpret_cast<const double2*>(sys->W), dt + R.t_wsrc, dt + R.t_wmap, dt + R.t_ng, P.nk,
+                          P.ng_max, Wf, st));
+  const bse_system s2 = unfolded_view(sys, reinterpret_cast<const double*>(Wf));
+  double* dWf = dW ? reinterpret_cast<double*>(w + R.o_dWf) : nullptr;
+  if ((rc = backward_impl(&s2, dH, dWf, deps, dX, drho_vv, drho_cc, precision, flags, w + R.extra,
+                          ws_bytes - R.extra, st)))
+    return rc;
+  if (dW)
+    HIP_TRY(launch_fold_dw(reinterpret_cast<const double2*>(dWf), dt + R.t_csr, dt + R.t_qlist, dt + R.t_wsrc,
+                           dt + R.t_winv, dt + R.t_ngirr, P.nirr, P.ng_max, reinterpret_cast<double2*>(dW), st));
   return BSE_OK;
 }
 

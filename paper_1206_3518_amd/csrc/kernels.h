@@ -286,6 +286,12 @@ hipError_t launch_adjoint(const AdjArgs& a, int precision, int ndw_tiles, bool h
 // after the last chunk: the projection of dW (if asked) and dL/de
 hipError_t launch_adjoint_finish(const AdjArgs& a, bool project, hipStream_t st);
 hipError_t launch_zero_f64(double* p, size_t n, hipStream_t st);
+// W at the irreducible q points: the unfolded W(q) at every q, and the adjoint
+// of that unfolding (dW of the nirr matrices from dW at every q)
+hipError_t launch_unfold_w(const double2* W, const int* wsrc, const int* wmap, const int* ng, int nk, int ng_max,
+                           double2* Wf, hipStream_t st);
+hipError_t launch_fold_dw(const double2* dWf, const int* csr, const int* qlist, const int* wsrc, const int* winv,
+                          const int* ngirr, int nirr, int ng_max, double2* dW, hipStream_t st);
 // dL/drho_cc' from Z (run before launch_adjoint overwrites Z with T)
 hipError_t launch_adj_drc(const AdjArgs& a, hipStream_t st);
 // dL/drho_vv' from T (after launch_adjoint)

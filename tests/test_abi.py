@@ -111,7 +111,7 @@ def test_workspace_size_and_host_errors():
                                   None, None, P.BSE_FP64, 0, ctypes.c_void_p(0x1000), n, None) == -7
     assert "momentum" in P.bse_last_error()
     # W of the irreducible q points: maps missing, out of range, not bijective,
-    # moving G = 0 of q = 0, two sphere sizes on one source; the backward refuses it
+    # moving G = 0 of q = 0
     s7 = B.make_system(B.cell_fcc(7.0), (16, 16, 16), (2, 2, 2), 2, 2, 3.0, seed=71)
     reps, wsrc, wmap = B.point_group_maps(s7)
     n7 = None
@@ -129,9 +129,12 @@ def test_workspace_size_and_host_errors():
         if code == 0:
             n7 = L.bse_workspace_size(ctypes.byref(st7), 1, 0, 0)
             assert n7 > 0
+            # the backward unfolds W into its workspace: a small one is refused on the host
             assert L.bse_build_H_backward(ctypes.byref(st7), ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), None,
-                                          None, None, None, P.BSE_FP64, 0, ctypes.c_void_p(0x1000), 1 << 40, None) == -7
-            assert "nirr" in P.bse_last_error()
+                                          None, None, None, P.BSE_FP64, 0, ctypes.c_void_p(0x1000), 4096, None) == -3
+            assert "workspace" in P.bse_last_error()
+            n7b = L.bse_workspace_size(ctypes.byref(st7), 1, 0, 0)
+            assert n7b >= 2 * 16 * s7.nk * s7.ng_max ** 2  # the unfolded W and dW at every q
             st7.nirr = s7.nk + 1
             assert L.bse_build_H(ctypes.byref(st7), 1, 0, 0, ctypes.c_void_p(0x1000), n7, None) == -1
             assert "nirr" in P.bse_last_error()

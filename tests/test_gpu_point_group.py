@@ -104,11 +104,10 @@ def test_irreducible_W_with_time_reversal_chunks_and_batch():
     assert torch.equal(d.H, one) and torch.equal(e.H, single)
 
 
-def test_irreducible_W_validation_and_backward():
+def test_irreducible_W_validation():
     """BSE_VALIDATE accepts the irreducible matrices and catches a
-    non-Hermitian one; the backward refuses W at the irreducible points."""
+    non-Hermitian one."""
     import paper_1206_3518_amd as P
-    import torch
     s = B.with_point_group_W(_fcc2(), proper=True)
     d = P.DeviceSystem(s, irreducible_W=True)
     P.bse_build_H([d], P.BSE_FP64, P.BSE_VALIDATE)
@@ -116,8 +115,6 @@ def test_irreducible_W_validation_and_backward():
     with pytest.raises(P.BseError) as ei:
         P.bse_build_H([d], P.BSE_FP64, P.BSE_VALIDATE)
     assert "Hermitian" in str(ei.value)
-    with pytest.raises(P.BseError):
-        P.bse_build_H_backward(d, torch.zeros_like(d.H))
 
 
 def test_screening_at_the_irreducible_points():
@@ -186,3 +183,36 @@ def test_irreducible_W_at_finite_momentum_and_beyond_tda():
     torch.cuda.synchronize()
     _say(f"finite Q and beyond-TDA with irreducible W: equal {torch.equal(a, b)}, {torch.equal(f1, f2)}")
     assert torch.equal(f1, f2)
+
+
+def test_backward_with_irreducible_W():
+    """The adjoint with W given at the irreducible points: dL/dW of the nirr
+    matrices equals the oracle's adjoint at every q folded by the oracle
+    (the adjoint of the unfolding), and the fold of the GPU's own full-W
+    backward; dL/de is unchanged."""
+    import paper_1206_3518_amd as P
+    import torch
+    s = B.with_point_group_W(B.make_system(B.cell_fcc(7.0), (16, 16, 16), (3, 3, 3), 2, 2, 2.0, seed=75),
+                             proper=True)
+    assert s.wsrc[:, 1].any()
+    d = P.DeviceSystem(s, irreducible_W=True)
+    H = P.build_H(d).cpu().numpy()
+    e, x = np.linalg.eigh(H)
+    G = np.outer(x[:, 0], np.conj(x[:, 0]))
+    dG = torch.from_numpy(G).cuda()
+    dWi, depsi = P.bse_build_H_backward(d, dG)
+    dWf, depsf = P.bse_build_H_backward(P.DeviceSystem(s), dG)
+    torch.cuda.synchronize()
+    dWi, depsi, dWf, depsf = dWi.cpu().numpy(), depsi.cpu().numpy(), dWf.cpu().numpy(), depsf.cpu().numpy()
+    nirr, ngm = len(s.W_irr), s.ng_max
+    assert dWi.shape == (nirr, ngm, ngm)
+    rW, reps = O.adjoint(s, G)
+    ref = O.fold_dW(rW, s.wsrc, s.wmap, s.ng, nirr, ngm)
+    scale = np.abs(ref).max()
+    err = np.abs(dWi - ref).max()
+    own = np.abs(dWi - O.fold_dW(dWf, s.wsrc, s.wmap, s.ng, nirr, ngm)).max()
+    _say(f"backward with irreducible W: {nirr} of {s.nk} matrices; max|dW - oracle| {err:.3e} "
+         f"(max {scale:.3e}); against the folded full-W backward {own:.3e}")
+    assert err <= 1e-10 * scale
+    assert own <= 1e-12 * scale
+    assert np.array_equal(depsi, depsf) and np.abs(depsi - reps).max() <= 1e-12

@@ -144,3 +144,24 @@ def test_hamiltonian_with_unfolded_W():
     assert np.abs(H - H.conj().T).max() <= 1e-12 * K
     assert np.abs(H - O.build_H(s)).max() <= 1e-12 * K
     assert np.abs(H - H0).max() > 1e-3 * K
+
+
+def test_fold_is_the_adjoint_of_the_unfolding():
+    """For random dW at every q and a random change d of the irreducible
+    matrices: Re <dW, unfold(d)> = Re <fold(dW), d>, the identity that makes
+    fold(dL/dW) the gradient of L with respect to the irreducible matrices.
+    A fold that forgets the conjugation of time-reversed images, or reads the
+    map the wrong way round, fails it."""
+    s = B.with_point_group_W(B.make_system(B.cell_fcc(7.0), (16, 16, 16), (3, 3, 3), 1, 1, 2.0, seed=74),
+                             proper=True)
+    rng = np.random.default_rng(9)
+    nirr, ngm = len(s.W_irr), s.ng_max
+    G = rng.standard_normal((s.nk, ngm, ngm)) + 1j * rng.standard_normal((s.nk, ngm, ngm))
+    dlt = rng.standard_normal((nirr, ngm, ngm)) + 1j * rng.standard_normal((nirr, ngm, ngm))
+    lhs = np.real(np.sum(np.conj(G) * O.unfold_W(dlt, s.wsrc, s.wmap, s.ng)))
+    F = O.fold_dW(G, s.wsrc, s.wmap, s.ng, nirr, ngm)
+    rhs = np.real(np.sum(np.conj(F) * dlt))
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
+    assert s.wsrc[:, 1].any()  # time-reversed images take part
+    bad = O.fold_dW(G, np.column_stack([s.wsrc[:, 0], 0 * s.wsrc[:, 1]]), s.wmap, s.ng, nirr, ngm)
+    assert abs(np.real(np.sum(np.conj(bad) * dlt)) - lhs) > 1e-3 * abs(lhs)
