@@ -362,8 +362,8 @@ def main():
                                                        out.get("lowest_exciton_eV"))
     if not args.no_beyond_tda and len(systems) == 1 and not args.kmesh and args.precision == "fp64":
         out["beyond_tda"] = beyond_tda_leg(P, args, ms)
-    if not args.no_point_group and len(systems) == 1 and not args.kmesh and args.config == 2:
-        out["point_group"] = point_group_leg(P, args, prec, flags, elements)
+    if not args.no_point_group and not args.kmesh and args.config in (2, 3):
+        out["point_group"] = point_group_leg(P, args, prec, flags, elements, systems)
     if not args.no_screening and args.config == 2 and not args.kmesh:
         out["screening"] = screening_leg(P)
     if not args.no_cpu_baseline:
@@ -553,31 +553,36 @@ def exciton_momentum_leg(P, args, prec, flags, elements, ms_optical, E_optical):
     return out
 
 
-def point_group_leg(P, args, prec, flags, elements):
-    """W of the same workload made symmetric under the cubic rotations and
-    time reversal, given once at every q and once at the irreducible q points
-    only (the library reads W(q) through the sphere maps of Sec. III.A); both
-    timed, H compared bit for bit."""
+def point_group_leg(P, args, prec, flags, elements, systems):
+    """W of the same workload made symmetric under the rotations of the
+    lattice and time reversal, given once at every q and once at the
+    irreducible q points only (the library reads W(q) through the sphere maps
+    of Sec. III.A); both timed, H compared bit for bit."""
     import torch
     import bse_synth as B
-    s = B.with_point_group_W(B.make_config(args.config), proper=True)
+    syms = [B.with_point_group_W(s, proper=True) for s in systems]
+    hexagonal = systems[0].cell[1, 0] < 0.0
     steps = max(2, args.steps // 2)
-    out = {"group": "cubic rotations + time reversal", "nirr": int(len(s.W_irr)), "nq": int(s.nk),
-           "W_bytes_every_q": int(s.W.nbytes), "W_bytes_irreducible": int(s.W_irr.nbytes)}
+    out = {"group": ("hexagonal rotations (D6)" if hexagonal else "cubic rotations (O)") + " + time reversal",
+           "nirr": [int(len(s.W_irr)) for s in syms], "nq": [int(s.nk) for s in syms],
+           "W_bytes_every_q": int(sum(s.W.nbytes for s in syms)),
+           "W_bytes_irreducible": int(sum(s.W_irr.nbytes for s in syms))}
+    if len(syms) == 1:
+        out["nirr"], out["nq"] = out["nirr"][0], out["nq"][0]
     H = None
     for name, irr in (("every_q", False), ("irreducible", True)):
-        d = P.DeviceSystem(s, device="cuda:0", irreducible_W=irr)
-        ws = P.workspace(P.bse_workspace_size([d], prec), d.device)
-        ms, _, stages = run_steps(P, [d], prec, flags, ws, steps, 1)
+        devs = [P.DeviceSystem(s, device="cuda:0", irreducible_W=irr) for s in syms]
+        ws = P.workspace(P.bse_workspace_size(devs, prec), devs[0].device)
+        ms, _, stages = run_steps(P, devs, prec, flags, ws, steps, 1)
         torch.cuda.synchronize()
         out[name] = {"ms_per_step": ms, "value": elements / (ms / 1e3), "unit": "H elements/s",
                      "stage_ms": {k: v[0] / steps for k, v in stages.items() if v[1]}}
         if H is None:
-            H = d.H.clone()
+            H = [d.H.clone() for d in devs]
         else:
-            out["bit_identical"] = bool(torch.equal(H, d.H))
-        del d, ws
-    del H
+            out["bit_identical"] = bool(all(torch.equal(h, d.H) for h, d in zip(H, devs)))
+        del devs, ws
+    del H, syms
     return out
 
 

@@ -320,32 +320,40 @@ def coulomb_table(sys: System) -> np.ndarray:
 # point-group symmetry of the q mesh (Sec. III.A)
 
 def point_group(cell: np.ndarray, kmesh, proper: bool = False) -> List[np.ndarray]:
-    """The cubic point-group operations (the 48 signed permutations of the
-    Cartesian axes; with ``proper`` only the 24 rotations, the group of a
-    crystal without inversion) that map the reciprocal lattice and the
-    Gamma-centred mesh onto themselves, as integer matrices M acting on
+    """The point-group operations of the lattice (with ``proper`` only its
+    rotations, the group of a crystal without inversion) that also map the
+    Gamma-centred mesh onto itself, as integer matrices M acting on
     coordinates in the basis of the reciprocal vectors: T q has coordinates
-    M f when q has f.  The identity comes first."""
+    M f when q has f.  Found among the matrices with entries in {-1, 0, 1}
+    whose Cartesian form is orthogonal (48 for cubic cells, 24 for hexagonal
+    ones).  The identity comes first."""
     b = reciprocal(cell)                 # rows b_d: q = f @ b
     n = np.array(kmesh)
     ops = []
-    for perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
-        for sg in range(8):
-            R = np.zeros((3, 3))
-            for i in range(3):
-                R[i, perm[i]] = -1.0 if (sg >> i) & 1 else 1.0
-            if proper and np.linalg.det(R) < 0:
-                continue
-            M = np.linalg.solve(b.T, R @ b.T)  # b^T M = R b^T
-            Mi = np.rint(M)
-            if np.abs(M - Mi).max() > 1e-9:
-                continue
-            Mi = Mi.astype(np.int64)
-            # the mesh i / n maps onto itself: M diag(1/n) i must stay on it
-            if np.any((Mi * n[None, :]) % n[:, None] != 0):
-                continue
-            ops.append(Mi)
+    for code in range(3 ** 9):
+        d = [(code // 3 ** i) % 3 - 1 for i in range(9)]
+        Mi = np.array(d, dtype=np.int64).reshape(3, 3)
+        if abs(round(np.linalg.det(Mi))) != 1:
+            continue
+        R = b.T @ Mi @ np.linalg.inv(b.T)   # b^T M = R b^T
+        if np.abs(R @ R.T - np.eye(3)).max() > 1e-9:
+            continue
+        if proper and np.linalg.det(R) < 0:
+            continue
+        # the mesh i / n maps onto itself: n_d M_de / n_e must be integers
+        if np.any((Mi * n[:, None]) % n[None, :] != 0):
+            continue
+        ops.append(Mi)
+    ident = [i for i, M in enumerate(ops) if np.array_equal(M, np.eye(3, dtype=np.int64))][0]
+    ops.insert(0, ops.pop(ident))
     return ops
+
+
+def _mesh_op(M: np.ndarray, kmesh) -> np.ndarray:
+    """M in units of the mesh: the integer matrix taking the triplet i of q
+    (coordinates i / n) to n * (M (i / n))."""
+    n = np.array(kmesh, dtype=np.int64)
+    return (M * n[:, None]) // n[None, :]
 
 
 def irreducible_q(cell: np.ndarray, kmesh, proper: bool = False):
@@ -356,8 +364,6 @@ def irreducible_q(cell: np.ndarray, kmesh, proper: bool = False):
     the first mesh point of its orbit and maps to itself by the identity."""
     ops = point_group(cell, kmesh, proper)
     n = np.array(kmesh)
-    if not (n[0] == n[1] == n[2]):
-        raise ValueError("the cubic point group needs an n x n x n mesh")
     nk = int(np.prod(n))
     assign = [None] * nk
     reps = []
@@ -368,9 +374,9 @@ def irreducible_q(cell: np.ndarray, kmesh, proper: bool = False):
         iq = ktriplet(kmesh, q)
         for oi, M in enumerate(ops):
             for s in (1, -1):
-                # s T q_rep in mesh units: s M i / n (a uniform mesh, so M commutes with 1/n);
-                # the mesh point it folds to, and G0 = q - s T q_rep
-                tm = s * (M @ iq)
+                # s T q_rep in mesh units; the mesh point it folds to, and
+                # G0 = q - s T q_rep
+                tm = s * (_mesh_op(M, kmesh) @ iq)
                 tgt = kindex(kmesh, tm % n)
                 if assign[tgt] is None:
                     assign[tgt] = (q, oi, s, ((tm % n) - tm) // n)
@@ -436,7 +442,7 @@ def with_point_group_W(sys: System, proper: bool = False) -> System:
         cnt = 0
         for oi, M in enumerate(ops):
             for s in (1, -1):
-                tm = s * (M @ iq)
+                tm = s * (_mesh_op(M, sys.kmesh) @ iq)
                 if kindex(sys.kmesh, tm % n) != q:
                     continue
                 acc += image(sys.W[q], _sphere_map(sys, inv, q, q, oi, s, ((tm % n) - tm) // n), ng, s < 0)

@@ -173,6 +173,33 @@ def test_autograd_function():
     assert np.abs(W.grad.cpu().numpy() - project(s, rW)).max() <= 1e-9 * np.abs(rW).max()
 
 
+def test_autograd_function_with_irreducible_W():
+    """build_H_autograd on a system whose W is given at the irreducible q
+    points: W.grad has the nirr matrices' shape and equals the oracle's
+    adjoint at every q, projected, then folded by the oracle onto those
+    matrices."""
+    import paper_1206_3518_amd as P
+    import torch
+    s = B.with_point_group_W(B.make_system(B.cell_fcc(7.0), (16, 16, 16), (3, 3, 3), 2, 2, 2.0, seed=77),
+                             proper=True)
+    d = P.DeviceSystem(s, irreducible_W=True)
+    W = d.W.clone().requires_grad_(True)
+    eps = d.eps.clone().requires_grad_(True)
+    H = P.build_H_autograd(d, W, eps)
+    L = torch.linalg.eigvalsh(H.cpu())[0]
+    L.backward()
+    e, x = np.linalg.eigh(H.detach().cpu().numpy())
+    G = np.outer(x[:, 0], np.conj(x[:, 0]))
+    rW, reps = O.adjoint(s, G)
+    nirr, ngm = len(s.W_irr), s.ng_max
+    ref = O.fold_dW(project(s, rW), s.wsrc, s.wmap, s.ng, nirr, ngm)
+    assert W.grad.shape == (nirr, ngm, ngm)
+    err = np.abs(W.grad.cpu().numpy() - ref).max()
+    _say(f"autograd with {nirr} irreducible W matrices: max|dW - oracle| {err:.3e} (max {np.abs(ref).max():.3e})")
+    assert np.abs(eps.grad.cpu().numpy() - reps).max() <= 1e-10
+    assert err <= 1e-9 * np.abs(ref).max()
+
+
 def test_full_size_adjoint_on_sampled_q():
     """32^3 grid, 8^3 k mesh (H of dimension 8192): dL/dW on one
     self-partner q against the oracle's all-blocks adjoint, both projected."""

@@ -22,7 +22,11 @@ def _fcc2():
     return B.make_system(B.cell_fcc(7.0), (16, 16, 16), (2, 2, 2), 2, 3, 3.0, seed=72)
 
 
-CASES = [("fcc2-O", _fcc2, True), ("si24-O", lambda: B.make_config(1), True),
+def _hex6():
+    return B.make_system(B.cell_hex(B.A_HBN, B.C_HBN), (12, 12, 40), (6, 6, 1), 2, 2, 4.0, seed=76)
+
+
+CASES = [("fcc2-O", _fcc2, True), ("hex6-D6", _hex6, True), ("si24-O", lambda: B.make_config(1), True),
          ("si24-Oh", lambda: B.make_config(1), False)]
 
 
@@ -43,7 +47,7 @@ def test_irreducible_W_equals_the_full_W_build(name, make, proper):
         assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("name,make,proper", CASES[:2], ids=[c[0] for c in CASES[:2]])
+@pytest.mark.parametrize("name,make,proper", CASES[:3], ids=[c[0] for c in CASES[:3]])
 def test_irreducible_W_matches_oracle(name, make, proper):
     """FP64 parity with the oracle on W unfolded by the oracle itself."""
     import dataclasses
