@@ -255,8 +255,9 @@ typedef struct bse_tuning {
     int ktile;       /* k tile of the pair-density dispatch order                 */
     int wg_per_cu;   /* persistent dispatch: workgroups per compute unit          */
     float pd_ms;     /* measured pair-density launch (first chunk), ms            */
-    int s1_rows;     /* rows per workgroup tile (64 or 128) of the first
-                        direct-term contraction conj(rho_vv')^T W(q)             */
+    int s1_rows;     /* rows per workgroup tile (64, or 128 with the BF16
+                        parts) of the first direct-term contraction
+                        conj(rho_vv')^T W(q)                                     */
     float s1_ms;     /* measured launch of that contraction (first chunk), ms;
                         0 in the entries that time the pair densities          */
     int order;       /* static pair-density job order: 0 one contiguous segment
@@ -272,7 +273,7 @@ typedef struct bse_tuning {
  * static dispatch with k tiles 4, 8, 16 in each job order (field order of
  * bse_tuning), and persistent dispatch with 1..4 workgroups per CU; then, with the fastest of those, the first direct-term
  * contraction of that chunk (in the given precision) with workgroup tiles of
- * 64 x 64 and 128 x 64 complex outputs.  It keeps both choices for every
+ * 64 x 64 and (BF16x3 only) 128 x 64 complex outputs.  It keeps both choices for every
  * later bse_build_H of the same signature in this process (BSE_PERSISTENT
  * still forces persistent dispatch).  flags: 0, or BSE_FP32_PAIRDENS (with a mixed precision) to tune
  * the FP32 pair-density kernel, whose builds then use that choice.  cache_path (HOST, nullable): a text file of one JSON object per

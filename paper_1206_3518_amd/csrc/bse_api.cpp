@@ -168,6 +168,23 @@ std::vector<PdJob> dispatch_order(std::vector<PdJob> jobs, int ktile, int order 
   return out;
 }
 
+// Workgroup b of a launch runs on XCD b mod 8, so tiles next to each other in
+// a list land in eight different L2 caches.  This reorders a tile list so that
+// XCD x takes the x-th contiguous segment of it, in order: the column tiles of
+// one row block, which read the same rows of the left operand, and the row
+// blocks of one q, which read the same W(q), then meet in one L2.  A
+// permutation, without holes.
+template <class T>
+std::vector<T> xcd_segments(const std::vector<T>& in) {
+  const size_t n = in.size(), base = n / kXcds, extra = n % kXcds;
+  std::vector<T> out(n);
+  for (size_t b = 0; b < n; ++b) {
+    const size_t x = b % kXcds, s = b / kXcds;
+    out[b] = in[x * base + std::min(x, extra) + s];
+  }
+  return out;
+}
+
 // The per-pair arrays of the build (RV, RC, Z and, in the mixed precisions,
 // the split copy of conj(RV)) hold one chunk of k pairs at a time.  A batch's
 // pairs are cut into chunks of about g_chunk_budget bytes of those arrays (all
@@ -936,6 +953,7 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
     }
     K.d2n = K.d2off[nsys];
     K.jd = dispatch_order(std::move(jd), tn.ktile, tn.order);
+    K.s1 = xcd_segments(K.s1);
   }
   // workspace: batch tables, then one region per system
   size_t o = 0;
@@ -1631,7 +1649,7 @@ int autotune(const bse_system* sys, int nsys, int precision, bool pd32, const ch
     float s1_best = -1.f;
     int rows_best = 64;
     for (int rows : {64, 128}) {
-      if (rows == 128 && precision == BSE_SPLIT_FP32) continue;  // FP32 parts: 64-row tiles only
+      if (rows == 128 && precision != BSE_BF16X3) continue;  // FP64 and FP32 parts: 64-row tiles only
       Tune c = best;
       c.s1_rows = rows;
       Batch B;
@@ -2022,7 +2040,7 @@ int bse_build_H(const bse_system* sys, int nsys, int precision, int flags, void*
   if (rc) return rc;
   Tune tn = tune_for(batch_key(Bp->P, precision, Bp->pd32));
   if (flags & BSE_PERSISTENT) tn.persist = 1;
-  if (precision == BSE_SPLIT_FP32) tn.s1_rows = 64;  // FP32 parts: 64-row tiles only
+  if (precision != BSE_BF16X3) tn.s1_rows = 64;  // FP64 and FP32 parts: 64-row tiles only
   if ((tn.ktile != Tune{}.ktile || tn.s1_rows != Tune{}.s1_rows || tn.order != Tune{}.order) &&
       (rc = cached_batch(sys, nsys, tn, opt, &Bp)))
     return rc;

@@ -48,13 +48,12 @@ hipError_t launch_exchange(const GemmArgs* gs, const HTile* tiles, int ntiles, i
 
 // MAP: some system of the batch gives W at the irreducible q points only; its
 // W(q) is read from the source matrix through the sphere map of q (Sec. III.A),
-// conjugated for the time-reversed images.  Tiles of 64 MR rows.  Waves per
-// SIMD: the compiler's choice (three) for the plain 64-row tile; three for the
-// mapped one, which would otherwise take a few registers more and drop to two;
-// two for 128 rows.
-template <bool MAP, int MR>
-__global__ __launch_bounds__(256, MR == 2 ? 2 : MAP ? 3 : 1) void k_direct_s1(const GemmArgs* __restrict__ gs,
-                                                                              const S1Tile* __restrict__ tiles) {
+// conjugated for the time-reversed images.  64-row tiles in the three-product
+// form (a quarter fewer MFMAs; its three accumulators hold the tile at two
+// waves per SIMD).
+template <bool MAP>
+__global__ __launch_bounds__(256, 2) void k_direct_s1(const GemmArgs* __restrict__ gs,
+                                                      const S1Tile* __restrict__ tiles) {
   const S1Tile tl = tiles[blockIdx.x];
   const GemmArgs g = gs[tl.sys];
   const int nv2 = g.rv_rows;
@@ -62,42 +61,41 @@ __global__ __launch_bounds__(256, MR == 2 ? 2 : MAP ? 3 : 1) void k_direct_s1(co
   const int rows = (gbl(g.qstart)[tl.iq + 1] - gbl(g.qstart)[tl.iq]) * nv2;
   const int K = gbl(g.ng)[tl.iq];
   const double2* A = g.RV + (size_t)row_base * g.ng_max;
-  d4 cre[2 * MR][2], cim[2 * MR][2];
-  const int r0 = tl.mt * TM * MR, c0 = tl.nt * TN;
+  d4 cre[2][2], cim[2][2];
+  const int r0 = tl.mt * TM, c0 = tl.nt * TN;
   if constexpr (MAP) {  // systems without maps take the same path with a null map
     const bool m = g.wmap != nullptr;
     const int src = m ? gbl(g.wsrc)[2 * tl.iq] : tl.iq, cj = m ? gbl(g.wsrc)[2 * tl.iq + 1] : 0;
-    tile_gemm<true, false, false, true, true, MR>(A, g.ng_max, r0, rows, g.W + (size_t)src * g.ng_max * g.ng_max,
-                                                  g.ng_max, c0, K, K, cre, cim,
-                                                  m ? g.wmap + (size_t)tl.iq * g.ng_max : nullptr, cj != 0);
+    tile_gemm<true, false, false, true, true, 1, true>(A, g.ng_max, r0, rows,
+                                                       g.W + (size_t)src * g.ng_max * g.ng_max, g.ng_max, c0, K, K,
+                                                       cre, cim, m ? g.wmap + (size_t)tl.iq * g.ng_max : nullptr,
+                                                       cj != 0);
   } else {
     const double2* Wq = g.W + (size_t)tl.iq * g.ng_max * g.ng_max;
-    tile_gemm<true, false, false, true, false, MR>(A, g.ng_max, r0, rows, Wq, g.ng_max, c0, K, K, cre, cim);
+    tile_gemm<true, false, false, true, false, 1, true>(A, g.ng_max, r0, rows, Wq, g.ng_max, c0, K, K, cre, cim);
   }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
   double2* Z = g.Z + (size_t)row_base * g.ng_max;
 #pragma unroll
-  for (int i = 0; i < 2 * MR; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = r0 + wr * 32 * MR + i * 16 + 4 * r + (lane >> 4);
+        const int row = r0 + wr * 32 + i * 16 + 4 * r + (lane >> 4);
         const int col = c0 + wc * 32 + j * 16 + (lane & 15);
         if (row < rows && col < K) gst(Z, (size_t)row * g.ng_max + col, make_double2(cre[i][j][r], cim[i][j][r]));
       }
 }
 
+// rows: tile rows, 64 in FP64 (128 only for the BF16 parts).
 hipError_t launch_direct_s1(const GemmArgs* gs, const S1Tile* tiles, int ntiles, int precision, int mapped,
                             int rows, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
   if (rows != 64 && rows != 128) return hipErrorInvalidValue;
   if (precision != BSE_FP64) return launch_direct_s1_mx(gs, tiles, ntiles, precision, rows, st);
-  void (*k)(const GemmArgs*, const S1Tile*);
-  if (rows == 128)
-    k = mapped ? k_direct_s1<true, 2> : k_direct_s1<false, 2>;
-  else
-    k = mapped ? k_direct_s1<true, 1> : k_direct_s1<false, 1>;
+  if (rows != 64) return hipErrorInvalidValue;
+  void (*k)(const GemmArgs*, const S1Tile*) = mapped ? k_direct_s1<true> : k_direct_s1<false>;
   hipLaunchKernelGGL(k, dim3(ntiles), dim3(256), 0, st, gs, tiles);
   return hipGetLastError();
 }

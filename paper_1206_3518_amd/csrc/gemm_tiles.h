@@ -32,13 +32,27 @@ constexpr int TM = 64, TN = 64, KC = 16;
 // elements are loaded into registers while the MFMAs consume the current one
 // (out-of-range elements are read from the array start and replaced by zero,
 // so the loads need no branches).
-template <bool CONJ_A, bool B_T, bool A_T = false, bool ZERO = true, bool B_MAP = false, int MR = 1>
+// G3: three real products per complex step instead of four (Gauss's form:
+// P1 = sum a_r b_r, P2 = sum a_i b_i, P3 = sum (a_r + a_i)(b_r + b_i), then
+// Re = P1 - P2, Im = P3 - P1 - P2), accumulated separately over K and
+// combined at the end; three quarters of the MFMA work, one extra addition per
+// operand fragment.  Im then carries rounding of the order of the unit
+// roundoff times sum |a||b| rather than times |Im| (starting from zero only).
+template <bool CONJ_A, bool B_T, bool A_T = false, bool ZERO = true, bool B_MAP = false, int MR = 1, bool G3 = false>
 __device__ __forceinline__ void tile_gemm(const double2* __restrict__ A, int lda, int a_off, int a_lim,
                                           const double2* __restrict__ B, int ldb, int b_off, int b_lim, int K,
                                           d4 (&cre)[2 * MR][2], d4 (&cim)[2 * MR][2],
                                           const int* __restrict__ bmap = nullptr, bool bconj = false) {
   static_assert(!(B_MAP && B_T), "the mapped B operand is read untransposed");
   static_assert(MR == 1 || MR == 2, "64 or 128 rows per tile");
+  static_assert(ZERO || !G3, "the three-product form starts from zero");
+  d4 p2[G3 ? 2 * MR : 1][2];  // G3: sum a_i b_i (cre holds P1, cim P3 until the end)
+  if constexpr (G3) {
+#pragma unroll
+    for (int i = 0; i < 2 * MR; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) p2[i][j] = d4{0, 0, 0, 0};
+  }
   __shared__ double As_re[TM * MR][KC + 1], As_im[TM * MR][KC + 1];
   __shared__ double Bs_re[KC][TN + 1], Bs_im[KC][TN + 1];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -148,17 +162,43 @@ __device__ __forceinline__ void tile_gemm(const double2* __restrict__ A, int lda
         bre[i] = Bs_re[kk + (lane >> 4)][wc * 32 + i * 16 + (lane & 15)];
         bim[i] = Bs_im[kk + (lane >> 4)][wc * 32 + i * 16 + (lane & 15)];
       }
+      if constexpr (G3) {
+        double asum[2 * MR], bsum[2];
 #pragma unroll
-      for (int i = 0; i < 2 * MR; ++i)
+        for (int i = 0; i < 2 * MR; ++i) asum[i] = are[i] + aim[i];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          cre[i][j] = mfma64(are[i], bre[j], cre[i][j]);
-          cre[i][j] = mfma64(-aim[i], bim[j], cre[i][j]);
-          cim[i][j] = mfma64(are[i], bim[j], cim[i][j]);
-          cim[i][j] = mfma64(aim[i], bre[j], cim[i][j]);
-        }
+        for (int j = 0; j < 2; ++j) bsum[j] = bre[j] + bim[j];
+#pragma unroll
+        for (int i = 0; i < 2 * MR; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            cre[i][j] = mfma64(are[i], bre[j], cre[i][j]);
+            p2[i][j] = mfma64(aim[i], bim[j], p2[i][j]);
+            cim[i][j] = mfma64(asum[i], bsum[j], cim[i][j]);
+          }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 2 * MR; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            cre[i][j] = mfma64(are[i], bre[j], cre[i][j]);
+            cre[i][j] = mfma64(-aim[i], bim[j], cre[i][j]);
+            cim[i][j] = mfma64(are[i], bim[j], cim[i][j]);
+            cim[i][j] = mfma64(aim[i], bre[j], cim[i][j]);
+          }
+      }
     }
     __syncthreads();
+  }
+  if constexpr (G3) {
+#pragma unroll
+    for (int i = 0; i < 2 * MR; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const d4 a = cre[i][j], b = p2[i][j];
+        cre[i][j] = a - b;
+        cim[i][j] = cim[i][j] - a - b;
+      }
   }
 }
 

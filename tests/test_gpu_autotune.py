@@ -83,9 +83,9 @@ def test_autotune_fp32_pairdens_separate_key(tmp_path):
 @pytest.mark.parametrize("prec", ["fp64", "split_fp32", "bf16x3"])
 def test_stage1_tile_shapes(tmp_path, prec):
     """The autotuner times the first direct-term contraction with 64- and
-    128-row tiles; a cached choice of either shape gives H bit-identical to
-    the default build (each output element sums its products in the same
-    order whatever the tile)."""
+    (BF16 parts) 128-row tiles; a cached choice of either shape gives H
+    bit-identical to the default build (each output element sums its products
+    in the same order whatever the tile)."""
     import paper_1206_3518_amd as P
     import torch
     p = P.PRECISIONS[prec]
@@ -100,7 +100,7 @@ def test_stage1_tile_shapes(tmp_path, prec):
     tried = P.bse_autotune_last()
     s1 = {t["s1_rows"]: t["s1_ms"] for t in tried if t["s1_ms"] > 0}
     print(f"{prec}: stage-1 tiles {s1}, chosen {got['s1_rows']}", flush=True)
-    shapes = {64} if prec == "split_fp32" else {64, 128}  # FP32 parts: 64-row tiles only
+    shapes = {64, 128} if prec == "bf16x3" else {64}  # FP64 and FP32 parts: 64-row tiles only
     assert set(s1) == shapes and got["s1_rows"] in shapes and got["s1_ms"] == min(s1.values())
     line = json.loads(cache.read_text().splitlines()[0])
     for rows in sorted(shapes, reverse=True):
