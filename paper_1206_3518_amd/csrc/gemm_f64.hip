@@ -17,12 +17,13 @@ namespace bse {
 
 // ------------------------------------------------------------------ exchange
 
-__global__ __launch_bounds__(256) void k_exchange(const GemmArgs* __restrict__ gs, const HTile* __restrict__ tiles) {
+__global__ __launch_bounds__(256, 2) void k_exchange(const GemmArgs* __restrict__ gs, const HTile* __restrict__ tiles) {
   const HTile tl = tiles[blockIdx.x];
   const GemmArgs g = gs[tl.sys];
   const int r0 = tl.i * TM, c0 = tl.j * TN;
   d4 cre[2][2], cim[2][2];
-  tile_gemm<true, true>(g.X, g.ng_max, r0, g.ns, g.Xb ? g.Xb : g.X, g.ng_max, c0, g.ns, g.ngx, cre, cim);
+  tile_gemm<true, true, false, true, false, 1, true>(g.X, g.ng_max, r0, g.ns, g.Xb ? g.Xb : g.X, g.ng_max, c0, g.ns,
+                                                     g.ngx, cre, cim);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
   const double s = 2.0 * g.cpref;
 #pragma unroll

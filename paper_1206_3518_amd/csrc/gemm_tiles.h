@@ -82,6 +82,10 @@ __device__ __forceinline__ void tile_gemm(const double2* __restrict__ A, int lda
       mn[i] = n < b_lim ? (bmap ? bmap[n] : n) : 0;
     }
   }
+  // mapped B: the row map entry of this thread's k for the chunk being
+  // loaded, read one chunk ahead so that the W load does not wait on it
+  int mk = 0;
+  if constexpr (B_MAP) mk = bk < K ? (bmap ? bmap[bk] : bk) : 0;
   auto load = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < 4 * MR; ++e) {
@@ -111,7 +115,7 @@ __device__ __forceinline__ void tile_gemm(const double2* __restrict__ A, int lda
       } else if constexpr (B_MAP) {
         const int n = b_off + bc + i, k = k0 + bk;
         ok = k < K && n < b_lim;
-        idx = (size_t)(k < K ? (bmap ? bmap[k] : k) : 0) * ldb + mn[i];
+        idx = (size_t)(k < K ? mk : 0) * ldb + mn[i];
       } else {
         const int n = b_off + bc + i, k = k0 + bk;
         ok = k < K && n < b_lim;
@@ -119,6 +123,10 @@ __device__ __forceinline__ void tile_gemm(const double2* __restrict__ A, int lda
       }
       const double2 v = gld(B, ok ? idx : 0);
       rb[i] = make_double2(ok ? v.x : 0.0, ok ? (B_MAP && bconj ? -v.y : v.y) : 0.0);
+    }
+    if constexpr (B_MAP) {
+      const int kn = k0 + KC + bk;  // the next chunk's row
+      mk = kn < K ? (bmap ? bmap[kn] : kn) : 0;
     }
   };
   auto store = [&]() {
