@@ -124,14 +124,24 @@ __global__ __launch_bounds__(256) void k_direct_s2(const GemmArgs* __restrict__ 
   const double2* zr = g.Z + ((size_t)p * nv2 + (ia < nv2 ? ia : 0)) * g.ng_max;
   const double2* cr = g.RC + ((size_t)p * nc2 + (jb < nc2 ? jb : 0)) * g.ng_max;
   d4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
-  for (int k0 = 0; k0 < K; k0 += 4) {
-    const int k = k0 + (lane >> 4);
-    const double2 a = (ia < nv2 && k < K) ? gld(zr, k) : make_double2(0.0, 0.0);
-    const double2 b = (jb < nc2 && k < K) ? gld(cr, k) : make_double2(0.0, 0.0);
-    cre = mfma64(a.x, b.x, cre);
-    cre = mfma64(-a.y, b.y, cre);
-    cim = mfma64(a.x, b.y, cim);
-    cim = mfma64(a.y, b.x, cim);
+  // four K steps of loads in flight before their MFMAs (the same products in
+  // the same order as one step at a time)
+  constexpr int U = 4;
+  for (int k0 = 0; k0 < K; k0 += 4 * U) {
+    double2 a[U], b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + 4 * u + (lane >> 4);
+      a[u] = (ia < nv2 && k < K) ? gld(zr, k) : make_double2(0.0, 0.0);
+      b[u] = (jb < nc2 && k < K) ? gld(cr, k) : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      cre = mfma64(a[u].x, b[u].x, cre);
+      cre = mfma64(-a[u].y, b[u].y, cre);
+      cim = mfma64(a[u].x, b[u].y, cim);
+      cim = mfma64(a[u].y, b[u].x, cim);
+    }
   }
   // mixed precisions: the q = 0 head of W, left out of their stage 1, in FP64
   const bool head = pr.z == 0 && g.w_head_fp64;
