@@ -282,18 +282,21 @@ def exciton_energies(H, n=10):
 
 
 def adjoint(sys, Gbar, qs=None, separable=True):
-    """Adjoint of the block-by-block map (W, eps) -> H of ``build_H``.
+    """Adjoint of the block-by-block map (W, eps) -> H of ``build_H`` (at
+    exciton momentum Q = ``sys.qexc``: of ``build_H_exciton``).
 
     Gbar = dL/dRe H + i dL/dIm H (the PyTorch convention for a real L of a
-    complex H).  With dL = Re sum conj(Gbar) dH:
-      dL/dW_{GG'}(q) = -c sum_{(k,k') folding to q} sum_{vv'cc'} Gbar_SS' n_{vk,v'k'}(G) conj(n_{ck,c'k'}(G'))
-      dL/de_ck = sum_v Re Gbar_SS,   dL/de_vk = -sum_c Re Gbar_SS
+    complex H).  With dL = Re sum conj(Gbar) dH and S = (k v c):
+      dL/dW_{GG'}(q) = -c sum_{(k,k') folding to q} sum_{vv'cc'} Gbar_SS' n_{vk,v'k'}(G) conj(n_{c k+Q,c' k'+Q}(G'))
+      dL/de_{c,k+Q} = sum_v Re Gbar_SS,   dL/de_vk = -sum_c Re Gbar_SS
     (direct term and transition energies of Sec. II.C).  ``qs`` restricts dW
     to those q.  Returns (dW [Nk][ng_max][ng_max], deps [Nk][nb]).
     """
     nk, nv, nc, nb = sys.nk, sys.nv, sys.nc, sys.nb
     nt = nv * nc
     c = HARTREE_EV / (nk * sys.omega_cell)
+    Q = int(getattr(sys, "qexc", 0))
+    kq = [k_plus_q(sys.kmesh, k, Q) for k in range(nk)]
     dW = np.zeros((nk, sys.ng_max, sys.ng_max), dtype=np.complex128)
     pairs = []
     for ka in range(nk):
@@ -304,7 +307,7 @@ def adjoint(sys, Gbar, qs=None, separable=True):
     items = []
     for ka, kb, _ in pairs:
         items += [(ka, v, kb, v2) for v in range(nv) for v2 in range(nv)]
-        items += [(ka, nv + c1, kb, nv + c2) for c1 in range(nc) for c2 in range(nc)]
+        items += [(kq[ka], nv + c1, kq[kb], nv + c2) for c1 in range(nc) for c2 in range(nc)]
     rho = pair_density_items(sys, items, separable) if items else None
     per = nv * nv + nc * nc
     for i, (ka, kb, iq) in enumerate(pairs):
@@ -316,7 +319,7 @@ def adjoint(sys, Gbar, qs=None, separable=True):
         dW[iq, :ng, :ng] += -c * np.einsum("acbd,abg,cdh->gh", gb, rv, np.conj(rc))
     deps = np.zeros((nk, nb))
     dg = np.real(np.diag(Gbar)).reshape(nk, nv, nc)
-    deps[:, nv:] = dg.sum(axis=1)
+    deps[kq, nv:] = dg.sum(axis=1)
     deps[:, :nv] = -dg.sum(axis=2)
     return dW, deps
 

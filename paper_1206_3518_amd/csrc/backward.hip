@@ -6,7 +6,7 @@
 // lower block adds its conjugate transpose) or Gbar (k = k'), and
 //   T[(kk' vv')][g']   = sum_{cc'} Gbar_eff[(k v c),(k' v' c')] conj(rho_cc'(g'))   (k_adj_T)
 //   dL/dW_q[g][g']     = -c sum_{pairs of q, vv'} rho_vv'(g) T[(kk' vv')][g']       (k_adj_dW, MFMA)
-//   dL/de_ck = sum_v Re Gbar_SS,  dL/de_vk = -sum_c Re Gbar_SS                       (k_adj_deps)
+//   dL/de_c(k+Q) = sum_v Re Gbar_SS,  dL/de_vk = -sum_c Re Gbar_SS, S = (k v c)      (k_adj_deps)
 // Optionally dW is projected onto Hermitian, time-reversal symmetric W by the
 // group average over (g g') -> conj(g' g) and (q g g') -> conj(qbar, t-g, t-g')
 // (Sec. III.A with T = 1).
@@ -165,9 +165,13 @@ __global__ void k_adj_deps(AdjArgs a) {
   const int k = id / nb, b = id % nb;
   double s = 0.0;
   if (b >= a.nv) {
+    // the electron at k is that of the states whose hole sits at k - Q
+    const int k1 = k / (a.kn[1] * a.kn[2]), k2 = (k / a.kn[2]) % a.kn[1], k3 = k % a.kn[2];
+    const int kh = (((k1 - a.qe[0] + a.kn[0]) % a.kn[0]) * a.kn[1] + (k2 - a.qe[1] + a.kn[1]) % a.kn[1]) * a.kn[2] +
+                   (k3 - a.qe[2] + a.kn[2]) % a.kn[2];
     const int c = b - a.nv;
     for (int v = 0; v < a.nv; ++v) {
-      const size_t S = ((size_t)k * a.nv + v) * a.nc + c;
+      const size_t S = ((size_t)kh * a.nv + v) * a.nc + c;
       s += a.dH[S * a.ns + S].x;
     }
   } else {

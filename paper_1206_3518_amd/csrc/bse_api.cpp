@@ -885,8 +885,6 @@ int make_batch(const bse_system* sys, int nsys, const Tune& tn, const BatchOpts&
     if (rc) return rc;
     if (B.P[i].qexc && opt.tr)
       return fail(BSE_ERR_INVALID_ARG, "system %d: BSE_TIME_REVERSAL needs exciton momentum Q = 0", i);
-    if (B.P[i].qexc && opt.backward)
-      return fail(BSE_ERR_UNSUPPORTED, "system %d: the backward needs exciton momentum Q = 0", i);
     if (B.P[i].nirr && opt.backward)
       return fail(BSE_ERR_UNSUPPORTED, "system %d: the backward needs W at every q (nirr = 0)", i);
     if ((rc = plan_pairs(&sys[i], B.P[i], opt, nchunk, i, B.s1_rows))) return rc;
@@ -1754,6 +1752,8 @@ int backward_impl(const bse_system* sys, const double* dH, double* dW, double* d
   if (ws_bytes < B.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, B.total);
   if (project && !P.tr_closed)
     return fail(BSE_ERR_NOT_HERMITIAN, "G spheres are not closed under time reversal; cannot project dW");
+  if (P.qexc && (dX || drho_vv || drho_cc))
+    return fail(BSE_ERR_UNSUPPORTED, "the gradients of the pair densities need exciton momentum Q = 0");
   char* w = static_cast<char*>(ws);
   if ((rc = upload_batch(B, sys, BSE_FP64, w, st))) return rc;
   char* r = w + B.base[0];
@@ -1776,6 +1776,10 @@ int backward_impl(const bse_system* sys, const double* dH, double* dW, double* d
   g.ns = P.ns;
   g.ng_max = P.ng_max;
   g.cpref = 27.211386245988 / ((double)P.nk * sys->omega_cell);
+  for (int d = 0; d < 3; ++d) g.kn[d] = sys->kmesh[d];
+  g.qe[0] = P.qexc / (sys->kmesh[1] * sys->kmesh[2]);
+  g.qe[1] = (P.qexc / sys->kmesh[2]) % sys->kmesh[1];
+  g.qe[2] = P.qexc % sys->kmesh[2];
   g.Z = reinterpret_cast<const double2*>(r + P.o_Z);
   g.W = reinterpret_cast<const double2*>(sys->W);
   g.Xs = reinterpret_cast<const double2*>(r + P.o_X);

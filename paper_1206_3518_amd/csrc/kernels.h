@@ -179,6 +179,7 @@ struct AdjArgs {
   const int* trmap;    // [Nk][ng_max] index of t - m_g in the sphere of qbar
   int nk, nv, nc, ns, ng_max, npairs;
   double cpref;
+  int qe[3], kn[3];    // exciton momentum Q and the k mesh (grid-axis triplets of the k index)
   // gradients with respect to the pair densities (nullable outputs)
   const double2* Z;    // forward stage-1 product conj(rho_vv')^T W, rows like RV
   const double2* W;    // [Nk][ng_max][ng_max]

@@ -83,3 +83,37 @@ def test_restricted_q_matches_full():
     dW2, _ = O.adjoint(s, G, qs={1, 2})
     assert np.abs(dW2[1] - dW[1]).max() < 1e-15 and np.abs(dW2[2] - dW[2]).max() < 1e-15
     assert np.abs(dW2[0]).max() == 0.0
+
+
+@pytest.mark.parametrize("kmesh,qexc", [((3, 1, 1), 1), ((2, 2, 1), 3)])
+def test_adjoint_at_finite_exciton_momentum(kmesh, qexc):
+    """At exciton momentum Q the map (W, eps) -> H of ``build_H_exciton`` is
+    affine, so for any Gbar and any changes dW0, de0 of W and eps:
+    Re <Gbar, H(W + dW0, eps + de0) - H(W, eps)> = Re <dL/dW, dW0> + <dL/de, de0>
+    up to rounding.  The conduction energies enter at k + Q and the
+    conduction densities pair (k + Q, k' + Q): an adjoint that credits the
+    energies at k, or contracts the unshifted densities, fails it (the last
+    two checks plant those mistakes)."""
+    s = B.with_exciton_momentum(B.make_system(B.cell_fcc(7.0), (8, 8, 8), kmesh, 2, 2, 2.0, seed=33), qexc)
+    rng = np.random.default_rng(8)
+    Gbar = rng.standard_normal((s.ns, s.ns)) + 1j * rng.standard_normal((s.ns, s.ns))
+    dW0 = np.zeros_like(s.W)
+    for q in range(s.nk):
+        ng = s.ng[q]
+        dW0[q, :ng, :ng] = rng.standard_normal((ng, ng)) + 1j * rng.standard_normal((ng, ng))
+    de0 = rng.standard_normal(s.eps.shape)
+    H = O.build_H_exciton(s)
+    H1 = O.build_H_exciton(dataclasses.replace(s, W=s.W + dW0, eps=s.eps + de0))
+    lhs = np.real(np.sum(np.conj(Gbar) * (H1 - H)))
+    dW, deps = O.adjoint(s, Gbar)
+    rhs = np.real(np.sum(np.conj(dW) * dW0)) + np.sum(deps * de0)
+    scale = np.abs(Gbar).sum() * np.abs(H1 - H).max()
+    assert abs(lhs - rhs) <= 1e-12 * scale
+    # the conduction energies credited at k instead of k + Q
+    bad = deps.copy()
+    dg = np.real(np.diag(Gbar)).reshape(s.nk, s.nv, s.nc)
+    bad[:, s.nv:] = dg.sum(axis=1)
+    assert abs(np.real(np.sum(np.conj(dW) * dW0)) + np.sum(bad * de0) - lhs) > 1e-6 * scale
+    # the conduction densities of (k, k') instead of (k + Q, k' + Q)
+    dWu, _ = O.adjoint(dataclasses.replace(s, qexc=0), Gbar)
+    assert abs(np.real(np.sum(np.conj(dWu) * dW0)) + np.sum(deps * de0) - lhs) > 1e-6 * scale
