@@ -160,8 +160,9 @@ typedef struct bse_system {
                              the transition energy is e_{c,k+Q} - e_{v,k}, the exchange runs
                              over S(Q) without G = 0 with the densities n_{vk,c k+Q}, and the
                              direct term pairs n_{vk,v'k'} with n_{c k+Q, c' k'+Q} (Eqs. V_eh,
-                             W_SS).  Q != 0: BSE_TIME_REVERSAL -> BSE_ERR_INVALID_ARG, the
-                             backward -> BSE_ERR_UNSUPPORTED; BSE_PD_EXCH then gives
+                             W_SS).  Q != 0: BSE_TIME_REVERSAL -> BSE_ERR_INVALID_ARG; the
+                             backward gives dW and deps (the gradients of the pair
+                             densities -> BSE_ERR_UNSUPPORTED); BSE_PD_EXCH then gives
                              n_{vk, c k+Q}.  Out of range -> BSE_ERR_INVALID_ARG.          */
     /* W from the irreducible q points only (Sec. III.A).  nirr = 0: W holds W(q) for every q
      * as above.  nirr > 0: W holds nirr matrices [nirr][ng_max][ng_max], the screened
@@ -222,7 +223,8 @@ int bse_build_H(const bse_system *sys, int nsys, int precision, int flags,
  * DEVICE complex or real as shown, nullable, fully written when given):
  *   dW      [Nk][ng_max][ng_max]     dL/dW_GG'(q), zero past ng(q) ([nirr][ng_max][ng_max] with W given
  *                                    at the irreducible q points: see bse_system.nirr)
- *   deps    [Nk][nb] (real)          dL/de (eV/eV)
+ *   deps    [Nk][nb] (real)          dL/de (eV/eV); at exciton momentum Q the conduction
+ *                                    energy of S = (k, v, c) is e_{c,k+Q}, so its gradient lands at k+Q
  *   dX      [Nk][nv][nc][ng_max]     dL/dn_{vk,ck}(G) on S(0) (the pair density
  *                                    itself, not scaled by v), zero at G = 0
  *                                    and past ng(0)
@@ -240,7 +242,10 @@ int bse_build_H(const bse_system *sys, int nsys, int precision, int flags,
  * checked here); with BSE_FP32_PAIRDENS (mixed precisions only) the valence
  * and conduction densities are recomputed in FP32 as in bse_build_H.  precision selects the arithmetic of the dW contraction
  * (its q = 0 head entry is FP64 in every mode); the density gradients are
- * FP64.  sys->H is not read.
+ * FP64.  At exciton momentum Q != 0 the recomputed conduction densities are
+ * those of the pairs (k+Q, k'+Q), as in bse_build_H; dX, drho_vv and drho_cc
+ * must then be NULL (else BSE_ERR_UNSUPPORTED), and BSE_TIME_REVERSAL is
+ * refused as in the build.  sys->H is not read.
  */
 int bse_build_H_backward(const bse_system *sys, const double *dH, double *dW, double *deps, double *dX,
                          double *drho_vv, double *drho_cc, int precision, int flags, void *ws, size_t ws_bytes,

@@ -1739,6 +1739,8 @@ int backward_impl(const bse_system* sys, const double* dH, double* dW, double* d
     return fail(BSE_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
   if ((flags & BSE_FP32_PAIRDENS) && precision == BSE_FP64)
     return fail(BSE_ERR_INVALID_ARG, "BSE_FP32_PAIRDENS needs a mixed precision (split-FP32 or BF16x3)");
+  if (sys->qexc != 0 && (dX || drho_vv || drho_cc))
+    return fail(BSE_ERR_UNSUPPORTED, "the gradients of the pair densities need exciton momentum Q = 0");
   const bool project = (flags & BSE_PROJECT_DW) != 0;
   Batch B;
   BatchOpts opt;
@@ -1752,8 +1754,6 @@ int backward_impl(const bse_system* sys, const double* dH, double* dW, double* d
   if (ws_bytes < B.total) return fail(BSE_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, B.total);
   if (project && !P.tr_closed)
     return fail(BSE_ERR_NOT_HERMITIAN, "G spheres are not closed under time reversal; cannot project dW");
-  if (P.qexc && (dX || drho_vv || drho_cc))
-    return fail(BSE_ERR_UNSUPPORTED, "the gradients of the pair densities need exciton momentum Q = 0");
   char* w = static_cast<char*>(ws);
   if ((rc = upload_batch(B, sys, BSE_FP64, w, st))) return rc;
   char* r = w + B.base[0];

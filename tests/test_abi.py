@@ -107,9 +107,14 @@ def test_workspace_size_and_host_errors():
     st6.qexc = 1
     assert L.bse_build_H(ctypes.byref(st6), 1, 0, P.BSE_TIME_REVERSAL, ctypes.c_void_p(0x1000), n, None) == -1
     assert "TIME_REVERSAL" in P.bse_last_error()
-    assert L.bse_build_H_backward(ctypes.byref(st6), ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), None, None,
-                                  None, None, P.BSE_FP64, 0, ctypes.c_void_p(0x1000), n, None) == -7
+    # the backward at finite Q gives dW and deps, not the density gradients
+    assert L.bse_build_H_backward(ctypes.byref(st6), ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), None,
+                                  ctypes.c_void_p(0x1000), None, None, P.BSE_FP64, 0, ctypes.c_void_p(0x1000), n,
+                                  None) == -7
     assert "momentum" in P.bse_last_error()
+    assert L.bse_build_H_backward(ctypes.byref(st6), ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), None, None,
+                                  None, None, P.BSE_FP64, P.BSE_TIME_REVERSAL, ctypes.c_void_p(0x1000), n, None) == -1
+    assert "TIME_REVERSAL" in P.bse_last_error()
     # W of the irreducible q points: maps missing, out of range, not bijective,
     # moving G = 0 of q = 0
     s7 = B.make_system(B.cell_fcc(7.0), (16, 16, 16), (2, 2, 2), 2, 2, 3.0, seed=71)
