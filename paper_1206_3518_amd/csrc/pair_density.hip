@@ -332,6 +332,8 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
       unsigned k2 = __builtin_amdgcn_readfirstlane(keep2), k3 = __builtin_amdgcn_readfirstlane(keep3);
       int lo2 = __builtin_amdgcn_readfirstlane(a.lo2), lo3 = __builtin_amdgcn_readfirstlane(a.lo3);
       asm volatile("" : "+s"(k2), "+s"(k3), "+s"(lo2), "+s"(lo3));
+      // (f - lo) mod N as f + sh with one wrap, sh = N - (lo mod N) in [1, N]
+      const int sh2 = N2 - imod(lo2, N2), sh3 = N3 - imod(lo3, N3);
       // ---- pass 1 (idle lanes load a valid column and write padding or a
       // plane that pass 3 skips), once per two planes
 #pragma unroll
@@ -374,9 +376,9 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
         static_for<0, N2>([&](auto fc) {
           constexpr int f = decltype(fc)::value;
           if (k2 & (1u << f)) {  // wave-uniform
-            int r = f - lo2;
-            r += r < 0 ? N2 : 0;
-            r -= r >= N2 ? N2 : 0;
+            int r = f + sh2;
+            if constexpr ((N2 & (N2 - 1)) == 0) r &= N2 - 1;
+            else r -= r >= N2 ? N2 : 0;
             constexpr int q = fft_pos<H2>(f % H2);
             T1w[r * S1 + c] = cadd(E[q], cmul_root<N2, f>(O[q]));
           }
@@ -403,9 +405,9 @@ __device__ __forceinline__ void pd_line_job(const PdArgs& a, const PdJob& job) {
         static_for<0, N3>([&](auto fc) {
           constexpr int f = decltype(fc)::value;
           if (k3 & (1u << f)) {  // wave-uniform
-            int r = f - lo3;
-            r += r < 0 ? N3 : 0;
-            r -= r >= N3 ? N3 : 0;
+            int r = f + sh3;
+            if constexpr ((N3 & (N3 - 1)) == 0) r &= N3 - 1;
+            else r -= r >= N3 ? N3 : 0;
             constexpr int q = fft_pos<H3>(f % H3);
             const C v = cadd(E[q], cmul_root<N3, f>(O[q]));
             if (ok) T2[rr * F3 + r] = v;
