@@ -189,15 +189,18 @@ def test_irreducible_W_at_finite_momentum_and_beyond_tda():
     assert torch.equal(f1, f2)
 
 
-def test_backward_with_irreducible_W():
+@pytest.mark.parametrize("make", [
+    lambda: B.make_system(B.cell_fcc(7.0), (16, 16, 16), (3, 3, 3), 2, 2, 2.0, seed=75),
+    lambda: B.make_system(B.cell_hex(B.A_HBN, B.C_HBN), (12, 12, 40), (3, 3, 1), 2, 2, 3.0, seed=79)],
+    ids=["fcc3-O", "hex3-D6"])
+def test_backward_with_irreducible_W(make):
     """The adjoint with W given at the irreducible points: dL/dW of the nirr
     matrices equals the oracle's adjoint at every q folded by the oracle
     (the adjoint of the unfolding), and the fold of the GPU's own full-W
     backward; dL/de is unchanged."""
     import paper_1206_3518_amd as P
     import torch
-    s = B.with_point_group_W(B.make_system(B.cell_fcc(7.0), (16, 16, 16), (3, 3, 3), 2, 2, 2.0, seed=75),
-                             proper=True)
+    s = B.with_point_group_W(make(), proper=True)
     assert s.wsrc[:, 1].any()
     d = P.DeviceSystem(s, irreducible_W=True)
     H = P.build_H(d).cpu().numpy()
