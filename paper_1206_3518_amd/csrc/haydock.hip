@@ -57,19 +57,19 @@ __global__ __launch_bounds__(1024) void k_hy_init(const double2* __restrict__ d,
 }
 
 // Y[p][r] = sum_c H[r][c] Q[p][c] for the NQ vectors Q[p] (p < nq; the rest
-// of the NQ slots are zero).  A workgroup takes 16 rows (4 per wave); column
-// chunks of 256 of Q go through LDS as [c][p]; lane l of a wave reads
-// columns c0 + l + 64 i of its rows, 1 KB per row and load instruction.
-constexpr int kHyCols = 256;
+// of the NQ slots are zero).  A workgroup takes 4 kHyRows rows (kHyRows per
+// wave); column chunks of 256 of Q go through LDS as [c][p]; lane l of a wave
+// reads columns c0 + l + 64 i of its rows, 1 KB per row and load instruction.
+constexpr int kHyCols = 256, kHyRows = 2;
 template <int NQ>
 __global__ __launch_bounds__(256) void k_hy_hemv(const double2* __restrict__ H, int ns, const double2* __restrict__ Q,
                                                  int nq, double2* __restrict__ Y) {
   __shared__ double2 qs[kHyCols][NQ];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r0 = blockIdx.x * 16 + wave * 4;
-  double2 acc[4][NQ];
+  const int r0 = blockIdx.x * 4 * kHyRows + wave * kHyRows;
+  double2 acc[kHyRows][NQ];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < kHyRows; ++i)
 #pragma unroll
     for (int p = 0; p < NQ; ++p) acc[i][p] = make_double2(0.0, 0.0);
   for (int c0 = 0; c0 < ns; c0 += kHyCols) {
@@ -79,9 +79,9 @@ __global__ __launch_bounds__(256) void k_hy_hemv(const double2* __restrict__ H, 
       qs[c][p] = (p < nq && c0 + c < ns) ? gld(Q, (size_t)p * ns + c0 + c) : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    double2 h[4][kHyCols / 64];
+    double2 h[kHyRows][kHyCols / 64];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < kHyRows; ++i) {
       const int r = r0 + i < ns ? r0 + i : 0;
 #pragma unroll
       for (int t = 0; t < kHyCols / 64; ++t) {
@@ -95,13 +95,13 @@ __global__ __launch_bounds__(256) void k_hy_hemv(const double2* __restrict__ H, 
 #pragma unroll
       for (int p = 0; p < NQ; ++p) qv[p] = qs[lane + 64 * t][p];  // zero past ns
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < kHyRows; ++i)
 #pragma unroll
         for (int p = 0; p < NQ; ++p) acc[i][p] = cfma(h[i][t], qv[p], acc[i][p]);
     }
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < kHyRows; ++i)
 #pragma unroll
     for (int p = 0; p < NQ; ++p) {
       const double re = wave_sum(acc[i][p].x), im = wave_sum(acc[i][p].y);
@@ -184,7 +184,7 @@ hipError_t launch_haydock(int ns, const double2* H, const double2* d, int nq, in
   hipLaunchKernelGGL(k_hy_init, dim3(nq), dim3(1024), 0, st, d, ns, V0, V1, norm2);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const dim3 grid((ns + 15) / 16), blk(256);
+  const dim3 grid((ns + 4 * kHyRows - 1) / (4 * kHyRows)), blk(256);
   for (int j = 0; j < niter; ++j) {
     double2* Qc = (j & 1) ? V1 : V0;
     double2* Qp = (j & 1) ? V0 : V1;
